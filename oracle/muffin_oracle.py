@@ -1,0 +1,324 @@
+"""FP64 CPU oracle of the spatio-spectral ADMM reconstruction (Ferrari et al.,
+"Multi-frequency image reconstruction for radio interferometry. A regularized
+inverse problem approach", arXiv 1504.06847).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``.  It shares no code with the GPU
+library.
+
+What it computes, and where the paper defines it
+------------------------------------------------
+* Data model (Section 2, eqs. nbmodel / wbmodel): band l of the dirty cube is
+  the band-l sky convolved with the band-l PSF.  H_l is read as a 2-D circular
+  convolution on the N x N grid, the PSF peak sitting at 0-based pixel
+  (ny/2, nx/2); the transfer function is h_hat = FFT2(ifftshift(psf)) and the
+  adjoint H_l^T is circular correlation (multiplication by conj(h_hat)).
+* Criterion (eqs. costreg, RegAll): 1/2 ||Y - HX||^2 + 1_{R+}(X)
+  + mu_eps/2 ||X||_F^2 + mu_s ||W_s X||_1 + mu_nu ||X W_nu||_1, with W_s the
+  Dirac basis (identity, n_s = 1) and W_nu the orthonormal DCT-II along the
+  band axis.
+* Algorithm 1 (Section 3, steps I-VI): all nine arrays X, P, T, V, S,
+  Gamma_P, Gamma_T, Gamma_V, Gamma_S are stored explicitly and start at zero.
+  Step I solves Q_l x_l = b_l with Q_l = H_l^T H_l + rho I,
+  rho = mu_eps + rho_S + rho_P + n_s rho_T (eq. Qlsimp), exactly, through the
+  Fourier-domain filter 1 / (|h_hat|^2 + rho) (end of Section 3).  Step V uses
+  the closed form for one orthonormal W_nu (m_nu = 1).
+* Stopping quantities: primal / dual residuals of the two-block splitting
+  (block 1 = {X, V}, block 2 = {P, T, S}) in the standard form of Boyd et al.
+  (2011, Section 3.3), and E^k = ||w^k - w^{k+1}||_H, the quantity He & Yuan
+  (2015) prove non-increasing for ADMM.
+* Gradient oracle: forward-mode tangents through K iterations, for the
+  derivative of ||X^K - sky||^2 with respect to (mu_s, mu_nu, rho) with the
+  four rho's tied.  Kink convention: d soft(z, t)/dz = 1[|z| > t],
+  d max(0, z)/dz = 1[z > 0].
+
+Layout: every cube is a float64 array [L][ny][nx]; the paper's matrix X
+(pixels x bands) is its transpose-reshape, so "X W_nu" is a DCT along axis 0.
+"""
+from __future__ import annotations
+
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+import scipy.fft as sfft
+
+_WORKERS = int(os.environ.get("MUFFIN_ORACLE_WORKERS", "1"))
+
+
+def set_workers(n: int) -> None:
+    """Threads used by scipy.fft inside the oracle."""
+    global _WORKERS
+    _WORKERS = max(1, int(n))
+
+
+def _fft2(a):
+    return sfft.fft2(a, axes=(-2, -1), workers=_WORKERS)
+
+
+def _ifft2(a):
+    return sfft.ifft2(a, axes=(-2, -1), workers=_WORKERS)
+
+
+def dct_nu(A):
+    """A W_nu: orthonormal DCT-II along the band axis (axis 0)."""
+    return sfft.dct(A, type=2, norm="ortho", axis=0, workers=_WORKERS)
+
+
+def idct_nu(C):
+    """C W_nu^T: the inverse (transpose) of ``dct_nu``."""
+    return sfft.idct(C, type=2, norm="ortho", axis=0, workers=_WORKERS)
+
+
+def soft(z, t):
+    """Element-wise soft threshold S_t(z) = sign(z) max(|z| - t, 0) (steps III, IV)."""
+    return np.sign(z) * np.maximum(np.abs(z) - t, 0.0)
+
+
+@dataclass
+class Params:
+    mu_eps: float
+    mu_s: float
+    mu_nu: float
+    rho_P: float
+    rho_T: float
+    rho_V: float
+    rho_S: float
+
+    @classmethod
+    def from_any(cls, p):
+        if isinstance(p, cls):
+            return p
+        if isinstance(p, dict):
+            return cls(**{f.name: float(p[f.name]) for f in fields(cls)})
+        return cls(**{f.name: float(getattr(p, f.name)) for f in fields(cls)})
+
+    @property
+    def rho_Q(self):
+        # eq. Qlsimp with the Dirac basis: n_s = 1
+        return self.mu_eps + self.rho_S + self.rho_P + 1.0 * self.rho_T
+
+
+class Problem:
+    """One cube: PSFs, dirty images and parameters, all in float64."""
+
+    def __init__(self, psf, dirty, params):
+        self.psf = np.asarray(psf, dtype=np.float64)
+        self.Y = np.asarray(dirty, dtype=np.float64)
+        assert self.psf.shape == self.Y.shape and self.psf.ndim == 3
+        self.p = Params.from_any(params)
+        # transfer function of H_l: PSF peak moved to lag (0, 0)
+        self.hhat = _fft2(np.fft.ifftshift(self.psf, axes=(-2, -1)))
+        self.HtY = self.HT(self.Y)
+        self._set_filter()
+
+    def _set_filter(self):
+        self.filt = 1.0 / (np.abs(self.hhat) ** 2 + self.p.rho_Q)
+
+    def with_params(self, params):
+        q = object.__new__(Problem)
+        q.psf, q.Y, q.hhat, q.HtY = self.psf, self.Y, self.hhat, self.HtY
+        q.p = Params.from_any(params)
+        q._set_filter()
+        return q
+
+    @property
+    def shape(self):
+        return self.Y.shape
+
+    def H(self, x):
+        """Band-wise circular convolution with the PSF (eq. nbmodel)."""
+        return _ifft2(self.hhat * _fft2(x)).real
+
+    def HT(self, y):
+        """Adjoint of H: band-wise circular correlation."""
+        return _ifft2(np.conj(self.hhat) * _fft2(y)).real
+
+    def solve_Q(self, b):
+        """Q_l^{-1} b_l for every band: filter with (|h_hat|^2 + rho)^{-1}."""
+        return _ifft2(self.filt * _fft2(b)).real
+
+
+@dataclass
+class State:
+    X: np.ndarray
+    P: np.ndarray
+    T: np.ndarray
+    V: np.ndarray
+    S: np.ndarray
+    GP: np.ndarray
+    GT: np.ndarray
+    GV: np.ndarray
+    GS: np.ndarray
+
+    @classmethod
+    def zeros(cls, shape):
+        return cls(*(np.zeros(shape) for _ in range(9)))
+
+    def copy(self):
+        return State(*(getattr(self, f.name).copy() for f in fields(self)))
+
+
+def admm_iteration(prob: Problem, st: State) -> State:
+    """One pass of Algorithm 1: steps I-VI in the paper's order."""
+    p = prob.p
+    # Step I: b_l from eq. matB (W_s = identity), then Q_l x_l = b_l
+    B = (prob.HtY + (st.GT + p.rho_T * st.T) + st.GP + p.rho_P * st.P
+         + st.GS + p.rho_S * st.S)
+    X = prob.solve_Q(B)
+    # Step II: positivity
+    P = np.maximum(0.0, X - st.GP / p.rho_P)
+    # Step III: spatial soft threshold (W_s X = X)
+    WX = X
+    T = soft(WX - st.GT / p.rho_T, p.mu_s / p.rho_T)
+    # Step IV: spectral soft threshold, on the S of the previous pass
+    V = soft(dct_nu(st.S) - st.GV / p.rho_V, p.mu_nu / p.rho_V)
+    # Step V: closed form for one orthonormal W_nu (m_nu = 1)
+    S = (idct_nu(st.GV + p.rho_V * V) - st.GS + p.rho_S * X) / (p.rho_V + p.rho_S)
+    # Step VI: multipliers, with the new P, T, V, S
+    GP = st.GP + p.rho_P * (P - X)
+    GT = st.GT + p.rho_T * (T - WX)
+    GV = st.GV + p.rho_V * (V - dct_nu(S))
+    GS = st.GS + p.rho_S * (S - X)
+    return State(X, P, T, V, S, GP, GT, GV, GS)
+
+
+def run(prob: Problem, K: int, state: State | None = None, callback=None) -> State:
+    """K passes of Algorithm 1 from the all-zero state (or from ``state``).
+
+    ``callback(k, prev, cur)`` is called after pass k (1-based)."""
+    st = State.zeros(prob.shape) if state is None else state
+    for k in range(1, K + 1):
+        nxt = admm_iteration(prob, st)
+        if callback is not None:
+            callback(k, st, nxt)
+        st = nxt
+    return st
+
+
+def objective(prob: Problem, P: np.ndarray) -> float:
+    """Criterion (costreg) + (RegAll) at P; finite because P >= 0."""
+    p = prob.p
+    r = prob.Y - prob.H(P)
+    return float(0.5 * np.sum(r * r) + 0.5 * p.mu_eps * np.sum(P * P)
+                 + p.mu_s * np.sum(np.abs(P)) + p.mu_nu * np.sum(np.abs(dct_nu(P))))
+
+
+def residuals(prob: Problem, prev: State, cur: State, eps_abs=1e-5, eps_rel=1e-4):
+    """Primal / dual residual norms and tolerances (Boyd et al. 2011, Sec. 3.3).
+
+    Constraints P - X, T - W_s X, V - S W_nu, S - X; block 1 = (X, V),
+    block 2 = (P, T, S)."""
+    p = prob.p
+    r2 = (np.sum((cur.P - cur.X) ** 2) + np.sum((cur.T - cur.X) ** 2)
+          + np.sum((cur.V - dct_nu(cur.S)) ** 2) + np.sum((cur.S - cur.X) ** 2))
+    dP, dT, dS = cur.P - prev.P, cur.T - prev.T, cur.S - prev.S
+    sX = p.rho_P * dP + p.rho_T * dT + p.rho_S * dS
+    sV = p.rho_V * dct_nu(dS)
+    s2 = np.sum(sX ** 2) + np.sum(sV ** 2)
+    nvox = cur.X.size
+    Ax = np.sqrt(3.0 * np.sum(cur.X ** 2) + np.sum(cur.V ** 2))
+    Bz = np.sqrt(np.sum(cur.P ** 2) + np.sum(cur.T ** 2) + np.sum(dct_nu(cur.S) ** 2)
+                 + np.sum(cur.S ** 2))
+    Aty = np.sqrt(np.sum((cur.GP + cur.GT + cur.GS) ** 2) + np.sum(cur.GV ** 2))
+    eps_pri = np.sqrt(4.0 * nvox) * eps_abs + eps_rel * max(Ax, Bz)
+    eps_dual = np.sqrt(2.0 * nvox) * eps_abs + eps_rel * Aty
+    return dict(r=float(np.sqrt(r2)), s=float(np.sqrt(s2)),
+                eps_pri=float(eps_pri), eps_dual=float(eps_dual))
+
+
+def energy(prob: Problem, prev: State, cur: State) -> float:
+    """E^k = ||w^k - w^{k+1}||_H^2 with w = (B z, Gamma) (He & Yuan 2015)."""
+    p = prob.p
+    dS = cur.S - prev.S
+    return float(p.rho_P * np.sum((cur.P - prev.P) ** 2)
+                 + p.rho_T * np.sum((cur.T - prev.T) ** 2)
+                 + p.rho_S * np.sum(dS ** 2)
+                 + p.rho_V * np.sum(dct_nu(dS) ** 2)
+                 + np.sum((cur.GP - prev.GP) ** 2) / p.rho_P
+                 + np.sum((cur.GT - prev.GT) ** 2) / p.rho_T
+                 + np.sum((cur.GV - prev.GV) ** 2) / p.rho_V
+                 + np.sum((cur.GS - prev.GS) ** 2) / p.rho_S)
+
+
+def mse_loss(XK, sky) -> float:
+    """||X^K - sky||_2^2 (a sum, not a mean)."""
+    d = np.asarray(XK, np.float64) - np.asarray(sky, np.float64)
+    return float(np.sum(d * d))
+
+
+def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params):
+    """Primal pass of Algorithm 1 with its forward-mode tangent."""
+    p = prob.p
+    drhoQ = dp.mu_eps + dp.rho_S + dp.rho_P + dp.rho_T
+    B = (prob.HtY + st.GT + p.rho_T * st.T + st.GP + p.rho_P * st.P
+         + st.GS + p.rho_S * st.S)
+    dB = (dst.GT + dp.rho_T * st.T + p.rho_T * dst.T + dst.GP + dp.rho_P * st.P
+          + p.rho_P * dst.P + dst.GS + dp.rho_S * st.S + p.rho_S * dst.S)
+    X = prob.solve_Q(B)
+    dX = prob.solve_Q(dB - drhoQ * X)          # d(Q^{-1}) = -Q^{-1} dQ Q^{-1}
+    zP = X - st.GP / p.rho_P
+    dzP = dX - dst.GP / p.rho_P + st.GP * dp.rho_P / p.rho_P ** 2
+    P = np.maximum(0.0, zP)
+    dP = np.where(zP > 0.0, dzP, 0.0)
+    zT = X - st.GT / p.rho_T
+    dzT = dX - dst.GT / p.rho_T + st.GT * dp.rho_T / p.rho_T ** 2
+    tT = p.mu_s / p.rho_T
+    dtT = dp.mu_s / p.rho_T - p.mu_s * dp.rho_T / p.rho_T ** 2
+    T = soft(zT, tT)
+    dT = np.where(np.abs(zT) > tT, dzT - np.sign(zT) * dtT, 0.0)
+    zV = dct_nu(st.S) - st.GV / p.rho_V
+    dzV = dct_nu(dst.S) - dst.GV / p.rho_V + st.GV * dp.rho_V / p.rho_V ** 2
+    tV = p.mu_nu / p.rho_V
+    dtV = dp.mu_nu / p.rho_V - p.mu_nu * dp.rho_V / p.rho_V ** 2
+    V = soft(zV, tV)
+    dV = np.where(np.abs(zV) > tV, dzV - np.sign(zV) * dtV, 0.0)
+    den = p.rho_V + p.rho_S
+    dden = dp.rho_V + dp.rho_S
+    num = idct_nu(st.GV + p.rho_V * V) - st.GS + p.rho_S * X
+    dnum = (idct_nu(dst.GV + dp.rho_V * V + p.rho_V * dV) - dst.GS
+            + dp.rho_S * X + p.rho_S * dX)
+    S = num / den
+    dS = (dnum - S * dden) / den
+    cS, dcS = dct_nu(S), dct_nu(dS)
+    GP = st.GP + p.rho_P * (P - X)
+    dGP = dst.GP + dp.rho_P * (P - X) + p.rho_P * (dP - dX)
+    GT = st.GT + p.rho_T * (T - X)
+    dGT = dst.GT + dp.rho_T * (T - X) + p.rho_T * (dT - dX)
+    GV = st.GV + p.rho_V * (V - cS)
+    dGV = dst.GV + dp.rho_V * (V - cS) + p.rho_V * (dV - dcS)
+    GS = st.GS + p.rho_S * (S - X)
+    dGS = dst.GS + dp.rho_S * (S - X) + p.rho_S * (dS - dX)
+    return (State(X, P, T, V, S, GP, GT, GV, GS),
+            State(dX, dP, dT, dV, dS, dGP, dGT, dGV, dGS))
+
+
+def jvp_run(prob: Problem, K: int, direction):
+    """X^K and its directional derivative along ``direction``.
+
+    ``direction`` = (d mu_s, d mu_nu, d rho) with rho_P = rho_T = rho_V = rho_S
+    = rho tied, or a full ``Params`` of tangents."""
+    if isinstance(direction, Params):
+        dp = direction
+    else:
+        a, b, c = (float(v) for v in direction)
+        dp = Params(0.0, a, b, c, c, c, c)
+    st = State.zeros(prob.shape)
+    dst = State.zeros(prob.shape)
+    for _ in range(K):
+        st, dst = _jvp_iteration(prob, st, dst, dp)
+    return st.X, dst.X
+
+
+def mse_grad(prob: Problem, K: int, sky):
+    """d ||X^K - sky||^2 / d(mu_s, mu_nu, rho) by three forward-mode passes."""
+    g = np.zeros(3)
+    loss = None
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        XK, dXK = jvp_run(prob, K, e)
+        r = XK - np.asarray(sky, np.float64)
+        g[i] = 2.0 * np.sum(r * dXK)
+        loss = float(np.sum(r * r))
+    return loss, g
