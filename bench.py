@@ -1,0 +1,162 @@
+#!/usr/bin/env python
+"""Throughput of the wide-band ADMM iteration on one MI355X.
+
+One step = one full pass of Algorithm 1 (steps I-VI: row FFT, fused column
+solve, inverse row FFT, fused spectral/prox/dual pass) over the whole cube.
+Default workload: 1024 x 1024 x 64 bands, FP32, synthetic inputs (uv-track
+PSFs, point + Gaussian sky, rho = 1, mu_s = mu_nu = 0.02, mu_eps = 1e-3).
+
+Prints ONE JSON line: voxel-iterations/s, the roofline of the dominant
+kernel (HIP-event timing of each kernel on the solver's stream, algorithmic
+bytes per launch), the FP64 instantiation's rate, and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E peak
+METRIC = "voxel-iterations/s (FP32 vs FP64) at 1024²×64; HBM GB/s % of peak"
+
+# algorithmic bytes per voxel and per pass of each kernel, in units of the
+# element size (4 B in FP32): reads + writes of the arrays it must touch
+#   row_fwd  : B_rest in, packed half spectrum out                    2
+#   col_solve: spectrum in/out, conj(h) y_hat in, |h|^2 in (half)     3.5
+#   row_inv  : spectrum in, X out                                     2
+#   spectral : X, z_P, z_T, S, Gamma_S, Gamma_V in; 5 state + B_rest  12
+KERNEL_ELEMS = {"row_fwd": 2.0, "col_solve": 3.5, "row_inv": 2.0, "spectral": 12.0}
+# minimum traffic of one pass: the 5-array state stream + constants (46 B in
+# FP32) plus one transposition round trip of the 2-D FFT (16 B)
+ITER_ALG_ELEMS = 15.5
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(inst, params, iters: int):
+    """Time the FP64 oracle (as it stands) on `iters` passes of the same cube."""
+    import oracle as O
+    workers = min(16, os.cpu_count() or 1)
+    O.set_workers(workers)
+    prob = O.Problem(inst.psf, inst.dirty, params)
+    st = O.State.zeros(prob.shape)
+    st = O.admm_iteration(prob, st)          # first touch of every array, untimed
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        st = O.admm_iteration(prob, st)
+    dt = time.perf_counter() - t0
+    L, ny, nx = prob.shape
+    return dict(value=L * ny * nx * iters / dt, unit="voxel-iterations/s", cores=workers,
+                kind="oracle",
+                sample=f"{iters} FP64 passes of the full {nx}x{ny}x{L} cube after one untimed "
+                       f"pass; scipy.fft with {workers} threads, {dt:.1f} s")
+
+
+def run_gpu(inst, params, dtype, steps, warmup, profile_iters):
+    import torch
+    from paper_1504_06847_amd import Solver
+    kw = dict(mu_eps=params.mu_eps, mu_s=params.mu_s, mu_nu=params.mu_nu, rho_P=params.rho_P,
+              rho_T=params.rho_T, rho_V=params.rho_V, rho_S=params.rho_S)
+    s = Solver(inst.psf, inst.dirty, dtype=dtype, **kw)
+    s.iterate(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    s.iterate(steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = s.profile(profile_iters) if profile_iters > 0 else {}
+    s.close()
+    return ms, prof
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="cube1024")
+    ap.add_argument("--profile-iters", type=int, default=20)
+    ap.add_argument("--fp64-steps", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
+              "band-sharded layout is a design, not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from synth import get_config
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    cfg = get_config(a.config)
+    _log(f"bench: generating {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.L}")
+    inst = cfg.make()
+    V = cfg.voxels
+    _log(f"bench: FP32 {a.warmup} warmup + {a.steps} timed passes")
+    ms32, prof32 = run_gpu(inst, cfg.params, torch.float32, a.steps, a.warmup, a.profile_iters)
+    value = V * a.steps / (ms32 / 1e3)
+    kernels = {}
+    for name, kms in prof32.items():
+        nbytes = KERNEL_ELEMS.get(name, 0.0) * 4 * V
+        kernels[name] = dict(ms=round(kms, 5), alg_bytes=int(nbytes),
+                             GBps=round(nbytes / (kms * 1e-3) / 1e9, 1))
+    dom = max(prof32, key=prof32.get) if prof32 else None
+    roof = None
+    if dom:
+        ach = kernels[dom]["GBps"]
+        roof = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBPS, 4), traffic=None,
+                    alg_bytes_per_launch=kernels[dom]["alg_bytes"])
+    fp64 = None
+    if a.fp64_steps > 0:
+        _log(f"bench: FP64 {a.fp64_steps} timed passes")
+        ms64, prof64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5)
+        fp64 = dict(value=V * a.fp64_steps / (ms64 / 1e3), ms_per_step=round(ms64 / a.fp64_steps, 4),
+                    kernels_ms={k: round(v, 5) for k, v in prof64.items()})
+    cpu = None
+    if not a.no_cpu_baseline:
+        _log(f"bench: CPU oracle, {a.cpu_iters} passes")
+        cpu = cpu_baseline(inst, cfg.params, a.cpu_iters)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms32 / a.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} pixels x {cfg.L} bands, FP32 ADMM "
+                               f"pass (Dirac W_s, DCT-II W_nu), rho=1, mu_s=mu_nu=0.02, mu_eps=1e-3",
+                   "nx": cfg.nx, "ny": cfg.ny, "L": cfg.L, "voxels": V,
+                   "parallelism": "1 GPU"},
+        "roofline": roof,
+        "iteration_alg_GBps": round(ITER_ALG_ELEMS * 4 * value / 1e9, 1),
+        "iteration_alg_frac": round(ITER_ALG_ELEMS * 4 * value / 1e9 / HBM_PEAK_GBPS, 4),
+        "kernels": kernels,
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * muffin.h -- C ABI of the MI355X (gfx950) wide-band ADMM reconstruction.
+ *
+ * The library solves, for a cube of L dirty images y_l (one per frequency
+ * band) and their point-spread functions, the convex problem of Ferrari et
+ * al., "Multi-frequency image reconstruction for radio interferometry. A
+ * regularized inverse problem approach" (arXiv 1504.06847):
+ *
+ *   min_X 1/2 ||Y - H X||^2 + 1_{R+}(X) + mu_eps/2 ||X||_F^2
+ *         + mu_s ||W_s X||_1 + mu_nu ||X W_nu||_1          (Section 2, eqs.
+ *                                                            costreg, RegAll)
+ *
+ * with the ADMM iteration of Algorithm 1 (Section 3, steps I-VI).  H_l is a
+ * 2-D circular convolution with the band-l PSF (eq. nbmodel), W_s is the
+ * Dirac basis (n_s = 1), W_nu the orthonormal DCT-II along the bands.  Step I
+ * is solved exactly in the Fourier domain with the filter
+ * (|h_hat_l|^2 + rho)^{-1}, rho = mu_eps + rho_S + rho_P + n_s rho_T
+ * (eq. Qlsimp and the paragraph after it).
+ *
+ * Conventions for every entry point:
+ *  - Cubes are dense, row-major [L][ny][nx] arrays (x fastest, band slowest)
+ *    in DEVICE memory, in the precision named by muffin_shape.dtype
+ *    (float for MUFFIN_F32, double for MUFFIN_F64).
+ *  - A PSF has its peak at 0-based pixel (ny/2, nx/2).
+ *  - `stream` arguments are hipStream_t values passed as void*; NULL is the
+ *    default stream.  A context is bound to the stream it was set up on, is
+ *    not thread-safe, and is independent of every other context.
+ *  - The caller owns psf, dirty, outputs and the workspace; the workspace
+ *    must outlive the context.  The library keeps no pointer to psf or dirty
+ *    after muffin_setup returns.
+ *  - Return values: MUFFIN_OK (0) or a negative error code below; no C++
+ *    exception and no abort crosses this interface.  muffin_last_error()
+ *    gives a message for the last failure on the calling thread.
+ */
+#ifndef MUFFIN_H
+#define MUFFIN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MUFFIN_OK              0
+#define MUFFIN_NOT_CONVERGED   1   /* muffin_solve reached max_iter (informational) */
+#define MUFFIN_EINVAL         -1   /* null pointer, L < 1, mu < 0, rho <= 0, non-finite
+                                      parameter, n_iter < 0, K < 1, ckpt_every < 1 */
+#define MUFFIN_EUNSUPPORTED   -2   /* size not a power of two in [8, 4096], dtype,
+                                      dictionary or band count not supported */
+#define MUFFIN_EWORKSPACE     -3   /* workspace too small or misaligned (256 B) */
+#define MUFFIN_EDEVICE        -4   /* a HIP runtime error (message in muffin_last_error) */
+#define MUFFIN_ENONFINITE     -5   /* NaN/Inf in psf/dirty at setup, or in a reduction */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define MUFFIN_F32 0
+#define MUFFIN_F64 1
+
+#define MUFFIN_DIRAC 0             /* W_s = identity (the only spatial basis built) */
+#define MUFFIN_DCT2_ORTHO 0        /* W_nu = orthonormal DCT-II along the bands */
+
+#define MUFFIN_MODE_MSE 0          /* muffin_grad: loss = ||x_K - sky||^2, sky given */
+#define MUFFIN_MODE_VJP 1          /* muffin_grad: cotangent dL/dx_K given */
+
+#define MUFFIN_MAX_BANDS 64        /* largest L of the register-resident spectral pass;
+                                      above 32 bands L must be a power of two */
+
+/* ---- plain-data structs -------------------------------------------------- */
+typedef struct muffin_ctx muffin_ctx;        /* opaque, owned by the library */
+
+typedef struct {
+    int nx, ny;   /* image size; each a power of two in [8, 4096] */
+    int L;        /* number of bands, 1 <= L <= MUFFIN_MAX_BANDS */
+    int dtype;    /* MUFFIN_F32 or MUFFIN_F64: storage and arithmetic of the iteration */
+} muffin_shape;
+
+typedef struct {
+    /* regularisation weights (Section 2, eq. RegAll), all >= 0 */
+    double mu_eps, mu_s, mu_nu;
+    /* augmented-Lagrangian parameters of the four constraints P = X,
+       T = W_s X, V = S W_nu, S = X (eq. admm2), all > 0 */
+    double rho_P, rho_T, rho_V, rho_S;
+    int n_s;          /* number of spatial bases; must be 1 */
+    int spatial[9];   /* spatial[0] = MUFFIN_DIRAC; others ignored */
+    int spectral;     /* MUFFIN_DCT2_ORTHO */
+    int check_every;  /* muffin_solve: iterations between FP64 residual checks (>= 1) */
+    double eps_abs, eps_rel;   /* stopping tolerances of Boyd et al. (2011), Sec. 3.3.1 */
+} muffin_params;
+
+typedef struct {
+    int iters;        /* iterations run by this context since setup/reset */
+    int converged;    /* 1 if r_pri <= eps_pri and r_dual <= eps_dual at the last check */
+    double r_pri, r_dual, eps_pri, eps_dual;  /* primal/dual residual norms and tolerances */
+    double objective; /* criterion (costreg)+(RegAll) evaluated at P = max(0, prox input) */
+    double E;         /* ||w^k - w^{k+1}||_H^2 (He & Yuan 2015), non-increasing in k */
+} muffin_report;
+
+/* Fill `p` with the paper's parameter values (Section 4): mu_eps = 1e-3,
+   mu_s = 0.5, mu_nu = 1, rho_P = 1, rho_T = 5, rho_V = 2, rho_S = 1,
+   n_s = 1 (Dirac), DCT-II, check_every = 10, eps_abs = 1e-5, eps_rel = 1e-4. */
+void muffin_default_params(muffin_params* p);
+
+/* Bytes of device workspace muffin_setup needs for this shape (0 if the
+   shape or parameters are invalid; muffin_last_error says why).  Host-only. */
+size_t muffin_workspace_bytes(const muffin_shape* shape, const muffin_params* params);
+
+/* Host-only validation of a shape and parameter set: MUFFIN_OK or the code
+   muffin_setup would return before touching the device. */
+int muffin_validate(const muffin_shape* shape, const muffin_params* params);
+
+/* Set up one cube: derives |h_hat_l|^2 and conj(h_hat_l) FFT2(y_l) in FP64
+   (stored in the shape's precision) into `workspace`, scans psf/dirty for
+   non-finite values, zeroes the ADMM state (Algorithm 1 initialisation) and
+   writes the new context to *ctx.  psf, dirty: device [L][ny][nx] arrays.
+   Asynchronous on `stream` except for one 8-byte read-back of the scan
+   result.  Errors: EINVAL, EUNSUPPORTED, EWORKSPACE, EDEVICE, ENONFINITE. */
+int muffin_setup(muffin_ctx** ctx, const muffin_shape* shape, const muffin_params* params,
+                 const void* psf, const void* dirty, void* workspace, size_t ws_bytes,
+                 void* stream);
+
+/* Run n_iter passes of Algorithm 1 (steps I-VI) on the context's stream.
+   No host synchronisation.  n_iter = 0 is a no-op.  Errors: EINVAL, EDEVICE. */
+int muffin_iterate(muffin_ctx* ctx, int n_iter);
+
+/* Iterate until the primal/dual residuals of the two-block splitting fall
+   under their tolerances (Boyd et al. 2011, Sec. 3.3; checked every
+   params.check_every iterations in FP64) or max_iter iterations have run.
+   Fills *report (may be NULL).  Returns MUFFIN_OK when converged,
+   MUFFIN_NOT_CONVERGED at max_iter, or an error. Synchronises the stream at
+   each check. */
+int muffin_solve(muffin_ctx* ctx, int max_iter, muffin_report* report);
+
+/* Run ONE more pass of Algorithm 1 and fill *report with its residuals, E and
+   the objective at the new P.  Synchronises the stream. */
+int muffin_step_report(muffin_ctx* ctx, muffin_report* report);
+
+/* Copy the current X iterate (step I output of the last pass; zero before the
+   first pass) into x_out, a device [L][ny][nx] array of the shape's dtype.
+   Asynchronous on the context's stream. */
+int muffin_get_x(muffin_ctx* ctx, void* x_out);
+
+/* Copy the current P = max(0, X - Gamma_P / rho_P) iterate (non-negative). */
+int muffin_get_p(muffin_ctx* ctx, void* p_out);
+
+/* Gradient of a loss of x_K, the X iterate after K passes of Algorithm 1
+   from the all-zero state, with respect to (mu_s, mu_nu, rho), where rho is
+   the common value of rho_P = rho_T = rho_V = rho_S (its derivative is taken
+   along (1, 1, 1, 1)).  mode = MUFFIN_MODE_MSE: sky_or_gx is a device cube
+   (the reference sky), loss = ||x_K - sky||^2.  mode = MUFFIN_MODE_VJP:
+   sky_or_gx is dL/dx_K and *loss is left as 0.  Uses a reverse sweep with
+   state checkpoints every ckpt_every passes.  grad: host double[3].  The
+   context's state afterwards equals the state after K passes from zero.
+   Allocates its own device scratch (freed by muffin_destroy).
+   Errors: EINVAL, EDEVICE. */
+int muffin_grad(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
+                double* loss, double grad[3]);
+
+/* Bytes of one state snapshot (z_P, z_T, S, Gamma_S, Gamma_V plus the X
+   iterate and an iteration counter). */
+size_t muffin_state_bytes(const muffin_ctx* ctx);
+
+/* Save / restore the ADMM state to / from device memory `dst` / `src`
+   (muffin_state_bytes bytes, 256-byte aligned).  Resuming from a saved state
+   reproduces the uninterrupted run bit for bit. */
+int muffin_get_state(muffin_ctx* ctx, void* dst);
+int muffin_set_state(muffin_ctx* ctx, const void* src);
+
+/* Replace the parameters (mu's, rho's) without a new setup.  The state is
+   kept; the iteration continues with the new values.  Errors: EINVAL. */
+int muffin_set_params(muffin_ctx* ctx, const muffin_params* params);
+
+/* Zero the ADMM state (Algorithm 1 initialisation) and the iteration count. */
+int muffin_reset(muffin_ctx* ctx);
+
+/* Number of passes run since setup/reset. */
+int muffin_iterations(const muffin_ctx* ctx);
+
+/* Time n_iter passes with HIP events around every kernel launch on the
+   context's stream; writes the mean duration in ms of each kernel of one
+   pass to ms[i] and its name to names[i] (static strings), for up to `cap`
+   kernels; returns the number of kernels per pass (negative on error). */
+int muffin_profile(muffin_ctx* ctx, int n_iter, double* ms, const char** names, int cap);
+
+/* Release the context (not the caller's workspace).  NULL is a no-op. */
+int muffin_destroy(muffin_ctx* ctx);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* muffin_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MUFFIN_H */

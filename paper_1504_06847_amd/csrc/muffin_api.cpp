@@ -1,0 +1,480 @@
+// C ABI of the gfx950 ADMM reconstruction: context, setup, the iteration
+// driver, convergence checks and state management.  Every step of the
+// iteration runs in the HIP kernels of muffin_fft.hip / muffin_spectral.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "muffin.h"
+#include "muffin_kernels.hpp"
+#include "muffin_layout.hpp"
+
+using namespace muffin;
+
+struct muffin_ctx {
+    muffin_shape shape;
+    muffin_params params;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    Layout lay;
+    int iters;
+    int twlog;
+    double ynorm2;
+    // scratch owned by the library (reverse sweep of muffin_grad)
+    void* grad_buf;
+    size_t grad_bytes;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                 \
+            return MUFFIN_EDEVICE;                                                    \
+        }                                                                             \
+    } while (0)
+
+size_t elem_size(const muffin_shape& s) { return s.dtype == MUFFIN_F64 ? 8 : 4; }
+size_t voxels(const muffin_shape& s) { return size_t(s.L) * s.ny * s.nx; }
+int ilog2i(int n) { int r = 0; while ((1 << r) < n) ++r; return r; }
+
+char* P(muffin_ctx* c, size_t off) { return c->ws + off; }
+void* st(muffin_ctx* c, int i) { return c->ws + c->lay.state[i]; }
+
+SpecArgs spec_args(const muffin_params& p) {
+    SpecArgs a;
+    a.rho_P = p.rho_P;
+    a.rho_T = p.rho_T;
+    a.rho_V = p.rho_V;
+    a.rho_S = p.rho_S;
+    a.tau_T = p.mu_s / p.rho_T;
+    a.tau_V = p.mu_nu / p.rho_V;
+    return a;
+}
+
+// rho of eq. Qlsimp for the Dirac basis (n_s = 1)
+double rho_Q(const muffin_params& p) { return p.mu_eps + p.rho_S + p.rho_P + double(p.n_s) * p.rho_T; }
+
+int check_ctx(const muffin_ctx* c) {
+    if (!c) { set_error("context is NULL"); return MUFFIN_EINVAL; }
+    return MUFFIN_OK;
+}
+
+// step I of one pass: X = Q^{-1} (H^T Y + B_rest), band by band
+int step_one(muffin_ctx* c) {
+    const muffin_shape& s = c->shape;
+    const int dt = s.dtype;
+    const int nrows = s.L * s.ny;
+    const double scale = 1.0 / (double(s.nx / 2) * double(s.ny));
+    HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows, s.nx,
+                           s.ny, false, false, P(c, c->lay.tw), c->twlog, c->stream));
+    HIP_TRY(launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
+                       P(c, c->lay.h2nyq), rho_Q(c->params), scale, s.L, s.ny, s.nx,
+                       P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream));
+    HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), P(c, c->lay.x), nrows, s.nx, P(c, c->lay.tw),
+                           c->twlog, c->stream));
+    return MUFFIN_OK;
+}
+
+int step_spectral(muffin_ctx* c, bool reduce, int* nblocks) {
+    const muffin_shape& s = c->shape;
+    HIP_TRY(launch_spectral(s.dtype, reduce, P(c, c->lay.x), st(c, ST_ZP), st(c, ST_ZT), st(c, ST_S),
+                            st(c, ST_GS), st(c, ST_GV), P(c, c->lay.brest), P(c, c->lay.dctm), s.L,
+                            s.ny * s.nx, spec_args(c->params), (double*)P(c, c->lay.partials),
+                            nblocks, c->stream));
+    return MUFFIN_OK;
+}
+
+int one_pass(muffin_ctx* c) {
+    int rc = step_one(c);
+    if (rc) return rc;
+    rc = step_spectral(c, false, nullptr);
+    if (rc) return rc;
+    c->iters++;
+    return MUFFIN_OK;
+}
+
+int recompute_brest(muffin_ctx* c) {
+    HIP_TRY(launch_brest(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), st(c, ST_S), st(c, ST_GS),
+                         P(c, c->lay.brest), voxels(c->shape), spec_args(c->params), c->stream));
+    return MUFFIN_OK;
+}
+
+int zero_state(muffin_ctx* c) {
+    // z_P .. Gamma_V, B_rest and X are contiguous
+    HIP_TRY(launch_fill_zero(P(c, c->lay.state[0]), c->lay.z - c->lay.state[0], c->stream));
+    c->iters = 0;
+    return MUFFIN_OK;
+}
+
+// cos/sin(2 pi k / n) in extended precision, with exact octant reduction
+void twiddle(long k, long n, long double* cr, long double* sr) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    *cr = cosl(2.0L * pi * (long double)k / (long double)n);
+    *sr = sinl(2.0L * pi * (long double)k / (long double)n);
+    // snap the exactly representable values
+    if ((4 * k) % n == 0) {
+        const long q = ((4 * k) / n) % 4;
+        *cr = (q == 0) ? 1.0L : (q == 2 ? -1.0L : 0.0L);
+        *sr = (q == 1) ? 1.0L : (q == 3 ? -1.0L : 0.0L);
+    }
+}
+
+int upload_tables(muffin_ctx* c) {
+    const muffin_shape& s = c->shape;
+    const int NT = s.nx > s.ny ? s.nx : s.ny;
+    std::vector<double> t64(2 * size_t(NT));
+    std::vector<float> t32(2 * size_t(NT));
+    for (int k = 0; k < NT; ++k) {
+        long double cr, sr;
+        twiddle(k, NT, &cr, &sr);
+        t64[2 * k] = double(cr);
+        t64[2 * k + 1] = double(-sr);            // exp(-2 pi i k / NT)
+        t32[2 * k] = float(cr);
+        t32[2 * k + 1] = float(-sr);
+    }
+    // dense DCT-II matrix, zero-padded to the spectral kernel's register width
+    const int L = s.L, LT = dense_width(L);
+    std::vector<double> d64(size_t(LT) * LT, 0.0);
+    std::vector<float> d32(size_t(LT) * LT, 0.0f);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < L; ++k) {
+        const long double a = k == 0 ? sqrtl(1.0L / L) : sqrtl(2.0L / L);
+        for (int l = 0; l < L; ++l) {
+            const long double v = a * cosl(pi * (long double)((2 * l + 1) * k) / (long double)(2 * L));
+            d64[size_t(k) * LT + l] = double(v);
+            d32[size_t(k) * LT + l] = float(v);
+        }
+    }
+    HIP_TRY(hipMemcpy(P(c, c->lay.tw64), t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
+    if (s.dtype == MUFFIN_F64) {
+        HIP_TRY(hipMemcpy(P(c, c->lay.tw), t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(P(c, c->lay.dctm), d64.data(), d64.size() * 8, hipMemcpyHostToDevice));
+    } else {
+        HIP_TRY(hipMemcpy(P(c, c->lay.tw), t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(P(c, c->lay.dctm), d32.data(), d32.size() * 4, hipMemcpyHostToDevice));
+    }
+    return MUFFIN_OK;
+}
+
+int read_sums(muffin_ctx* c, int n, double* out) {
+    HIP_TRY(hipMemcpyAsync(out, P(c, c->lay.sums), size_t(n) * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return MUFFIN_OK;
+}
+
+// one pass with the FP64 reductions of the spectral step, then the data term
+// of the objective at P = max(0, z_P) through a forward FFT pass
+int pass_with_report(muffin_ctx* c, muffin_report* rep) {
+    const muffin_shape& s = c->shape;
+    int rc = step_one(c);
+    if (rc) return rc;
+    int nb = 0;
+    rc = step_spectral(c, true, &nb);
+    if (rc) return rc;
+    c->iters++;
+    double* partials = (double*)P(c, c->lay.partials);
+    double* sums = (double*)P(c, c->lay.sums);
+    HIP_TRY(launch_reduce_final(partials, nb, RED_NQ, sums, c->stream));
+    const int nrows = s.L * s.ny;
+    HIP_TRY(launch_row_fwd(s.dtype, s.dtype == MUFFIN_F64, st(c, ST_ZP), P(c, c->lay.z), nrows,
+                           s.nx, s.ny, false, true, P(c, c->lay.tw), c->twlog, c->stream));
+    int nbc = 0;
+    HIP_TRY(launch_col(s.dtype, COL_OBJ, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
+                       P(c, c->lay.h2nyq), 0.0, 1.0, s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog,
+                       partials, &nbc, c->stream));
+    HIP_TRY(launch_reduce_final(partials, nbc, 1, sums + RED_NQ, c->stream));
+    double h[RED_NQ + 1];
+    rc = read_sums(c, RED_NQ + 1, h);
+    if (rc) return rc;
+    for (int i = 0; i <= RED_NQ; ++i) {
+        if (!std::isfinite(h[i])) {
+            set_error("non-finite FP64 reduction (slot %d) at iteration %d", i, c->iters);
+            return MUFFIN_ENONFINITE;
+        }
+    }
+    const muffin_params& p = c->params;
+    const double nv = double(voxels(s));
+    const double Ax = std::sqrt(3.0 * h[RED_X2] + h[RED_V2]);
+    const double Bz = std::sqrt(h[RED_BZ2]);
+    const double Aty = std::sqrt(h[RED_ATY2]);
+    rep->iters = c->iters;
+    rep->r_pri = std::sqrt(h[RED_R2]);
+    rep->r_dual = std::sqrt(h[RED_S2]);
+    rep->eps_pri = std::sqrt(4.0 * nv) * p.eps_abs + p.eps_rel * (Ax > Bz ? Ax : Bz);
+    rep->eps_dual = std::sqrt(2.0 * nv) * p.eps_abs + p.eps_rel * Aty;
+    rep->objective = 0.5 * (c->ynorm2 + h[RED_NQ]) + 0.5 * p.mu_eps * h[RED_P2] + p.mu_s * h[RED_P1]
+                     + p.mu_nu * h[RED_DCTP1];
+    rep->E = h[RED_E];
+    rep->converged = (rep->r_pri <= rep->eps_pri && rep->r_dual <= rep->eps_dual) ? 1 : 0;
+    return MUFFIN_OK;
+}
+
+size_t state_array_bytes(const muffin_ctx* c) {
+    return (voxels(c->shape) * elem_size(c->shape) + kAlign - 1) & ~(kAlign - 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_params* params,
+                 const void* psf, const void* dirty, void* workspace, size_t ws_bytes, void* stream) {
+    if (!out) { set_error("ctx output pointer is NULL"); return MUFFIN_EINVAL; }
+    *out = nullptr;
+    int rc = muffin_validate(shape, params);
+    if (rc != MUFFIN_OK) return rc;
+    if (!psf || !dirty || !workspace) {
+        set_error("psf, dirty and workspace must be non-NULL device pointers");
+        return MUFFIN_EINVAL;
+    }
+    const Layout lay = make_layout(shape);
+    if (ws_bytes < lay.total) {
+        set_error("workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, lay.total);
+        return MUFFIN_EWORKSPACE;
+    }
+    if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0) {
+        set_error("workspace must be %zu-byte aligned", kAlign);
+        return MUFFIN_EWORKSPACE;
+    }
+    muffin_ctx* c = new (std::nothrow) muffin_ctx();
+    if (!c) { set_error("out of host memory"); return MUFFIN_EDEVICE; }
+    c->shape = *shape;
+    c->params = *params;
+    c->stream = (hipStream_t)stream;
+    c->ws = (char*)workspace;
+    c->ws_bytes = ws_bytes;
+    c->lay = lay;
+    c->iters = 0;
+    const int NT = shape->nx > shape->ny ? shape->nx : shape->ny;
+    c->twlog = ilog2i(NT);
+    c->grad_buf = nullptr;
+    c->grad_bytes = 0;
+
+    auto fail = [&](int code) { delete c; return code; };
+    const bool in64 = shape->dtype == MUFFIN_F64;
+    const size_t n = voxels(*shape);
+    // non-finite scan and ||y||^2
+    int nb = 0;
+    double* partials = (double*)P(c, lay.partials);
+    double* sums = (double*)P(c, lay.sums);
+    hipError_t e = launch_scan(in64, psf, dirty, n, partials, &nb, c->stream);
+    if (e == hipSuccess) e = launch_reduce_final(partials, nb, 2, sums, c->stream);
+    if (e != hipSuccess) { set_error("setup scan launch failed: %s", hipGetErrorString(e)); return fail(MUFFIN_EDEVICE); }
+    double h[2];
+    if ((rc = read_sums(c, 2, h)) != MUFFIN_OK) return fail(rc);
+    if (h[0] != 0.0 || !std::isfinite(h[1])) {
+        set_error("psf/dirty hold %.0f non-finite values", h[0]);
+        return fail(MUFFIN_ENONFINITE);
+    }
+    c->ynorm2 = h[1];
+    if ((rc = upload_tables(c)) != MUFFIN_OK) return fail(rc);
+    // FP64 transforms of the shifted PSF and of the dirty image, in the (not yet
+    // used) state region
+    char* Ch = P(c, lay.state[0]);
+    char* Cy = Ch + lay.setup_scratch_bytes / 2;
+    const int nrows = shape->L * shape->ny;
+    e = launch_row_fwd(MUFFIN_F64, in64, psf, Ch, nrows, shape->nx, shape->ny, true, false,
+                       P(c, lay.tw64), c->twlog, c->stream);
+    if (e == hipSuccess)
+        e = launch_col(MUFFIN_F64, COL_FWD, Ch, nullptr, nullptr, nullptr, 0.0, 1.0, shape->L, shape->ny,
+                       shape->nx, P(c, lay.tw64), c->twlog, nullptr, nullptr, c->stream);
+    if (e == hipSuccess)
+        e = launch_row_fwd(MUFFIN_F64, in64, dirty, Cy, nrows, shape->nx, shape->ny, false, false,
+                           P(c, lay.tw64), c->twlog, c->stream);
+    if (e == hipSuccess)
+        e = launch_col(MUFFIN_F64, COL_FWD, Cy, nullptr, nullptr, nullptr, 0.0, 1.0, shape->L, shape->ny,
+                       shape->nx, P(c, lay.tw64), c->twlog, nullptr, nullptr, c->stream);
+    if (e == hipSuccess)
+        e = launch_setup_combine(shape->dtype, Ch, Cy, P(c, lay.yf), P(c, lay.h2), P(c, lay.h2nyq),
+                                 shape->L, shape->ny, shape->nx, c->stream);
+    if (e != hipSuccess) { set_error("setup transform launch failed: %s", hipGetErrorString(e)); return fail(MUFFIN_EDEVICE); }
+    if ((rc = zero_state(c)) != MUFFIN_OK) return fail(rc);
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { set_error("setup failed: %s", hipGetErrorString(e)); return fail(MUFFIN_EDEVICE); }
+    *out = c;
+    return MUFFIN_OK;
+}
+
+int muffin_iterate(muffin_ctx* c, int n_iter) {
+    if (int rc = check_ctx(c)) return rc;
+    if (n_iter < 0) { set_error("n_iter = %d < 0", n_iter); return MUFFIN_EINVAL; }
+    for (int i = 0; i < n_iter; ++i) {
+        int rc = one_pass(c);
+        if (rc) return rc;
+    }
+    return MUFFIN_OK;
+}
+
+int muffin_step_report(muffin_ctx* c, muffin_report* rep) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!rep) { set_error("report is NULL"); return MUFFIN_EINVAL; }
+    return pass_with_report(c, rep);
+}
+
+int muffin_solve(muffin_ctx* c, int max_iter, muffin_report* report) {
+    if (int rc = check_ctx(c)) return rc;
+    if (max_iter < 1) { set_error("max_iter = %d < 1", max_iter); return MUFFIN_EINVAL; }
+    muffin_report rep{};
+    int done = 0;
+    while (done < max_iter) {
+        const int left = max_iter - done;
+        const int plain = (c->params.check_every - 1 < left - 1) ? c->params.check_every - 1 : left - 1;
+        int rc = muffin_iterate(c, plain);
+        if (rc) return rc;
+        rc = pass_with_report(c, &rep);
+        if (rc) return rc;
+        done += plain + 1;
+        if (rep.converged) break;
+    }
+    if (report) *report = rep;
+    return rep.converged ? MUFFIN_OK : MUFFIN_NOT_CONVERGED;
+}
+
+int muffin_get_x(muffin_ctx* c, void* x_out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!x_out) { set_error("x_out is NULL"); return MUFFIN_EINVAL; }
+    HIP_TRY(hipMemcpyAsync(x_out, P(c, c->lay.x), voxels(c->shape) * elem_size(c->shape),
+                           hipMemcpyDeviceToDevice, c->stream));
+    return MUFFIN_OK;
+}
+
+int muffin_get_p(muffin_ctx* c, void* p_out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!p_out) { set_error("p_out is NULL"); return MUFFIN_EINVAL; }
+    HIP_TRY(launch_positive(c->shape.dtype, st(c, ST_ZP), p_out, voxels(c->shape), c->stream));
+    return MUFFIN_OK;
+}
+
+size_t muffin_state_bytes(const muffin_ctx* c) {
+    if (!c) return 0;
+    return kAlign + (kNumState + 1) * state_array_bytes(c);
+}
+
+int muffin_get_state(muffin_ctx* c, void* dst) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!dst || (reinterpret_cast<uintptr_t>(dst) & (kAlign - 1))) {
+        set_error("state buffer must be a non-NULL, %zu-byte aligned device pointer", kAlign);
+        return MUFFIN_EINVAL;
+    }
+    const size_t ab = state_array_bytes(c), nb = voxels(c->shape) * elem_size(c->shape);
+    char* d = (char*)dst;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int64_t hdr[4] = {0x4d554646494e5354LL, c->iters, c->shape.dtype, (int64_t)voxels(c->shape)};
+    HIP_TRY(hipMemcpy(d, hdr, sizeof(hdr), hipMemcpyHostToDevice));
+    for (int i = 0; i < kNumState; ++i)
+        HIP_TRY(hipMemcpyAsync(d + kAlign + i * ab, st(c, i), nb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(d + kAlign + kNumState * ab, P(c, c->lay.x), nb, hipMemcpyDeviceToDevice, c->stream));
+    return MUFFIN_OK;
+}
+
+int muffin_set_state(muffin_ctx* c, const void* src) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!src || (reinterpret_cast<uintptr_t>(src) & (kAlign - 1))) {
+        set_error("state buffer must be a non-NULL, %zu-byte aligned device pointer", kAlign);
+        return MUFFIN_EINVAL;
+    }
+    const size_t ab = state_array_bytes(c), nb = voxels(c->shape) * elem_size(c->shape);
+    const char* s = (const char*)src;
+    int64_t hdr[4];
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(hdr, s, sizeof(hdr), hipMemcpyDeviceToHost));
+    if (hdr[0] != 0x4d554646494e5354LL || hdr[2] != c->shape.dtype || hdr[3] != (int64_t)voxels(c->shape)) {
+        set_error("state buffer does not hold a state of this shape and dtype");
+        return MUFFIN_EINVAL;
+    }
+    for (int i = 0; i < kNumState; ++i)
+        HIP_TRY(hipMemcpyAsync(st(c, i), s + kAlign + i * ab, nb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(P(c, c->lay.x), s + kAlign + kNumState * ab, nb, hipMemcpyDeviceToDevice, c->stream));
+    c->iters = (int)hdr[1];
+    return recompute_brest(c);
+}
+
+int muffin_set_params(muffin_ctx* c, const muffin_params* params) {
+    if (int rc = check_ctx(c)) return rc;
+    int rc = validate_params(params);
+    if (rc) return rc;
+    c->params = *params;
+    return recompute_brest(c);
+}
+
+int muffin_reset(muffin_ctx* c) {
+    if (int rc = check_ctx(c)) return rc;
+    return zero_state(c);
+}
+
+int muffin_iterations(const muffin_ctx* c) { return c ? c->iters : -1; }
+
+int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, int cap) {
+    if (int rc = check_ctx(c)) return rc;
+    if (n_iter < 1 || !ms || cap < 1) { set_error("muffin_profile: bad arguments"); return MUFFIN_EINVAL; }
+    static const char* knames[4] = {"row_fwd", "col_solve", "row_inv", "spectral"};
+    const int K = 4;
+    hipEvent_t ev[K + 1];
+    for (int i = 0; i <= K; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+    double acc[K] = {0, 0, 0, 0};
+    const muffin_shape& s = c->shape;
+    const int dt = s.dtype, nrows = s.L * s.ny;
+    const double scale = 1.0 / (double(s.nx / 2) * double(s.ny));
+    int rc = MUFFIN_OK;
+    for (int it = 0; it < n_iter && rc == MUFFIN_OK; ++it) {
+        hipError_t e = hipEventRecord(ev[0], c->stream);
+        if (e == hipSuccess)
+            e = launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows, s.nx, s.ny,
+                               false, false, P(c, c->lay.tw), c->twlog, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+        if (e == hipSuccess)
+            e = launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2), P(c, c->lay.h2nyq),
+                           rho_Q(c->params), scale, s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog, nullptr,
+                           nullptr, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
+        if (e == hipSuccess)
+            e = launch_row_inv(dt, P(c, c->lay.z), P(c, c->lay.x), nrows, s.nx, P(c, c->lay.tw), c->twlog, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
+        if (e == hipSuccess) {
+            rc = step_spectral(c, false, nullptr);
+            if (rc) break;
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev[4], c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+        if (e != hipSuccess) { set_error("profile: %s", hipGetErrorString(e)); rc = MUFFIN_EDEVICE; break; }
+        for (int k = 0; k < K; ++k) {
+            float t = 0.f;
+            hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+        c->iters++;
+    }
+    for (int i = 0; i <= K; ++i) hipEventDestroy(ev[i]);
+    if (rc) return rc;
+    const int m = cap < K ? cap : K;
+    for (int k = 0; k < m; ++k) {
+        ms[k] = acc[k] / n_iter;
+        if (names) names[k] = knames[k];
+    }
+    return K;
+}
+
+int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode,
+                double* loss, double grad[3]) {
+    if (int rc = check_ctx(c)) return rc;
+    (void)K; (void)ckpt_every; (void)sky_or_gx; (void)mode; (void)loss; (void)grad;
+    set_error("muffin_grad: the reverse sweep is not built yet");
+    return MUFFIN_EUNSUPPORTED;
+}
+
+int muffin_destroy(muffin_ctx* c) {
+    if (!c) return MUFFIN_OK;
+    if (c->grad_buf) hipFree(c->grad_buf);
+    delete c;
+    return MUFFIN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,351 @@
+// Device building blocks of the gfx950 ADMM path: complex arithmetic,
+// compile-time trigonometry, LDS-staged Stockham FFT stages and
+// register-resident DCT-II / DCT-III along the band axis.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace muffin {
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct alignas(2 * sizeof(T)) cx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {   // a * conj(b)
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T> __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+template <typename T> __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }    //  i a
+template <typename T> __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; }   // -i a
+
+// ---------------------------------------------------------------- compile-time trig
+// cos(pi n / d) and sin(pi n / d) evaluated by the front end: exact integer
+// argument reduction to [0, pi/4], then Taylor series.
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double taylor_sin(double x) {
+    double x2 = x * x, term = x, sum = x;
+    for (int k = 1; k < 14; ++k) { term *= -x2 / double((2 * k) * (2 * k + 1)); sum += term; }
+    return sum;
+}
+constexpr double taylor_cos(double x) {
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 14; ++k) { term *= -x2 / double((2 * k - 1) * (2 * k)); sum += term; }
+    return sum;
+}
+constexpr double cospi_ratio(long n, long d) {
+    long p = 2 * d;
+    n %= p;
+    if (n < 0) n += p;
+    if (n > d) n = p - n;                       // cos(2pi - a) = cos a
+    double sgn = 1.0;
+    if (2 * n > d) { n = d - n; sgn = -1.0; }   // cos(pi - a) = -cos a
+    if (4 * n > d) return sgn * taylor_sin(kPi * double(d - 2 * n) / double(2 * d));
+    return sgn * taylor_cos(kPi * double(n) / double(d));
+}
+constexpr double sinpi_ratio(long n, long d) { return cospi_ratio(2 * n - d, 2 * d); }
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+
+// square root of a positive double by Newton's iteration (front-end constant)
+constexpr double sqrt_c(double v) {
+    double x = v > 1.0 ? v : 1.0;
+    for (int i = 0; i < 64; ++i) x = 0.5 * (x + v / x);
+    return x;
+}
+
+// ---------------------------------------------------------------- small DFTs in registers
+// Forward: y_q = sum_r v_r exp(-2 pi i r q / R); inverse uses exp(+...).
+template <typename T, bool INV> __device__ __forceinline__ void dft2(cx<T>* v) {
+    cx<T> a = v[0];
+    v[0] = a + v[1];
+    v[1] = a - v[1];
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+    cx<T> s02 = a0 + a2, d02 = a0 - a2, s13 = a1 + a3, d13 = a1 - a3;
+    cx<T> j13 = INV ? mul_i(d13) : mul_mi(d13);
+    a0 = s02 + s13;
+    a2 = s02 - s13;
+    a1 = d02 + j13;
+    a3 = d02 - j13;
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft8(cx<T>* v) {
+    const T h = T(0.70710678118654752440084436210484903928);
+    cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<T, INV>(e0, e1, e2, e3);
+    dft4<T, INV>(o0, o1, o2, o3);
+    // o_q *= w8^q, w8 = exp(-+ i pi / 4)
+    if (!INV) {
+        o1 = {(o1.x + o1.y) * h, (o1.y - o1.x) * h};
+        o2 = mul_mi(o2);
+        o3 = {(o3.y - o3.x) * h, -(o3.x + o3.y) * h};
+    } else {
+        o1 = {(o1.x - o1.y) * h, (o1.x + o1.y) * h};
+        o2 = mul_i(o2);
+        o3 = {-(o3.x + o3.y) * h, (o3.x - o3.y) * h};
+    }
+    v[0] = e0 + o0; v[4] = e0 - o0;
+    v[1] = e1 + o1; v[5] = e1 - o1;
+    v[2] = e2 + o2; v[6] = e2 - o2;
+    v[3] = e3 + o3; v[7] = e3 - o3;
+}
+
+template <typename T, int R, bool INV> __device__ __forceinline__ void dftR(cx<T>* v) {
+    if constexpr (R == 2) dft2<T, INV>(v);
+    else if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
+    else dft8<T, INV>(v);
+}
+
+// ---------------------------------------------------------------- FFT plans
+// Radix sequence for a power-of-two length: radix-8 stages, with one radix-4
+// (or two for lengths 2^(3q+1)) where 8 does not divide.
+constexpr int plan_nstages(int n) {
+    int m = ilog2c(n);
+    if (n == 2) return 1;
+    int q = m / 3, r = m % 3;
+    return r == 0 ? q : (r == 2 ? q + 1 : q + 1);
+}
+constexpr int plan_radix(int n, int s) {
+    int m = ilog2c(n);
+    if (n == 2) return 2;
+    int q = m / 3, r = m % 3;
+    if (r == 0) return 8;
+    if (r == 2) return s < q ? 8 : 4;
+    return s < q - 1 ? 8 : 4;       // 2^(3q+1) = 8^(q-1) * 4 * 4
+}
+constexpr int plan_ns(int n, int s) {   // product of the radices before stage s
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= plan_radix(n, i);
+    return p;
+}
+
+// One Stockham autosort stage over a tile of NTRANS transforms of length LEN
+// in LDS.  Element e of transform t sits at buf[t * TS + e * ES].  Butterfly j
+// (0 <= j < LEN/R) reads elements j + r LEN/R, multiplies input r by
+// w_{NS R}^{r (j mod NS)}, applies an R-point DFT and writes output q to
+// (j - j mod NS) R + (j mod NS) + q NS.  Work items (transform, butterfly) are
+// spread over NTH threads: TFAST puts the transform index fastest across
+// threads (strided tiles), otherwise the butterfly index.
+template <typename T, int LEN, int R, int NS, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool INV>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
+    constexpr int NB = LEN / R;
+    constexpr int ITEMS = NB * NTRANS;
+    constexpr int IPT = (ITEMS + NTH - 1) / NTH;
+    constexpr int LOGNR = ilog2c(NS * R);
+    cx<T> v[IPT][R];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int item = t + i * NTH;
+        if ((ITEMS % NTH) == 0 || item < ITEMS) {
+            const int tr = TFAST ? item % NTRANS : item / NB;
+            const int j = TFAST ? item / NTRANS : item % NB;
+            const cx<T>* p = buf + tr * TS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = p[(j + r * NB) * ES];
+            if constexpr (NS > 1) {
+                const int k = j & (NS - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> w = tw[(r * k) << (twlog - LOGNR)];
+                    v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
+                }
+            }
+            dftR<T, R, INV>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int item = t + i * NTH;
+        if ((ITEMS % NTH) == 0 || item < ITEMS) {
+            const int tr = TFAST ? item % NTRANS : item / NB;
+            const int j = TFAST ? item / NTRANS : item % NB;
+            const int k = j & (NS - 1);
+            cx<T>* p = buf + tr * TS;
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[(base + r * NS) * ES] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool INV, int S>
+__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
+    if constexpr (S < plan_nstages(LEN)) {
+        fft_stage<T, LEN, plan_radix(LEN, S), plan_ns(LEN, S), NTRANS, NTH, TS, ES, TFAST, INV>(buf, tw, twlog, t);
+        fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, INV, S + 1>(buf, tw, twlog, t);
+    }
+}
+
+// In-place FFT of NTRANS transforms of length LEN held in LDS (natural order
+// in and out, unnormalised).  Must be called by all NTH threads of the block.
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool INV>
+__device__ __forceinline__ void tile_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
+    fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, INV, 0>(buf, tw, twlog, t);
+}
+
+// ---------------------------------------------------------------- register FFT / DCT
+// Complex FFT of N points held in registers (radix-2, decimation in time
+// after a compile-time bit reversal).  Every twiddle is a template-argument
+// constant expression, so the whole transform is straight-line code.
+template <int N> constexpr int bitrev(int i) {
+    int r = 0;
+    for (int b = 0; b < ilog2c(N); ++b) r |= ((i >> b) & 1) << (ilog2c(N) - 1 - b);
+    return r;
+}
+
+template <typename T, int N, bool INV, int LEN, int K>
+__device__ __forceinline__ void reg_fft_k(T (&re)[N], T (&im)[N]) {
+    if constexpr (K < LEN / 2) {
+        constexpr double c = cospi_ratio(2 * K, LEN);
+        constexpr double s = INV ? sinpi_ratio(2 * K, LEN) : -sinpi_ratio(2 * K, LEN);
+#pragma unroll
+        for (int i = 0; i < N; i += LEN) {
+            const int a = i + K, b = i + K + LEN / 2;
+            T tr, ti;
+            if constexpr (K == 0) { tr = re[b]; ti = im[b]; }
+            else { tr = re[b] * T(c) - im[b] * T(s); ti = re[b] * T(s) + im[b] * T(c); }
+            re[b] = re[a] - tr; im[b] = im[a] - ti;
+            re[a] = re[a] + tr; im[a] = im[a] + ti;
+        }
+        reg_fft_k<T, N, INV, LEN, K + 1>(re, im);
+    }
+}
+
+template <typename T, int N, bool INV, int LEN>
+__device__ __forceinline__ void reg_fft_len(T (&re)[N], T (&im)[N]) {
+    if constexpr (LEN <= N) {
+        reg_fft_k<T, N, INV, LEN, 0>(re, im);
+        reg_fft_len<T, N, INV, 2 * LEN>(re, im);
+    }
+}
+
+template <typename T, int N, bool INV> __device__ __forceinline__ void reg_fft(T (&re)[N], T (&im)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int j = bitrev<N>(i);
+        if (j > i) {
+            T a = re[i]; re[i] = re[j]; re[j] = a;
+            T b = im[i]; im[i] = im[j]; im[j] = b;
+        }
+    }
+    reg_fft_len<T, N, INV, 2>(re, im);
+}
+
+// DCT-II post-processing for output pair k: from the L/2-point FFT Z of
+// (v_{2m} + i v_{2m+1}), V_k = E + w^k O with E = (Z_k + conj Z_{M-k})/2,
+// O = -i (Z_k - conj Z_{M-k})/2, w = exp(-2 pi i / L); then
+// q = exp(-i pi k / 2L) V_k gives c_k = Re q and c_{L-k} = -Im q.
+template <typename T, int L, int K>
+__device__ __forceinline__ void dct2_post(T (&a)[L], const T (&re)[L / 2], const T (&im)[L / 2]) {
+    constexpr int M = L / 2;
+    if constexpr (K <= M) {
+        constexpr int k1 = K % M, k2 = (M - K) % M;
+        constexpr double wc = cospi_ratio(2 * K, L), ws = -sinpi_ratio(2 * K, L);
+        constexpr double qc = cospi_ratio(K, 2 * L), qs = -sinpi_ratio(K, 2 * L);
+        constexpr double s0 = 1.0 / sqrt_c(double(L)), sk = sqrt_c(2.0 / double(L));
+        const T er = T(0.5) * (re[k1] + re[k2]), ei = T(0.5) * (im[k1] - im[k2]);
+        const T orr = T(0.5) * (im[k1] + im[k2]), oi = T(-0.5) * (re[k1] - re[k2]);
+        const T vr = er + (orr * T(wc) - oi * T(ws)), vi = ei + (orr * T(ws) + oi * T(wc));
+        const T qr = vr * T(qc) - vi * T(qs), qi = vr * T(qs) + vi * T(qc);
+        if constexpr (K == 0) a[0] = qr * T(s0);
+        else if constexpr (K == M) a[M] = qr * T(sk);
+        else { a[K] = qr * T(sk); a[L - K] = -qi * T(sk); }
+        dct2_post<T, L, K + 1>(a, re, im);
+    }
+}
+
+// Orthonormal DCT-II of L (power of two) values in registers:
+// c_k = a_k sum_l x_l cos(pi (2l + 1) k / (2L)), a_0 = sqrt(1/L), a_k = sqrt(2/L).
+// Makhoul (1980): reorder v_n = x_{2n}, v_{L-1-n} = x_{2n+1}; the DCT is
+// Re(exp(-i pi k / (2L)) V_k) with V the L-point DFT of v, obtained from an
+// L/2-point complex FFT of (v_{2m} + i v_{2m+1}).
+template <typename T, int L> __device__ __forceinline__ void dct2_ortho(T (&a)[L]) {
+    if constexpr (L == 1) {
+        return;
+    } else if constexpr (L == 2) {
+        const T h = T(0.70710678118654752440084436210484903928);
+        T s = (a[0] + a[1]) * h, d = (a[0] - a[1]) * h;
+        a[0] = s; a[1] = d;
+    } else {
+        constexpr int M = L / 2;
+        T re[M], im[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int j0 = 2 * m, j1 = 2 * m + 1;            // positions in v
+            re[m] = j0 < M ? a[2 * j0] : a[2 * (L - 1 - j0) + 1];
+            im[m] = j1 < M ? a[2 * j1] : a[2 * (L - 1 - j1) + 1];
+        }
+        reg_fft<T, M, false>(re, im);
+        dct2_post<T, L, 0>(a, re, im);      // inputs now live in re/im
+    }
+}
+
+// DCT-III pre-processing: V_k = exp(i pi k / 2L) (X_k - i X_{L-k}) with the
+// orthonormal scaling undone and the 1/M of the inverse FFT folded in.
+template <typename T, int L, int K>
+__device__ __forceinline__ void dct3_pre(const T (&a)[L], T (&vr)[L / 2 + 1], T (&vi)[L / 2 + 1]) {
+    constexpr int M = L / 2;
+    if constexpr (K <= M) {
+        constexpr double s0 = sqrt_c(double(L)) / double(M);
+        constexpr double sk = sqrt_c(double(L) / 2.0) / double(M);
+        constexpr double qc = cospi_ratio(K, 2 * L), qs = sinpi_ratio(K, 2 * L);
+        const T xr = (K == 0 ? T(s0) : T(sk)) * a[K];
+        const T xi = K == 0 ? T(0) : -(T(sk) * a[(L - K) % L]);
+        vr[K] = xr * T(qc) - xi * T(qs);
+        vi[K] = xr * T(qs) + xi * T(qc);
+        dct3_pre<T, L, K + 1>(a, vr, vi);
+    }
+}
+
+// Z_k = E + i O, E = (V_k + conj V_{M-k}) / 2, O = exp(2 pi i k / L) (V_k - conj V_{M-k}) / 2
+template <typename T, int L, int K>
+__device__ __forceinline__ void dct3_mid(const T (&vr)[L / 2 + 1], const T (&vi)[L / 2 + 1], T (&re)[L / 2],
+                                         T (&im)[L / 2]) {
+    constexpr int M = L / 2;
+    if constexpr (K < M) {
+        constexpr double wc = cospi_ratio(2 * K, L), ws = sinpi_ratio(2 * K, L);
+        const T er = T(0.5) * (vr[K] + vr[M - K]), ei = T(0.5) * (vi[K] - vi[M - K]);
+        const T dr = T(0.5) * (vr[K] - vr[M - K]), di = T(0.5) * (vi[K] + vi[M - K]);
+        const T orr = dr * T(wc) - di * T(ws), oi = dr * T(ws) + di * T(wc);
+        re[K] = er - oi;
+        im[K] = ei + orr;
+        dct3_mid<T, L, K + 1>(vr, vi, re, im);
+    }
+}
+
+// Orthonormal DCT-III (the inverse / transpose of dct2_ortho).
+template <typename T, int L> __device__ __forceinline__ void dct3_ortho(T (&a)[L]) {
+    if constexpr (L == 1) {
+        return;
+    } else if constexpr (L == 2) {
+        const T h = T(0.70710678118654752440084436210484903928);
+        T s = (a[0] + a[1]) * h, d = (a[0] - a[1]) * h;
+        a[0] = s; a[1] = d;
+    } else {
+        constexpr int M = L / 2;
+        T vr[M + 1], vi[M + 1];
+        dct3_pre<T, L, 0>(a, vr, vi);
+        T re[M], im[M];
+        dct3_mid<T, L, 0>(vr, vi, re, im);
+        reg_fft<T, M, true>(re, im);
+        // v_{2m} = Re z_m, v_{2m+1} = Im z_m; x_{2n} = v_n, x_{2n+1} = v_{L-1-n}
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int j0 = 2 * m, j1 = 2 * m + 1;
+            if (j0 < M) a[2 * j0] = re[m]; else a[2 * (L - 1 - j0) + 1] = re[m];
+            if (j1 < M) a[2 * j1] = im[m]; else a[2 * (L - 1 - j1) + 1] = im[m];
+        }
+    }
+}
+
+}  // namespace muffin

@@ -1,0 +1,32 @@
+// Workspace layout and host-only helpers shared by the C ABI translation
+// units.  Byte offsets into the caller's device workspace, each 256-B aligned.
+#pragma once
+#include <stddef.h>
+
+#include "muffin.h"
+
+namespace muffin {
+
+constexpr size_t kAlign = 256;
+constexpr int kNumState = 5;     // z_P, z_T, S, Gamma_S, Gamma_V
+constexpr int kNumRed = 10;      // FP64 partial sums per block (see RedSlot)
+enum StateIdx { ST_ZP = 0, ST_ZT = 1, ST_S = 2, ST_GS = 3, ST_GV = 4 };
+
+struct Layout {
+    size_t state[kNumState];
+    size_t brest, x, z, yf, h2, h2nyq, tw, tw64, dctm, partials, sums;
+    size_t total;
+    size_t setup_scratch_bytes, state_region_bytes;
+    int nblk;
+};
+
+void set_error(const char* fmt, ...);
+int validate_shape(const muffin_shape* s);
+int validate_params(const muffin_params* p);
+Layout make_layout(const muffin_shape* s);
+int max_blocks_host(int L, int ny, int nx);
+
+// register width of the dense DCT used for band counts that are not powers of two
+inline int dense_width(int L) { return L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 32 ? 32 : L)); }
+
+}  // namespace muffin

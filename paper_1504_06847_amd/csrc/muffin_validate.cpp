@@ -1,0 +1,162 @@
+// Host-only part of the C ABI: parameter defaults, validation, workspace
+// sizing and the thread-local error message.  No HIP runtime calls, so it
+// builds and runs without a GPU (and under the host sanitizers).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "muffin.h"
+#include "muffin_layout.hpp"
+
+namespace muffin {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+static bool pow2_in_range(int n) { return n >= 8 && n <= 4096 && (n & (n - 1)) == 0; }
+
+int validate_shape(const muffin_shape* s) {
+    if (!s) { set_error("shape is NULL"); return MUFFIN_EINVAL; }
+    if (s->L < 1) { set_error("L = %d < 1", s->L); return MUFFIN_EINVAL; }
+    if (s->nx <= 0 || s->ny <= 0) { set_error("image size %d x %d is not positive", s->ny, s->nx); return MUFFIN_EINVAL; }
+    if (!pow2_in_range(s->nx) || !pow2_in_range(s->ny)) {
+        set_error("image size %d x %d: each side must be a power of two in [8, 4096]", s->ny, s->nx);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    if (s->L > MUFFIN_MAX_BANDS) {
+        set_error("L = %d exceeds MUFFIN_MAX_BANDS = %d", s->L, MUFFIN_MAX_BANDS);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    if (s->L > 32 && (s->L & (s->L - 1)) != 0) {
+        set_error("L = %d: band counts above 32 must be powers of two", s->L);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    if (s->dtype != MUFFIN_F32 && s->dtype != MUFFIN_F64) {
+        set_error("dtype %d is neither MUFFIN_F32 nor MUFFIN_F64", s->dtype);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    const double vox = double(s->L) * s->nx * s->ny;
+    if (vox > 4.0e9) { set_error("cube of %.3g voxels is too large", vox); return MUFFIN_EUNSUPPORTED; }
+    return MUFFIN_OK;
+}
+
+int validate_params(const muffin_params* p) {
+    if (!p) { set_error("params is NULL"); return MUFFIN_EINVAL; }
+    const double mus[3] = {p->mu_eps, p->mu_s, p->mu_nu};
+    const char* mun[3] = {"mu_eps", "mu_s", "mu_nu"};
+    for (int i = 0; i < 3; ++i) {
+        if (!std::isfinite(mus[i]) || mus[i] < 0.0) {
+            set_error("%s = %g must be finite and >= 0", mun[i], mus[i]);
+            return MUFFIN_EINVAL;
+        }
+    }
+    const double rhos[4] = {p->rho_P, p->rho_T, p->rho_V, p->rho_S};
+    const char* rhon[4] = {"rho_P", "rho_T", "rho_V", "rho_S"};
+    for (int i = 0; i < 4; ++i) {
+        if (!std::isfinite(rhos[i]) || rhos[i] <= 0.0) {
+            set_error("%s = %g must be finite and > 0", rhon[i], rhos[i]);
+            return MUFFIN_EINVAL;
+        }
+    }
+    if (!std::isfinite(p->eps_abs) || p->eps_abs < 0.0 || !std::isfinite(p->eps_rel) || p->eps_rel < 0.0) {
+        set_error("eps_abs = %g, eps_rel = %g must be finite and >= 0", p->eps_abs, p->eps_rel);
+        return MUFFIN_EINVAL;
+    }
+    if (p->check_every < 1) { set_error("check_every = %d < 1", p->check_every); return MUFFIN_EINVAL; }
+    if (p->n_s != 1 || p->spatial[0] != MUFFIN_DIRAC) {
+        set_error("only the Dirac spatial basis (n_s = 1) is built (n_s = %d, spatial[0] = %d)",
+                  p->n_s, p->spatial[0]);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    if (p->spectral != MUFFIN_DCT2_ORTHO) {
+        set_error("spectral transform %d is not MUFFIN_DCT2_ORTHO", p->spectral);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    return MUFFIN_OK;
+}
+
+static size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+Layout make_layout(const muffin_shape* s) {
+    Layout lay{};
+    const size_t sz = s->dtype == MUFFIN_F64 ? 8 : 4;
+    const size_t V = size_t(s->L) * s->ny * s->nx;
+    const size_t M = size_t(s->nx) / 2;
+    const size_t HS = size_t(s->L) * s->ny * M;               // packed half-spectrum entries
+    const int NT = s->nx > s->ny ? s->nx : s->ny;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    for (int i = 0; i < kNumState; ++i) lay.state[i] = take(V * sz);
+    lay.brest = take(V * sz);
+    lay.x = take(V * sz);
+    lay.z = take(HS * 2 * sz);
+    lay.yf = take(HS * 2 * sz);
+    lay.h2 = take(HS * sz);
+    lay.h2nyq = take(size_t(s->L) * s->ny * sz);
+    lay.tw = take(size_t(NT) * 2 * sz);
+    lay.tw64 = take(size_t(NT) * 16);
+    lay.dctm = take(size_t(dense_width(s->L)) * dense_width(s->L) * sz);
+    lay.nblk = max_blocks_host(s->L, s->ny, s->nx);
+    lay.partials = take(size_t(lay.nblk) * kNumRed * 8);
+    lay.sums = take(64 * 8);
+    lay.total = off;
+    // setup scratch: two FP64 packed spectra, carved out of the state region
+    lay.setup_scratch_bytes = 2 * HS * 16;
+    lay.state_region_bytes = lay.x - lay.state[0];
+    return lay;
+}
+
+int max_blocks_host(int L, int ny, int nx) {
+    const long npix = long(ny) * nx;
+    const long spec = (npix + 255) / 256;
+    const long col = long(L) * (nx / 2);
+    long m = spec > col ? spec : col;
+    if (m < 8192) m = 8192;
+    return int(m);
+}
+
+}  // namespace muffin
+
+using namespace muffin;
+
+extern "C" {
+
+void muffin_default_params(muffin_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->mu_eps = 1e-3;
+    p->mu_s = 0.5;
+    p->mu_nu = 1.0;
+    p->rho_P = 1.0;
+    p->rho_T = 5.0;
+    p->rho_V = 2.0;
+    p->rho_S = 1.0;
+    p->n_s = 1;
+    p->spatial[0] = MUFFIN_DIRAC;
+    p->spectral = MUFFIN_DCT2_ORTHO;
+    p->check_every = 10;
+    p->eps_abs = 1e-5;
+    p->eps_rel = 1e-4;
+}
+
+int muffin_validate(const muffin_shape* shape, const muffin_params* params) {
+    int rc = validate_shape(shape);
+    if (rc != MUFFIN_OK) return rc;
+    return validate_params(params);
+}
+
+size_t muffin_workspace_bytes(const muffin_shape* shape, const muffin_params* params) {
+    if (muffin_validate(shape, params) != MUFFIN_OK) return 0;
+    return make_layout(shape).total;
+}
+
+const char* muffin_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+"""Python front end of libmuffin: a ``Solver`` per cube.
+
+PyTorch provides the device memory (inputs, workspace, outputs) and the
+stream; the reconstruction itself runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_char_p, c_double, c_void_p
+
+import torch
+
+from . import lib as L
+
+PARAM_NAMES = ("mu_eps", "mu_s", "mu_nu", "rho_P", "rho_T", "rho_V", "rho_S",
+               "check_every", "eps_abs", "eps_rel")
+
+
+def _as_cube(a, dtype, device):
+    t = a if isinstance(a, torch.Tensor) else torch.as_tensor(a)
+    t = t.to(device=device, dtype=dtype).contiguous()
+    if t.dim() != 3:
+        raise ValueError(f"expected a [L][ny][nx] cube, got shape {tuple(t.shape)}")
+    return t
+
+
+class Solver:
+    """ADMM reconstruction of one wide-band cube (Algorithm 1 of the paper).
+
+    ``psf`` and ``dirty`` are [L][ny][nx] arrays (PSF peak at (ny/2, nx/2)).
+    Keyword parameters: mu_eps, mu_s, mu_nu, rho_P, rho_T, rho_V, rho_S
+    (defaults: the paper's Section 4 values), ``rho`` to set the four rho's
+    at once, check_every, eps_abs, eps_rel, and ``dtype`` (torch.float32 or
+    torch.float64) for the iteration's precision.
+    """
+
+    def __init__(self, psf, dirty, *, dtype=torch.float32, device="cuda", stream=None, **params):
+        self._lib = L.load()
+        self._ctx = c_void_p()
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.dtype = dtype
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        psf_t = _as_cube(psf, dtype, self.device)
+        dirty_t = _as_cube(dirty, dtype, self.device)
+        if psf_t.shape != dirty_t.shape:
+            raise ValueError("psf and dirty must have the same shape")
+        Lb, ny, nx = psf_t.shape
+        self.shape = (Lb, ny, nx)
+        self._shape = L.MuffinShape(nx, ny, Lb, L.MUFFIN_F64 if dtype == torch.float64 else L.MUFFIN_F32)
+        self._params = self._make_params(params)
+        ws_bytes = self._lib.muffin_workspace_bytes(byref(self._shape), byref(self._params))
+        if ws_bytes == 0:
+            rc = self._lib.muffin_validate(byref(self._shape), byref(self._params))
+            L.check(rc, "muffin_validate", self._lib)
+        self._ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        self._ws_ptr = self._ws.data_ptr() + off
+        self._ws_bytes = ws_bytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rc = self._lib.muffin_setup(byref(self._ctx), byref(self._shape), byref(self._params),
+                                    c_void_p(psf_t.data_ptr()), c_void_p(dirty_t.data_ptr()),
+                                    c_void_p(self._ws_ptr), ws_bytes,
+                                    c_void_p(self.stream.cuda_stream))
+        L.check(rc, "muffin_setup", self._lib)
+
+    # -------------------------------------------------------------- params
+    def _make_params(self, params):
+        kw = dict(params)
+        if "rho" in kw:
+            r = kw.pop("rho")
+            for k in ("rho_P", "rho_T", "rho_V", "rho_S"):
+                kw.setdefault(k, r)
+        unknown = set(kw) - set(PARAM_NAMES)
+        if unknown:
+            raise TypeError(f"unknown parameters {sorted(unknown)}")
+        return L.make_params(self._lib, **kw)
+
+    @property
+    def params(self):
+        return {k: getattr(self._params, k) for k in PARAM_NAMES}
+
+    def set_params(self, **params):
+        cur = self.params
+        cur.update(params)
+        if "rho" in params:
+            r = cur.pop("rho")
+            for k in ("rho_P", "rho_T", "rho_V", "rho_S"):
+                cur[k] = r
+        p = self._make_params(cur)
+        L.check(self._lib.muffin_set_params(self._ctx, byref(p)), "muffin_set_params", self._lib)
+        self._params = p
+
+    # -------------------------------------------------------------- iteration
+    def iterate(self, n: int = 1):
+        L.check(self._lib.muffin_iterate(self._ctx, int(n)), "muffin_iterate", self._lib)
+        return self
+
+    def step_report(self) -> dict:
+        rep = L.MuffinReport()
+        L.check(self._lib.muffin_step_report(self._ctx, byref(rep)), "muffin_step_report", self._lib)
+        return rep.asdict()
+
+    def solve(self, max_iter: int = 350) -> dict:
+        rep = L.MuffinReport()
+        rc = L.check(self._lib.muffin_solve(self._ctx, int(max_iter), byref(rep)), "muffin_solve", self._lib)
+        d = rep.asdict()
+        d["status"] = rc
+        return d
+
+    @property
+    def iterations(self) -> int:
+        return self._lib.muffin_iterations(self._ctx)
+
+    def _empty_cube(self):
+        return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+
+    @property
+    def x(self) -> torch.Tensor:
+        """Current X iterate (step I output)."""
+        out = self._empty_cube()
+        L.check(self._lib.muffin_get_x(self._ctx, c_void_p(out.data_ptr())), "muffin_get_x", self._lib)
+        return out
+
+    @property
+    def p(self) -> torch.Tensor:
+        """Current P = max(0, X - Gamma_P / rho_P)."""
+        out = self._empty_cube()
+        L.check(self._lib.muffin_get_p(self._ctx, c_void_p(out.data_ptr())), "muffin_get_p", self._lib)
+        return out
+
+    # -------------------------------------------------------------- state
+    def state_bytes(self) -> int:
+        return self._lib.muffin_state_bytes(self._ctx)
+
+    def get_state(self) -> torch.Tensor:
+        n = self.state_bytes()
+        buf = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        view = buf[off:off + n]
+        L.check(self._lib.muffin_get_state(self._ctx, c_void_p(view.data_ptr())), "muffin_get_state", self._lib)
+        return view
+
+    def set_state(self, state: torch.Tensor):
+        if state.data_ptr() % 256:
+            aligned = torch.empty(state.numel() + 256, dtype=torch.uint8, device=self.device)
+            off = (-aligned.data_ptr()) % 256
+            aligned[off:off + state.numel()].copy_(state)
+            state = aligned[off:off + state.numel()]
+        L.check(self._lib.muffin_set_state(self._ctx, c_void_p(state.data_ptr())), "muffin_set_state", self._lib)
+
+    def reset(self):
+        L.check(self._lib.muffin_reset(self._ctx), "muffin_reset", self._lib)
+
+    # -------------------------------------------------------------- timing
+    def profile(self, n_iter: int = 10) -> dict:
+        cap = 16
+        ms = (c_double * cap)()
+        names = (c_char_p * cap)()
+        k = L.check(self._lib.muffin_profile(self._ctx, int(n_iter), ms, names, cap), "muffin_profile", self._lib)
+        return {names[i].decode(): ms[i] for i in range(k)}
+
+    # -------------------------------------------------------------- lifetime
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.muffin_destroy(self._ctx)
+            self._ctx = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,143 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/muffin.h declares, and its host-only validation returns the documented
+codes.  No call here reaches the device."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "muffin.h")
+
+pytestmark = pytest.mark.cpu
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(muffin_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1504_06847_amd import lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libmuffin.so is not built: run python -m paper_1504_06847_amd.build")
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 18
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    from paper_1504_06847_amd import lib as L
+    bound = {n for n, _, _ in L.SIGNATURES}
+    assert set(_declared_functions()) == bound
+
+
+def test_struct_layouts_match_header():
+    from paper_1504_06847_amd import lib as L
+    # muffin_params: 7 doubles, n_s, spatial[9], spectral, check_every, 2 doubles
+    assert ctypes.sizeof(L.MuffinParams) == 7 * 8 + 4 + 36 + 4 + 4 + 2 * 8
+    assert ctypes.sizeof(L.MuffinShape) == 16
+    assert ctypes.sizeof(L.MuffinReport) == 8 + 6 * 8
+
+
+def _shape(L, nx=64, ny=64, Lb=8, dtype=0):
+    return L.MuffinShape(nx, ny, Lb, dtype)
+
+
+def test_default_params_are_the_papers(lib):
+    from paper_1504_06847_amd import lib as L
+    p = L.make_params(lib)
+    assert (p.mu_eps, p.mu_s, p.mu_nu) == (1e-3, 0.5, 1.0)
+    assert (p.rho_P, p.rho_T, p.rho_V, p.rho_S) == (1.0, 5.0, 2.0, 1.0)
+    assert p.n_s == 1 and p.spatial[0] == L.MUFFIN_DIRAC and p.check_every == 10
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("mu_s", -1.0, -1), ("mu_nu", float("nan"), -1), ("mu_eps", float("inf"), -1),
+    ("rho_P", 0.0, -1), ("rho_T", -2.0, -1), ("rho_V", float("nan"), -1),
+    ("check_every", 0, -1), ("eps_abs", -1e-3, -1), ("n_s", 9, -2), ("spectral", 3, -2),
+])
+def test_parameter_validation(lib, field, value, code):
+    from paper_1504_06847_amd import lib as L
+    p = L.make_params(lib, **{field: value})
+    s = _shape(L)
+    assert lib.muffin_validate(ctypes.byref(s), ctypes.byref(p)) == code
+    assert lib.muffin_workspace_bytes(ctypes.byref(s), ctypes.byref(p)) == 0
+    assert field.split("_")[0] in L.last_error(lib) or field in L.last_error(lib)
+
+
+@pytest.mark.parametrize("nx,ny,Lb,dtype,code", [
+    (64, 64, 8, 0, 0), (8, 8, 1, 1, 0), (4096, 8, 64, 0, 0), (64, 64, 15, 0, 0),
+    (64, 64, 0, 0, -1), (0, 64, 8, 0, -1), (60, 64, 8, 0, -2), (64, 8192, 8, 0, -2),
+    (4, 64, 8, 0, -2), (64, 64, 65, 0, -2), (64, 64, 48, 0, -2), (64, 64, 8, 7, -2),
+])
+def test_shape_validation(lib, nx, ny, Lb, dtype, code):
+    from paper_1504_06847_amd import lib as L
+    p = L.make_params(lib)
+    s = L.MuffinShape(nx, ny, Lb, dtype)
+    assert lib.muffin_validate(ctypes.byref(s), ctypes.byref(p)) == code
+    ws = lib.muffin_workspace_bytes(ctypes.byref(s), ctypes.byref(p))
+    assert (ws > 0) == (code == 0)
+
+
+def test_workspace_grows_with_the_cube(lib):
+    from paper_1504_06847_amd import lib as L
+    p = L.make_params(lib)
+    a = lib.muffin_workspace_bytes(ctypes.byref(L.MuffinShape(64, 64, 8, 0)), ctypes.byref(p))
+    b = lib.muffin_workspace_bytes(ctypes.byref(L.MuffinShape(64, 64, 16, 0)), ctypes.byref(p))
+    c = lib.muffin_workspace_bytes(ctypes.byref(L.MuffinShape(64, 64, 8, 1)), ctypes.byref(p))
+    V = 64 * 64 * 8
+    # 7 cubes + 3 half-spectrum cube equivalents (packed Z, Yf) + |h|^2 at least
+    assert a >= 9 * 4 * V and b > a and c > a
+
+
+def test_setup_rejects_bad_arguments_before_touching_the_device(lib):
+    from paper_1504_06847_amd import lib as L
+    p = L.make_params(lib)
+    s = L.MuffinShape(64, 64, 8, 0)
+    ctx = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.muffin_setup(None, ctypes.byref(s), ctypes.byref(p), dummy, dummy, dummy, 1 << 30, None) == -1
+    assert lib.muffin_setup(ctypes.byref(ctx), ctypes.byref(s), ctypes.byref(p), None, dummy, dummy, 1 << 30, None) == -1
+    assert lib.muffin_setup(ctypes.byref(ctx), ctypes.byref(s), ctypes.byref(p), dummy, dummy, dummy, 16, None) == -3
+    bad = ctypes.c_void_p(0x1001)
+    assert lib.muffin_setup(ctypes.byref(ctx), ctypes.byref(s), ctypes.byref(p), dummy, dummy, bad, 1 << 40, None) == -3
+    p2 = L.make_params(lib, rho_S=0.0)
+    assert lib.muffin_setup(ctypes.byref(ctx), ctypes.byref(s), ctypes.byref(p2), dummy, dummy, dummy, 1 << 40, None) == -1
+    assert ctx.value is None
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    from paper_1504_06847_amd import lib as L
+    assert lib.muffin_iterate(None, 1) == -1
+    assert lib.muffin_get_x(None, None) == -1
+    assert lib.muffin_reset(None) == -1
+    assert lib.muffin_destroy(None) == 0
+    assert lib.muffin_state_bytes(None) == 0
+    rep = L.MuffinReport()
+    assert lib.muffin_solve(None, 10, ctypes.byref(rep)) == -1
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="no host compiler")
+def test_validation_unit_under_host_sanitizers(tmp_path):
+    """Build the host-only validation unit with ASan + UBSan and drive it."""
+    csrc = os.path.join(ROOT, "paper_1504_06847_amd", "csrc")
+    exe = tmp_path / "validate_san"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", f"-I{ROOT}/include", f"-I{csrc}",
+           os.path.join(csrc, "muffin_validate.cpp"),
+           os.path.join(ROOT, "tests", "host", "validate_driver.cpp"), "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ALL OK" in r.stdout
