@@ -165,8 +165,13 @@ size_t muffin_state_bytes(const muffin_ctx* ctx);
 int muffin_get_state(muffin_ctx* ctx, void* dst);
 int muffin_set_state(muffin_ctx* ctx, const void* src);
 
-/* Replace the parameters (mu's, rho's) without a new setup.  The state is
-   kept; the iteration continues with the new values.  Errors: EINVAL. */
+/* Replace the parameters (mu's, rho's) without a new setup.  The ADMM
+   variables are kept: P, Gamma_P, S, Gamma_S, Gamma_V exactly, and T, Gamma_T
+   exactly when mu_s is unchanged, so a change of the rho's continues
+   Algorithm 1 with the multipliers held fixed (the rule for varying penalty
+   parameters, Boyd et al. 2011, Sec. 3.4.1).  With a new mu_s the stored
+   input of the spatial soft threshold is kept, i.e. the run continues from a
+   warm start of the new problem.  Errors: EINVAL, EUNSUPPORTED, EDEVICE. */
 int muffin_set_params(muffin_ctx* ctx, const muffin_params* params);
 
 /* Zero the ADMM state (Algorithm 1 initialisation) and the iteration count. */

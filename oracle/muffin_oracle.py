@@ -93,6 +93,10 @@ class Params:
             return cls(**{f.name: float(p[f.name]) for f in fields(cls)})
         return cls(**{f.name: float(getattr(p, f.name)) for f in fields(cls)})
 
+    def with_(self, **kw):
+        from dataclasses import replace
+        return replace(self, **kw)
+
     @property
     def rho_Q(self):
         # eq. Qlsimp with the Dirac basis: n_s = 1

@@ -401,6 +401,13 @@ int muffin_set_params(muffin_ctx* c, const muffin_params* params) {
     if (int rc = check_ctx(c)) return rc;
     int rc = validate_params(params);
     if (rc) return rc;
+    const muffin_params old = c->params;
+    if (old.rho_P != params->rho_P || old.rho_T != params->rho_T) {
+        // keep P, Gamma_P and T, Gamma_T of the stored state under the new rho's
+        HIP_TRY(launch_reencode(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), voxels(c->shape),
+                                old.rho_P / params->rho_P, old.rho_T / params->rho_T,
+                                old.mu_s / old.rho_T, c->stream));
+    }
     c->params = *params;
     return recompute_brest(c);
 }

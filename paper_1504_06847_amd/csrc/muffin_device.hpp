@@ -204,7 +204,7 @@ template <int N> constexpr int bitrev(int i) {
 }
 
 template <typename T, int N, bool INV, int LEN, int K>
-__device__ __forceinline__ void reg_fft_k(T (&re)[N], T (&im)[N]) {
+__host__ __device__ __forceinline__ void reg_fft_k(T (&re)[N], T (&im)[N]) {
     if constexpr (K < LEN / 2) {
         constexpr double c = cospi_ratio(2 * K, LEN);
         constexpr double s = INV ? sinpi_ratio(2 * K, LEN) : -sinpi_ratio(2 * K, LEN);
@@ -222,14 +222,14 @@ __device__ __forceinline__ void reg_fft_k(T (&re)[N], T (&im)[N]) {
 }
 
 template <typename T, int N, bool INV, int LEN>
-__device__ __forceinline__ void reg_fft_len(T (&re)[N], T (&im)[N]) {
+__host__ __device__ __forceinline__ void reg_fft_len(T (&re)[N], T (&im)[N]) {
     if constexpr (LEN <= N) {
         reg_fft_k<T, N, INV, LEN, 0>(re, im);
         reg_fft_len<T, N, INV, 2 * LEN>(re, im);
     }
 }
 
-template <typename T, int N, bool INV> __device__ __forceinline__ void reg_fft(T (&re)[N], T (&im)[N]) {
+template <typename T, int N, bool INV> __host__ __device__ __forceinline__ void reg_fft(T (&re)[N], T (&im)[N]) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const int j = bitrev<N>(i);
@@ -241,26 +241,46 @@ template <typename T, int N, bool INV> __device__ __forceinline__ void reg_fft(T
     reg_fft_len<T, N, INV, 2>(re, im);
 }
 
-// DCT-II post-processing for output pair k: from the L/2-point FFT Z of
-// (v_{2m} + i v_{2m+1}), V_k = E + w^k O with E = (Z_k + conj Z_{M-k})/2,
-// O = -i (Z_k - conj Z_{M-k})/2, w = exp(-2 pi i / L); then
-// q = exp(-i pi k / 2L) V_k gives c_k = Re q and c_{L-k} = -Im q.
+// DCT-II post-processing of output index K (0 <= K <= M = L/2) from the
+// L/2-point FFT Z of (v_{2m} + i v_{2m+1}):
+//   V_K = E + w^K O, E = (Z_K + conj Z_{M-K}) / 2, O = -i (Z_K - conj Z_{M-K}) / 2,
+//   w = exp(-2 pi i / L);  q = exp(-i pi K / 2L) V_K;  c_K = Re q, c_{L-K} = -Im q.
 template <typename T, int L, int K>
-__device__ __forceinline__ void dct2_post(T (&a)[L], const T (&re)[L / 2], const T (&im)[L / 2]) {
+__host__ __device__ __forceinline__ void dct2_one(T zr, T zi, T mr, T mi, T& qr, T& qi) {
+    constexpr double wc = cospi_ratio(2 * K, L), ws = -sinpi_ratio(2 * K, L);
+    constexpr double qc = cospi_ratio(K, 2 * L), qs = -sinpi_ratio(K, 2 * L);
+    const T er = T(0.5) * (zr + mr), ei = T(0.5) * (zi - mi);
+    const T orr = T(0.5) * (zi + mi), oi = T(-0.5) * (zr - mr);
+    const T vr = er + (orr * T(wc) - oi * T(ws)), vi = ei + (orr * T(ws) + oi * T(wc));
+    qr = vr * T(qc) - vi * T(qs);
+    qi = vr * T(qs) + vi * T(qc);
+}
+
+// Outputs K and M - K are produced together from Z_K and Z_{M-K}, so the four
+// registers consumed become the four outputs (the transform stays in place).
+template <typename T, int L, int K>
+__host__ __device__ __forceinline__ void dct2_post(T (&a)[L], T (&re)[L / 2], T (&im)[L / 2]) {
     constexpr int M = L / 2;
-    if constexpr (K <= M) {
-        constexpr int k1 = K % M, k2 = (M - K) % M;
-        constexpr double wc = cospi_ratio(2 * K, L), ws = -sinpi_ratio(2 * K, L);
-        constexpr double qc = cospi_ratio(K, 2 * L), qs = -sinpi_ratio(K, 2 * L);
-        constexpr double s0 = 1.0 / sqrt_c(double(L)), sk = sqrt_c(2.0 / double(L));
-        const T er = T(0.5) * (re[k1] + re[k2]), ei = T(0.5) * (im[k1] - im[k2]);
-        const T orr = T(0.5) * (im[k1] + im[k2]), oi = T(-0.5) * (re[k1] - re[k2]);
-        const T vr = er + (orr * T(wc) - oi * T(ws)), vi = ei + (orr * T(ws) + oi * T(wc));
-        const T qr = vr * T(qc) - vi * T(qs), qi = vr * T(qs) + vi * T(qc);
-        if constexpr (K == 0) a[0] = qr * T(s0);
-        else if constexpr (K == M) a[M] = qr * T(sk);
-        else { a[K] = qr * T(sk); a[L - K] = -qi * T(sk); }
+    constexpr double s0 = 1.0 / sqrt_c(double(L)), sk = sqrt_c(2.0 / double(L));
+    if constexpr (K == 0) {
+        T q0r, q0i, qmr, qmi;
+        dct2_one<T, L, 0>(re[0], im[0], re[0], im[0], q0r, q0i);
+        dct2_one<T, L, M>(re[0], im[0], re[0], im[0], qmr, qmi);
+        a[0] = q0r * T(s0);
+        a[M] = qmr * T(sk);
+        dct2_post<T, L, 1>(a, re, im);
+    } else if constexpr (2 * K < M) {
+        constexpr int J = M - K;
+        T qkr, qki, qjr, qji;
+        dct2_one<T, L, K>(re[K], im[K], re[J], im[J], qkr, qki);
+        dct2_one<T, L, J>(re[J], im[J], re[K], im[K], qjr, qji);
+        a[K] = qkr * T(sk); a[L - K] = -qki * T(sk);
+        a[J] = qjr * T(sk); a[L - J] = -qji * T(sk);
         dct2_post<T, L, K + 1>(a, re, im);
+    } else if constexpr (2 * K == M) {
+        T qr, qi;
+        dct2_one<T, L, K>(re[K], im[K], re[K], im[K], qr, qi);
+        a[K] = qr * T(sk); a[L - K] = -qi * T(sk);
     }
 }
 
@@ -269,7 +289,7 @@ __device__ __forceinline__ void dct2_post(T (&a)[L], const T (&re)[L / 2], const
 // Makhoul (1980): reorder v_n = x_{2n}, v_{L-1-n} = x_{2n+1}; the DCT is
 // Re(exp(-i pi k / (2L)) V_k) with V the L-point DFT of v, obtained from an
 // L/2-point complex FFT of (v_{2m} + i v_{2m+1}).
-template <typename T, int L> __device__ __forceinline__ void dct2_ortho(T (&a)[L]) {
+template <typename T, int L> __host__ __device__ __forceinline__ void dct2_ortho(T (&a)[L]) {
     if constexpr (L == 1) {
         return;
     } else if constexpr (L == 2) {
@@ -290,41 +310,59 @@ template <typename T, int L> __device__ __forceinline__ void dct2_ortho(T (&a)[L
     }
 }
 
-// DCT-III pre-processing: V_k = exp(i pi k / 2L) (X_k - i X_{L-k}) with the
-// orthonormal scaling undone and the 1/M of the inverse FFT folded in.
+// DCT-III pre-processing for index K (0 <= K <= M): with the orthonormal
+// scaling undone and the 1/M of the inverse FFT folded in,
+//   V_K = exp(i pi K / 2L) (X_K - i X_{L-K})  (X_L = 0).
 template <typename T, int L, int K>
-__device__ __forceinline__ void dct3_pre(const T (&a)[L], T (&vr)[L / 2 + 1], T (&vi)[L / 2 + 1]) {
+__host__ __device__ __forceinline__ void dct3_v(T xk, T xlk, T& vr, T& vi) {
     constexpr int M = L / 2;
-    if constexpr (K <= M) {
-        constexpr double s0 = sqrt_c(double(L)) / double(M);
-        constexpr double sk = sqrt_c(double(L) / 2.0) / double(M);
-        constexpr double qc = cospi_ratio(K, 2 * L), qs = sinpi_ratio(K, 2 * L);
-        const T xr = (K == 0 ? T(s0) : T(sk)) * a[K];
-        const T xi = K == 0 ? T(0) : -(T(sk) * a[(L - K) % L]);
-        vr[K] = xr * T(qc) - xi * T(qs);
-        vi[K] = xr * T(qs) + xi * T(qc);
-        dct3_pre<T, L, K + 1>(a, vr, vi);
-    }
+    constexpr double s0 = sqrt_c(double(L)) / double(M);
+    constexpr double sk = sqrt_c(double(L) / 2.0) / double(M);
+    constexpr double qc = cospi_ratio(K, 2 * L), qs = sinpi_ratio(K, 2 * L);
+    const T xr = (K == 0 ? T(s0) : T(sk)) * xk;
+    const T xi = K == 0 ? T(0) : -(T(sk) * xlk);
+    vr = xr * T(qc) - xi * T(qs);
+    vi = xr * T(qs) + xi * T(qc);
 }
 
-// Z_k = E + i O, E = (V_k + conj V_{M-k}) / 2, O = exp(2 pi i k / L) (V_k - conj V_{M-k}) / 2
+// Z_K = E + i O with E = (V_K + conj V_{M-K}) / 2, O = exp(2 pi i K / L) (V_K - conj V_{M-K}) / 2
 template <typename T, int L, int K>
-__device__ __forceinline__ void dct3_mid(const T (&vr)[L / 2 + 1], const T (&vi)[L / 2 + 1], T (&re)[L / 2],
-                                         T (&im)[L / 2]) {
+__host__ __device__ __forceinline__ void dct3_z(T vkr, T vki, T vjr, T vji, T& zr, T& zi) {
+    constexpr double wc = cospi_ratio(2 * K, L), ws = sinpi_ratio(2 * K, L);
+    const T er = T(0.5) * (vkr + vjr), ei = T(0.5) * (vki - vji);
+    const T dr = T(0.5) * (vkr - vjr), di = T(0.5) * (vki + vji);
+    const T orr = dr * T(wc) - di * T(ws), oi = dr * T(ws) + di * T(wc);
+    zr = er - oi;
+    zi = ei + orr;
+}
+
+// pairs (K, M - K): inputs X_K, X_{L-K}, X_{M-K}, X_{M+K} -> Z_K, Z_{M-K}
+template <typename T, int L, int K>
+__host__ __device__ __forceinline__ void dct3_pre(const T (&a)[L], T (&re)[L / 2], T (&im)[L / 2]) {
     constexpr int M = L / 2;
-    if constexpr (K < M) {
-        constexpr double wc = cospi_ratio(2 * K, L), ws = sinpi_ratio(2 * K, L);
-        const T er = T(0.5) * (vr[K] + vr[M - K]), ei = T(0.5) * (vi[K] - vi[M - K]);
-        const T dr = T(0.5) * (vr[K] - vr[M - K]), di = T(0.5) * (vi[K] + vi[M - K]);
-        const T orr = dr * T(wc) - di * T(ws), oi = dr * T(ws) + di * T(wc);
-        re[K] = er - oi;
-        im[K] = ei + orr;
-        dct3_mid<T, L, K + 1>(vr, vi, re, im);
+    if constexpr (K == 0) {
+        T v0r, v0i, vmr, vmi;
+        dct3_v<T, L, 0>(a[0], T(0), v0r, v0i);
+        dct3_v<T, L, M>(a[M], a[M], vmr, vmi);
+        dct3_z<T, L, 0>(v0r, v0i, vmr, vmi, re[0], im[0]);
+        dct3_pre<T, L, 1>(a, re, im);
+    } else if constexpr (2 * K < M) {
+        constexpr int J = M - K;
+        T vkr, vki, vjr, vji;
+        dct3_v<T, L, K>(a[K], a[L - K], vkr, vki);
+        dct3_v<T, L, J>(a[J], a[L - J], vjr, vji);
+        dct3_z<T, L, K>(vkr, vki, vjr, vji, re[K], im[K]);
+        dct3_z<T, L, J>(vjr, vji, vkr, vki, re[J], im[J]);
+        dct3_pre<T, L, K + 1>(a, re, im);
+    } else if constexpr (2 * K == M) {
+        T vr, vi;
+        dct3_v<T, L, K>(a[K], a[L - K], vr, vi);
+        dct3_z<T, L, K>(vr, vi, vr, vi, re[K], im[K]);
     }
 }
 
 // Orthonormal DCT-III (the inverse / transpose of dct2_ortho).
-template <typename T, int L> __device__ __forceinline__ void dct3_ortho(T (&a)[L]) {
+template <typename T, int L> __host__ __device__ __forceinline__ void dct3_ortho(T (&a)[L]) {
     if constexpr (L == 1) {
         return;
     } else if constexpr (L == 2) {
@@ -333,10 +371,8 @@ template <typename T, int L> __device__ __forceinline__ void dct3_ortho(T (&a)[L
         a[0] = s; a[1] = d;
     } else {
         constexpr int M = L / 2;
-        T vr[M + 1], vi[M + 1];
-        dct3_pre<T, L, 0>(a, vr, vi);
         T re[M], im[M];
-        dct3_mid<T, L, 0>(vr, vi, re, im);
+        dct3_pre<T, L, 0>(a, re, im);
         reg_fft<T, M, true>(re, im);
         // v_{2m} = Re z_m, v_{2m+1} = Im z_m; x_{2n} = v_n, x_{2n+1} = v_{L-1-n}
 #pragma unroll

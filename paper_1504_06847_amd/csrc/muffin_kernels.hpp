@@ -75,5 +75,8 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* S, const void* GS,
                         void* Brest, size_t n, const SpecArgs& a, hipStream_t s);
 hipError_t launch_positive(int dtype, const void* z, void* out, size_t n, hipStream_t s);
+// z_P <- max(0, z_P) - rP max(0, -z_P);  z_T <- soft(z_T, tau) + rT clip(z_T, tau)
+hipError_t launch_reencode(int dtype, void* zP, void* zT, size_t n, double rP, double rT, double tau,
+                           hipStream_t s);
 
 }  // namespace muffin

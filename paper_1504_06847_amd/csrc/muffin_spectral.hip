@@ -246,6 +246,21 @@ k_brest(const T* __restrict__ zP, const T* __restrict__ zT, const T* __restrict_
     }
 }
 
+// Re-encode the prox inputs for new parameters so that P, Gamma_P (always)
+// and T, Gamma_T (when mu_s is unchanged) keep their values:
+//   z_P' = max(0, z_P) - (rho_P / rho_P') max(0, -z_P)          (= P - Gamma_P / rho_P')
+//   z_T' = soft(z_T, tau) + (rho_T / rho_T') clip(z_T, tau)     (= T - Gamma_T / rho_T')
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_reencode(T* __restrict__ zP, T* __restrict__ zT, long n, double rP, double rT, double tau) {
+    const T ratioP = T(rP), ratioT = T(rT), t = T(tau);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const T zp = zP[i], zt = zT[i];
+        zP[i] = (zp > T(0) ? zp : T(0)) - ratioP * (zp < T(0) ? -zp : T(0));
+        zT[i] = softt(zt, t) + ratioT * clipt(zt, t);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_positive(const T* __restrict__ z, T* __restrict__ o, long n) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -300,6 +315,15 @@ hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* S
     else
         hipLaunchKernelGGL((k_brest<double>), dim3(grid_for(n)), dim3(256), 0, s, (const double*)zP,
                            (const double*)zT, (const double*)S, (const double*)GS, (double*)Brest, (long)n, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reencode(int dtype, void* zP, void* zT, size_t n, double rP, double rT, double tau,
+                           hipStream_t s) {
+    if (dtype == 0)
+        hipLaunchKernelGGL((k_reencode<float>), dim3(grid_for(n)), dim3(256), 0, s, (float*)zP, (float*)zT, (long)n, rP, rT, tau);
+    else
+        hipLaunchKernelGGL((k_reencode<double>), dim3(grid_for(n)), dim3(256), 0, s, (double*)zP, (double*)zT, (long)n, rP, rT, tau);
     return hipGetLastError();
 }
 
