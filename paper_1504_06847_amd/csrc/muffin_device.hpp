@@ -59,6 +59,52 @@ constexpr double sqrt_c(double v) {
     return x;
 }
 
+// ---------------------------------------------------------------- band-strided access
+// Element (l, p) of a [L][npix] array through raw buffer instructions: the
+// descriptor (SGPRs) points at the first band of a group of 2^gshift bands,
+// the band offset inside the group is a scalar offset and the pixel offset is
+// one VGPR shared by every access of the thread.  With global loads the
+// compiler keeps one 64-bit address per band live, which costs two VGPRs per
+// band.  Groups keep every offset below 2^31 bytes (gshift from
+// band_group_shift, groups of at most 1 GiB).  Callers mask lanes whose pixel lies outside the array.
+constexpr int kBufWord3 = 0x00020000;   // raw 32-bit data format, gfx9 family
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+
+template <typename T> struct BandArray {
+    char* base;
+    unsigned band_bytes;
+    int gshift;
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int l) const {
+        const int g = l >> gshift;
+        return __builtin_amdgcn_make_buffer_rsrc(base + (size_t)(g << gshift) * band_bytes, (short)0,
+                                                 0x7fffffff, kBufWord3);
+    }
+    __device__ __forceinline__ unsigned soff(int l) const {
+        return (unsigned)(l & ((1 << gshift) - 1)) * band_bytes;
+    }
+    __device__ __forceinline__ T load(int l, unsigned lane_off) const {
+        if constexpr (sizeof(T) == 4) {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(l), lane_off, soff(l), 0));
+        } else {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(l), lane_off, soff(l), 0));
+        }
+    }
+    __device__ __forceinline__ void store(int l, unsigned lane_off, T v) const {
+        if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsrc(l), lane_off, soff(l), 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rsrc(l), lane_off, soff(l), 0);
+        }
+    }
+};
+
+// largest gshift with 2^gshift bands of band_bytes each within 2^30 bytes
+__host__ __device__ inline int band_group_shift(unsigned long long band_bytes) {
+    int g = 0;
+    while (g < 29 && (band_bytes << (g + 1)) <= (1ull << 30)) ++g;
+    return g;
+}
+
 // ---------------------------------------------------------------- small DFTs in registers
 // Forward: y_q = sum_r v_r exp(-2 pi i r q / R); inverse uses exp(+...).
 template <typename T, bool INV> __device__ __forceinline__ void dft2(cx<T>* v) {

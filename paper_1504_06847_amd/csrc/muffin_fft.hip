@@ -152,8 +152,19 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
     __shared__ cx<T> lds[NY * TC];
     __shared__ double red[NTH / 64];
     const int t = threadIdx.x;
-    const int band = blockIdx.y;
-    const int c0 = blockIdx.x * TC;
+    // XCD-aware tile order.  Work-groups go to the 8 XCDs round-robin in
+    // dispatch order, each XCD with its own L2.  Adjacent column tiles share
+    // the 128-B lines of Z, Yf and |h|^2 (a tile row is TC * 8 B of Z, TC * 4 B
+    // of |h|^2), so logical tiles 4j .. 4j+3 run as work-groups i, i+8, i+16,
+    // i+24: on one XCD, in consecutive dispatch rounds.
+    const unsigned ntiles = gridDim.x, nwg = gridDim.x * gridDim.y;
+    unsigned wg = blockIdx.x + blockIdx.y * gridDim.x;
+    if ((nwg & 31u) == 0) {
+        const unsigned r = wg >> 3, x = wg & 7u;
+        wg = (r >> 2) * 32u + x * 4u + (r & 3u);
+    }
+    const int band = int(wg / ntiles);
+    const int c0 = int(wg % ntiles) * TC;
     const long base = (long)band * NY * M;
     for (int i = t; i < NY * TC; i += NTH) {
         const int y = i / TC, c = i % TC;

@@ -27,6 +27,8 @@ namespace muffin {
 
 constexpr int SPEC_NTH = 256;
 
+// deterministic block sum (valid in thread 0): wavefront tree, then the
+// per-wave sums in wave order; blockDim.x is a multiple of 64, at most NTH
 template <int NTH> __device__ __forceinline__ double block_sum_s(double v, double* sh) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -35,7 +37,7 @@ template <int NTH> __device__ __forceinline__ double block_sum_s(double v, doubl
     __syncthreads();
     double r = 0.0;
     if (threadIdx.x == 0) {
-        for (int i = 0; i < NTH / 64; ++i) r += sh[i];
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
     }
     __syncthreads();
     return r;
@@ -74,13 +76,25 @@ __device__ __forceinline__ void dct_any(T (&v)[LT], const T* __restrict__ D, int
     else dct2_ortho<T, LT>(v);
 }
 
+// the seven [L][npix] arrays of the spectral pass
+struct SpecArrays {
+    char *X, *zP, *zT, *S, *GS, *GV, *Brest;
+    unsigned band_bytes;
+    int gshift;
+};
+
 template <typename T, int LT, bool DENSE, bool REDUCE>
 __global__ void __launch_bounds__(SPEC_NTH)
-k_spectral(const T* __restrict__ X, T* __restrict__ zP, T* __restrict__ zT, T* __restrict__ S,
-           T* __restrict__ GS, T* __restrict__ GV, T* __restrict__ Brest,
-           const T* __restrict__ D, int Lrt, long npix, SpecArgs a, double* __restrict__ partials) {
-    const long p = (long)blockIdx.x * SPEC_NTH + threadIdx.x;
-    const bool live = p < npix;
+k_spectral(SpecArrays A, const T* __restrict__ D, int Lrt, long npix, SpecArgs a,
+           double* __restrict__ partials) {
+    // the launch covers npix exactly (npix is a power of two >= 64 and the
+    // block size min(256, npix) divides it), so every lane owns a pixel
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const BandArray<T> X{A.X, A.band_bytes, A.gshift}, zP{A.zP, A.band_bytes, A.gshift},
+        zT{A.zT, A.band_bytes, A.gshift}, S{A.S, A.band_bytes, A.gshift},
+        GS{A.GS, A.band_bytes, A.gshift}, GV{A.GV, A.band_bytes, A.gshift},
+        Brest{A.Brest, A.band_bytes, A.gshift};
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
     const T tauT = T(a.tau_T), tauV = T(a.tau_V);
@@ -90,28 +104,37 @@ k_spectral(const T* __restrict__ X, T* __restrict__ zP, T* __restrict__ zT, T* _
     for (int q = 0; q < (REDUCE ? RED_NQ : 1); ++q) acc[q] = 0.0;
 
     T v[LT];
+    // previous Gamma_V, held for the residual / E^k sums of the reduction variant
+    T gvold[REDUCE ? LT : 1];
     // step IV input: DCT of the previous S
 #pragma unroll
-    for (int l = 0; l < LT; ++l) v[l] = (live && l < L) ? S[l * npix + p] : T(0);
+    for (int l = 0; l < LT; ++l) v[l] = (l < L) ? S.load(l, off) : T(0);
     dct_any<T, LT, DENSE, false>(v, D, L);
+    // Phase boundaries: keep each phase's loads inside it.  Left free, the
+    // scheduler hoists the next phase's band loads above the register DCT
+    // and the kernel needs 200+ VGPRs (occupancy 2) or spills.
+    __builtin_amdgcn_sched_barrier(0);
     // step IV: V = soft(S W - Gamma_V / rho_V); keep Gamma_V + rho_V V
 #pragma unroll
     for (int k = 0; k < LT; ++k) {
         if (k < L) {
-            const T gv = live ? GV[k * npix + p] : T(0);
+            const T gv = GV.load(k, off);
             const T V = softt(v[k] - gv * inv_rhoV, tauV);
             v[k] = gv + rhoV * V;
-            if constexpr (REDUCE) acc[RED_V2] += double(V) * V;
+            if constexpr (REDUCE) {
+                acc[RED_V2] += double(V) * V;
+                gvold[k] = gv;
+            }
         }
     }
+    __builtin_amdgcn_sched_barrier(0);
     dct_any<T, LT, DENSE, true>(v, D, L);
+    __builtin_amdgcn_sched_barrier(0);
     // steps II, III, V and the Gamma_P, Gamma_T, Gamma_S updates, band by band
 #pragma unroll
     for (int l = 0; l < LT; ++l) {
         if (l < L) {
-            const long i = l * npix + p;
-            T x = T(0), gs = T(0), zp = T(0), zt = T(0);
-            if (live) { x = X[i]; gs = GS[i]; zp = zP[i]; zt = zT[i]; }
+            const T x = X.load(l, off), gs = GS.load(l, off), zp = zP.load(l, off), zt = zT.load(l, off);
             const T s = (v[l] - gs + rhoS * x) * inv_VS;
             const T gs2 = gs + rhoS * (s - x);
             const T zp2 = x - (zp < T(0) ? -zp : T(0));
@@ -119,7 +142,7 @@ k_spectral(const T* __restrict__ X, T* __restrict__ zP, T* __restrict__ zT, T* _
             const T tt = softt(zt2, tauT);
             const T b = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * s;
             if constexpr (REDUCE) {
-                const T sold = live ? S[i] : T(0);
+                const T sold = S.load(l, off);
                 const double P = zp2 > T(0) ? double(zp2) : 0.0;
                 const double Pold = zp > T(0) ? double(zp) : 0.0;
                 const double Told = double(softt(zt, tauT));
@@ -143,31 +166,40 @@ k_spectral(const T* __restrict__ X, T* __restrict__ zP, T* __restrict__ zT, T* _
                 acc[RED_P2] += P * P;
                 acc[RED_P1] += P;
             }
-            if (live) { S[i] = s; GS[i] = gs2; zP[i] = zp2; zT[i] = zt2; Brest[i] = b; }
+            S.store(l, off, s);
+            GS.store(l, off, gs2);
+            zP.store(l, off, zp2);
+            zT.store(l, off, zt2);
+            Brest.store(l, off, b);
             v[l] -= rhoV * s;
         }
+        // the reduction variant carries 10 FP64 sums and their operands: keep
+        // each band's loads inside its own iteration
+        if constexpr (REDUCE) __builtin_amdgcn_sched_barrier(0);
     }
     // step VI for Gamma_V
+    __builtin_amdgcn_sched_barrier(0);
     dct_any<T, LT, DENSE, false>(v, D, L);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < LT; ++k) {
         if (k < L) {
-            const long i = k * npix + p;
             if constexpr (REDUCE) {
-                const double gvo = live ? double(GV[i]) : 0.0;
+                const double gvo = double(gvold[k]);
                 const double dg = double(v[k]) - gvo;
                 acc[RED_R2] += dg * dg / (a.rho_V * a.rho_V);
                 acc[RED_E] += dg * dg / a.rho_V;
                 acc[RED_ATY2] += double(v[k]) * v[k];
             }
-            if (live) GV[i] = v[k];
+            GV.store(k, off, v[k]);
         }
+        if constexpr (REDUCE) __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (REDUCE) {
         // spectral l1 norm of P for the objective
 #pragma unroll
         for (int l = 0; l < LT; ++l) {
-            const T z = (live && l < L) ? zP[l * npix + p] : T(0);
+            const T z = (l < L) ? zP.load(l, off) : T(0);
             v[l] = z > T(0) ? z : T(0);
         }
         dct_any<T, LT, DENSE, false>(v, D, L);
@@ -187,15 +219,18 @@ template <typename T, int LT, bool DENSE>
 static hipError_t spectral_t(bool reduce, const void* X, void* zP, void* zT, void* S, void* GS,
                              void* GV, void* Brest, const void* D, int L, long npix,
                              const SpecArgs& a, double* partials, int* nb, hipStream_t s) {
-    dim3 grid((unsigned)((npix + SPEC_NTH - 1) / SPEC_NTH));
+    // npix = nx ny is a power of two >= 64: the block size divides it
+    const int nth = npix < SPEC_NTH ? (int)npix : SPEC_NTH;
+    if (npix < 64 || (npix & (npix - 1)) != 0) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(npix / nth));
     if (nb) *nb = (int)grid.x;
+    SpecArrays A{(char*)X, (char*)zP, (char*)zT, (char*)S, (char*)GS, (char*)GV, (char*)Brest,
+                 (unsigned)(npix * (long)sizeof(T)), band_group_shift((unsigned long long)npix * sizeof(T))};
     if (reduce)
-        hipLaunchKernelGGL((k_spectral<T, LT, DENSE, true>), grid, dim3(SPEC_NTH), 0, s,
-                           (const T*)X, (T*)zP, (T*)zT, (T*)S, (T*)GS, (T*)GV, (T*)Brest,
+        hipLaunchKernelGGL((k_spectral<T, LT, DENSE, true>), grid, dim3(nth), 0, s, A,
                            (const T*)D, L, npix, a, partials);
     else
-        hipLaunchKernelGGL((k_spectral<T, LT, DENSE, false>), grid, dim3(SPEC_NTH), 0, s,
-                           (const T*)X, (T*)zP, (T*)zT, (T*)S, (T*)GS, (T*)GV, (T*)Brest,
+        hipLaunchKernelGGL((k_spectral<T, LT, DENSE, false>), grid, dim3(nth), 0, s, A,
                            (const T*)D, L, npix, a, partials);
     return hipGetLastError();
 }
