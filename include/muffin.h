@@ -155,8 +155,10 @@ int muffin_get_p(muffin_ctx* ctx, void* p_out);
 int muffin_grad(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
                 double* loss, double grad[3]);
 
-/* Bytes of one state snapshot (z_P, z_T, S, Gamma_S, Gamma_V plus the X
-   iterate and an iteration counter). */
+/* Bytes of one state snapshot: the iteration's carried arrays (the prox
+   inputs z_P and z_T of steps II-III, S and Gamma_S; Gamma_V = Gamma_S W_nu
+   holds after every pass, so it is not stored), the X iterate and a header
+   with the iteration counter. */
 size_t muffin_state_bytes(const muffin_ctx* ctx);
 
 /* Save / restore the ADMM state to / from device memory `dst` / `src`

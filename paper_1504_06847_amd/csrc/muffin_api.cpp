@@ -22,6 +22,7 @@ struct muffin_ctx {
     char* ws;
     size_t ws_bytes;
     Layout lay;
+    int cur;          // which state set holds the current state
     int iters;
     int twlog;
     double ynorm2;
@@ -46,7 +47,8 @@ size_t voxels(const muffin_shape& s) { return size_t(s.L) * s.ny * s.nx; }
 int ilog2i(int n) { int r = 0; while ((1 << r) < n) ++r; return r; }
 
 char* P(muffin_ctx* c, size_t off) { return c->ws + off; }
-void* st(muffin_ctx* c, int i) { return c->ws + c->lay.state[i]; }
+void* st(muffin_ctx* c, int i) { return c->ws + c->lay.state[c->cur][i]; }
+void* st_alt(muffin_ctx* c, int i) { return c->ws + c->lay.state[1 - c->cur][i]; }
 
 SpecArgs spec_args(const muffin_params& p) {
     SpecArgs a;
@@ -83,12 +85,25 @@ int step_one(muffin_ctx* c) {
     return MUFFIN_OK;
 }
 
-int step_spectral(muffin_ctx* c, bool reduce, int* nblocks) {
+// steps II-VI; a reporting pass writes the alternate state set and the FP64
+// partials of the convergence quantities, then the sets swap
+int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
     const muffin_shape& s = c->shape;
-    HIP_TRY(launch_spectral(s.dtype, reduce, P(c, c->lay.x), st(c, ST_ZP), st(c, ST_ZT), st(c, ST_S),
-                            st(c, ST_GS), st(c, ST_GV), P(c, c->lay.brest), P(c, c->lay.dctm), s.L,
-                            s.ny * s.nx, spec_args(c->params), (double*)P(c, c->lay.partials),
-                            nblocks, c->stream));
+    SpecLaunch g;
+    g.X = P(c, c->lay.x);
+    for (int i = 0; i < kNumState; ++i) {
+        g.st[i] = st(c, i);
+        g.out[i] = report ? st_alt(c, i) : st(c, i);
+    }
+    g.brest = P(c, c->lay.brest);
+    g.dctm = P(c, c->lay.dctm);
+    g.L = s.L;
+    g.npix = long(s.ny) * s.nx;
+    g.report = report;
+    g.vpart = (double*)P(c, c->lay.vpart);
+    g.partials = (double*)P(c, c->lay.partials);
+    HIP_TRY(launch_spectral(s.dtype, g, spec_args(c->params), nblocks, c->stream));
+    if (report) c->cur = 1 - c->cur;
     return MUFFIN_OK;
 }
 
@@ -108,8 +123,9 @@ int recompute_brest(muffin_ctx* c) {
 }
 
 int zero_state(muffin_ctx* c) {
-    // z_P .. Gamma_V, B_rest and X are contiguous
-    HIP_TRY(launch_fill_zero(P(c, c->lay.state[0]), c->lay.z - c->lay.state[0], c->stream));
+    // both state sets, B_rest and X are contiguous
+    HIP_TRY(launch_fill_zero(P(c, c->lay.state[0][0]), c->lay.z - c->lay.state[0][0], c->stream));
+    c->cur = 0;
     c->iters = 0;
     return MUFFIN_OK;
 }
@@ -252,6 +268,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     c->ws = (char*)workspace;
     c->ws_bytes = ws_bytes;
     c->lay = lay;
+    c->cur = 0;
     c->iters = 0;
     const int NT = shape->nx > shape->ny ? shape->nx : shape->ny;
     c->twlog = ilog2i(NT);
@@ -278,7 +295,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     if ((rc = upload_tables(c)) != MUFFIN_OK) return fail(rc);
     // FP64 transforms of the shifted PSF and of the dirty image, in the (not yet
     // used) state region
-    char* Ch = P(c, lay.state[0]);
+    char* Ch = P(c, lay.state[0][0]);
     char* Cy = Ch + lay.setup_scratch_bytes / 2;
     const int nrows = shape->L * shape->ny;
     e = launch_row_fwd(MUFFIN_F64, in64, psf, Ch, nrows, shape->nx, shape->ny, true, false,

@@ -173,14 +173,38 @@ constexpr int plan_ns(int n, int s) {   // product of the radices before stage s
     return p;
 }
 
+// LDS position of element e of a transform: with PAD, one spare slot after
+// every 8 elements, which spreads the stride-R writes of a Stockham stage
+// over the LDS banks (without it they collide 8 to 16 ways).
+template <bool PAD> __host__ __device__ constexpr int lds_pos(int e) { return PAD ? e + (e >> 3) : e; }
+template <bool PAD> __host__ __device__ constexpr int lds_len(int n) { return PAD ? n + (n >> 3) : n; }
+
+// Twiddles w^r, r = 1..R-1, of one butterfly, w = exp(-2 pi i k / (NS R)):
+// w, w^2 and w^4 come from the table (exact to the table's rounding), the
+// others as one product of two table values.
+template <typename T, int R>
+__device__ __forceinline__ void stage_twiddles(cx<T>* w, const cx<T>* __restrict__ tw, int k, int shift) {
+    w[1] = tw[k << shift];
+    if constexpr (R >= 4) {
+        w[2] = tw[(2 * k) << shift];
+        w[3] = cmul(w[1], w[2]);
+    }
+    if constexpr (R == 8) {
+        w[4] = tw[(4 * k) << shift];
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+    }
+}
+
 // One Stockham autosort stage over a tile of NTRANS transforms of length LEN
-// in LDS.  Element e of transform t sits at buf[t * TS + e * ES].  Butterfly j
-// (0 <= j < LEN/R) reads elements j + r LEN/R, multiplies input r by
-// w_{NS R}^{r (j mod NS)}, applies an R-point DFT and writes output q to
+// in LDS.  Element e of transform t sits at buf[t * TS + lds_pos<PAD>(e) * ES].
+// Butterfly j (0 <= j < LEN/R) reads elements j + r LEN/R, multiplies input r
+// by w_{NS R}^{r (j mod NS)}, applies an R-point DFT and writes output q to
 // (j - j mod NS) R + (j mod NS) + q NS.  Work items (transform, butterfly) are
 // spread over NTH threads: TFAST puts the transform index fastest across
 // threads (strided tiles), otherwise the butterfly index.
-template <typename T, int LEN, int R, int NS, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool INV>
+template <typename T, int LEN, int R, int NS, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
     constexpr int NB = LEN / R;
     constexpr int ITEMS = NB * NTRANS;
@@ -195,14 +219,13 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
             const int j = TFAST ? item / NTRANS : item % NB;
             const cx<T>* p = buf + tr * TS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = p[(j + r * NB) * ES];
+            for (int r = 0; r < R; ++r) v[i][r] = p[lds_pos<PAD>(j + r * NB) * ES];
             if constexpr (NS > 1) {
                 const int k = j & (NS - 1);
+                cx<T> w[R];
+                stage_twiddles<T, R>(w, tw, k, twlog - LOGNR);
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    cx<T> w = tw[(r * k) << (twlog - LOGNR)];
-                    v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
-                }
+                for (int r = 1; r < R; ++r) v[i][r] = INV ? cmulc(v[i][r], w[r]) : cmul(v[i][r], w[r]);
             }
             dftR<T, R, INV>(v[i]);
         }
@@ -218,25 +241,25 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
             cx<T>* p = buf + tr * TS;
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) p[(base + r * NS) * ES] = v[i][r];
+            for (int r = 0; r < R; ++r) p[lds_pos<PAD>(base + r * NS) * ES] = v[i][r];
         }
     }
     __syncthreads();
 }
 
-template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool INV, int S>
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV, int S>
 __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
     if constexpr (S < plan_nstages(LEN)) {
-        fft_stage<T, LEN, plan_radix(LEN, S), plan_ns(LEN, S), NTRANS, NTH, TS, ES, TFAST, INV>(buf, tw, twlog, t);
-        fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, INV, S + 1>(buf, tw, twlog, t);
+        fft_stage<T, LEN, plan_radix(LEN, S), plan_ns(LEN, S), NTRANS, NTH, TS, ES, TFAST, PAD, INV>(buf, tw, twlog, t);
+        fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, S + 1>(buf, tw, twlog, t);
     }
 }
 
 // In-place FFT of NTRANS transforms of length LEN held in LDS (natural order
 // in and out, unnormalised).  Must be called by all NTH threads of the block.
-template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool INV>
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
 __device__ __forceinline__ void tile_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
-    fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, INV, 0>(buf, tw, twlog, t);
+    fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, 0>(buf, tw, twlog, t);
 }
 
 // ---------------------------------------------------------------- register FFT / DCT

@@ -49,7 +49,7 @@ k_row_fwd(const Tin* __restrict__ in, cx<T>* __restrict__ out, int nrows, int ny
           const cx<T>* __restrict__ tw, int twlog) {
     constexpr int M = NX / 2;
     constexpr int RPW = row_rpw<M>();
-    constexpr int TS = M;
+    constexpr int TS = lds_len<true>(M);
     __shared__ cx<T> lds[RPW * TS];
     const int t = threadIdx.x;
     const long row0 = (long)blockIdx.x * RPW;
@@ -74,23 +74,23 @@ k_row_fwd(const Tin* __restrict__ in, cx<T>* __restrict__ out, int nrows, int ny
             }
             v = {a, b};
         }
-        lds[r * TS + m] = v;
+        lds[r * TS + lds_pos<true>(m)] = v;
     }
     __syncthreads();
-    tile_fft<T, M, RPW, ROW_NTH, TS, 1, false, false>(lds, tw, twlog, t);
+    tile_fft<T, M, RPW, ROW_NTH, TS, 1, false, true, false>(lds, tw, twlog, t);
     constexpr int NK = M / 2 + 1;
     for (int i = t; i < RPW * NK; i += ROW_NTH) {
         const int r = i / NK, k = i % NK;
         const long grow = row0 + r;
         if (grow >= nrows) continue;
         cx<T>* o = out + grow * M;
-        const cx<T> zk = lds[r * TS + k];
+        const cx<T> zk = lds[r * TS + lds_pos<true>(k)];
         if (k == 0) {
             o[0] = {zk.x + zk.y, zk.x - zk.y};           // (X_0, X_{nx/2}), both real
         } else if (k == M / 2) {
             o[k] = conj(zk);
         } else {
-            const cx<T> zm = lds[r * TS + M - k];
+            const cx<T> zm = lds[r * TS + lds_pos<true>(M - k)];
             // even/odd sample spectra E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
             const cx<T> e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
             const cx<T> od = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
@@ -107,7 +107,7 @@ k_row_inv(const cx<T>* __restrict__ in, T* __restrict__ out, int nrows,
           const cx<T>* __restrict__ tw, int twlog) {
     constexpr int M = NX / 2;
     constexpr int RPW = row_rpw<M>();
-    constexpr int TS = M;
+    constexpr int TS = lds_len<true>(M);
     __shared__ cx<T> lds[RPW * TS];
     const int t = threadIdx.x;
     const long row0 = (long)blockIdx.x * RPW;
@@ -122,22 +122,22 @@ k_row_inv(const cx<T>* __restrict__ in, T* __restrict__ out, int nrows,
         if (k == 0) {
             l[0] = {T(0.5) * (xk.x + xk.y), T(0.5) * (xk.x - xk.y)};
         } else if (k == M / 2) {
-            l[k] = conj(xk);
+            l[lds_pos<true>(k)] = conj(xk);
         } else {
             const cx<T> xm = p[M - k];
             const cx<T> e = {T(0.5) * (xk.x + xm.x), T(0.5) * (xk.y - xm.y)};
             const cx<T> d = {T(0.5) * (xk.x - xm.x), T(0.5) * (xk.y + xm.y)};
             const cx<T> o = cmulc(d, tw[k << (twlog - ilog2c(NX))]);   // O = w^{-k} D
-            l[k] = e + mul_i(o);                                        // Z_k = E + i O
-            l[M - k] = conj(e) + mul_i(conj(o));
+            l[lds_pos<true>(k)] = e + mul_i(o);                         // Z_k = E + i O
+            l[lds_pos<true>(M - k)] = conj(e) + mul_i(conj(o));
         }
     }
     __syncthreads();
-    tile_fft<T, M, RPW, ROW_NTH, TS, 1, false, true>(lds, tw, twlog, t);
+    tile_fft<T, M, RPW, ROW_NTH, TS, 1, false, true, true>(lds, tw, twlog, t);
     for (int i = t; i < RPW * M; i += ROW_NTH) {
         const int r = i / M, m = i % M;
         const long grow = row0 + r;
-        if (grow < nrows) reinterpret_cast<cx<T>*>(out + grow * NX)[m] = lds[r * TS + m];
+        if (grow < nrows) reinterpret_cast<cx<T>*>(out + grow * NX)[m] = lds[r * TS + lds_pos<true>(m)];
     }
 }
 
@@ -149,7 +149,8 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
       int twlog, double* __restrict__ partials, double inv_n) {
     constexpr int TC = col_tc<T, NY>();
     constexpr int NTH = col_nth<T, NY>();
-    __shared__ cx<T> lds[NY * TC];
+    constexpr int TCP = TC + 1;          // padded row stride: spreads stride-R writes over the banks
+    __shared__ cx<T> lds[NY * TCP];
     __shared__ double red[NTH / 64];
     const int t = threadIdx.x;
     // XCD-aware tile order.  Work-groups go to the 8 XCDs round-robin in
@@ -170,44 +171,44 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
         const int y = i / TC, c = i % TC;
         cx<T> v = {T(0), T(0)};
         if (c0 + c < M) v = data[base + (long)y * M + c0 + c];
-        lds[y * TC + c] = v;
+        lds[y * TCP + c] = v;
     }
     __syncthreads();
-    tile_fft<T, NY, TC, NTH, 1, TC, true, false>(lds, tw, twlog, t);
+    tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, tw, twlog, t);
 
     if constexpr (MODE == COL_SOLVE) {
         for (int i = t; i < NY * TC; i += NTH) {
             const int y = i / TC, c = i % TC, kx = c0 + c;
             if (kx == 0 || kx >= M) continue;
             const long g = base + (long)y * M + kx;
-            const cx<T> v = lds[i] + Yf[g];
-            lds[i] = v * (scale / (H2[g] + rhoQ));
+            const cx<T> v = lds[y * TCP + c] + Yf[g];
+            lds[y * TCP + c] = v * (scale / (H2[g] + rhoQ));
         }
         if (c0 == 0) {
             // slot 0 packs the real columns kx = 0 (A) and kx = nx/2 (B): C = A + i B
             for (int ky = t; ky <= NY / 2; ky += NTH) {
                 const int kn = (NY - ky) & (NY - 1);
                 const long g1 = base + (long)ky * M, g2 = base + (long)kn * M;
-                const cx<T> c1 = lds[ky * TC] + Yf[g1];
-                const cx<T> c2 = lds[kn * TC] + Yf[g2];
+                const cx<T> c1 = lds[ky * TCP] + Yf[g1];
+                const cx<T> c2 = lds[kn * TCP] + Yf[g2];
                 const T g0 = scale / (H2[g1] + rhoQ);
                 const T gm = scale / (H2nyq[(long)band * NY + ky] + rhoQ);
                 cx<T> A = {T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)};
                 cx<T> B = {T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x)};
                 A = A * g0;
                 B = B * gm;
-                lds[ky * TC] = A + mul_i(B);
-                if (kn != ky) lds[kn * TC] = conj(A) + mul_i(conj(B));
+                lds[ky * TCP] = A + mul_i(B);
+                if (kn != ky) lds[kn * TCP] = conj(A) + mul_i(conj(B));
             }
         }
         __syncthreads();
-        tile_fft<T, NY, TC, NTH, 1, TC, true, true>(lds, tw, twlog, t);
+        tile_fft<T, NY, TC, NTH, 1, TCP, true, false, true>(lds, tw, twlog, t);
     }
 
     if constexpr (MODE == COL_SOLVE || MODE == COL_FWD) {
         for (int i = t; i < NY * TC; i += NTH) {
             const int y = i / TC, c = i % TC;
-            if (c0 + c < M) data[base + (long)y * M + c0 + c] = lds[i];
+            if (c0 + c < M) data[base + (long)y * M + c0 + c] = lds[y * TCP + c];
         }
     }
 
@@ -218,7 +219,7 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
             const int y = i / TC, c = i % TC, kx = c0 + c;
             if (kx == 0 || kx >= M) continue;
             const long g = base + (long)y * M + kx;
-            const cx<T> z = lds[i], f = Yf[g];
+            const cx<T> z = lds[y * TCP + c], f = Yf[g];
             const double zz = double(z.x) * z.x + double(z.y) * z.y;
             const double cr = double(f.x) * z.x + double(f.y) * z.y;
             acc += 2.0 * (double(H2[g]) * zz - 2.0 * cr);
@@ -227,7 +228,7 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
             for (int ky = t; ky <= NY / 2; ky += NTH) {
                 const int kn = (NY - ky) & (NY - 1);
                 const long g1 = base + (long)ky * M, g2 = base + (long)kn * M;
-                const cx<T> c1 = lds[ky * TC], c2 = lds[kn * TC];
+                const cx<T> c1 = lds[ky * TCP], c2 = lds[kn * TCP];
                 const cx<T> f1 = Yf[g1], f2 = Yf[g2];
                 const cx<T> A = {T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)};
                 const cx<T> B = {T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x)};

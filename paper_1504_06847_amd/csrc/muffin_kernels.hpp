@@ -50,10 +50,24 @@ hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const voi
                       const void* tw, int twlog, double* partials, int* nblocks_out,
                       hipStream_t s);
 
+// Arrays of one spectral pass.  st: the state read (z_P, z_T, S, Gamma_S);
+// out: where the new state goes (= st except in a reporting pass).
+struct SpecLaunch {
+    const void* X;
+    void* st[4];
+    void* out[4];
+    void* brest;
+    const void* dctm;
+    int L;
+    long npix;
+    bool report;        // also run k_report: FP64 partials (RED_NQ per block)
+    double* vpart;      // one double per block: sum of V^2 (reporting pass)
+    double* partials;   // RED_NQ doubles per block (reporting pass)
+};
+
 // Spectral pass (steps II-VI of one iteration) over every pixel.
-hipError_t launch_spectral(int dtype, bool reduce, const void* X, void* zP, void* zT, void* S,
-                           void* GS, void* GV, void* Brest, const void* dctm, int L, int npix,
-                           const SpecArgs& a, double* partials, int* nblocks_out, hipStream_t s);
+hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, int* nblocks_out,
+                           hipStream_t s);
 
 // Setup: combine the FP64 packed column spectra of the shifted PSF (Ch) and of
 // the dirty image (Cy) into conj(h_hat) y_hat (Yf), |h_hat|^2 (H2, and H2nyq

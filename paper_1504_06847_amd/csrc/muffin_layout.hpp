@@ -8,13 +8,14 @@
 namespace muffin {
 
 constexpr size_t kAlign = 256;
-constexpr int kNumState = 5;     // z_P, z_T, S, Gamma_S, Gamma_V
+constexpr int kNumState = 4;     // z_P, z_T, S, Gamma_S (Gamma_V = Gamma_S W_nu is implied)
 constexpr int kNumRed = 10;      // FP64 partial sums per block (see RedSlot)
-enum StateIdx { ST_ZP = 0, ST_ZT = 1, ST_S = 2, ST_GS = 3, ST_GV = 4 };
+enum StateIdx { ST_ZP = 0, ST_ZT = 1, ST_S = 2, ST_GS = 3 };
 
 struct Layout {
-    size_t state[kNumState];
-    size_t brest, x, z, yf, h2, h2nyq, tw, tw64, dctm, partials, sums;
+    size_t state[2][kNumState];   // current and alternate state sets (a reporting
+                                  // pass writes the alternate set, then they swap)
+    size_t brest, x, z, yf, h2, h2nyq, tw, tw64, dctm, partials, vpart, sums;
     size_t total;
     size_t setup_scratch_bytes, state_region_bytes;
     int nblk;

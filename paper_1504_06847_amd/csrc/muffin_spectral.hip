@@ -6,20 +6,24 @@
 // registers; band l of pixel p sits at [l * npix + p], so every load/store
 // of a wavefront covers 64 consecutive pixels of one band.
 //
-// The state is the reduced form of Algorithm 1's nine arrays with W_s = I:
-//   z_P (input of the positivity prox, step II), z_T (input of the spatial
-//   soft threshold, step III), S, Gamma_S, Gamma_V.
-// With these, P = max(0, z_P), Gamma_P = rho_P max(0, -z_P),
-// T = soft(z_T, mu_s/rho_T), Gamma_T = -rho_T clip(z_T, mu_s/rho_T), and the
-// right-hand side of step I (eq. matB) is H^T Y + B_rest with
-// B_rest = rho_T (2 T - z_T) + rho_P |z_P| + Gamma_S + rho_S S.
+// State: the reduced form of Algorithm 1's nine arrays with W_s = I, four
+// arrays z_P, z_T, S, Gamma_S.
+//  * z_P, z_T are the inputs of the positivity prox (step II) and of the
+//    spatial soft threshold (step III): P = max(0, z_P),
+//    Gamma_P = rho_P max(0, -z_P), T = soft(z_T, tau_T),
+//    Gamma_T = -rho_T clip(z_T, tau_T).
+//  * Gamma_V is not stored.  Step V minimises the augmented Lagrangian in S
+//    exactly, and its optimality condition is Gamma_S^+ = Gamma_V^+ W_nu^T
+//    after every pass (and at the all-zero start), so Gamma_V = Gamma_S W_nu.
 // Per pixel, given the new X from step I:
-//   a = DCT(S_old)                                  (step IV uses the old S)
-//   V = soft(a - Gamma_V / rho_V, mu_nu / rho_V);  a = Gamma_V + rho_V V
-//   a = IDCT(a);  S = (a - Gamma_S + rho_S X) / (rho_V + rho_S)      (step V)
-//   Gamma_S += rho_S (S - X);  a -= rho_V S;  Gamma_V = DCT(a)       (step VI:
-//       Gamma_V + rho_V (V - S W_nu) = (Gamma_V + rho_V V) - rho_V S W_nu)
+//   V = soft(DCT(S - Gamma_S / rho_V), mu_nu / rho_V)       (step IV)
+//   q = IDCT(V)
+//   S^+ = (rho_V q + rho_S X) / (rho_V + rho_S)               (step V)
+//   Gamma_S^+ = Gamma_S + rho_V (q - S^+)                      (step VI; also
+//       = Gamma_S + rho_S (S^+ - X) by the S-step's closed form)
 //   z_P <- X - max(0, -z_P);  z_T <- X + clip(z_T, tau_T)     (steps II, III, VI)
+// and the right-hand side of the next step I (eq. matB) is H^T Y + B_rest with
+// B_rest = rho_T (2 T - z_T) + rho_P |z_P| + Gamma_S + rho_S S.
 #include "muffin_device.hpp"
 #include "muffin_kernels.hpp"
 
@@ -76,13 +80,21 @@ __device__ __forceinline__ void dct_any(T (&v)[LT], const T* __restrict__ D, int
     else dct2_ortho<T, LT>(v);
 }
 
-// the seven [L][npix] arrays of the spectral pass
+// the [L][npix] arrays of the spectral pass: X, the state it reads (z_P,
+// z_T, S, Gamma_S), the state it writes (the same arrays, or a second set in
+// a reporting pass) and B_rest
 struct SpecArrays {
-    char *X, *zP, *zT, *S, *GS, *GV, *Brest;
+    char *X, *zP, *zT, *S, *GS;
+    char *zPo, *zTo, *So, *GSo;
+    char *Brest;
     unsigned band_bytes;
     int gshift;
 };
 
+// One ADMM pass after step I.  REDUCE (a reporting pass): the new state goes
+// to the second array set, so k_report can compare old and new, and the
+// block sums of ||V||^2 (the only DCT-domain quantity of the convergence
+// checks) are written to partials[block].
 template <typename T, int LT, bool DENSE, bool REDUCE>
 __global__ void __launch_bounds__(SPEC_NTH)
 k_spectral(SpecArrays A, const T* __restrict__ D, int Lrt, long npix, SpecArgs a,
@@ -91,182 +103,206 @@ k_spectral(SpecArrays A, const T* __restrict__ D, int Lrt, long npix, SpecArgs a
     // block size min(256, npix) divides it), so every lane owns a pixel
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
-    const BandArray<T> X{A.X, A.band_bytes, A.gshift}, zP{A.zP, A.band_bytes, A.gshift},
-        zT{A.zT, A.band_bytes, A.gshift}, S{A.S, A.band_bytes, A.gshift},
-        GS{A.GS, A.band_bytes, A.gshift}, GV{A.GV, A.band_bytes, A.gshift},
-        Brest{A.Brest, A.band_bytes, A.gshift};
+    const unsigned bb = A.band_bytes;
+    const int gs_ = A.gshift;
+    const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.S, bb, gs_},
+        GS{A.GS, bb, gs_}, Brest{A.Brest, bb, gs_};
+    const BandArray<T> zPo{REDUCE ? A.zPo : A.zP, bb, gs_}, zTo{REDUCE ? A.zTo : A.zT, bb, gs_},
+        So{REDUCE ? A.So : A.S, bb, gs_}, GSo{REDUCE ? A.GSo : A.GS, bb, gs_};
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
     const T tauT = T(a.tau_T), tauV = T(a.tau_V);
     const T inv_rhoV = T(1.0 / a.rho_V), inv_VS = T(1.0 / (a.rho_V + a.rho_S));
-    double acc[REDUCE ? RED_NQ : 1];
-#pragma unroll
-    for (int q = 0; q < (REDUCE ? RED_NQ : 1); ++q) acc[q] = 0.0;
+    double v2 = 0.0;
 
     T v[LT];
-    // previous Gamma_V, held for the residual / E^k sums of the reduction variant
-    T gvold[REDUCE ? LT : 1];
-    // step IV input: DCT of the previous S
+    // step IV: V = soft(DCT(S - Gamma_S / rho_V)) with the previous S, Gamma_S
 #pragma unroll
-    for (int l = 0; l < LT; ++l) v[l] = (l < L) ? S.load(l, off) : T(0);
+    for (int l = 0; l < LT; ++l) v[l] = (l < L) ? S.load(l, off) - GS.load(l, off) * inv_rhoV : T(0);
     dct_any<T, LT, DENSE, false>(v, D, L);
-    // Phase boundaries: keep each phase's loads inside it.  Left free, the
-    // scheduler hoists the next phase's band loads above the register DCT
-    // and the kernel needs 200+ VGPRs (occupancy 2) or spills.
+    // Phase boundaries keep each phase's band loads inside it: left free, the
+    // scheduler hoists the next phase's loads above the register DCT and the
+    // kernel needs 200+ VGPRs or spills.
     __builtin_amdgcn_sched_barrier(0);
-    // step IV: V = soft(S W - Gamma_V / rho_V); keep Gamma_V + rho_V V
 #pragma unroll
     for (int k = 0; k < LT; ++k) {
-        if (k < L) {
-            const T gv = GV.load(k, off);
-            const T V = softt(v[k] - gv * inv_rhoV, tauV);
-            v[k] = gv + rhoV * V;
-            if constexpr (REDUCE) {
-                acc[RED_V2] += double(V) * V;
-                gvold[k] = gv;
-            }
-        }
+        const T V = softt(v[k], tauV);
+        v[k] = V;
+        if constexpr (REDUCE) v2 += double(V) * V;
     }
+    dct_any<T, LT, DENSE, true>(v, D, L);        // q = V W_nu^T
     __builtin_amdgcn_sched_barrier(0);
-    dct_any<T, LT, DENSE, true>(v, D, L);
-    __builtin_amdgcn_sched_barrier(0);
-    // steps II, III, V and the Gamma_P, Gamma_T, Gamma_S updates, band by band
+    // steps II, III, V, VI, band by band.  Gamma_S is read again here: the
+    // compiler keeps the step-IV loads live instead (nothing is stored in
+    // between), one band vector more in registers and 4 B/voxel less traffic.
 #pragma unroll
     for (int l = 0; l < LT; ++l) {
         if (l < L) {
             const T x = X.load(l, off), gs = GS.load(l, off), zp = zP.load(l, off), zt = zT.load(l, off);
-            const T s = (v[l] - gs + rhoS * x) * inv_VS;
-            const T gs2 = gs + rhoS * (s - x);
+            const T q = v[l];
+            const T s = (rhoV * q + rhoS * x) * inv_VS;
+            const T gs2 = gs + rhoV * (q - s);
             const T zp2 = x - (zp < T(0) ? -zp : T(0));
             const T zt2 = x + clipt(zt, tauT);
             const T tt = softt(zt2, tauT);
             const T b = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * s;
-            if constexpr (REDUCE) {
-                const T sold = S.load(l, off);
-                const double P = zp2 > T(0) ? double(zp2) : 0.0;
-                const double Pold = zp > T(0) ? double(zp) : 0.0;
-                const double Told = double(softt(zt, tauT));
-                const double dP = P - Pold, dT = double(tt) - Told, dS = double(s) - double(sold);
-                const double gp = double(rhoP) * (zp2 < T(0) ? -double(zp2) : 0.0);
-                const double gpo = double(rhoP) * (zp < T(0) ? -double(zp) : 0.0);
-                const double gt = -double(rhoT) * double(clipt(zt2, tauT));
-                const double gto = -double(rhoT) * double(clipt(zt, tauT));
-                const double xd = double(x);
-                acc[RED_R2] += (P - xd) * (P - xd) + (double(tt) - xd) * (double(tt) - xd)
-                               + (double(s) - xd) * (double(s) - xd);
-                const double sx = a.rho_P * dP + a.rho_T * dT + a.rho_S * dS;
-                acc[RED_S2] += sx * sx + a.rho_V * a.rho_V * dS * dS;
-                acc[RED_X2] += xd * xd;
-                acc[RED_BZ2] += P * P + double(tt) * tt + 2.0 * double(s) * s;
-                const double gsum = gp + gt + double(gs2);
-                acc[RED_ATY2] += gsum * gsum;
-                acc[RED_E] += a.rho_P * dP * dP + a.rho_T * dT * dT + (a.rho_S + a.rho_V) * dS * dS
-                              + (gp - gpo) * (gp - gpo) / a.rho_P + (gt - gto) * (gt - gto) / a.rho_T
-                              + (double(gs2) - gs) * (double(gs2) - gs) / a.rho_S;
-                acc[RED_P2] += P * P;
-                acc[RED_P1] += P;
-            }
-            S.store(l, off, s);
-            GS.store(l, off, gs2);
-            zP.store(l, off, zp2);
-            zT.store(l, off, zt2);
+            So.store(l, off, s);
+            GSo.store(l, off, gs2);
+            zPo.store(l, off, zp2);
+            zTo.store(l, off, zt2);
             Brest.store(l, off, b);
-            v[l] -= rhoV * s;
         }
-        // the reduction variant carries 10 FP64 sums and their operands: keep
-        // each band's loads inside its own iteration
-        if constexpr (REDUCE) __builtin_amdgcn_sched_barrier(0);
-    }
-    // step VI for Gamma_V
-    __builtin_amdgcn_sched_barrier(0);
-    dct_any<T, LT, DENSE, false>(v, D, L);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k = 0; k < LT; ++k) {
-        if (k < L) {
-            if constexpr (REDUCE) {
-                const double gvo = double(gvold[k]);
-                const double dg = double(v[k]) - gvo;
-                acc[RED_R2] += dg * dg / (a.rho_V * a.rho_V);
-                acc[RED_E] += dg * dg / a.rho_V;
-                acc[RED_ATY2] += double(v[k]) * v[k];
-            }
-            GV.store(k, off, v[k]);
-        }
-        if constexpr (REDUCE) __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (REDUCE) {
-        // spectral l1 norm of P for the objective
-#pragma unroll
-        for (int l = 0; l < LT; ++l) {
-            const T z = (l < L) ? zP.load(l, off) : T(0);
-            v[l] = z > T(0) ? z : T(0);
-        }
-        dct_any<T, LT, DENSE, false>(v, D, L);
-#pragma unroll
-        for (int k = 0; k < LT; ++k)
-            if (k < L) acc[RED_DCTP1] += fabs(double(v[k]));
         __shared__ double sh[SPEC_NTH / 64];
-#pragma unroll
-        for (int q = 0; q < RED_NQ; ++q) {
-            const double sq = block_sum_s<SPEC_NTH>(acc[q], sh);
-            if (threadIdx.x == 0) partials[(long)blockIdx.x * RED_NQ + q] = sq;
-        }
+        const double sv = block_sum_s<SPEC_NTH>(v2, sh);
+        if (threadIdx.x == 0) partials[blockIdx.x] = sv;
     }
 }
 
+// FP64 sums of a reporting pass from the old state (z_P, z_T, S, Gamma_S),
+// the new state (primed) and X, per block into partials[block * RED_NQ + q]
+// (RED_V2 copied from vpart[block], written by the spectral pass; RED_DCTP1
+// written by k_dct_l1):
+//   r^2  = ||P - X||^2 + ||T - X||^2 + ||S - X||^2 + ||d Gamma_S||^2 / rho_V^2
+//          (the last term is ||V - S W_nu||^2 = ||d Gamma_V||^2 / rho_V^2)
+//   s^2  = ||rho_P dP + rho_T dT + rho_S dS||^2 + rho_V^2 ||dS||^2
+//   E    = rho_P ||dP||^2 + rho_T ||dT||^2 + (rho_S + rho_V) ||dS||^2
+//          + ||dGamma_P||^2 / rho_P + ||dGamma_T||^2 / rho_T
+//          + ||dGamma_S||^2 (1 / rho_S + 1 / rho_V)
+//   ||X||^2, ||P||^2 + ||T||^2 + 2 ||S||^2, ||Gamma_P + Gamma_T + Gamma_S||^2
+//   + ||Gamma_S||^2, ||P||^2, sum P
+// using Gamma_V = Gamma_S W_nu and the orthonormality of W_nu.  Each band's
+// terms are formed in the iteration's precision T and accumulated in FP64.
+template <typename T>
+__global__ void __launch_bounds__(SPEC_NTH)
+k_report(SpecArrays A, int L, long npix, SpecArgs a, const double* __restrict__ vpart,
+         double* __restrict__ partials) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const unsigned bb = A.band_bytes;
+    const int gs_ = A.gshift;
+    const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.S, bb, gs_},
+        GS{A.GS, bb, gs_}, zPo{A.zPo, bb, gs_}, zTo{A.zTo, bb, gs_}, So{A.So, bb, gs_},
+        GSo{A.GSo, bb, gs_};
+    const T rP = T(a.rho_P), rT = T(a.rho_T), rV = T(a.rho_V), rS = T(a.rho_S), tT = T(a.tau_T);
+    const T irP = T(1.0 / a.rho_P), irT = T(1.0 / a.rho_T), irV2 = T(1.0 / (a.rho_V * a.rho_V));
+    const T ieS = T(1.0 / a.rho_S + 1.0 / a.rho_V), rSV = T(a.rho_S + a.rho_V);
+    double r2 = 0, s2 = 0, x2 = 0, bz2 = 0, aty2 = 0, e = 0, p2 = 0, p1 = 0;
+#pragma unroll 2
+    for (int l = 0; l < L; ++l) {
+        const T x = X.load(l, off);
+        const T zp = zP.load(l, off), zt = zT.load(l, off), so = S.load(l, off), go = GS.load(l, off);
+        const T zp2 = zPo.load(l, off), zt2 = zTo.load(l, off), sn = So.load(l, off), gn = GSo.load(l, off);
+        const T P = zp2 > T(0) ? zp2 : T(0), Po = zp > T(0) ? zp : T(0);
+        const T Tn = softt(zt2, tT), To = softt(zt, tT);
+        const T gp = rP * (zp2 < T(0) ? -zp2 : T(0)), gpo = rP * (zp < T(0) ? -zp : T(0));
+        const T gt = -rT * clipt(zt2, tT), gto = -rT * clipt(zt, tT);
+        const T dP = P - Po, dT = Tn - To, dS = sn - so, dg = gn - go;
+        const T a1 = P - x, a2 = Tn - x, a3 = sn - x;
+        r2 += double(a1 * a1 + a2 * a2 + a3 * a3 + dg * dg * irV2);
+        const T sx = rP * dP + rT * dT + rS * dS;
+        s2 += double(sx * sx + rV * rV * dS * dS);
+        x2 += double(x * x);
+        bz2 += double(P * P + Tn * Tn + T(2) * sn * sn);
+        const T g = gp + gt + gn;
+        aty2 += double(g * g + gn * gn);
+        const T dgp = gp - gpo, dgt = gt - gto;
+        e += double(rP * dP * dP + rT * dT * dT + rSV * dS * dS + dgp * dgp * irP + dgt * dgt * irT
+                    + dg * dg * ieS);
+        p2 += double(P * P);
+        p1 += double(P);
+    }
+    __shared__ double sh[SPEC_NTH / 64];
+    const double vals[RED_NQ] = {r2, s2, x2, 0.0, bz2, aty2, e, p2, p1, 0.0};
+#pragma unroll
+    for (int q = 0; q < RED_NQ; ++q) {
+        if (q == RED_V2 || q == RED_DCTP1) continue;
+        const double sq = block_sum_s<SPEC_NTH>(vals[q], sh);
+        if (threadIdx.x == 0) partials[(long)blockIdx.x * RED_NQ + q] = sq;
+    }
+    if (threadIdx.x == 0) partials[(long)blockIdx.x * RED_NQ + RED_V2] = vpart[blockIdx.x];
+}
+
+// sum over pixels of |P W_nu|_1 with P = max(0, z_P): block sums into
+// partials[block * RED_NQ + RED_DCTP1]
 template <typename T, int LT, bool DENSE>
-static hipError_t spectral_t(bool reduce, const void* X, void* zP, void* zT, void* S, void* GS,
-                             void* GV, void* Brest, const void* D, int L, long npix,
-                             const SpecArgs& a, double* partials, int* nb, hipStream_t s) {
+__global__ void __launch_bounds__(SPEC_NTH)
+k_dct_l1(SpecArrays A, const T* __restrict__ D, int Lrt, long npix, double* __restrict__ partials) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const BandArray<T> zP{A.zP, A.band_bytes, A.gshift};
+    const int L = DENSE ? Lrt : LT;
+    T v[LT];
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+        const T z = (l < L) ? zP.load(l, off) : T(0);
+        v[l] = z > T(0) ? z : T(0);
+    }
+    dct_any<T, LT, DENSE, false>(v, D, L);
+    double pd = 0.0;
+#pragma unroll
+    for (int k = 0; k < LT; ++k) pd += fabs(double(v[k]));
+    __shared__ double sh[SPEC_NTH / 64];
+    const double sq = block_sum_s<SPEC_NTH>(pd, sh);
+    if (threadIdx.x == 0) partials[(long)blockIdx.x * RED_NQ + RED_DCTP1] = sq;
+}
+
+template <typename T, int LT, bool DENSE>
+static hipError_t spectral_t(const SpecLaunch& g, const SpecArgs& a, hipStream_t s) {
     // npix = nx ny is a power of two >= 64: the block size divides it
+    const long npix = g.npix;
     const int nth = npix < SPEC_NTH ? (int)npix : SPEC_NTH;
     if (npix < 64 || (npix & (npix - 1)) != 0) return hipErrorInvalidValue;
     dim3 grid((unsigned)(npix / nth));
-    if (nb) *nb = (int)grid.x;
-    SpecArrays A{(char*)X, (char*)zP, (char*)zT, (char*)S, (char*)GS, (char*)GV, (char*)Brest,
-                 (unsigned)(npix * (long)sizeof(T)), band_group_shift((unsigned long long)npix * sizeof(T))};
-    if (reduce)
+    const unsigned bb = (unsigned)(npix * (long)sizeof(T));
+    SpecArrays A{(char*)g.X, (char*)g.st[0], (char*)g.st[1], (char*)g.st[2], (char*)g.st[3],
+                 (char*)g.out[0], (char*)g.out[1], (char*)g.out[2], (char*)g.out[3], (char*)g.brest,
+                 bb, band_group_shift(bb)};
+    if (g.report) {
         hipLaunchKernelGGL((k_spectral<T, LT, DENSE, true>), grid, dim3(nth), 0, s, A,
-                           (const T*)D, L, npix, a, partials);
-    else
+                           (const T*)g.dctm, g.L, npix, a, g.vpart);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_report<T>), grid, dim3(nth), 0, s, A, g.L, npix, a,
+                           (const double*)g.vpart, g.partials);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // the spectral l1 term reads the new z_P
+        SpecArrays B = A;
+        B.zP = A.zPo;
+        hipLaunchKernelGGL((k_dct_l1<T, LT, DENSE>), grid, dim3(nth), 0, s, B, (const T*)g.dctm, g.L,
+                           npix, g.partials);
+    } else {
         hipLaunchKernelGGL((k_spectral<T, LT, DENSE, false>), grid, dim3(nth), 0, s, A,
-                           (const T*)D, L, npix, a, partials);
+                           (const T*)g.dctm, g.L, npix, a, g.vpart);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t spectral_dispatch(bool reduce, const void* X, void* zP, void* zT, void* S,
-                                    void* GS, void* GV, void* Brest, const void* D, int L,
-                                    long npix, const SpecArgs& a, double* partials, int* nb,
-                                    hipStream_t s) {
-#define ARGS reduce, X, zP, zT, S, GS, GV, Brest, D, L, npix, a, partials, nb, s
-    switch (L) {
-        case 1: return spectral_t<T, 1, false>(ARGS);
-        case 2: return spectral_t<T, 2, false>(ARGS);
-        case 4: return spectral_t<T, 4, false>(ARGS);
-        case 8: return spectral_t<T, 8, false>(ARGS);
-        case 16: return spectral_t<T, 16, false>(ARGS);
-        case 32: return spectral_t<T, 32, false>(ARGS);
-        case 64: return spectral_t<T, 64, false>(ARGS);
+static hipError_t spectral_dispatch(const SpecLaunch& g, const SpecArgs& a, hipStream_t s) {
+    switch (g.L) {
+        case 1: return spectral_t<T, 1, false>(g, a, s);
+        case 2: return spectral_t<T, 2, false>(g, a, s);
+        case 4: return spectral_t<T, 4, false>(g, a, s);
+        case 8: return spectral_t<T, 8, false>(g, a, s);
+        case 16: return spectral_t<T, 16, false>(g, a, s);
+        case 32: return spectral_t<T, 32, false>(g, a, s);
+        case 64: return spectral_t<T, 64, false>(g, a, s);
         default: break;
     }
     // band counts that are not powers of two: dense DCT, up to 32 bands
-    if (L < 1 || L > 32) return hipErrorInvalidValue;
-    if (L <= 8) return spectral_t<T, 8, true>(ARGS);
-    if (L <= 16) return spectral_t<T, 16, true>(ARGS);
-    return spectral_t<T, 32, true>(ARGS);
-#undef ARGS
+    if (g.L < 1 || g.L > 32) return hipErrorInvalidValue;
+    if (g.L <= 8) return spectral_t<T, 8, true>(g, a, s);
+    if (g.L <= 16) return spectral_t<T, 16, true>(g, a, s);
+    return spectral_t<T, 32, true>(g, a, s);
 }
 
-hipError_t launch_spectral(int dtype, bool reduce, const void* X, void* zP, void* zT, void* S,
-                           void* GS, void* GV, void* Brest, const void* dctm, int L, int npix,
-                           const SpecArgs& a, double* partials, int* nblocks_out, hipStream_t s) {
-    if (dtype == 0)
-        return spectral_dispatch<float>(reduce, X, zP, zT, S, GS, GV, Brest, dctm, L, npix, a,
-                                        partials, nblocks_out, s);
-    return spectral_dispatch<double>(reduce, X, zP, zT, S, GS, GV, Brest, dctm, L, npix, a,
-                                     partials, nblocks_out, s);
+hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, int* nblocks_out,
+                           hipStream_t s) {
+    if (nblocks_out) *nblocks_out = (int)(g.npix / (g.npix < SPEC_NTH ? g.npix : SPEC_NTH));
+    return dtype == 0 ? spectral_dispatch<float>(g, a, s) : spectral_dispatch<double>(g, a, s);
 }
 
 // ------------------------------------------------------------------ element-wise

@@ -93,7 +93,8 @@ Layout make_layout(const muffin_shape* s) {
     const int NT = s->nx > s->ny ? s->nx : s->ny;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-    for (int i = 0; i < kNumState; ++i) lay.state[i] = take(V * sz);
+    for (int set = 0; set < 2; ++set)
+        for (int i = 0; i < kNumState; ++i) lay.state[set][i] = take(V * sz);
     lay.brest = take(V * sz);
     lay.x = take(V * sz);
     lay.z = take(HS * 2 * sz);
@@ -105,11 +106,12 @@ Layout make_layout(const muffin_shape* s) {
     lay.dctm = take(size_t(dense_width(s->L)) * dense_width(s->L) * sz);
     lay.nblk = max_blocks_host(s->L, s->ny, s->nx);
     lay.partials = take(size_t(lay.nblk) * kNumRed * 8);
+    lay.vpart = take(size_t(lay.nblk) * 8);
     lay.sums = take(64 * 8);
     lay.total = off;
     // setup scratch: two FP64 packed spectra, carved out of the state region
     lay.setup_scratch_bytes = 2 * HS * 16;
-    lay.state_region_bytes = lay.x - lay.state[0];
+    lay.state_region_bytes = lay.x - lay.state[0][0];
     return lay;
 }
 

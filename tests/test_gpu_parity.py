@@ -176,7 +176,7 @@ def test_set_params_new_mu_s_converges_to_new_problem(gpu_lib):
     from paper_1504_06847_amd import Solver
     inst = make_instance(32, 32, 4, n_points=3, n_gauss=1, n_ant=12, noise_sigma=0.01, seed=9)
     p1 = O.Params(1e-2, 0.05, 0.05, 1.0, 1.0, 1.0, 1.0)
-    p2 = p1.with_(mu_s=0.2, rho_T=1.5)
+    p2 = p1.with_(mu_s=1.0, rho_T=1.5)
     s = Solver(inst.psf, inst.dirty, dtype=torch.float64, **_params(p1))
     s.iterate(30)
     s.set_params(**_params(p2))
@@ -184,8 +184,8 @@ def test_set_params_new_mu_s_converges_to_new_problem(gpu_lib):
     ref = O.run(O.Problem(inst.psf, inst.dirty, p2), 4000).X
     old_sol = O.run(O.Problem(inst.psf, inst.dirty, p1), 4000).X
     x = s.x.cpu().numpy()
-    assert rel(old_sol, ref) > 1e-2          # the two problems differ
-    assert rel(x, ref) < 1e-6
+    assert rel(old_sol, ref) > 1e-3          # the two problems differ (6e-3)
+    assert rel(x, ref) < 1e-8                # a CPU model of this run reaches 7e-12
 
 
 def test_report_matches_oracle(gpu_lib):
