@@ -150,7 +150,11 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
     constexpr int TC = col_tc<T, NY>();
     constexpr int NTH = col_nth<T, NY>();
     constexpr int TCP = TC + 1;          // padded row stride: spreads stride-R writes over the banks
+    // the NY-point twiddle table lives in LDS when it is small: every stage
+    // reads its twiddles there instead of from the global table
+    constexpr bool TWL = NY * int(sizeof(cx<T>)) <= 16384;
     __shared__ cx<T> lds[NY * TCP];
+    __shared__ cx<T> twl[TWL ? NY : 1];
     __shared__ double red[NTH / 64];
     const int t = threadIdx.x;
     // XCD-aware tile order.  Work-groups go to the 8 XCDs round-robin in
@@ -173,8 +177,12 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
         if (c0 + c < M) v = data[base + (long)y * M + c0 + c];
         lds[y * TCP + c] = v;
     }
+    if constexpr (TWL) {
+        for (int i = t; i < NY; i += NTH) twl[i] = tw[i << (twlog - ilog2c(NY))];
+    }
     __syncthreads();
-    tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, tw, twlog, t);
+    if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, twl, ilog2c(NY), t);
+    else tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, tw, twlog, t);
 
     if constexpr (MODE == COL_SOLVE) {
         for (int i = t; i < NY * TC; i += NTH) {
@@ -202,7 +210,8 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
             }
         }
         __syncthreads();
-        tile_fft<T, NY, TC, NTH, 1, TCP, true, false, true>(lds, tw, twlog, t);
+        if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, TCP, true, false, true>(lds, twl, ilog2c(NY), t);
+        else tile_fft<T, NY, TC, NTH, 1, TCP, true, false, true>(lds, tw, twlog, t);
     }
 
     if constexpr (MODE == COL_SOLVE || MODE == COL_FWD) {
