@@ -111,12 +111,12 @@ def cpu_baseline(inst, params, iters: int):
                        f"pass; scipy.fft with {workers} threads, {dt:.1f} s")
 
 
-def run_gpu(inst, params, dtype, steps, warmup, profile_iters):
+def run_gpu(inst, params, dtype, steps, warmup, profile_iters, graph=False):
     import torch
     from paper_1504_06847_amd import Solver
     kw = dict(mu_eps=params.mu_eps, mu_s=params.mu_s, mu_nu=params.mu_nu, rho_P=params.rho_P,
               rho_T=params.rho_T, rho_V=params.rho_V, rho_S=params.rho_S)
-    s = Solver(inst.psf, inst.dirty, dtype=dtype, **kw)
+    s = Solver(inst.psf, inst.dirty, dtype=dtype, graph=graph, **kw)
     s.iterate(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -141,6 +141,7 @@ def main(argv=None):
     ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay each pass from a HIP graph")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration)")
     a = ap.parse_args(argv)
@@ -161,7 +162,8 @@ def main(argv=None):
     inst = cfg.make()
     V = cfg.voxels
     _log(f"bench: FP32 {a.warmup} warmup + {a.steps} timed passes")
-    ms32, prof32 = run_gpu(inst, cfg.params, torch.float32, a.steps, a.warmup, a.profile_iters)
+    ms32, prof32 = run_gpu(inst, cfg.params, torch.float32, a.steps, a.warmup, a.profile_iters,
+                           graph=a.graph)
     value = V * a.steps / (ms32 / 1e3)
     kernels = {}
     for name, kms in prof32.items():
@@ -203,7 +205,7 @@ def main(argv=None):
         "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} pixels x {cfg.L} bands, FP32 ADMM "
                                f"pass (Dirac W_s, DCT-II W_nu), rho=1, mu_s=mu_nu=0.02, mu_eps=1e-3",
                    "nx": cfg.nx, "ny": cfg.ny, "L": cfg.L, "voxels": V,
-                   "parallelism": "1 GPU"},
+                   "parallelism": "1 GPU", "graph": bool(a.graph)},
         "roofline": roof,
         # one pass at this rate against the HBM peak, counting the minimum
         # bytes of this algorithm (4-array state, 54 B/voxel in FP32) and of

@@ -62,7 +62,7 @@ extern "C" {
 #define MUFFIN_MODE_MSE 0          /* muffin_grad: loss = ||x_K - sky||^2, sky given */
 #define MUFFIN_MODE_VJP 1          /* muffin_grad: cotangent dL/dx_K given */
 
-#define MUFFIN_MAX_BANDS 64        /* largest L of the register-resident spectral pass;
+#define MUFFIN_MAX_BANDS 128       /* largest L of the register-resident spectral pass;
                                       above 32 bands L must be a power of two */
 
 /* ---- plain-data structs -------------------------------------------------- */
@@ -178,6 +178,13 @@ int muffin_set_params(muffin_ctx* ctx, const muffin_params* params);
 
 /* Zero the ADMM state (Algorithm 1 initialisation) and the iteration count. */
 int muffin_reset(muffin_ctx* ctx);
+
+/* Replay each pass of muffin_iterate / muffin_solve from a HIP graph
+   (enable = 1) instead of launching its kernels one by one (0, the default).
+   The graph is recorded on a private stream at the first pass and replayed
+   on the context's stream; muffin_set_params records a new one.  Results are
+   bitwise identical to the launched form.  Errors: EINVAL, EDEVICE. */
+int muffin_set_graph(muffin_ctx* ctx, int enable);
 
 /* Number of passes run since setup/reset. */
 int muffin_iterations(const muffin_ctx* ctx);

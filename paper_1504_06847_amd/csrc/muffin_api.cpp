@@ -29,6 +29,11 @@ struct muffin_ctx {
     // scratch owned by the library (reverse sweep of muffin_grad)
     void* grad_buf;
     size_t grad_bytes;
+    // graph replay of one pass: captured on a private stream, one executable
+    // graph per state set, replayed on `stream`
+    int use_graph;
+    hipStream_t cap;
+    hipGraphExec_t gexec[2];
 };
 
 namespace {
@@ -107,11 +112,56 @@ int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
     return MUFFIN_OK;
 }
 
-int one_pass(muffin_ctx* c) {
+int pass_kernels(muffin_ctx* c) {
     int rc = step_one(c);
     if (rc) return rc;
-    rc = step_spectral(c, false, nullptr);
-    if (rc) return rc;
+    return step_spectral(c, false, nullptr);
+}
+
+void drop_graphs(muffin_ctx* c) {
+    for (int i = 0; i < 2; ++i) {
+        if (c->gexec[i]) hipGraphExecDestroy(c->gexec[i]);
+        c->gexec[i] = nullptr;
+    }
+}
+
+// record the kernels of one pass (state set c->cur) into an executable graph
+int capture_pass(muffin_ctx* c) {
+    if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    c->stream = c->cap;
+    hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? pass_kernels(c) : MUFFIN_EDEVICE;
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+    c->stream = user;
+    if (e != hipSuccess || e2 != hipSuccess || rc != MUFFIN_OK) {
+        if (g) hipGraphDestroy(g);
+        if (rc == MUFFIN_OK)
+            set_error("graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        return rc == MUFFIN_OK ? MUFFIN_EDEVICE : rc;
+    }
+    e = hipGraphInstantiate(&c->gexec[c->cur], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec[c->cur] = nullptr;
+        set_error("graph instantiation failed: %s", hipGetErrorString(e));
+        return MUFFIN_EDEVICE;
+    }
+    return MUFFIN_OK;
+}
+
+int one_pass(muffin_ctx* c) {
+    if (c->use_graph) {
+        if (!c->gexec[c->cur]) {
+            int rc = capture_pass(c);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
+    } else {
+        int rc = pass_kernels(c);
+        if (rc) return rc;
+    }
     c->iters++;
     return MUFFIN_OK;
 }
@@ -274,6 +324,9 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     c->twlog = ilog2i(NT);
     c->grad_buf = nullptr;
     c->grad_bytes = 0;
+    c->use_graph = 0;
+    c->cap = nullptr;
+    c->gexec[0] = c->gexec[1] = nullptr;
 
     auto fail = [&](int code) { delete c; return code; };
     const bool in64 = shape->dtype == MUFFIN_F64;
@@ -419,6 +472,7 @@ int muffin_set_params(muffin_ctx* c, const muffin_params* params) {
     int rc = validate_params(params);
     if (rc) return rc;
     const muffin_params old = c->params;
+    drop_graphs(c);      // the parameters are kernel arguments of the recorded pass
     if (old.rho_P != params->rho_P || old.rho_T != params->rho_T) {
         // keep P, Gamma_P and T, Gamma_T of the stored state under the new rho's
         HIP_TRY(launch_reencode(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), voxels(c->shape),
@@ -494,8 +548,16 @@ int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int
     return MUFFIN_EUNSUPPORTED;
 }
 
+int muffin_set_graph(muffin_ctx* c, int enable) {
+    if (int rc = check_ctx(c)) return rc;
+    c->use_graph = enable ? 1 : 0;
+    return MUFFIN_OK;
+}
+
 int muffin_destroy(muffin_ctx* c) {
     if (!c) return MUFFIN_OK;
+    drop_graphs(c);
+    if (c->cap) hipStreamDestroy(c->cap);
     if (c->grad_buf) hipFree(c->grad_buf);
     delete c;
     return MUFFIN_OK;

@@ -290,6 +290,7 @@ static hipError_t spectral_dispatch(const SpecLaunch& g, const SpecArgs& a, hipS
         case 16: return spectral_t<T, 16, false>(g, a, s);
         case 32: return spectral_t<T, 32, false>(g, a, s);
         case 64: return spectral_t<T, 64, false>(g, a, s);
+        case 128: return spectral_t<T, 128, false>(g, a, s);
         default: break;
     }
     // band counts that are not powers of two: dense DCT, up to 32 bands

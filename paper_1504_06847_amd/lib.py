@@ -27,7 +27,7 @@ MUFFIN_DIRAC = 0
 MUFFIN_DCT2_ORTHO = 0
 MUFFIN_MODE_MSE = 0
 MUFFIN_MODE_VJP = 1
-MUFFIN_MAX_BANDS = 64
+MUFFIN_MAX_BANDS = 128
 
 ERROR_NAMES = {
     MUFFIN_EINVAL: "MUFFIN_EINVAL", MUFFIN_EUNSUPPORTED: "MUFFIN_EUNSUPPORTED",
@@ -77,6 +77,7 @@ SIGNATURES = [
     ("muffin_set_params", c_int, [c_void_p, POINTER(MuffinParams)]),
     ("muffin_reset", c_int, [c_void_p]),
     ("muffin_iterations", c_int, [c_void_p]),
+    ("muffin_set_graph", c_int, [c_void_p, c_int]),
     ("muffin_profile", c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_char_p), c_int]),
     ("muffin_destroy", c_int, [c_void_p]),
     ("muffin_last_error", c_char_p, []),

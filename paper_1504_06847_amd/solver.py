@@ -34,7 +34,8 @@ class Solver:
     torch.float64) for the iteration's precision.
     """
 
-    def __init__(self, psf, dirty, *, dtype=torch.float32, device="cuda", stream=None, **params):
+    def __init__(self, psf, dirty, *, dtype=torch.float32, device="cuda", stream=None, graph=False,
+                 **params):
         self._lib = L.load()
         self._ctx = c_void_p()
         if dtype not in (torch.float32, torch.float64):
@@ -65,6 +66,12 @@ class Solver:
                                     c_void_p(self._ws_ptr), ws_bytes,
                                     c_void_p(self.stream.cuda_stream))
         L.check(rc, "muffin_setup", self._lib)
+        if graph:
+            self.set_graph(True)
+
+    def set_graph(self, enable: bool = True):
+        """Replay each pass from a HIP graph (bitwise identical results)."""
+        L.check(self._lib.muffin_set_graph(self._ctx, 1 if enable else 0), "muffin_set_graph", self._lib)
 
     # -------------------------------------------------------------- params
     def _make_params(self, params):

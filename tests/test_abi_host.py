@@ -79,7 +79,8 @@ def test_parameter_validation(lib, field, value, code):
 @pytest.mark.parametrize("nx,ny,Lb,dtype,code", [
     (64, 64, 8, 0, 0), (8, 8, 1, 1, 0), (4096, 8, 64, 0, 0), (64, 64, 15, 0, 0),
     (64, 64, 0, 0, -1), (0, 64, 8, 0, -1), (60, 64, 8, 0, -2), (64, 8192, 8, 0, -2),
-    (4, 64, 8, 0, -2), (64, 64, 65, 0, -2), (64, 64, 48, 0, -2), (64, 64, 8, 7, -2),
+    (4, 64, 8, 0, -2), (64, 64, 129, 0, -2), (64, 64, 48, 0, -2), (64, 64, 96, 0, -2),
+    (64, 64, 128, 0, 0), (64, 64, 8, 7, -2),
 ])
 def test_shape_validation(lib, nx, ny, Lb, dtype, code):
     from paper_1504_06847_amd import lib as L
