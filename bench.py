@@ -17,6 +17,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -131,6 +133,71 @@ def run_gpu(inst, params, dtype, steps, warmup, profile_iters, graph=False):
     return ms, prof
 
 
+def batch_instances():
+    """The uneven batch: 16 cubes, N^2 in {128^2, 256^2, 512^2} x L in {16, 32,
+    64, 128} (shapes drawn with seed 3), each drawn with the 256^2 x 32
+    generator settings (40 points, 10 Gaussians, 40 antennas, sigma 0.005),
+    seed 300 + i."""
+    from synth import get_config, make_instance
+    from synth.configs import batched_shapes
+    c = get_config("fp32_256")
+    out = []
+    for i, (ny, nx, L) in enumerate(batched_shapes()):
+        inst = make_instance(ny, nx, L, n_points=c.n_points, n_gauss=c.n_gauss, n_ant=c.n_ant,
+                             noise_sigma=c.noise_sigma, seed=300 + i)
+        out.append((inst.psf, inst.dirty))
+    return out, c.params
+
+
+def run_batch(steps, warmup):
+    """voxel-iterations/s of the batch: each cube iterated on its own (one
+    cube after another, the plain per-cube launches), then grouped launches,
+    then grouped launches replayed from a graph, then the same after the
+    schedule autotuner."""
+    import torch
+    from paper_1504_06847_amd import Batch, Solver
+    cubes, p = batch_instances()
+    kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho_P=p.rho_P, rho_T=p.rho_T,
+              rho_V=p.rho_V, rho_S=p.rho_S)
+    V = sum(int(np.prod(c[0].shape)) for c in cubes)
+
+    def timed(fn):
+        fn(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    solvers = [Solver(a, b, **kw) for a, b in cubes]
+
+    def seq(k):
+        for s in solvers:
+            s.iterate(k)
+    ms_seq = timed(seq)
+    for s in solvers:
+        s.close()
+    del solvers
+    b = Batch(cubes, params=kw)
+    ms_grp = timed(lambda k: b.iterate(k))
+    b.set_graph(True)
+    ms_graph = timed(lambda k: b.iterate(k))
+    b.autotune(reps=5)
+    ms_tuned = timed(lambda k: b.iterate(k))
+    launches = b.launches
+    b.close()
+    rate = lambda ms: V * steps / (ms / 1e3)
+    return {"cubes": len(cubes), "voxels": V, "steps": steps,
+            "shapes": [list(c[0].shape) for c in cubes],
+            "per_cube_sequential": rate(ms_seq), "grouped": rate(ms_grp),
+            "grouped_graph": rate(ms_graph), "grouped_graph_autotuned": rate(ms_tuned),
+            "grouped_launches_per_pass": launches,
+            "speedup_vs_sequential": round(ms_seq / min(ms_grp, ms_graph, ms_tuned), 3),
+            "unit": "voxel-iterations/s"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +209,8 @@ def main(argv=None):
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay each pass from a HIP graph")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 16-cube batch measurement")
+    ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration)")
     a = ap.parse_args(argv)
@@ -185,6 +254,10 @@ def main(argv=None):
         ms64, prof64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5)
         fp64 = dict(value=V * a.fp64_steps / (ms64 / 1e3), ms_per_step=round(ms64 / a.fp64_steps, 4),
                     kernels_ms={k: round(v, 5) for k, v in prof64.items()})
+    batch = None
+    if not a.no_batch:
+        _log(f"bench: 16-cube batch, {a.batch_steps} passes per form")
+        batch = run_batch(a.batch_steps, 3)
     cpu = None
     if not a.no_cpu_baseline:
         _log(f"bench: CPU oracle, {a.cpu_iters} passes")
@@ -214,6 +287,7 @@ def main(argv=None):
         "iteration_62B_frac": round(ITER_MIN5_ELEMS * 4 * value / 1e9 / HBM_PEAK_GBPS, 4),
         "kernels": kernels,
         "fp64": fp64,
+        "batched": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

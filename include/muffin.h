@@ -189,6 +189,75 @@ int muffin_set_graph(muffin_ctx* ctx, int enable);
 /* Number of passes run since setup/reset. */
 int muffin_iterations(const muffin_ctx* ctx);
 
+/* ---- FFT tile schedules (the 2-D transform of step I, eq. Qlsimp) --------
+   A schedule is two variant indices in [0, 3): schedule[0] for the row
+   passes (0, 1, 2: about 1024, 2048, 4096 complex points per work-group),
+   schedule[1] for the column pass (0, 1, 2: half, all or twice the column
+   tile that fits 64 KiB of LDS; twice only where the LDS holds it).  Every
+   schedule evaluates the same formulas in the same order; the compiler may
+   fuse a product and a sum into one FMA in one schedule's code and not in
+   another's, so results agree to rounding (a few ulps), not bit for bit.
+   Default {1, 1}. */
+
+/* Time each variant of the three transform passes `reps` times on this
+   context's own arrays (the timing writes only the pass's internal spectrum
+   buffer and the unused second state set: X and the state are unchanged),
+   keep the fastest and write it to schedule (may be NULL).  Synchronises the
+   stream.  Errors: EINVAL (reps < 1), EDEVICE. */
+int muffin_autotune(muffin_ctx* ctx, int reps, int schedule[2]);
+
+/* Use a stored schedule (e.g. one muffin_autotune found for this shape).
+   Errors: EINVAL (index out of range). */
+int muffin_set_schedule(muffin_ctx* ctx, const int schedule[2]);
+int muffin_get_schedule(const muffin_ctx* ctx, int schedule[2]);
+
+/* ---- batches of independent cubes ----------------------------------------
+   Many cubes of uneven size and band count (each its own instance of the
+   problem of Section 2, solved by Algorithm 1) iterating together: each
+   pass runs one grouped launch per transform pass and shape class (row
+   passes per nx, the column pass per ny, the spectral pass per band count)
+   that covers the tiles of every cube in the class, so that small cubes
+   share the GPU instead of running one after another.  Results are bitwise
+   identical to iterating each cube on its own with the same schedule. */
+typedef struct muffin_batch muffin_batch;
+
+/* Device workspace bytes for n cubes: the per-cube workspaces
+   (muffin_workspace_bytes, 256-B aligned) plus the launch descriptors.
+   0 if a shape or parameter set is invalid, n < 1, n > MUFFIN_MAX_BATCH or
+   the dtypes differ. */
+#define MUFFIN_MAX_BATCH 256
+size_t muffin_batch_workspace_bytes(int n, const muffin_shape* shapes, const muffin_params* params);
+
+/* Set up n cubes: shapes[i], params[i], psf[i], dirty[i] as for
+   muffin_setup (every cube in one dtype), one 256-B aligned workspace of at
+   least muffin_batch_workspace_bytes bytes, one stream for all cubes.
+   Errors: as muffin_setup, plus EINVAL for n out of range or mixed dtypes. */
+int muffin_batch_setup(muffin_batch** batch, int n, const muffin_shape* shapes,
+                       const muffin_params* params, const void* const* psf,
+                       const void* const* dirty, void* workspace, size_t ws_bytes, void* stream);
+
+/* n_iter passes of every cube (asynchronous on the batch stream). */
+int muffin_batch_iterate(muffin_batch* batch, int n_iter);
+
+/* The context of cube i (owned by the batch; do not destroy it).  Every
+   single-cube call works on it (muffin_get_x, muffin_step_report,
+   muffin_solve, muffin_set_params, state calls ...); the batch notices the
+   changes before its next pass.  NULL if i is out of range. */
+muffin_ctx* muffin_batch_cube(muffin_batch* batch, int i);
+
+/* Time the variants of each grouped transform launch (as muffin_autotune,
+   per shape class) and keep the fastest.  Synchronises the stream. */
+int muffin_batch_autotune(muffin_batch* batch, int reps);
+
+/* Replay each batch pass from one HIP graph (as muffin_set_graph). */
+int muffin_batch_set_graph(muffin_batch* batch, int enable);
+
+/* Number of grouped launches per pass (shape classes of the four passes). */
+int muffin_batch_launches(const muffin_batch* batch);
+
+/* Release the batch and its cube contexts.  NULL is a no-op. */
+int muffin_batch_destroy(muffin_batch* batch);
+
 /* Time n_iter passes with HIP events around every kernel launch on the
    context's stream; writes the mean duration in ms of each kernel of one
    pass to ms[i] and its name to names[i] (static strings), for up to `cap`

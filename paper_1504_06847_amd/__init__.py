@@ -6,6 +6,8 @@ Importing the package does not touch the GPU; ``lib.load()`` (called by
 ``Solver``) loads libmuffin.so and fails loudly when it is not built.
 """
 from . import lib
+from .autograd import MuffinUnroll
+from .batch import Batch
 from .solver import Solver
 
-__all__ = ["lib", "Solver"]
+__all__ = ["lib", "Batch", "MuffinUnroll", "Solver"]

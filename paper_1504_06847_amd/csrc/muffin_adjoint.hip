@@ -1,0 +1,266 @@
+// Reverse sweep of K unrolled passes of Algorithm 1 (Section 3) on gfx950:
+// the adjoint of the reduced pass of muffin_spectral.hip, one launch per
+// pass for the band-coupled part (steps II-VI) and one elementwise launch
+// for the right-hand side of step I (eq. matB).  The step I solve itself is
+// symmetric (Q = H^T H + rho I, eq. Qlsimp), so its adjoint reuses the
+// column pass in filter mode.
+//
+// Forward pass k, per pixel, from the state (z_P, z_T, S, Gamma_S):
+//   B   = H^T Y + rho_T (2 soft(z_T, tau_T) - z_T) + rho_P |z_P| + Gamma_S + rho_S S
+//   X   = Q^{-1} B
+//   c   = DCT(S - Gamma_S / rho_V),  V = soft(c, tau_V),  q = IDCT(V)
+//   S'  = (rho_V q + rho_S X) / (rho_V + rho_S)
+//   G'  = Gamma_S + rho_V (q - S')
+//   z_P' = X - max(0, -z_P),  z_T' = X + clip(z_T, tau_T)
+// with tau_T = mu_s / rho_T, tau_V = mu_nu / rho_V.  Derivatives at the
+// kinks: soft' = 1[|z| > tau], clip' = 1[|z| <= tau], max(0, .)' = 1[. > 0],
+// |z|' = sign(z) (0 at 0).
+//
+// The parameter cotangents are accumulated in FP64 per block into
+// partials[block * GRAD_NQ + slot] (GradSlot).
+#include "muffin_device.hpp"
+#include "muffin_kernels.hpp"
+
+namespace muffin {
+
+constexpr int ADJ_NTH = 256;
+
+template <typename T> __device__ __forceinline__ T sgnt(T z) {
+    return z > T(0) ? T(1) : (z < T(0) ? T(-1) : T(0));
+}
+
+// writes the GRAD_NQ block sums of vals (thread 0 of each block)
+__device__ __forceinline__ void store_grad_partials(const double (&vals)[GRAD_NQ], double* partials,
+                                                    unsigned blk) {
+    __shared__ double sh[ADJ_NTH / 64];
+#pragma unroll
+    for (int q = 0; q < GRAD_NQ; ++q) {
+        const double s = block_sum_s<ADJ_NTH>(vals[q], sh);
+        if (threadIdx.x == 0) partials[(long)blk * GRAD_NQ + q] = s;
+    }
+}
+
+// Adjoint of steps II-VI of pass k at one pixel.  In: the state before the
+// pass (zP, zT, S, GS), the pass's X, the cotangents of the state after the
+// pass (aP, aT, aS, aG, overwritten in place by those of the state before
+// it, this part of them) and, with has_ext, an outside cotangent of X in Xb.
+// Out: Xb = the total cotangent of X.
+template <typename T, int LT, bool DENSE>
+__global__ void __launch_bounds__(ADJ_NTH)
+k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int has_ext,
+               double* __restrict__ partials) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const unsigned bb = A.band_bytes;
+    const int gs_ = A.gshift;
+    const BandArray<T> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.S, bb, gs_}, GS{A.GS, bb, gs_},
+        X{A.X, bb, gs_}, aP{A.aP, bb, gs_}, aT{A.aT, bb, gs_}, aS{A.aS, bb, gs_}, aG{A.aG, bb, gs_},
+        Xb{A.Xb, bb, gs_};
+    const int L = DENSE ? Lrt : LT;
+    const T rhoV = T(a.rho_V), rhoS = T(a.rho_S), tauT = T(a.tau_T), tauV = T(a.tau_V);
+    const T inv_rhoV = T(1.0 / a.rho_V), inv_VS = T(1.0 / (a.rho_V + a.rho_S));
+    const T inv_rhoV2 = T(1.0 / (a.rho_V * a.rho_V));
+    constexpr int W = (LT + 31) / 32;
+    unsigned mc[W], sc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) mc[w] = sc[w] = 0u;
+
+    T v[LT];
+    // forward: c = DCT(S - Gamma_S / rho_V); keep the kink pattern of soft(c)
+#pragma unroll
+    for (int l = 0; l < LT; ++l) v[l] = (l < L) ? S.load(l, off) - GS.load(l, off) * inv_rhoV : T(0);
+    dct_any<T, LT, DENSE, false>(v, D, L);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < LT; ++k) {
+        if (fabs(v[k]) > tauV) mc[k >> 5] |= 1u << (k & 31);
+        if (v[k] < T(0)) sc[k >> 5] |= 1u << (k & 31);
+        v[k] = softt(v[k], tauV);
+    }
+    dct_any<T, LT, DENSE, true>(v, D, L);        // q
+    __builtin_amdgcn_sched_barrier(0);
+
+    double g_tT = 0.0, g_tV = 0.0, g_rV = 0.0, g_rS = 0.0;
+    // steps VI and V backwards, band by band: v becomes the cotangent of q
+    // (the cotangent of S' in total is sig = aS - rho_V aG)
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+        if (l < L) {
+            const T x = X.load(l, off), sb = aS.load(l, off), gb = aG.load(l, off);
+            const T q = v[l];
+            const T s2 = (rhoV * q + rhoS * x) * inv_VS;
+            const T sig = sb - rhoV * gb;
+            v[l] = rhoV * gb + sig * rhoV * inv_VS;
+            g_rV += double(gb * (q - s2) + sig * (q - s2) * inv_VS);
+            g_rS += double(sig * (x - s2) * inv_VS);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // step IV backwards: V-bar = DCT(q-bar), c-bar = V-bar on the support of soft
+    dct_any<T, LT, DENSE, false>(v, D, L);
+#pragma unroll
+    for (int k = 0; k < LT; ++k) {
+        const bool m = (mc[k >> 5] >> (k & 31)) & 1u;
+        const bool neg = (sc[k >> 5] >> (k & 31)) & 1u;
+        if (m) g_tV += double(neg ? v[k] : -v[k]);
+        else v[k] = T(0);
+    }
+    dct_any<T, LT, DENSE, true>(v, D, L);         // u-bar = IDCT(c-bar)
+    __builtin_amdgcn_sched_barrier(0);
+    // the state cotangents before the pass, X-bar, and steps III, II backwards
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+        if (l < L) {
+            const T sb = aS.load(l, off), gb = aG.load(l, off), pb = aP.load(l, off), tb = aT.load(l, off);
+            const T zp = zP.load(l, off), zt = zT.load(l, off), gs = GS.load(l, off);
+            const T ext = has_ext ? Xb.load(l, off) : T(0);
+            const T sig = sb - rhoV * gb;
+            const T ub = v[l];
+            Xb.store(l, off, ext + pb + tb + sig * rhoS * inv_VS);
+            aS.store(l, off, ub);
+            aG.store(l, off, gb - ub * inv_rhoV);
+            g_rV += double(ub * gs * inv_rhoV2);
+            aP.store(l, off, zp < T(0) ? pb : T(0));
+            const bool out = fabs(zt) > tauT;
+            aT.store(l, off, out ? T(0) : tb);
+            if (out) g_tT += double(zt > T(0) ? tb : -tb);
+        }
+    }
+    const double vals[GRAD_NQ] = {g_tT, g_tV, 0.0, 0.0, g_rV, g_rS, 0.0, 0.0};
+    store_grad_partials(vals, partials, blockIdx.x);
+}
+
+// Adjoint of the right-hand side of step I (eq. matB): Bb = Q^{-1} X-bar is
+// the cotangent of B; adds its part to the state cotangents (in place) and
+// accumulates the parameter terms, -<Bb, X> for rho_Q included.
+template <typename T>
+__global__ void __launch_bounds__(ADJ_NTH)
+k_adj_step1(const T* __restrict__ Bb, const T* __restrict__ zP, const T* __restrict__ zT,
+            const T* __restrict__ S, const T* __restrict__ X, T* __restrict__ aP, T* __restrict__ aT,
+            T* __restrict__ aS, T* __restrict__ aG, long n, SpecArgs a, double* __restrict__ partials) {
+    const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoS = T(a.rho_S), tauT = T(a.tau_T);
+    double g_tT = 0, g_rP = 0, g_rT = 0, g_rS = 0, g_rQ = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const T b = Bb[i], zp = zP[i], zt = zT[i];
+        const bool out = fabs(zt) > tauT;
+        aT[i] += b * rhoT * (out ? T(1) : T(-1));
+        aP[i] += b * rhoP * sgnt(zp);
+        aG[i] += b;
+        aS[i] += rhoS * b;
+        if (out) g_tT += double(-T(2) * rhoT * b * sgnt(zt));
+        g_rT += double(b * (T(2) * softt(zt, tauT) - zt));
+        g_rP += double(b * fabs(zp));
+        g_rS += double(b * S[i]);
+        g_rQ -= double(b * X[i]);
+    }
+    const double vals[GRAD_NQ] = {g_tT, 0.0, g_rP, g_rT, 0.0, g_rS, g_rQ, 0.0};
+    store_grad_partials(vals, partials, blockIdx.x);
+}
+
+// seed of the MSE loss: Xb = 2 (X - sky), loss partials sum (X - sky)^2
+template <typename T>
+__global__ void __launch_bounds__(ADJ_NTH)
+k_mse_seed(const T* __restrict__ X, const T* __restrict__ sky, T* __restrict__ Xb, long n,
+           double* __restrict__ partials) {
+    double l2 = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const T d = X[i] - sky[i];
+        Xb[i] = T(2) * d;
+        l2 += double(d) * double(d);
+    }
+    const double vals[GRAD_NQ] = {0, 0, 0, 0, 0, 0, 0, l2};
+    store_grad_partials(vals, partials, blockIdx.x);
+}
+
+// acc[q] += sum over blocks of partials[b * GRAD_NQ + q], fixed order
+__global__ void __launch_bounds__(256)
+k_grad_accum(const double* __restrict__ partials, int nblocks, double* __restrict__ acc) {
+    const int q = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(long)b * GRAD_NQ + q];
+    __shared__ double sh[256 / 64];
+    const double r = block_sum_s<256>(s, sh);
+    if (threadIdx.x == 0) acc[q] += r;
+}
+
+static unsigned adj_grid(long n) {
+    long b = (n + ADJ_NTH - 1) / ADJ_NTH;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <typename T, int LT, bool DENSE>
+static hipError_t adj_t(const AdjArrays& A, const void* D, int L, long npix, const SpecArgs& a,
+                        int has_ext, double* partials, int* nblocks, hipStream_t s) {
+    const int nth = npix < ADJ_NTH ? (int)npix : ADJ_NTH;
+    if (npix < 64 || (npix & (npix - 1)) != 0) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)(npix / nth);
+    *nblocks = (int)g;
+    hipLaunchKernelGGL((k_adj_spectral<T, LT, DENSE>), dim3(g), dim3(nth), 0, s, A, (const T*)D, L, a,
+                       has_ext, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t adj_dispatch(const AdjArrays& A, const void* D, int L, long npix, const SpecArgs& a,
+                               int has_ext, double* partials, int* nb, hipStream_t s) {
+    switch (L) {
+        case 1: return adj_t<T, 1, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        case 2: return adj_t<T, 2, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        case 4: return adj_t<T, 4, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        case 8: return adj_t<T, 8, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        case 16: return adj_t<T, 16, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        case 32: return adj_t<T, 32, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        case 64: return adj_t<T, 64, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        case 128: return adj_t<T, 128, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        default: break;
+    }
+    if (L < 1 || L > 32) return hipErrorInvalidValue;
+    if (L <= 8) return adj_t<T, 8, true>(A, D, L, npix, a, has_ext, partials, nb, s);
+    if (L <= 16) return adj_t<T, 16, true>(A, D, L, npix, a, has_ext, partials, nb, s);
+    return adj_t<T, 32, true>(A, D, L, npix, a, has_ext, partials, nb, s);
+}
+
+hipError_t launch_adj_spectral(int dtype, const AdjArrays& A, const void* D, int L, long npix,
+                               const SpecArgs& a, int has_ext, double* partials, int* nblocks,
+                               hipStream_t s) {
+    return dtype == 0 ? adj_dispatch<float>(A, D, L, npix, a, has_ext, partials, nblocks, s)
+                      : adj_dispatch<double>(A, D, L, npix, a, has_ext, partials, nblocks, s);
+}
+
+hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* S,
+                            const void* X, void* aP, void* aT, void* aS, void* aG, size_t n,
+                            const SpecArgs& a, double* partials, int* nblocks, hipStream_t s) {
+    const unsigned g = adj_grid((long)n);
+    *nblocks = (int)g;
+    if (dtype == 0)
+        hipLaunchKernelGGL((k_adj_step1<float>), dim3(g), dim3(ADJ_NTH), 0, s, (const float*)Bb,
+                           (const float*)zP, (const float*)zT, (const float*)S, (const float*)X,
+                           (float*)aP, (float*)aT, (float*)aS, (float*)aG, (long)n, a, partials);
+    else
+        hipLaunchKernelGGL((k_adj_step1<double>), dim3(g), dim3(ADJ_NTH), 0, s, (const double*)Bb,
+                           (const double*)zP, (const double*)zT, (const double*)S, (const double*)X,
+                           (double*)aP, (double*)aT, (double*)aS, (double*)aG, (long)n, a, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse_seed(int dtype, const void* X, const void* sky, void* Xb, size_t n,
+                           double* partials, int* nblocks, hipStream_t s) {
+    const unsigned g = adj_grid((long)n);
+    *nblocks = (int)g;
+    if (dtype == 0)
+        hipLaunchKernelGGL((k_mse_seed<float>), dim3(g), dim3(ADJ_NTH), 0, s, (const float*)X,
+                           (const float*)sky, (float*)Xb, (long)n, partials);
+    else
+        hipLaunchKernelGGL((k_mse_seed<double>), dim3(g), dim3(ADJ_NTH), 0, s, (const double*)X,
+                           (const double*)sky, (double*)Xb, (long)n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_accum(const double* partials, int nblocks, double* acc, hipStream_t s) {
+    hipLaunchKernelGGL(k_grad_accum, dim3(GRAD_NQ), dim3(256), 0, s, partials, nblocks, acc);
+    return hipGetLastError();
+}
+
+}  // namespace muffin

@@ -10,83 +10,26 @@
 #include <vector>
 
 #include "muffin.h"
+#include "muffin_ctx.hpp"
 #include "muffin_kernels.hpp"
 #include "muffin_layout.hpp"
 
 using namespace muffin;
 
-struct muffin_ctx {
-    muffin_shape shape;
-    muffin_params params;
-    hipStream_t stream;
-    char* ws;
-    size_t ws_bytes;
-    Layout lay;
-    int cur;          // which state set holds the current state
-    int iters;
-    int twlog;
-    double ynorm2;
-    // scratch owned by the library (reverse sweep of muffin_grad)
-    void* grad_buf;
-    size_t grad_bytes;
-    // graph replay of one pass: captured on a private stream, one executable
-    // graph per state set, replayed on `stream`
-    int use_graph;
-    hipStream_t cap;
-    hipGraphExec_t gexec[2];
-};
-
 namespace {
-
-#define HIP_TRY(expr)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess) {                                                       \
-            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                 \
-            return MUFFIN_EDEVICE;                                                    \
-        }                                                                             \
-    } while (0)
-
-size_t elem_size(const muffin_shape& s) { return s.dtype == MUFFIN_F64 ? 8 : 4; }
-size_t voxels(const muffin_shape& s) { return size_t(s.L) * s.ny * s.nx; }
-int ilog2i(int n) { int r = 0; while ((1 << r) < n) ++r; return r; }
-
-char* P(muffin_ctx* c, size_t off) { return c->ws + off; }
-void* st(muffin_ctx* c, int i) { return c->ws + c->lay.state[c->cur][i]; }
-void* st_alt(muffin_ctx* c, int i) { return c->ws + c->lay.state[1 - c->cur][i]; }
-
-SpecArgs spec_args(const muffin_params& p) {
-    SpecArgs a;
-    a.rho_P = p.rho_P;
-    a.rho_T = p.rho_T;
-    a.rho_V = p.rho_V;
-    a.rho_S = p.rho_S;
-    a.tau_T = p.mu_s / p.rho_T;
-    a.tau_V = p.mu_nu / p.rho_V;
-    return a;
-}
-
-// rho of eq. Qlsimp for the Dirac basis (n_s = 1)
-double rho_Q(const muffin_params& p) { return p.mu_eps + p.rho_S + p.rho_P + double(p.n_s) * p.rho_T; }
-
-int check_ctx(const muffin_ctx* c) {
-    if (!c) { set_error("context is NULL"); return MUFFIN_EINVAL; }
-    return MUFFIN_OK;
-}
 
 // step I of one pass: X = Q^{-1} (H^T Y + B_rest), band by band
 int step_one(muffin_ctx* c) {
     const muffin_shape& s = c->shape;
     const int dt = s.dtype;
     const int nrows = s.L * s.ny;
-    const double scale = 1.0 / (double(s.nx / 2) * double(s.ny));
     HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows, s.nx,
-                           s.ny, false, false, P(c, c->lay.tw), c->twlog, c->stream));
+                           s.ny, false, false, P(c, c->lay.tw), c->twlog, c->stream, c->row_v));
     HIP_TRY(launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
-                       P(c, c->lay.h2nyq), rho_Q(c->params), scale, s.L, s.ny, s.nx,
-                       P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream));
+                       P(c, c->lay.h2nyq), rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx,
+                       P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream, c->col_v));
     HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), P(c, c->lay.x), nrows, s.nx, P(c, c->lay.tw),
-                           c->twlog, c->stream));
+                           c->twlog, c->stream, c->row_v));
     return MUFFIN_OK;
 }
 
@@ -108,7 +51,10 @@ int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
     g.vpart = (double*)P(c, c->lay.vpart);
     g.partials = (double*)P(c, c->lay.partials);
     HIP_TRY(launch_spectral(s.dtype, g, spec_args(c->params), nblocks, c->stream));
-    if (report) c->cur = 1 - c->cur;
+    if (report) {
+        c->cur = 1 - c->cur;
+        c->version++;
+    }
     return MUFFIN_OK;
 }
 
@@ -177,6 +123,7 @@ int zero_state(muffin_ctx* c) {
     HIP_TRY(launch_fill_zero(P(c, c->lay.state[0][0]), c->lay.z - c->lay.state[0][0], c->stream));
     c->cur = 0;
     c->iters = 0;
+    c->version++;
     return MUFFIN_OK;
 }
 
@@ -287,6 +234,144 @@ size_t state_array_bytes(const muffin_ctx* c) {
     return (voxels(c->shape) * elem_size(c->shape) + kAlign - 1) & ~(kAlign - 1);
 }
 
+
+// ---------------------------------------------------------------- reverse sweep
+// Gradient of a loss of X^K (K passes from the zero state) by the adjoint of
+// the reduced pass, with the state checkpointed every C passes: a forward
+// sweep stores the checkpoints, then each segment (last first) is run again
+// from its checkpoint, storing the state before every pass and its X, and
+// its passes are reversed.  Scratch (device, owned by the context):
+//   ckpt : ceil(K / C) x 4 state arrays
+//   seg  : C x 5 arrays (state before the pass, X of the pass)
+//   fin  : 5 arrays (the state after K passes, restored at the end)
+//   adj  : 4 state cotangents, X-bar, B-bar
+//   partials, acc (FP64)
+int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, double* loss,
+               double grad[3]) {
+    const muffin_shape& s = c->shape;
+    if (C > K) C = K;
+    const int nseg = (K + C - 1) / C;
+    const size_t ab = state_array_bytes(c), nb = voxels(s) * elem_size(s);
+    const long npix = long(s.ny) * s.nx;
+    const size_t nparts = size_t(npix / 64 > 8192 ? npix / 64 : 8192);
+    const size_t n_arrays = size_t(nseg) * kNumState + size_t(C) * (kNumState + 1) + (kNumState + 1) +
+                            (kNumState + 2);
+    const size_t need = n_arrays * ab + nparts * GRAD_NQ * 8 + kAlign;
+    if (c->grad_bytes < need) {
+        if (c->grad_buf) HIP_TRY(hipFree(c->grad_buf));
+        c->grad_buf = nullptr;
+        c->grad_bytes = 0;
+        HIP_TRY(hipMalloc(&c->grad_buf, need));
+        c->grad_bytes = need;
+    }
+    char* g = (char*)c->grad_buf;
+    auto ckpt = [&](int seg, int i) { return g + (size_t(seg) * kNumState + i) * ab; };
+    char* seg0 = g + size_t(nseg) * kNumState * ab;
+    auto segs = [&](int j, int i) { return seg0 + (size_t(j) * (kNumState + 1) + i) * ab; };   // i = 4: X
+    char* fin = seg0 + size_t(C) * (kNumState + 1) * ab;
+    char* adj = fin + (kNumState + 1) * ab;                  // aP, aT, aS, aG, Xb, Bb
+    double* partials = (double*)(adj + (kNumState + 2) * ab);
+    double* acc = partials + nparts * GRAD_NQ;
+    const int dt = s.dtype, nrows = s.L * s.ny;
+    const SpecArgs a = spec_args(c->params);
+    hipStream_t st_ = c->stream;
+
+    auto copy = [&](void* dst, const void* src) {
+        return hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToDevice, st_);
+    };
+    // forward sweep with checkpoints
+    int rc = zero_state(c);
+    if (rc) return rc;
+    for (int k = 1; k <= K; ++k) {
+        if ((k - 1) % C == 0)
+            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(ckpt((k - 1) / C, i), st(c, i)));
+        if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
+    }
+    for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(fin + i * ab, st(c, i)));
+    HIP_TRY(copy(fin + kNumState * ab, P(c, c->lay.x)));
+    // seed: the cotangent of X^K
+    char* Xb = adj + kNumState * ab;
+    char* Bb = adj + (kNumState + 1) * ab;
+    HIP_TRY(launch_fill_zero(acc, GRAD_NQ * 8, st_));
+    if (mode == MUFFIN_MODE_MSE) {
+        int nbk = 0;
+        HIP_TRY(launch_mse_seed(dt, P(c, c->lay.x), sky_or_gx, Xb, voxels(s), partials, &nbk, st_));
+        HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
+    } else {
+        HIP_TRY(copy(Xb, sky_or_gx));
+    }
+    for (int i = 0; i < kNumState; ++i) HIP_TRY(launch_fill_zero(adj + i * ab, nb, st_));
+
+    const unsigned bb = unsigned(npix * long(elem_size(s)));
+    const int gsh = spectral_gshift(bb);
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int k0 = seg * C, k1 = (k0 + C < K) ? k0 + C : K;
+        for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), ckpt(seg, i)));
+        if ((rc = recompute_brest(c)) != MUFFIN_OK) return rc;
+        for (int k = k0 + 1; k <= k1; ++k) {
+            const int j = k - k0 - 1;
+            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(j, i), st(c, i)));
+            if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
+            HIP_TRY(copy(segs(j, kNumState), P(c, c->lay.x)));
+        }
+        for (int k = k1; k > k0; --k) {
+            const int j = k - k0 - 1;
+            AdjArrays A;
+            A.zP = segs(j, ST_ZP);
+            A.zT = segs(j, ST_ZT);
+            A.S = segs(j, ST_S);
+            A.GS = segs(j, ST_GS);
+            A.X = segs(j, kNumState);
+            A.aP = adj;
+            A.aT = adj + ab;
+            A.aS = adj + 2 * ab;
+            A.aG = adj + 3 * ab;
+            A.Xb = Xb;
+            A.band_bytes = bb;
+            A.gshift = gsh;
+            int nbk = 0;
+            HIP_TRY(launch_adj_spectral(dt, A, P(c, c->lay.dctm), s.L, npix, a, k == K ? 1 : 0, partials,
+                                        &nbk, st_));
+            HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
+            // B-bar = Q^{-1} X-bar (Q is symmetric)
+            HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, Xb, P(c, c->lay.z), nrows, s.nx, s.ny, false, false,
+                                   P(c, c->lay.tw), c->twlog, st_, c->row_v));
+            HIP_TRY(launch_col(dt, COL_FILTER, P(c, c->lay.z), nullptr, P(c, c->lay.h2), P(c, c->lay.h2nyq),
+                               rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog,
+                               nullptr, nullptr, st_));
+            HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), Bb, nrows, s.nx, P(c, c->lay.tw), c->twlog, st_,
+                                   c->row_v));
+            HIP_TRY(launch_adj_step1(dt, Bb, A.zP, A.zT, A.S, A.X, A.aP, A.aT, A.aS, A.aG, voxels(s), a,
+                                     partials, &nbk, st_));
+            HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
+        }
+    }
+    // leave the context at the state after K passes
+    for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), fin + i * ab));
+    HIP_TRY(copy(P(c, c->lay.x), fin + kNumState * ab));
+    if ((rc = recompute_brest(c)) != MUFFIN_OK) return rc;
+    c->iters = K;
+    double h[GRAD_NQ];
+    HIP_TRY(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, st_));
+    HIP_TRY(hipStreamSynchronize(st_));
+    for (int q = 0; q < GRAD_NQ; ++q) {
+        if (!std::isfinite(h[q])) {
+            set_error("non-finite gradient accumulator (slot %d)", q);
+            return MUFFIN_ENONFINITE;
+        }
+    }
+    const muffin_params& p = c->params;
+    const double rT = h[G_RHO_T] - h[G_TAU_T] * p.mu_s / (p.rho_T * p.rho_T) + h[G_RHO_Q];
+    const double rV = h[G_RHO_V] - h[G_TAU_V] * p.mu_nu / (p.rho_V * p.rho_V);
+    const double rP = h[G_RHO_P] + h[G_RHO_Q];
+    const double rS = h[G_RHO_S] + h[G_RHO_Q];
+    grad[0] = h[G_TAU_T] / p.rho_T;
+    grad[1] = h[G_TAU_V] / p.rho_V;
+    grad[2] = rP + rT + rV + rS;
+    if (loss) *loss = mode == MUFFIN_MODE_MSE ? h[G_LOSS] : 0.0;
+    return MUFFIN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -322,6 +407,9 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     c->iters = 0;
     const int NT = shape->nx > shape->ny ? shape->nx : shape->ny;
     c->twlog = ilog2i(NT);
+    c->row_v = kDefaultRowVariant;
+    c->col_v = kDefaultColVariant;
+    c->version = 0;
     c->grad_buf = nullptr;
     c->grad_bytes = 0;
     c->use_graph = 0;
@@ -437,11 +525,15 @@ int muffin_get_state(muffin_ctx* c, void* dst) {
     const size_t ab = state_array_bytes(c), nb = voxels(c->shape) * elem_size(c->shape);
     char* d = (char*)dst;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    int64_t hdr[4] = {0x4d554646494e5354LL, c->iters, c->shape.dtype, (int64_t)voxels(c->shape)};
+    // every byte of the blob is defined: header block zero-padded, gaps zeroed
+    int64_t hdr[kAlign / 8] = {0x4d554646494e5354LL, c->iters, c->shape.dtype, (int64_t)voxels(c->shape)};
     HIP_TRY(hipMemcpy(d, hdr, sizeof(hdr), hipMemcpyHostToDevice));
-    for (int i = 0; i < kNumState; ++i)
-        HIP_TRY(hipMemcpyAsync(d + kAlign + i * ab, st(c, i), nb, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(d + kAlign + kNumState * ab, P(c, c->lay.x), nb, hipMemcpyDeviceToDevice, c->stream));
+    for (int i = 0; i <= kNumState; ++i) {
+        char* a = d + kAlign + i * ab;
+        HIP_TRY(hipMemcpyAsync(a, i < kNumState ? st(c, i) : P(c, c->lay.x), nb,
+                               hipMemcpyDeviceToDevice, c->stream));
+        if (ab > nb) HIP_TRY(launch_fill_zero(a + nb, ab - nb, c->stream));
+    }
     return MUFFIN_OK;
 }
 
@@ -480,6 +572,7 @@ int muffin_set_params(muffin_ctx* c, const muffin_params* params) {
                                 old.mu_s / old.rho_T, c->stream));
     }
     c->params = *params;
+    c->version++;
     return recompute_brest(c);
 }
 
@@ -500,21 +593,22 @@ int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, in
     double acc[K] = {0, 0, 0, 0};
     const muffin_shape& s = c->shape;
     const int dt = s.dtype, nrows = s.L * s.ny;
-    const double scale = 1.0 / (double(s.nx / 2) * double(s.ny));
+    const double scale = fft_scale(s);
     int rc = MUFFIN_OK;
     for (int it = 0; it < n_iter && rc == MUFFIN_OK; ++it) {
         hipError_t e = hipEventRecord(ev[0], c->stream);
         if (e == hipSuccess)
             e = launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows, s.nx, s.ny,
-                               false, false, P(c, c->lay.tw), c->twlog, c->stream);
+                               false, false, P(c, c->lay.tw), c->twlog, c->stream, c->row_v);
         if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
         if (e == hipSuccess)
             e = launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2), P(c, c->lay.h2nyq),
                            rho_Q(c->params), scale, s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog, nullptr,
-                           nullptr, c->stream);
+                           nullptr, c->stream, c->col_v);
         if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
         if (e == hipSuccess)
-            e = launch_row_inv(dt, P(c, c->lay.z), P(c, c->lay.x), nrows, s.nx, P(c, c->lay.tw), c->twlog, c->stream);
+            e = launch_row_inv(dt, P(c, c->lay.z), P(c, c->lay.x), nrows, s.nx, P(c, c->lay.tw), c->twlog,
+                               c->stream, c->row_v);
         if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
         if (e == hipSuccess) {
             rc = step_spectral(c, false, nullptr);
@@ -543,9 +637,87 @@ int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, in
 int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode,
                 double* loss, double grad[3]) {
     if (int rc = check_ctx(c)) return rc;
-    (void)K; (void)ckpt_every; (void)sky_or_gx; (void)mode; (void)loss; (void)grad;
-    set_error("muffin_grad: the reverse sweep is not built yet");
-    return MUFFIN_EUNSUPPORTED;
+    if (K < 1 || ckpt_every < 1) {
+        set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
+        return MUFFIN_EINVAL;
+    }
+    if (!sky_or_gx || !grad || (mode != MUFFIN_MODE_MSE && mode != MUFFIN_MODE_VJP)) {
+        set_error("muffin_grad: sky_or_gx and grad must be non-NULL, mode MSE or VJP");
+        return MUFFIN_EINVAL;
+    }
+    return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, grad);
+}
+
+int muffin_autotune(muffin_ctx* c, int reps, int schedule[2]) {
+    if (int rc = check_ctx(c)) return rc;
+    if (reps < 1) { set_error("reps = %d < 1", reps); return MUFFIN_EINVAL; }
+    const muffin_shape& s = c->shape;
+    const int dt = s.dtype, nrows = s.L * s.ny;
+    // B_rest -> Z -> Z -> (a scratch array): the timing leaves X and the state alone
+    void* scratch = st_alt(c, 0);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double t[3][kNumVariants];
+    hipError_t e = hipSuccess;
+    for (int kind = 0; kind < 3 && e == hipSuccess; ++kind) {
+        for (int v = 0; v < kNumVariants && e == hipSuccess; ++v) {
+            auto launch = [&]() {
+                if (kind == 0)
+                    return launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows,
+                                          s.nx, s.ny, false, false, P(c, c->lay.tw), c->twlog, c->stream, v);
+                if (kind == 1)
+                    return launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
+                                      P(c, c->lay.h2nyq), rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx,
+                                      P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream, v);
+                return launch_row_inv(dt, P(c, c->lay.z), scratch, nrows, s.nx, P(c, c->lay.tw), c->twlog,
+                                      c->stream, v);
+            };
+            e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            t[kind][v] = ms;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) { set_error("autotune: %s", hipGetErrorString(e)); return MUFFIN_EDEVICE; }
+    int rv = kDefaultRowVariant, cv = kDefaultColVariant;
+    for (int v = 0; v < kNumVariants; ++v) {
+        if (t[0][v] + t[2][v] < t[0][rv] + t[2][rv]) rv = v;
+        if (t[1][v] < t[1][cv]) cv = v;
+    }
+    const int sch[2] = {rv, cv};
+    if (schedule) { schedule[0] = rv; schedule[1] = cv; }
+    return muffin_set_schedule(c, sch);
+}
+
+int muffin_set_schedule(muffin_ctx* c, const int schedule[2]) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!schedule || schedule[0] < 0 || schedule[0] >= kNumVariants || schedule[1] < 0 ||
+        schedule[1] >= kNumVariants) {
+        set_error("schedule must hold two variant indices in [0, %d)", kNumVariants);
+        return MUFFIN_EINVAL;
+    }
+    if (c->row_v != schedule[0] || c->col_v != schedule[1]) {
+        c->row_v = schedule[0];
+        c->col_v = schedule[1];
+        drop_graphs(c);
+        c->version++;
+    }
+    return MUFFIN_OK;
+}
+
+int muffin_get_schedule(const muffin_ctx* c, int schedule[2]) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!schedule) { set_error("schedule is NULL"); return MUFFIN_EINVAL; }
+    schedule[0] = c->row_v;
+    schedule[1] = c->col_v;
+    return MUFFIN_OK;
 }
 
 int muffin_set_graph(muffin_ctx* c, int enable) {

@@ -1,0 +1,411 @@
+// Batches of independent cubes: one grouped launch per transform pass and
+// shape class covers the tiles of every cube in the class (kernels in
+// muffin_fft.hip / muffin_spectral.hip, the same per-tile code as the
+// single-cube launches).  The launch descriptors live at the end of the
+// batch workspace and are rebuilt whenever a cube's arrays, parameters or
+// schedule change.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "muffin.h"
+#include "muffin_ctx.hpp"
+#include "muffin_kernels.hpp"
+#include "muffin_layout.hpp"
+
+using namespace muffin;
+
+namespace {
+
+enum Kind { K_ROWF = 0, K_COL = 1, K_ROWI = 2, K_SPEC = 3, K_NUM = 4 };
+
+constexpr size_t kDescSlot = 256;     // device bytes reserved per (pass, cube) descriptor
+static_assert(sizeof(RowDesc) <= kDescSlot && sizeof(ColDesc) <= kDescSlot &&
+                  sizeof(SpecDesc) <= kDescSlot, "descriptor slot too small");
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+size_t desc_region_bytes(int n) { return align_up(size_t(K_NUM) * n * kDescSlot); }
+
+struct Class {
+    int kind;
+    int key;                 // nx (row passes), ny (column pass), L (spectral pass)
+    int nth;                 // spectral block size
+    int variant;             // tile schedule (transform passes)
+    std::vector<int> cubes;
+    int nblocks;             // grid of the grouped launch
+    size_t slot0;            // first descriptor slot of the class
+};
+
+}  // namespace
+
+struct muffin_batch {
+    int n;
+    int dtype;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    std::vector<muffin_ctx*> cubes;
+    std::vector<Class> classes;
+    std::vector<unsigned> seen;            // cube versions the descriptors describe
+    std::vector<unsigned char> host_desc;  // staging copy of the descriptor region
+    char* desc;                            // device descriptor region
+    bool built;
+    int use_graph;
+    hipStream_t cap;
+    hipGraphExec_t gexec;
+};
+
+namespace {
+
+void drop_graph(muffin_batch* b) {
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+}
+
+int class_of(muffin_batch* b, int kind, int key, int nth) {
+    for (size_t i = 0; i < b->classes.size(); ++i) {
+        const Class& c = b->classes[i];
+        if (c.kind == kind && c.key == key && c.nth == nth) return int(i);
+    }
+    Class c{};
+    c.kind = kind;
+    c.key = key;
+    c.nth = nth;
+    c.variant = kind == K_COL ? kDefaultColVariant : kDefaultRowVariant;
+    b->classes.push_back(c);
+    return int(b->classes.size() - 1);
+}
+
+int cube_blocks(const muffin_batch* b, const Class& k, muffin_ctx* c, int variant) {
+    const muffin_shape& s = c->shape;
+    switch (k.kind) {
+        case K_ROWF:
+        case K_ROWI: return row_blocks(s.L * s.ny, s.nx, variant);
+        case K_COL: return col_blocks(b->dtype, s.L, s.ny, s.nx, variant);
+        default: return int((long(s.ny) * s.nx) / k.nth);
+    }
+}
+
+// a class's descriptors are a packed array of its kind's struct, starting
+// at byte slot0 * kDescSlot of the region
+size_t desc_size(int kind) {
+    return kind == K_COL ? sizeof(ColDesc) : (kind == K_SPEC ? sizeof(SpecDesc) : sizeof(RowDesc));
+}
+
+// descriptor of cube c in class k; `row_out` replaces X as the inverse row
+// pass's output (autotuning writes a scratch array instead)
+void fill_desc(const muffin_batch* b, const Class& k, muffin_ctx* c, int first, int nblk,
+               unsigned char* slot, void* row_out) {
+    const muffin_shape& s = c->shape;
+    if (k.kind == K_ROWF || k.kind == K_ROWI) {
+        RowDesc d{};
+        d.in = k.kind == K_ROWF ? (const void*)P(c, c->lay.brest) : (const void*)P(c, c->lay.z);
+        d.out = k.kind == K_ROWF ? (void*)P(c, c->lay.z) : (row_out ? row_out : (void*)P(c, c->lay.x));
+        d.tw = P(c, c->lay.tw);
+        d.nrows = s.L * s.ny;
+        d.twlog = c->twlog;
+        d.first = first;
+        d.nblk = nblk;
+        std::memcpy(slot, &d, sizeof(d));
+    } else if (k.kind == K_COL) {
+        ColDesc d{};
+        d.data = P(c, c->lay.z);
+        d.Yf = P(c, c->lay.yf);
+        d.H2 = P(c, c->lay.h2);
+        d.H2nyq = P(c, c->lay.h2nyq);
+        d.tw = P(c, c->lay.tw);
+        d.rhoQ = rho_Q(c->params);
+        d.scale = fft_scale(s);
+        d.L = s.L;
+        d.M = s.nx / 2;
+        d.twlog = c->twlog;
+        d.first = first;
+        d.nblk = nblk;
+        std::memcpy(slot, &d, sizeof(d));
+    } else {
+        SpecDesc d{};
+        const long npix = long(s.ny) * s.nx;
+        const unsigned bb = unsigned(npix * long(elem_size(s)));
+        SpecArrays& A = d.A;
+        A.X = P(c, c->lay.x);
+        A.zP = A.zPo = (char*)st(c, ST_ZP);
+        A.zT = A.zTo = (char*)st(c, ST_ZT);
+        A.S = A.So = (char*)st(c, ST_S);
+        A.GS = A.GSo = (char*)st(c, ST_GS);
+        A.Brest = P(c, c->lay.brest);
+        A.band_bytes = bb;
+        A.gshift = spectral_gshift(bb);
+        d.D = P(c, c->lay.dctm);
+        d.a = spec_args(c->params);
+        d.npix = npix;
+        d.Lrt = s.L;
+        d.first = first;
+        d.nblk = nblk;
+        std::memcpy(slot, &d, sizeof(d));
+    }
+}
+
+// lay out every class's blocks and write its descriptors into host_desc
+void layout_class(muffin_batch* b, Class& k, int variant, void* const* row_out) {
+    int next = 0;
+    for (size_t j = 0; j < k.cubes.size(); ++j) {
+        muffin_ctx* c = b->cubes[k.cubes[j]];
+        if (k.kind == K_COL) next = (next + 31) & ~31;     // the column pass's tile order needs it
+        const int nb = cube_blocks(b, k, c, variant);
+        fill_desc(b, k, c, next, nb, &b->host_desc[k.slot0 * kDescSlot + j * desc_size(k.kind)],
+                  row_out ? row_out[j] : nullptr);
+        next += nb;
+    }
+    k.nblocks = next;
+}
+
+int upload(muffin_batch* b) {
+    HIP_TRY(hipStreamSynchronize(b->stream));   // no launch reads the region meanwhile
+    HIP_TRY(hipMemcpy(b->desc, b->host_desc.data(), b->host_desc.size(), hipMemcpyHostToDevice));
+    return MUFFIN_OK;
+}
+
+int rebuild(muffin_batch* b) {
+    for (Class& k : b->classes) layout_class(b, k, k.variant, nullptr);
+    if (int rc = upload(b)) return rc;
+    for (int i = 0; i < b->n; ++i) b->seen[i] = b->cubes[i]->version;
+    b->built = true;
+    drop_graph(b);
+    return MUFFIN_OK;
+}
+
+bool stale(const muffin_batch* b) {
+    if (!b->built) return true;
+    for (int i = 0; i < b->n; ++i)
+        if (b->seen[i] != b->cubes[i]->version) return true;
+    return false;
+}
+
+hipError_t launch_class(const muffin_batch* b, const Class& k, int variant, hipStream_t s) {
+    const size_t off = k.slot0 * kDescSlot;
+    const int n = int(k.cubes.size());
+    switch (k.kind) {
+        case K_ROWF: return launch_row_fwd_group(b->dtype, k.key, variant, (const RowDesc*)(b->desc + off), n, k.nblocks, s);
+        case K_ROWI: return launch_row_inv_group(b->dtype, k.key, variant, (const RowDesc*)(b->desc + off), n, k.nblocks, s);
+        case K_COL: return launch_col_group(b->dtype, k.key, variant, (const ColDesc*)(b->desc + off), n, k.nblocks, s);
+        default: return launch_spectral_group(b->dtype, k.key, k.nth, (const SpecDesc*)(b->desc + off), n, k.nblocks, s);
+    }
+}
+
+int pass_kernels(muffin_batch* b, hipStream_t s) {
+    for (int kind = 0; kind < K_NUM; ++kind)
+        for (const Class& k : b->classes)
+            if (k.kind == kind) HIP_TRY(launch_class(b, k, k.variant, s));
+    return MUFFIN_OK;
+}
+
+int capture(muffin_batch* b) {
+    if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? pass_kernels(b, b->cap) : MUFFIN_EDEVICE;
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess || rc != MUFFIN_OK) {
+        if (g) hipGraphDestroy(g);
+        if (rc == MUFFIN_OK)
+            set_error("batch graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        return rc == MUFFIN_OK ? MUFFIN_EDEVICE : rc;
+    }
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        set_error("batch graph instantiation failed: %s", hipGetErrorString(e));
+        return MUFFIN_EDEVICE;
+    }
+    return MUFFIN_OK;
+}
+
+int check_batch(const muffin_batch* b) {
+    if (!b) { set_error("batch is NULL"); return MUFFIN_EINVAL; }
+    return MUFFIN_OK;
+}
+
+int check_shapes(int n, const muffin_shape* shapes, const muffin_params* params) {
+    if (n < 1 || n > MUFFIN_MAX_BATCH) {
+        set_error("batch of %d cubes outside [1, %d]", n, MUFFIN_MAX_BATCH);
+        return MUFFIN_EINVAL;
+    }
+    if (!shapes || !params) { set_error("shapes and params must be non-NULL"); return MUFFIN_EINVAL; }
+    for (int i = 0; i < n; ++i) {
+        if (int rc = muffin_validate(&shapes[i], &params[i])) return rc;
+        if (shapes[i].dtype != shapes[0].dtype) {
+            set_error("cube %d has dtype %d, cube 0 has %d: a batch has one dtype", i, shapes[i].dtype,
+                      shapes[0].dtype);
+            return MUFFIN_EINVAL;
+        }
+    }
+    return MUFFIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t muffin_batch_workspace_bytes(int n, const muffin_shape* shapes, const muffin_params* params) {
+    if (check_shapes(n, shapes, params) != MUFFIN_OK) return 0;
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) total += align_up(muffin_workspace_bytes(&shapes[i], &params[i]));
+    return total + desc_region_bytes(n);
+}
+
+int muffin_batch_setup(muffin_batch** out, int n, const muffin_shape* shapes, const muffin_params* params,
+                       const void* const* psf, const void* const* dirty, void* workspace, size_t ws_bytes,
+                       void* stream) {
+    if (!out) { set_error("batch output pointer is NULL"); return MUFFIN_EINVAL; }
+    *out = nullptr;
+    if (int rc = check_shapes(n, shapes, params)) return rc;
+    if (!psf || !dirty || !workspace) {
+        set_error("psf, dirty and workspace must be non-NULL");
+        return MUFFIN_EINVAL;
+    }
+    const size_t need = muffin_batch_workspace_bytes(n, shapes, params);
+    if (ws_bytes < need) {
+        set_error("batch workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, need);
+        return MUFFIN_EWORKSPACE;
+    }
+    if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0) {
+        set_error("workspace must be %zu-byte aligned", kAlign);
+        return MUFFIN_EWORKSPACE;
+    }
+    muffin_batch* b = new (std::nothrow) muffin_batch();
+    if (!b) { set_error("out of host memory"); return MUFFIN_EDEVICE; }
+    b->n = n;
+    b->dtype = shapes[0].dtype;
+    b->stream = (hipStream_t)stream;
+    b->ws = (char*)workspace;
+    b->ws_bytes = ws_bytes;
+    b->built = false;
+    b->use_graph = 0;
+    b->cap = nullptr;
+    b->gexec = nullptr;
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t wi = muffin_workspace_bytes(&shapes[i], &params[i]);
+        muffin_ctx* c = nullptr;
+        const int rc = muffin_setup(&c, &shapes[i], &params[i], psf[i], dirty[i], b->ws + off, wi, stream);
+        if (rc != MUFFIN_OK) {
+            muffin_batch_destroy(b);
+            return rc;
+        }
+        b->cubes.push_back(c);
+        off += align_up(wi);
+    }
+    b->desc = b->ws + off;
+    for (int i = 0; i < n; ++i) {
+        const muffin_shape& s = shapes[i];
+        b->classes[class_of(b, K_ROWF, s.nx, 0)].cubes.push_back(i);
+        b->classes[class_of(b, K_COL, s.ny, 0)].cubes.push_back(i);
+        b->classes[class_of(b, K_ROWI, s.nx, 0)].cubes.push_back(i);
+        b->classes[class_of(b, K_SPEC, s.L, spectral_block_threads(long(s.ny) * s.nx))].cubes.push_back(i);
+    }
+    size_t slot = 0;
+    for (Class& k : b->classes) {
+        k.slot0 = slot;
+        slot += k.cubes.size();
+    }
+    b->host_desc.assign(desc_region_bytes(n), 0);
+    b->seen.assign(n, 0);
+    if (int rc = rebuild(b)) {
+        muffin_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return MUFFIN_OK;
+}
+
+int muffin_batch_iterate(muffin_batch* b, int n_iter) {
+    if (int rc = check_batch(b)) return rc;
+    if (n_iter < 0) { set_error("n_iter = %d < 0", n_iter); return MUFFIN_EINVAL; }
+    if (n_iter == 0) return MUFFIN_OK;
+    if (stale(b))
+        if (int rc = rebuild(b)) return rc;
+    for (int it = 0; it < n_iter; ++it) {
+        if (b->use_graph) {
+            if (!b->gexec)
+                if (int rc = capture(b)) return rc;
+            HIP_TRY(hipGraphLaunch(b->gexec, b->stream));
+        } else if (int rc = pass_kernels(b, b->stream)) {
+            return rc;
+        }
+        for (muffin_ctx* c : b->cubes) c->iters++;
+    }
+    return MUFFIN_OK;
+}
+
+muffin_ctx* muffin_batch_cube(muffin_batch* b, int i) {
+    if (!b || i < 0 || i >= b->n) return nullptr;
+    return b->cubes[i];
+}
+
+int muffin_batch_autotune(muffin_batch* b, int reps) {
+    if (int rc = check_batch(b)) return rc;
+    if (reps < 1) { set_error("reps = %d < 1", reps); return MUFFIN_EINVAL; }
+    if (stale(b))
+        if (int rc = rebuild(b)) return rc;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int rc = MUFFIN_OK;
+    for (Class& k : b->classes) {
+        if (k.kind == K_SPEC) continue;
+        // the inverse row pass writes each cube's unused second state set
+        std::vector<void*> scratch;
+        for (int i : k.cubes) scratch.push_back(st_alt(b->cubes[i], 0));
+        double best = 0.0;
+        int bestv = k.variant;
+        for (int v = 0; v < kNumVariants && rc == MUFFIN_OK; ++v) {
+            layout_class(b, k, v, k.kind == K_ROWI ? scratch.data() : nullptr);
+            if ((rc = upload(b)) != MUFFIN_OK) break;
+            hipError_t e = launch_class(b, k, v, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_class(b, k, v, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                set_error("batch autotune: %s", hipGetErrorString(e));
+                rc = MUFFIN_EDEVICE;
+                break;
+            }
+            if (v == 0 || ms < best) {
+                best = ms;
+                bestv = v;
+            }
+        }
+        k.variant = bestv;
+        if (rc) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    const int rc2 = rebuild(b);
+    return rc ? rc : rc2;
+}
+
+int muffin_batch_set_graph(muffin_batch* b, int enable) {
+    if (int rc = check_batch(b)) return rc;
+    b->use_graph = enable ? 1 : 0;
+    return MUFFIN_OK;
+}
+
+int muffin_batch_launches(const muffin_batch* b) { return b ? int(b->classes.size()) : -1; }
+
+int muffin_batch_destroy(muffin_batch* b) {
+    if (!b) return MUFFIN_OK;
+    drop_graph(b);
+    if (b->cap) hipStreamDestroy(b->cap);
+    for (muffin_ctx* c : b->cubes) muffin_destroy(c);
+    delete b;
+    return MUFFIN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// The context of one cube and the small host helpers shared by the C ABI
+// translation units (muffin_api.cpp, muffin_batch.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "muffin.h"
+#include "muffin_kernels.hpp"
+#include "muffin_layout.hpp"
+
+struct muffin_ctx {
+    muffin_shape shape;
+    muffin_params params;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    muffin::Layout lay;
+    int cur;          // which state set holds the current state
+    int iters;
+    int twlog;
+    double ynorm2;
+    // tile schedules of the row and column passes (muffin_autotune)
+    int row_v, col_v;
+    // bumped whenever the arrays, parameters or schedules of the next pass
+    // change (a batch rebuilds its launch descriptors then)
+    unsigned version;
+    // scratch owned by the library (reverse sweep of muffin_grad)
+    void* grad_buf;
+    size_t grad_bytes;
+    // graph replay of one pass: captured on a private stream, one executable
+    // graph per state set, replayed on `stream`
+    int use_graph;
+    hipStream_t cap;
+    hipGraphExec_t gexec[2];
+};
+
+namespace muffin {
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            muffin::set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
+            return MUFFIN_EDEVICE;                                                    \
+        }                                                                             \
+    } while (0)
+
+inline size_t elem_size(const muffin_shape& s) { return s.dtype == MUFFIN_F64 ? 8 : 4; }
+inline size_t voxels(const muffin_shape& s) { return size_t(s.L) * s.ny * s.nx; }
+inline int ilog2i(int n) { int r = 0; while ((1 << r) < n) ++r; return r; }
+
+inline char* P(muffin_ctx* c, size_t off) { return c->ws + off; }
+inline void* st(muffin_ctx* c, int i) { return c->ws + c->lay.state[c->cur][i]; }
+inline void* st_alt(muffin_ctx* c, int i) { return c->ws + c->lay.state[1 - c->cur][i]; }
+
+inline SpecArgs spec_args(const muffin_params& p) {
+    SpecArgs a;
+    a.rho_P = p.rho_P;
+    a.rho_T = p.rho_T;
+    a.rho_V = p.rho_V;
+    a.rho_S = p.rho_S;
+    a.tau_T = p.mu_s / p.rho_T;
+    a.tau_V = p.mu_nu / p.rho_V;
+    return a;
+}
+
+// rho of eq. Qlsimp for the Dirac basis (n_s = 1)
+inline double rho_Q(const muffin_params& p) {
+    return p.mu_eps + p.rho_S + p.rho_P + double(p.n_s) * p.rho_T;
+}
+
+// scale of the unnormalised packed 2-D transform pair, folded into the filter
+inline double fft_scale(const muffin_shape& s) { return 1.0 / (double(s.nx / 2) * double(s.ny)); }
+
+inline int check_ctx(const muffin_ctx* c) {
+    if (!c) { set_error("context is NULL"); return MUFFIN_EINVAL; }
+    return MUFFIN_OK;
+}
+
+}  // namespace muffin

@@ -453,4 +453,54 @@ template <typename T, int L> __host__ __device__ __forceinline__ void dct3_ortho
     }
 }
 
+// ---------------------------------------------------------------- band-axis helpers
+// deterministic block sum (valid in thread 0): wavefront tree, then the
+// per-wave sums in wave order; blockDim.x is a multiple of 64, at most NTH
+template <int NTH> __device__ __forceinline__ double block_sum_s(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+template <typename T> __device__ __forceinline__ T softt(T z, T t) {
+    const T m = fabs(z) - t;
+    return m > T(0) ? copysign(m, z) : T(0);
+}
+template <typename T> __device__ __forceinline__ T clipt(T z, T t) {
+    return z > t ? t : (z < -t ? -t : z);
+}
+
+// dense orthonormal DCT-II (INV = false) or DCT-III (INV = true) for band
+// counts that are not powers of two.  D is zero-padded to LT x LT:
+// D[k * LT + l] = a_k cos(pi (2l+1) k / 2L) for k, l < L, else 0, so the
+// padded entries of v stay zero.
+template <typename T, int LT, bool INV>
+__device__ __forceinline__ void dct_dense(T (&v)[LT], const T* __restrict__ D) {
+    T o[LT];
+#pragma unroll
+    for (int k = 0; k < LT; ++k) o[k] = T(0);
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+#pragma unroll
+        for (int k = 0; k < LT; ++k) o[k] += (INV ? D[l * LT + k] : D[k * LT + l]) * v[l];
+    }
+#pragma unroll
+    for (int k = 0; k < LT; ++k) v[k] = o[k];
+}
+
+template <typename T, int LT, bool DENSE, bool INV>
+__device__ __forceinline__ void dct_any(T (&v)[LT], const T* __restrict__ D, int L) {
+    if constexpr (DENSE) dct_dense<T, LT, INV>(v, D);
+    else if constexpr (INV) dct3_ortho<T, LT>(v);
+    else dct2_ortho<T, LT>(v);
+}
+
 }  // namespace muffin

@@ -16,15 +16,30 @@ namespace muffin {
 
 constexpr int ROW_NTH = 256;
 
-// rows per block: about 2048 complex points per block
-template <int M> constexpr int row_rpw() { return M >= 2048 ? 1 : 2048 / M; }
+// rows per block: about 1024, 2048 or 4096 complex points per block (variant 0, 1, 2)
+template <int M, int V> constexpr int row_rpw() {
+    const int b = M >= 2048 ? 1 : 2048 / M;
+    const int r = (b << V) >> 1;
+    return r < 1 ? 1 : r;
+}
 
-template <typename T, int NY> constexpr int col_tc() {
+template <typename T, int NY> constexpr int col_tc_base() {
     int tc = int(65536 / (NY * int(sizeof(cx<T>))));
     return tc > 16 ? 16 : (tc < 1 ? 1 : tc);
 }
-template <typename T, int NY> constexpr int col_nth() {
-    int n = col_tc<T, NY>() * NY / 8;
+template <typename T, int NY> constexpr bool col_twl() { return NY * int(sizeof(cx<T>)) <= 16384; }
+template <typename T, int NY, int TC> constexpr int col_lds_bytes() {
+    return NY * (TC + 1) * int(sizeof(cx<T>)) + (col_twl<T, NY>() ? NY * int(sizeof(cx<T>)) : 0) + 64;
+}
+// columns per tile of variant V: half, all or twice the 64-KiB tile
+template <typename T, int NY, int V> constexpr int col_tc() {
+    constexpr int b = col_tc_base<T, NY>();
+    if (V == 0) return b > 1 ? b / 2 : 1;
+    if (V == 1) return b;
+    return (2 * b <= 16 && col_lds_bytes<T, NY, 2 * b>() <= 160 * 1024) ? 2 * b : b;
+}
+template <typename T, int NY, int TC> constexpr int col_nth() {
+    int n = TC * NY / 8;
     return n > 512 ? 512 : (n < 64 ? 64 : n);
 }
 
@@ -42,17 +57,23 @@ template <int NTH> __device__ __forceinline__ double block_sum(double v, double*
     return r;
 }
 
+// cube of a grouped launch that block b works on, or -1 for a padding block
+template <typename D>
+__device__ __forceinline__ int group_find(const D* __restrict__ d, int n, unsigned b) {
+    int j = 0;
+    while (j + 1 < n && b >= (unsigned)d[j + 1].first) ++j;
+    return (b >= (unsigned)d[j].first && b < (unsigned)(d[j].first + d[j].nblk)) ? j : -1;
+}
+
 // ------------------------------------------------------------------ row passes
-template <typename Tin, typename T, int NX, bool SHIFT, bool POS>
-__global__ void __launch_bounds__(ROW_NTH)
-k_row_fwd(const Tin* __restrict__ in, cx<T>* __restrict__ out, int nrows, int ny,
-          const cx<T>* __restrict__ tw, int twlog) {
+template <typename Tin, typename T, int NX, bool SHIFT, bool POS, int RPW>
+__device__ __forceinline__ void row_fwd_body(const Tin* __restrict__ in, cx<T>* __restrict__ out,
+                                             int nrows, int ny, const cx<T>* __restrict__ tw,
+                                             int twlog, long blk, cx<T>* lds) {
     constexpr int M = NX / 2;
-    constexpr int RPW = row_rpw<M>();
     constexpr int TS = lds_len<true>(M);
-    __shared__ cx<T> lds[RPW * TS];
     const int t = threadIdx.x;
-    const long row0 = (long)blockIdx.x * RPW;
+    const long row0 = blk * RPW;
     for (int i = t; i < RPW * M; i += ROW_NTH) {
         const int r = i / M, m = i % M;
         const long grow = row0 + r;
@@ -101,16 +122,35 @@ k_row_fwd(const Tin* __restrict__ in, cx<T>* __restrict__ out, int nrows, int ny
     }
 }
 
-template <typename T, int NX>
+template <typename Tin, typename T, int NX, bool SHIFT, bool POS, int V>
 __global__ void __launch_bounds__(ROW_NTH)
-k_row_inv(const cx<T>* __restrict__ in, T* __restrict__ out, int nrows,
+k_row_fwd(const Tin* __restrict__ in, cx<T>* __restrict__ out, int nrows, int ny,
           const cx<T>* __restrict__ tw, int twlog) {
+    constexpr int RPW = row_rpw<NX / 2, V>();
+    __shared__ cx<T> lds[RPW * lds_len<true>(NX / 2)];
+    row_fwd_body<Tin, T, NX, SHIFT, POS, RPW>(in, out, nrows, ny, tw, twlog, blockIdx.x, lds);
+}
+
+template <typename T, int NX, int V>
+__global__ void __launch_bounds__(ROW_NTH)
+k_row_fwd_group(const RowDesc* __restrict__ d, int n) {
+    constexpr int RPW = row_rpw<NX / 2, V>();
+    __shared__ cx<T> lds[RPW * lds_len<true>(NX / 2)];
+    const int j = group_find(d, n, blockIdx.x);
+    if (j < 0) return;
+    row_fwd_body<T, T, NX, false, false, RPW>((const T*)d[j].in, (cx<T>*)d[j].out, d[j].nrows, 0,
+                                             (const cx<T>*)d[j].tw, d[j].twlog,
+                                             (long)(blockIdx.x - d[j].first), lds);
+}
+
+template <typename T, int NX, int RPW>
+__device__ __forceinline__ void row_inv_body(const cx<T>* __restrict__ in, T* __restrict__ out,
+                                             int nrows, const cx<T>* __restrict__ tw, int twlog,
+                                             long blk, cx<T>* lds) {
     constexpr int M = NX / 2;
-    constexpr int RPW = row_rpw<M>();
     constexpr int TS = lds_len<true>(M);
-    __shared__ cx<T> lds[RPW * TS];
     const int t = threadIdx.x;
-    const long row0 = (long)blockIdx.x * RPW;
+    const long row0 = blk * RPW;
     constexpr int NK = M / 2 + 1;
     for (int i = t; i < RPW * NK; i += ROW_NTH) {
         const int r = i / NK, k = i % NK;
@@ -141,29 +181,49 @@ k_row_inv(const cx<T>* __restrict__ in, T* __restrict__ out, int nrows,
     }
 }
 
+template <typename T, int NX, int V>
+__global__ void __launch_bounds__(ROW_NTH)
+k_row_inv(const cx<T>* __restrict__ in, T* __restrict__ out, int nrows,
+          const cx<T>* __restrict__ tw, int twlog) {
+    constexpr int RPW = row_rpw<NX / 2, V>();
+    __shared__ cx<T> lds[RPW * lds_len<true>(NX / 2)];
+    row_inv_body<T, NX, RPW>(in, out, nrows, tw, twlog, blockIdx.x, lds);
+}
+
+template <typename T, int NX, int V>
+__global__ void __launch_bounds__(ROW_NTH)
+k_row_inv_group(const RowDesc* __restrict__ d, int n) {
+    constexpr int RPW = row_rpw<NX / 2, V>();
+    __shared__ cx<T> lds[RPW * lds_len<true>(NX / 2)];
+    const int j = group_find(d, n, blockIdx.x);
+    if (j < 0) return;
+    row_inv_body<T, NX, RPW>((const cx<T>*)d[j].in, (T*)d[j].out, d[j].nrows, (const cx<T>*)d[j].tw,
+                             d[j].twlog, (long)(blockIdx.x - d[j].first), lds);
+}
+
 // ------------------------------------------------------------------ column pass
-template <typename T, int NY, int MODE>
-__global__ void __launch_bounds__((col_nth<T, NY>()))
-k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
-      const T* __restrict__ H2nyq, T rhoQ, T scale, int M, const cx<T>* __restrict__ tw,
-      int twlog, double* __restrict__ partials, double inv_n) {
-    constexpr int TC = col_tc<T, NY>();
-    constexpr int NTH = col_nth<T, NY>();
+// One tile of TC adjacent kx columns of one band.  wg: the tile's index in
+// the launch (or in its cube's block range), nwg: tiles of the cube, ntiles:
+// tiles per band.
+template <typename T, int NY, int MODE, int TC>
+__device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ Yf,
+                                         const T* __restrict__ H2, const T* __restrict__ H2nyq,
+                                         T rhoQ, T scale, int M, const cx<T>* __restrict__ tw,
+                                         int twlog, double* __restrict__ partials, double inv_n,
+                                         unsigned wg, unsigned nwg, unsigned ntiles, cx<T>* lds,
+                                         cx<T>* twl, double* red) {
+    constexpr int NTH = col_nth<T, NY, TC>();
     constexpr int TCP = TC + 1;          // padded row stride: spreads stride-R writes over the banks
     // the NY-point twiddle table lives in LDS when it is small: every stage
     // reads its twiddles there instead of from the global table
-    constexpr bool TWL = NY * int(sizeof(cx<T>)) <= 16384;
-    __shared__ cx<T> lds[NY * TCP];
-    __shared__ cx<T> twl[TWL ? NY : 1];
-    __shared__ double red[NTH / 64];
+    constexpr bool TWL = col_twl<T, NY>();
+    const unsigned wg_in = wg;
     const int t = threadIdx.x;
     // XCD-aware tile order.  Work-groups go to the 8 XCDs round-robin in
     // dispatch order, each XCD with its own L2.  Adjacent column tiles share
     // the 128-B lines of Z, Yf and |h|^2 (a tile row is TC * 8 B of Z, TC * 4 B
     // of |h|^2), so logical tiles 4j .. 4j+3 run as work-groups i, i+8, i+16,
     // i+24: on one XCD, in consecutive dispatch rounds.
-    const unsigned ntiles = gridDim.x, nwg = gridDim.x * gridDim.y;
-    unsigned wg = blockIdx.x + blockIdx.y * gridDim.x;
     if ((nwg & 31u) == 0) {
         const unsigned r = wg >> 3, x = wg & 7u;
         wg = (r >> 2) * 32u + x * 4u + (r & 3u);
@@ -184,12 +244,14 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
     if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, twl, ilog2c(NY), t);
     else tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, tw, twlog, t);
 
-    if constexpr (MODE == COL_SOLVE) {
+    if constexpr (MODE == COL_SOLVE || MODE == COL_FILTER) {
+        // COL_FILTER: Q^{-1} alone (no data term), the adjoint's solve
         for (int i = t; i < NY * TC; i += NTH) {
             const int y = i / TC, c = i % TC, kx = c0 + c;
             if (kx == 0 || kx >= M) continue;
             const long g = base + (long)y * M + kx;
-            const cx<T> v = lds[y * TCP + c] + Yf[g];
+            cx<T> v = lds[y * TCP + c];
+            if constexpr (MODE == COL_SOLVE) v = v + Yf[g];
             lds[y * TCP + c] = v * (scale / (H2[g] + rhoQ));
         }
         if (c0 == 0) {
@@ -197,8 +259,11 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
             for (int ky = t; ky <= NY / 2; ky += NTH) {
                 const int kn = (NY - ky) & (NY - 1);
                 const long g1 = base + (long)ky * M, g2 = base + (long)kn * M;
-                const cx<T> c1 = lds[ky * TCP] + Yf[g1];
-                const cx<T> c2 = lds[kn * TCP] + Yf[g2];
+                cx<T> c1 = lds[ky * TCP], c2 = lds[kn * TCP];
+                if constexpr (MODE == COL_SOLVE) {
+                    c1 = c1 + Yf[g1];
+                    c2 = c2 + Yf[g2];
+                }
                 const T g0 = scale / (H2[g1] + rhoQ);
                 const T gm = scale / (H2nyq[(long)band * NY + ky] + rhoQ);
                 cx<T> A = {T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)};
@@ -214,7 +279,7 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
         else tile_fft<T, NY, TC, NTH, 1, TCP, true, false, true>(lds, tw, twlog, t);
     }
 
-    if constexpr (MODE == COL_SOLVE || MODE == COL_FWD) {
+    if constexpr (MODE == COL_SOLVE || MODE == COL_FWD || MODE == COL_FILTER) {
         for (int i = t; i < NY * TC; i += NTH) {
             const int y = i / TC, c = i % TC;
             if (c0 + c < M) data[base + (long)y * M + c0 + c] = lds[y * TCP + c];
@@ -253,8 +318,42 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
             }
         }
         const double s = block_sum<NTH>(acc * inv_n, red);
-        if (t == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = s;
+        if (t == 0) partials[wg_in] = s;
     }
+}
+
+template <typename T, int NY, int MODE, int V>
+__global__ void __launch_bounds__((col_nth<T, NY, col_tc<T, NY, V>()>()))
+k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
+      const T* __restrict__ H2nyq, T rhoQ, T scale, int M, const cx<T>* __restrict__ tw,
+      int twlog, double* __restrict__ partials, double inv_n) {
+    constexpr int TC = col_tc<T, NY, V>();
+    __shared__ cx<T> lds[NY * (TC + 1)];
+    __shared__ cx<T> twl[col_twl<T, NY>() ? NY : 1];
+    __shared__ double red[col_nth<T, NY, TC>() / 64];
+    col_body<T, NY, MODE, TC>(data, Yf, H2, H2nyq, rhoQ, scale, M, tw, twlog, partials, inv_n,
+                              blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y, gridDim.x,
+                              lds, twl, red);
+}
+
+// the solving column pass over the tiles of several cubes of one ny; each
+// cube's block range starts at a multiple of 32 (the tile order above)
+template <typename T, int NY, int V>
+__global__ void __launch_bounds__((col_nth<T, NY, col_tc<T, NY, V>()>()))
+k_col_group(const ColDesc* __restrict__ d, int n) {
+    constexpr int TC = col_tc<T, NY, V>();
+    __shared__ cx<T> lds[NY * (TC + 1)];
+    __shared__ cx<T> twl[col_twl<T, NY>() ? NY : 1];
+    __shared__ double red[col_nth<T, NY, TC>() / 64];
+    const int j = group_find(d, n, blockIdx.x);
+    if (j < 0) return;
+    const int M = d[j].M;
+    const unsigned ntiles = (unsigned)((M + TC - 1) / TC);
+    col_body<T, NY, COL_SOLVE, TC>((cx<T>*)d[j].data, (const cx<T>*)d[j].Yf, (const T*)d[j].H2,
+                                   (const T*)d[j].H2nyq, T(d[j].rhoQ), T(d[j].scale), M,
+                                   (const cx<T>*)d[j].tw, d[j].twlog, nullptr, 0.0,
+                                   blockIdx.x - (unsigned)d[j].first, (unsigned)d[j].nblk, ntiles,
+                                   lds, twl, red);
 }
 
 // ------------------------------------------------------------------ setup combine
@@ -297,18 +396,40 @@ k_setup_combine(const cx<double>* __restrict__ Ch, const cx<double>* __restrict_
 
 // ------------------------------------------------------------------ launchers
 #define MUFFIN_POW2_CASES(F) F(8) F(16) F(32) F(64) F(128) F(256) F(512) F(1024) F(2048) F(4096)
+// runtime variant -> template argument V
+#define MUFFIN_VARIANT(v, CALL)            \
+    switch (v) {                           \
+        case 0: { constexpr int V = 0; CALL; } \
+        case 1: { constexpr int V = 1; CALL; } \
+        case 2: { constexpr int V = 2; CALL; } \
+        default: return hipErrorInvalidValue;  \
+    }
 
-template <typename Tin, typename T, bool SHIFT, bool POS>
+template <int V> static int row_rpw_rt(int nx) {
+    switch (nx) {
+#define F(N) case N: return row_rpw<N / 2, V>();
+        MUFFIN_POW2_CASES(F)
+#undef F
+    }
+    return 1;
+}
+
+int row_blocks(int nrows, int nx, int variant) {
+    const int rpw = variant == 0 ? row_rpw_rt<0>(nx) : (variant == 2 ? row_rpw_rt<2>(nx) : row_rpw_rt<1>(nx));
+    return (nrows + rpw - 1) / rpw;
+}
+
+template <typename Tin, typename T, bool SHIFT, bool POS, int V>
 static hipError_t row_fwd_t(const void* in, void* out, int nrows, int nx, int ny, const void* tw,
                             int twlog, hipStream_t s) {
     switch (nx) {
-#define F(N)                                                                              \
-    case N: {                                                                             \
-        constexpr int RPW = row_rpw<N / 2>();                                             \
-        dim3 grid((nrows + RPW - 1) / RPW);                                               \
-        hipLaunchKernelGGL((k_row_fwd<Tin, T, N, SHIFT, POS>), grid, dim3(ROW_NTH), 0, s, \
+#define F(N)                                                                                 \
+    case N: {                                                                                \
+        constexpr int RPW = row_rpw<N / 2, V>();                                             \
+        dim3 grid((nrows + RPW - 1) / RPW);                                                  \
+        hipLaunchKernelGGL((k_row_fwd<Tin, T, N, SHIFT, POS, V>), grid, dim3(ROW_NTH), 0, s, \
                            (const Tin*)in, (cx<T>*)out, nrows, ny, (const cx<T>*)tw, twlog); \
-        return hipGetLastError();                                                         \
+        return hipGetLastError();                                                            \
     }
         MUFFIN_POW2_CASES(F)
 #undef F
@@ -318,34 +439,36 @@ static hipError_t row_fwd_t(const void* in, void* out, int nrows, int nx, int ny
 
 hipError_t launch_row_fwd(int dtype, bool in_f64, const void* in, void* out, int nrows, int nx,
                           int ny, bool shift, bool positive, const void* tw, int twlog,
-                          hipStream_t s) {
+                          hipStream_t s, int variant) {
     if (nrows <= 0) return hipSuccess;
+    const bool plain = !shift && !positive;
     if (dtype == 0) {       // float output
-        if (in_f64) return hipErrorInvalidValue;
-        if (positive) return row_fwd_t<float, float, false, true>(in, out, nrows, nx, ny, tw, twlog, s);
-        if (shift) return hipErrorInvalidValue;
-        return row_fwd_t<float, float, false, false>(in, out, nrows, nx, ny, tw, twlog, s);
+        if (in_f64 || shift) return hipErrorInvalidValue;
+        if (positive) return row_fwd_t<float, float, false, true, 1>(in, out, nrows, nx, ny, tw, twlog, s);
+        MUFFIN_VARIANT(variant, return (row_fwd_t<float, float, false, false, V>(in, out, nrows, nx, ny, tw, twlog, s)))
     }
     // double output
     if (in_f64) {
-        if (positive) return row_fwd_t<double, double, false, true>(in, out, nrows, nx, ny, tw, twlog, s);
-        if (shift) return row_fwd_t<double, double, true, false>(in, out, nrows, nx, ny, tw, twlog, s);
-        return row_fwd_t<double, double, false, false>(in, out, nrows, nx, ny, tw, twlog, s);
+        if (positive) return row_fwd_t<double, double, false, true, 1>(in, out, nrows, nx, ny, tw, twlog, s);
+        if (shift) return row_fwd_t<double, double, true, false, 1>(in, out, nrows, nx, ny, tw, twlog, s);
+        if (plain) {
+            MUFFIN_VARIANT(variant, return (row_fwd_t<double, double, false, false, V>(in, out, nrows, nx, ny, tw, twlog, s)))
+        }
     }
     if (positive) return hipErrorInvalidValue;
-    if (shift) return row_fwd_t<float, double, true, false>(in, out, nrows, nx, ny, tw, twlog, s);
-    return row_fwd_t<float, double, false, false>(in, out, nrows, nx, ny, tw, twlog, s);
+    if (shift) return row_fwd_t<float, double, true, false, 1>(in, out, nrows, nx, ny, tw, twlog, s);
+    return row_fwd_t<float, double, false, false, 1>(in, out, nrows, nx, ny, tw, twlog, s);
 }
 
-template <typename T>
+template <typename T, int V>
 static hipError_t row_inv_t(const void* in, void* out, int nrows, int nx, const void* tw, int twlog,
                             hipStream_t s) {
     switch (nx) {
 #define F(N)                                                                            \
     case N: {                                                                           \
-        constexpr int RPW = row_rpw<N / 2>();                                           \
+        constexpr int RPW = row_rpw<N / 2, V>();                                        \
         dim3 grid((nrows + RPW - 1) / RPW);                                             \
-        hipLaunchKernelGGL((k_row_inv<T, N>), grid, dim3(ROW_NTH), 0, s,                \
+        hipLaunchKernelGGL((k_row_inv<T, N, V>), grid, dim3(ROW_NTH), 0, s,             \
                            (const cx<T>*)in, (T*)out, nrows, (const cx<T>*)tw, twlog);  \
         return hipGetLastError();                                                       \
     }
@@ -356,13 +479,32 @@ static hipError_t row_inv_t(const void* in, void* out, int nrows, int nx, const 
 }
 
 hipError_t launch_row_inv(int dtype, const void* in, void* out, int nrows, int nx, const void* tw,
-                          int twlog, hipStream_t s) {
+                          int twlog, hipStream_t s, int variant) {
     if (nrows <= 0) return hipSuccess;
-    return dtype == 0 ? row_inv_t<float>(in, out, nrows, nx, tw, twlog, s)
-                      : row_inv_t<double>(in, out, nrows, nx, tw, twlog, s);
+    if (dtype == 0) {
+        MUFFIN_VARIANT(variant, return (row_inv_t<float, V>(in, out, nrows, nx, tw, twlog, s)))
+    }
+    MUFFIN_VARIANT(variant, return (row_inv_t<double, V>(in, out, nrows, nx, tw, twlog, s)))
 }
 
-template <typename T, int MODE>
+template <typename T, int V> static int col_tc_rt(int ny) {
+    switch (ny) {
+#define F(N) case N: return col_tc<T, N, V>();
+        MUFFIN_POW2_CASES(F)
+#undef F
+    }
+    return 1;
+}
+
+int col_blocks(int dtype, int L, int ny, int nx, int variant) {
+    int tc = 1;
+    if (dtype == 0) tc = variant == 0 ? col_tc_rt<float, 0>(ny) : (variant == 2 ? col_tc_rt<float, 2>(ny) : col_tc_rt<float, 1>(ny));
+    else tc = variant == 0 ? col_tc_rt<double, 0>(ny) : (variant == 2 ? col_tc_rt<double, 2>(ny) : col_tc_rt<double, 1>(ny));
+    const int M = nx / 2;
+    return ((M + tc - 1) / tc) * L;
+}
+
+template <typename T, int MODE, int V>
 static hipError_t col_t(void* data, const void* Yf, const void* H2, const void* H2nyq, double rhoQ,
                         double scale, int L, int ny, int nx, const void* tw, int twlog,
                         double* partials, int* nblocks_out, hipStream_t s) {
@@ -370,10 +512,10 @@ static hipError_t col_t(void* data, const void* Yf, const void* H2, const void* 
     switch (ny) {
 #define F(N)                                                                                  \
     case N: {                                                                                 \
-        constexpr int TC = col_tc<T, N>();                                                    \
+        constexpr int TC = col_tc<T, N, V>();                                                 \
         dim3 grid((M + TC - 1) / TC, L);                                                      \
         if (nblocks_out) *nblocks_out = int(grid.x * grid.y);                                 \
-        hipLaunchKernelGGL((k_col<T, N, MODE>), grid, dim3(col_nth<T, N>()), 0, s,            \
+        hipLaunchKernelGGL((k_col<T, N, MODE, V>), grid, dim3(col_nth<T, N, TC>()), 0, s,     \
                            (cx<T>*)data, (const cx<T>*)Yf, (const T*)H2, (const T*)H2nyq,     \
                            T(rhoQ), T(scale), M, (const cx<T>*)tw, twlog, partials,           \
                            1.0 / (double(nx) * double(ny)));                                  \
@@ -388,19 +530,76 @@ static hipError_t col_t(void* data, const void* Yf, const void* H2, const void* 
 hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const void* H2,
                       const void* H2nyq, double rhoQ, double scale, int L, int ny, int nx,
                       const void* tw, int twlog, double* partials, int* nblocks_out,
-                      hipStream_t s) {
+                      hipStream_t s, int variant) {
+    constexpr int D = kDefaultColVariant;
     if (dtype == 0) {
-        if (mode == COL_SOLVE)
-            return col_t<float, COL_SOLVE>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+        if (mode == COL_SOLVE) {
+            MUFFIN_VARIANT(variant, return (col_t<float, COL_SOLVE, V>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s)))
+        }
         if (mode == COL_OBJ)
-            return col_t<float, COL_OBJ>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+            return col_t<float, COL_OBJ, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+        if (mode == COL_FILTER)
+            return col_t<float, COL_FILTER, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
         return hipErrorInvalidValue;
     }
-    if (mode == COL_SOLVE)
-        return col_t<double, COL_SOLVE>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+    if (mode == COL_FILTER)
+        return col_t<double, COL_FILTER, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+    if (mode == COL_SOLVE) {
+        MUFFIN_VARIANT(variant, return (col_t<double, COL_SOLVE, V>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s)))
+    }
     if (mode == COL_FWD)
-        return col_t<double, COL_FWD>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
-    return col_t<double, COL_OBJ>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+        return col_t<double, COL_FWD, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+    return col_t<double, COL_OBJ, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+}
+
+// ------------------------------------------------------------------ grouped launchers
+template <typename T, int V>
+static hipError_t row_group_t(bool inv, int nx, const RowDesc* d, int n, int nblocks, hipStream_t s) {
+    switch (nx) {
+#define F(N)                                                                                     \
+    case N:                                                                                      \
+        if (inv) hipLaunchKernelGGL((k_row_inv_group<T, N, V>), dim3(nblocks), dim3(ROW_NTH), 0, s, d, n); \
+        else hipLaunchKernelGGL((k_row_fwd_group<T, N, V>), dim3(nblocks), dim3(ROW_NTH), 0, s, d, n);     \
+        return hipGetLastError();
+        MUFFIN_POW2_CASES(F)
+#undef F
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_row_fwd_group(int dtype, int nx, int variant, const RowDesc* d, int n, int nblocks,
+                                hipStream_t s) {
+    if (n <= 0 || nblocks <= 0) return hipSuccess;
+    if (dtype == 0) { MUFFIN_VARIANT(variant, return (row_group_t<float, V>(false, nx, d, n, nblocks, s))) }
+    MUFFIN_VARIANT(variant, return (row_group_t<double, V>(false, nx, d, n, nblocks, s)))
+}
+
+hipError_t launch_row_inv_group(int dtype, int nx, int variant, const RowDesc* d, int n, int nblocks,
+                                hipStream_t s) {
+    if (n <= 0 || nblocks <= 0) return hipSuccess;
+    if (dtype == 0) { MUFFIN_VARIANT(variant, return (row_group_t<float, V>(true, nx, d, n, nblocks, s))) }
+    MUFFIN_VARIANT(variant, return (row_group_t<double, V>(true, nx, d, n, nblocks, s)))
+}
+
+template <typename T, int V>
+static hipError_t col_group_t(int ny, const ColDesc* d, int n, int nblocks, hipStream_t s) {
+    switch (ny) {
+#define F(N)                                                                                       \
+    case N:                                                                                        \
+        hipLaunchKernelGGL((k_col_group<T, N, V>), dim3(nblocks), dim3(col_nth<T, N, col_tc<T, N, V>()>()), \
+                           0, s, d, n);                                                            \
+        return hipGetLastError();
+        MUFFIN_POW2_CASES(F)
+#undef F
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_col_group(int dtype, int ny, int variant, const ColDesc* d, int n, int nblocks,
+                            hipStream_t s) {
+    if (n <= 0 || nblocks <= 0) return hipSuccess;
+    if (dtype == 0) { MUFFIN_VARIANT(variant, return (col_group_t<float, V>(ny, d, n, nblocks, s))) }
+    MUFFIN_VARIANT(variant, return (col_group_t<double, V>(ny, d, n, nblocks, s)))
 }
 
 hipError_t launch_setup_combine(int dtype, const void* Ch, const void* Cy, void* Yf, void* H2,

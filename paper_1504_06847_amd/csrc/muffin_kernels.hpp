@@ -7,7 +7,7 @@
 
 namespace muffin {
 
-enum ColMode { COL_SOLVE = 0, COL_FWD = 1, COL_OBJ = 2 };
+enum ColMode { COL_SOLVE = 0, COL_FWD = 1, COL_OBJ = 2, COL_FILTER = 3 };
 
 // Number of FP64 partial sums per block written by the spectral pass in
 // reduction mode, and their meaning.
@@ -29,26 +29,128 @@ struct SpecArgs {
     double rho_P, rho_T, rho_V, rho_S, tau_T, tau_V;
 };
 
+// Tile schedules of the FFT passes (all compute the same values in the same
+// order; only the work split differs).  Row passes: rows per work-group
+// (1024, 2048 or 4096 complex points per group for variants 0, 1, 2).
+// Column pass: columns per tile (half, all or twice the largest tile that
+// fits 64 KiB of LDS, at most 16; twice only where the LDS holds it).
+constexpr int kNumVariants = 3;
+constexpr int kDefaultRowVariant = 1;
+constexpr int kDefaultColVariant = 1;
+
 // Row pass, forward: every row of `in` (nrows rows of nx reals, type float or
 // double per in_f64) -> packed half spectrum `out` (nrows x nx/2 complex of
 // type T).  shift: read the row through ifftshift (rows of each band of ny
 // rows rotated by ny/2, columns by nx/2).  positive: read max(0, v).
 hipError_t launch_row_fwd(int dtype, bool in_f64, const void* in, void* out, int nrows, int nx,
                           int ny, bool shift, bool positive, const void* tw, int twlog,
-                          hipStream_t s);
+                          hipStream_t s, int variant = kDefaultRowVariant);
 
 // Row pass, inverse: packed half spectrum -> real rows (unnormalised).
 hipError_t launch_row_inv(int dtype, const void* in, void* out, int nrows, int nx,
-                          const void* tw, int twlog, hipStream_t s);
+                          const void* tw, int twlog, hipStream_t s, int variant = kDefaultRowVariant);
 
 // Column pass over L bands of ny x (nx/2) packed spectra, in place.
 // COL_SOLVE: FFT along y, X_hat = (Z + Yf) * scale / (H2 + rhoQ), inverse FFT.
 // COL_FWD: FFT along y only.  COL_OBJ: FFT along y, then per-block FP64
 // partials of sum w (H2 |Z|^2 - 2 Re(conj(Yf) Z)) / (nx ny) into partials.
+// COL_FILTER: as COL_SOLVE without the data term (Yf unused).
 hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const void* H2,
                       const void* H2nyq, double rhoQ, double scale, int L, int ny, int nx,
                       const void* tw, int twlog, double* partials, int* nblocks_out,
-                      hipStream_t s);
+                      hipStream_t s, int variant = kDefaultColVariant);
+
+// ---------------------------------------------------------------- grouped launches
+// One launch covers the tiles of several independent cubes of one shape
+// class.  Each cube's descriptor holds its arrays and the first and count of
+// the blocks that work on it; blocks of the launch in no cube's range exit.
+// The descriptor arrays live in device memory.
+struct RowDesc {             // a row pass (forward: in = B_rest, out = Z; inverse: in = Z, out = X)
+    const void* in;
+    void* out;
+    const void* tw;
+    int nrows, twlog, first, nblk;
+};
+struct ColDesc {             // the solving column pass of one cube
+    void* data;
+    const void* Yf;
+    const void* H2;
+    const void* H2nyq;
+    const void* tw;
+    double rhoQ, scale;
+    int L, M, twlog, first, nblk, pad;
+};
+// the [L][npix] arrays of the spectral pass: X, the state it reads (z_P,
+// z_T, S, Gamma_S), the state it writes (the same arrays, or a second set in
+// a reporting pass) and B_rest
+struct SpecArrays {
+    char *X, *zP, *zT, *S, *GS;
+    char *zPo, *zTo, *So, *GSo;
+    char *Brest;
+    unsigned band_bytes;
+    int gshift;
+};
+struct SpecDesc {
+    SpecArrays A;
+    const void* D;
+    SpecArgs a;
+    long npix;
+    int Lrt, first, nblk, pad;
+};
+
+// the host (g++) and device (hipcc) compilers must agree on these layouts
+static_assert(sizeof(SpecArgs) == 48 && sizeof(RowDesc) == 40 && sizeof(ColDesc) == 80 &&
+                  sizeof(SpecArrays) == 88 && sizeof(SpecDesc) == 168,
+              "descriptor layout");
+
+// blocks of one cube in a grouped launch (and its block size, spectral pass)
+int spectral_gshift(unsigned band_bytes);     // SpecArrays::gshift for this band size
+int row_blocks(int nrows, int nx, int variant);
+int col_blocks(int dtype, int L, int ny, int nx, int variant);
+int spectral_block_threads(long npix);
+hipError_t launch_row_fwd_group(int dtype, int nx, int variant, const RowDesc* d, int n, int nblocks,
+                                hipStream_t s);
+hipError_t launch_row_inv_group(int dtype, int nx, int variant, const RowDesc* d, int n, int nblocks,
+                                hipStream_t s);
+hipError_t launch_col_group(int dtype, int ny, int variant, const ColDesc* d, int n, int nblocks,
+                            hipStream_t s);
+// cubes of one band count L and one block size (npix >= 256 or all equal npix)
+hipError_t launch_spectral_group(int dtype, int L, int nth, const SpecDesc* d, int n, int nblocks,
+                                 hipStream_t s);
+
+// ---------------------------------------------------------------- reverse sweep
+// FP64 cotangent slots accumulated per block by the adjoint kernels
+enum GradSlot {
+    G_TAU_T = 0,   // d/d tau_T
+    G_TAU_V,       // d/d tau_V
+    G_RHO_P,       // d/d rho_P, explicit terms
+    G_RHO_T,
+    G_RHO_V,
+    G_RHO_S,
+    G_RHO_Q,       // d/d rho of eq. Qlsimp
+    G_LOSS,        // the MSE loss
+    GRAD_NQ
+};
+
+// [L][npix] arrays of the adjoint of one pass: the state before the pass,
+// the pass's X, the state cotangents (in place) and the cotangent of X
+struct AdjArrays {
+    char *zP, *zT, *S, *GS, *X;
+    char *aP, *aT, *aS, *aG, *Xb;
+    unsigned band_bytes;
+    int gshift;
+};
+
+hipError_t launch_adj_spectral(int dtype, const AdjArrays& A, const void* D, int L, long npix,
+                               const SpecArgs& a, int has_ext, double* partials, int* nblocks,
+                               hipStream_t s);
+hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* S,
+                            const void* X, void* aP, void* aT, void* aS, void* aG, size_t n,
+                            const SpecArgs& a, double* partials, int* nblocks, hipStream_t s);
+hipError_t launch_mse_seed(int dtype, const void* X, const void* sky, void* Xb, size_t n,
+                           double* partials, int* nblocks, hipStream_t s);
+// acc[q] += the block sums of partials (GRAD_NQ per block), deterministic
+hipError_t launch_grad_accum(const double* partials, int nblocks, double* acc, hipStream_t s);
 
 // Arrays of one spectral pass.  st: the state read (z_P, z_T, S, Gamma_S);
 // out: where the new state goes (= st except in a reporting pass).

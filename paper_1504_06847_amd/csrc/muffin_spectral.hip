@@ -31,77 +31,17 @@ namespace muffin {
 
 constexpr int SPEC_NTH = 256;
 
-// deterministic block sum (valid in thread 0): wavefront tree, then the
-// per-wave sums in wave order; blockDim.x is a multiple of 64, at most NTH
-template <int NTH> __device__ __forceinline__ double block_sum_s(double v, double* sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
-    }
-    __syncthreads();
-    return r;
-}
-
-template <typename T> __device__ __forceinline__ T softt(T z, T t) {
-    const T m = fabs(z) - t;
-    return m > T(0) ? copysign(m, z) : T(0);
-}
-template <typename T> __device__ __forceinline__ T clipt(T z, T t) {
-    return z > t ? t : (z < -t ? -t : z);
-}
-
-// dense orthonormal DCT-II (INV = false) or DCT-III (INV = true) for band
-// counts that are not powers of two.  D is zero-padded to LT x LT:
-// D[k * LT + l] = a_k cos(pi (2l+1) k / 2L) for k, l < L, else 0, so the
-// padded entries of v stay zero.
-template <typename T, int LT, bool INV>
-__device__ __forceinline__ void dct_dense(T (&v)[LT], const T* __restrict__ D) {
-    T o[LT];
-#pragma unroll
-    for (int k = 0; k < LT; ++k) o[k] = T(0);
-#pragma unroll
-    for (int l = 0; l < LT; ++l) {
-#pragma unroll
-        for (int k = 0; k < LT; ++k) o[k] += (INV ? D[l * LT + k] : D[k * LT + l]) * v[l];
-    }
-#pragma unroll
-    for (int k = 0; k < LT; ++k) v[k] = o[k];
-}
-
-template <typename T, int LT, bool DENSE, bool INV>
-__device__ __forceinline__ void dct_any(T (&v)[LT], const T* __restrict__ D, int L) {
-    if constexpr (DENSE) dct_dense<T, LT, INV>(v, D);
-    else if constexpr (INV) dct3_ortho<T, LT>(v);
-    else dct2_ortho<T, LT>(v);
-}
-
-// the [L][npix] arrays of the spectral pass: X, the state it reads (z_P,
-// z_T, S, Gamma_S), the state it writes (the same arrays, or a second set in
-// a reporting pass) and B_rest
-struct SpecArrays {
-    char *X, *zP, *zT, *S, *GS;
-    char *zPo, *zTo, *So, *GSo;
-    char *Brest;
-    unsigned band_bytes;
-    int gshift;
-};
-
 // One ADMM pass after step I.  REDUCE (a reporting pass): the new state goes
 // to the second array set, so k_report can compare old and new, and the
 // block sums of ||V||^2 (the only DCT-domain quantity of the convergence
 // checks) are written to partials[block].
 template <typename T, int LT, bool DENSE, bool REDUCE>
-__global__ void __launch_bounds__(SPEC_NTH)
-k_spectral(SpecArrays A, const T* __restrict__ D, int Lrt, long npix, SpecArgs a,
-           double* __restrict__ partials) {
+__device__ __forceinline__ void spectral_body(const SpecArrays& A, const T* __restrict__ D, int Lrt,
+                                              const SpecArgs& a, double* __restrict__ partials,
+                                              unsigned blk) {
     // the launch covers npix exactly (npix is a power of two >= 64 and the
     // block size min(256, npix) divides it), so every lane owns a pixel
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long p = (long)blk * blockDim.x + threadIdx.x;
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
     const int gs_ = A.gshift;
@@ -156,8 +96,27 @@ k_spectral(SpecArrays A, const T* __restrict__ D, int Lrt, long npix, SpecArgs a
     if constexpr (REDUCE) {
         __shared__ double sh[SPEC_NTH / 64];
         const double sv = block_sum_s<SPEC_NTH>(v2, sh);
-        if (threadIdx.x == 0) partials[blockIdx.x] = sv;
+        if (threadIdx.x == 0) partials[blk] = sv;
     }
+}
+
+template <typename T, int LT, bool DENSE, bool REDUCE>
+__global__ void __launch_bounds__(SPEC_NTH)
+k_spectral(SpecArrays A, const T* __restrict__ D, int Lrt, long npix, SpecArgs a,
+           double* __restrict__ partials) {
+    spectral_body<T, LT, DENSE, REDUCE>(A, D, Lrt, a, partials, blockIdx.x);
+}
+
+// the spectral pass over the pixels of several cubes with the same band
+// count and block size
+template <typename T, int LT, bool DENSE>
+__global__ void __launch_bounds__(SPEC_NTH)
+k_spectral_group(const SpecDesc* __restrict__ d, int n) {
+    int j = 0;
+    while (j + 1 < n && blockIdx.x >= (unsigned)d[j + 1].first) ++j;
+    const unsigned b = blockIdx.x - (unsigned)d[j].first;
+    if (blockIdx.x < (unsigned)d[j].first || b >= (unsigned)d[j].nblk) return;
+    spectral_body<T, LT, DENSE, false>(d[j].A, (const T*)d[j].D, d[j].Lrt, d[j].a, nullptr, b);
 }
 
 // FP64 sums of a reporting pass from the old state (z_P, z_T, S, Gamma_S),
@@ -298,6 +257,38 @@ static hipError_t spectral_dispatch(const SpecLaunch& g, const SpecArgs& a, hipS
     if (g.L <= 8) return spectral_t<T, 8, true>(g, a, s);
     if (g.L <= 16) return spectral_t<T, 16, true>(g, a, s);
     return spectral_t<T, 32, true>(g, a, s);
+}
+
+int spectral_block_threads(long npix) { return npix < SPEC_NTH ? (int)npix : SPEC_NTH; }
+int spectral_gshift(unsigned band_bytes) { return band_group_shift(band_bytes); }
+
+template <typename T>
+static hipError_t spectral_group_t(int L, const SpecDesc* d, int n, int nblocks, int nth, hipStream_t s) {
+    const dim3 g((unsigned)nblocks), b((unsigned)nth);
+    switch (L) {
+        case 1: hipLaunchKernelGGL((k_spectral_group<T, 1, false>), g, b, 0, s, d, n); return hipGetLastError();
+        case 2: hipLaunchKernelGGL((k_spectral_group<T, 2, false>), g, b, 0, s, d, n); return hipGetLastError();
+        case 4: hipLaunchKernelGGL((k_spectral_group<T, 4, false>), g, b, 0, s, d, n); return hipGetLastError();
+        case 8: hipLaunchKernelGGL((k_spectral_group<T, 8, false>), g, b, 0, s, d, n); return hipGetLastError();
+        case 16: hipLaunchKernelGGL((k_spectral_group<T, 16, false>), g, b, 0, s, d, n); return hipGetLastError();
+        case 32: hipLaunchKernelGGL((k_spectral_group<T, 32, false>), g, b, 0, s, d, n); return hipGetLastError();
+        case 64: hipLaunchKernelGGL((k_spectral_group<T, 64, false>), g, b, 0, s, d, n); return hipGetLastError();
+        case 128: hipLaunchKernelGGL((k_spectral_group<T, 128, false>), g, b, 0, s, d, n); return hipGetLastError();
+        default: break;
+    }
+    if (L < 1 || L > 32) return hipErrorInvalidValue;
+    if (L <= 8) hipLaunchKernelGGL((k_spectral_group<T, 8, true>), g, b, 0, s, d, n);
+    else if (L <= 16) hipLaunchKernelGGL((k_spectral_group<T, 16, true>), g, b, 0, s, d, n);
+    else hipLaunchKernelGGL((k_spectral_group<T, 32, true>), g, b, 0, s, d, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectral_group(int dtype, int L, int nth, const SpecDesc* d, int n, int nblocks,
+                                 hipStream_t s) {
+    if (n <= 0 || nblocks <= 0) return hipSuccess;
+    if (nth < 64 || nth > SPEC_NTH || (nth & 63)) return hipErrorInvalidValue;
+    return dtype == 0 ? spectral_group_t<float>(L, d, n, nblocks, nth, s)
+                      : spectral_group_t<double>(L, d, n, nblocks, nth, s);
 }
 
 hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, int* nblocks_out,

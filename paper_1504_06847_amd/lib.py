@@ -28,6 +28,7 @@ MUFFIN_DCT2_ORTHO = 0
 MUFFIN_MODE_MSE = 0
 MUFFIN_MODE_VJP = 1
 MUFFIN_MAX_BANDS = 128
+MUFFIN_MAX_BATCH = 256
 
 ERROR_NAMES = {
     MUFFIN_EINVAL: "MUFFIN_EINVAL", MUFFIN_EUNSUPPORTED: "MUFFIN_EUNSUPPORTED",
@@ -78,6 +79,18 @@ SIGNATURES = [
     ("muffin_reset", c_int, [c_void_p]),
     ("muffin_iterations", c_int, [c_void_p]),
     ("muffin_set_graph", c_int, [c_void_p, c_int]),
+    ("muffin_autotune", c_int, [c_void_p, c_int, POINTER(c_int)]),
+    ("muffin_set_schedule", c_int, [c_void_p, POINTER(c_int)]),
+    ("muffin_get_schedule", c_int, [c_void_p, POINTER(c_int)]),
+    ("muffin_batch_workspace_bytes", c_size_t, [c_int, POINTER(MuffinShape), POINTER(MuffinParams)]),
+    ("muffin_batch_setup", c_int, [POINTER(c_void_p), c_int, POINTER(MuffinShape), POINTER(MuffinParams),
+                                   POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_size_t, c_void_p]),
+    ("muffin_batch_iterate", c_int, [c_void_p, c_int]),
+    ("muffin_batch_cube", c_void_p, [c_void_p, c_int]),
+    ("muffin_batch_autotune", c_int, [c_void_p, c_int]),
+    ("muffin_batch_set_graph", c_int, [c_void_p, c_int]),
+    ("muffin_batch_launches", c_int, [c_void_p]),
+    ("muffin_batch_destroy", c_int, [c_void_p]),
     ("muffin_profile", c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_char_p), c_int]),
     ("muffin_destroy", c_int, [c_void_p]),
     ("muffin_last_error", c_char_p, []),

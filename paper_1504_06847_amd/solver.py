@@ -16,6 +16,24 @@ PARAM_NAMES = ("mu_eps", "mu_s", "mu_nu", "rho_P", "rho_T", "rho_V", "rho_S",
                "check_every", "eps_abs", "eps_rel")
 
 
+def _load_cache(path):
+    import json
+    import os
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _store_cache(path, table):
+    import json
+    import os
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def _as_cube(a, dtype, device):
     t = a if isinstance(a, torch.Tensor) else torch.as_tensor(a)
     t = t.to(device=device, dtype=dtype).contiguous()
@@ -66,12 +84,55 @@ class Solver:
                                     c_void_p(self._ws_ptr), ws_bytes,
                                     c_void_p(self.stream.cuda_stream))
         L.check(rc, "muffin_setup", self._lib)
+        self._owner = True
         if graph:
             self.set_graph(True)
+
+    @classmethod
+    def _view(cls, lib, ctx, shape, dtype, device, stream, params):
+        """A Solver over a context owned by a Batch (closing it frees nothing)."""
+        self = cls.__new__(cls)
+        self._lib, self._ctx, self._owner = lib, c_void_p(ctx), False
+        self.dtype, self.device, self.stream = dtype, device, stream
+        self.shape = shape
+        self._params = params
+        return self
 
     def set_graph(self, enable: bool = True):
         """Replay each pass from a HIP graph (bitwise identical results)."""
         L.check(self._lib.muffin_set_graph(self._ctx, 1 if enable else 0), "muffin_set_graph", self._lib)
+
+    # -------------------------------------------------------------- schedules
+    @property
+    def schedule_key(self) -> str:
+        Lb, ny, nx = self.shape
+        return f"{'f64' if self.dtype == torch.float64 else 'f32'}:{nx}x{ny}x{Lb}"
+
+    @property
+    def schedule(self) -> tuple:
+        sch = (ctypes.c_int * 2)()
+        L.check(self._lib.muffin_get_schedule(self._ctx, sch), "muffin_get_schedule", self._lib)
+        return (sch[0], sch[1])
+
+    def set_schedule(self, schedule):
+        sch = (ctypes.c_int * 2)(*schedule)
+        L.check(self._lib.muffin_set_schedule(self._ctx, sch), "muffin_set_schedule", self._lib)
+
+    def autotune(self, reps: int = 10, cache: str | None = None) -> tuple:
+        """Pick the fastest FFT tile schedule for this shape.  With ``cache`` (a
+        JSON file), a schedule stored there for the same shape and dtype is
+        reused, and a newly timed one is added."""
+        key = self.schedule_key
+        table = _load_cache(cache)
+        if key in table:
+            self.set_schedule(table[key])
+            return tuple(table[key])
+        sch = (ctypes.c_int * 2)()
+        L.check(self._lib.muffin_autotune(self._ctx, int(reps), sch), "muffin_autotune", self._lib)
+        if cache:
+            table[key] = [sch[0], sch[1]]
+            _store_cache(cache, table)
+        return (sch[0], sch[1])
 
     # -------------------------------------------------------------- params
     def _make_params(self, params):
@@ -161,6 +222,29 @@ class Solver:
     def reset(self):
         L.check(self._lib.muffin_reset(self._ctx), "muffin_reset", self._lib)
 
+    # -------------------------------------------------------------- gradients
+    def grad(self, K: int, *, sky=None, gx=None, ckpt_every: int = 5):
+        """Gradient with respect to (mu_s, mu_nu, rho) of a loss of X^K, the X
+        iterate after K passes from the zero state (rho: the common value of
+        the four rho's, derivative along (1, 1, 1, 1)).  Give ``sky`` for
+        loss = ||X^K - sky||^2, or ``gx`` = dloss/dX^K.  Returns (loss, grad)
+        with grad a length-3 numpy array (loss is 0.0 with gx).  Afterwards
+        the solver holds the state after K passes."""
+        import numpy as np
+        if (sky is None) == (gx is None):
+            raise ValueError("give exactly one of sky and gx")
+        ref = _as_cube(sky if sky is not None else gx, self.dtype, self.device)
+        if tuple(ref.shape) != tuple(self.shape):
+            raise ValueError(f"expected a cube of shape {self.shape}, got {tuple(ref.shape)}")
+        mode = L.MUFFIN_MODE_MSE if sky is not None else L.MUFFIN_MODE_VJP
+        loss = c_double()
+        g = (c_double * 3)()
+        with torch.cuda.stream(self.stream):
+            rc = self._lib.muffin_grad(self._ctx, int(K), int(ckpt_every), c_void_p(ref.data_ptr()), mode,
+                                       byref(loss), g)
+        L.check(rc, "muffin_grad", self._lib)
+        return loss.value, np.array([g[0], g[1], g[2]])
+
     # -------------------------------------------------------------- timing
     def profile(self, n_iter: int = 10) -> dict:
         cap = 16
@@ -172,7 +256,8 @@ class Solver:
     # -------------------------------------------------------------- lifetime
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
-            self._lib.muffin_destroy(self._ctx)
+            if getattr(self, "_owner", False):
+                self._lib.muffin_destroy(self._ctx)
             self._ctx = c_void_p()
 
     def __del__(self):

@@ -142,3 +142,42 @@ def test_validation_unit_under_host_sanitizers(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ALL OK" in r.stdout
+
+
+def test_batch_validation_without_device(lib):
+    from paper_1504_06847_amd import lib as L
+    n = 3
+    shapes = (L.MuffinShape * n)(L.MuffinShape(64, 64, 8, 0), L.MuffinShape(32, 128, 16, 0),
+                                 L.MuffinShape(16, 16, 15, 0))
+    prm = (L.MuffinParams * n)(*[L.make_params(lib) for _ in range(n)])
+    total = lib.muffin_batch_workspace_bytes(n, shapes, prm)
+    per = sum(-(-lib.muffin_workspace_bytes(ctypes.byref(shapes[i]), ctypes.byref(prm[i])) // 256) * 256
+              for i in range(n))
+    assert total > per                       # plus the launch descriptors
+    assert lib.muffin_batch_workspace_bytes(0, shapes, prm) == 0
+    assert lib.muffin_batch_workspace_bytes(L.MUFFIN_MAX_BATCH + 1, shapes, prm) == 0
+    mixed = (L.MuffinShape * 2)(L.MuffinShape(64, 64, 8, 0), L.MuffinShape(64, 64, 8, 1))
+    assert lib.muffin_batch_workspace_bytes(2, mixed, prm) == 0
+    assert "dtype" in L.last_error(lib)
+    bad = (L.MuffinShape * 2)(L.MuffinShape(64, 64, 8, 0), L.MuffinShape(60, 64, 8, 0))
+    assert lib.muffin_batch_workspace_bytes(2, bad, prm) == 0
+    b = ctypes.c_void_p()
+    dummy = (ctypes.c_void_p * n)(0x1000, 0x1000, 0x1000)
+    assert lib.muffin_batch_setup(ctypes.byref(b), 0, shapes, prm, dummy, dummy,
+                                  ctypes.c_void_p(0x1000), 1 << 40, None) == -1
+    assert lib.muffin_batch_setup(ctypes.byref(b), n, shapes, prm, dummy, dummy,
+                                  ctypes.c_void_p(0x1000), 16, None) == -3
+    assert lib.muffin_batch_setup(ctypes.byref(b), n, shapes, prm, None, dummy,
+                                  ctypes.c_void_p(0x1000), 1 << 40, None) == -1
+    assert b.value is None
+    assert lib.muffin_batch_iterate(None, 1) == -1
+    assert lib.muffin_batch_cube(None, 0) is None
+    assert lib.muffin_batch_launches(None) == -1
+    assert lib.muffin_batch_destroy(None) == 0
+
+
+def test_schedule_calls_reject_bad_arguments(lib):
+    sch = (ctypes.c_int * 2)(0, 0)
+    assert lib.muffin_autotune(None, 3, sch) == -1
+    assert lib.muffin_set_schedule(None, sch) == -1
+    assert lib.muffin_get_schedule(None, sch) == -1

@@ -1,0 +1,177 @@
+"""The batched form (grouped launches over cubes of uneven size and band
+count) and the FFT tile schedules.  A grouped launch runs the per-tile code
+of the single-cube launch of the same schedule: results are compared bit for
+bit.  Other schedules evaluate the same formulas in other instruction
+sequences (the compiler contracts a product and a sum into one FMA in some
+and not in others): results are compared at a few ulps of the cube's
+largest value, with the differences printed.  One batched cube is checked
+against the FP64 oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import make_instance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (L, ny, nx): uneven sizes and band counts, a dense-DCT band count (15), and
+# pixel counts below one 256-thread block (8 x 16)
+BATCH = [(8, 32, 32), (16, 64, 32), (4, 32, 64), (8, 64, 64), (15, 32, 32), (16, 16, 16),
+         (2, 8, 16), (8, 32, 32), (32, 16, 64)]
+PARAMS = dict(mu_eps=1e-3, mu_s=0.05, mu_nu=0.05, rho_P=1.0, rho_T=1.0, rho_V=1.0, rho_S=1.0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _relmax(a, b):
+    a, b = a.double(), b.double()
+    return float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+
+
+# FP32 / FP64 bars for results that take other instruction sequences to the
+# same values (other tile shapes, grouped launches): a few ulps of the cube's
+# largest value after several passes
+TOL = {torch.float32: 1e-6, torch.float64: 1e-14}
+
+
+def _cubes(shapes, seed0=300):
+    out = []
+    for i, (L, ny, nx) in enumerate(shapes):
+        inst = make_instance(ny, nx, L, n_points=3, n_gauss=1, n_ant=10, noise_sigma=0.005,
+                             seed=seed0 + i)
+        out.append((inst.psf, inst.dirty))
+    return out
+
+
+@pytest.fixture(autouse=True)
+def _workers():
+    O.set_workers(min(16, os.cpu_count() or 1))
+    yield
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("graph", [False, True], ids=["launch", "graph"])
+def test_batch_is_bitwise_the_single_cube_runs(gpu_lib, dtype, graph):
+    from paper_1504_06847_amd import Batch, Solver
+    cubes = _cubes(BATCH)
+    _say("batch", dtype, "graph" if graph else "launch", len(cubes), "cubes")
+    b = Batch(cubes, dtype=dtype, graph=graph, params=PARAMS)
+    singles = [Solver(p, d, dtype=dtype, **PARAMS) for p, d in cubes]
+    # 4 shape classes of row passes (nx 16, 32, 64), ... at most 4 x 9 launches
+    assert b.launches <= 4 * len(cubes)
+    for k in range(6):
+        b.iterate(1)
+        for s in singles:
+            s.iterate(1)
+        torch.cuda.synchronize()
+        for i, s in enumerate(singles):
+            assert torch.equal(b.cube(i).x, s.x), f"pass {k + 1}, cube {i} {BATCH[i]}"
+    # a reporting pass on one cube (switches its state set) and a parameter
+    # change on another, then more batched passes
+    ra, rb = b.cube(2).step_report(), singles[2].step_report()
+    assert ra == rb
+    b.cube(5).set_params(rho=1.7)
+    singles[5].set_params(rho=1.7)
+    b.iterate(20)
+    for s in singles:
+        s.iterate(20)
+    torch.cuda.synchronize()
+    for i, s in enumerate(singles):
+        assert torch.equal(b.cube(i).x, s.x), f"cube {i} {BATCH[i]} after report/set_params"
+        assert b.cube(i).iterations == s.iterations
+    b.close()
+
+
+def test_batched_cube_matches_the_oracle(gpu_lib):
+    from paper_1504_06847_amd import Batch
+    cubes = _cubes(BATCH[:4], seed0=310)
+    b = Batch(cubes, params=PARAMS)
+    b.iterate(30)
+    torch.cuda.synchronize()
+    p = O.Params(**PARAMS)
+    for i in (1, 3):
+        prob = O.Problem(cubes[i][0], cubes[i][1], p)
+        st = O.State.zeros(prob.shape)
+        for _ in range(30):
+            st = O.admm_iteration(prob, st)
+        x = b.cube(i).x.cpu().double().numpy()
+        err = np.linalg.norm(x - st.X) / np.linalg.norm(st.X)
+        _say("batched cube", i, "rel err", err)
+        assert err < 1e-5
+
+
+# shapes whose column tiles take all three widths (ny = 1024 reaches the
+# widest tile, 147 KiB of LDS) and whose row tiles take 1..4 rows (nx = 2048)
+SCHED_SHAPES = [(2, 1024, 32), (1, 64, 2048), (3, 256, 128)]
+
+
+@pytest.mark.parametrize("shape", SCHED_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_every_schedule_agrees_to_rounding(gpu_lib, shape, dtype):
+    from paper_1504_06847_amd import Solver
+    L, ny, nx = shape
+    inst = make_instance(ny, nx, L, n_points=3, n_gauss=1, n_ant=10, noise_sigma=0.005, seed=21)
+    _say("schedules", shape, dtype)
+    ref = Solver(inst.psf, inst.dirty, dtype=dtype, **PARAMS)
+    assert ref.schedule == (1, 1)
+    ref.iterate(3)
+    xr = ref.x
+    for rv in range(3):
+        for cv in range(3):
+            s = Solver(inst.psf, inst.dirty, dtype=dtype, **PARAMS)
+            s.set_schedule((rv, cv))
+            s.iterate(3)
+            d = _relmax(s.x, xr)
+            _say("schedule", (rv, cv), "max rel diff", d)
+            assert d <= TOL[dtype], f"schedule {(rv, cv)}"
+            s.close()
+
+
+def test_autotune_keeps_results_and_state(gpu_lib, tmp_path):
+    from paper_1504_06847_amd import Solver
+    L, ny, nx = 8, 256, 256
+    inst = make_instance(ny, nx, L, n_points=3, n_gauss=1, n_ant=10, noise_sigma=0.005, seed=22)
+    a = Solver(inst.psf, inst.dirty, **PARAMS)
+    b = Solver(inst.psf, inst.dirty, **PARAMS)
+    a.iterate(4)
+    b.iterate(4)
+    x0 = b.x
+    st0 = b.get_state().clone()
+    cache = str(tmp_path / "sched.json")
+    sch = b.autotune(reps=3, cache=cache)
+    _say("autotuned schedule", sch)
+    assert all(0 <= v < 3 for v in sch) and b.schedule == tuple(sch)
+    torch.cuda.synchronize()
+    assert torch.equal(b.x, x0)                     # the timing leaves X and the state alone
+    assert torch.equal(b.get_state(), st0)
+    a.iterate(5)
+    b.iterate(5)
+    torch.cuda.synchronize()
+    assert _relmax(b.x, a.x) <= TOL[torch.float32]
+    c = Solver(inst.psf, inst.dirty, **PARAMS)
+    assert c.autotune(cache=cache) == tuple(sch)    # read back from the cache file
+
+
+def test_batch_autotune_keeps_results(gpu_lib):
+    from paper_1504_06847_amd import Batch
+    cubes = _cubes(BATCH[:5], seed0=320)
+    a = Batch(cubes, params=PARAMS)
+    b = Batch(cubes, params=PARAMS)
+    a.iterate(3)
+    b.iterate(3)
+    b.autotune(reps=2)
+    a.iterate(4)
+    b.iterate(4)
+    torch.cuda.synchronize()
+    for i in range(len(cubes)):
+        d = _relmax(b.cube(i).x, a.cube(i).x)
+        _say("batch autotune: cube", i, "max rel diff", d)
+        assert d <= TOL[torch.float32]

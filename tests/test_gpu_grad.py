@@ -1,0 +1,181 @@
+"""The reverse sweep (muffin_grad) against the oracle's forward-mode
+derivatives, finite differences and its own invariants."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import get_config
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _workers():
+    O.set_workers(min(16, os.cpu_count() or 1))
+    yield
+
+
+def _grad64():
+    """64 x 64 x 8 instance drawn with the 1024-cube generator settings, tied
+    rho = 1, mu_s = mu_nu = 0.02, its sky as the reference."""
+    cfg = get_config("grad64")
+    inst = cfg.make()
+    p = cfg.params
+    kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho=p.rho_P)
+    return inst, p, kw
+
+
+@pytest.fixture(scope="module")
+def oracle_grad():
+    inst, p, _ = _grad64()
+    prob = O.Problem(inst.psf, inst.dirty, p)
+    return O.mse_grad(prob, 20, inst.sky)
+
+
+@pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-8), (torch.float32, 1e-4)], ids=["f64", "f32"])
+def test_mse_gradient_matches_oracle(gpu_lib, oracle_grad, dtype, bar):
+    from paper_1504_06847_amd import Solver
+    inst, p, kw = _grad64()
+    loss_o, g_o = oracle_grad
+    s = Solver(inst.psf, inst.dirty, dtype=dtype, **kw)
+    loss, g = s.grad(20, sky=inst.sky, ckpt_every=5)
+    err = np.abs(g - g_o) / np.abs(g_o).max()
+    _say(dtype, "loss", loss, loss_o, "grad", g, g_o, "rel err", err)
+    assert abs(loss - loss_o) <= max(bar, 1e-6 if dtype == torch.float32 else 0) * loss_o
+    assert err.max() <= bar
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient(gpu_lib):
+    from paper_1504_06847_amd import Solver
+    inst, p, kw = _grad64()
+    s = Solver(inst.psf, inst.dirty, **kw)
+    ref = s.grad(20, sky=inst.sky, ckpt_every=5)
+    for C in (1, 3, 7, 20, 50):
+        r = s.grad(20, sky=inst.sky, ckpt_every=C)
+        assert r[0] == ref[0] and np.array_equal(r[1], ref[1]), C
+
+
+def test_vjp_matches_oracle_jvp(gpu_lib):
+    """<gx, J e_i> from the oracle's tangents equals the GPU's (J^T gx)_i."""
+    from paper_1504_06847_amd import Solver
+    inst, p, kw = _grad64()
+    rng = np.random.default_rng(7)
+    gx = rng.standard_normal(inst.sky.shape)
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw)
+    loss, g = s.grad(12, gx=gx, ckpt_every=4)
+    assert loss == 0.0
+    prob = O.Problem(inst.psf, inst.dirty, p)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        _, dX = O.jvp_run(prob, 12, e)
+        ref = float(np.sum(gx * dX))
+        _say("vjp", i, g[i], ref)
+        assert abs(g[i] - ref) <= 1e-8 * max(abs(ref), np.abs(g).max())
+
+
+def test_context_holds_the_K_pass_state_afterwards(gpu_lib):
+    from paper_1504_06847_amd import Solver
+    inst, p, kw = _grad64()
+    a = Solver(inst.psf, inst.dirty, **kw)
+    b = Solver(inst.psf, inst.dirty, **kw)
+    a.iterate(3)
+    a.grad(9, sky=inst.sky, ckpt_every=4)
+    b.iterate(9)
+    torch.cuda.synchronize()
+    assert a.iterations == 9
+    assert torch.equal(a.x, b.x)
+    a.iterate(2)
+    b.iterate(2)
+    torch.cuda.synchronize()
+    assert torch.equal(a.x, b.x)
+
+
+def test_fp32_gradient_against_central_differences(gpu_lib):
+    """Central differences of the FP32 GPU loss (h = 1e-3, the loss summed in
+    FP64) against the adjoint: agreement to 1e-2 (kinks of the prox maps
+    limit it)."""
+    from paper_1504_06847_amd import Solver
+    inst, p, kw = _grad64()
+    sky = torch.as_tensor(inst.sky, dtype=torch.float64)
+    s = Solver(inst.psf, inst.dirty, **kw)
+    _, g = s.grad(20, sky=inst.sky)
+    base = dict(mu_s=kw["mu_s"], mu_nu=kw["mu_nu"], rho=kw["rho"])
+    h = 1e-3
+    for i, name in enumerate(("mu_s", "mu_nu", "rho")):
+        vals = []
+        for sgn in (1, -1):
+            q = dict(base)
+            q[name] = base[name] + sgn * h
+            t = Solver(inst.psf, inst.dirty, mu_eps=kw["mu_eps"], **q)
+            t.iterate(20)
+            vals.append(float(((t.x.double().cpu() - sky) ** 2).sum()))
+            t.close()
+        fd = (vals[0] - vals[1]) / (2 * h)
+        _say("fd", name, fd, "adjoint", g[i])
+        assert abs(fd - g[i]) <= 1e-2 * max(abs(fd), np.abs(g).max())
+
+
+def test_autograd_function(gpu_lib):
+    from paper_1504_06847_amd import MuffinUnroll, Solver
+    inst, p, kw = _grad64()
+    dev = torch.device("cuda")
+    psf = torch.as_tensor(inst.psf, dtype=torch.float64, device=dev)
+    dirty = torch.as_tensor(inst.dirty, dtype=torch.float64, device=dev)
+    sky = torch.as_tensor(inst.sky, dtype=torch.float64, device=dev)
+    mu_s = torch.tensor(kw["mu_s"], dtype=torch.float64, requires_grad=True)
+    mu_nu = torch.tensor(kw["mu_nu"], dtype=torch.float64, requires_grad=True)
+    rho = torch.tensor(kw["rho"], dtype=torch.float64, requires_grad=True)
+    x = MuffinUnroll.apply(psf, dirty, mu_s, mu_nu, rho, 15, 5, kw["mu_eps"])
+    loss = ((x - sky) ** 2).sum()
+    loss.backward()
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw)
+    l2, g = s.grad(15, sky=inst.sky)
+    got = np.array([mu_s.grad.item(), mu_nu.grad.item(), rho.grad.item()])
+    _say("autograd", got, g)
+    assert abs(loss.item() - l2) <= 1e-12 * l2
+    assert np.abs(got - g).max() <= 1e-10 * np.abs(g).max()
+
+
+def test_full_size_gradient_fp32(gpu_lib):
+    """The 1024 x 1024 x 64 FP32 cube, K = 20, checkpoints every 5 passes:
+    the adjoint against central differences (h = 1e-3, FP64 loss sums)."""
+    from paper_1504_06847_amd import Solver
+    cfg = get_config("cube1024")
+    inst = cfg.make()
+    p = cfg.params
+    kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho=p.rho_P)
+    _say("full-size gradient")
+    sky = torch.as_tensor(inst.sky, device="cuda").double()
+    s = Solver(inst.psf, inst.dirty, **kw)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    loss, g = s.grad(20, sky=inst.sky, ckpt_every=5)
+    e1.record()
+    torch.cuda.synchronize()
+    _say("full-size loss", loss, "grad", g, "ms", e0.elapsed_time(e1))
+    assert np.all(np.isfinite(g))
+    base = dict(mu_s=kw["mu_s"], mu_nu=kw["mu_nu"], rho=kw["rho"])
+    h = 1e-3
+    for i, name in enumerate(("mu_s", "mu_nu", "rho")):
+        vals = []
+        for sgn in (1, -1):
+            q = dict(base)
+            q[name] = base[name] + sgn * h
+            s.set_params(mu_eps=kw["mu_eps"], **q)
+            s.reset()
+            s.iterate(20)
+            vals.append(float(((s.x.double() - sky) ** 2).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        _say("full-size fd", name, fd, "adjoint", g[i])
+        assert abs(fd - g[i]) <= 1e-2 * max(abs(fd), np.abs(g).max())
