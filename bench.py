@@ -11,7 +11,11 @@ kernel (HIP-event timing of each kernel on the solver's stream, algorithmic
 bytes per launch), the FP64 instantiation's rate, and the FP64 CPU oracle
 timed on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-graph] [--no-batch]
+
+Each pass is replayed from a HIP graph unless --no-graph is given.  The
+16-cube batch (uneven sizes and band counts) is timed in its per-cube
+sequential, grouped, grouped + graph and autotuned forms.
 """
 from __future__ import annotations
 
@@ -208,7 +212,8 @@ def main(argv=None):
     ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="replay each pass from a HIP graph")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="launch each pass's kernels one by one instead of replaying a HIP graph")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-cube batch measurement")
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--copy-probe", action="store_true",
@@ -251,7 +256,7 @@ def main(argv=None):
     fp64 = None
     if a.fp64_steps > 0:
         _log(f"bench: FP64 {a.fp64_steps} timed passes")
-        ms64, prof64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5)
+        ms64, prof64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5, graph=a.graph)
         fp64 = dict(value=V * a.fp64_steps / (ms64 / 1e3), ms_per_step=round(ms64 / a.fp64_steps, 4),
                     kernels_ms={k: round(v, 5) for k, v in prof64.items()})
     batch = None
