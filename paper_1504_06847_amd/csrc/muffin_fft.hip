@@ -74,7 +74,10 @@ __device__ __forceinline__ void row_fwd_body(const Tin* __restrict__ in, cx<T>* 
     constexpr int TS = lds_len<true>(M);
     const int t = threadIdx.x;
     const long row0 = blk * RPW;
-    for (int i = t; i < RPW * M; i += ROW_NTH) {
+#pragma unroll
+    for (int j = 0; j < (RPW * M + ROW_NTH - 1) / ROW_NTH; ++j) {
+        const int i = t + j * ROW_NTH;
+        if ((RPW * M) % ROW_NTH != 0 && i >= RPW * M) break;
         const int r = i / M, m = i % M;
         const long grow = row0 + r;
         cx<T> v = {T(0), T(0)};
@@ -100,7 +103,10 @@ __device__ __forceinline__ void row_fwd_body(const Tin* __restrict__ in, cx<T>* 
     __syncthreads();
     tile_fft<T, M, RPW, ROW_NTH, TS, 1, false, true, false>(lds, tw, twlog, t);
     constexpr int NK = M / 2 + 1;
-    for (int i = t; i < RPW * NK; i += ROW_NTH) {
+#pragma unroll
+    for (int j = 0; j < (RPW * NK + ROW_NTH - 1) / ROW_NTH; ++j) {
+        const int i = t + j * ROW_NTH;
+        if (i >= RPW * NK) break;
         const int r = i / NK, k = i % NK;
         const long grow = row0 + r;
         if (grow >= nrows) continue;
@@ -152,7 +158,10 @@ __device__ __forceinline__ void row_inv_body(const cx<T>* __restrict__ in, T* __
     const int t = threadIdx.x;
     const long row0 = blk * RPW;
     constexpr int NK = M / 2 + 1;
-    for (int i = t; i < RPW * NK; i += ROW_NTH) {
+#pragma unroll
+    for (int j = 0; j < (RPW * NK + ROW_NTH - 1) / ROW_NTH; ++j) {
+        const int i = t + j * ROW_NTH;
+        if (i >= RPW * NK) break;
         const int r = i / NK, k = i % NK;
         const long grow = row0 + r;
         cx<T>* l = lds + r * TS;
@@ -174,7 +183,10 @@ __device__ __forceinline__ void row_inv_body(const cx<T>* __restrict__ in, T* __
     }
     __syncthreads();
     tile_fft<T, M, RPW, ROW_NTH, TS, 1, false, true, true>(lds, tw, twlog, t);
-    for (int i = t; i < RPW * M; i += ROW_NTH) {
+#pragma unroll
+    for (int j = 0; j < (RPW * M + ROW_NTH - 1) / ROW_NTH; ++j) {
+        const int i = t + j * ROW_NTH;
+        if ((RPW * M) % ROW_NTH != 0 && i >= RPW * M) break;
         const int r = i / M, m = i % M;
         const long grow = row0 + r;
         if (grow < nrows) reinterpret_cast<cx<T>*>(out + grow * NX)[m] = lds[r * TS + lds_pos<true>(m)];
@@ -231,28 +243,60 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
     const int band = int(wg / ntiles);
     const int c0 = int(wg % ntiles) * TC;
     const long base = (long)band * NY * M;
-    for (int i = t; i < NY * TC; i += NTH) {
+    constexpr int NIT = (NY * TC + NTH - 1) / NTH;
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int i = t + j * NTH;
         const int y = i / TC, c = i % TC;
         cx<T> v = {T(0), T(0)};
-        if (c0 + c < M) v = data[base + (long)y * M + c0 + c];
-        lds[y * TCP + c] = v;
+        if (i < NY * TC && c0 + c < M) v = data[base + (long)y * M + c0 + c];
+        if (i < NY * TC) lds[y * TCP + c] = v;
     }
     if constexpr (TWL) {
         for (int i = t; i < NY; i += NTH) twl[i] = tw[i << (twlog - ilog2c(NY))];
+    }
+    // the data term and the filter of this thread's elements, loaded before
+    // the forward transform so that their latency hides behind it (up to 8
+    // elements per thread: more would cost the occupancy of wide tiles)
+    constexpr bool FILT = MODE == COL_SOLVE || MODE == COL_FILTER;
+    constexpr int IPT = NIT;
+    constexpr bool PRE = FILT && IPT <= 8;
+    cx<T> yfp[MODE == COL_SOLVE && PRE ? IPT : 1];
+    T gp[PRE ? IPT : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int i = t + j * NTH;
+            const int y = i / TC, c = i % TC, kx = c0 + c;
+            gp[j] = T(0);
+            if constexpr (MODE == COL_SOLVE) yfp[j] = {T(0), T(0)};
+            if (i < NY * TC && kx != 0 && kx < M) {
+                const long g = base + (long)y * M + kx;
+                if constexpr (MODE == COL_SOLVE) yfp[j] = Yf[g];
+                gp[j] = scale / (H2[g] + rhoQ);
+            }
+        }
     }
     __syncthreads();
     if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, twl, ilog2c(NY), t);
     else tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, tw, twlog, t);
 
-    if constexpr (MODE == COL_SOLVE || MODE == COL_FILTER) {
+    if constexpr (FILT) {
         // COL_FILTER: Q^{-1} alone (no data term), the adjoint's solve
-        for (int i = t; i < NY * TC; i += NTH) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int i = t + j * NTH;
             const int y = i / TC, c = i % TC, kx = c0 + c;
-            if (kx == 0 || kx >= M) continue;
-            const long g = base + (long)y * M + kx;
+            if (i >= NY * TC || kx == 0 || kx >= M) continue;
             cx<T> v = lds[y * TCP + c];
-            if constexpr (MODE == COL_SOLVE) v = v + Yf[g];
-            lds[y * TCP + c] = v * (scale / (H2[g] + rhoQ));
+            if constexpr (PRE) {
+                if constexpr (MODE == COL_SOLVE) v = v + yfp[j];
+                lds[y * TCP + c] = v * gp[j];
+            } else {
+                const long g = base + (long)y * M + kx;
+                if constexpr (MODE == COL_SOLVE) v = v + Yf[g];
+                lds[y * TCP + c] = v * (scale / (H2[g] + rhoQ));
+            }
         }
         if (c0 == 0) {
             // slot 0 packs the real columns kx = 0 (A) and kx = nx/2 (B): C = A + i B
@@ -280,9 +324,11 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
     }
 
     if constexpr (MODE == COL_SOLVE || MODE == COL_FWD || MODE == COL_FILTER) {
-        for (int i = t; i < NY * TC; i += NTH) {
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int i = t + j * NTH;
             const int y = i / TC, c = i % TC;
-            if (c0 + c < M) data[base + (long)y * M + c0 + c] = lds[y * TCP + c];
+            if (i < NY * TC && c0 + c < M) data[base + (long)y * M + c0 + c] = lds[y * TCP + c];
         }
     }
 
