@@ -40,7 +40,9 @@ METRIC = "voxel-iterations/s (FP32 vs FP64) at 1024²×64; HBM GB/s % of peak"
 #   row_inv  : spectrum in, X out                                      2
 #   spectral : X, z_P, z_T, S, Gamma_S, Gamma_S again in;
 #              z_P, z_T, S, Gamma_S, B_rest out                        11
-KERNEL_ELEMS = {"row_fwd": 2.0, "col_solve": 3.5, "row_inv": 2.0, "spectral": 11.0}
+#   fused    : Z, S, Gamma_S, z_P, z_T, Gamma_S again in;
+#              Z, X, z_P, z_T, S, Gamma_S out                            12
+KERNEL_ELEMS = {"row_fwd": 2.0, "col_solve": 3.5, "row_inv": 2.0, "spectral": 11.0, "fused": 12.0}
 # minimum traffic of one pass of this algorithm: the 4-array state stream in
 # and out plus the constants (38 B in FP32) and one transposition round trip
 # of the 2-D FFT (16 B)
@@ -54,7 +56,7 @@ def kernel_source_hash():
     """Hash of the sources of the iteration kernels (counters go stale with them)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("muffin_device.hpp", "muffin_kernels.hpp", "muffin_fft.hip", "muffin_spectral.hip"):
+    for f in ("muffin_device.hpp", "muffin_kernels.hpp", "muffin_fft.hip", "muffin_spectral.hip", "muffin_fused.hip"):
         with open(os.path.join(ROOT, "paper_1504_06847_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

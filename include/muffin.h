@@ -189,27 +189,34 @@ int muffin_set_graph(muffin_ctx* ctx, int enable);
 /* Number of passes run since setup/reset. */
 int muffin_iterations(const muffin_ctx* ctx);
 
-/* ---- FFT tile schedules (the 2-D transform of step I, eq. Qlsimp) --------
-   A schedule is two variant indices in [0, 3): schedule[0] for the row
-   passes (0, 1, 2: about 1024, 2048, 4096 complex points per work-group),
-   schedule[1] for the column pass (0, 1, 2: half, all or twice the column
-   tile that fits 64 KiB of LDS; twice only where the LDS holds it).  Every
-   schedule evaluates the same formulas in the same order; the compiler may
-   fuse a product and a sum into one FMA in one schedule's code and not in
-   another's, so results agree to rounding (a few ulps), not bit for bit.
-   Default {1, 1}. */
+/* ---- schedules of a pass (the 2-D transform of step I, eq. Qlsimp, and
+   the pass structure) -----------------------------------------------------
+   A schedule is three integers: schedule[0] in [0, 3) for the row passes
+   (about 1024, 2048, 4096 complex points per work-group), schedule[1] in
+   [0, 3) for the column pass (half, all or twice the column tile that fits
+   64 KiB of LDS; twice only where the LDS holds it), schedule[2] = 1 to run
+   the inverse row pass, steps II-VI and the forward row pass of the next
+   step I as one fused launch where it is built (muffin_fused_available),
+   0 for three launches.  Every schedule evaluates the same formulas in the
+   same order; the compiler may fuse a product and a sum into one FMA in one
+   schedule's code and not in another's, so results agree to rounding (a few
+   ulps), not bit for bit.  Default {1, 1, 1}. */
 
-/* Time each variant of the three transform passes `reps` times on this
-   context's own arrays (the timing writes only the pass's internal spectrum
-   buffer and the unused second state set: X and the state are unchanged),
-   keep the fastest and write it to schedule (may be NULL).  Synchronises the
+/* Time each variant of the transform passes, and the fused launch against
+   the three it replaces, `reps` times on this context's own arrays (the
+   timing writes only internal scratch: X and the state are unchanged), keep
+   the fastest and write it to schedule (may be NULL).  Synchronises the
    stream.  Errors: EINVAL (reps < 1), EDEVICE. */
-int muffin_autotune(muffin_ctx* ctx, int reps, int schedule[2]);
+int muffin_autotune(muffin_ctx* ctx, int reps, int schedule[3]);
 
 /* Use a stored schedule (e.g. one muffin_autotune found for this shape).
-   Errors: EINVAL (index out of range). */
-int muffin_set_schedule(muffin_ctx* ctx, const int schedule[2]);
-int muffin_get_schedule(const muffin_ctx* ctx, int schedule[2]);
+   Errors: EINVAL (value out of range). */
+int muffin_set_schedule(muffin_ctx* ctx, const int schedule[3]);
+int muffin_get_schedule(const muffin_ctx* ctx, int schedule[3]);
+
+/* 1 if this context's shape has the fused launch (FP32, 64 <= nx <= 1024,
+   L in {4, 8, 16, 32, 64}, a cube of at most 1 GiB), else 0. */
+int muffin_fused_available(const muffin_ctx* ctx);
 
 /* ---- batches of independent cubes ----------------------------------------
    Many cubes of uneven size and band count (each its own instance of the

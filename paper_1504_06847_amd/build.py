@@ -24,7 +24,7 @@ LIB = os.path.join(HERE, "libmuffin.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["muffin_fft.hip", "muffin_spectral.hip", "muffin_adjoint.hip"]
+HIP_SOURCES = ["muffin_fft.hip", "muffin_spectral.hip", "muffin_adjoint.hip", "muffin_fused.hip"]
 HOST_SOURCES = ["muffin_validate.cpp", "muffin_api.cpp", "muffin_batch.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

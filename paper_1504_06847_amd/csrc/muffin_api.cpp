@@ -18,18 +18,57 @@ using namespace muffin;
 
 namespace {
 
+bool use_fused(const muffin_ctx* c) {
+    return c->fused && fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L);
+}
+
+// the row pass of step I: Z = row spectra of B_rest, unless Z holds them
+// already (after a fused pass)
+int row_forward(muffin_ctx* c) {
+    if (c->zvalid) return MUFFIN_OK;
+    const muffin_shape& s = c->shape;
+    HIP_TRY(launch_row_fwd(s.dtype, s.dtype == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), s.L * s.ny,
+                           s.nx, s.ny, false, false, P(c, c->lay.tw), c->twlog, c->stream, c->row_v));
+    c->zvalid = 1;
+    return MUFFIN_OK;
+}
+
+int col_solve(muffin_ctx* c) {
+    const muffin_shape& s = c->shape;
+    HIP_TRY(launch_col(s.dtype, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
+                       P(c, c->lay.h2nyq), rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx,
+                       P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream, c->col_v));
+    c->zvalid = 0;
+    return MUFFIN_OK;
+}
+
 // step I of one pass: X = Q^{-1} (H^T Y + B_rest), band by band
 int step_one(muffin_ctx* c) {
     const muffin_shape& s = c->shape;
-    const int dt = s.dtype;
-    const int nrows = s.L * s.ny;
-    HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows, s.nx,
-                           s.ny, false, false, P(c, c->lay.tw), c->twlog, c->stream, c->row_v));
-    HIP_TRY(launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
-                       P(c, c->lay.h2nyq), rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx,
-                       P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream, c->col_v));
-    HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), P(c, c->lay.x), nrows, s.nx, P(c, c->lay.tw),
+    if (int rc = row_forward(c)) return rc;
+    if (int rc = col_solve(c)) return rc;
+    HIP_TRY(launch_row_inv(s.dtype, P(c, c->lay.z), P(c, c->lay.x), s.L * s.ny, s.nx, P(c, c->lay.tw),
                            c->twlog, c->stream, c->row_v));
+    return MUFFIN_OK;
+}
+
+// the inverse row pass, steps II-VI and the forward row pass of the next
+// step I in one launch: X and the state as step_one + step_spectral, and Z
+// holds the row spectra of the new B_rest (B_rest itself is not written)
+int fused_rows(muffin_ctx* c) {
+    const muffin_shape& s = c->shape;
+    FusedArrays A;
+    A.X = P(c, c->lay.x);
+    A.zP = (char*)st(c, ST_ZP);
+    A.zT = (char*)st(c, ST_ZT);
+    A.S = (char*)st(c, ST_S);
+    A.GS = (char*)st(c, ST_GS);
+    A.Z = P(c, c->lay.z);
+    A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
+    A.gshift = 0;
+    HIP_TRY(launch_fused(s.dtype, A, P(c, c->lay.dctm), s.L, s.ny, s.nx, spec_args(c->params),
+                         P(c, c->lay.tw), c->twlog, c->stream));
+    c->zvalid = 1;
     return MUFFIN_OK;
 }
 
@@ -51,6 +90,7 @@ int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
     g.vpart = (double*)P(c, c->lay.vpart);
     g.partials = (double*)P(c, c->lay.partials);
     HIP_TRY(launch_spectral(s.dtype, g, spec_args(c->params), nblocks, c->stream));
+    c->zvalid = 0;        // B_rest written; Z holds the previous step I's spectrum
     if (report) {
         c->cur = 1 - c->cur;
         c->version++;
@@ -59,6 +99,11 @@ int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
 }
 
 int pass_kernels(muffin_ctx* c) {
+    if (use_fused(c)) {
+        if (int rc = row_forward(c)) return rc;
+        if (int rc = col_solve(c)) return rc;
+        return fused_rows(c);
+    }
     int rc = step_one(c);
     if (rc) return rc;
     return step_spectral(c, false, nullptr);
@@ -99,11 +144,16 @@ int capture_pass(muffin_ctx* c) {
 
 int one_pass(muffin_ctx* c) {
     if (c->use_graph) {
+        // a recorded fused pass starts from Z (the graph holds the column
+        // and fused launches only)
+        if (use_fused(c))
+            if (int rc = row_forward(c)) return rc;
         if (!c->gexec[c->cur]) {
             int rc = capture_pass(c);
             if (rc) return rc;
         }
         HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
+        c->zvalid = use_fused(c) ? 1 : 0;
     } else {
         int rc = pass_kernels(c);
         if (rc) return rc;
@@ -115,6 +165,7 @@ int one_pass(muffin_ctx* c) {
 int recompute_brest(muffin_ctx* c) {
     HIP_TRY(launch_brest(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), st(c, ST_S), st(c, ST_GS),
                          P(c, c->lay.brest), voxels(c->shape), spec_args(c->params), c->stream));
+    c->zvalid = 0;
     return MUFFIN_OK;
 }
 
@@ -123,6 +174,7 @@ int zero_state(muffin_ctx* c) {
     HIP_TRY(launch_fill_zero(P(c, c->lay.state[0][0]), c->lay.z - c->lay.state[0][0], c->stream));
     c->cur = 0;
     c->iters = 0;
+    c->zvalid = 0;
     c->version++;
     return MUFFIN_OK;
 }
@@ -374,6 +426,10 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
 
 }  // namespace
 
+namespace muffin {
+int refresh_brest(muffin_ctx* c) { return recompute_brest(c); }
+}  // namespace muffin
+
 extern "C" {
 
 int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_params* params,
@@ -409,6 +465,8 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     c->twlog = ilog2i(NT);
     c->row_v = kDefaultRowVariant;
     c->col_v = kDefaultColVariant;
+    c->fused = kDefaultFused;
+    c->zvalid = 0;
     c->version = 0;
     c->grad_buf = nullptr;
     c->grad_bytes = 0;
@@ -598,36 +656,39 @@ int muffin_iterations(const muffin_ctx* c) { return c ? c->iters : -1; }
 int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, int cap) {
     if (int rc = check_ctx(c)) return rc;
     if (n_iter < 1 || !ms || cap < 1) { set_error("muffin_profile: bad arguments"); return MUFFIN_EINVAL; }
-    static const char* knames[4] = {"row_fwd", "col_solve", "row_inv", "spectral"};
-    const int K = 4;
-    hipEvent_t ev[K + 1];
+    // the kernels of one pass of the context's schedule, timed with events
+    // between the launches (each pass runs: the state advances)
+    static const char* unfused[4] = {"row_fwd", "col_solve", "row_inv", "spectral"};
+    static const char* fused[2] = {"col_solve", "fused"};
+    const bool fu = use_fused(c);
+    const int K = fu ? 2 : 4;
+    const char** knames = fu ? fused : unfused;
+    hipEvent_t ev[5];
     for (int i = 0; i <= K; ++i) HIP_TRY(hipEventCreate(&ev[i]));
-    double acc[K] = {0, 0, 0, 0};
+    double acc[4] = {0, 0, 0, 0};
     const muffin_shape& s = c->shape;
-    const int dt = s.dtype, nrows = s.L * s.ny;
-    const double scale = fft_scale(s);
     int rc = MUFFIN_OK;
+    if (fu) rc = row_forward(c);
     for (int it = 0; it < n_iter && rc == MUFFIN_OK; ++it) {
         hipError_t e = hipEventRecord(ev[0], c->stream);
-        if (e == hipSuccess)
-            e = launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows, s.nx, s.ny,
-                               false, false, P(c, c->lay.tw), c->twlog, c->stream, c->row_v);
-        if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
-        if (e == hipSuccess)
-            e = launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2), P(c, c->lay.h2nyq),
-                           rho_Q(c->params), scale, s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog, nullptr,
-                           nullptr, c->stream, c->col_v);
-        if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
-        if (e == hipSuccess)
-            e = launch_row_inv(dt, P(c, c->lay.z), P(c, c->lay.x), nrows, s.nx, P(c, c->lay.tw), c->twlog,
-                               c->stream, c->row_v);
-        if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
-        if (e == hipSuccess) {
-            rc = step_spectral(c, false, nullptr);
-            if (rc) break;
+        if (fu) {
+            if (e == hipSuccess && (rc = col_solve(c)) != MUFFIN_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+            if (e == hipSuccess && (rc = fused_rows(c)) != MUFFIN_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
+        } else {
+            if (e == hipSuccess && (rc = row_forward(c)) != MUFFIN_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+            if (e == hipSuccess && (rc = col_solve(c)) != MUFFIN_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
+            if (e == hipSuccess)
+                e = launch_row_inv(s.dtype, P(c, c->lay.z), P(c, c->lay.x), s.L * s.ny, s.nx, P(c, c->lay.tw),
+                                   c->twlog, c->stream, c->row_v);
+            if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
+            if (e == hipSuccess && (rc = step_spectral(c, false, nullptr)) != MUFFIN_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(ev[4], c->stream);
         }
-        if (e == hipSuccess) e = hipEventRecord(ev[4], c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[K]);
         if (e != hipSuccess) { set_error("profile: %s", hipGetErrorString(e)); rc = MUFFIN_EDEVICE; break; }
         for (int k = 0; k < K; ++k) {
             float t = 0.f;
@@ -660,76 +721,121 @@ int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int
     return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, grad);
 }
 
-int muffin_autotune(muffin_ctx* c, int reps, int schedule[2]) {
+int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
     if (int rc = check_ctx(c)) return rc;
     if (reps < 1) { set_error("reps = %d < 1", reps); return MUFFIN_EINVAL; }
     const muffin_shape& s = c->shape;
     const int dt = s.dtype, nrows = s.L * s.ny;
-    // B_rest -> Z -> Z -> (a scratch array): the timing leaves X and the state alone
+    // Scratch only: Z, B_rest (recomputed from the state at the end) and the
+    // second state set; X and the state stay as they are.
     void* scratch = st_alt(c, 0);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    double t[3][kNumVariants];
     hipError_t e = hipSuccess;
-    for (int kind = 0; kind < 3 && e == hipSuccess; ++kind) {
-        for (int v = 0; v < kNumVariants && e == hipSuccess; ++v) {
-            auto launch = [&]() {
-                if (kind == 0)
-                    return launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows,
-                                          s.nx, s.ny, false, false, P(c, c->lay.tw), c->twlog, c->stream, v);
-                if (kind == 1)
-                    return launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
-                                      P(c, c->lay.h2nyq), rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx,
-                                      P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream, v);
-                return launch_row_inv(dt, P(c, c->lay.z), scratch, nrows, s.nx, P(c, c->lay.tw), c->twlog,
-                                      c->stream, v);
-            };
-            e = launch();
-            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            t[kind][v] = ms;
-        }
+    auto timeit = [&](auto&& launch) -> double {
+        if (e == hipSuccess) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        return double(ms) / reps;
+    };
+    double t[3][kNumVariants];
+    for (int v = 0; v < kNumVariants; ++v) {
+        t[0][v] = timeit([&] {
+            return launch_row_fwd(dt, dt == MUFFIN_F64, P(c, c->lay.brest), P(c, c->lay.z), nrows, s.nx, s.ny,
+                                  false, false, P(c, c->lay.tw), c->twlog, c->stream, v);
+        });
+        t[1][v] = timeit([&] {
+            return launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
+                              P(c, c->lay.h2nyq), rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx,
+                              P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream, v);
+        });
+        t[2][v] = timeit([&] {
+            return launch_row_inv(dt, P(c, c->lay.z), scratch, nrows, s.nx, P(c, c->lay.tw), c->twlog, c->stream, v);
+        });
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (e != hipSuccess) { set_error("autotune: %s", hipGetErrorString(e)); return MUFFIN_EDEVICE; }
     int rv = kDefaultRowVariant, cv = kDefaultColVariant;
     for (int v = 0; v < kNumVariants; ++v) {
         if (t[0][v] + t[2][v] < t[0][rv] + t[2][rv]) rv = v;
         if (t[1][v] < t[1][cv]) cv = v;
     }
-    const int sch[2] = {rv, cv};
-    if (schedule) { schedule[0] = rv; schedule[1] = cv; }
+    // fused or not: the spectral pass and the fused kernel on a copy of the
+    // state in the second set (X of the fused kernel into the B_rest buffer)
+    int fu = 0;
+    if (e == hipSuccess && fused_supported(dt, s.nx, s.ny, s.L)) {
+        const size_t nb = voxels(s) * elem_size(s);
+        for (int i = 0; i < kNumState && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(st_alt(c, i), st(c, i), nb, hipMemcpyDeviceToDevice, c->stream);
+        SpecLaunch g;
+        g.X = P(c, c->lay.x);
+        for (int i = 0; i < kNumState; ++i) g.st[i] = g.out[i] = st_alt(c, i);
+        g.brest = P(c, c->lay.brest);
+        g.dctm = P(c, c->lay.dctm);
+        g.L = s.L;
+        g.npix = long(s.ny) * s.nx;
+        g.report = false;
+        g.vpart = (double*)P(c, c->lay.vpart);
+        g.partials = (double*)P(c, c->lay.partials);
+        const SpecArgs a = spec_args(c->params);
+        const double tspec = timeit([&] { return launch_spectral(dt, g, a, nullptr, c->stream); });
+        FusedArrays A;
+        A.X = P(c, c->lay.brest);
+        A.zP = (char*)st_alt(c, ST_ZP);
+        A.zT = (char*)st_alt(c, ST_ZT);
+        A.S = (char*)st_alt(c, ST_S);
+        A.GS = (char*)st_alt(c, ST_GS);
+        A.Z = P(c, c->lay.z);
+        A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
+        A.gshift = 0;
+        const double tfu = timeit([&] {
+            return launch_fused(dt, A, P(c, c->lay.dctm), s.L, s.ny, s.nx, a, P(c, c->lay.tw), c->twlog, c->stream);
+        });
+        fu = (tfu < t[0][rv] + t[2][rv] + tspec) ? 1 : 0;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) { set_error("autotune: %s", hipGetErrorString(e)); return MUFFIN_EDEVICE; }
+    if (int rc = recompute_brest(c)) return rc;      // Z and B_rest were scratch
+    const int sch[3] = {rv, cv, fu};
+    if (schedule) { schedule[0] = rv; schedule[1] = cv; schedule[2] = fu; }
     return muffin_set_schedule(c, sch);
 }
 
-int muffin_set_schedule(muffin_ctx* c, const int schedule[2]) {
+int muffin_set_schedule(muffin_ctx* c, const int schedule[3]) {
     if (int rc = check_ctx(c)) return rc;
     if (!schedule || schedule[0] < 0 || schedule[0] >= kNumVariants || schedule[1] < 0 ||
-        schedule[1] >= kNumVariants) {
-        set_error("schedule must hold two variant indices in [0, %d)", kNumVariants);
+        schedule[1] >= kNumVariants || schedule[2] < 0 || schedule[2] > 1) {
+        set_error("schedule must hold two variant indices in [0, %d) and a 0/1 fused flag", kNumVariants);
         return MUFFIN_EINVAL;
     }
-    if (c->row_v != schedule[0] || c->col_v != schedule[1]) {
+    if (c->row_v != schedule[0] || c->col_v != schedule[1] || c->fused != schedule[2]) {
+        const bool was_fused = use_fused(c);
         c->row_v = schedule[0];
         c->col_v = schedule[1];
+        c->fused = schedule[2];
+        if (was_fused && !use_fused(c))
+            if (int rc = recompute_brest(c)) return rc;    // B_rest was not kept up to date
         drop_graphs(c);
         c->version++;
     }
     return MUFFIN_OK;
 }
 
-int muffin_get_schedule(const muffin_ctx* c, int schedule[2]) {
+int muffin_get_schedule(const muffin_ctx* c, int schedule[3]) {
     if (int rc = check_ctx(c)) return rc;
     if (!schedule) { set_error("schedule is NULL"); return MUFFIN_EINVAL; }
     schedule[0] = c->row_v;
     schedule[1] = c->col_v;
+    schedule[2] = c->fused;
     return MUFFIN_OK;
+}
+
+int muffin_fused_available(const muffin_ctx* c) {
+    return c && fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L) ? 1 : 0;
 }
 
 int muffin_set_graph(muffin_ctx* c, int enable) {

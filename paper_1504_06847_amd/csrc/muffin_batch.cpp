@@ -326,6 +326,11 @@ int muffin_batch_iterate(muffin_batch* b, int n_iter) {
     if (int rc = check_batch(b)) return rc;
     if (n_iter < 0) { set_error("n_iter = %d < 0", n_iter); return MUFFIN_EINVAL; }
     if (n_iter == 0) return MUFFIN_OK;
+    // the grouped passes start from B_rest: a cube whose last pass was a
+    // fused single-cube pass has it only as row spectra
+    for (muffin_ctx* c : b->cubes)
+        if (c->zvalid)
+            if (int rc = refresh_brest(c)) return rc;
     if (stale(b))
         if (int rc = rebuild(b)) return rc;
     for (int it = 0; it < n_iter; ++it) {

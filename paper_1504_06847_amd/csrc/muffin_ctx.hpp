@@ -18,8 +18,12 @@ struct muffin_ctx {
     int iters;
     int twlog;
     double ynorm2;
-    // tile schedules of the row and column passes (muffin_autotune)
-    int row_v, col_v;
+    // tile schedules of the row and column passes, and whether a pass runs
+    // the fused row/spectral kernel (muffin_autotune)
+    int row_v, col_v, fused;
+    // Z holds the row spectra of the current B_rest (set by the forward row
+    // pass and by the fused kernel, which does not write B_rest itself)
+    int zvalid;
     // bumped whenever the arrays, parameters or schedules of the next pass
     // change (a batch rebuilds its launch descriptors then)
     unsigned version;
@@ -70,6 +74,9 @@ inline double rho_Q(const muffin_params& p) {
 
 // scale of the unnormalised packed 2-D transform pair, folded into the filter
 inline double fft_scale(const muffin_shape& s) { return 1.0 / (double(s.nx / 2) * double(s.ny)); }
+
+// recompute B_rest from the stored state (muffin_api.cpp)
+int refresh_brest(muffin_ctx* c);
 
 inline int check_ctx(const muffin_ctx* c) {
     if (!c) { set_error("context is NULL"); return MUFFIN_EINVAL; }

@@ -98,6 +98,22 @@ template <typename T> struct BandArray {
     }
 };
 
+// The same for an array whose L bands all lie within 2^30 bytes of its base:
+// one descriptor for every band (the band offset is the scalar offset).
+template <typename T> struct BandArray1 {
+    __amdgpu_buffer_rsrc_t r;
+    unsigned band_bytes;
+    __device__ __forceinline__ BandArray1(char* base, unsigned bb)
+        : r(__builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7fffffff, kBufWord3)), band_bytes(bb) {}
+    __device__ __forceinline__ T load(int l, unsigned lane_off) const {
+        static_assert(sizeof(T) == 4, "FP32 arrays");
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, (unsigned)l * band_bytes, 0));
+    }
+    __device__ __forceinline__ void store(int l, unsigned lane_off, T v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, lane_off, (unsigned)l * band_bytes, 0);
+    }
+};
+
 // largest gshift with 2^gshift bands of band_bytes each within 2^30 bytes
 __host__ __device__ inline int band_group_shift(unsigned long long band_bytes) {
     int g = 0;
@@ -260,6 +276,54 @@ __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__
 template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
 __device__ __forceinline__ void tile_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
     fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, 0>(buf, tw, twlog, t);
+}
+
+// ---------------------------------------------------------------- real rows
+// A real row x_0 .. x_{nx-1} is transformed as the M = nx/2 point complex
+// sequence z_m = x_{2m} + i x_{2m+1}.  Packed half spectrum of the row:
+// slot 0 holds the two real values (X_0, X_{nx/2}), slot k (0 < k < M) X_k.
+// l: the row's M-point spectrum Z in LDS (padded positions); o: the packed
+// output row; k in [0, M/2] produces slots k and M - k.
+template <typename T, int NX>
+__device__ __forceinline__ void rfft_post(const cx<T>* l, cx<T>* o, int k, const cx<T>* __restrict__ tw,
+                                          int twlog) {
+    constexpr int M = NX / 2;
+    const cx<T> zk = l[lds_pos<true>(k)];
+    if (k == 0) {
+        o[0] = {zk.x + zk.y, zk.x - zk.y};           // (X_0, X_{nx/2}), both real
+    } else if (k == M / 2) {
+        o[k] = conj(zk);
+    } else {
+        const cx<T> zm = l[lds_pos<true>(M - k)];
+        // even/odd sample spectra E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
+        const cx<T> e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+        const cx<T> od = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+        const cx<T> wo = cmul(od, tw[k << (twlog - ilog2c(NX))]);
+        o[k] = e + wo;                                // X_k = E + w^k O
+        o[M - k] = conj(e - wo);                      // X_{M-k} = conj(E - w^k O)
+    }
+}
+
+// The inverse: from the packed half spectrum p of a row, slots k and M - k of
+// the M-point spectrum whose inverse FFT is z_m = x_{2m} + i x_{2m+1}
+// (unnormalised), written to the LDS row l.
+template <typename T, int NX>
+__device__ __forceinline__ void irfft_pre(const cx<T>* p, cx<T>* l, int k, const cx<T>* __restrict__ tw,
+                                          int twlog) {
+    constexpr int M = NX / 2;
+    const cx<T> xk = p[k];
+    if (k == 0) {
+        l[0] = {T(0.5) * (xk.x + xk.y), T(0.5) * (xk.x - xk.y)};
+    } else if (k == M / 2) {
+        l[lds_pos<true>(k)] = conj(xk);
+    } else {
+        const cx<T> xm = p[M - k];
+        const cx<T> e = {T(0.5) * (xk.x + xm.x), T(0.5) * (xk.y - xm.y)};
+        const cx<T> d = {T(0.5) * (xk.x - xm.x), T(0.5) * (xk.y + xm.y)};
+        const cx<T> o = cmulc(d, tw[k << (twlog - ilog2c(NX))]);   // O = w^{-k} D
+        l[lds_pos<true>(k)] = e + mul_i(o);                         // Z_k = E + i O
+        l[lds_pos<true>(M - k)] = conj(e) + mul_i(conj(o));
+    }
 }
 
 // ---------------------------------------------------------------- register FFT / DCT

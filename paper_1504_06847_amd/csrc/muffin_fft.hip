@@ -110,21 +110,7 @@ __device__ __forceinline__ void row_fwd_body(const Tin* __restrict__ in, cx<T>* 
         const int r = i / NK, k = i % NK;
         const long grow = row0 + r;
         if (grow >= nrows) continue;
-        cx<T>* o = out + grow * M;
-        const cx<T> zk = lds[r * TS + lds_pos<true>(k)];
-        if (k == 0) {
-            o[0] = {zk.x + zk.y, zk.x - zk.y};           // (X_0, X_{nx/2}), both real
-        } else if (k == M / 2) {
-            o[k] = conj(zk);
-        } else {
-            const cx<T> zm = lds[r * TS + lds_pos<true>(M - k)];
-            // even/odd sample spectra E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
-            const cx<T> e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-            const cx<T> od = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
-            const cx<T> wo = cmul(od, tw[k << (twlog - ilog2c(NX))]);
-            o[k] = e + wo;                                // X_k = E + w^k O
-            o[M - k] = conj(e - wo);                      // X_{M-k} = conj(E - w^k O)
-        }
+        rfft_post<T, NX>(lds + r * TS, out + grow * M, k, tw, twlog);
     }
 }
 
@@ -164,22 +150,8 @@ __device__ __forceinline__ void row_inv_body(const cx<T>* __restrict__ in, T* __
         if (i >= RPW * NK) break;
         const int r = i / NK, k = i % NK;
         const long grow = row0 + r;
-        cx<T>* l = lds + r * TS;
         if (grow >= nrows) continue;
-        const cx<T>* p = in + grow * M;
-        const cx<T> xk = p[k];
-        if (k == 0) {
-            l[0] = {T(0.5) * (xk.x + xk.y), T(0.5) * (xk.x - xk.y)};
-        } else if (k == M / 2) {
-            l[lds_pos<true>(k)] = conj(xk);
-        } else {
-            const cx<T> xm = p[M - k];
-            const cx<T> e = {T(0.5) * (xk.x + xm.x), T(0.5) * (xk.y - xm.y)};
-            const cx<T> d = {T(0.5) * (xk.x - xm.x), T(0.5) * (xk.y + xm.y)};
-            const cx<T> o = cmulc(d, tw[k << (twlog - ilog2c(NX))]);   // O = w^{-k} D
-            l[lds_pos<true>(k)] = e + mul_i(o);                         // Z_k = E + i O
-            l[lds_pos<true>(M - k)] = conj(e) + mul_i(conj(o));
-        }
+        irfft_pre<T, NX>(in + grow * M, lds + r * TS, k, tw, twlog);
     }
     __syncthreads();
     tile_fft<T, M, RPW, ROW_NTH, TS, 1, false, true, true>(lds, tw, twlog, t);

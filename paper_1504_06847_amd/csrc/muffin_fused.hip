@@ -1,0 +1,185 @@
+// The inverse row pass of step I, steps II-VI and the forward row pass of the
+// next step I fused into one launch (Section 3, Algorithm 1; the 2-D FFT of
+// the Fourier-domain solve of eq. Qlsimp split as in muffin_fft.hip).
+//
+// A work-group owns one image row y of every band: one thread per pixel x,
+// holding the pixel's band vector in registers for the spectral steps (as
+// k_spectral), and the row of G bands at a time in LDS for the row
+// transforms:
+//   A  V = soft(DCT(S - Gamma_S / rho_V)), q = IDCT(V)        (registers)
+//   B  for each group of G bands:
+//        inverse real FFT of the column pass's spectrum rows -> X rows (LDS)
+//        steps II, III, V, VI per pixel; X and the new state to HBM; B_rest
+//          into the LDS rows in place of X
+//        forward real FFT of B_rest -> the spectrum rows of the next column
+//          pass (written over the rows read)
+// X and B_rest never make an HBM round trip between kernels: 48 B/voxel in
+// FP32 (Z, X, z_P, z_T, S, Gamma_S, Gamma_S again; Z, X, z_P, z_T, S,
+// Gamma_S) against 60 B for the inverse row pass, spectral pass and forward
+// row pass launched one after another.
+#include "muffin_device.hpp"
+#include "muffin_kernels.hpp"
+
+namespace muffin {
+
+// PPT pixels per thread (x = t + p NX / PPT): two when the band vectors of
+// two pixels fit the registers of a half-size work-group better than one
+// pixel's band vector next to the row transforms of a full-size one.
+template <int NX, int LT> constexpr int fused_ppt() { return 1; }
+
+template <typename T, int NX, int LT, bool DENSE>
+__global__ void __launch_bounds__((NX / fused_ppt<NX, LT>()))
+k_fused(FusedArrays A, const T* __restrict__ D, int Lrt, int ny, SpecArgs a,
+        const cx<T>* __restrict__ tw, int twlog) {
+    constexpr int PPT = fused_ppt<NX, LT>();
+    constexpr int NTH = NX / PPT;
+    constexpr int M = NX / 2;
+    constexpr int G = LT < 16 ? LT : (LT >= 64 ? 8 : 16);   // bands per LDS row group
+    constexpr int TS = lds_len<true>(M);
+    constexpr int NK = M / 2 + 1;
+    constexpr int TPR = NTH / G;                    // threads per LDS row in B1, B3
+    static_assert(NTH % G == 0, "row split");
+    __shared__ cx<T> lds[G * TS];
+    __shared__ cx<T> twl[NX];                       // w_NX^i, i < NX
+    // with 64 bands, q of the first QB bands waits in LDS: the band vector
+    // of the others plus the row transforms fill the registers
+    constexpr int QB = LT >= 64 ? 24 : 0;
+    __shared__ T qlds[QB > 0 ? QB * NTH : 1];
+    const int t = threadIdx.x;
+    const int y = blockIdx.x;
+    const int r0 = t / TPR, k0 = t % TPR;
+    for (int i = t; i < NX; i += NTH) twl[i] = tw[i << (twlog - ilog2c(NX))];
+    __syncthreads();
+    unsigned off[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) off[p] = (unsigned)((long)y * NX + t + p * NTH) * (unsigned)sizeof(T);
+    const unsigned bb = A.band_bytes;
+    // every band of an array within 2^30 bytes of its base (checked on the host)
+    const BandArray1<T> X(A.X, bb), zP(A.zP, bb), zT(A.zT, bb), S(A.S, bb), GS(A.GS, bb);
+    cx<T>* Z = (cx<T>*)A.Z;
+    const int L = DENSE ? Lrt : LT;
+    const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
+    const T tauT = T(a.tau_T), tauV = T(a.tau_V);
+    const T inv_rhoV = T(1.0 / a.rho_V), inv_VS = T(1.0 / (a.rho_V + a.rho_S));
+
+    T v[PPT][LT];
+    // A: step IV with the previous S, Gamma_S
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+#pragma unroll
+        for (int l = 0; l < LT; ++l)
+            v[p][l] = (l < L) ? S.load(l, off[p]) - GS.load(l, off[p]) * inv_rhoV : T(0);
+        dct_any<T, LT, DENSE, false>(v[p], D, L);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < LT; ++k) v[p][k] = softt(v[p][k], tauV);
+        dct_any<T, LT, DENSE, true>(v[p], D, L);        // q = V W_nu^T
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int l = 0; l < QB; ++l) qlds[l * NTH + t] = v[0][l];
+
+    T* lrow = reinterpret_cast<T*>(lds);
+#pragma unroll
+    for (int g = 0; g < LT / G; ++g) {
+        // B1: spectrum rows of bands g G .. g G + G - 1 at image row y; TPR
+        // threads per row (one wavefront per row for NX = 1024)
+        {
+            const int l = g * G + r0;
+            const cx<T>* prow = Z + ((long)l * ny + y) * M;
+#pragma unroll
+            for (int j = 0; j < (NK + TPR - 1) / TPR; ++j) {
+                const int k = k0 + j * TPR;
+                if (k < NK && l < L) irfft_pre<T, NX>(prow, lds + r0 * TS, k, twl, ilog2c(NX));
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+        tile_fft<T, M, G, NTH, TS, 1, false, true, true>(lds, twl, ilog2c(NX), t);
+        __builtin_amdgcn_sched_barrier(0);
+        // B2: steps II, III, V, VI at the thread's pixels for the group's bands
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            const int l = g * G + r;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                if (l < L) {
+                    const int x = t + p * NTH;
+                    const int e = r * TS * 2 + 2 * lds_pos<true>(x >> 1) + (x & 1);
+                    const T xv = lrow[e];
+                    const T gs = GS.load(l, off[p]), zp = zP.load(l, off[p]), zt = zT.load(l, off[p]);
+                    const T q = (l < QB) ? qlds[l * NTH + t] : v[p][l];
+                    const T s = (rhoV * q + rhoS * xv) * inv_VS;
+                    const T gs2 = gs + rhoV * (q - s);
+                    const T zp2 = xv - (zp < T(0) ? -zp : T(0));
+                    const T zt2 = xv + clipt(zt, tauT);
+                    const T tt = softt(zt2, tauT);
+                    lrow[e] = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * s;
+                    X.store(l, off[p], xv);
+                    S.store(l, off[p], s);
+                    GS.store(l, off[p], gs2);
+                    zP.store(l, off[p], zp2);
+                    zT.store(l, off[p], zt2);
+                }
+            }
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+        tile_fft<T, M, G, NTH, TS, 1, false, true, false>(lds, twl, ilog2c(NX), t);
+        __builtin_amdgcn_sched_barrier(0);
+        // B3: packed spectrum rows of B_rest, over the rows read in B1
+        {
+            const int l = g * G + r0;
+            cx<T>* prow = Z + ((long)l * ny + y) * M;
+#pragma unroll
+            for (int j = 0; j < (NK + TPR - 1) / TPR; ++j) {
+                const int k = k0 + j * TPR;
+                if (k < NK && l < L) rfft_post<T, NX>(lds + r0 * TS, prow, k, twl, ilog2c(NX));
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <typename T, int NX, int LT, bool DENSE>
+static hipError_t fused_t(const FusedArrays& A, const void* D, int L, int ny, const SpecArgs& a,
+                          const void* tw, int twlog, hipStream_t s) {
+    hipLaunchKernelGGL((k_fused<T, NX, LT, DENSE>), dim3(ny), dim3(NX / fused_ppt<NX, LT>()), 0, s, A,
+                       (const T*)D, L, ny, a, (const cx<T>*)tw, twlog);
+    return hipGetLastError();
+}
+
+template <typename T, int NX>
+static hipError_t fused_l(const FusedArrays& A, const void* D, int L, int ny, const SpecArgs& a,
+                          const void* tw, int twlog, hipStream_t s) {
+    switch (L) {
+        case 4: return fused_t<T, NX, 4, false>(A, D, L, ny, a, tw, twlog, s);
+        case 8: return fused_t<T, NX, 8, false>(A, D, L, ny, a, tw, twlog, s);
+        case 16: return fused_t<T, NX, 16, false>(A, D, L, ny, a, tw, twlog, s);
+        case 32: return fused_t<T, NX, 32, false>(A, D, L, ny, a, tw, twlog, s);
+        case 64: return fused_t<T, NX, 64, false>(A, D, L, ny, a, tw, twlog, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool fused_supported(int dtype, int nx, int ny, int L) {
+    return dtype == 0 && nx >= 64 && nx <= 1024 && (L == 4 || L == 8 || L == 16 || L == 32 || L == 64) &&
+           (long long)L * ny * nx * 4 <= (1ll << 30);
+}
+
+hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
+                        const SpecArgs& a, const void* tw, int twlog, hipStream_t s) {
+    if (!fused_supported(dtype, nx, ny, L)) return hipErrorInvalidValue;
+    switch (nx) {
+        case 64: return fused_l<float, 64>(A, D, L, ny, a, tw, twlog, s);
+        case 128: return fused_l<float, 128>(A, D, L, ny, a, tw, twlog, s);
+        case 256: return fused_l<float, 256>(A, D, L, ny, a, tw, twlog, s);
+        case 512: return fused_l<float, 512>(A, D, L, ny, a, tw, twlog, s);
+        case 1024: return fused_l<float, 1024>(A, D, L, ny, a, tw, twlog, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace muffin

@@ -37,6 +37,7 @@ struct SpecArgs {
 constexpr int kNumVariants = 3;
 constexpr int kDefaultRowVariant = 1;
 constexpr int kDefaultColVariant = 1;
+constexpr int kDefaultFused = 1;      // the fused row/spectral kernel where it is built
 
 // Row pass, forward: every row of `in` (nrows rows of nx reals, type float or
 // double per in_f64) -> packed half spectrum `out` (nrows x nx/2 complex of
@@ -151,6 +152,22 @@ hipError_t launch_mse_seed(int dtype, const void* X, const void* sky, void* Xb, 
                            double* partials, int* nblocks, hipStream_t s);
 // acc[q] += the block sums of partials (GRAD_NQ per block), deterministic
 hipError_t launch_grad_accum(const double* partials, int nblocks, double* acc, hipStream_t s);
+
+// ---------------------------------------------------------------- fused row/spectral pass
+// The inverse row pass, steps II-VI and the forward row pass in one launch
+// (FP32, 64 <= nx <= 1024, L in {4, 8, 16, 32, 64}, a cube of at most 1 GiB):
+// reads the column pass's
+// spectrum Z and the state, writes X, the new state and the spectrum of
+// B_rest over Z.
+struct FusedArrays {
+    char *X, *zP, *zT, *S, *GS;
+    char* Z;
+    unsigned band_bytes;
+    int gshift;
+};
+bool fused_supported(int dtype, int nx, int ny, int L);
+hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
+                        const SpecArgs& a, const void* tw, int twlog, hipStream_t s);
 
 // Arrays of one spectral pass.  st: the state read (z_P, z_T, S, Gamma_S);
 // out: where the new state goes (= st except in a reporting pass).

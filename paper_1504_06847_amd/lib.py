@@ -82,6 +82,7 @@ SIGNATURES = [
     ("muffin_autotune", c_int, [c_void_p, c_int, POINTER(c_int)]),
     ("muffin_set_schedule", c_int, [c_void_p, POINTER(c_int)]),
     ("muffin_get_schedule", c_int, [c_void_p, POINTER(c_int)]),
+    ("muffin_fused_available", c_int, [c_void_p]),
     ("muffin_batch_workspace_bytes", c_size_t, [c_int, POINTER(MuffinShape), POINTER(MuffinParams)]),
     ("muffin_batch_setup", c_int, [POINTER(c_void_p), c_int, POINTER(MuffinShape), POINTER(MuffinParams),
                                    POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_size_t, c_void_p]),

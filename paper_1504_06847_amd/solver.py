@@ -110,13 +110,18 @@ class Solver:
 
     @property
     def schedule(self) -> tuple:
-        sch = (ctypes.c_int * 2)()
+        """(row variant, column variant, fused flag)."""
+        sch = (ctypes.c_int * 3)()
         L.check(self._lib.muffin_get_schedule(self._ctx, sch), "muffin_get_schedule", self._lib)
-        return (sch[0], sch[1])
+        return (sch[0], sch[1], sch[2])
 
     def set_schedule(self, schedule):
-        sch = (ctypes.c_int * 2)(*schedule)
+        sch = (ctypes.c_int * 3)(*schedule)
         L.check(self._lib.muffin_set_schedule(self._ctx, sch), "muffin_set_schedule", self._lib)
+
+    @property
+    def fused_available(self) -> bool:
+        return bool(self._lib.muffin_fused_available(self._ctx))
 
     def autotune(self, reps: int = 10, cache: str | None = None) -> tuple:
         """Pick the fastest FFT tile schedule for this shape.  With ``cache`` (a
@@ -127,12 +132,12 @@ class Solver:
         if key in table:
             self.set_schedule(table[key])
             return tuple(table[key])
-        sch = (ctypes.c_int * 2)()
+        sch = (ctypes.c_int * 3)()
         L.check(self._lib.muffin_autotune(self._ctx, int(reps), sch), "muffin_autotune", self._lib)
         if cache:
-            table[key] = [sch[0], sch[1]]
+            table[key] = [sch[0], sch[1], sch[2]]
             _store_cache(cache, table)
-        return (sch[0], sch[1])
+        return (sch[0], sch[1], sch[2])
 
     # -------------------------------------------------------------- params
     def _make_params(self, params):

@@ -65,6 +65,8 @@ def test_batch_is_bitwise_the_single_cube_runs(gpu_lib, dtype, graph):
     _say("batch", dtype, "graph" if graph else "launch", len(cubes), "cubes")
     b = Batch(cubes, dtype=dtype, graph=graph, params=PARAMS)
     singles = [Solver(p, d, dtype=dtype, **PARAMS) for p, d in cubes]
+    for s in singles:
+        s.set_schedule((1, 1, 0))        # the grouped launches are the three-launch pass
     # 4 shape classes of row passes (nx 16, 32, 64), ... at most 4 x 9 launches
     assert b.launches <= 4 * len(cubes)
     for k in range(6):
@@ -121,18 +123,20 @@ def test_every_schedule_agrees_to_rounding(gpu_lib, shape, dtype):
     inst = make_instance(ny, nx, L, n_points=3, n_gauss=1, n_ant=10, noise_sigma=0.005, seed=21)
     _say("schedules", shape, dtype)
     ref = Solver(inst.psf, inst.dirty, dtype=dtype, **PARAMS)
-    assert ref.schedule == (1, 1)
+    assert ref.schedule == (1, 1, 1)
+    ref.set_schedule((1, 1, 0))
     ref.iterate(3)
     xr = ref.x
     for rv in range(3):
         for cv in range(3):
-            s = Solver(inst.psf, inst.dirty, dtype=dtype, **PARAMS)
-            s.set_schedule((rv, cv))
-            s.iterate(3)
-            d = _relmax(s.x, xr)
-            _say("schedule", (rv, cv), "max rel diff", d)
-            assert d <= TOL[dtype], f"schedule {(rv, cv)}"
-            s.close()
+            for fu in range(2):
+                s = Solver(inst.psf, inst.dirty, dtype=dtype, **PARAMS)
+                s.set_schedule((rv, cv, fu))
+                s.iterate(3)
+                d = _relmax(s.x, xr)
+                _say("schedule", (rv, cv, fu), "max rel diff", d)
+                assert d <= TOL[dtype], f"schedule {(rv, cv, fu)}"
+                s.close()
 
 
 def test_autotune_keeps_results_and_state(gpu_lib, tmp_path):
@@ -148,7 +152,7 @@ def test_autotune_keeps_results_and_state(gpu_lib, tmp_path):
     cache = str(tmp_path / "sched.json")
     sch = b.autotune(reps=3, cache=cache)
     _say("autotuned schedule", sch)
-    assert all(0 <= v < 3 for v in sch) and b.schedule == tuple(sch)
+    assert 0 <= sch[0] < 3 and 0 <= sch[1] < 3 and sch[2] in (0, 1) and b.schedule == tuple(sch)
     torch.cuda.synchronize()
     assert torch.equal(b.x, x0)                     # the timing leaves X and the state alone
     assert torch.equal(b.get_state(), st0)
