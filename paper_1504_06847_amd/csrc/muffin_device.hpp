@@ -213,8 +213,29 @@ __device__ __forceinline__ void stage_twiddles(cx<T>* w, const cx<T>* __restrict
     }
 }
 
+// Element e of transform tr of an LDS tile.  ES > 0: at tr * TS + pos(e) * ES.
+// ES == 0: column tiles (transform index fastest, NTRANS per row, no
+// padding) with the rows of each window of W consecutive rows permuted,
+// W = min(32 / NTRANS, first radix): row e goes to slot (e + e / R0) mod W
+// of its window.  A wavefront then hits distinct banks both when it reads
+// consecutive rows (every stage) and when the first stage writes rows R0
+// apart.
+template <int LEN, int NTRANS>
+__device__ __forceinline__ int swz_pos(int e, int tr) {
+    constexpr int R0 = plan_radix(LEN, 0);
+    constexpr int W0 = NTRANS >= 32 ? 1 : 32 / NTRANS;
+    constexpr int W = W0 < R0 ? W0 : R0;
+    const int q = (e + (e >> ilog2c(R0))) & (W - 1);
+    return ((e & ~(W - 1)) + q) * NTRANS + tr;
+}
+template <int LEN, int NTRANS, int TS, int ES, bool PAD>
+__device__ __forceinline__ int tile_index(int tr, int e) {
+    if constexpr (ES == 0) return swz_pos<LEN, NTRANS>(e, tr);
+    else return tr * TS + lds_pos<PAD>(e) * ES;
+}
+
 // One Stockham autosort stage over a tile of NTRANS transforms of length LEN
-// in LDS.  Element e of transform t sits at buf[t * TS + lds_pos<PAD>(e) * ES].
+// in LDS.  Element e of transform t sits at buf[tile_index(t, e)].
 // Butterfly j (0 <= j < LEN/R) reads elements j + r LEN/R, multiplies input r
 // by w_{NS R}^{r (j mod NS)}, applies an R-point DFT and writes output q to
 // (j - j mod NS) R + (j mod NS) + q NS.  Work items (transform, butterfly) are
@@ -233,9 +254,8 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
         if ((ITEMS % NTH) == 0 || item < ITEMS) {
             const int tr = TFAST ? item % NTRANS : item / NB;
             const int j = TFAST ? item / NTRANS : item % NB;
-            const cx<T>* p = buf + tr * TS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i][r] = p[lds_pos<PAD>(j + r * NB) * ES];
+            for (int r = 0; r < R; ++r) v[i][r] = buf[tile_index<LEN, NTRANS, TS, ES, PAD>(tr, j + r * NB)];
             if constexpr (NS > 1) {
                 const int k = j & (NS - 1);
                 cx<T> w[R];
@@ -254,10 +274,9 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
             const int tr = TFAST ? item % NTRANS : item / NB;
             const int j = TFAST ? item / NTRANS : item % NB;
             const int k = j & (NS - 1);
-            cx<T>* p = buf + tr * TS;
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) p[lds_pos<PAD>(base + r * NS) * ES] = v[i][r];
+            for (int r = 0; r < R; ++r) buf[tile_index<LEN, NTRANS, TS, ES, PAD>(tr, base + r * NS)] = v[i][r];
         }
     }
     __syncthreads();

@@ -29,7 +29,7 @@ template <typename T, int NY> constexpr int col_tc_base() {
 }
 template <typename T, int NY> constexpr bool col_twl() { return NY * int(sizeof(cx<T>)) <= 16384; }
 template <typename T, int NY, int TC> constexpr int col_lds_bytes() {
-    return NY * (TC + 1) * int(sizeof(cx<T>)) + (col_twl<T, NY>() ? NY * int(sizeof(cx<T>)) : 0) + 64;
+    return NY * TC * int(sizeof(cx<T>)) + (col_twl<T, NY>() ? NY * int(sizeof(cx<T>)) : 0) + 64;
 }
 // columns per tile of variant V: half, all or twice the 64-KiB tile
 template <typename T, int NY, int V> constexpr int col_tc() {
@@ -197,7 +197,6 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
                                          unsigned wg, unsigned nwg, unsigned ntiles, cx<T>* lds,
                                          cx<T>* twl, double* red) {
     constexpr int NTH = col_nth<T, NY, TC>();
-    constexpr int TCP = TC + 1;          // padded row stride: spreads stride-R writes over the banks
     // the NY-point twiddle table lives in LDS when it is small: every stage
     // reads its twiddles there instead of from the global table
     constexpr bool TWL = col_twl<T, NY>();
@@ -222,7 +221,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         const int y = i / TC, c = i % TC;
         cx<T> v = {T(0), T(0)};
         if (i < NY * TC && c0 + c < M) v = data[base + (long)y * M + c0 + c];
-        if (i < NY * TC) lds[y * TCP + c] = v;
+        if (i < NY * TC) lds[swz_pos<NY, TC>(y, c)] = v;
     }
     if constexpr (TWL) {
         for (int i = t; i < NY; i += NTH) twl[i] = tw[i << (twlog - ilog2c(NY))];
@@ -250,8 +249,8 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         }
     }
     __syncthreads();
-    if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, twl, ilog2c(NY), t);
-    else tile_fft<T, NY, TC, NTH, 1, TCP, true, false, false>(lds, tw, twlog, t);
+    if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, 0, true, false, false>(lds, twl, ilog2c(NY), t);
+    else tile_fft<T, NY, TC, NTH, 1, 0, true, false, false>(lds, tw, twlog, t);
 
     if constexpr (FILT) {
         // COL_FILTER: Q^{-1} alone (no data term), the adjoint's solve
@@ -260,14 +259,14 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             const int i = t + j * NTH;
             const int y = i / TC, c = i % TC, kx = c0 + c;
             if (i >= NY * TC || kx == 0 || kx >= M) continue;
-            cx<T> v = lds[y * TCP + c];
+            cx<T> v = lds[swz_pos<NY, TC>(y, c)];
             if constexpr (PRE) {
                 if constexpr (MODE == COL_SOLVE) v = v + yfp[j];
-                lds[y * TCP + c] = v * gp[j];
+                lds[swz_pos<NY, TC>(y, c)] = v * gp[j];
             } else {
                 const long g = base + (long)y * M + kx;
                 if constexpr (MODE == COL_SOLVE) v = v + Yf[g];
-                lds[y * TCP + c] = v * (scale / (H2[g] + rhoQ));
+                lds[swz_pos<NY, TC>(y, c)] = v * (scale / (H2[g] + rhoQ));
             }
         }
         if (c0 == 0) {
@@ -275,7 +274,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             for (int ky = t; ky <= NY / 2; ky += NTH) {
                 const int kn = (NY - ky) & (NY - 1);
                 const long g1 = base + (long)ky * M, g2 = base + (long)kn * M;
-                cx<T> c1 = lds[ky * TCP], c2 = lds[kn * TCP];
+                cx<T> c1 = lds[swz_pos<NY, TC>(ky, 0)], c2 = lds[swz_pos<NY, TC>(kn, 0)];
                 if constexpr (MODE == COL_SOLVE) {
                     c1 = c1 + Yf[g1];
                     c2 = c2 + Yf[g2];
@@ -286,13 +285,13 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
                 cx<T> B = {T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x)};
                 A = A * g0;
                 B = B * gm;
-                lds[ky * TCP] = A + mul_i(B);
-                if (kn != ky) lds[kn * TCP] = conj(A) + mul_i(conj(B));
+                lds[swz_pos<NY, TC>(ky, 0)] = A + mul_i(B);
+                if (kn != ky) lds[swz_pos<NY, TC>(kn, 0)] = conj(A) + mul_i(conj(B));
             }
         }
         __syncthreads();
-        if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, TCP, true, false, true>(lds, twl, ilog2c(NY), t);
-        else tile_fft<T, NY, TC, NTH, 1, TCP, true, false, true>(lds, tw, twlog, t);
+        if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, 0, true, false, true>(lds, twl, ilog2c(NY), t);
+        else tile_fft<T, NY, TC, NTH, 1, 0, true, false, true>(lds, tw, twlog, t);
     }
 
     if constexpr (MODE == COL_SOLVE || MODE == COL_FWD || MODE == COL_FILTER) {
@@ -300,7 +299,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         for (int j = 0; j < NIT; ++j) {
             const int i = t + j * NTH;
             const int y = i / TC, c = i % TC;
-            if (i < NY * TC && c0 + c < M) data[base + (long)y * M + c0 + c] = lds[y * TCP + c];
+            if (i < NY * TC && c0 + c < M) data[base + (long)y * M + c0 + c] = lds[swz_pos<NY, TC>(y, c)];
         }
     }
 
@@ -311,7 +310,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             const int y = i / TC, c = i % TC, kx = c0 + c;
             if (kx == 0 || kx >= M) continue;
             const long g = base + (long)y * M + kx;
-            const cx<T> z = lds[y * TCP + c], f = Yf[g];
+            const cx<T> z = lds[swz_pos<NY, TC>(y, c)], f = Yf[g];
             const double zz = double(z.x) * z.x + double(z.y) * z.y;
             const double cr = double(f.x) * z.x + double(f.y) * z.y;
             acc += 2.0 * (double(H2[g]) * zz - 2.0 * cr);
@@ -320,7 +319,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             for (int ky = t; ky <= NY / 2; ky += NTH) {
                 const int kn = (NY - ky) & (NY - 1);
                 const long g1 = base + (long)ky * M, g2 = base + (long)kn * M;
-                const cx<T> c1 = lds[ky * TCP], c2 = lds[kn * TCP];
+                const cx<T> c1 = lds[swz_pos<NY, TC>(ky, 0)], c2 = lds[swz_pos<NY, TC>(kn, 0)];
                 const cx<T> f1 = Yf[g1], f2 = Yf[g2];
                 const cx<T> A = {T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)};
                 const cx<T> B = {T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x)};
@@ -346,7 +345,7 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
       const T* __restrict__ H2nyq, T rhoQ, T scale, int M, const cx<T>* __restrict__ tw,
       int twlog, double* __restrict__ partials, double inv_n) {
     constexpr int TC = col_tc<T, NY, V>();
-    __shared__ cx<T> lds[NY * (TC + 1)];
+    __shared__ cx<T> lds[NY * TC];
     __shared__ cx<T> twl[col_twl<T, NY>() ? NY : 1];
     __shared__ double red[col_nth<T, NY, TC>() / 64];
     col_body<T, NY, MODE, TC>(data, Yf, H2, H2nyq, rhoQ, scale, M, tw, twlog, partials, inv_n,
@@ -360,7 +359,7 @@ template <typename T, int NY, int V>
 __global__ void __launch_bounds__((col_nth<T, NY, col_tc<T, NY, V>()>()))
 k_col_group(const ColDesc* __restrict__ d, int n) {
     constexpr int TC = col_tc<T, NY, V>();
-    __shared__ cx<T> lds[NY * (TC + 1)];
+    __shared__ cx<T> lds[NY * TC];
     __shared__ cx<T> twl[col_twl<T, NY>() ? NY : 1];
     __shared__ double red[col_nth<T, NY, TC>() / 64];
     const int j = group_find(d, n, blockIdx.x);
