@@ -252,8 +252,9 @@ int muffin_batch_iterate(muffin_batch* batch, int n_iter);
    changes before its next pass.  NULL if i is out of range. */
 muffin_ctx* muffin_batch_cube(muffin_batch* batch, int i);
 
-/* Time the variants of each grouped transform launch (as muffin_autotune,
-   per shape class) and keep the fastest.  Synchronises the stream. */
+/* Autotune every cube's own schedule (muffin_autotune: which pass form the
+   cube joins), then time the variants of each grouped transform launch per
+   shape class and keep the fastest.  Synchronises the stream. */
 int muffin_batch_autotune(muffin_batch* batch, int reps);
 
 /* Replay each batch pass from one HIP graph (as muffin_set_graph). */

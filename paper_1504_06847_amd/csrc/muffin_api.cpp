@@ -428,6 +428,8 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
 
 namespace muffin {
 int refresh_brest(muffin_ctx* c) { return recompute_brest(c); }
+int ensure_z(muffin_ctx* c) { return row_forward(c); }
+bool fused_pass(const muffin_ctx* c) { return use_fused(c); }
 }  // namespace muffin
 
 extern "C" {

@@ -20,19 +20,20 @@ using namespace muffin;
 
 namespace {
 
-enum Kind { K_ROWF = 0, K_COL = 1, K_ROWI = 2, K_SPEC = 3, K_NUM = 4 };
+enum Kind { K_ROWF = 0, K_COL = 1, K_ROWI = 2, K_SPEC = 3, K_FUSED = 4, K_NUM = 5 };
 
 constexpr size_t kDescSlot = 256;     // device bytes reserved per (pass, cube) descriptor
 static_assert(sizeof(RowDesc) <= kDescSlot && sizeof(ColDesc) <= kDescSlot &&
-                  sizeof(SpecDesc) <= kDescSlot, "descriptor slot too small");
+                  sizeof(SpecDesc) <= kDescSlot && sizeof(FusedDesc) <= kDescSlot,
+              "descriptor slot too small");
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 size_t desc_region_bytes(int n) { return align_up(size_t(K_NUM) * n * kDescSlot); }
 
 struct Class {
     int kind;
-    int key;                 // nx (row passes), ny (column pass), L (spectral pass)
-    int nth;                 // spectral block size
+    int key;                 // nx (row and fused passes), ny (column pass), L (spectral pass)
+    int nth;                 // spectral block size; L of a fused class
     int variant;             // tile schedule (transform passes)
     std::vector<int> cubes;
     int nblocks;             // grid of the grouped launch
@@ -85,6 +86,7 @@ int cube_blocks(const muffin_batch* b, const Class& k, muffin_ctx* c, int varian
         case K_ROWF:
         case K_ROWI: return row_blocks(s.L * s.ny, s.nx, variant);
         case K_COL: return col_blocks(b->dtype, s.L, s.ny, s.nx, variant);
+        case K_FUSED: return s.ny;
         default: return int((long(s.ny) * s.nx) / k.nth);
     }
 }
@@ -92,6 +94,7 @@ int cube_blocks(const muffin_batch* b, const Class& k, muffin_ctx* c, int varian
 // a class's descriptors are a packed array of its kind's struct, starting
 // at byte slot0 * kDescSlot of the region
 size_t desc_size(int kind) {
+    if (kind == K_FUSED) return sizeof(FusedDesc);
     return kind == K_COL ? sizeof(ColDesc) : (kind == K_SPEC ? sizeof(SpecDesc) : sizeof(RowDesc));
 }
 
@@ -122,6 +125,25 @@ void fill_desc(const muffin_batch* b, const Class& k, muffin_ctx* c, int first, 
         d.L = s.L;
         d.M = s.nx / 2;
         d.twlog = c->twlog;
+        d.first = first;
+        d.nblk = nblk;
+        std::memcpy(slot, &d, sizeof(d));
+    } else if (k.kind == K_FUSED) {
+        FusedDesc d{};
+        d.A.X = P(c, c->lay.x);
+        d.A.zP = (char*)st(c, ST_ZP);
+        d.A.zT = (char*)st(c, ST_ZT);
+        d.A.S = (char*)st(c, ST_S);
+        d.A.GS = (char*)st(c, ST_GS);
+        d.A.Z = P(c, c->lay.z);
+        d.A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
+        d.A.gshift = 0;
+        d.D = P(c, c->lay.dctm);
+        d.a = spec_args(c->params);
+        d.tw = P(c, c->lay.tw);
+        d.twlog = c->twlog;
+        d.L = s.L;
+        d.ny = s.ny;
         d.first = first;
         d.nblk = nblk;
         std::memcpy(slot, &d, sizeof(d));
@@ -168,7 +190,35 @@ int upload(muffin_batch* b) {
     return MUFFIN_OK;
 }
 
+// class membership: a cube whose schedule runs the fused pass (where built)
+// joins a column class and a fused class, the others the four classes of
+// the three-launch pass; tile schedules chosen earlier are kept
+void build_classes(muffin_batch* b) {
+    std::vector<Class> old;
+    old.swap(b->classes);
+    for (int i = 0; i < b->n; ++i) {
+        const muffin_shape& s = b->cubes[i]->shape;
+        if (fused_pass(b->cubes[i])) {
+            b->classes[class_of(b, K_COL, s.ny, 0)].cubes.push_back(i);
+            b->classes[class_of(b, K_FUSED, s.nx, s.L)].cubes.push_back(i);
+        } else {
+            b->classes[class_of(b, K_ROWF, s.nx, 0)].cubes.push_back(i);
+            b->classes[class_of(b, K_COL, s.ny, 0)].cubes.push_back(i);
+            b->classes[class_of(b, K_ROWI, s.nx, 0)].cubes.push_back(i);
+            b->classes[class_of(b, K_SPEC, s.L, spectral_block_threads(long(s.ny) * s.nx))].cubes.push_back(i);
+        }
+    }
+    size_t slot = 0;
+    for (Class& k : b->classes) {
+        k.slot0 = slot;
+        slot += k.cubes.size();
+        for (const Class& o : old)
+            if (o.kind == k.kind && o.key == k.key && o.nth == k.nth) k.variant = o.variant;
+    }
+}
+
 int rebuild(muffin_batch* b) {
+    build_classes(b);
     for (Class& k : b->classes) layout_class(b, k, k.variant, nullptr);
     if (int rc = upload(b)) return rc;
     for (int i = 0; i < b->n; ++i) b->seen[i] = b->cubes[i]->version;
@@ -191,6 +241,7 @@ hipError_t launch_class(const muffin_batch* b, const Class& k, int variant, hipS
         case K_ROWF: return launch_row_fwd_group(b->dtype, k.key, variant, (const RowDesc*)(b->desc + off), n, k.nblocks, s);
         case K_ROWI: return launch_row_inv_group(b->dtype, k.key, variant, (const RowDesc*)(b->desc + off), n, k.nblocks, s);
         case K_COL: return launch_col_group(b->dtype, k.key, variant, (const ColDesc*)(b->desc + off), n, k.nblocks, s);
+        case K_FUSED: return launch_fused_group(b->dtype, k.key, k.nth, (const FusedDesc*)(b->desc + off), n, k.nblocks, s);
         default: return launch_spectral_group(b->dtype, k.key, k.nth, (const SpecDesc*)(b->desc + off), n, k.nblocks, s);
     }
 }
@@ -244,6 +295,76 @@ int check_shapes(int n, const muffin_shape* shapes, const muffin_params* params)
         }
     }
     return MUFFIN_OK;
+}
+
+// Grouped launches of the three-launch pass fill the GPU differently from
+// the fused pass each cube picked on its own: time `reps` real batch passes
+// with the cubes' own choices and with every cube on the three-launch pass,
+// each from the same saved states (restored afterwards), and keep the faster.
+int choose_pass_form(muffin_batch* b, int reps) {
+    std::vector<void*> saved(b->n, nullptr);
+    std::vector<int> own(b->n);
+    int rc = MUFFIN_OK;
+    auto cleanup = [&]() {
+        for (void* p : saved)
+            if (p) hipFree(p);
+    };
+    for (int i = 0; i < b->n && rc == MUFFIN_OK; ++i) {
+        muffin_ctx* c = b->cubes[i];
+        own[i] = c->fused;
+        if (hipMalloc(&saved[i], muffin_state_bytes(c)) != hipSuccess) {
+            saved[i] = nullptr;
+            set_error("batch autotune: no device memory to save cube %d's state", i);
+            rc = MUFFIN_EDEVICE;
+        } else {
+            rc = muffin_get_state(c, saved[i]);
+        }
+    }
+    auto set_form = [&](bool three) -> int {
+        for (int i = 0; i < b->n; ++i) {
+            muffin_ctx* c = b->cubes[i];
+            const int sch[3] = {c->row_v, c->col_v, three ? 0 : own[i]};
+            if (int r = muffin_set_schedule(c, sch)) return r;
+        }
+        return MUFFIN_OK;
+    };
+    auto restore = [&]() -> int {
+        for (int i = 0; i < b->n; ++i)
+            if (int r = muffin_set_state(b->cubes[i], saved[i])) return r;
+        return MUFFIN_OK;
+    };
+    double t[2] = {0.0, 0.0};
+    for (int form = 0; form < 2 && rc == MUFFIN_OK; ++form) {
+        if ((rc = set_form(form == 1)) != MUFFIN_OK || (rc = restore()) != MUFFIN_OK) break;
+        if ((rc = muffin_batch_iterate(b, 1)) != MUFFIN_OK) break;       // warm-up pass
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            set_error("batch autotune: event creation failed");
+            rc = MUFFIN_EDEVICE;
+            break;
+        }
+        hipError_t e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess && (rc = muffin_batch_iterate(b, reps)) != MUFFIN_OK) e = hipSuccess;
+        if (rc == MUFFIN_OK && e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (rc == MUFFIN_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (rc == MUFFIN_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (rc == MUFFIN_OK && e != hipSuccess) {
+            set_error("batch autotune: %s", hipGetErrorString(e));
+            rc = MUFFIN_EDEVICE;
+        }
+        t[form] = ms;
+    }
+    if (rc == MUFFIN_OK) rc = set_form(t[1] < t[0]);
+    if (rc == MUFFIN_OK) rc = restore();
+    if (rc == MUFFIN_OK && hipStreamSynchronize(b->stream) != hipSuccess) {
+        set_error("batch autotune: stream synchronisation failed");
+        rc = MUFFIN_EDEVICE;
+    }
+    cleanup();
+    return rc;
 }
 
 }  // namespace
@@ -300,18 +421,6 @@ int muffin_batch_setup(muffin_batch** out, int n, const muffin_shape* shapes, co
         off += align_up(wi);
     }
     b->desc = b->ws + off;
-    for (int i = 0; i < n; ++i) {
-        const muffin_shape& s = shapes[i];
-        b->classes[class_of(b, K_ROWF, s.nx, 0)].cubes.push_back(i);
-        b->classes[class_of(b, K_COL, s.ny, 0)].cubes.push_back(i);
-        b->classes[class_of(b, K_ROWI, s.nx, 0)].cubes.push_back(i);
-        b->classes[class_of(b, K_SPEC, s.L, spectral_block_threads(long(s.ny) * s.nx))].cubes.push_back(i);
-    }
-    size_t slot = 0;
-    for (Class& k : b->classes) {
-        k.slot0 = slot;
-        slot += k.cubes.size();
-    }
     b->host_desc.assign(desc_region_bytes(n), 0);
     b->seen.assign(n, 0);
     if (int rc = rebuild(b)) {
@@ -326,11 +435,15 @@ int muffin_batch_iterate(muffin_batch* b, int n_iter) {
     if (int rc = check_batch(b)) return rc;
     if (n_iter < 0) { set_error("n_iter = %d < 0", n_iter); return MUFFIN_EINVAL; }
     if (n_iter == 0) return MUFFIN_OK;
-    // the grouped passes start from B_rest: a cube whose last pass was a
-    // fused single-cube pass has it only as row spectra
-    for (muffin_ctx* c : b->cubes)
-        if (c->zvalid)
+    // a fused cube's pass starts from Z (the row spectra of B_rest), the
+    // others' from B_rest (rebuilt from the state after fused passes)
+    for (muffin_ctx* c : b->cubes) {
+        if (fused_pass(c)) {
+            if (int rc = ensure_z(c)) return rc;
+        } else if (c->zvalid) {
             if (int rc = refresh_brest(c)) return rc;
+        }
+    }
     if (stale(b))
         if (int rc = rebuild(b)) return rc;
     for (int it = 0; it < n_iter; ++it) {
@@ -341,7 +454,10 @@ int muffin_batch_iterate(muffin_batch* b, int n_iter) {
         } else if (int rc = pass_kernels(b, b->stream)) {
             return rc;
         }
-        for (muffin_ctx* c : b->cubes) c->iters++;
+        for (muffin_ctx* c : b->cubes) {
+            c->iters++;
+            c->zvalid = fused_pass(c) ? 1 : 0;
+        }
     }
     return MUFFIN_OK;
 }
@@ -354,6 +470,10 @@ muffin_ctx* muffin_batch_cube(muffin_batch* b, int i) {
 int muffin_batch_autotune(muffin_batch* b, int reps) {
     if (int rc = check_batch(b)) return rc;
     if (reps < 1) { set_error("reps = %d < 1", reps); return MUFFIN_EINVAL; }
+    // each cube's own schedule first (which pass form it joins), then the
+    // tile schedule of every grouped transform launch
+    for (muffin_ctx* c : b->cubes)
+        if (int rc = muffin_autotune(c, reps, nullptr)) return rc;
     if (stale(b))
         if (int rc = rebuild(b)) return rc;
     hipEvent_t e0, e1;
@@ -361,7 +481,7 @@ int muffin_batch_autotune(muffin_batch* b, int reps) {
     HIP_TRY(hipEventCreate(&e1));
     int rc = MUFFIN_OK;
     for (Class& k : b->classes) {
-        if (k.kind == K_SPEC) continue;
+        if (k.kind == K_SPEC || k.kind == K_FUSED) continue;
         // the inverse row pass writes each cube's unused second state set
         std::vector<void*> scratch;
         for (int i : k.cubes) scratch.push_back(st_alt(b->cubes[i], 0));
@@ -392,8 +512,13 @@ int muffin_batch_autotune(muffin_batch* b, int reps) {
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    const int rc2 = rebuild(b);
-    return rc ? rc : rc2;
+    if (rc) return rc;
+    // the timing used Z as scratch: a fused cube's pass restarts from B_rest
+    for (muffin_ctx* c : b->cubes)
+        if (fused_pass(c))
+            if (int r = refresh_brest(c)) return r;
+    if (int r = rebuild(b)) return r;
+    return choose_pass_form(b, reps);
 }
 
 int muffin_batch_set_graph(muffin_batch* b, int enable) {

@@ -75,8 +75,11 @@ inline double rho_Q(const muffin_params& p) {
 // scale of the unnormalised packed 2-D transform pair, folded into the filter
 inline double fft_scale(const muffin_shape& s) { return 1.0 / (double(s.nx / 2) * double(s.ny)); }
 
-// recompute B_rest from the stored state (muffin_api.cpp)
+// recompute B_rest from the stored state; make Z hold the row spectra of
+// B_rest; whether the context's passes are fused passes (muffin_api.cpp)
 int refresh_brest(muffin_ctx* c);
+int ensure_z(muffin_ctx* c);
+bool fused_pass(const muffin_ctx* c);
 
 inline int check_ctx(const muffin_ctx* c) {
     if (!c) { set_error("context is NULL"); return MUFFIN_EINVAL; }

@@ -27,26 +27,36 @@ namespace muffin {
 // pixel's band vector next to the row transforms of a full-size one.
 template <int NX, int LT> constexpr int fused_ppt() { return 1; }
 
+template <int LT> constexpr int fused_g() { return LT < 16 ? LT : (LT >= 64 ? 8 : 16); }
+// with 64 bands, q of the first fused_qb bands waits in LDS: the band vector
+// of the others plus the row transforms fill the registers
+template <int LT> constexpr int fused_qb() { return LT >= 64 ? 24 : 0; }
+
+template <typename T, int NX, int LT> struct FusedLds {
+    static constexpr int NTH = NX / fused_ppt<NX, LT>();
+    cx<T> rows[fused_g<LT>() * lds_len<true>(NX / 2)];   // G spectrum / image rows
+    cx<T> twl[NX];                                        // w_NX^i, i < NX
+    T q[fused_qb<LT>() > 0 ? fused_qb<LT>() * NTH : 1];
+};
+
+// One image row y of every band (see the head of this file).
 template <typename T, int NX, int LT, bool DENSE>
-__global__ void __launch_bounds__((NX / fused_ppt<NX, LT>()))
-k_fused(FusedArrays A, const T* __restrict__ D, int Lrt, int ny, SpecArgs a,
-        const cx<T>* __restrict__ tw, int twlog) {
+__device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __restrict__ D, int Lrt, int ny,
+                                           const SpecArgs& a, const cx<T>* __restrict__ tw, int twlog, int y,
+                                           FusedLds<T, NX, LT>& sh) {
     constexpr int PPT = fused_ppt<NX, LT>();
     constexpr int NTH = NX / PPT;
     constexpr int M = NX / 2;
-    constexpr int G = LT < 16 ? LT : (LT >= 64 ? 8 : 16);   // bands per LDS row group
+    constexpr int G = fused_g<LT>();                // bands per LDS row group
     constexpr int TS = lds_len<true>(M);
     constexpr int NK = M / 2 + 1;
     constexpr int TPR = NTH / G;                    // threads per LDS row in B1, B3
     static_assert(NTH % G == 0, "row split");
-    __shared__ cx<T> lds[G * TS];
-    __shared__ cx<T> twl[NX];                       // w_NX^i, i < NX
-    // with 64 bands, q of the first QB bands waits in LDS: the band vector
-    // of the others plus the row transforms fill the registers
-    constexpr int QB = LT >= 64 ? 24 : 0;
-    __shared__ T qlds[QB > 0 ? QB * NTH : 1];
+    cx<T>* lds = sh.rows;
+    cx<T>* twl = sh.twl;
+    constexpr int QB = fused_qb<LT>();
+    T* qlds = sh.q;
     const int t = threadIdx.x;
-    const int y = blockIdx.x;
     const int r0 = t / TPR, k0 = t % TPR;
     for (int i = t; i < NX; i += NTH) twl[i] = tw[i << (twlog - ilog2c(NX))];
     __syncthreads();
@@ -144,6 +154,28 @@ k_fused(FusedArrays A, const T* __restrict__ D, int Lrt, int ny, SpecArgs a,
 }
 
 template <typename T, int NX, int LT, bool DENSE>
+__global__ void __launch_bounds__((NX / fused_ppt<NX, LT>()))
+k_fused(FusedArrays A, const T* __restrict__ D, int Lrt, int ny, SpecArgs a,
+        const cx<T>* __restrict__ tw, int twlog) {
+    __shared__ FusedLds<T, NX, LT> sh;
+    fused_body<T, NX, LT, DENSE>(A, D, Lrt, ny, a, tw, twlog, blockIdx.x, sh);
+}
+
+// the fused pass over the rows of several cubes of one row length and band
+// count (one block per image row of each cube)
+template <typename T, int NX, int LT, bool DENSE>
+__global__ void __launch_bounds__((NX / fused_ppt<NX, LT>()))
+k_fused_group(const FusedDesc* __restrict__ d, int n) {
+    __shared__ FusedLds<T, NX, LT> sh;
+    int j = 0;
+    while (j + 1 < n && blockIdx.x >= (unsigned)d[j + 1].first) ++j;
+    const unsigned y = blockIdx.x - (unsigned)d[j].first;
+    if (blockIdx.x < (unsigned)d[j].first || y >= (unsigned)d[j].nblk) return;
+    fused_body<T, NX, LT, DENSE>(d[j].A, (const T*)d[j].D, d[j].L, d[j].ny, d[j].a, (const cx<T>*)d[j].tw,
+                                 d[j].twlog, (int)y, sh);
+}
+
+template <typename T, int NX, int LT, bool DENSE>
 static hipError_t fused_t(const FusedArrays& A, const void* D, int L, int ny, const SpecArgs& a,
                           const void* tw, int twlog, hipStream_t s) {
     hipLaunchKernelGGL((k_fused<T, NX, LT, DENSE>), dim3(ny), dim3(NX / fused_ppt<NX, LT>()), 0, s, A,
@@ -178,6 +210,39 @@ hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, i
         case 256: return fused_l<float, 256>(A, D, L, ny, a, tw, twlog, s);
         case 512: return fused_l<float, 512>(A, D, L, ny, a, tw, twlog, s);
         case 1024: return fused_l<float, 1024>(A, D, L, ny, a, tw, twlog, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int NX, int LT>
+static hipError_t fused_group_t(const FusedDesc* d, int n, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_fused_group<T, NX, LT, false>), dim3(nblocks), dim3(NX / fused_ppt<NX, LT>()), 0, s,
+                       d, n);
+    return hipGetLastError();
+}
+
+template <int NX>
+static hipError_t fused_group_l(int L, const FusedDesc* d, int n, int nblocks, hipStream_t s) {
+    switch (L) {
+        case 4: return fused_group_t<float, NX, 4>(d, n, nblocks, s);
+        case 8: return fused_group_t<float, NX, 8>(d, n, nblocks, s);
+        case 16: return fused_group_t<float, NX, 16>(d, n, nblocks, s);
+        case 32: return fused_group_t<float, NX, 32>(d, n, nblocks, s);
+        case 64: return fused_group_t<float, NX, 64>(d, n, nblocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fused_group(int dtype, int nx, int L, const FusedDesc* d, int n, int nblocks,
+                              hipStream_t s) {
+    if (n <= 0 || nblocks <= 0) return hipSuccess;
+    if (dtype != 0) return hipErrorInvalidValue;
+    switch (nx) {
+        case 64: return fused_group_l<64>(L, d, n, nblocks, s);
+        case 128: return fused_group_l<128>(L, d, n, nblocks, s);
+        case 256: return fused_group_l<256>(L, d, n, nblocks, s);
+        case 512: return fused_group_l<512>(L, d, n, nblocks, s);
+        case 1024: return fused_group_l<1024>(L, d, n, nblocks, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -165,7 +165,17 @@ struct FusedArrays {
     unsigned band_bytes;
     int gshift;
 };
+struct FusedDesc {                   // one cube of a grouped fused launch
+    FusedArrays A;
+    const void* D;
+    SpecArgs a;
+    const void* tw;
+    int twlog, L, ny, first, nblk, pad;
+};
+static_assert(sizeof(FusedArrays) == 56 && sizeof(FusedDesc) == 144, "descriptor layout");
 bool fused_supported(int dtype, int nx, int ny, int L);
+hipError_t launch_fused_group(int dtype, int nx, int L, const FusedDesc* d, int n, int nblocks,
+                              hipStream_t s);
 hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
                         const SpecArgs& a, const void* tw, int twlog, hipStream_t s);
 

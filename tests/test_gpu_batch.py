@@ -65,8 +65,11 @@ def test_batch_is_bitwise_the_single_cube_runs(gpu_lib, dtype, graph):
     _say("batch", dtype, "graph" if graph else "launch", len(cubes), "cubes")
     b = Batch(cubes, dtype=dtype, graph=graph, params=PARAMS)
     singles = [Solver(p, d, dtype=dtype, **PARAMS) for p, d in cubes]
-    for s in singles:
-        s.set_schedule((1, 1, 0))        # the grouped launches are the three-launch pass
+    # cubes with the fused pass built (FP32, 64 <= nx <= 1024, L in 4..64)
+    # run it in the batch too; the others the three-launch pass
+    if dtype == torch.float32:
+        assert [s.fused_available for s in singles] == [False, False, True, True, False, False, False,
+                                                       False, True]
     # 4 shape classes of row passes (nx 16, 32, 64), ... at most 4 x 9 launches
     assert b.launches <= 4 * len(cubes)
     for k in range(6):
