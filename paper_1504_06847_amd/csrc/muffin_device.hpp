@@ -292,6 +292,88 @@ __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__
 
 // In-place FFT of NTRANS transforms of length LEN held in LDS (natural order
 // in and out, unnormalised).  Must be called by all NTH threads of the block.
+// Stages S .. E-1 of the plan.
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV, int S, int E>
+__device__ __forceinline__ void fft_stage_range(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
+    if constexpr (S < E) {
+        fft_stage<T, LEN, plan_radix(LEN, S), plan_ns(LEN, S), NTRANS, NTH, TS, ES, TFAST, PAD, INV>(buf, tw, twlog, t);
+        fft_stage_range<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, S + 1, E>(buf, tw, twlog, t);
+    }
+}
+
+// The first stage (no twiddles) with its input read from global memory:
+// element e of transform tr at src[e * ld + tr], zero for tr >= ntr.  Its
+// output goes to the LDS tile; ends with a barrier.
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
+__device__ __forceinline__ void fft_first_stage_global(cx<T>* buf, const cx<T>* __restrict__ src, long ld,
+                                                       int ntr, int t) {
+    constexpr int R = plan_radix(LEN, 0);
+    constexpr int NB = LEN / R;
+    constexpr int ITEMS = NB * NTRANS;
+    constexpr int IPT = (ITEMS + NTH - 1) / NTH;
+    cx<T> v[IPT][R];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int item = t + i * NTH;
+        if ((ITEMS % NTH) == 0 || item < ITEMS) {
+            const int tr = TFAST ? item % NTRANS : item / NB;
+            const int j = TFAST ? item / NTRANS : item % NB;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[i][r] = tr < ntr ? src[(long)(j + r * NB) * ld + tr] : cx<T>{T(0), T(0)};
+            dftR<T, R, INV>(v[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int item = t + i * NTH;
+        if ((ITEMS % NTH) == 0 || item < ITEMS) {
+            const int tr = TFAST ? item % NTRANS : item / NB;
+            const int j = TFAST ? item / NTRANS : item % NB;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[tile_index<LEN, NTRANS, TS, ES, PAD>(tr, j * R + r)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// The last stage with its output written to global memory: element e of
+// transform tr to dst[e * ld + tr] for tr < ntr.  No barrier at the end.
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
+__device__ __forceinline__ void fft_last_stage_global(const cx<T>* buf, const cx<T>* __restrict__ tw, int twlog,
+                                                      cx<T>* dst, long ld, int ntr, int t) {
+    constexpr int S = plan_nstages(LEN) - 1;
+    constexpr int R = plan_radix(LEN, S), NS = plan_ns(LEN, S);
+    constexpr int NB = LEN / R;
+    constexpr int ITEMS = NB * NTRANS;
+    constexpr int IPT = (ITEMS + NTH - 1) / NTH;
+    constexpr int LOGNR = ilog2c(NS * R);
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int item = t + i * NTH;
+        if ((ITEMS % NTH) == 0 || item < ITEMS) {
+            const int tr = TFAST ? item % NTRANS : item / NB;
+            const int j = TFAST ? item / NTRANS : item % NB;
+            cx<T> v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = buf[tile_index<LEN, NTRANS, TS, ES, PAD>(tr, j + r * NB)];
+            const int k = j & (NS - 1);
+            if constexpr (NS > 1) {
+                cx<T> w[R];
+                stage_twiddles<T, R>(w, tw, k, twlog - LOGNR);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
+            }
+            dftR<T, R, INV>(v);
+            const int base = (j - k) * R + k;
+            if (tr < ntr) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[(long)(base + r * NS) * ld + tr] = v[r];
+            }
+        }
+    }
+}
+
 template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
 __device__ __forceinline__ void tile_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
     fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, 0>(buf, tw, twlog, t);

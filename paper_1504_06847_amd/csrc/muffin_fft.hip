@@ -215,14 +215,8 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
     const int c0 = int(wg % ntiles) * TC;
     const long base = (long)band * NY * M;
     constexpr int NIT = (NY * TC + NTH - 1) / NTH;
-#pragma unroll
-    for (int j = 0; j < NIT; ++j) {
-        const int i = t + j * NTH;
-        const int y = i / TC, c = i % TC;
-        cx<T> v = {T(0), T(0)};
-        if (i < NY * TC && c0 + c < M) v = data[base + (long)y * M + c0 + c];
-        if (i < NY * TC) lds[swz_pos<NY, TC>(y, c)] = v;
-    }
+    constexpr int NST = plan_nstages(NY);
+    const int ntr = M - c0 < TC ? M - c0 : TC;      // columns of this tile inside the spectrum
     if constexpr (TWL) {
         for (int i = t; i < NY; i += NTH) twl[i] = tw[i << (twlog - ilog2c(NY))];
     }
@@ -248,9 +242,11 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             }
         }
     }
-    __syncthreads();
-    if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, 0, true, false, false>(lds, twl, ilog2c(NY), t);
-    else tile_fft<T, NY, TC, NTH, 1, 0, true, false, false>(lds, tw, twlog, t);
+    // forward FFT along y; its first stage reads the tile straight from Z
+    // (the barrier that ends it also publishes the twiddle table)
+    fft_first_stage_global<T, NY, TC, NTH, 1, 0, true, false, false>(lds, data + base + c0, M, ntr, t);
+    if constexpr (TWL) fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, false, 1, NST>(lds, twl, ilog2c(NY), t);
+    else fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, false, 1, NST>(lds, tw, twlog, t);
 
     if constexpr (FILT) {
         // COL_FILTER: Q^{-1} alone (no data term), the adjoint's solve
@@ -290,11 +286,19 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             }
         }
         __syncthreads();
-        if constexpr (TWL) tile_fft<T, NY, TC, NTH, 1, 0, true, false, true>(lds, twl, ilog2c(NY), t);
-        else tile_fft<T, NY, TC, NTH, 1, 0, true, false, true>(lds, tw, twlog, t);
+        // inverse FFT along y; its last stage writes the tile straight to Z
+        if constexpr (TWL) {
+            fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1>(lds, twl, ilog2c(NY), t);
+            fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true>(lds, twl, ilog2c(NY), data + base + c0,
+                                                                          M, ntr, t);
+        } else {
+            fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1>(lds, tw, twlog, t);
+            fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true>(lds, tw, twlog, data + base + c0, M,
+                                                                          ntr, t);
+        }
     }
 
-    if constexpr (MODE == COL_SOLVE || MODE == COL_FWD || MODE == COL_FILTER) {
+    if constexpr (MODE == COL_FWD) {
 #pragma unroll
         for (int j = 0; j < NIT; ++j) {
             const int i = t + j * NTH;
