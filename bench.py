@@ -125,6 +125,7 @@ def run_gpu(inst, params, dtype, steps, warmup, profile_iters, graph=False):
     kw = dict(mu_eps=params.mu_eps, mu_s=params.mu_s, mu_nu=params.mu_nu, rho_P=params.rho_P,
               rho_T=params.rho_T, rho_V=params.rho_V, rho_S=params.rho_S)
     s = Solver(inst.psf, inst.dirty, dtype=dtype, graph=graph, **kw)
+    schedule = s.autotune(reps=5)             # tile schedules and pass form for this shape
     s.iterate(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -136,7 +137,7 @@ def run_gpu(inst, params, dtype, steps, warmup, profile_iters, graph=False):
     ms = ev0.elapsed_time(ev1)
     prof = s.profile(profile_iters) if profile_iters > 0 else {}
     s.close()
-    return ms, prof
+    return ms, prof, schedule
 
 
 def batch_instances():
@@ -238,8 +239,8 @@ def main(argv=None):
     inst = cfg.make()
     V = cfg.voxels
     _log(f"bench: FP32 {a.warmup} warmup + {a.steps} timed passes")
-    ms32, prof32 = run_gpu(inst, cfg.params, torch.float32, a.steps, a.warmup, a.profile_iters,
-                           graph=a.graph)
+    ms32, prof32, sched32 = run_gpu(inst, cfg.params, torch.float32, a.steps, a.warmup, a.profile_iters,
+                                    graph=a.graph)
     value = V * a.steps / (ms32 / 1e3)
     kernels = {}
     for name, kms in prof32.items():
@@ -258,9 +259,9 @@ def main(argv=None):
     fp64 = None
     if a.fp64_steps > 0:
         _log(f"bench: FP64 {a.fp64_steps} timed passes")
-        ms64, prof64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5, graph=a.graph)
+        ms64, prof64, sched64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5, graph=a.graph)
         fp64 = dict(value=V * a.fp64_steps / (ms64 / 1e3), ms_per_step=round(ms64 / a.fp64_steps, 4),
-                    kernels_ms={k: round(v, 5) for k, v in prof64.items()})
+                    kernels_ms={k: round(v, 5) for k, v in prof64.items()}, schedule=list(sched64))
     batch = None
     if not a.no_batch:
         _log(f"bench: 16-cube batch, {a.batch_steps} passes per form")
@@ -285,7 +286,7 @@ def main(argv=None):
         "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} pixels x {cfg.L} bands, FP32 ADMM "
                                f"pass (Dirac W_s, DCT-II W_nu), rho=1, mu_s=mu_nu=0.02, mu_eps=1e-3",
                    "nx": cfg.nx, "ny": cfg.ny, "L": cfg.L, "voxels": V,
-                   "parallelism": "1 GPU", "graph": bool(a.graph)},
+                   "parallelism": "1 GPU", "graph": bool(a.graph), "schedule": list(sched32)},
         "roofline": roof,
         # one pass at this rate against the HBM peak, counting the minimum
         # bytes of this algorithm (4-array state, 54 B/voxel in FP32) and of

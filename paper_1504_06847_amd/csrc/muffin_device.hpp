@@ -106,11 +106,16 @@ template <typename T> struct BandArray1 {
     __device__ __forceinline__ BandArray1(char* base, unsigned bb)
         : r(__builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7fffffff, kBufWord3)), band_bytes(bb) {}
     __device__ __forceinline__ T load(int l, unsigned lane_off) const {
-        static_assert(sizeof(T) == 4, "FP32 arrays");
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, (unsigned)l * band_bytes, 0));
+        if constexpr (sizeof(T) == 4)
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, (unsigned)l * band_bytes, 0));
+        else
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, (unsigned)l * band_bytes, 0));
     }
     __device__ __forceinline__ void store(int l, unsigned lane_off, T v) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, lane_off, (unsigned)l * band_bytes, 0);
+        if constexpr (sizeof(T) == 4)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, lane_off, (unsigned)l * band_bytes, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, lane_off, (unsigned)l * band_bytes, 0);
     }
 };
 
