@@ -203,15 +203,20 @@ template <bool PAD> __host__ __device__ constexpr int lds_len(int n) { return PA
 // Twiddles w^r, r = 1..R-1, of one butterfly, w = exp(-2 pi i k / (NS R)):
 // w, w^2 and w^4 come from the table (exact to the table's rounding), the
 // others as one product of two table values.
-template <typename T, int R>
+// Entry i of a twiddle table with one spare slot after every 2^TWP entries
+// (TWP > 0, tables in LDS: the stride-2^s reads of a stage then spread over
+// the banks instead of hitting one).
+template <int TWP> __host__ __device__ constexpr int tw_at(int i) { return TWP > 0 ? i + (i >> TWP) : i; }
+
+template <typename T, int R, int TWP = 0>
 __device__ __forceinline__ void stage_twiddles(cx<T>* w, const cx<T>* __restrict__ tw, int k, int shift) {
-    w[1] = tw[k << shift];
+    w[1] = tw[tw_at<TWP>(k << shift)];
     if constexpr (R >= 4) {
-        w[2] = tw[(2 * k) << shift];
+        w[2] = tw[tw_at<TWP>((2 * k) << shift)];
         w[3] = cmul(w[1], w[2]);
     }
     if constexpr (R == 8) {
-        w[4] = tw[(4 * k) << shift];
+        w[4] = tw[tw_at<TWP>((4 * k) << shift)];
         w[5] = cmul(w[1], w[4]);
         w[6] = cmul(w[2], w[4]);
         w[7] = cmul(w[3], w[4]);
@@ -246,7 +251,8 @@ __device__ __forceinline__ int tile_index(int tr, int e) {
 // (j - j mod NS) R + (j mod NS) + q NS.  Work items (transform, butterfly) are
 // spread over NTH threads: TFAST puts the transform index fastest across
 // threads (strided tiles), otherwise the butterfly index.
-template <typename T, int LEN, int R, int NS, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
+template <typename T, int LEN, int R, int NS, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV,
+          int TWP = 0>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
     constexpr int NB = LEN / R;
     constexpr int ITEMS = NB * NTRANS;
@@ -264,7 +270,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
             if constexpr (NS > 1) {
                 const int k = j & (NS - 1);
                 cx<T> w[R];
-                stage_twiddles<T, R>(w, tw, k, twlog - LOGNR);
+                stage_twiddles<T, R, TWP>(w, tw, k, twlog - LOGNR);
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[i][r] = INV ? cmulc(v[i][r], w[r]) : cmul(v[i][r], w[r]);
             }
@@ -287,22 +293,24 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
     __syncthreads();
 }
 
-template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV, int S>
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV, int S,
+          int TWP = 0>
 __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
     if constexpr (S < plan_nstages(LEN)) {
-        fft_stage<T, LEN, plan_radix(LEN, S), plan_ns(LEN, S), NTRANS, NTH, TS, ES, TFAST, PAD, INV>(buf, tw, twlog, t);
-        fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, S + 1>(buf, tw, twlog, t);
+        fft_stage<T, LEN, plan_radix(LEN, S), plan_ns(LEN, S), NTRANS, NTH, TS, ES, TFAST, PAD, INV, TWP>(buf, tw, twlog, t);
+        fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, S + 1, TWP>(buf, tw, twlog, t);
     }
 }
 
 // In-place FFT of NTRANS transforms of length LEN held in LDS (natural order
 // in and out, unnormalised).  Must be called by all NTH threads of the block.
 // Stages S .. E-1 of the plan.
-template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV, int S, int E>
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV, int S, int E,
+          int TWP = 0>
 __device__ __forceinline__ void fft_stage_range(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
     if constexpr (S < E) {
-        fft_stage<T, LEN, plan_radix(LEN, S), plan_ns(LEN, S), NTRANS, NTH, TS, ES, TFAST, PAD, INV>(buf, tw, twlog, t);
-        fft_stage_range<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, S + 1, E>(buf, tw, twlog, t);
+        fft_stage<T, LEN, plan_radix(LEN, S), plan_ns(LEN, S), NTRANS, NTH, TS, ES, TFAST, PAD, INV, TWP>(buf, tw, twlog, t);
+        fft_stage_range<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, S + 1, E, TWP>(buf, tw, twlog, t);
     }
 }
 
@@ -344,7 +352,7 @@ __device__ __forceinline__ void fft_first_stage_global(cx<T>* buf, const cx<T>* 
 
 // The last stage with its output written to global memory: element e of
 // transform tr to dst[e * ld + tr] for tr < ntr.  No barrier at the end.
-template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV, int TWP = 0>
 __device__ __forceinline__ void fft_last_stage_global(const cx<T>* buf, const cx<T>* __restrict__ tw, int twlog,
                                                       cx<T>* dst, long ld, int ntr, int t) {
     constexpr int S = plan_nstages(LEN) - 1;
@@ -365,7 +373,7 @@ __device__ __forceinline__ void fft_last_stage_global(const cx<T>* buf, const cx
             const int k = j & (NS - 1);
             if constexpr (NS > 1) {
                 cx<T> w[R];
-                stage_twiddles<T, R>(w, tw, k, twlog - LOGNR);
+                stage_twiddles<T, R, TWP>(w, tw, k, twlog - LOGNR);
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
             }
@@ -379,9 +387,9 @@ __device__ __forceinline__ void fft_last_stage_global(const cx<T>* buf, const cx
     }
 }
 
-template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
+template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV, int TWP = 0>
 __device__ __forceinline__ void tile_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int twlog, int t) {
-    fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, 0>(buf, tw, twlog, t);
+    fft_stages<T, LEN, NTRANS, NTH, TS, ES, TFAST, PAD, INV, 0, TWP>(buf, tw, twlog, t);
 }
 
 // ---------------------------------------------------------------- real rows
@@ -390,7 +398,7 @@ __device__ __forceinline__ void tile_fft(cx<T>* buf, const cx<T>* __restrict__ t
 // slot 0 holds the two real values (X_0, X_{nx/2}), slot k (0 < k < M) X_k.
 // l: the row's M-point spectrum Z in LDS (padded positions); o: the packed
 // output row; k in [0, M/2] produces slots k and M - k.
-template <typename T, int NX>
+template <typename T, int NX, int TWP = 0>
 __device__ __forceinline__ void rfft_post(const cx<T>* l, cx<T>* o, int k, const cx<T>* __restrict__ tw,
                                           int twlog) {
     constexpr int M = NX / 2;
@@ -404,7 +412,7 @@ __device__ __forceinline__ void rfft_post(const cx<T>* l, cx<T>* o, int k, const
         // even/odd sample spectra E = (Z_k + conj Z_{M-k})/2, O = -i (Z_k - conj Z_{M-k})/2
         const cx<T> e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
         const cx<T> od = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
-        const cx<T> wo = cmul(od, tw[k << (twlog - ilog2c(NX))]);
+        const cx<T> wo = cmul(od, tw[tw_at<TWP>(k << (twlog - ilog2c(NX)))]);
         o[k] = e + wo;                                // X_k = E + w^k O
         o[M - k] = conj(e - wo);                      // X_{M-k} = conj(E - w^k O)
     }
@@ -413,7 +421,7 @@ __device__ __forceinline__ void rfft_post(const cx<T>* l, cx<T>* o, int k, const
 // The inverse: from the packed half spectrum p of a row, slots k and M - k of
 // the M-point spectrum whose inverse FFT is z_m = x_{2m} + i x_{2m+1}
 // (unnormalised), written to the LDS row l.
-template <typename T, int NX>
+template <typename T, int NX, int TWP = 0>
 __device__ __forceinline__ void irfft_pre(const cx<T>* p, cx<T>* l, int k, const cx<T>* __restrict__ tw,
                                           int twlog) {
     constexpr int M = NX / 2;
@@ -426,7 +434,7 @@ __device__ __forceinline__ void irfft_pre(const cx<T>* p, cx<T>* l, int k, const
         const cx<T> xm = p[M - k];
         const cx<T> e = {T(0.5) * (xk.x + xm.x), T(0.5) * (xk.y - xm.y)};
         const cx<T> d = {T(0.5) * (xk.x - xm.x), T(0.5) * (xk.y + xm.y)};
-        const cx<T> o = cmulc(d, tw[k << (twlog - ilog2c(NX))]);   // O = w^{-k} D
+        const cx<T> o = cmulc(d, tw[tw_at<TWP>(k << (twlog - ilog2c(NX)))]);   // O = w^{-k} D
         l[lds_pos<true>(k)] = e + mul_i(o);                         // Z_k = E + i O
         l[lds_pos<true>(M - k)] = conj(e) + mul_i(conj(o));
     }

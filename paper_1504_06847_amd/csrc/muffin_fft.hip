@@ -28,8 +28,10 @@ template <typename T, int NY> constexpr int col_tc_base() {
     return tc > 16 ? 16 : (tc < 1 ? 1 : tc);
 }
 template <typename T, int NY> constexpr bool col_twl() { return NY * int(sizeof(cx<T>)) <= 16384; }
+constexpr int COL_TWP = 4;                 // LDS twiddle table: one spare slot per 16 entries
+template <int NY> constexpr int col_twl_len() { return tw_at<COL_TWP>(NY); }
 template <typename T, int NY, int TC> constexpr int col_lds_bytes() {
-    return NY * TC * int(sizeof(cx<T>)) + (col_twl<T, NY>() ? NY * int(sizeof(cx<T>)) : 0) + 64;
+    return NY * TC * int(sizeof(cx<T>)) + (col_twl<T, NY>() ? col_twl_len<NY>() * int(sizeof(cx<T>)) : 0) + 64;
 }
 // columns per tile of variant V: half, all or twice the 64-KiB tile
 template <typename T, int NY, int V> constexpr int col_tc() {
@@ -218,7 +220,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
     constexpr int NST = plan_nstages(NY);
     const int ntr = M - c0 < TC ? M - c0 : TC;      // columns of this tile inside the spectrum
     if constexpr (TWL) {
-        for (int i = t; i < NY; i += NTH) twl[i] = tw[i << (twlog - ilog2c(NY))];
+        for (int i = t; i < NY; i += NTH) twl[tw_at<COL_TWP>(i)] = tw[i << (twlog - ilog2c(NY))];
     }
     // the data term and the filter of this thread's elements, loaded before
     // the forward transform so that their latency hides behind it (up to 8
@@ -245,7 +247,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
     // forward FFT along y; its first stage reads the tile straight from Z
     // (the barrier that ends it also publishes the twiddle table)
     fft_first_stage_global<T, NY, TC, NTH, 1, 0, true, false, false>(lds, data + base + c0, M, ntr, t);
-    if constexpr (TWL) fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, false, 1, NST>(lds, twl, ilog2c(NY), t);
+    if constexpr (TWL) fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, false, 1, NST, COL_TWP>(lds, twl, ilog2c(NY), t);
     else fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, false, 1, NST>(lds, tw, twlog, t);
 
     if constexpr (FILT) {
@@ -288,9 +290,9 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         __syncthreads();
         // inverse FFT along y; its last stage writes the tile straight to Z
         if constexpr (TWL) {
-            fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1>(lds, twl, ilog2c(NY), t);
-            fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true>(lds, twl, ilog2c(NY), data + base + c0,
-                                                                          M, ntr, t);
+            fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1, COL_TWP>(lds, twl, ilog2c(NY), t);
+            fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true, COL_TWP>(lds, twl, ilog2c(NY),
+                                                                                   data + base + c0, M, ntr, t);
         } else {
             fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1>(lds, tw, twlog, t);
             fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true>(lds, tw, twlog, data + base + c0, M,
@@ -350,7 +352,7 @@ k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
       int twlog, double* __restrict__ partials, double inv_n) {
     constexpr int TC = col_tc<T, NY, V>();
     __shared__ cx<T> lds[NY * TC];
-    __shared__ cx<T> twl[col_twl<T, NY>() ? NY : 1];
+    __shared__ cx<T> twl[col_twl<T, NY>() ? col_twl_len<NY>() : 1];
     __shared__ double red[col_nth<T, NY, TC>() / 64];
     col_body<T, NY, MODE, TC>(data, Yf, H2, H2nyq, rhoQ, scale, M, tw, twlog, partials, inv_n,
                               blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y, gridDim.x,
@@ -364,7 +366,7 @@ __global__ void __launch_bounds__((col_nth<T, NY, col_tc<T, NY, V>()>()))
 k_col_group(const ColDesc* __restrict__ d, int n) {
     constexpr int TC = col_tc<T, NY, V>();
     __shared__ cx<T> lds[NY * TC];
-    __shared__ cx<T> twl[col_twl<T, NY>() ? NY : 1];
+    __shared__ cx<T> twl[col_twl<T, NY>() ? col_twl_len<NY>() : 1];
     __shared__ double red[col_nth<T, NY, TC>() / 64];
     const int j = group_find(d, n, blockIdx.x);
     if (j < 0) return;

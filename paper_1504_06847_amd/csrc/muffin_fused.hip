@@ -35,7 +35,7 @@ template <int LT> constexpr int fused_qb() { return LT >= 64 ? 24 : 0; }
 template <typename T, int NX, int LT> struct FusedLds {
     static constexpr int NTH = NX / fused_ppt<NX, LT>();
     cx<T> rows[fused_g<LT>() * lds_len<true>(NX / 2)];   // G spectrum / image rows
-    cx<T> twl[NX];                                        // w_NX^i, i < NX
+    cx<T> twl[tw_at<4>(NX)];                              // w_NX^i, i < NX (padded)
     T q[fused_qb<LT>() > 0 ? fused_qb<LT>() * NTH : 1];
 };
 
@@ -58,7 +58,7 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
     T* qlds = sh.q;
     const int t = threadIdx.x;
     const int r0 = t / TPR, k0 = t % TPR;
-    for (int i = t; i < NX; i += NTH) twl[i] = tw[i << (twlog - ilog2c(NX))];
+    for (int i = t; i < NX; i += NTH) twl[tw_at<4>(i)] = tw[i << (twlog - ilog2c(NX))];
     __syncthreads();
     unsigned off[PPT];
 #pragma unroll
@@ -100,12 +100,12 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
 #pragma unroll
             for (int j = 0; j < (NK + TPR - 1) / TPR; ++j) {
                 const int k = k0 + j * TPR;
-                if (k < NK && l < L) irfft_pre<T, NX>(prow, lds + r0 * TS, k, twl, ilog2c(NX));
+                if (k < NK && l < L) irfft_pre<T, NX, 4>(prow, lds + r0 * TS, k, twl, ilog2c(NX));
             }
         }
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
-        tile_fft<T, M, G, NTH, TS, 1, false, true, true>(lds, twl, ilog2c(NX), t);
+        tile_fft<T, M, G, NTH, TS, 1, false, true, true, 4>(lds, twl, ilog2c(NX), t);
         __builtin_amdgcn_sched_barrier(0);
         // B2: steps II, III, V, VI at the thread's pixels for the group's bands
 #pragma unroll
@@ -136,7 +136,7 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
         }
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
-        tile_fft<T, M, G, NTH, TS, 1, false, true, false>(lds, twl, ilog2c(NX), t);
+        tile_fft<T, M, G, NTH, TS, 1, false, true, false, 4>(lds, twl, ilog2c(NX), t);
         __builtin_amdgcn_sched_barrier(0);
         // B3: packed spectrum rows of B_rest, over the rows read in B1
         {
@@ -145,7 +145,7 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
 #pragma unroll
             for (int j = 0; j < (NK + TPR - 1) / TPR; ++j) {
                 const int k = k0 + j * TPR;
-                if (k < NK && l < L) rfft_post<T, NX>(lds + r0 * TS, prow, k, twl, ilog2c(NX));
+                if (k < NK && l < L) rfft_post<T, NX, 4>(lds + r0 * TS, prow, k, twl, ilog2c(NX));
             }
         }
         __syncthreads();
