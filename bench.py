@@ -42,7 +42,7 @@ METRIC = "voxel-iterations/s (FP32 vs FP64) at 1024²×64; HBM GB/s % of peak"
 #              z_P, z_T, S, Gamma_S, B_rest out                        11
 #   fused    : Z, S, Gamma_S, z_P, z_T, Gamma_S again in;
 #              Z, X, z_P, z_T, S, Gamma_S out                            12
-KERNEL_ELEMS = {"row_fwd": 2.0, "col_solve": 3.5, "row_inv": 2.0, "spectral": 11.0, "fused": 12.0}
+KERNEL_ELEMS = {"row_fwd": 2.0, "col_solve": 3.5, "row_inv": 2.0, "spectral": 10.0, "fused": 11.0}
 # minimum traffic of one pass of this algorithm: the 4-array state stream in
 # and out plus the constants (38 B in FP32) and one transposition round trip
 # of the 2-D FFT (16 B)

@@ -156,9 +156,11 @@ int muffin_grad(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, i
                 double* loss, double grad[3]);
 
 /* Bytes of one state snapshot: the iteration's carried arrays (the prox
-   inputs z_P and z_T of steps II-III, S and Gamma_S; Gamma_V = Gamma_S W_nu
+   inputs z_P and z_T of steps II-III, the spectral prox input
+   z_V = S - Gamma_S / rho_V of step IV, and Gamma_S; Gamma_V = Gamma_S W_nu
    holds after every pass, so it is not stored), the X iterate and a header
-   with the iteration counter. */
+   with the iteration counter.  The arrays encode the variables under the
+   context's rho's: restore a state into a context with the same parameters. */
 size_t muffin_state_bytes(const muffin_ctx* ctx);
 
 /* Save / restore the ADMM state to / from device memory `dst` / `src`
@@ -168,8 +170,8 @@ int muffin_get_state(muffin_ctx* ctx, void* dst);
 int muffin_set_state(muffin_ctx* ctx, const void* src);
 
 /* Replace the parameters (mu's, rho's) without a new setup.  The ADMM
-   variables are kept: P, Gamma_P, S, Gamma_S, Gamma_V exactly, and T, Gamma_T
-   exactly when mu_s is unchanged, so a change of the rho's continues
+   variables are kept (up to rounding): P, Gamma_P, S, Gamma_S, Gamma_V, and
+   T, Gamma_T when mu_s is unchanged, so a change of the rho's continues
    Algorithm 1 with the multipliers held fixed (the rule for varying penalty
    parameters, Boyd et al. 2011, Sec. 3.4.1).  With a new mu_s the stored
    input of the spatial soft threshold is kept, i.e. the run continues from a

@@ -12,7 +12,10 @@
 //   S'  = (rho_V q + rho_S X) / (rho_V + rho_S)
 //   G'  = Gamma_S + rho_V (q - S')
 //   z_P' = X - max(0, -z_P),  z_T' = X + clip(z_T, tau_T)
-// with tau_T = mu_s / rho_T, tau_V = mu_nu / rho_V.  Derivatives at the
+// with tau_T = mu_s / rho_T, tau_V = mu_nu / rho_V.  The sweep differentiates
+// this map, with cotangents of (z_P, z_T, S, Gamma_S); the stored states
+// hold z_V = S - Gamma_S / rho_V in place of S (the DCT input above), and
+// S = z_V + Gamma_S / rho_V where S itself enters.  Derivatives at the
 // kinks: soft' = 1[|z| > tau], clip' = 1[|z| <= tau], max(0, .)' = 1[. > 0],
 // |z|' = sign(z) (0 at 0).
 //
@@ -41,7 +44,7 @@ __device__ __forceinline__ void store_grad_partials(const double (&vals)[GRAD_NQ
 }
 
 // Adjoint of steps II-VI of pass k at one pixel.  In: the state before the
-// pass (zP, zT, S, GS), the pass's X, the cotangents of the state after the
+// pass (zP, zT, zV, GS), the pass's X, the cotangents of the state after the
 // pass (aP, aT, aS, aG, overwritten in place by those of the state before
 // it, this part of them) and, with has_ext, an outside cotangent of X in Xb.
 // Out: Xb = the total cotangent of X.
@@ -53,7 +56,7 @@ k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int ha
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
     const int gs_ = A.gshift;
-    const BandArray<T> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.S, bb, gs_}, GS{A.GS, bb, gs_},
+    const BandArray<T> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_}, GS{A.GS, bb, gs_},
         X{A.X, bb, gs_}, aP{A.aP, bb, gs_}, aT{A.aT, bb, gs_}, aS{A.aS, bb, gs_}, aG{A.aG, bb, gs_},
         Xb{A.Xb, bb, gs_};
     const int L = DENSE ? Lrt : LT;
@@ -66,9 +69,9 @@ k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int ha
     for (int w = 0; w < W; ++w) mc[w] = sc[w] = 0u;
 
     T v[LT];
-    // forward: c = DCT(S - Gamma_S / rho_V); keep the kink pattern of soft(c)
+    // forward: c = DCT(z_V); keep the kink pattern of soft(c)
 #pragma unroll
-    for (int l = 0; l < LT; ++l) v[l] = (l < L) ? S.load(l, off) - GS.load(l, off) * inv_rhoV : T(0);
+    for (int l = 0; l < LT; ++l) v[l] = (l < L) ? zV.load(l, off) : T(0);
     dct_any<T, LT, DENSE, false>(v, D, L);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -136,9 +139,11 @@ k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int ha
 template <typename T>
 __global__ void __launch_bounds__(ADJ_NTH)
 k_adj_step1(const T* __restrict__ Bb, const T* __restrict__ zP, const T* __restrict__ zT,
-            const T* __restrict__ S, const T* __restrict__ X, T* __restrict__ aP, T* __restrict__ aT,
-            T* __restrict__ aS, T* __restrict__ aG, long n, SpecArgs a, double* __restrict__ partials) {
+            const T* __restrict__ zV, const T* __restrict__ GS, const T* __restrict__ X, T* __restrict__ aP,
+            T* __restrict__ aT, T* __restrict__ aS, T* __restrict__ aG, long n, SpecArgs a,
+            double* __restrict__ partials) {
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoS = T(a.rho_S), tauT = T(a.tau_T);
+    const T inv_rhoV = T(1.0 / a.rho_V);
     double g_tT = 0, g_rP = 0, g_rT = 0, g_rS = 0, g_rQ = 0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const T b = Bb[i], zp = zP[i], zt = zT[i];
@@ -150,7 +155,7 @@ k_adj_step1(const T* __restrict__ Bb, const T* __restrict__ zP, const T* __restr
         if (out) g_tT += double(-T(2) * rhoT * b * sgnt(zt));
         g_rT += double(b * (T(2) * softt(zt, tauT) - zt));
         g_rP += double(b * fabs(zp));
-        g_rS += double(b * S[i]);
+        g_rS += double(b * (zV[i] + GS[i] * inv_rhoV));
         g_rQ -= double(b * X[i]);
     }
     const double vals[GRAD_NQ] = {g_tT, 0.0, g_rP, g_rT, 0.0, g_rS, g_rQ, 0.0};
@@ -229,19 +234,20 @@ hipError_t launch_adj_spectral(int dtype, const AdjArrays& A, const void* D, int
                       : adj_dispatch<double>(A, D, L, npix, a, has_ext, partials, nblocks, s);
 }
 
-hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* S,
-                            const void* X, void* aP, void* aT, void* aS, void* aG, size_t n,
+hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* zV,
+                            const void* GS, const void* X, void* aP, void* aT, void* aS, void* aG, size_t n,
                             const SpecArgs& a, double* partials, int* nblocks, hipStream_t s) {
     const unsigned g = adj_grid((long)n);
     *nblocks = (int)g;
     if (dtype == 0)
         hipLaunchKernelGGL((k_adj_step1<float>), dim3(g), dim3(ADJ_NTH), 0, s, (const float*)Bb,
-                           (const float*)zP, (const float*)zT, (const float*)S, (const float*)X,
-                           (float*)aP, (float*)aT, (float*)aS, (float*)aG, (long)n, a, partials);
+                           (const float*)zP, (const float*)zT, (const float*)zV, (const float*)GS,
+                           (const float*)X, (float*)aP, (float*)aT, (float*)aS, (float*)aG, (long)n, a, partials);
     else
         hipLaunchKernelGGL((k_adj_step1<double>), dim3(g), dim3(ADJ_NTH), 0, s, (const double*)Bb,
-                           (const double*)zP, (const double*)zT, (const double*)S, (const double*)X,
-                           (double*)aP, (double*)aT, (double*)aS, (double*)aG, (long)n, a, partials);
+                           (const double*)zP, (const double*)zT, (const double*)zV, (const double*)GS,
+                           (const double*)X, (double*)aP, (double*)aT, (double*)aS, (double*)aG, (long)n, a,
+                           partials);
     return hipGetLastError();
 }
 

@@ -61,7 +61,7 @@ int fused_rows(muffin_ctx* c) {
     A.X = P(c, c->lay.x);
     A.zP = (char*)st(c, ST_ZP);
     A.zT = (char*)st(c, ST_ZT);
-    A.S = (char*)st(c, ST_S);
+    A.zV = (char*)st(c, ST_ZV);
     A.GS = (char*)st(c, ST_GS);
     A.Z = P(c, c->lay.z);
     A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
@@ -163,7 +163,7 @@ int one_pass(muffin_ctx* c) {
 }
 
 int recompute_brest(muffin_ctx* c) {
-    HIP_TRY(launch_brest(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), st(c, ST_S), st(c, ST_GS),
+    HIP_TRY(launch_brest(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), st(c, ST_ZV), st(c, ST_GS),
                          P(c, c->lay.brest), voxels(c->shape), spec_args(c->params), c->stream));
     c->zvalid = 0;
     return MUFFIN_OK;
@@ -371,7 +371,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             AdjArrays A;
             A.zP = segs(j, ST_ZP);
             A.zT = segs(j, ST_ZT);
-            A.S = segs(j, ST_S);
+            A.zV = segs(j, ST_ZV);
             A.GS = segs(j, ST_GS);
             A.X = segs(j, kNumState);
             A.aP = adj;
@@ -393,7 +393,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
                                nullptr, nullptr, st_));
             HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), Bb, nrows, s.nx, P(c, c->lay.tw), c->twlog, st_,
                                    c->row_v));
-            HIP_TRY(launch_adj_step1(dt, Bb, A.zP, A.zT, A.S, A.X, A.aP, A.aT, A.aS, A.aG, voxels(s), a,
+            HIP_TRY(launch_adj_step1(dt, Bb, A.zP, A.zT, A.zV, A.GS, A.X, A.aP, A.aT, A.aS, A.aG, voxels(s), a,
                                      partials, &nbk, st_));
             HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
         }
@@ -637,11 +637,13 @@ int muffin_set_params(muffin_ctx* c, const muffin_params* params) {
     if (rc) return rc;
     const muffin_params old = c->params;
     drop_graphs(c);      // the parameters are kernel arguments of the recorded pass
-    if (old.rho_P != params->rho_P || old.rho_T != params->rho_T) {
-        // keep P, Gamma_P and T, Gamma_T of the stored state under the new rho's
-        HIP_TRY(launch_reencode(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), voxels(c->shape),
-                                old.rho_P / params->rho_P, old.rho_T / params->rho_T,
-                                old.mu_s / old.rho_T, c->stream));
+    if (old.rho_P != params->rho_P || old.rho_T != params->rho_T || old.rho_V != params->rho_V) {
+        // keep P, Gamma_P, S and T, Gamma_T of the stored state under the new rho's
+        HIP_TRY(launch_reencode(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), st(c, ST_ZV), st(c, ST_GS),
+                                voxels(c->shape), old.rho_P / params->rho_P, old.rho_T / params->rho_T,
+                                old.mu_s / old.rho_T,
+                                old.rho_V != params->rho_V ? 1.0 / old.rho_V - 1.0 / params->rho_V : 0.0,
+                                c->stream));
     }
     c->params = *params;
     c->version++;
@@ -788,7 +790,7 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
         A.X = P(c, c->lay.brest);
         A.zP = (char*)st_alt(c, ST_ZP);
         A.zT = (char*)st_alt(c, ST_ZT);
-        A.S = (char*)st_alt(c, ST_S);
+        A.zV = (char*)st_alt(c, ST_ZV);
         A.GS = (char*)st_alt(c, ST_GS);
         A.Z = P(c, c->lay.z);
         A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));

@@ -133,7 +133,7 @@ void fill_desc(const muffin_batch* b, const Class& k, muffin_ctx* c, int first, 
         d.A.X = P(c, c->lay.x);
         d.A.zP = (char*)st(c, ST_ZP);
         d.A.zT = (char*)st(c, ST_ZT);
-        d.A.S = (char*)st(c, ST_S);
+        d.A.zV = (char*)st(c, ST_ZV);
         d.A.GS = (char*)st(c, ST_GS);
         d.A.Z = P(c, c->lay.z);
         d.A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
@@ -155,7 +155,7 @@ void fill_desc(const muffin_batch* b, const Class& k, muffin_ctx* c, int first, 
         A.X = P(c, c->lay.x);
         A.zP = A.zPo = (char*)st(c, ST_ZP);
         A.zT = A.zTo = (char*)st(c, ST_ZT);
-        A.S = A.So = (char*)st(c, ST_S);
+        A.zV = A.zVo = (char*)st(c, ST_ZV);
         A.GS = A.GSo = (char*)st(c, ST_GS);
         A.Brest = P(c, c->lay.brest);
         A.band_bytes = bb;

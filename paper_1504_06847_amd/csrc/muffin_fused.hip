@@ -6,17 +6,18 @@
 // holding the pixel's band vector in registers for the spectral steps (as
 // k_spectral), and the row of G bands at a time in LDS for the row
 // transforms:
-//   A  V = soft(DCT(S - Gamma_S / rho_V)), q = IDCT(V)        (registers)
+//   A  V = soft(DCT(z_V)), q = IDCT(V)                         (registers)
 //   B  for each group of G bands:
 //        inverse real FFT of the column pass's spectrum rows -> X rows (LDS)
 //        steps II, III, V, VI per pixel; X and the new state to HBM; B_rest
 //          into the LDS rows in place of X
 //        forward real FFT of B_rest -> the spectrum rows of the next column
 //          pass (written over the rows read)
-// X and B_rest never make an HBM round trip between kernels: 48 B/voxel in
-// FP32 (Z, X, z_P, z_T, S, Gamma_S, Gamma_S again; Z, X, z_P, z_T, S,
-// Gamma_S) against 60 B for the inverse row pass, spectral pass and forward
-// row pass launched one after another.
+// X and B_rest never make an HBM round trip between kernels: 44 B/voxel in
+// FP32 (Z, z_P, z_T, z_V, Gamma_S in; Z, X, z_P, z_T, z_V, Gamma_S out)
+// against 56 B for the inverse row pass, spectral pass and forward row pass
+// launched one after another.  The state is that of muffin_spectral.hip
+// (z_V = S - Gamma_S / rho_V in place of S).
 #include "muffin_device.hpp"
 #include "muffin_kernels.hpp"
 
@@ -65,7 +66,7 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
     for (int p = 0; p < PPT; ++p) off[p] = (unsigned)((long)y * NX + t + p * NTH) * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
     // every band of an array within 2^30 bytes of its base (checked on the host)
-    const BandArray1<T> X(A.X, bb), zP(A.zP, bb), zT(A.zT, bb), S(A.S, bb), GS(A.GS, bb);
+    const BandArray1<T> X(A.X, bb), zP(A.zP, bb), zT(A.zT, bb), zV(A.zV, bb), GS(A.GS, bb);
     cx<T>* Z = (cx<T>*)A.Z;
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
@@ -73,12 +74,11 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
     const T inv_rhoV = T(1.0 / a.rho_V), inv_VS = T(1.0 / (a.rho_V + a.rho_S));
 
     T v[PPT][LT];
-    // A: step IV with the previous S, Gamma_S
+    // A: step IV with the previous z_V
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
 #pragma unroll
-        for (int l = 0; l < LT; ++l)
-            v[p][l] = (l < L) ? S.load(l, off[p]) - GS.load(l, off[p]) * inv_rhoV : T(0);
+        for (int l = 0; l < LT; ++l) v[p][l] = (l < L) ? zV.load(l, off[p]) : T(0);
         dct_any<T, LT, DENSE, false>(v[p], D, L);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -124,9 +124,11 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
                     const T zp2 = xv - (zp < T(0) ? -zp : T(0));
                     const T zt2 = xv + clipt(zt, tauT);
                     const T tt = softt(zt2, tauT);
-                    lrow[e] = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * s;
+                    const T zv2 = s - gs2 * inv_rhoV;
+                    const T sv = zv2 + gs2 * inv_rhoV;       // S as stored (see k_spectral)
+                    lrow[e] = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * sv;
                     X.store(l, off[p], xv);
-                    S.store(l, off[p], s);
+                    zV.store(l, off[p], zv2);
                     GS.store(l, off[p], gs2);
                     zP.store(l, off[p], zp2);
                     zT.store(l, off[p], zt2);

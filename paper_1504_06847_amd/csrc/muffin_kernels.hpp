@@ -82,11 +82,11 @@ struct ColDesc {             // the solving column pass of one cube
     int L, M, twlog, first, nblk, pad;
 };
 // the [L][npix] arrays of the spectral pass: X, the state it reads (z_P,
-// z_T, S, Gamma_S), the state it writes (the same arrays, or a second set in
-// a reporting pass) and B_rest
+// z_T, z_V = S - Gamma_S / rho_V, Gamma_S), the state it writes (the same
+// arrays, or a second set in a reporting pass) and B_rest
 struct SpecArrays {
-    char *X, *zP, *zT, *S, *GS;
-    char *zPo, *zTo, *So, *GSo;
+    char *X, *zP, *zT, *zV, *GS;
+    char *zPo, *zTo, *zVo, *GSo;
     char *Brest;
     unsigned band_bytes;
     int gshift;
@@ -133,10 +133,11 @@ enum GradSlot {
     GRAD_NQ
 };
 
-// [L][npix] arrays of the adjoint of one pass: the state before the pass,
-// the pass's X, the state cotangents (in place) and the cotangent of X
+// [L][npix] arrays of the adjoint of one pass: the state before the pass
+// (z_P, z_T, z_V, Gamma_S), the pass's X, the state cotangents (in place;
+// those of z_P, z_T, S and Gamma_S) and the cotangent of X
 struct AdjArrays {
-    char *zP, *zT, *S, *GS, *X;
+    char *zP, *zT, *zV, *GS, *X;
     char *aP, *aT, *aS, *aG, *Xb;
     unsigned band_bytes;
     int gshift;
@@ -145,8 +146,8 @@ struct AdjArrays {
 hipError_t launch_adj_spectral(int dtype, const AdjArrays& A, const void* D, int L, long npix,
                                const SpecArgs& a, int has_ext, double* partials, int* nblocks,
                                hipStream_t s);
-hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* S,
-                            const void* X, void* aP, void* aT, void* aS, void* aG, size_t n,
+hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* zV,
+                            const void* GS, const void* X, void* aP, void* aT, void* aS, void* aG, size_t n,
                             const SpecArgs& a, double* partials, int* nblocks, hipStream_t s);
 hipError_t launch_mse_seed(int dtype, const void* X, const void* sky, void* Xb, size_t n,
                            double* partials, int* nblocks, hipStream_t s);
@@ -160,7 +161,7 @@ hipError_t launch_grad_accum(const double* partials, int nblocks, double* acc, h
 // spectrum Z and the state, writes X, the new state and the spectrum of
 // B_rest over Z.
 struct FusedArrays {
-    char *X, *zP, *zT, *S, *GS;
+    char *X, *zP, *zT, *zV, *GS;
     char* Z;
     unsigned band_bytes;
     int gshift;
@@ -179,7 +180,7 @@ hipError_t launch_fused_group(int dtype, int nx, int L, const FusedDesc* d, int 
 hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
                         const SpecArgs& a, const void* tw, int twlog, hipStream_t s);
 
-// Arrays of one spectral pass.  st: the state read (z_P, z_T, S, Gamma_S);
+// Arrays of one spectral pass.  st: the state read (z_P, z_T, z_V, Gamma_S);
 // out: where the new state goes (= st except in a reporting pass).
 struct SpecLaunch {
     const void* X;
@@ -215,11 +216,12 @@ hipError_t launch_reduce_final(const double* partials, int nblocks, int nq, doub
 
 // Elementwise helpers.
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
-hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* S, const void* GS,
+hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* zV, const void* GS,
                         void* Brest, size_t n, const SpecArgs& a, hipStream_t s);
 hipError_t launch_positive(int dtype, const void* z, void* out, size_t n, hipStream_t s);
-// z_P <- max(0, z_P) - rP max(0, -z_P);  z_T <- soft(z_T, tau) + rT clip(z_T, tau)
-hipError_t launch_reencode(int dtype, void* zP, void* zT, size_t n, double rP, double rT, double tau,
-                           hipStream_t s);
+// z_P <- max(0, z_P) - rP max(0, -z_P);  z_T <- soft(z_T, tau) + rT clip(z_T, tau);
+// z_V <- z_V + dV Gamma_S (dV = 1 / rho_V - 1 / rho_V', skipped when 0)
+hipError_t launch_reencode(int dtype, void* zP, void* zT, void* zV, const void* GS, size_t n, double rP,
+                           double rT, double tau, double dV, hipStream_t s);
 
 }  // namespace muffin

@@ -8,9 +8,9 @@
 namespace muffin {
 
 constexpr size_t kAlign = 256;
-constexpr int kNumState = 4;     // z_P, z_T, S, Gamma_S (Gamma_V = Gamma_S W_nu is implied)
+constexpr int kNumState = 4;     // z_P, z_T, z_V = S - Gamma_S / rho_V, Gamma_S (Gamma_V = Gamma_S W_nu implied)
 constexpr int kNumRed = 10;      // FP64 partial sums per block (see RedSlot)
-enum StateIdx { ST_ZP = 0, ST_ZT = 1, ST_S = 2, ST_GS = 3 };
+enum StateIdx { ST_ZP = 0, ST_ZT = 1, ST_ZV = 2, ST_GS = 3 };
 
 struct Layout {
     size_t state[2][kNumState];   // current and alternate state sets (a reporting

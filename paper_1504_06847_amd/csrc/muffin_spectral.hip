@@ -7,7 +7,7 @@
 // of a wavefront covers 64 consecutive pixels of one band.
 //
 // State: the reduced form of Algorithm 1's nine arrays with W_s = I, four
-// arrays z_P, z_T, S, Gamma_S.
+// arrays z_P, z_T, z_V, Gamma_S.
 //  * z_P, z_T are the inputs of the positivity prox (step II) and of the
 //    spatial soft threshold (step III): P = max(0, z_P),
 //    Gamma_P = rho_P max(0, -z_P), T = soft(z_T, tau_T),
@@ -15,12 +15,17 @@
 //  * Gamma_V is not stored.  Step V minimises the augmented Lagrangian in S
 //    exactly, and its optimality condition is Gamma_S^+ = Gamma_V^+ W_nu^T
 //    after every pass (and at the all-zero start), so Gamma_V = Gamma_S W_nu.
+//  * z_V = S - Gamma_S / rho_V is the pixel-domain input of the spectral
+//    soft threshold (step IV), stored in place of S: step IV reads only z_V
+//    and steps V, VI only Gamma_S, one band vector per pixel each, and
+//    S = z_V + Gamma_S / rho_V where S itself is needed.
 // Per pixel, given the new X from step I:
-//   V = soft(DCT(S - Gamma_S / rho_V), mu_nu / rho_V)       (step IV)
+//   V = soft(DCT(z_V), mu_nu / rho_V)                          (step IV)
 //   q = IDCT(V)
 //   S^+ = (rho_V q + rho_S X) / (rho_V + rho_S)               (step V)
 //   Gamma_S^+ = Gamma_S + rho_V (q - S^+)                      (step VI; also
 //       = Gamma_S + rho_S (S^+ - X) by the S-step's closed form)
+//   z_V <- S^+ - Gamma_S^+ / rho_V
 //   z_P <- X - max(0, -z_P);  z_T <- X + clip(z_T, tau_T)     (steps II, III, VI)
 // and the right-hand side of the next step I (eq. matB) is H^T Y + B_rest with
 // B_rest = rho_T (2 T - z_T) + rho_P |z_P| + Gamma_S + rho_S S.
@@ -45,10 +50,10 @@ __device__ __forceinline__ void spectral_body(const SpecArrays& A, const T* __re
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
     const int gs_ = A.gshift;
-    const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.S, bb, gs_},
+    const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_},
         GS{A.GS, bb, gs_}, Brest{A.Brest, bb, gs_};
     const BandArray<T> zPo{REDUCE ? A.zPo : A.zP, bb, gs_}, zTo{REDUCE ? A.zTo : A.zT, bb, gs_},
-        So{REDUCE ? A.So : A.S, bb, gs_}, GSo{REDUCE ? A.GSo : A.GS, bb, gs_};
+        zVo{REDUCE ? A.zVo : A.zV, bb, gs_}, GSo{REDUCE ? A.GSo : A.GS, bb, gs_};
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
     const T tauT = T(a.tau_T), tauV = T(a.tau_V);
@@ -56,9 +61,9 @@ __device__ __forceinline__ void spectral_body(const SpecArrays& A, const T* __re
     double v2 = 0.0;
 
     T v[LT];
-    // step IV: V = soft(DCT(S - Gamma_S / rho_V)) with the previous S, Gamma_S
+    // step IV: V = soft(DCT(z_V)) with the previous z_V = S - Gamma_S / rho_V
 #pragma unroll
-    for (int l = 0; l < LT; ++l) v[l] = (l < L) ? S.load(l, off) - GS.load(l, off) * inv_rhoV : T(0);
+    for (int l = 0; l < LT; ++l) v[l] = (l < L) ? zV.load(l, off) : T(0);
     dct_any<T, LT, DENSE, false>(v, D, L);
     // Phase boundaries keep each phase's band loads inside it: left free, the
     // scheduler hoists the next phase's loads above the register DCT and the
@@ -72,9 +77,7 @@ __device__ __forceinline__ void spectral_body(const SpecArrays& A, const T* __re
     }
     dct_any<T, LT, DENSE, true>(v, D, L);        // q = V W_nu^T
     __builtin_amdgcn_sched_barrier(0);
-    // steps II, III, V, VI, band by band.  Gamma_S is read again here: the
-    // compiler keeps the step-IV loads live instead (nothing is stored in
-    // between), one band vector more in registers and 4 B/voxel less traffic.
+    // steps II, III, V, VI, band by band
 #pragma unroll
     for (int l = 0; l < LT; ++l) {
         if (l < L) {
@@ -85,8 +88,12 @@ __device__ __forceinline__ void spectral_body(const SpecArrays& A, const T* __re
             const T zp2 = x - (zp < T(0) ? -zp : T(0));
             const T zt2 = x + clipt(zt, tauT);
             const T tt = softt(zt2, tauT);
-            const T b = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * s;
-            So.store(l, off, s);
+            // B_rest from S as the stored state gives it (as k_brest forms
+            // it), so a pass from a restored state repeats this one exactly
+            const T zv2 = s - gs2 * inv_rhoV;
+            const T sv = zv2 + gs2 * inv_rhoV;
+            const T b = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * sv;
+            zVo.store(l, off, zv2);
             GSo.store(l, off, gs2);
             zPo.store(l, off, zp2);
             zTo.store(l, off, zt2);
@@ -119,7 +126,7 @@ k_spectral_group(const SpecDesc* __restrict__ d, int n) {
     spectral_body<T, LT, DENSE, false>(d[j].A, (const T*)d[j].D, d[j].Lrt, d[j].a, nullptr, b);
 }
 
-// FP64 sums of a reporting pass from the old state (z_P, z_T, S, Gamma_S),
+// FP64 sums of a reporting pass from the old state (z_P, z_T, z_V, Gamma_S),
 // the new state (primed) and X, per block into partials[block * RED_NQ + q]
 // (RED_V2 copied from vpart[block], written by the spectral pass; RED_DCTP1
 // written by k_dct_l1):
@@ -141,18 +148,20 @@ k_report(SpecArrays A, int L, long npix, SpecArgs a, const double* __restrict__ 
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
     const int gs_ = A.gshift;
-    const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.S, bb, gs_},
-        GS{A.GS, bb, gs_}, zPo{A.zPo, bb, gs_}, zTo{A.zTo, bb, gs_}, So{A.So, bb, gs_},
+    const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_},
+        GS{A.GS, bb, gs_}, zPo{A.zPo, bb, gs_}, zTo{A.zTo, bb, gs_}, zVo{A.zVo, bb, gs_},
         GSo{A.GSo, bb, gs_};
     const T rP = T(a.rho_P), rT = T(a.rho_T), rV = T(a.rho_V), rS = T(a.rho_S), tT = T(a.tau_T);
     const T irP = T(1.0 / a.rho_P), irT = T(1.0 / a.rho_T), irV2 = T(1.0 / (a.rho_V * a.rho_V));
+    const T irV = T(1.0 / a.rho_V);
     const T ieS = T(1.0 / a.rho_S + 1.0 / a.rho_V), rSV = T(a.rho_S + a.rho_V);
     double r2 = 0, s2 = 0, x2 = 0, bz2 = 0, aty2 = 0, e = 0, p2 = 0, p1 = 0;
 #pragma unroll 2
     for (int l = 0; l < L; ++l) {
         const T x = X.load(l, off);
-        const T zp = zP.load(l, off), zt = zT.load(l, off), so = S.load(l, off), go = GS.load(l, off);
-        const T zp2 = zPo.load(l, off), zt2 = zTo.load(l, off), sn = So.load(l, off), gn = GSo.load(l, off);
+        const T zp = zP.load(l, off), zt = zT.load(l, off), go = GS.load(l, off);
+        const T zp2 = zPo.load(l, off), zt2 = zTo.load(l, off), gn = GSo.load(l, off);
+        const T so = zV.load(l, off) + go * irV, sn = zVo.load(l, off) + gn * irV;
         const T P = zp2 > T(0) ? zp2 : T(0), Po = zp > T(0) ? zp : T(0);
         const T Tn = softt(zt2, tT), To = softt(zt, tT);
         const T gp = rP * (zp2 < T(0) ? -zp2 : T(0)), gpo = rP * (zp < T(0) ? -zp : T(0));
@@ -300,27 +309,32 @@ hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, in
 // ------------------------------------------------------------------ element-wise
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_brest(const T* __restrict__ zP, const T* __restrict__ zT, const T* __restrict__ S,
+k_brest(const T* __restrict__ zP, const T* __restrict__ zT, const T* __restrict__ zV,
         const T* __restrict__ GS, T* __restrict__ Brest, long n, SpecArgs a) {
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoS = T(a.rho_S), tauT = T(a.tau_T);
+    const T inv_rhoV = T(1.0 / a.rho_V);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const T zt = zT[i];
-        Brest[i] = rhoT * (T(2) * softt(zt, tauT) - zt) + rhoP * fabs(zP[i]) + GS[i] + rhoS * S[i];
+        const T zt = zT[i], gs = GS[i];
+        const T sv = zV[i] + gs * inv_rhoV;
+        Brest[i] = rhoT * (T(2) * softt(zt, tauT) - zt) + rhoP * fabs(zP[i]) + gs + rhoS * sv;
     }
 }
 
-// Re-encode the prox inputs for new parameters so that P, Gamma_P (always)
-// and T, Gamma_T (when mu_s is unchanged) keep their values:
+// Re-encode the prox inputs for new parameters so that P, Gamma_P, S
+// (always) and T, Gamma_T (when mu_s is unchanged) keep their values:
 //   z_P' = max(0, z_P) - (rho_P / rho_P') max(0, -z_P)          (= P - Gamma_P / rho_P')
 //   z_T' = soft(z_T, tau) + (rho_T / rho_T') clip(z_T, tau)     (= T - Gamma_T / rho_T')
+//   z_V' = z_V + (1 / rho_V - 1 / rho_V') Gamma_S               (= S - Gamma_S / rho_V')
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_reencode(T* __restrict__ zP, T* __restrict__ zT, long n, double rP, double rT, double tau) {
-    const T ratioP = T(rP), ratioT = T(rT), t = T(tau);
+k_reencode(T* __restrict__ zP, T* __restrict__ zT, T* __restrict__ zV, const T* __restrict__ GS, long n,
+           double rP, double rT, double tau, double dV) {
+    const T ratioP = T(rP), ratioT = T(rT), t = T(tau), dv = T(dV);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const T zp = zP[i], zt = zT[i];
         zP[i] = (zp > T(0) ? zp : T(0)) - ratioP * (zp < T(0) ? -zp : T(0));
         zT[i] = softt(zt, t) + ratioT * clipt(zt, t);
+        if (dV != 0.0) zV[i] += dv * GS[i];
     }
 }
 
@@ -370,23 +384,25 @@ static unsigned grid_for(long n) {
     return (unsigned)b;
 }
 
-hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* S, const void* GS,
+hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* zV, const void* GS,
                         void* Brest, size_t n, const SpecArgs& a, hipStream_t s) {
     if (dtype == 0)
         hipLaunchKernelGGL((k_brest<float>), dim3(grid_for(n)), dim3(256), 0, s, (const float*)zP,
-                           (const float*)zT, (const float*)S, (const float*)GS, (float*)Brest, (long)n, a);
+                           (const float*)zT, (const float*)zV, (const float*)GS, (float*)Brest, (long)n, a);
     else
         hipLaunchKernelGGL((k_brest<double>), dim3(grid_for(n)), dim3(256), 0, s, (const double*)zP,
-                           (const double*)zT, (const double*)S, (const double*)GS, (double*)Brest, (long)n, a);
+                           (const double*)zT, (const double*)zV, (const double*)GS, (double*)Brest, (long)n, a);
     return hipGetLastError();
 }
 
-hipError_t launch_reencode(int dtype, void* zP, void* zT, size_t n, double rP, double rT, double tau,
-                           hipStream_t s) {
+hipError_t launch_reencode(int dtype, void* zP, void* zT, void* zV, const void* GS, size_t n, double rP,
+                           double rT, double tau, double dV, hipStream_t s) {
     if (dtype == 0)
-        hipLaunchKernelGGL((k_reencode<float>), dim3(grid_for(n)), dim3(256), 0, s, (float*)zP, (float*)zT, (long)n, rP, rT, tau);
+        hipLaunchKernelGGL((k_reencode<float>), dim3(grid_for(n)), dim3(256), 0, s, (float*)zP, (float*)zT,
+                           (float*)zV, (const float*)GS, (long)n, rP, rT, tau, dV);
     else
-        hipLaunchKernelGGL((k_reencode<double>), dim3(grid_for(n)), dim3(256), 0, s, (double*)zP, (double*)zT, (long)n, rP, rT, tau);
+        hipLaunchKernelGGL((k_reencode<double>), dim3(grid_for(n)), dim3(256), 0, s, (double*)zP, (double*)zT,
+                           (double*)zV, (const double*)GS, (long)n, rP, rT, tau, dV);
     return hipGetLastError();
 }
 

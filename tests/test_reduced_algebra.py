@@ -1,4 +1,4 @@
-"""The GPU path stores a reduced state (z_P, z_T, S, Gamma_S) instead of
+"""The GPU path stores a reduced state (z_P, z_T, z_V, Gamma_S) instead of
 Algorithm 1's nine arrays.  This pins that algebra against the explicit oracle
 in FP64.
 
@@ -11,6 +11,8 @@ optimality condition Gamma_S^+ = Gamma_V^+ W_nu^T holds after every pass;
 with Gamma_V = Gamma_S W_nu,
   V = soft(DCT(S - Gamma_S / rho_V), mu_nu / rho_V),  q = IDCT(V),
   S^+ = (rho_V q + rho_S X) / (rho_V + rho_S),  Gamma_S^+ = Gamma_S + rho_V (q - S^+).
+The state holds z_V = S - Gamma_S / rho_V (the DCT input of step IV) in place
+of S, and S = z_V + Gamma_S / rho_V where S enters b.
 """
 import numpy as np
 import pytest
@@ -23,21 +25,21 @@ pytestmark = pytest.mark.cpu
 def _reduced_run(prob, K):
     p = prob.p
     shape = prob.shape
-    zP, zT, S, GS = (np.zeros(shape) for _ in range(4))
+    zP, zT, zV, GS = (np.zeros(shape) for _ in range(4))
     tT, tV = p.mu_s / p.rho_T, p.mu_nu / p.rho_V
     Xs = []
     for _ in range(K):
         B = (prob.HtY + p.rho_T * (2 * O.soft(zT, tT) - zT) + p.rho_P * np.abs(zP)
-             + GS + p.rho_S * S)
+             + GS + p.rho_S * (zV + GS / p.rho_V))
         X = prob.solve_Q(B)
-        q = O.idct_nu(O.soft(O.dct_nu(S - GS / p.rho_V), tV))
+        q = O.idct_nu(O.soft(O.dct_nu(zV), tV))
         Sn = (p.rho_V * q + p.rho_S * X) / (p.rho_V + p.rho_S)
         GS = GS + p.rho_V * (q - Sn)
+        zV = Sn - GS / p.rho_V
         zP = X - np.maximum(0.0, -zP)
         zT = X + np.clip(zT, -tT, tT)
-        S = Sn
         Xs.append(X)
-    return Xs, dict(zP=zP, zT=zT, S=S, GS=GS)
+    return Xs, dict(zP=zP, zT=zT, S=zV + GS / p.rho_V, GS=GS)
 
 
 def test_gamma_S_equals_gamma_V_transformed_after_every_pass():
