@@ -45,6 +45,22 @@ template <typename T, int NY, int TC> constexpr int col_nth() {
     return n > 512 ? 512 : (n < 64 ? 64 : n);
 }
 
+// The column pass's constants (the data term conj(h_hat) y_hat and
+// |h_hat|^2, one value per packed half-spectrum point of each band) are
+// stored in column-block order: blocks of W adjacent kx columns, each
+// block's ny rows of W values contiguous, with W the tile width of the
+// default column schedule (col_tc_base, at most M).  A column tile then
+// reads them as consecutive runs instead of one short run per spectrum row.
+template <typename T> __device__ __forceinline__ int filt_shift(int ny, int M) {
+    int w = 65536 / (ny * int(sizeof(cx<T>)));
+    w = w > 16 ? 16 : (w < 1 ? 1 : w);
+    return __builtin_ctz(w < M ? w : M);
+}
+// offset of (ky, kx) in one band's block-ordered constants (sh = filt_shift)
+__device__ __forceinline__ long filt_pos(int ny, int sh, int ky, int kx) {
+    return ((long)(kx >> sh) * ny << sh) + ((long)ky << sh) + (kx & ((1 << sh) - 1));
+}
+
 template <int NTH> __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -216,6 +232,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
     const int band = int(wg / ntiles);
     const int c0 = int(wg % ntiles) * TC;
     const long base = (long)band * NY * M;
+    const int fsh = filt_shift<T>(NY, M);
     constexpr int NIT = (NY * TC + NTH - 1) / NTH;
     constexpr int NST = plan_nstages(NY);
     const int ntr = M - c0 < TC ? M - c0 : TC;      // columns of this tile inside the spectrum
@@ -238,7 +255,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             gp[j] = T(0);
             if constexpr (MODE == COL_SOLVE) yfp[j] = {T(0), T(0)};
             if (i < NY * TC && kx != 0 && kx < M) {
-                const long g = base + (long)y * M + kx;
+                const long g = base + filt_pos(NY, fsh, y, kx);
                 if constexpr (MODE == COL_SOLVE) yfp[j] = Yf[g];
                 gp[j] = scale / (H2[g] + rhoQ);
             }
@@ -262,7 +279,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
                 if constexpr (MODE == COL_SOLVE) v = v + yfp[j];
                 lds[swz_pos<NY, TC>(y, c)] = v * gp[j];
             } else {
-                const long g = base + (long)y * M + kx;
+                const long g = base + filt_pos(NY, fsh, y, kx);
                 if constexpr (MODE == COL_SOLVE) v = v + Yf[g];
                 lds[swz_pos<NY, TC>(y, c)] = v * (scale / (H2[g] + rhoQ));
             }
@@ -271,7 +288,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             // slot 0 packs the real columns kx = 0 (A) and kx = nx/2 (B): C = A + i B
             for (int ky = t; ky <= NY / 2; ky += NTH) {
                 const int kn = (NY - ky) & (NY - 1);
-                const long g1 = base + (long)ky * M, g2 = base + (long)kn * M;
+                const long g1 = base + filt_pos(NY, fsh, ky, 0), g2 = base + filt_pos(NY, fsh, kn, 0);
                 cx<T> c1 = lds[swz_pos<NY, TC>(ky, 0)], c2 = lds[swz_pos<NY, TC>(kn, 0)];
                 if constexpr (MODE == COL_SOLVE) {
                     c1 = c1 + Yf[g1];
@@ -315,7 +332,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         for (int i = t; i < NY * TC; i += NTH) {
             const int y = i / TC, c = i % TC, kx = c0 + c;
             if (kx == 0 || kx >= M) continue;
-            const long g = base + (long)y * M + kx;
+            const long g = base + filt_pos(NY, fsh, y, kx);
             const cx<T> z = lds[swz_pos<NY, TC>(y, c)], f = Yf[g];
             const double zz = double(z.x) * z.x + double(z.y) * z.y;
             const double cr = double(f.x) * z.x + double(f.y) * z.y;
@@ -324,7 +341,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         if (c0 == 0) {
             for (int ky = t; ky <= NY / 2; ky += NTH) {
                 const int kn = (NY - ky) & (NY - 1);
-                const long g1 = base + (long)ky * M, g2 = base + (long)kn * M;
+                const long g1 = base + filt_pos(NY, fsh, ky, 0), g2 = base + filt_pos(NY, fsh, kn, 0);
                 const cx<T> c1 = lds[swz_pos<NY, TC>(ky, 0)], c2 = lds[swz_pos<NY, TC>(kn, 0)];
                 const cx<T> f1 = Yf[g1], f2 = Yf[g2];
                 const cx<T> A = {T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)};
@@ -385,19 +402,23 @@ __global__ void __launch_bounds__(256)
 k_setup_combine(const cx<double>* __restrict__ Ch, const cx<double>* __restrict__ Cy,
                 cx<T>* __restrict__ Yf, T* __restrict__ H2, T* __restrict__ H2nyq, int L,
                 int ny, int M) {
+    // Ch, Cy in spectrum order [L][ny][M]; Yf, H2 written in column-block order
     const long n = (long)L * ny * M;
+    const int fsh = filt_shift<T>(ny, M);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const long band = i / ((long)ny * M);
         const long rem = i - band * ny * M;
         const int ky = int(rem / M), kx = int(rem % M);
+        const long o = band * ny * M + filt_pos(ny, fsh, ky, kx);
         if (kx != 0) {
             const cx<double> h = Ch[i], y = Cy[i];
             const cx<double> f = {h.x * y.x + h.y * y.y, h.x * y.y - h.y * y.x};   // conj(h) y
-            Yf[i] = {T(f.x), T(f.y)};
-            H2[i] = T(h.x * h.x + h.y * h.y);
+            Yf[o] = {T(f.x), T(f.y)};
+            H2[o] = T(h.x * h.x + h.y * h.y);
         } else if (ky <= ny / 2) {
             const int kn = (ny - ky) & (ny - 1);
             const long i2 = band * ny * M + (long)kn * M;
+            const long o2 = band * ny * M + filt_pos(ny, fsh, kn, 0);
             const cx<double> h1 = Ch[i], h2 = Ch[i2], y1 = Cy[i], y2 = Cy[i2];
             const cx<double> Ah = {0.5 * (h1.x + h2.x), 0.5 * (h1.y - h2.y)};
             const cx<double> Bh = {0.5 * (h1.y + h2.y), -0.5 * (h1.x - h2.x)};
@@ -406,11 +427,11 @@ k_setup_combine(const cx<double>* __restrict__ Ch, const cx<double>* __restrict_
             const cx<double> FA = {Ah.x * Ay.x + Ah.y * Ay.y, Ah.x * Ay.y - Ah.y * Ay.x};
             const cx<double> FB = {Bh.x * By.x + Bh.y * By.y, Bh.x * By.y - Bh.y * By.x};
             // packed: FA + i FB at ky, conj(FA) + i conj(FB) at -ky
-            Yf[i] = {T(FA.x - FB.y), T(FA.y + FB.x)};
-            Yf[i2] = {T(FA.x + FB.y), T(FB.x - FA.y)};
+            Yf[o] = {T(FA.x - FB.y), T(FA.y + FB.x)};
+            Yf[o2] = {T(FA.x + FB.y), T(FB.x - FA.y)};
             const T a2 = T(Ah.x * Ah.x + Ah.y * Ah.y), b2 = T(Bh.x * Bh.x + Bh.y * Bh.y);
-            H2[i] = a2;
-            H2[i2] = a2;
+            H2[o] = a2;
+            H2[o2] = a2;
             H2nyq[band * ny + ky] = b2;
             H2nyq[band * ny + kn] = b2;
         }

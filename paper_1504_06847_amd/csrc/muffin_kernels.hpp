@@ -55,7 +55,8 @@ hipError_t launch_row_inv(int dtype, const void* in, void* out, int nrows, int n
 // COL_SOLVE: FFT along y, X_hat = (Z + Yf) * scale / (H2 + rhoQ), inverse FFT.
 // COL_FWD: FFT along y only.  COL_OBJ: FFT along y, then per-block FP64
 // partials of sum w (H2 |Z|^2 - 2 Re(conj(Yf) Z)) / (nx ny) into partials.
-// COL_FILTER: as COL_SOLVE without the data term (Yf unused).
+// COL_FILTER: as COL_SOLVE without the data term (Yf unused).  Yf and H2
+// are in the column-block order launch_setup_combine writes (H2nyq: [L][ny]).
 hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const void* H2,
                       const void* H2nyq, double rhoQ, double scale, int L, int ny, int nx,
                       const void* tw, int twlog, double* partials, int* nblocks_out,
@@ -201,7 +202,10 @@ hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, in
 
 // Setup: combine the FP64 packed column spectra of the shifted PSF (Ch) and of
 // the dirty image (Cy) into conj(h_hat) y_hat (Yf), |h_hat|^2 (H2, and H2nyq
-// for the kx = nx/2 column), stored in the iteration's precision.
+// for the kx = nx/2 column), stored in the iteration's precision.  Yf and H2
+// go in column-block order: per band, blocks of W adjacent kx columns (W =
+// min(16, 64 KiB / (ny complex values), nx/2), the default column tile),
+// each block's ny rows contiguous.
 hipError_t launch_setup_combine(int dtype, const void* Ch, const void* Cy, void* Yf, void* H2,
                                 void* H2nyq, int L, int ny, int nx, hipStream_t s);
 
