@@ -69,8 +69,13 @@ constexpr double sqrt_c(double v) {
 // band_group_shift, groups of at most 1 GiB).  Callers mask lanes whose pixel lies outside the array.
 constexpr int kBufWord3 = 0x00020000;   // raw 32-bit data format, gfx9 family
 typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+// Cache-policy operand of the buffer instructions (CP below): 0 = default,
+// kStreamCpol = non-temporal (the NT bit), for arrays read and written once
+// per pass, so that they do not displace what the caches hold for reuse
+// (the spectrum between the two kernels of a pass, register spills).
+constexpr int kStreamCpol = 2;
 
-template <typename T> struct BandArray {
+template <typename T, int CP = 0> struct BandArray {
     char* base;
     unsigned band_bytes;
     int gshift;
@@ -84,38 +89,38 @@ template <typename T> struct BandArray {
     }
     __device__ __forceinline__ T load(int l, unsigned lane_off) const {
         if constexpr (sizeof(T) == 4) {
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(l), lane_off, soff(l), 0));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(l), lane_off, soff(l), CP));
         } else {
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(l), lane_off, soff(l), 0));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(l), lane_off, soff(l), CP));
         }
     }
     __device__ __forceinline__ void store(int l, unsigned lane_off, T v) const {
         if constexpr (sizeof(T) == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsrc(l), lane_off, soff(l), 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsrc(l), lane_off, soff(l), CP);
         } else {
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rsrc(l), lane_off, soff(l), 0);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rsrc(l), lane_off, soff(l), CP);
         }
     }
 };
 
 // The same for an array whose L bands all lie within 2^30 bytes of its base:
 // one descriptor for every band (the band offset is the scalar offset).
-template <typename T> struct BandArray1 {
+template <typename T, int CP = 0> struct BandArray1 {
     __amdgpu_buffer_rsrc_t r;
     unsigned band_bytes;
     __device__ __forceinline__ BandArray1(char* base, unsigned bb)
         : r(__builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7fffffff, kBufWord3)), band_bytes(bb) {}
     __device__ __forceinline__ T load(int l, unsigned lane_off) const {
         if constexpr (sizeof(T) == 4)
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, (unsigned)l * band_bytes, 0));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, lane_off, (unsigned)l * band_bytes, CP));
         else
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, (unsigned)l * band_bytes, 0));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, (unsigned)l * band_bytes, CP));
     }
     __device__ __forceinline__ void store(int l, unsigned lane_off, T v) const {
         if constexpr (sizeof(T) == 4)
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, lane_off, (unsigned)l * band_bytes, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, lane_off, (unsigned)l * band_bytes, CP);
         else
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, lane_off, (unsigned)l * band_bytes, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, lane_off, (unsigned)l * band_bytes, CP);
     }
 };
 
@@ -438,6 +443,14 @@ __device__ __forceinline__ void irfft_pre(const cx<T>* p, cx<T>* l, int k, const
         l[lds_pos<true>(k)] = e + mul_i(o);                         // Z_k = E + i O
         l[lds_pos<true>(M - k)] = conj(e) + mul_i(conj(o));
     }
+}
+
+// non-temporal loads of constants read once per pass
+template <typename T> __device__ __forceinline__ T stream_load(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T> __device__ __forceinline__ cx<T> stream_load(const cx<T>* p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return {v.x, v.y};
 }
 
 // ---------------------------------------------------------------- register FFT / DCT

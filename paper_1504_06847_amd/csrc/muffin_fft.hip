@@ -256,8 +256,8 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             if constexpr (MODE == COL_SOLVE) yfp[j] = {T(0), T(0)};
             if (i < NY * TC && kx != 0 && kx < M) {
                 const long g = base + filt_pos(NY, fsh, y, kx);
-                if constexpr (MODE == COL_SOLVE) yfp[j] = Yf[g];
-                gp[j] = scale / (H2[g] + rhoQ);
+                if constexpr (MODE == COL_SOLVE) yfp[j] = stream_load(Yf + g);
+                gp[j] = scale / (stream_load(H2 + g) + rhoQ);
             }
         }
     }
@@ -280,8 +280,8 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
                 lds[swz_pos<NY, TC>(y, c)] = v * gp[j];
             } else {
                 const long g = base + filt_pos(NY, fsh, y, kx);
-                if constexpr (MODE == COL_SOLVE) v = v + Yf[g];
-                lds[swz_pos<NY, TC>(y, c)] = v * (scale / (H2[g] + rhoQ));
+                if constexpr (MODE == COL_SOLVE) v = v + stream_load(Yf + g);
+                lds[swz_pos<NY, TC>(y, c)] = v * (scale / (stream_load(H2 + g) + rhoQ));
             }
         }
         if (c0 == 0) {

@@ -31,7 +31,7 @@ template <int NX, int LT> constexpr int fused_ppt() { return 1; }
 template <int LT> constexpr int fused_g() { return LT < 16 ? LT : (LT >= 64 ? 8 : 16); }
 // with 64 bands, q of the first fused_qb bands waits in LDS: the band vector
 // of the others plus the row transforms fill the registers
-template <int LT> constexpr int fused_qb() { return LT >= 64 ? 24 : 0; }
+template <int LT> constexpr int fused_qb() { return LT >= 64 ? 28 : 0; }
 
 template <typename T, int NX, int LT> struct FusedLds {
     static constexpr int NTH = NX / fused_ppt<NX, LT>();
@@ -39,6 +39,7 @@ template <typename T, int NX, int LT> struct FusedLds {
     cx<T> twl[tw_at<4>(NX)];                              // w_NX^i, i < NX (padded)
     T q[fused_qb<LT>() > 0 ? fused_qb<LT>() * NTH : 1];
 };
+static_assert(sizeof(FusedLds<float, 1024, 64>) <= 160 * 1024, "fused LDS exceeds 160 KiB");
 
 // One image row y of every band (see the head of this file).
 template <typename T, int NX, int LT, bool DENSE>
@@ -66,7 +67,8 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
     for (int p = 0; p < PPT; ++p) off[p] = (unsigned)((long)y * NX + t + p * NTH) * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
     // every band of an array within 2^30 bytes of its base (checked on the host)
-    const BandArray1<T> X(A.X, bb), zP(A.zP, bb), zT(A.zT, bb), zV(A.zV, bb), GS(A.GS, bb);
+    // the state and X stream through once per pass: non-temporal
+    const BandArray1<T, kStreamCpol> X(A.X, bb), zP(A.zP, bb), zT(A.zT, bb), zV(A.zV, bb), GS(A.GS, bb);
     cx<T>* Z = (cx<T>*)A.Z;
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
