@@ -50,9 +50,12 @@ __device__ __forceinline__ void spectral_body(const SpecArrays& A, const T* __re
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
     const int gs_ = A.gshift;
-    const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_},
-        GS{A.GS, bb, gs_}, Brest{A.Brest, bb, gs_};
-    const BandArray<T> zPo{REDUCE ? A.zPo : A.zP, bb, gs_}, zTo{REDUCE ? A.zTo : A.zT, bb, gs_},
+    // X (written by the row pass just before) and B_rest (read by the next
+    // one) through the caches; the state streams through (non-temporal)
+    const BandArray<T> X{A.X, bb, gs_}, Brest{A.Brest, bb, gs_};
+    const BandArray<T, kStreamCpol> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_},
+        GS{A.GS, bb, gs_};
+    const BandArray<T, kStreamCpol> zPo{REDUCE ? A.zPo : A.zP, bb, gs_}, zTo{REDUCE ? A.zTo : A.zT, bb, gs_},
         zVo{REDUCE ? A.zVo : A.zV, bb, gs_}, GSo{REDUCE ? A.GSo : A.GS, bb, gs_};
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
