@@ -15,8 +15,9 @@ What it computes, and where the paper defines it
   adjoint H_l^T is circular correlation (multiplication by conj(h_hat)).
 * Criterion (eqs. costreg, RegAll): 1/2 ||Y - HX||^2 + 1_{R+}(X)
   + mu_eps/2 ||X||_F^2 + mu_s ||W_s X||_1 + mu_nu ||X W_nu||_1, with W_s the
-  Dirac basis (identity, n_s = 1) and W_nu the orthonormal DCT-II along the
-  band axis.
+  Dirac basis (identity, n_s = 1) or a union of n_s orthonormal bases (the
+  Dirac basis and Daubechies wavelets, Section 4; ``oracle/wavelets.py``) and
+  W_nu the orthonormal DCT-II along the band axis.
 * Algorithm 1 (Section 3, steps I-VI): all nine arrays X, P, T, V, S,
   Gamma_P, Gamma_T, Gamma_V, Gamma_S are stored explicitly and start at zero.
   Step I solves Q_l x_l = b_l with Q_l = H_l^T H_l + rho I,
@@ -42,6 +43,8 @@ from dataclasses import dataclass, fields
 
 import numpy as np
 import scipy.fft as sfft
+
+from .wavelets import DIRAC, Dictionary
 
 _WORKERS = int(os.environ.get("MUFFIN_ORACLE_WORKERS", "1"))
 
@@ -102,26 +105,33 @@ class Params:
         # eq. Qlsimp with the Dirac basis: n_s = 1
         return self.mu_eps + self.rho_S + self.rho_P + 1.0 * self.rho_T
 
+    def rho_Q_for(self, n_s: int):
+        # eq. Qlsimp for a union of n_s orthonormal bases
+        return self.mu_eps + self.rho_S + self.rho_P + float(n_s) * self.rho_T
+
 
 class Problem:
-    """One cube: PSFs, dirty images and parameters, all in float64."""
+    """One cube: PSFs, dirty images and parameters, all in float64.
+    ``bases``: the spatial dictionary W_s (codes of ``oracle/wavelets.py``;
+    the Dirac basis alone by default)."""
 
-    def __init__(self, psf, dirty, params):
+    def __init__(self, psf, dirty, params, bases=(DIRAC,)):
         self.psf = np.asarray(psf, dtype=np.float64)
         self.Y = np.asarray(dirty, dtype=np.float64)
         assert self.psf.shape == self.Y.shape and self.psf.ndim == 3
         self.p = Params.from_any(params)
+        self.W = Dictionary(bases)
         # transfer function of H_l: PSF peak moved to lag (0, 0)
         self.hhat = _fft2(np.fft.ifftshift(self.psf, axes=(-2, -1)))
         self.HtY = self.HT(self.Y)
         self._set_filter()
 
     def _set_filter(self):
-        self.filt = 1.0 / (np.abs(self.hhat) ** 2 + self.p.rho_Q)
+        self.filt = 1.0 / (np.abs(self.hhat) ** 2 + self.rho_Q)
 
     def with_params(self, params):
         q = object.__new__(Problem)
-        q.psf, q.Y, q.hhat, q.HtY = self.psf, self.Y, self.hhat, self.HtY
+        q.psf, q.Y, q.hhat, q.HtY, q.W = self.psf, self.Y, self.hhat, self.HtY, self.W
         q.p = Params.from_any(params)
         q._set_filter()
         return q
@@ -129,6 +139,30 @@ class Problem:
     @property
     def shape(self):
         return self.Y.shape
+
+    @property
+    def n_s(self) -> int:
+        return self.W.n_s
+
+    @property
+    def rho_Q(self) -> float:
+        return self.p.rho_Q_for(self.n_s)
+
+    @property
+    def dirac_only(self) -> bool:
+        return self.W.bases == (DIRAC,)
+
+    def Ws(self, x):
+        """W_s x: x itself for the Dirac basis alone, else the stacked
+        coefficient cubes [n_s][L][ny][nx]."""
+        return x if self.dirac_only else self.W.forward(x)
+
+    def WsT(self, c):
+        """W_s^T c (the adjoint of ``Ws``)."""
+        return c if self.dirac_only else self.W.adjoint(c)
+
+    def zero_state(self):
+        return State.zeros(self.shape, 1 if self.dirac_only else self.n_s)
 
     def H(self, x):
         """Band-wise circular convolution with the PSF (eq. nbmodel)."""
@@ -156,8 +190,13 @@ class State:
     GS: np.ndarray
 
     @classmethod
-    def zeros(cls, shape):
-        return cls(*(np.zeros(shape) for _ in range(9)))
+    def zeros(cls, shape, n_s: int = 1):
+        """All nine arrays zero; with n_s > 1 bases T and Gamma_T hold one
+        coefficient cube per basis ([n_s][L][ny][nx])."""
+        tshape = tuple(shape) if n_s == 1 else (n_s,) + tuple(shape)
+        a = [np.zeros(tshape) if f in ("T", "GT") else np.zeros(shape)
+             for f in ("X", "P", "T", "V", "S", "GP", "GT", "GV", "GS")]
+        return cls(*a)
 
     def copy(self):
         return State(*(getattr(self, f.name).copy() for f in fields(self)))
@@ -166,14 +205,14 @@ class State:
 def admm_iteration(prob: Problem, st: State) -> State:
     """One pass of Algorithm 1: steps I-VI in the paper's order."""
     p = prob.p
-    # Step I: b_l from eq. matB (W_s = identity), then Q_l x_l = b_l
-    B = (prob.HtY + (st.GT + p.rho_T * st.T) + st.GP + p.rho_P * st.P
+    # Step I: b_l from eq. matB, then Q_l x_l = b_l
+    B = (prob.HtY + prob.WsT(st.GT + p.rho_T * st.T) + st.GP + p.rho_P * st.P
          + st.GS + p.rho_S * st.S)
     X = prob.solve_Q(B)
     # Step II: positivity
     P = np.maximum(0.0, X - st.GP / p.rho_P)
-    # Step III: spatial soft threshold (W_s X = X)
-    WX = X
+    # Step III: spatial soft threshold, per coefficient of every basis
+    WX = prob.Ws(X)
     T = soft(WX - st.GT / p.rho_T, p.mu_s / p.rho_T)
     # Step IV: spectral soft threshold, on the S of the previous pass
     V = soft(dct_nu(st.S) - st.GV / p.rho_V, p.mu_nu / p.rho_V)
@@ -191,7 +230,7 @@ def run(prob: Problem, K: int, state: State | None = None, callback=None) -> Sta
     """K passes of Algorithm 1 from the all-zero state (or from ``state``).
 
     ``callback(k, prev, cur)`` is called after pass k (1-based)."""
-    st = State.zeros(prob.shape) if state is None else state
+    st = prob.zero_state() if state is None else state
     for k in range(1, K + 1):
         nxt = admm_iteration(prob, st)
         if callback is not None:
@@ -205,7 +244,7 @@ def objective(prob: Problem, P: np.ndarray) -> float:
     p = prob.p
     r = prob.Y - prob.H(P)
     return float(0.5 * np.sum(r * r) + 0.5 * p.mu_eps * np.sum(P * P)
-                 + p.mu_s * np.sum(np.abs(P)) + p.mu_nu * np.sum(np.abs(dct_nu(P))))
+                 + p.mu_s * np.sum(np.abs(prob.Ws(P))) + p.mu_nu * np.sum(np.abs(dct_nu(P))))
 
 
 def residuals(prob: Problem, prev: State, cur: State, eps_abs=1e-5, eps_rel=1e-4):
@@ -214,18 +253,19 @@ def residuals(prob: Problem, prev: State, cur: State, eps_abs=1e-5, eps_rel=1e-4
     Constraints P - X, T - W_s X, V - S W_nu, S - X; block 1 = (X, V),
     block 2 = (P, T, S)."""
     p = prob.p
-    r2 = (np.sum((cur.P - cur.X) ** 2) + np.sum((cur.T - cur.X) ** 2)
+    WX = prob.Ws(cur.X)
+    r2 = (np.sum((cur.P - cur.X) ** 2) + np.sum((cur.T - WX) ** 2)
           + np.sum((cur.V - dct_nu(cur.S)) ** 2) + np.sum((cur.S - cur.X) ** 2))
     dP, dT, dS = cur.P - prev.P, cur.T - prev.T, cur.S - prev.S
-    sX = p.rho_P * dP + p.rho_T * dT + p.rho_S * dS
+    sX = p.rho_P * dP + p.rho_T * prob.WsT(dT) + p.rho_S * dS
     sV = p.rho_V * dct_nu(dS)
     s2 = np.sum(sX ** 2) + np.sum(sV ** 2)
     nvox = cur.X.size
-    Ax = np.sqrt(3.0 * np.sum(cur.X ** 2) + np.sum(cur.V ** 2))
+    Ax = np.sqrt(2.0 * np.sum(cur.X ** 2) + np.sum(WX ** 2) + np.sum(cur.V ** 2))
     Bz = np.sqrt(np.sum(cur.P ** 2) + np.sum(cur.T ** 2) + np.sum(dct_nu(cur.S) ** 2)
                  + np.sum(cur.S ** 2))
-    Aty = np.sqrt(np.sum((cur.GP + cur.GT + cur.GS) ** 2) + np.sum(cur.GV ** 2))
-    eps_pri = np.sqrt(4.0 * nvox) * eps_abs + eps_rel * max(Ax, Bz)
+    Aty = np.sqrt(np.sum((cur.GP + prob.WsT(cur.GT) + cur.GS) ** 2) + np.sum(cur.GV ** 2))
+    eps_pri = np.sqrt((3.0 + prob.n_s) * nvox) * eps_abs + eps_rel * max(Ax, Bz)
     eps_dual = np.sqrt(2.0 * nvox) * eps_abs + eps_rel * Aty
     return dict(r=float(np.sqrt(r2)), s=float(np.sqrt(s2)),
                 eps_pri=float(eps_pri), eps_dual=float(eps_dual))
@@ -252,7 +292,8 @@ def mse_loss(XK, sky) -> float:
 
 
 def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params):
-    """Primal pass of Algorithm 1 with its forward-mode tangent."""
+    """Primal pass of Algorithm 1 with its forward-mode tangent (Dirac W_s)."""
+    assert prob.dirac_only, "the tangent pass is written for W_s = identity"
     p = prob.p
     drhoQ = dp.mu_eps + dp.rho_S + dp.rho_P + dp.rho_T
     B = (prob.HtY + st.GT + p.rho_T * st.T + st.GP + p.rho_P * st.P

@@ -71,3 +71,32 @@ def brute_min(f, center, halfwidth, n_grid=4001, n_golden=200):
         c, d = c2, d2
         fc, fd = f(c[..., None])[..., 0], f(d[..., None])[..., 0]
     return 0.5 * (a + b)
+
+
+def dense_dwt_matrix(h, ny, nx, levels):
+    """Dense matrix of the periodised multi-level 2-D DWT (Mallat layout), row
+    per coefficient, built from the one-level definition with plain loops:
+    level j maps the top-left (ny >> j) x (nx >> j) block through
+      c[i, m] = sum_{a, b} f_y[a] f_x[b] x[(2 i + a) mod sy, (2 m + b) mod sx]
+    with (f_y, f_x) in {h, g}^2, g[k] = (-1)^k h[K-1-k], and leaves the rest."""
+    K = len(h)
+    g = [(-1) ** k * h[K - 1 - k] for k in range(K)]
+    n = ny * nx
+    M = np.eye(n)
+    for j in range(levels):
+        sy, sx = ny >> j, nx >> j
+        Lj = np.eye(n)
+        for q in range(sy * sx):                   # clear the transformed block
+            qy, qx = divmod(q, sx)
+            Lj[qy * nx + qx, qy * nx + qx] = 0.0
+        for by, fy in ((0, h), (1, g)):
+            for bx, fx in ((0, h), (1, g)):
+                for i in range(sy // 2):
+                    for m in range(sx // 2):
+                        row = (by * (sy // 2) + i) * nx + bx * (sx // 2) + m
+                        for a in range(K):
+                            for b in range(K):
+                                col = ((2 * i + a) % sy) * nx + (2 * m + b) % sx
+                                Lj[row, col] += fy[a] * fx[b]
+        M = Lj @ M
+    return M

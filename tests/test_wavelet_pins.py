@@ -1,0 +1,131 @@
+"""Pins of the oracle's spatial dictionary (Section 4: W_s = the Dirac basis
+and the Daubechies wavelet bases Db1-Db8): the filters against closed forms
+and their defining properties, the periodised 2-D transform against a dense
+matrix built by loops from its definition, orthonormality, and the ADMM with
+a union of bases against special cases and a KKT certificate."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.independent import dct_matrix, dense_conv_matrix, dense_dwt_matrix, spec_t
+
+pytestmark = pytest.mark.cpu
+
+
+def test_db1_db2_db3_closed_forms():
+    r2 = math.sqrt(2.0)
+    np.testing.assert_allclose(O.daubechies_filter(1), [1 / r2, 1 / r2], atol=1e-15)
+    s3 = math.sqrt(3.0)
+    db2 = np.array([1 + s3, 3 + s3, 3 - s3, 1 - s3]) / (4 * r2)
+    np.testing.assert_allclose(O.daubechies_filter(2), db2, atol=1e-14)
+    s10 = math.sqrt(10.0)
+    r = math.sqrt(5 + 2 * s10)
+    db3 = np.array([1 + s10 + r, 5 + s10 + 3 * r, 10 - 2 * s10 + 2 * r,
+                    10 - 2 * s10 - 2 * r, 5 + s10 - 3 * r, 1 + s10 - r]) / (16 * r2)
+    np.testing.assert_allclose(O.daubechies_filter(3), db3, atol=1e-13)
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_filter_properties(p):
+    """Length 2p, sum sqrt 2, orthonormal to its even shifts, p vanishing
+    moments of the wavelet filter, extra zeros outside the unit circle."""
+    h = O.daubechies_filter(p)
+    K = len(h)
+    assert K == 2 * p
+    assert abs(h.sum() - math.sqrt(2.0)) < 1e-13
+    for m in range(0, p):
+        dot = sum(h[k] * h[k + 2 * m] for k in range(K - 2 * m))
+        assert abs(dot - (1.0 if m == 0 else 0.0)) < 1e-12, m
+    g = np.array([(-1) ** k * h[K - 1 - k] for k in range(K)])
+    k = np.arange(K, dtype=np.float64)
+    for m in range(p):
+        mom = np.sum(k ** m * g)
+        assert abs(mom) < 1e-10 * max(1.0, np.sum(np.abs(k ** m * g))), (p, m, mom)
+    # h(z) = (1 + z)^p r(z): the zeros of r lie outside the unit circle
+    r = np.array(h[::-1])
+    for _ in range(p):
+        r, rem = np.polydiv(r, [1.0, 1.0])
+        assert np.abs(rem).max() < 1e-9
+    if len(r) > 1:
+        assert np.abs(np.roots(r)).min() > 1.0 + 1e-6
+
+
+@pytest.mark.parametrize("p,ny,nx", [(1, 8, 8), (2, 8, 16), (4, 16, 8), (8, 8, 8), (3, 4, 4)])
+def test_dwt2_equals_dense_definition_and_is_orthonormal(p, ny, nx):
+    h = O.daubechies_filter(p)
+    J = O.dwt_levels(nx, ny)
+    M = dense_dwt_matrix(list(h), ny, nx, J)
+    np.testing.assert_allclose(M @ M.T, np.eye(ny * nx), atol=1e-12)
+    rng = np.random.default_rng(p)
+    x = rng.standard_normal((2, ny, nx))
+    c = O.dwt2(x, h, J)
+    for b in range(2):
+        np.testing.assert_allclose(c[b].ravel(), M @ x[b].ravel(), atol=1e-12)
+        np.testing.assert_allclose(O.idwt2(c, h, J)[b].ravel(), M.T @ c[b].ravel(), atol=1e-12)
+    np.testing.assert_allclose(O.idwt2(c, h, J), x, atol=1e-12)
+
+
+def test_levels_reading_and_constant_image():
+    """4 levels, fewer on small images; a constant image keeps only the
+    coarsest LL block, scaled by 2 per level ((sum h)^2 = 2)."""
+    assert O.dwt_levels(1024, 1024) == 4 and O.dwt_levels(8, 8) == 2 and O.dwt_levels(4, 64) == 1
+    for p in (1, 2, 5, 8):
+        c = O.dwt2(np.full((1, 32, 32), 3.0), O.daubechies_filter(p), 4)
+        np.testing.assert_allclose(c[0, :2, :2], 3.0 * 2 ** 4, atol=1e-11)
+        c[0, :2, :2] = 0.0
+        assert np.abs(c).max() < 1e-11
+
+
+def test_dictionary_is_a_union_of_orthonormal_bases():
+    rng = np.random.default_rng(3)
+    W = O.Dictionary(O.PAPER_DICTIONARY)
+    assert W.n_s == 9
+    x = rng.standard_normal((2, 16, 32))
+    np.testing.assert_allclose(W.adjoint(W.forward(x)), 9 * x, atol=1e-11)
+    c = rng.standard_normal((9, 2, 16, 32))
+    assert abs(np.sum(W.forward(x) * c) - np.sum(x * W.adjoint(c))) < 1e-10
+
+
+def test_two_dirac_bases_reach_the_dirac_minimiser_with_twice_mu_s():
+    """||[I; I] X||_1 = 2 ||X||_1: the limits agree (the iterates differ:
+    rho of eq. Qlsimp counts n_s)."""
+    rng = np.random.default_rng(8)
+    L, n = 2, 8
+    psf = rng.uniform(0.0, 0.3, (L, n, n))
+    psf[:, n // 2, n // 2] = 1.0
+    Y = rng.uniform(-0.2, 1.5, (L, n, n))
+    p = O.Params(1e-2, 0.05, 0.1, 1.0, 1.0, 1.0, 1.0)
+    a = O.run(O.Problem(psf, Y, p, bases=(O.DIRAC, O.DIRAC)), 3000).X
+    b = O.run(O.Problem(psf, Y, p.with_(mu_s=2 * p.mu_s)), 3000).X
+    np.testing.assert_allclose(a, b, atol=1e-9)
+
+
+def test_kkt_certificate_with_wavelet_dictionary():
+    """At the ADMM limit with W_s = (Dirac, Db1, Db2): H^T(HX - Y) + mu_eps X
+    - Gamma_P - W_s^T Gamma_T - Gamma_V W_nu^T = 0, Gamma_T = -mu_s sign(T)
+    where T != 0 and |Gamma_T| <= mu_s, with dense H, W_s and W_nu."""
+    rng = np.random.default_rng(9)
+    L, n = 2, 8
+    psf = rng.uniform(0.0, 0.3, (L, n, n))
+    psf[:, n // 2, n // 2] = 1.0
+    Y = rng.uniform(-0.2, 1.5, (L, n, n))
+    p = O.Params(1e-2, 0.03, 0.1, 1.0, 1.0, 1.0, 1.0)
+    bases = (O.DIRAC, 1, 2)
+    prob = O.Problem(psf, Y, p, bases=bases)
+    st = O.run(prob, 6000)
+    J = O.dwt_levels(n, n)
+    Wb = [np.eye(n * n)] + [dense_dwt_matrix(list(O.daubechies_filter(q)), n, n, J) for q in bases[1:]]
+    Hd = [dense_conv_matrix(psf[l]) for l in range(L)]
+    WsT_GT = np.stack([sum(Wb[i].T @ st.GT[i, l].ravel() for i in range(3)).reshape(n, n)
+                       for l in range(L)])
+    HtHX = np.stack([(Hd[l].T @ (Hd[l] @ st.X[l].ravel() - Y[l].ravel())).reshape(n, n) for l in range(L)])
+    g = HtHX + p.mu_eps * st.X - st.GP - WsT_GT - spec_t(st.GV, dct_matrix(L))
+    assert np.abs(g).max() < 1e-8
+    for i in range(3):
+        WX = np.stack([(Wb[i] @ st.X[l].ravel()).reshape(n, n) for l in range(L)])
+        assert np.abs(st.T[i] - WX).max() < 1e-8           # the constraint T = W_s X holds
+    nz = np.abs(st.T) > 1e-6
+    np.testing.assert_allclose(st.GT[nz], -p.mu_s * np.sign(st.T[nz]), atol=1e-8)
+    assert np.abs(st.GT).max() <= p.mu_s + 1e-9
