@@ -12,7 +12,9 @@
  *
  * with the ADMM iteration of Algorithm 1 (Section 3, steps I-VI).  H_l is a
  * 2-D circular convolution with the band-l PSF (eq. nbmodel), W_s is the
- * Dirac basis (n_s = 1), W_nu the orthonormal DCT-II along the bands.  Step I
+ * Dirac basis (n_s = 1) or the Dirac basis followed by up to eight
+ * orthonormal Daubechies wavelet bases (Section 4 uses Db1-Db8, n_s = 9),
+ * W_nu the orthonormal DCT-II along the bands.  Step I
  * is solved exactly in the Fourier domain with the filter
  * (|h_hat_l|^2 + rho)^{-1}, rho = mu_eps + rho_S + rho_P + n_s rho_T
  * (eq. Qlsimp and the paragraph after it).
@@ -56,7 +58,19 @@ extern "C" {
 #define MUFFIN_F32 0
 #define MUFFIN_F64 1
 
-#define MUFFIN_DIRAC 0             /* W_s = identity (the only spatial basis built) */
+#define MUFFIN_DIRAC 0             /* the Dirac basis (identity) */
+/* Daubechies wavelet basis Db_p (p vanishing moments, filter length 2p;
+   scaling filter by Daubechies' spectral factorisation, extra zeros outside
+   the unit circle), periodised, 4 levels (fewer when the smaller image side
+   is below 32: levels = min(4, log2(min(nx, ny)) - 1)), Mallat layout */
+#define MUFFIN_DB1 1
+#define MUFFIN_DB2 2
+#define MUFFIN_DB3 3
+#define MUFFIN_DB4 4
+#define MUFFIN_DB5 5
+#define MUFFIN_DB6 6
+#define MUFFIN_DB7 7
+#define MUFFIN_DB8 8
 #define MUFFIN_DCT2_ORTHO 0        /* W_nu = orthonormal DCT-II along the bands */
 
 #define MUFFIN_MODE_MSE 0          /* muffin_grad: loss = ||x_K - sky||^2, sky given */
@@ -80,8 +94,12 @@ typedef struct {
     /* augmented-Lagrangian parameters of the four constraints P = X,
        T = W_s X, V = S W_nu, S = X (eq. admm2), all > 0 */
     double rho_P, rho_T, rho_V, rho_S;
-    int n_s;          /* number of spatial bases; must be 1 */
-    int spatial[9];   /* spatial[0] = MUFFIN_DIRAC; others ignored */
+    int n_s;          /* number of spatial bases W_s stacks, 1 <= n_s <= 9 */
+    int spatial[9];   /* spatial[0] = MUFFIN_DIRAC; spatial[1 .. n_s-1] in
+                         MUFFIN_DB1 .. MUFFIN_DB8.  With n_s > 1: the
+                         three-launch pass, no convergence reports
+                         (muffin_step_report, muffin_solve), no gradient and
+                         no batches (MUFFIN_EUNSUPPORTED) */
     int spectral;     /* MUFFIN_DCT2_ORTHO */
     int check_every;  /* muffin_solve: iterations between FP64 residual checks (>= 1) */
     double eps_abs, eps_rel;   /* stopping tolerances of Boyd et al. (2011), Sec. 3.3.1 */
@@ -107,6 +125,12 @@ size_t muffin_workspace_bytes(const muffin_shape* shape, const muffin_params* pa
 /* Host-only validation of a shape and parameter set: MUFFIN_OK or the code
    muffin_setup would return before touching the device. */
 int muffin_validate(const muffin_shape* shape, const muffin_params* params);
+
+/* Host-only: the scaling filter of the wavelet basis Db_p (MUFFIN_DB1 <= p
+   <= MUFFIN_DB8; Section 4's dictionary) into h[0 .. 2p-1], FP64, as the
+   library's wavelet passes use it (wavelet filter g[k] = (-1)^k h[2p-1-k]).
+   Errors: EINVAL (p out of range or h NULL). */
+int muffin_wavelet_filter(int p, double* h);
 
 /* Set up one cube: derives |h_hat_l|^2 and conj(h_hat_l) FFT2(y_l) in FP64
    (stored in the shape's precision) into `workspace`, scans psf/dirty for

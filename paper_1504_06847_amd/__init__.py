@@ -8,6 +8,6 @@ Importing the package does not touch the GPU; ``lib.load()`` (called by
 from . import lib
 from .autograd import MuffinUnroll
 from .batch import Batch
-from .solver import Solver
+from .solver import PAPER_DICTIONARY, Solver
 
-__all__ = ["lib", "Batch", "MuffinUnroll", "Solver"]
+__all__ = ["lib", "Batch", "MuffinUnroll", "PAPER_DICTIONARY", "Solver"]

@@ -19,7 +19,7 @@ using namespace muffin;
 namespace {
 
 bool use_fused(const muffin_ctx* c) {
-    return c->fused && fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L);
+    return c->fused && c->lay.n_w == 0 && fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L);
 }
 
 // the row pass of step I: Z = row spectra of B_rest, unless Z holds them
@@ -106,7 +106,8 @@ int pass_kernels(muffin_ctx* c) {
     }
     int rc = step_one(c);
     if (rc) return rc;
-    return step_spectral(c, false, nullptr);
+    if ((rc = step_spectral(c, false, nullptr))) return rc;
+    return c->lay.n_w ? dict_pass(c) : MUFFIN_OK;
 }
 
 void drop_graphs(muffin_ctx* c) {
@@ -166,7 +167,7 @@ int recompute_brest(muffin_ctx* c) {
     HIP_TRY(launch_brest(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), st(c, ST_ZV), st(c, ST_GS),
                          P(c, c->lay.brest), voxels(c->shape), spec_args(c->params), c->stream));
     c->zvalid = 0;
-    return MUFFIN_OK;
+    return c->lay.n_w ? dict_brest(c) : MUFFIN_OK;
 }
 
 int zero_state(muffin_ctx* c) {
@@ -444,7 +445,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
         set_error("psf, dirty and workspace must be non-NULL device pointers");
         return MUFFIN_EINVAL;
     }
-    const Layout lay = make_layout(shape);
+    const Layout lay = make_layout(shape, params->n_s);
     if (ws_bytes < lay.total) {
         set_error("workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, lay.total);
         return MUFFIN_EWORKSPACE;
@@ -467,7 +468,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     c->twlog = ilog2i(NT);
     c->row_v = kDefaultRowVariant;
     c->col_v = kDefaultColVariant;
-    c->fused = kDefaultFused;
+    c->fused = lay.n_w ? 0 : kDefaultFused;    // the fused kernel serves the Dirac basis alone
     c->zvalid = 0;
     c->version = 0;
     c->grad_buf = nullptr;
@@ -506,6 +507,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     }
     c->ynorm2 = h[1];
     if ((rc = upload_tables(c)) != MUFFIN_OK) return fail(rc);
+    if ((rc = dict_setup(c)) != MUFFIN_OK) return fail(rc);
     // FP64 transforms of the shifted PSF and of the dirty image, in the (not yet
     // used) state region
     char* Ch = P(c, lay.state[0][0]);
@@ -543,14 +545,22 @@ int muffin_iterate(muffin_ctx* c, int n_iter) {
     return MUFFIN_OK;
 }
 
+static int no_wavelets(const muffin_ctx* c, const char* what) {
+    if (c->lay.n_w == 0) return MUFFIN_OK;
+    set_error("%s: not built for a spatial dictionary with wavelet bases (n_s = %d)", what, c->params.n_s);
+    return MUFFIN_EUNSUPPORTED;
+}
+
 int muffin_step_report(muffin_ctx* c, muffin_report* rep) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = no_wavelets(c, "convergence reports")) return rc;
     if (!rep) { set_error("report is NULL"); return MUFFIN_EINVAL; }
     return pass_with_report(c, rep);
 }
 
 int muffin_solve(muffin_ctx* c, int max_iter, muffin_report* report) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = no_wavelets(c, "muffin_solve (convergence reports)")) return rc;
     if (max_iter < 1) { set_error("max_iter = %d < 1", max_iter); return MUFFIN_EINVAL; }
     muffin_report rep{};
     int done = 0;
@@ -583,9 +593,18 @@ int muffin_get_p(muffin_ctx* c, void* p_out) {
     return MUFFIN_OK;
 }
 
+// state arrays of a snapshot: the four of the reduced state, X, then the
+// coefficient cube z_b of every wavelet basis
+static int snapshot_arrays(const muffin_ctx* c) { return kNumState + 1 + c->lay.n_w; }
+static char* snapshot_array(muffin_ctx* c, int i) {
+    if (i < kNumState) return (char*)st(c, i);
+    if (i == kNumState) return P(c, c->lay.x);
+    return P(c, c->lay.wz[i - kNumState - 1]);
+}
+
 size_t muffin_state_bytes(const muffin_ctx* c) {
     if (!c) return 0;
-    return kAlign + (kNumState + 1) * state_array_bytes(c);
+    return kAlign + snapshot_arrays(c) * state_array_bytes(c);
 }
 
 int muffin_get_state(muffin_ctx* c, void* dst) {
@@ -600,10 +619,9 @@ int muffin_get_state(muffin_ctx* c, void* dst) {
     // every byte of the blob is defined: header block zero-padded, gaps zeroed
     int64_t hdr[kAlign / 8] = {0x4d554646494e5354LL, c->iters, c->shape.dtype, (int64_t)voxels(c->shape)};
     HIP_TRY(hipMemcpy(d, hdr, sizeof(hdr), hipMemcpyHostToDevice));
-    for (int i = 0; i <= kNumState; ++i) {
+    for (int i = 0; i < snapshot_arrays(c); ++i) {
         char* a = d + kAlign + i * ab;
-        HIP_TRY(hipMemcpyAsync(a, i < kNumState ? st(c, i) : P(c, c->lay.x), nb,
-                               hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(a, snapshot_array(c, i), nb, hipMemcpyDeviceToDevice, c->stream));
         if (ab > nb) HIP_TRY(launch_fill_zero(a + nb, ab - nb, c->stream));
     }
     return MUFFIN_OK;
@@ -624,9 +642,8 @@ int muffin_set_state(muffin_ctx* c, const void* src) {
         set_error("state buffer does not hold a state of this shape and dtype");
         return MUFFIN_EINVAL;
     }
-    for (int i = 0; i < kNumState; ++i)
-        HIP_TRY(hipMemcpyAsync(st(c, i), s + kAlign + i * ab, nb, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(P(c, c->lay.x), s + kAlign + kNumState * ab, nb, hipMemcpyDeviceToDevice, c->stream));
+    for (int i = 0; i < snapshot_arrays(c); ++i)
+        HIP_TRY(hipMemcpyAsync(snapshot_array(c, i), s + kAlign + i * ab, nb, hipMemcpyDeviceToDevice, c->stream));
     c->iters = (int)hdr[1];
     return recompute_brest(c);
 }
@@ -635,6 +652,11 @@ int muffin_set_params(muffin_ctx* c, const muffin_params* params) {
     if (int rc = check_ctx(c)) return rc;
     int rc = validate_params(params);
     if (rc) return rc;
+    if (params->n_s != c->params.n_s ||
+        std::memcmp(params->spatial, c->params.spatial, sizeof(int) * size_t(params->n_s)) != 0) {
+        set_error("the spatial dictionary (n_s, spatial) is fixed at setup");
+        return MUFFIN_EINVAL;
+    }
     const muffin_params old = c->params;
     drop_graphs(c);      // the parameters are kernel arguments of the recorded pass
     if (old.rho_P != params->rho_P || old.rho_T != params->rho_T || old.rho_V != params->rho_V) {
@@ -644,6 +666,8 @@ int muffin_set_params(muffin_ctx* c, const muffin_params* params) {
                                 old.mu_s / old.rho_T,
                                 old.rho_V != params->rho_V ? 1.0 / old.rho_V - 1.0 / params->rho_V : 0.0,
                                 c->stream));
+        if (old.rho_T != params->rho_T)
+            if (int rc2 = dict_reencode(c, old.rho_T / params->rho_T, old.mu_s / old.rho_T)) return rc2;
     }
     c->params = *params;
     c->version++;
@@ -662,14 +686,14 @@ int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, in
     if (n_iter < 1 || !ms || cap < 1) { set_error("muffin_profile: bad arguments"); return MUFFIN_EINVAL; }
     // the kernels of one pass of the context's schedule, timed with events
     // between the launches (each pass runs: the state advances)
-    static const char* unfused[4] = {"row_fwd", "col_solve", "row_inv", "spectral"};
+    static const char* unfused[5] = {"row_fwd", "col_solve", "row_inv", "spectral", "dictionary"};
     static const char* fused[2] = {"col_solve", "fused"};
     const bool fu = use_fused(c);
-    const int K = fu ? 2 : 4;
+    const int K = fu ? 2 : (c->lay.n_w ? 5 : 4);
     const char** knames = fu ? fused : unfused;
-    hipEvent_t ev[5];
+    hipEvent_t ev[6];
     for (int i = 0; i <= K; ++i) HIP_TRY(hipEventCreate(&ev[i]));
-    double acc[4] = {0, 0, 0, 0};
+    double acc[5] = {0, 0, 0, 0, 0};
     const muffin_shape& s = c->shape;
     int rc = MUFFIN_OK;
     if (fu) rc = row_forward(c);
@@ -691,6 +715,10 @@ int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, in
             if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
             if (e == hipSuccess && (rc = step_spectral(c, false, nullptr)) != MUFFIN_OK) break;
             if (e == hipSuccess) e = hipEventRecord(ev[4], c->stream);
+            if (K == 5) {
+                if (e == hipSuccess && (rc = dict_pass(c)) != MUFFIN_OK) break;
+                if (e == hipSuccess) e = hipEventRecord(ev[5], c->stream);
+            }
         }
         if (e == hipSuccess) e = hipEventSynchronize(ev[K]);
         if (e != hipSuccess) { set_error("profile: %s", hipGetErrorString(e)); rc = MUFFIN_EDEVICE; break; }
@@ -714,6 +742,7 @@ int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, in
 int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode,
                 double* loss, double grad[3]) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = no_wavelets(c, "muffin_grad")) return rc;
     if (K < 1 || ckpt_every < 1) {
         set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
         return MUFFIN_EINVAL;
@@ -770,7 +799,7 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
     // fused or not: the spectral pass and the fused kernel on a copy of the
     // state in the second set (X of the fused kernel into the B_rest buffer)
     int fu = 0;
-    if (e == hipSuccess && fused_supported(dt, s.nx, s.ny, s.L)) {
+    if (e == hipSuccess && c->lay.n_w == 0 && fused_supported(dt, s.nx, s.ny, s.L)) {
         const size_t nb = voxels(s) * elem_size(s);
         for (int i = 0; i < kNumState && e == hipSuccess; ++i)
             e = hipMemcpyAsync(st_alt(c, i), st(c, i), nb, hipMemcpyDeviceToDevice, c->stream);
@@ -839,7 +868,7 @@ int muffin_get_schedule(const muffin_ctx* c, int schedule[3]) {
 }
 
 int muffin_fused_available(const muffin_ctx* c) {
-    return c && fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L) ? 1 : 0;
+    return c && c->lay.n_w == 0 && fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L) ? 1 : 0;
 }
 
 int muffin_set_graph(muffin_ctx* c, int enable) {

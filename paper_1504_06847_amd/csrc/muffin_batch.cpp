@@ -288,6 +288,10 @@ int check_shapes(int n, const muffin_shape* shapes, const muffin_params* params)
     if (!shapes || !params) { set_error("shapes and params must be non-NULL"); return MUFFIN_EINVAL; }
     for (int i = 0; i < n; ++i) {
         if (int rc = muffin_validate(&shapes[i], &params[i])) return rc;
+        if (params[i].n_s != 1) {
+            set_error("cube %d: batches run the Dirac spatial basis only (n_s = %d)", i, params[i].n_s);
+            return MUFFIN_EUNSUPPORTED;
+        }
         if (shapes[i].dtype != shapes[0].dtype) {
             set_error("cube %d has dtype %d, cube 0 has %d: a batch has one dtype", i, shapes[i].dtype,
                       shapes[0].dtype);

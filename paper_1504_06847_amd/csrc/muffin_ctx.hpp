@@ -35,6 +35,10 @@ struct muffin_ctx {
     int use_graph;
     hipStream_t cap;
     hipGraphExec_t gexec[2];
+    // wavelet bases of the spatial dictionary: filter length and the FP64
+    // scaling filter of each (lay.n_w of them)
+    int wK[muffin::kMaxWavelets];
+    double wh[muffin::kMaxWavelets][16];
 };
 
 namespace muffin {
@@ -67,7 +71,7 @@ inline SpecArgs spec_args(const muffin_params& p) {
     return a;
 }
 
-// rho of eq. Qlsimp for the Dirac basis (n_s = 1)
+// rho of eq. Qlsimp for a union of n_s orthonormal bases
 inline double rho_Q(const muffin_params& p) {
     return p.mu_eps + p.rho_S + p.rho_P + double(p.n_s) * p.rho_T;
 }
@@ -80,6 +84,15 @@ inline double fft_scale(const muffin_shape& s) { return 1.0 / (double(s.nx / 2) 
 int refresh_brest(muffin_ctx* c);
 int ensure_z(muffin_ctx* c);
 bool fused_pass(const muffin_ctx* c);
+
+// the wavelet bases of the spatial dictionary (muffin_dict.cpp): filters at
+// setup; steps III, VI and the B_rest terms of one pass (after the spectral
+// pass); the B_rest terms of the stored state; re-encoding for new rho_T
+int daubechies_filter(int p, double* h);
+int dict_setup(muffin_ctx* c);
+int dict_pass(muffin_ctx* c);
+int dict_brest(muffin_ctx* c);
+int dict_reencode(muffin_ctx* c, double ratio, double tau);
 
 inline int check_ctx(const muffin_ctx* c) {
     if (!c) { set_error("context is NULL"); return MUFFIN_EINVAL; }

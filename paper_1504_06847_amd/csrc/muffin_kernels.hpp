@@ -218,13 +218,29 @@ hipError_t launch_scan(bool in_f64, const void* psf, const void* dirty, size_t n
 hipError_t launch_reduce_final(const double* partials, int nblocks, int nq, double* out,
                                hipStream_t s);
 
+// ---------------------------------------------------------------- wavelet bases
+// One level of the periodised 2-D DWT with the length-K scaling filter h
+// (FP64 host array; K even, 2 <= K <= 16) over L images of sy x sx (powers
+// of two >= 4).  Forward: reads `in` (row stride in_ld, band stride in_bs),
+// updates the detail blocks of the coefficient cube z (row stride ld, band
+// stride z_bs) as z <- c + clip(z, tau), and writes LL densely to llout
+// ([L][sy/2][sx/2]) or, with llout null, updates z's LL block too.
+hipError_t launch_dwt_fwd(int dtype, int K, const double* h, const void* in, int in_ld, long in_bs, void* z,
+                          int ld, long z_bs, void* llout, int sy, int sx, int L, double tau, hipStream_t s);
+// Inverse: synthesises the sy x sx images of u = 2 soft(z, tau) - z, LL from
+// llin (dense) or from z when llin is null; out = x, or out += scale x.
+hipError_t launch_dwt_inv(int dtype, int K, const double* h, const void* llin, const void* z, int ld, long z_bs,
+                          void* out, int out_ld, long out_bs, int sy, int sx, int L, double tau, double scale,
+                          bool accumulate, hipStream_t s);
+
 // Elementwise helpers.
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* zV, const void* GS,
                         void* Brest, size_t n, const SpecArgs& a, hipStream_t s);
 hipError_t launch_positive(int dtype, const void* z, void* out, size_t n, hipStream_t s);
 // z_P <- max(0, z_P) - rP max(0, -z_P);  z_T <- soft(z_T, tau) + rT clip(z_T, tau);
-// z_V <- z_V + dV Gamma_S (dV = 1 / rho_V - 1 / rho_V', skipped when 0)
+// z_V <- z_V + dV Gamma_S (dV = 1 / rho_V - 1 / rho_V', skipped when 0); a
+// null zP, zT or zV is left out
 hipError_t launch_reencode(int dtype, void* zP, void* zT, void* zV, const void* GS, size_t n, double rP,
                            double rT, double tau, double dV, hipStream_t s);
 

@@ -12,10 +12,19 @@ constexpr int kNumState = 4;     // z_P, z_T, z_V = S - Gamma_S / rho_V, Gamma_S
 constexpr int kNumRed = 10;      // FP64 partial sums per block (see RedSlot)
 enum StateIdx { ST_ZP = 0, ST_ZT = 1, ST_ZV = 2, ST_GS = 3 };
 
+constexpr int kMaxWavelets = 8;  // Db1..Db8 beside the Dirac basis
+constexpr int kMaxDwtLevels = 4;
+
 struct Layout {
     size_t state[2][kNumState];   // current and alternate state sets (a reporting
                                   // pass writes the alternate set, then they swap)
     size_t brest, x, z, yf, h2, h2nyq, tw, tw64, dctm, partials, vpart, sums;
+    // wavelet bases of the spatial dictionary: one coefficient cube z_b per
+    // basis, and the scratch image of each DWT level j >= 1 (its LL block
+    // going down, its reconstruction coming back)
+    size_t wz[kMaxWavelets];
+    size_t wtmp[kMaxDwtLevels];
+    int n_w, levels;
     size_t total;
     size_t setup_scratch_bytes, state_region_bytes;
     int nblk;
@@ -24,7 +33,10 @@ struct Layout {
 void set_error(const char* fmt, ...);
 int validate_shape(const muffin_shape* s);
 int validate_params(const muffin_params* p);
-Layout make_layout(const muffin_shape* s);
+Layout make_layout(const muffin_shape* s, int n_s = 1);
+// DWT depth of the wavelet bases: 4 levels, fewer when the smaller image side
+// would leave a coarsest band under 2 x 2
+int dwt_levels(int nx, int ny);
 int max_blocks_host(int L, int ny, int nx);
 
 // register width of the dense DCT used for band counts that are not powers of two

@@ -334,10 +334,15 @@ k_reencode(T* __restrict__ zP, T* __restrict__ zT, T* __restrict__ zV, const T* 
            double rP, double rT, double tau, double dV) {
     const T ratioP = T(rP), ratioT = T(rT), t = T(tau), dv = T(dV);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const T zp = zP[i], zt = zT[i];
-        zP[i] = (zp > T(0) ? zp : T(0)) - ratioP * (zp < T(0) ? -zp : T(0));
-        zT[i] = softt(zt, t) + ratioT * clipt(zt, t);
-        if (dV != 0.0) zV[i] += dv * GS[i];
+        if (zP) {
+            const T zp = zP[i];
+            zP[i] = (zp > T(0) ? zp : T(0)) - ratioP * (zp < T(0) ? -zp : T(0));
+        }
+        if (zT) {
+            const T zt = zT[i];
+            zT[i] = softt(zt, t) + ratioT * clipt(zt, t);
+        }
+        if (zV && dV != 0.0) zV[i] += dv * GS[i];
     }
 }
 

@@ -70,10 +70,19 @@ int validate_params(const muffin_params* p) {
         return MUFFIN_EINVAL;
     }
     if (p->check_every < 1) { set_error("check_every = %d < 1", p->check_every); return MUFFIN_EINVAL; }
-    if (p->n_s != 1 || p->spatial[0] != MUFFIN_DIRAC) {
-        set_error("only the Dirac spatial basis (n_s = 1) is built (n_s = %d, spatial[0] = %d)",
-                  p->n_s, p->spatial[0]);
+    if (p->n_s < 1 || p->n_s > 1 + kMaxWavelets) {
+        set_error("n_s = %d spatial bases: 1 to %d are supported", p->n_s, 1 + kMaxWavelets);
         return MUFFIN_EUNSUPPORTED;
+    }
+    if (p->spatial[0] != MUFFIN_DIRAC) {
+        set_error("spatial[0] = %d: the first spatial basis must be MUFFIN_DIRAC", p->spatial[0]);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    for (int b = 1; b < p->n_s; ++b) {
+        if (p->spatial[b] < MUFFIN_DB1 || p->spatial[b] > MUFFIN_DB8) {
+            set_error("spatial[%d] = %d is not one of MUFFIN_DB1 .. MUFFIN_DB8", b, p->spatial[b]);
+            return MUFFIN_EUNSUPPORTED;
+        }
     }
     if (p->spectral != MUFFIN_DCT2_ORTHO) {
         set_error("spectral transform %d is not MUFFIN_DCT2_ORTHO", p->spectral);
@@ -84,7 +93,15 @@ int validate_params(const muffin_params* p) {
 
 static size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
-Layout make_layout(const muffin_shape* s) {
+int dwt_levels(int nx, int ny) {
+    int m = nx < ny ? nx : ny, lg = 0;
+    while ((1 << (lg + 1)) <= m) ++lg;
+    int J = lg - 1;
+    if (J > kMaxDwtLevels) J = kMaxDwtLevels;
+    return J < 1 ? 1 : J;
+}
+
+Layout make_layout(const muffin_shape* s, int n_s) {
     Layout lay{};
     const size_t sz = s->dtype == MUFFIN_F64 ? 8 : 4;
     const size_t V = size_t(s->L) * s->ny * s->nx;
@@ -97,6 +114,12 @@ Layout make_layout(const muffin_shape* s) {
         for (int i = 0; i < kNumState; ++i) lay.state[set][i] = take(V * sz);
     lay.brest = take(V * sz);
     lay.x = take(V * sz);
+    lay.n_w = n_s > 1 ? n_s - 1 : 0;
+    lay.levels = dwt_levels(s->nx, s->ny);
+    for (int b = 0; b < lay.n_w; ++b) lay.wz[b] = take(V * sz);
+    if (lay.n_w)
+        for (int j = 1; j < lay.levels; ++j)
+            lay.wtmp[j] = take(size_t(s->L) * size_t(s->ny >> j) * size_t(s->nx >> j) * sz);
     lay.z = take(HS * 2 * sz);
     lay.yf = take(HS * 2 * sz);
     lay.h2 = take(HS * sz);
@@ -156,7 +179,7 @@ int muffin_validate(const muffin_shape* shape, const muffin_params* params) {
 
 size_t muffin_workspace_bytes(const muffin_shape* shape, const muffin_params* params) {
     if (muffin_validate(shape, params) != MUFFIN_OK) return 0;
-    return make_layout(shape).total;
+    return make_layout(shape, params->n_s).total;
 }
 
 const char* muffin_last_error(void) { return g_err; }

@@ -63,6 +63,7 @@ SIGNATURES = [
     ("muffin_default_params", None, [POINTER(MuffinParams)]),
     ("muffin_workspace_bytes", c_size_t, [POINTER(MuffinShape), POINTER(MuffinParams)]),
     ("muffin_validate", c_int, [POINTER(MuffinShape), POINTER(MuffinParams)]),
+    ("muffin_wavelet_filter", c_int, [c_int, POINTER(c_double)]),
     ("muffin_setup", c_int, [POINTER(c_void_p), POINTER(MuffinShape), POINTER(MuffinParams),
                              c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("muffin_iterate", c_int, [c_void_p, c_int]),

@@ -13,7 +13,10 @@ import torch
 from . import lib as L
 
 PARAM_NAMES = ("mu_eps", "mu_s", "mu_nu", "rho_P", "rho_T", "rho_V", "rho_S",
-               "check_every", "eps_abs", "eps_rel")
+               "check_every", "eps_abs", "eps_rel", "spatial")
+
+# Section 4's spatial dictionary: the Dirac basis and Db1..Db8
+PAPER_DICTIONARY = (0, 1, 2, 3, 4, 5, 6, 7, 8)
 
 
 def _load_cache(path):
@@ -48,8 +51,10 @@ class Solver:
     ``psf`` and ``dirty`` are [L][ny][nx] arrays (PSF peak at (ny/2, nx/2)).
     Keyword parameters: mu_eps, mu_s, mu_nu, rho_P, rho_T, rho_V, rho_S
     (defaults: the paper's Section 4 values), ``rho`` to set the four rho's
-    at once, check_every, eps_abs, eps_rel, and ``dtype`` (torch.float32 or
-    torch.float64) for the iteration's precision.
+    at once, check_every, eps_abs, eps_rel, ``spatial`` (the spatial
+    dictionary: 0 for the Dirac basis first, then Daubechies orders 1..8;
+    ``PAPER_DICTIONARY`` is Section 4's; default the Dirac basis alone), and
+    ``dtype`` (torch.float32 or torch.float64) for the iteration's precision.
     """
 
     def __init__(self, psf, dirty, *, dtype=torch.float32, device="cuda", stream=None, graph=False,
@@ -149,11 +154,16 @@ class Solver:
         unknown = set(kw) - set(PARAM_NAMES)
         if unknown:
             raise TypeError(f"unknown parameters {sorted(unknown)}")
+        if "spatial" in kw:
+            kw["spatial"] = tuple(int(b) for b in kw["spatial"])
+            kw["n_s"] = len(kw["spatial"])
         return L.make_params(self._lib, **kw)
 
     @property
     def params(self):
-        return {k: getattr(self._params, k) for k in PARAM_NAMES}
+        d = {k: getattr(self._params, k) for k in PARAM_NAMES if k != "spatial"}
+        d["spatial"] = tuple(self._params.spatial[i] for i in range(self._params.n_s))
+        return d
 
     def set_params(self, **params):
         cur = self.params

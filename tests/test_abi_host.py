@@ -7,6 +7,7 @@ import re
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -65,7 +66,7 @@ def test_default_params_are_the_papers(lib):
 @pytest.mark.parametrize("field,value,code", [
     ("mu_s", -1.0, -1), ("mu_nu", float("nan"), -1), ("mu_eps", float("inf"), -1),
     ("rho_P", 0.0, -1), ("rho_T", -2.0, -1), ("rho_V", float("nan"), -1),
-    ("check_every", 0, -1), ("eps_abs", -1e-3, -1), ("n_s", 9, -2), ("spectral", 3, -2),
+    ("check_every", 0, -1), ("eps_abs", -1e-3, -1), ("n_s", 10, -2), ("n_s", 0, -2), ("spectral", 3, -2),
 ])
 def test_parameter_validation(lib, field, value, code):
     from paper_1504_06847_amd import lib as L
@@ -181,3 +182,41 @@ def test_schedule_calls_reject_bad_arguments(lib):
     assert lib.muffin_autotune(None, 3, sch) == -1
     assert lib.muffin_set_schedule(None, sch) == -1
     assert lib.muffin_get_schedule(None, sch) == -1
+
+
+def test_wavelet_filter_matches_the_oracle(lib):
+    """The library's Daubechies filters (host FP64, its own root finder)
+    against the oracle's spectral factorisation."""
+    import oracle as O
+    for p in range(1, 9):
+        h = (ctypes.c_double * 16)()
+        assert lib.muffin_wavelet_filter(p, h) == 0
+        np.testing.assert_allclose(np.array(h[:2 * p]), O.daubechies_filter(p), atol=2e-14, rtol=0)
+    h = (ctypes.c_double * 16)()
+    assert lib.muffin_wavelet_filter(0, h) == -1 and lib.muffin_wavelet_filter(9, h) == -1
+    assert lib.muffin_wavelet_filter(2, None) == -1
+
+
+@pytest.mark.parametrize("spatial,code", [
+    ((0,), 0), ((0, 1, 2, 3, 4, 5, 6, 7, 8), 0), ((0, 8, 8), 0), ((1, 2), -2), ((0, 9), -2), ((0, 0), -2),
+])
+def test_spatial_dictionary_validation(lib, spatial, code):
+    from paper_1504_06847_amd import lib as L
+    p = L.make_params(lib, n_s=len(spatial), spatial=spatial)
+    s = _shape(L)
+    assert lib.muffin_validate(ctypes.byref(s), ctypes.byref(p)) == code
+    if code:
+        assert "spatial" in L.last_error(lib)
+
+
+def test_workspace_grows_by_one_cube_per_wavelet_basis(lib):
+    from paper_1504_06847_amd import lib as L
+    s = L.MuffinShape(64, 32, 4, 0)
+    one = lib.muffin_workspace_bytes(ctypes.byref(s), ctypes.byref(L.make_params(lib)))
+    nine = lib.muffin_workspace_bytes(ctypes.byref(s), ctypes.byref(
+        L.make_params(lib, n_s=9, spatial=(0, 1, 2, 3, 4, 5, 6, 7, 8))))
+    V = 64 * 32 * 4 * 4
+    # 8 coefficient cubes plus the DWT scratch of levels 1..3 (V/4 + V/16 + V/64)
+    assert nine - one >= 8 * V + V // 4 + V // 16 + V // 64
+    assert nine - one <= 8 * V + V // 4 + V // 16 + V // 64 + 12 * 256
+
