@@ -15,7 +15,9 @@ timed on a bounded sample of the same workload.
 
 Each pass is replayed from a HIP graph unless --no-graph is given.  The
 16-cube batch (uneven sizes and band counts) is timed in its per-cube
-sequential, grouped, grouped + graph and autotuned forms.
+sequential, grouped, grouped + graph and autotuned forms, and the paper's
+spatial dictionary (Dirac + Db1..Db8) on the same cube and on the paper's
+256 x 256 x 15 run shape (the `dictionary` object).
 """
 from __future__ import annotations
 
@@ -38,10 +40,10 @@ METRIC = "voxel-iterations/s (FP32 vs FP64) at 1024²×64; HBM GB/s % of peak"
 #   row_fwd  : B_rest in, packed half spectrum out                     2
 #   col_solve: spectrum in/out, conj(h) y_hat in, |h|^2 in (half)      3.5
 #   row_inv  : spectrum in, X out                                      2
-#   spectral : X, z_P, z_T, S, Gamma_S, Gamma_S again in;
-#              z_P, z_T, S, Gamma_S, B_rest out                        11
-#   fused    : Z, S, Gamma_S, z_P, z_T, Gamma_S again in;
-#              Z, X, z_P, z_T, S, Gamma_S out                            12
+#   spectral : X, z_P, z_T, z_V, Gamma_S in;
+#              z_P, z_T, z_V, Gamma_S, B_rest out                      10
+#   fused    : Z, z_P, z_T, z_V, Gamma_S in;
+#              Z, X, z_P, z_T, z_V, Gamma_S out                          11
 KERNEL_ELEMS = {"row_fwd": 2.0, "col_solve": 3.5, "row_inv": 2.0, "spectral": 10.0, "fused": 11.0}
 # minimum traffic of one pass of this algorithm: the 4-array state stream in
 # and out plus the constants (38 B in FP32) and one transposition round trip
@@ -140,6 +142,45 @@ def run_gpu(inst, params, dtype, steps, warmup, profile_iters, graph=False):
     return ms, prof, schedule
 
 
+# algorithmic elements per voxel of one wavelet basis in a pass: X read,
+# the basis's coefficient cube read and written, B_rest read and written
+DICT_ELEMS_PER_BASIS = 5.0
+
+
+def run_dictionary(inst, params, steps, warmup, profile_iters, graph=True):
+    """The paper's spatial dictionary (Dirac + Db1..Db8, n_s = 9) on the same
+    cube: voxel-iterations/s and the kernels of a pass."""
+    import torch
+    from paper_1504_06847_amd import PAPER_DICTIONARY, Solver
+    kw = dict(mu_eps=params.mu_eps, mu_s=params.mu_s, mu_nu=params.mu_nu, rho_P=params.rho_P,
+              rho_T=params.rho_T, rho_V=params.rho_V, rho_S=params.rho_S)
+    s = Solver(inst.psf, inst.dirty, graph=graph, spatial=PAPER_DICTIONARY, **kw)
+    schedule = s.autotune(reps=3)
+    s.iterate(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    s.iterate(steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = s.profile(profile_iters) if profile_iters > 0 else {}
+    s.close()
+    L, ny, nx = inst.psf.shape
+    V = L * ny * nx
+    n_w = len(PAPER_DICTIONARY) - 1
+    out = {"bases": "Dirac + Db1..Db8", "n_s": len(PAPER_DICTIONARY), "shape": [L, ny, nx],
+           "value": V * steps / (ms / 1e3), "unit": "voxel-iterations/s",
+           "ms_per_step": round(ms / steps, 4), "steps": steps, "schedule": list(schedule),
+           "kernels_ms": {k: round(v, 5) for k, v in prof.items()}}
+    if "dictionary" in prof:
+        nbytes = DICT_ELEMS_PER_BASIS * n_w * 4 * V
+        out["dictionary_alg_bytes"] = int(nbytes)
+        out["dictionary_GBps"] = round(nbytes / (prof["dictionary"] * 1e-3) / 1e9, 1)
+    return out
+
+
 def batch_instances():
     """The uneven batch: 16 cubes, N^2 in {128^2, 256^2, 512^2} x L in {16, 32,
     64, 128} (shapes drawn with seed 3), each drawn with the 256^2 x 32
@@ -219,6 +260,8 @@ def main(argv=None):
                     help="launch each pass's kernels one by one instead of replaying a HIP graph")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-cube batch measurement")
     ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--dict-steps", type=int, default=10,
+                    help="timed passes with the paper's spatial dictionary (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration)")
     a = ap.parse_args(argv)
@@ -262,6 +305,13 @@ def main(argv=None):
         ms64, prof64, sched64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5, graph=a.graph)
         fp64 = dict(value=V * a.fp64_steps / (ms64 / 1e3), ms_per_step=round(ms64 / a.fp64_steps, 4),
                     kernels_ms={k: round(v, 5) for k, v in prof64.items()}, schedule=list(sched64))
+    dictionary = None
+    if a.dict_steps > 0:
+        _log(f"bench: spatial dictionary, {a.dict_steps} timed passes")
+        dictionary = run_dictionary(inst, cfg.params, a.dict_steps, 2, 3, graph=a.graph)
+        pcfg = get_config("paper256")
+        dictionary["paper_shape"] = run_dictionary(pcfg.make(), pcfg.params, 5 * a.dict_steps, 3, 3,
+                                                   graph=a.graph)
     batch = None
     if not a.no_batch:
         _log(f"bench: 16-cube batch, {a.batch_steps} passes per form")
@@ -295,6 +345,7 @@ def main(argv=None):
         "iteration_62B_frac": round(ITER_MIN5_ELEMS * 4 * value / 1e9 / HBM_PEAK_GBPS, 4),
         "kernels": kernels,
         "fp64": fp64,
+        "dictionary": dictionary,
         "batched": batch,
         "cpu_baseline": cpu,
     }
