@@ -154,6 +154,20 @@ int muffin_iterate(muffin_ctx* ctx, int n_iter);
    each check. */
 int muffin_solve(muffin_ctx* ctx, int max_iter, muffin_report* report);
 
+/* muffin_solve with residual balancing (Boyd et al. 2011, Sec. 3.4.1; the
+   paper notes that the rho's set the speed of convergence, Section 4): at
+   every check that does not stop the run, the four rho's are multiplied by
+   tau when r_pri > mu r_dual and divided by tau when r_dual > mu r_pri, the
+   multipliers held as in muffin_set_params (the filter of eq. Qlsimp follows
+   the new rho).  mu > 1, tau > 1 (Boyd et al. use 10 and 2).  The rho's in
+   force at the end are read back with muffin_get_params.
+   Returns as muffin_solve.  Errors: EINVAL, EUNSUPPORTED (wavelet
+   dictionary), EDEVICE, ENONFINITE. */
+int muffin_solve_adaptive(muffin_ctx* ctx, int max_iter, double mu, double tau, muffin_report* report);
+
+/* The context's parameters (host copy).  Errors: EINVAL. */
+int muffin_get_params(const muffin_ctx* ctx, muffin_params* out);
+
 /* Run ONE more pass of Algorithm 1 and fill *report with its residuals, E and
    the objective at the new P.  Synchronises the stream. */
 int muffin_step_report(muffin_ctx* ctx, muffin_report* report);

@@ -8,11 +8,11 @@ package.
 from .muffin_oracle import (Params, Problem, State, soft, dct_nu, idct_nu,
                             run, admm_iteration, objective, residuals,
                             energy, jvp_run, mse_loss, mse_grad,
-                            set_workers)
+                            set_workers, solve_adaptive)
 from .wavelets import (DIRAC, PAPER_DICTIONARY, Dictionary, daubechies_filter,
                        dwt2, idwt2, dwt_levels)
 
 __all__ = ["Params", "Problem", "State", "soft", "dct_nu", "idct_nu", "run",
            "admm_iteration", "objective", "residuals", "energy", "jvp_run",
-           "mse_loss", "mse_grad", "set_workers", "DIRAC", "PAPER_DICTIONARY",
+           "mse_loss", "mse_grad", "set_workers", "solve_adaptive", "DIRAC", "PAPER_DICTIONARY",
            "Dictionary", "daubechies_filter", "dwt2", "idwt2", "dwt_levels"]

@@ -285,6 +285,37 @@ def energy(prob: Problem, prev: State, cur: State) -> float:
                  + np.sum((cur.GS - prev.GS) ** 2) / p.rho_S)
 
 
+def solve_adaptive(prob: Problem, max_iter: int, check_every: int, mu: float, tau: float,
+                   eps_abs=1e-5, eps_rel=1e-4):
+    """Algorithm 1 with the stopping rule and residual balancing of Boyd et
+    al. (2011, Sec. 3.3.1 and 3.4.1), checked every ``check_every`` passes
+    and after the last one: stop when r <= eps_pri and s <= eps_dual; else
+    multiply the four rho's by tau when r > mu s, divide them by tau when
+    s > mu r, keeping every array (the multipliers Gamma are not rescaled).
+    Returns (state, problem with the final rho's, [(k, rho_P, r, s), ...])."""
+    st = prob.zero_state()
+    k = 0
+    history = []
+    while k < max_iter:
+        plain = min(check_every - 1, max_iter - k - 1)
+        for _ in range(plain):
+            st = admm_iteration(prob, st)
+        k += plain
+        prev = st
+        st = admm_iteration(prob, st)
+        k += 1
+        res = residuals(prob, prev, st, eps_abs, eps_rel)
+        history.append((k, prob.p.rho_P, res["r"], res["s"]))
+        if (res["r"] <= res["eps_pri"] and res["s"] <= res["eps_dual"]) or k >= max_iter:
+            break
+        f = tau if res["r"] > mu * res["s"] else (1.0 / tau if res["s"] > mu * res["r"] else 1.0)
+        if f != 1.0:
+            p = prob.p
+            prob = prob.with_params(p.with_(rho_P=p.rho_P * f, rho_T=p.rho_T * f,
+                                            rho_V=p.rho_V * f, rho_S=p.rho_S * f))
+    return st, prob, history
+
+
 def mse_loss(XK, sky) -> float:
     """||X^K - sky||_2^2 (a sum, not a mean)."""
     d = np.asarray(XK, np.float64) - np.asarray(sky, np.float64)

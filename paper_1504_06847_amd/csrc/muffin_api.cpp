@@ -578,6 +578,49 @@ int muffin_solve(muffin_ctx* c, int max_iter, muffin_report* report) {
     return rep.converged ? MUFFIN_OK : MUFFIN_NOT_CONVERGED;
 }
 
+int muffin_solve_adaptive(muffin_ctx* c, int max_iter, double mu, double tau, muffin_report* report) {
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = no_wavelets(c, "muffin_solve_adaptive (convergence reports)")) return rc;
+    if (max_iter < 1) { set_error("max_iter = %d < 1", max_iter); return MUFFIN_EINVAL; }
+    if (!std::isfinite(mu) || !std::isfinite(tau) || mu <= 1.0 || tau <= 1.0) {
+        set_error("residual balancing needs finite mu > 1 and tau > 1 (mu = %g, tau = %g)", mu, tau);
+        return MUFFIN_EINVAL;
+    }
+    muffin_report rep{};
+    int done = 0;
+    while (done < max_iter) {
+        const int left = max_iter - done;
+        const int plain = (c->params.check_every - 1 < left - 1) ? c->params.check_every - 1 : left - 1;
+        int rc = muffin_iterate(c, plain);
+        if (rc) return rc;
+        rc = pass_with_report(c, &rep);
+        if (rc) return rc;
+        done += plain + 1;
+        if (rep.converged || done >= max_iter) break;
+        // residual balancing: the four rho's together, multipliers held
+        double f = 1.0;
+        if (rep.r_pri > mu * rep.r_dual) f = tau;
+        else if (rep.r_dual > mu * rep.r_pri) f = 1.0 / tau;
+        if (f != 1.0) {
+            muffin_params np = c->params;
+            np.rho_P *= f;
+            np.rho_T *= f;
+            np.rho_V *= f;
+            np.rho_S *= f;
+            if ((rc = muffin_set_params(c, &np))) return rc;
+        }
+    }
+    if (report) *report = rep;
+    return rep.converged ? MUFFIN_OK : MUFFIN_NOT_CONVERGED;
+}
+
+int muffin_get_params(const muffin_ctx* c, muffin_params* out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!out) { set_error("params output is NULL"); return MUFFIN_EINVAL; }
+    *out = c->params;
+    return MUFFIN_OK;
+}
+
 int muffin_get_x(muffin_ctx* c, void* x_out) {
     if (int rc = check_ctx(c)) return rc;
     if (!x_out) { set_error("x_out is NULL"); return MUFFIN_EINVAL; }

@@ -68,6 +68,8 @@ SIGNATURES = [
                              c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("muffin_iterate", c_int, [c_void_p, c_int]),
     ("muffin_solve", c_int, [c_void_p, c_int, POINTER(MuffinReport)]),
+    ("muffin_solve_adaptive", c_int, [c_void_p, c_int, c_double, c_double, POINTER(MuffinReport)]),
+    ("muffin_get_params", c_int, [c_void_p, POINTER(MuffinParams)]),
     ("muffin_step_report", c_int, [c_void_p, POINTER(MuffinReport)]),
     ("muffin_get_x", c_int, [c_void_p, c_void_p]),
     ("muffin_get_p", c_int, [c_void_p, c_void_p]),

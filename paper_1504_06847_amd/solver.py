@@ -186,9 +186,20 @@ class Solver:
         L.check(self._lib.muffin_step_report(self._ctx, byref(rep)), "muffin_step_report", self._lib)
         return rep.asdict()
 
-    def solve(self, max_iter: int = 350) -> dict:
+    def solve(self, max_iter: int = 350, adaptive=None) -> dict:
+        """Iterate until the Boyd stopping rule holds or max_iter passes.
+        ``adaptive=(mu, tau)`` balances the residuals by scaling the four
+        rho's (muffin_solve_adaptive); ``params`` then shows the final rho's."""
         rep = L.MuffinReport()
-        rc = L.check(self._lib.muffin_solve(self._ctx, int(max_iter), byref(rep)), "muffin_solve", self._lib)
+        if adaptive is None:
+            rc = L.check(self._lib.muffin_solve(self._ctx, int(max_iter), byref(rep)), "muffin_solve", self._lib)
+        else:
+            mu, tau = adaptive
+            rc = L.check(self._lib.muffin_solve_adaptive(self._ctx, int(max_iter), float(mu), float(tau),
+                                                         byref(rep)), "muffin_solve_adaptive", self._lib)
+            p = L.MuffinParams()
+            L.check(self._lib.muffin_get_params(self._ctx, byref(p)), "muffin_get_params", self._lib)
+            self._params = p
         d = rep.asdict()
         d["status"] = rc
         return d
