@@ -73,6 +73,8 @@ int daubechies_filter(int p, double* h) {
 }
 
 int dict_setup(muffin_ctx* c) {
+    if (c->lay.n_w == 0) return MUFFIN_OK;
+    double tab[kMaxWavelets * 32] = {};
     for (int b = 0; b < c->lay.n_w; ++b) {
         const int p = c->params.spatial[b + 1];
         c->wK[b] = 2 * p;
@@ -80,42 +82,83 @@ int dict_setup(muffin_ctx* c) {
             set_error("Daubechies filter Db%d", p);
             return rc;
         }
+        const int K = c->wK[b];
+        for (int k = 0; k < K; ++k) {
+            tab[32 * b + k] = c->wh[b][k];
+            tab[32 * b + 16 + k] = (k & 1) ? -c->wh[b][K - 1 - k] : c->wh[b][K - 1 - k];
+        }
+    }
+    // the device filter table of the all-bases launches, in the iteration's precision
+    if (c->shape.dtype == MUFFIN_F64) {
+        HIP_TRY(hipMemcpy(P(c, c->lay.wfilt), tab, sizeof(tab), hipMemcpyHostToDevice));
+    } else {
+        float t32[kMaxWavelets * 32];
+        for (int i = 0; i < kMaxWavelets * 32; ++i) t32[i] = float(tab[i]);
+        HIP_TRY(hipMemcpy(P(c, c->lay.wfilt), t32, sizeof(t32), hipMemcpyHostToDevice));
     }
     return MUFFIN_OK;
 }
 
 // steps III and VI of every wavelet basis from X (z_b updated) and their
 // terms of B_rest (added to it); with update = false only the B_rest terms
-// of the stored z_b
+// of the stored z_b.  Analysis: one launch per level for every basis;
+// synthesis: one launch per coarser level for every basis, then the finest
+// level basis by basis into B_rest (a fixed summation order).
 static int dict_run(muffin_ctx* c, bool update) {
     const muffin_shape& s = c->shape;
-    const int J = c->lay.levels;
-    const double tau = c->params.mu_s / c->params.rho_T;
+    const int J = c->lay.levels, nw = c->lay.n_w;
+    if (nw == 0) return MUFFIN_OK;
+    const size_t es = elem_size(s);
     const long vb = long(s.ny) * s.nx;
-    for (int b = 0; b < c->lay.n_w; ++b) {
-        char* z = P(c, c->lay.wz[b]);
-        const double* h = c->wh[b];
-        const int K = c->wK[b];
-        if (update) {
-            for (int j = 0; j < J; ++j) {
-                const int sy = s.ny >> j, sx = s.nx >> j;
-                const void* in = j == 0 ? (const void*)P(c, c->lay.x) : (const void*)P(c, c->lay.wtmp[j]);
-                void* ll = j + 1 < J ? (void*)P(c, c->lay.wtmp[j + 1]) : nullptr;
-                HIP_TRY(launch_dwt_fwd(s.dtype, K, h, in, j == 0 ? s.nx : sx, j == 0 ? vb : long(sy) * sx, z,
-                                       s.nx, vb, ll, sy, sx, s.L, tau, c->stream));
-            }
-        }
-        for (int j = J - 1; j >= 0; --j) {
-            const int sy = s.ny >> j, sx = s.nx >> j;
-            const void* ll = j + 1 < J ? (const void*)P(c, c->lay.wtmp[j + 1]) : nullptr;
-            if (j == 0)
-                HIP_TRY(launch_dwt_inv(s.dtype, K, h, ll, z, s.nx, vb, P(c, c->lay.brest), s.nx, vb, sy, sx, s.L,
-                                       tau, c->params.rho_T, true, c->stream));
-            else
-                HIP_TRY(launch_dwt_inv(s.dtype, K, h, ll, z, s.nx, vb, P(c, c->lay.wtmp[j]), sx, long(sy) * sx,
-                                       sy, sx, s.L, tau, 1.0, false, c->stream));
+    // consecutive bases' cubes and scratch images lie at fixed strides
+    auto stride = [&](const size_t* off0, const size_t* off1) { return nw > 1 ? long((*off1 - *off0) / es) : 0L; };
+    const long zstride = stride(&c->lay.wz[0], &c->lay.wz[nw > 1 ? 1 : 0]);
+    long tstride[kMaxDwtLevels] = {};
+    for (int j = 1; j < J; ++j) tstride[j] = stride(&c->lay.wtmp[0][j], &c->lay.wtmp[nw > 1 ? 1 : 0][j]);
+    for (int b = 1; b < nw; ++b) {
+        bool ok = c->lay.wz[b] - c->lay.wz[0] == size_t(b) * size_t(zstride) * es;
+        for (int j = 1; j < J; ++j) ok = ok && c->lay.wtmp[b][j] - c->lay.wtmp[0][j] == size_t(b) * size_t(tstride[j]) * es;
+        if (!ok) {
+            set_error("wavelet workspace regions are not evenly spaced");
+            return MUFFIN_EDEVICE;
         }
     }
+    DwtLevel A{};
+    A.ftab = P(c, c->lay.wfilt);
+    for (int b = 0; b < nw; ++b) A.kpack |= unsigned(c->wK[b] / 2) << (4 * b);
+    A.n = nw;
+    A.L = s.L;
+    A.ld = s.nx;
+    A.z0 = P(c, c->lay.wz[0]);
+    A.zstride = zstride;
+    A.z_bs = vb;
+    A.tau = c->params.mu_s / c->params.rho_T;
+    if (update) {
+        for (int j = 0; j < J; ++j) {
+            A.sy = s.ny >> j;
+            A.sx = s.nx >> j;
+            A.in0 = j == 0 ? (const void*)P(c, c->lay.x) : (const void*)P(c, c->lay.wtmp[0][j]);
+            A.in_bstride = j == 0 ? 0 : tstride[j];
+            A.in_ld = j == 0 ? s.nx : A.sx;
+            A.in_bs = j == 0 ? vb : long(A.sy) * A.sx;
+            A.ll0 = j + 1 < J ? (void*)P(c, c->lay.wtmp[0][j + 1]) : nullptr;
+            A.llstride = j + 1 < J ? tstride[j + 1] : 0;
+            HIP_TRY(launch_dwt_fwd_all(s.dtype, A, c->stream));
+        }
+    }
+    for (int j = J - 1; j >= 1; --j) {
+        A.sy = s.ny >> j;
+        A.sx = s.nx >> j;
+        A.ll0 = j + 1 < J ? (void*)P(c, c->lay.wtmp[0][j + 1]) : nullptr;
+        A.llstride = j + 1 < J ? tstride[j + 1] : 0;
+        A.out0 = P(c, c->lay.wtmp[0][j]);
+        A.outstride = tstride[j];
+        HIP_TRY(launch_dwt_inv_all(s.dtype, A, c->stream));
+    }
+    for (int b = 0; b < nw; ++b)
+        HIP_TRY(launch_dwt_inv0(s.dtype, c->wK[b], c->wh[b], J > 1 ? (const void*)P(c, c->lay.wtmp[b][1]) : nullptr,
+                                P(c, c->lay.wz[b]), P(c, c->lay.brest), s.ny, s.nx, s.L, A.tau, c->params.rho_T,
+                                c->stream));
     return MUFFIN_OK;
 }
 

@@ -219,19 +219,38 @@ hipError_t launch_reduce_final(const double* partials, int nblocks, int nq, doub
                                hipStream_t s);
 
 // ---------------------------------------------------------------- wavelet bases
-// One level of the periodised 2-D DWT with the length-K scaling filter h
-// (FP64 host array; K even, 2 <= K <= 16) over L images of sy x sx (powers
-// of two >= 4).  Forward: reads `in` (row stride in_ld, band stride in_bs),
-// updates the detail blocks of the coefficient cube z (row stride ld, band
-// stride z_bs) as z <- c + clip(z, tau), and writes LL densely to llout
-// ([L][sy/2][sx/2]) or, with llout null, updates z's LL block too.
-hipError_t launch_dwt_fwd(int dtype, int K, const double* h, const void* in, int in_ld, long in_bs, void* z,
-                          int ld, long z_bs, void* llout, int sy, int sx, int L, double tau, hipStream_t s);
-// Inverse: synthesises the sy x sx images of u = 2 soft(z, tau) - z, LL from
-// llin (dense) or from z when llin is null; out = x, or out += scale x.
-hipError_t launch_dwt_inv(int dtype, int K, const double* h, const void* llin, const void* z, int ld, long z_bs,
-                          void* out, int out_ld, long out_bs, int sy, int sx, int L, double tau, double scale,
-                          bool accumulate, hipStream_t s);
+// One level of the periodised 2-D DWT of n wavelet bases over L images of
+// sy x sx (powers of two >= 4), one launch for every basis and band.  Basis b
+// uses the filter at ftab + 32 b (h then g, 16 taps each, in the iteration's
+// precision; K / 2 in bits 4b .. 4b+3 of kpack), its input at in0 + b
+// in_bstride elements (row stride in_ld, band stride in_bs), its coefficient
+// cube at z0 + b zstride (row stride ld, band stride z_bs) and its dense LL
+// image ([L][sy/2][sx/2]) at ll0 + b llstride, or LL in the cube when ll0 is
+// null.  Analysis: z <- c + clip(z, tau) for the coefficients, LL to ll0.
+// Synthesis (a level above the finest): the sy x sx images of
+// u = 2 soft(z, tau) - z, into out0 + b outstride ([L][sy][sx]).
+struct DwtLevel {
+    const void* ftab;
+    unsigned kpack;
+    int n, L, sy, sx;
+    const void* in0;
+    long in_bstride, in_bs;
+    int in_ld, ld;
+    void* z0;
+    long zstride, z_bs;
+    void* ll0;
+    long llstride;
+    void* out0;
+    long outstride;
+    double tau;
+};
+hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s);
+hipError_t launch_dwt_inv_all(int dtype, const DwtLevel& A, hipStream_t s);
+// The finest synthesis level of one basis (filter h, length K, FP64 host
+// array): Brest += scale * the ny x nx images of u (LL from llin, dense
+// [L][ny/2][nx/2], or from z when null; z row stride nx).
+hipError_t launch_dwt_inv0(int dtype, int K, const double* h, const void* llin, const void* z, void* Brest, int ny,
+                           int nx, int L, double tau, double scale, hipStream_t s);
 
 // Elementwise helpers.
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -20,10 +20,12 @@ struct Layout {
                                   // pass writes the alternate set, then they swap)
     size_t brest, x, z, yf, h2, h2nyq, tw, tw64, dctm, partials, vpart, sums;
     // wavelet bases of the spatial dictionary: one coefficient cube z_b per
-    // basis, and the scratch image of each DWT level j >= 1 (its LL block
-    // going down, its reconstruction coming back)
+    // basis, per basis the scratch image of each DWT level j >= 1 (its LL
+    // block going down, its reconstruction coming back), and the filter
+    // table (per basis h then g, 16 taps each, in the iteration's precision)
     size_t wz[kMaxWavelets];
-    size_t wtmp[kMaxDwtLevels];
+    size_t wtmp[kMaxWavelets][kMaxDwtLevels];
+    size_t wfilt;
     int n_w, levels;
     size_t total;
     size_t setup_scratch_bytes, state_region_bytes;

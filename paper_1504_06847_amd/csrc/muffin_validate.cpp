@@ -117,9 +117,9 @@ Layout make_layout(const muffin_shape* s, int n_s) {
     lay.n_w = n_s > 1 ? n_s - 1 : 0;
     lay.levels = dwt_levels(s->nx, s->ny);
     for (int b = 0; b < lay.n_w; ++b) lay.wz[b] = take(V * sz);
-    if (lay.n_w)
+    for (int b = 0; b < lay.n_w; ++b)
         for (int j = 1; j < lay.levels; ++j)
-            lay.wtmp[j] = take(size_t(s->L) * size_t(s->ny >> j) * size_t(s->nx >> j) * sz);
+            lay.wtmp[b][j] = take(size_t(s->L) * size_t(s->ny >> j) * size_t(s->nx >> j) * sz);
     lay.z = take(HS * 2 * sz);
     lay.yf = take(HS * 2 * sz);
     lay.h2 = take(HS * sz);
@@ -131,6 +131,8 @@ Layout make_layout(const muffin_shape* s, int n_s) {
     lay.partials = take(size_t(lay.nblk) * kNumRed * 8);
     lay.vpart = take(size_t(lay.nblk) * 8);
     lay.sums = take(64 * 8);
+    // outside the region zero_state clears (state sets .. Z)
+    if (lay.n_w) lay.wfilt = take(size_t(kMaxWavelets) * 32 * sz);
     lay.total = off;
     // setup scratch: two FP64 packed spectra, carved out of the state region
     lay.setup_scratch_bytes = 2 * HS * 16;

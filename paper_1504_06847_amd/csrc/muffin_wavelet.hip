@@ -15,8 +15,9 @@
 // along x, then along y, coefficients in Mallat layout (LL top-left, then
 // x-high top-right, y-high bottom-left, both high bottom-right); each level
 // recurses on LL.  One launch per level and direction, all bands at once: a
-// work-group transforms one tile (16 x 16 coefficients per sub-band) staged
-// with its periodic halo in LDS.
+// work-group transforms one tile (16 rows x 32 columns of coefficients per
+// sub-band, so each row of a sub-band block is one 128-B line) staged with
+// its periodic halo in LDS.
 //   k_dwt_fwd: one analysis level; the detail coefficients (and at the last
 //     level the LL block) go straight into the z_b update; LL otherwise to a
 //     dense scratch image for the next level.
@@ -28,12 +29,18 @@
 
 namespace muffin {
 
-constexpr int DWT_OT = 16;      // coefficients per sub-band per tile side
+constexpr int DWT_OTY = 16;     // coefficient rows per sub-band per tile
+constexpr int DWT_OTX = 32;     // coefficient columns per sub-band per tile
 constexpr int DWT_NTH = 256;
 
 template <typename T> struct WFilt {
     T h[16], g[16];
 };
+#define MUFFIN_DWT_K_CASES(F) F(2) F(4) F(6) F(8) F(10) F(12) F(14) F(16)
+
+// LDS of one tile, in elements, for the longest filter (K = 16)
+constexpr int DWT_FWD_LDS = (2 * DWT_OTY + 14) * (2 * DWT_OTX + 14) + 2 * (2 * DWT_OTY + 14) * DWT_OTX;
+constexpr int DWT_INV_LDS = 4 * (DWT_OTY + 7) * (DWT_OTX + 7) + 2 * (2 * DWT_OTY) * (DWT_OTX + 7);
 
 template <typename T> __device__ __forceinline__ T wclip(T z, T t) { return z > t ? t : (z < -t ? -t : z); }
 template <typename T> __device__ __forceinline__ T wsoft(T z, T t) {
@@ -44,26 +51,41 @@ template <typename T> __device__ __forceinline__ void zupdate(T* p, T c, T tau) 
 // u = 2 soft(z, tau) - z
 template <typename T> __device__ __forceinline__ T ucoef(T z, T tau) { return T(2) * wsoft(z, tau) - z; }
 
-// One analysis level of an sy x sx image per band.  in: [L] images with row
-// stride in_ld and band stride in_bs; z: the basis's coefficient cube (row
-// stride ld, band stride z_bs); llout: dense [L][sy/2][sx/2] or null (last
-// level: LL into z).  Grid: (hx / otx, hy / oty, L).
+// One analysis tile of an sy x sx image (one band): src with row stride
+// in_ld; zb the band's coefficient block (row stride ld); llb the band's
+// dense LL image ([sy/2][sx/2]) or null (last level: LL into zb).
 template <typename T, int K>
-__global__ void __launch_bounds__(DWT_NTH)
-k_dwt_fwd(const T* __restrict__ in, int in_ld, long in_bs, T* __restrict__ z, int ld, long z_bs,
-          T* __restrict__ llout, int sy, int sx, WFilt<T> f, T tau) {
-    constexpr int HM = 2 * DWT_OT + K - 2;
-    __shared__ T tin[HM * HM];
-    __shared__ T rl[HM * DWT_OT], rh[HM * DWT_OT];
+__device__ __forceinline__ void dwt_fwd_tile(const T* __restrict__ src, int in_ld, T* __restrict__ zb, int ld,
+                                             T* __restrict__ llb, int sy, int sx, const T (&h)[K],
+                                             const T (&g)[K], T tau, T* smem) {
+    constexpr int HMX = 2 * DWT_OTX + K - 2;
+    constexpr int HMY = 2 * DWT_OTY + K - 2;
+    T* tin = smem;
+    T* rl = smem + HMY * HMX;
+    T* rh = rl + HMY * DWT_OTX;
     const int hy = sy >> 1, hx = sx >> 1;
-    const int oty = hy < DWT_OT ? hy : DWT_OT, otx = hx < DWT_OT ? hx : DWT_OT;
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
-    const long band = blockIdx.z;
     const int HY = 2 * oty + K - 2, HX = 2 * otx + K - 2;
-    const T* src = in + band * in_bs;
+    // the coefficients this thread updates, loaded first so that their
+    // latency overlaps the tile load and the row pass
+    constexpr int IPT = (DWT_OTY * DWT_OTX + DWT_NTH - 1) / DWT_NTH;
+    T zq[IPT][4];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int e = threadIdx.x + j * DWT_NTH;
+        if (e < oty * otx) {
+            const int i = e / otx, m = e - i * otx;
+            const long gi = i0 + i, gm = m0 + m;
+            zq[j][0] = zb[gi * ld + hx + gm];
+            zq[j][1] = zb[(hy + gi) * ld + gm];
+            zq[j][2] = zb[(hy + gi) * ld + hx + gm];
+            zq[j][3] = llb ? T(0) : zb[gi * ld + gm];
+        }
+    }
     for (int e = threadIdx.x; e < HY * HX; e += DWT_NTH) {
         const int r = e / HX, c = e - r * HX;
-        tin[r * HM + c] = src[(long)((2 * i0 + r) & (sy - 1)) * in_ld + ((2 * m0 + c) & (sx - 1))];
+        tin[r * HMX + c] = src[(long)((2 * i0 + r) & (sy - 1)) * in_ld + ((2 * m0 + c) & (sx - 1))];
     }
     __syncthreads();
     // along x
@@ -72,94 +94,201 @@ k_dwt_fwd(const T* __restrict__ in, int in_ld, long in_bs, T* __restrict__ z, in
         T lo = T(0), hi = T(0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const T v = tin[r * HM + 2 * m + k];
-            lo += f.h[k] * v;
-            hi += f.g[k] * v;
+            const T v = tin[r * HMX + 2 * m + k];
+            lo += h[k] * v;
+            hi += g[k] * v;
         }
-        rl[r * DWT_OT + m] = lo;
-        rh[r * DWT_OT + m] = hi;
+        rl[r * DWT_OTX + m] = lo;
+        rh[r * DWT_OTX + m] = hi;
     }
     __syncthreads();
-    // along y: the four sub-bands
-    T* zb = z + band * z_bs;
-    for (int e = threadIdx.x; e < oty * otx; e += DWT_NTH) {
-        const int i = e / otx, m = e - i * otx;
-        T a = T(0), by = T(0), bx = T(0), d = T(0);
+    // along y: the four sub-bands; z <- c + clip(z, tau)
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const T vl = rl[(2 * i + k) * DWT_OT + m], vh = rh[(2 * i + k) * DWT_OT + m];
-            a += f.h[k] * vl;
-            by += f.g[k] * vl;
-            bx += f.h[k] * vh;
-            d += f.g[k] * vh;
+    for (int j = 0; j < IPT; ++j) {
+        const int e = threadIdx.x + j * DWT_NTH;
+        if (e < oty * otx) {
+            const int i = e / otx, m = e - i * otx;
+            T a = T(0), by = T(0), bx = T(0), d = T(0);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const T vl = rl[(2 * i + k) * DWT_OTX + m], vh = rh[(2 * i + k) * DWT_OTX + m];
+                a += h[k] * vl;
+                by += g[k] * vl;
+                bx += h[k] * vh;
+                d += g[k] * vh;
+            }
+            const long gi = i0 + i, gm = m0 + m;
+            zb[gi * ld + hx + gm] = bx + wclip(zq[j][0], tau);               // x high, y low
+            zb[(hy + gi) * ld + gm] = by + wclip(zq[j][1], tau);             // x low, y high
+            zb[(hy + gi) * ld + hx + gm] = d + wclip(zq[j][2], tau);
+            if (llb) llb[gi * hx + gm] = a;
+            else zb[gi * ld + gm] = a + wclip(zq[j][3], tau);
         }
-        const long gi = i0 + i, gm = m0 + m;
-        zupdate(zb + gi * ld + hx + gm, bx, tau);               // x high, y low
-        zupdate(zb + (hy + gi) * ld + gm, by, tau);             // x low, y high
-        zupdate(zb + (hy + gi) * ld + hx + gm, d, tau);
-        if (llout) llout[band * long(hy) * hx + gi * hx + gm] = a;
-        else zupdate(zb + gi * ld + gm, a, tau);
     }
 }
 
-// One synthesis level producing an sy x sx image per band from the four
-// sub-bands of u = 2 soft(z, tau) - z (LL from llin, dense [L][sy/2][sx/2],
-// or from z when llin is null).  out: row stride out_ld, band stride out_bs;
-// accumulate: out += scale * x, else out = x.  Grid: (hx / otx, hy / oty, L).
+// One synthesis tile producing 2 oty x 2 otx pixels of an sy x sx image (one
+// band) from the four sub-bands of u = 2 soft(z, tau) - z (LL from llb, the
+// band's dense [sy/2][sx/2] image, or from zb when null); ob with row stride
+// out_ld: ob = x, or ob += scale x.
 template <typename T, int K>
-__global__ void __launch_bounds__(DWT_NTH)
-k_dwt_inv(const T* __restrict__ llin, const T* __restrict__ z, int ld, long z_bs, T* __restrict__ out,
-          int out_ld, long out_bs, int sy, int sx, WFilt<T> f, T tau, T scale, int accumulate) {
+__device__ __forceinline__ void dwt_inv_tile(const T* __restrict__ llb, const T* __restrict__ zb, int ld,
+                                             T* __restrict__ ob, int out_ld, int sy, int sx, const T (&h)[K],
+                                             const T (&g)[K], T tau, T scale, bool accumulate, T* smem) {
     constexpr int H2 = K / 2 - 1;                 // coefficient halo below the tile
-    constexpr int CM = DWT_OT + H2;
-    __shared__ T ca[CM * CM], cbx[CM * CM], cby[CM * CM], cd[CM * CM];
-    __shared__ T xl[2 * DWT_OT * CM], xh[2 * DWT_OT * CM];
+    constexpr int CMY = DWT_OTY + H2, CM = DWT_OTX + H2;
+    T* ca = smem;
+    T* cbx = ca + CMY * CM;
+    T* cby = cbx + CMY * CM;
+    T* cd = cby + CMY * CM;
+    T* xl = cd + CMY * CM;
+    T* xh = xl + 2 * DWT_OTY * CM;
     const int hy = sy >> 1, hx = sx >> 1;
-    const int oty = hy < DWT_OT ? hy : DWT_OT, otx = hx < DWT_OT ? hx : DWT_OT;
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
-    const long band = blockIdx.z;
     const int CY = oty + H2, CX = otx + H2;
-    const T* zb = z + band * z_bs;
+    // the outputs this thread adds to, loaded first (accumulating form)
+    constexpr int OPT = (2 * DWT_OTY * DWT_OTX + DWT_NTH - 1) / DWT_NTH;
+    T oq[2][OPT];
+    if (accumulate) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int j = 0; j < OPT; ++j) {
+                const int e = threadIdx.x + j * DWT_NTH;
+                if (e < 2 * oty * otx) {
+                    const int rr = e / otx, c2 = e - rr * otx;
+                    oq[p][j] = ob[long(2 * i0 + rr) * out_ld + 2 * m0 + 2 * c2 + p];
+                }
+            }
+    }
     for (int e = threadIdx.x; e < CY * CX; e += DWT_NTH) {
         const int n = e / CX, q = e - n * CX;
         // periodic coefficient indices i0 - H2 + n, m0 - H2 + q (hy, hx powers of two)
         const long gi = (i0 - H2 + n + 8 * hy) & (hy - 1), gm = (m0 - H2 + q + 8 * hx) & (hx - 1);
-        ca[n * CM + q] = llin ? llin[band * long(hy) * hx + gi * hx + gm] : ucoef(zb[gi * ld + gm], tau);
+        ca[n * CM + q] = llb ? llb[gi * hx + gm] : ucoef(zb[gi * ld + gm], tau);
         cbx[n * CM + q] = ucoef(zb[gi * ld + hx + gm], tau);
         cby[n * CM + q] = ucoef(zb[(hy + gi) * ld + gm], tau);
         cd[n * CM + q] = ucoef(zb[(hy + gi) * ld + hx + gm], tau);
     }
     __syncthreads();
-    // along y: output rows rr of the tile, coefficient columns q
-    for (int e = threadIdx.x; e < 2 * oty * CX; e += DWT_NTH) {
-        const int rr = e / CX, q = e - rr * CX;
-        const int p = rr & 1, base = (rr >> 1) + H2;
-        T lo = T(0), hi = T(0);
+    // along y: output rows rr = 2 r2 + p of the tile (the parity p picks the
+    // filter taps, so it is the outer, unrolled loop), coefficient columns q
 #pragma unroll
-        for (int kk = 0; kk < K / 2; ++kk) {
-            const int k = 2 * kk + p, n = base - kk;
-            lo += f.h[k] * ca[n * CM + q] + f.g[k] * cby[n * CM + q];
-            hi += f.h[k] * cbx[n * CM + q] + f.g[k] * cd[n * CM + q];
+    for (int p = 0; p < 2; ++p) {
+        for (int e = threadIdx.x; e < oty * CX; e += DWT_NTH) {
+            const int r2 = e / CX, q = e - r2 * CX;
+            const int base = r2 + H2;
+            T lo = T(0), hi = T(0);
+#pragma unroll
+            for (int kk = 0; kk < K / 2; ++kk) {
+                const int n = base - kk;
+                lo += h[2 * kk + p] * ca[n * CM + q] + g[2 * kk + p] * cby[n * CM + q];
+                hi += h[2 * kk + p] * cbx[n * CM + q] + g[2 * kk + p] * cd[n * CM + q];
+            }
+            xl[(2 * r2 + p) * CM + q] = lo;
+            xh[(2 * r2 + p) * CM + q] = hi;
         }
-        xl[rr * CM + q] = lo;
-        xh[rr * CM + q] = hi;
     }
     __syncthreads();
-    // along x
-    T* ob = out + band * out_bs;
-    for (int e = threadIdx.x; e < 4 * oty * otx; e += DWT_NTH) {
-        const int rr = e / (2 * otx), cc = e - rr * (2 * otx);
-        const int p = cc & 1, base = (cc >> 1) + H2;
-        T v = T(0);
+    // along x: output columns cc = 2 c2 + p
 #pragma unroll
-        for (int kk = 0; kk < K / 2; ++kk) {
-            const int k = 2 * kk + p, q = base - kk;
-            v += f.h[k] * xl[rr * CM + q] + f.g[k] * xh[rr * CM + q];
+    for (int p = 0; p < 2; ++p) {
+#pragma unroll
+        for (int j = 0; j < OPT; ++j) {
+            const int e = threadIdx.x + j * DWT_NTH;
+            if (e < 2 * oty * otx) {
+                const int rr = e / otx, c2 = e - rr * otx;
+                const int base = c2 + H2;
+                T v = T(0);
+#pragma unroll
+                for (int kk = 0; kk < K / 2; ++kk) {
+                    const int q = base - kk;
+                    v += h[2 * kk + p] * xl[rr * CM + q] + g[2 * kk + p] * xh[rr * CM + q];
+                }
+                T* o = ob + long(2 * i0 + rr) * out_ld + 2 * m0 + 2 * c2 + p;
+                *o = accumulate ? oq[p][j] + scale * v : v;
+            }
         }
-        T* o = ob + long(2 * i0 + rr) * out_ld + 2 * m0 + cc;
-        if (accumulate) *o += scale * v;
-        else *o = v;
     }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void load_taps(const T* __restrict__ fb, T (&h)[K], T (&g)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        h[k] = fb[k];
+        g[k] = fb[16 + k];
+    }
+}
+
+// One analysis level of every basis and band: blockIdx.z = basis * L + band.
+template <typename T>
+__global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd_all(DwtLevel A) {
+    __shared__ T smem[DWT_FWD_LDS];
+    const int b = blockIdx.z / A.L;
+    const long band = blockIdx.z - b * A.L;
+    const T* src = (const T*)A.in0 + b * A.in_bstride + band * A.in_bs;
+    T* zb = (T*)A.z0 + b * A.zstride + band * A.z_bs;
+    T* llb = A.ll0 ? (T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
+    const T* fb = (const T*)A.ftab + 32 * b;
+    switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
+#define F(KK)                                                                                  \
+    case KK: {                                                                                 \
+        T h[KK], g[KK];                                                                        \
+        load_taps<T, KK>(fb, h, g);                                                            \
+        dwt_fwd_tile<T, KK>(src, A.in_ld, zb, A.ld, llb, A.sy, A.sx, h, g, T(A.tau), smem);    \
+        break;                                                                                 \
+    }
+        MUFFIN_DWT_K_CASES(F)
+#undef F
+        default: break;
+    }
+}
+
+// One synthesis level (not the finest) of every basis and band into the
+// bases' dense scratch images: blockIdx.z = basis * L + band.
+template <typename T>
+__global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
+    __shared__ T smem[DWT_INV_LDS];
+    const int b = blockIdx.z / A.L;
+    const long band = blockIdx.z - b * A.L;
+    const T* zb = (const T*)A.z0 + b * A.zstride + band * A.z_bs;
+    const T* llb = A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
+    T* ob = (T*)A.out0 + b * A.outstride + band * long(A.sy) * A.sx;
+    const T* fb = (const T*)A.ftab + 32 * b;
+    switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
+#define F(KK)                                                                                          \
+    case KK: {                                                                                         \
+        T h[KK], g[KK];                                                                                \
+        load_taps<T, KK>(fb, h, g);                                                                    \
+        dwt_inv_tile<T, KK>(llb, zb, A.ld, ob, A.sx, A.sy, A.sx, h, g, T(A.tau), T(1), false, smem);   \
+        break;                                                                                         \
+    }
+        MUFFIN_DWT_K_CASES(F)
+#undef F
+        default: break;
+    }
+}
+
+// The finest synthesis level of one basis, added into B_rest (row stride nx,
+// band stride ny nx): Brest += scale * x.
+template <typename T, int K>
+__global__ void __launch_bounds__(DWT_NTH)
+k_dwt_inv0(const T* __restrict__ llin, const T* __restrict__ z, T* __restrict__ Brest, int ny, int nx,
+           WFilt<T> f, T tau, T scale) {
+    constexpr int CMY = DWT_OTY + K / 2 - 1, CM = DWT_OTX + K / 2 - 1;
+    __shared__ T smem[4 * CMY * CM + 2 * (2 * DWT_OTY) * CM];
+    const long band = blockIdx.z;
+    T h[K], g[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        h[k] = f.h[k];
+        g[k] = f.g[k];
+    }
+    const long vb = long(ny) * nx;
+    dwt_inv_tile<T, K>(llin ? llin + band * (vb / 4) : nullptr, z + band * vb, nx, Brest + band * vb, nx, ny, nx,
+                       h, g, tau, scale, true, smem);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -172,62 +301,55 @@ template <typename T> static WFilt<T> make_filt(const double* h, int K) {
     return f;
 }
 
-static dim3 dwt_grid(int sy, int sx, int L) {
+static dim3 dwt_grid(int sy, int sx, int nz) {
     const int hy = sy / 2, hx = sx / 2;
-    const int oty = hy < DWT_OT ? hy : DWT_OT, otx = hx < DWT_OT ? hx : DWT_OT;
-    return dim3((unsigned)(hx / otx), (unsigned)(hy / oty), (unsigned)L);
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
+    return dim3((unsigned)(hx / otx), (unsigned)(hy / oty), (unsigned)nz);
 }
 
-template <typename T, int K>
-static hipError_t dwt_fwd_t(const double* h, const void* in, int in_ld, long in_bs, void* z, int ld, long z_bs,
-                            void* llout, int sy, int sx, int L, double tau, hipStream_t s) {
-    hipLaunchKernelGGL((k_dwt_fwd<T, K>), dwt_grid(sy, sx, L), dim3(DWT_NTH), 0, s, (const T*)in, in_ld, in_bs,
-                       (T*)z, ld, z_bs, (T*)llout, sy, sx, make_filt<T>(h, K), T(tau));
-    return hipGetLastError();
-}
-
-template <typename T, int K>
-static hipError_t dwt_inv_t(const double* h, const void* llin, const void* z, int ld, long z_bs, void* out,
-                            int out_ld, long out_bs, int sy, int sx, int L, double tau, double scale,
-                            bool accumulate, hipStream_t s) {
-    hipLaunchKernelGGL((k_dwt_inv<T, K>), dwt_grid(sy, sx, L), dim3(DWT_NTH), 0, s, (const T*)llin,
-                       (const T*)z, ld, z_bs, (T*)out, out_ld, out_bs, sy, sx, make_filt<T>(h, K), T(tau),
-                       T(scale), accumulate ? 1 : 0);
-    return hipGetLastError();
-}
-
-#define MUFFIN_DWT_K_CASES(F) F(2) F(4) F(6) F(8) F(10) F(12) F(14) F(16)
-
-static bool dwt_args_ok(int K, int sy, int sx, int L) {
-    return K >= 2 && K <= 16 && (K & 1) == 0 && sy >= 4 && sx >= 4 && (sy & (sy - 1)) == 0 &&
-           (sx & (sx - 1)) == 0 && L >= 1;
-}
-
-hipError_t launch_dwt_fwd(int dtype, int K, const double* h, const void* in, int in_ld, long in_bs, void* z,
-                          int ld, long z_bs, void* llout, int sy, int sx, int L, double tau, hipStream_t s) {
-    if (!dwt_args_ok(K, sy, sx, L)) return hipErrorInvalidValue;
-    switch (K) {
-#define F(KK)                                                                                              \
-    case KK:                                                                                               \
-        return dtype == 0 ? dwt_fwd_t<float, KK>(h, in, in_ld, in_bs, z, ld, z_bs, llout, sy, sx, L, tau, s) \
-                          : dwt_fwd_t<double, KK>(h, in, in_ld, in_bs, z, ld, z_bs, llout, sy, sx, L, tau, s);
-        MUFFIN_DWT_K_CASES(F)
-#undef F
+static bool level_ok(const DwtLevel& A) {
+    if (A.n < 1 || A.n > 8 || A.L < 1 || A.sy < 4 || A.sx < 4 || (A.sy & (A.sy - 1)) || (A.sx & (A.sx - 1)))
+        return false;
+    for (int b = 0; b < A.n; ++b) {
+        const unsigned k2 = (A.kpack >> (4 * b)) & 15u;
+        if (k2 < 1 || k2 > 8) return false;
     }
-    return hipErrorInvalidValue;
+    return true;
 }
 
-hipError_t launch_dwt_inv(int dtype, int K, const double* h, const void* llin, const void* z, int ld, long z_bs,
-                          void* out, int out_ld, long out_bs, int sy, int sx, int L, double tau, double scale,
-                          bool accumulate, hipStream_t s) {
-    if (!dwt_args_ok(K, sy, sx, L)) return hipErrorInvalidValue;
+hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s) {
+    if (!level_ok(A)) return hipErrorInvalidValue;
+    const dim3 grid = dwt_grid(A.sy, A.sx, A.n * A.L);
+    if (dtype == 0) hipLaunchKernelGGL(k_dwt_fwd_all<float>, grid, dim3(DWT_NTH), 0, s, A);
+    else hipLaunchKernelGGL(k_dwt_fwd_all<double>, grid, dim3(DWT_NTH), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_dwt_inv_all(int dtype, const DwtLevel& A, hipStream_t s) {
+    if (!level_ok(A) || !A.out0) return hipErrorInvalidValue;
+    const dim3 grid = dwt_grid(A.sy, A.sx, A.n * A.L);
+    if (dtype == 0) hipLaunchKernelGGL(k_dwt_inv_all<float>, grid, dim3(DWT_NTH), 0, s, A);
+    else hipLaunchKernelGGL(k_dwt_inv_all<double>, grid, dim3(DWT_NTH), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+static hipError_t inv0_t(const double* h, const void* llin, const void* z, void* Brest, int ny, int nx, int L,
+                         double tau, double scale, hipStream_t s) {
+    hipLaunchKernelGGL((k_dwt_inv0<T, K>), dwt_grid(ny, nx, L), dim3(DWT_NTH), 0, s, (const T*)llin, (const T*)z,
+                       (T*)Brest, ny, nx, make_filt<T>(h, K), T(tau), T(scale));
+    return hipGetLastError();
+}
+
+hipError_t launch_dwt_inv0(int dtype, int K, const double* h, const void* llin, const void* z, void* Brest, int ny,
+                           int nx, int L, double tau, double scale, hipStream_t s) {
+    if (K < 2 || K > 16 || (K & 1) || ny < 4 || nx < 4 || L < 1 || (ny & (ny - 1)) || (nx & (nx - 1)))
+        return hipErrorInvalidValue;
     switch (K) {
-#define F(KK)                                                                                           \
-    case KK:                                                                                            \
-        return dtype == 0 ? dwt_inv_t<float, KK>(h, llin, z, ld, z_bs, out, out_ld, out_bs, sy, sx, L, tau, \
-                                                 scale, accumulate, s)                                   \
-                          : dwt_inv_t<double, KK>(h, llin, z, ld, z_bs, out, out_ld, out_bs, sy, sx, L,  \
-                                                  tau, scale, accumulate, s);
+#define F(KK)                                                                                          \
+    case KK:                                                                                           \
+        return dtype == 0 ? inv0_t<float, KK>(h, llin, z, Brest, ny, nx, L, tau, scale, s)             \
+                          : inv0_t<double, KK>(h, llin, z, Brest, ny, nx, L, tau, scale, s);
         MUFFIN_DWT_K_CASES(F)
 #undef F
     }
