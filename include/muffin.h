@@ -193,6 +193,14 @@ int muffin_get_p(muffin_ctx* ctx, void* p_out);
 int muffin_grad(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
                 double* loss, double grad[3]);
 
+/* The same reverse sweep, with the derivative along each parameter on its
+   own: grad = d/d(mu_eps, mu_s, mu_nu, rho_P, rho_T, rho_V, rho_S) (host
+   double[7]).  mu_eps enters through rho of eq. Qlsimp only; the tied-rho
+   derivative of muffin_grad is the sum of the last four.  Errors as
+   muffin_grad. */
+int muffin_grad_params(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
+                       double* loss, double grad[7]);
+
 /* Bytes of one state snapshot: the iteration's carried arrays (the prox
    inputs z_P and z_T of steps II-III, the spectral prox input
    z_V = S - Gamma_S / rho_V of step IV, and Gamma_S; Gamma_V = Gamma_S W_nu

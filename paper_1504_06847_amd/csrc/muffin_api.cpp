@@ -418,9 +418,15 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     const double rV = h[G_RHO_V] - h[G_TAU_V] * p.mu_nu / (p.rho_V * p.rho_V);
     const double rP = h[G_RHO_P] + h[G_RHO_Q];
     const double rS = h[G_RHO_S] + h[G_RHO_Q];
-    grad[0] = h[G_TAU_T] / p.rho_T;
-    grad[1] = h[G_TAU_V] / p.rho_V;
-    grad[2] = rP + rT + rV + rS;
+    // d/d(mu_eps, mu_s, mu_nu, rho_P, rho_T, rho_V, rho_S): mu_eps enters
+    // through rho of eq. Qlsimp only, mu_s and mu_nu through the thresholds
+    grad[0] = h[G_RHO_Q];
+    grad[1] = h[G_TAU_T] / p.rho_T;
+    grad[2] = h[G_TAU_V] / p.rho_V;
+    grad[3] = rP;
+    grad[4] = rT;
+    grad[5] = rV;
+    grad[6] = rS;
     if (loss) *loss = mode == MUFFIN_MODE_MSE ? h[G_LOSS] : 0.0;
     return MUFFIN_OK;
 }
@@ -792,6 +798,27 @@ int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int
     }
     if (!sky_or_gx || !grad || (mode != MUFFIN_MODE_MSE && mode != MUFFIN_MODE_VJP)) {
         set_error("muffin_grad: sky_or_gx and grad must be non-NULL, mode MSE or VJP");
+        return MUFFIN_EINVAL;
+    }
+    double full[7];
+    const int rc = grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, full);
+    if (rc) return rc;
+    grad[0] = full[1];
+    grad[1] = full[2];
+    grad[2] = full[3] + full[4] + full[5] + full[6];
+    return MUFFIN_OK;
+}
+
+int muffin_grad_params(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, double* loss,
+                       double grad[7]) {
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = no_wavelets(c, "muffin_grad_params")) return rc;
+    if (K < 1 || ckpt_every < 1) {
+        set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
+        return MUFFIN_EINVAL;
+    }
+    if (!sky_or_gx || !grad || (mode != MUFFIN_MODE_MSE && mode != MUFFIN_MODE_VJP)) {
+        set_error("muffin_grad_params: sky_or_gx and grad must be non-NULL, mode MSE or VJP");
         return MUFFIN_EINVAL;
     }
     return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, grad);

@@ -75,6 +75,8 @@ SIGNATURES = [
     ("muffin_get_p", c_int, [c_void_p, c_void_p]),
     ("muffin_grad", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double),
                             POINTER(c_double)]),
+    ("muffin_grad_params", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double),
+                                   POINTER(c_double)]),
     ("muffin_state_bytes", c_size_t, [c_void_p]),
     ("muffin_get_state", c_int, [c_void_p, c_void_p]),
     ("muffin_set_state", c_int, [c_void_p, c_void_p]),

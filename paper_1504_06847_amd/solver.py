@@ -271,6 +271,25 @@ class Solver:
         L.check(rc, "muffin_grad", self._lib)
         return loss.value, np.array([g[0], g[1], g[2]])
 
+    GRAD_PARAMS = ("mu_eps", "mu_s", "mu_nu", "rho_P", "rho_T", "rho_V", "rho_S")
+
+    def grad_params(self, K: int, *, sky=None, gx=None, ckpt_every: int = 5):
+        """As ``grad``, with the derivative along each parameter on its own:
+        returns (loss, {name: d loss / d name}) for GRAD_PARAMS."""
+        if (sky is None) == (gx is None):
+            raise ValueError("give exactly one of sky and gx")
+        ref = _as_cube(sky if sky is not None else gx, self.dtype, self.device)
+        if tuple(ref.shape) != tuple(self.shape):
+            raise ValueError(f"expected a cube of shape {self.shape}, got {tuple(ref.shape)}")
+        mode = L.MUFFIN_MODE_MSE if sky is not None else L.MUFFIN_MODE_VJP
+        loss = c_double()
+        g = (c_double * 7)()
+        with torch.cuda.stream(self.stream):
+            rc = self._lib.muffin_grad_params(self._ctx, int(K), int(ckpt_every), c_void_p(ref.data_ptr()), mode,
+                                              byref(loss), g)
+        L.check(rc, "muffin_grad_params", self._lib)
+        return loss.value, {n: g[i] for i, n in enumerate(self.GRAD_PARAMS)}
+
     # -------------------------------------------------------------- timing
     def profile(self, n_iter: int = 10) -> dict:
         cap = 16
