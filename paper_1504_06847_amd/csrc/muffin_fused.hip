@@ -29,7 +29,7 @@ namespace muffin {
 template <int NX, int LT> constexpr int fused_ppt() { return 1; }
 
 template <int LT> constexpr int fused_g() { return LT < 16 ? LT : (LT >= 64 ? 8 : 16); }
-// with 64 bands, q of the first fused_qb bands waits in LDS: the band vector
+// with 64 bands, q of the last fused_qb bands waits in LDS: the band vector
 // of the others plus the row transforms fill the registers
 template <int LT> constexpr int fused_qb() { return LT >= 64 ? 28 : 0; }
 
@@ -88,8 +88,10 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
         dct_any<T, LT, DENSE, true>(v[p], D, L);        // q = V W_nu^T
         __builtin_amdgcn_sched_barrier(0);
     }
+    // the last QB bands wait in LDS: the register-held ones are consumed by
+    // the first groups, so fewer of them stay live across the row transforms
 #pragma unroll
-    for (int l = 0; l < QB; ++l) qlds[l * NTH + t] = v[0][l];
+    for (int l = 0; l < QB; ++l) qlds[l * NTH + t] = v[0][LT - QB + l];
 
     T* lrow = reinterpret_cast<T*>(lds);
 #pragma unroll
@@ -120,7 +122,7 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
                     const int e = r * TS * 2 + 2 * lds_pos<true>(x >> 1) + (x & 1);
                     const T xv = lrow[e];
                     const T gs = GS.load(l, off[p]), zp = zP.load(l, off[p]), zt = zT.load(l, off[p]);
-                    const T q = (l < QB) ? qlds[l * NTH + t] : v[p][l];
+                    const T q = (l >= LT - QB) ? qlds[(l - (LT - QB)) * NTH + t] : v[p][l];
                     const T s = (rhoV * q + rhoS * xv) * inv_VS;
                     const T gs2 = gs + rhoV * (q - s);
                     const T zp2 = xv - (zp < T(0) ? -zp : T(0));
