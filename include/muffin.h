@@ -201,6 +201,14 @@ int muffin_grad(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, i
 int muffin_grad_params(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
                        double* loss, double grad[7]);
 
+/* The same reverse sweep, returning the cotangent of the dirty images:
+   gy_out (device [L][ny][nx], the iteration's dtype, caller-owned) receives
+   dL/dY.  Y enters every pass through H^T Y in the right-hand side of step
+   I (eq. matB), so dL/dY = H sum_k Q^{-1} X-bar_k, with X-bar_k the
+   cotangent of pass k's X.  loss as muffin_grad.  Errors as muffin_grad. */
+int muffin_grad_dirty(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
+                      double* loss, void* gy_out);
+
 /* Bytes of one state snapshot: the iteration's carried arrays (the prox
    inputs z_P and z_T of steps II-III, the spectral prox input
    z_V = S - Gamma_S / rho_V of step IV, and Gamma_S; Gamma_V = Gamma_S W_nu

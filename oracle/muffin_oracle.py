@@ -322,8 +322,9 @@ def mse_loss(XK, sky) -> float:
     return float(np.sum(d * d))
 
 
-def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params):
-    """Primal pass of Algorithm 1 with its forward-mode tangent (Dirac W_s)."""
+def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params, dHtY=None):
+    """Primal pass of Algorithm 1 with its forward-mode tangent (Dirac W_s);
+    dHtY: the tangent of H^T Y (a change of the dirty images), or None."""
     assert prob.dirac_only, "the tangent pass is written for W_s = identity"
     p = prob.p
     drhoQ = dp.mu_eps + dp.rho_S + dp.rho_P + dp.rho_T
@@ -331,6 +332,8 @@ def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params):
          + st.GS + p.rho_S * st.S)
     dB = (dst.GT + dp.rho_T * st.T + p.rho_T * dst.T + dst.GP + dp.rho_P * st.P
           + p.rho_P * dst.P + dst.GS + dp.rho_S * st.S + p.rho_S * dst.S)
+    if dHtY is not None:
+        dB = dB + dHtY
     X = prob.solve_Q(B)
     dX = prob.solve_Q(dB - drhoQ * X)          # d(Q^{-1}) = -Q^{-1} dQ Q^{-1}
     zP = X - st.GP / p.rho_P
@@ -369,11 +372,12 @@ def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params):
             State(dX, dP, dT, dV, dS, dGP, dGT, dGV, dGS))
 
 
-def jvp_run(prob: Problem, K: int, direction):
+def jvp_run(prob: Problem, K: int, direction, dY=None):
     """X^K and its directional derivative along ``direction``.
 
     ``direction`` = (d mu_s, d mu_nu, d rho) with rho_P = rho_T = rho_V = rho_S
-    = rho tied, or a full ``Params`` of tangents."""
+    = rho tied, or a full ``Params`` of tangents; ``dY``: a tangent of the
+    dirty images (entering through H^T Y of eq. matB) added to it."""
     if isinstance(direction, Params):
         dp = direction
     else:
@@ -381,8 +385,9 @@ def jvp_run(prob: Problem, K: int, direction):
         dp = Params(0.0, a, b, c, c, c, c)
     st = State.zeros(prob.shape)
     dst = State.zeros(prob.shape)
+    dHtY = None if dY is None else prob.HT(np.asarray(dY, np.float64))
     for _ in range(K):
-        st, dst = _jvp_iteration(prob, st, dst, dp)
+        st, dst = _jvp_iteration(prob, st, dst, dp, dHtY)
     return st.X, dst.X
 
 

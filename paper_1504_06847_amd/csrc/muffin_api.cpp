@@ -298,9 +298,13 @@ size_t state_array_bytes(const muffin_ctx* c) {
 //   seg  : C x 5 arrays (state before the pass, X of the pass)
 //   fin  : 5 arrays (the state after K passes, restored at the end)
 //   adj  : 4 state cotangents, X-bar, B-bar
+//   gyac : (with gy_out) the sum over the passes of B-bar
 //   partials, acc (FP64)
+// With gy_out, the cotangent of the dirty images goes there too: Y enters
+// every pass through H^T Y in step I's right-hand side (eq. matB), so
+// dL/dY = H sum_k B-bar_k.
 int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, double* loss,
-               double grad[3]) {
+               double grad[7], void* gy_out = nullptr) {
     const muffin_shape& s = c->shape;
     if (C > K) C = K;
     const int nseg = (K + C - 1) / C;
@@ -308,7 +312,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     const long npix = long(s.ny) * s.nx;
     const size_t nparts = size_t(npix / 64 > 8192 ? npix / 64 : 8192);
     const size_t n_arrays = size_t(nseg) * kNumState + size_t(C) * (kNumState + 1) + (kNumState + 1) +
-                            (kNumState + 2);
+                            (kNumState + 2) + (gy_out ? 1 : 0);
     const size_t need = n_arrays * ab + nparts * GRAD_NQ * 8 + kAlign;
     if (c->grad_bytes < need) {
         if (c->grad_buf) HIP_TRY(hipFree(c->grad_buf));
@@ -323,7 +327,8 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     auto segs = [&](int j, int i) { return seg0 + (size_t(j) * (kNumState + 1) + i) * ab; };   // i = 4: X
     char* fin = seg0 + size_t(C) * (kNumState + 1) * ab;
     char* adj = fin + (kNumState + 1) * ab;                  // aP, aT, aS, aG, Xb, Bb
-    double* partials = (double*)(adj + (kNumState + 2) * ab);
+    char* gyac = adj + (kNumState + 2) * ab;
+    double* partials = (double*)(gyac + (gy_out ? ab : 0));
     double* acc = partials + nparts * GRAD_NQ;
     const int dt = s.dtype, nrows = s.L * s.ny;
     const SpecArgs a = spec_args(c->params);
@@ -354,6 +359,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         HIP_TRY(copy(Xb, sky_or_gx));
     }
     for (int i = 0; i < kNumState; ++i) HIP_TRY(launch_fill_zero(adj + i * ab, nb, st_));
+    if (gy_out) HIP_TRY(launch_fill_zero(gyac, nb, st_));
 
     const unsigned bb = unsigned(npix * long(elem_size(s)));
     const int gsh = spectral_gshift(bb);
@@ -394,6 +400,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
                                nullptr, nullptr, st_));
             HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), Bb, nrows, s.nx, P(c, c->lay.tw), c->twlog, st_,
                                    c->row_v));
+            if (gy_out) HIP_TRY(launch_add(dt, gyac, Bb, voxels(s), st_));
             HIP_TRY(launch_adj_step1(dt, Bb, A.zP, A.zT, A.zV, A.GS, A.X, A.aP, A.aT, A.aS, A.aG, voxels(s), a,
                                      partials, &nbk, st_));
             HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
@@ -402,6 +409,16 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     // leave the context at the state after K passes
     for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), fin + i * ab));
     HIP_TRY(copy(P(c, c->lay.x), fin + kNumState * ab));
+    if (gy_out) {
+        // dL/dY = H (sum of B-bar): the transfer function applied in the
+        // Fourier domain (Z is scratch here; B_rest is rebuilt below)
+        HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, gyac, P(c, c->lay.z), nrows, s.nx, s.ny, false, false,
+                               P(c, c->lay.tw), c->twlog, st_, c->row_v));
+        HIP_TRY(launch_col(dt, COL_CONV, P(c, c->lay.z), P(c, c->lay.hh), nullptr, P(c, c->lay.hhnyq), 0.0,
+                           fft_scale(s), s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog, nullptr, nullptr, st_));
+        HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), gy_out, nrows, s.nx, P(c, c->lay.tw), c->twlog, st_,
+                               c->row_v));
+    }
     if ((rc = recompute_brest(c)) != MUFFIN_OK) return rc;
     c->iters = K;
     double h[GRAD_NQ];
@@ -531,7 +548,8 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
         e = launch_col(MUFFIN_F64, COL_FWD, Cy, nullptr, nullptr, nullptr, 0.0, 1.0, shape->L, shape->ny,
                        shape->nx, P(c, lay.tw64), c->twlog, nullptr, nullptr, c->stream);
     if (e == hipSuccess)
-        e = launch_setup_combine(shape->dtype, Ch, Cy, P(c, lay.yf), P(c, lay.h2), P(c, lay.h2nyq),
+        e = launch_setup_combine(shape->dtype, Ch, Cy, P(c, lay.yf), P(c, lay.h2), P(c, lay.h2nyq), P(c, lay.hh),
+                                 P(c, lay.hhnyq),
                                  shape->L, shape->ny, shape->nx, c->stream);
     if (e != hipSuccess) { set_error("setup transform launch failed: %s", hipGetErrorString(e)); return fail(MUFFIN_EDEVICE); }
     if ((rc = zero_state(c)) != MUFFIN_OK) return fail(rc);
@@ -807,6 +825,22 @@ int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int
     grad[1] = full[2];
     grad[2] = full[3] + full[4] + full[5] + full[6];
     return MUFFIN_OK;
+}
+
+int muffin_grad_dirty(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, double* loss,
+                      void* gy_out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = no_wavelets(c, "muffin_grad_dirty")) return rc;
+    if (K < 1 || ckpt_every < 1) {
+        set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
+        return MUFFIN_EINVAL;
+    }
+    if (!sky_or_gx || !gy_out || (mode != MUFFIN_MODE_MSE && mode != MUFFIN_MODE_VJP)) {
+        set_error("muffin_grad_dirty: sky_or_gx and gy_out must be non-NULL, mode MSE or VJP");
+        return MUFFIN_EINVAL;
+    }
+    double full[7];
+    return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, full, gy_out);
 }
 
 int muffin_grad_params(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, double* loss,

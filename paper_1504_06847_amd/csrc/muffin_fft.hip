@@ -317,6 +317,43 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         }
     }
 
+    if constexpr (MODE == COL_CONV) {
+        // multiplication by the transfer function h_hat (Yf holds it packed,
+        // H2nyq its kx = nx/2 column as complex values), then the inverse FFT
+        const cx<T>* Hh = Yf;
+        const cx<T>* Hn = reinterpret_cast<const cx<T>*>(H2nyq);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int i = t + j * NTH;
+            const int y = i / TC, c = i % TC, kx = c0 + c;
+            if (i >= NY * TC || kx == 0 || kx >= M) continue;
+            const long g = base + filt_pos(NY, fsh, y, kx);
+            lds[swz_pos<NY, TC>(y, c)] = cmul(lds[swz_pos<NY, TC>(y, c)], Hh[g]) * scale;
+        }
+        if (c0 == 0) {
+            for (int ky = t; ky <= NY / 2; ky += NTH) {
+                const int kn = (NY - ky) & (NY - 1);
+                const cx<T> c1 = lds[swz_pos<NY, TC>(ky, 0)], c2 = lds[swz_pos<NY, TC>(kn, 0)];
+                cx<T> A = {T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)};
+                cx<T> B = {T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x)};
+                A = cmul(A, Hh[base + filt_pos(NY, fsh, ky, 0)]) * scale;
+                B = cmul(B, Hn[(long)band * NY + ky]) * scale;
+                lds[swz_pos<NY, TC>(ky, 0)] = A + mul_i(B);
+                if (kn != ky) lds[swz_pos<NY, TC>(kn, 0)] = conj(A) + mul_i(conj(B));
+            }
+        }
+        __syncthreads();
+        if constexpr (TWL) {
+            fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1, COL_TWP>(lds, twl, ilog2c(NY), t);
+            fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true, COL_TWP>(lds, twl, ilog2c(NY),
+                                                                                   data + base + c0, M, ntr, t);
+        } else {
+            fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1>(lds, tw, twlog, t);
+            fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true>(lds, tw, twlog, data + base + c0, M,
+                                                                          ntr, t);
+        }
+    }
+
     if constexpr (MODE == COL_FWD) {
 #pragma unroll
         for (int j = 0; j < NIT; ++j) {
@@ -400,8 +437,8 @@ k_col_group(const ColDesc* __restrict__ d, int n) {
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_setup_combine(const cx<double>* __restrict__ Ch, const cx<double>* __restrict__ Cy,
-                cx<T>* __restrict__ Yf, T* __restrict__ H2, T* __restrict__ H2nyq, int L,
-                int ny, int M) {
+                cx<T>* __restrict__ Yf, T* __restrict__ H2, T* __restrict__ H2nyq, cx<T>* __restrict__ Hh,
+                cx<T>* __restrict__ Hhnyq, int L, int ny, int M) {
     // Ch, Cy in spectrum order [L][ny][M]; Yf, H2 written in column-block order
     const long n = (long)L * ny * M;
     const int fsh = filt_shift<T>(ny, M);
@@ -415,6 +452,7 @@ k_setup_combine(const cx<double>* __restrict__ Ch, const cx<double>* __restrict_
             const cx<double> f = {h.x * y.x + h.y * y.y, h.x * y.y - h.y * y.x};   // conj(h) y
             Yf[o] = {T(f.x), T(f.y)};
             H2[o] = T(h.x * h.x + h.y * h.y);
+            Hh[o] = {T(h.x), T(h.y)};
         } else if (ky <= ny / 2) {
             const int kn = (ny - ky) & (ny - 1);
             const long i2 = band * ny * M + (long)kn * M;
@@ -434,6 +472,12 @@ k_setup_combine(const cx<double>* __restrict__ Ch, const cx<double>* __restrict_
             H2[o2] = a2;
             H2nyq[band * ny + ky] = b2;
             H2nyq[band * ny + kn] = b2;
+            // the transfer functions of the kx = 0 and kx = nx/2 columns
+            // (each Hermitian in ky)
+            Hh[o] = {T(Ah.x), T(Ah.y)};
+            Hh[o2] = {T(Ah.x), T(-Ah.y)};
+            Hhnyq[band * ny + ky] = {T(Bh.x), T(Bh.y)};
+            Hhnyq[band * ny + kn] = {T(Bh.x), T(-Bh.y)};
         }
     }
 }
@@ -584,10 +628,14 @@ hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const voi
             return col_t<float, COL_OBJ, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
         if (mode == COL_FILTER)
             return col_t<float, COL_FILTER, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+        if (mode == COL_CONV)
+            return col_t<float, COL_CONV, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
         return hipErrorInvalidValue;
     }
     if (mode == COL_FILTER)
         return col_t<double, COL_FILTER, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+    if (mode == COL_CONV)
+        return col_t<double, COL_CONV, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
     if (mode == COL_SOLVE) {
         MUFFIN_VARIANT(variant, return (col_t<double, COL_SOLVE, V>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s)))
     }
@@ -647,18 +695,18 @@ hipError_t launch_col_group(int dtype, int ny, int variant, const ColDesc* d, in
 }
 
 hipError_t launch_setup_combine(int dtype, const void* Ch, const void* Cy, void* Yf, void* H2,
-                                void* H2nyq, int L, int ny, int nx, hipStream_t s) {
+                                void* H2nyq, void* Hh, void* Hhnyq, int L, int ny, int nx, hipStream_t s) {
     const int M = nx / 2;
     const long n = (long)L * ny * M;
     const int blocks = int((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
     if (dtype == 0)
         hipLaunchKernelGGL((k_setup_combine<float>), dim3(blocks), dim3(256), 0, s,
                            (const cx<double>*)Ch, (const cx<double>*)Cy, (cx<float>*)Yf,
-                           (float*)H2, (float*)H2nyq, L, ny, M);
+                           (float*)H2, (float*)H2nyq, (cx<float>*)Hh, (cx<float>*)Hhnyq, L, ny, M);
     else
         hipLaunchKernelGGL((k_setup_combine<double>), dim3(blocks), dim3(256), 0, s,
                            (const cx<double>*)Ch, (const cx<double>*)Cy, (cx<double>*)Yf,
-                           (double*)H2, (double*)H2nyq, L, ny, M);
+                           (double*)H2, (double*)H2nyq, (cx<double>*)Hh, (cx<double>*)Hhnyq, L, ny, M);
     return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@
 
 namespace muffin {
 
-enum ColMode { COL_SOLVE = 0, COL_FWD = 1, COL_OBJ = 2, COL_FILTER = 3 };
+enum ColMode { COL_SOLVE = 0, COL_FWD = 1, COL_OBJ = 2, COL_FILTER = 3, COL_CONV = 4 };
 
 // Number of FP64 partial sums per block written by the spectral pass in
 // reduction mode, and their meaning.
@@ -55,8 +55,11 @@ hipError_t launch_row_inv(int dtype, const void* in, void* out, int nrows, int n
 // COL_SOLVE: FFT along y, X_hat = (Z + Yf) * scale / (H2 + rhoQ), inverse FFT.
 // COL_FWD: FFT along y only.  COL_OBJ: FFT along y, then per-block FP64
 // partials of sum w (H2 |Z|^2 - 2 Re(conj(Yf) Z)) / (nx ny) into partials.
-// COL_FILTER: as COL_SOLVE without the data term (Yf unused).  Yf and H2
-// are in the column-block order launch_setup_combine writes (H2nyq: [L][ny]).
+// COL_FILTER: as COL_SOLVE without the data term (Yf unused).  COL_CONV:
+// FFT along y, multiplication by h_hat * scale (the convolution H; Yf points
+// at the packed h_hat, H2nyq at its kx = nx/2 column, complex), inverse FFT.
+// Yf, H2 and h_hat are in the column-block order launch_setup_combine
+// writes (H2nyq: [L][ny]; the h_hat column: [L][ny] complex).
 hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const void* H2,
                       const void* H2nyq, double rhoQ, double scale, int L, int ny, int nx,
                       const void* tw, int twlog, double* partials, int* nblocks_out,
@@ -207,7 +210,10 @@ hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, in
 // min(16, 64 KiB / (ny complex values), nx/2), the default column tile),
 // each block's ny rows contiguous.
 hipError_t launch_setup_combine(int dtype, const void* Ch, const void* Cy, void* Yf, void* H2,
-                                void* H2nyq, int L, int ny, int nx, hipStream_t s);
+                                void* H2nyq, void* Hh, void* Hhnyq, int L, int ny, int nx, hipStream_t s);
+
+// dst[i] += src[i], i < n
+hipError_t launch_add(int dtype, void* dst, const void* src, size_t n, hipStream_t s);
 
 // Non-finite scan of psf and dirty plus sum dirty^2; writes per-block
 // partials (2 per block: count of non-finite values, sum of squares).

@@ -347,6 +347,12 @@ k_reencode(T* __restrict__ zP, T* __restrict__ zT, T* __restrict__ zV, const T* 
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) k_add(T* __restrict__ d, const T* __restrict__ a, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        d[i] += a[i];
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_positive(const T* __restrict__ z, T* __restrict__ o, long n) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const T v = z[i];
@@ -411,6 +417,15 @@ hipError_t launch_reencode(int dtype, void* zP, void* zT, void* zV, const void* 
     else
         hipLaunchKernelGGL((k_reencode<double>), dim3(grid_for(n)), dim3(256), 0, s, (double*)zP, (double*)zT,
                            (double*)zV, (const double*)GS, (long)n, rP, rT, tau, dV);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(int dtype, void* dst, const void* src, size_t n, hipStream_t s) {
+    if (dtype == 0)
+        hipLaunchKernelGGL((k_add<float>), dim3(grid_for(n)), dim3(256), 0, s, (float*)dst, (const float*)src, (long)n);
+    else
+        hipLaunchKernelGGL((k_add<double>), dim3(grid_for(n)), dim3(256), 0, s, (double*)dst, (const double*)src,
+                           (long)n);
     return hipGetLastError();
 }
 

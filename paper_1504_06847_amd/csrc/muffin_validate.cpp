@@ -124,6 +124,8 @@ Layout make_layout(const muffin_shape* s, int n_s) {
     lay.yf = take(HS * 2 * sz);
     lay.h2 = take(HS * sz);
     lay.h2nyq = take(size_t(s->L) * s->ny * sz);
+    lay.hh = take(HS * 2 * sz);
+    lay.hhnyq = take(size_t(s->L) * s->ny * 2 * sz);
     lay.tw = take(size_t(NT) * 2 * sz);
     lay.tw64 = take(size_t(NT) * 16);
     lay.dctm = take(size_t(dense_width(s->L)) * dense_width(s->L) * sz);

@@ -77,6 +77,7 @@ SIGNATURES = [
                             POINTER(c_double)]),
     ("muffin_grad_params", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double),
                                    POINTER(c_double)]),
+    ("muffin_grad_dirty", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double), c_void_p]),
     ("muffin_state_bytes", c_size_t, [c_void_p]),
     ("muffin_get_state", c_int, [c_void_p, c_void_p]),
     ("muffin_set_state", c_int, [c_void_p, c_void_p]),

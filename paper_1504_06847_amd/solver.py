@@ -290,6 +290,23 @@ class Solver:
         L.check(rc, "muffin_grad_params", self._lib)
         return loss.value, {n: g[i] for i, n in enumerate(self.GRAD_PARAMS)}
 
+    def grad_dirty(self, K: int, *, sky=None, gx=None, ckpt_every: int = 5):
+        """Cotangent of the dirty images: returns (loss, dL/dY) with dL/dY a
+        cube on the device (muffin_grad_dirty)."""
+        if (sky is None) == (gx is None):
+            raise ValueError("give exactly one of sky and gx")
+        ref = _as_cube(sky if sky is not None else gx, self.dtype, self.device)
+        if tuple(ref.shape) != tuple(self.shape):
+            raise ValueError(f"expected a cube of shape {self.shape}, got {tuple(ref.shape)}")
+        mode = L.MUFFIN_MODE_MSE if sky is not None else L.MUFFIN_MODE_VJP
+        loss = c_double()
+        gy = self._empty_cube()
+        with torch.cuda.stream(self.stream):
+            rc = self._lib.muffin_grad_dirty(self._ctx, int(K), int(ckpt_every), c_void_p(ref.data_ptr()), mode,
+                                             byref(loss), c_void_p(gy.data_ptr()))
+        L.check(rc, "muffin_grad_dirty", self._lib)
+        return loss.value, gy
+
     # -------------------------------------------------------------- timing
     def profile(self, n_iter: int = 10) -> dict:
         cap = 16

@@ -108,6 +108,32 @@ def test_per_parameter_gradient_matches_oracle_jvp(gpu_lib):
     assert g3[0] == g["mu_s"] and g3[1] == g["mu_nu"]
 
 
+@pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-9), (torch.float32, 1e-4)], ids=["f64", "f32"])
+def test_dirty_image_gradient_matches_oracle_jvp(gpu_lib, dtype, bar):
+    """muffin_grad_dirty: <dL/dY, dY> equals <gx, dX> for the oracle's tangent
+    along random changes dY of the dirty images (H applied to the summed
+    B-bar in the Fourier domain, the packed kx = 0 and nx/2 columns
+    included); the context ends in the state after K passes."""
+    from paper_1504_06847_amd import Solver
+    inst, p, kw = _grad64()
+    rng = np.random.default_rng(9)
+    gx = rng.standard_normal(inst.sky.shape)
+    s = Solver(inst.psf, inst.dirty, dtype=dtype, **kw)
+    loss, gy = s.grad_dirty(10, gx=gx, ckpt_every=4)
+    assert loss == 0.0
+    gy = gy.cpu().double().numpy()
+    prob = O.Problem(inst.psf, inst.dirty, p)
+    for trial in range(2):
+        dY = rng.standard_normal(inst.sky.shape)
+        _, dX = O.jvp_run(prob, 10, (0.0, 0.0, 0.0), dY=dY)
+        lhs, rhs = float(np.sum(gy * dY)), float(np.sum(gx * dX))
+        _say("dL/dY", dtype, lhs, rhs)
+        assert abs(lhs - rhs) <= bar * max(abs(rhs), float(np.sqrt(np.sum(gy ** 2) * np.sum(dY ** 2))))
+    ref = Solver(inst.psf, inst.dirty, dtype=dtype, **kw)
+    ref.iterate(10)
+    assert torch.equal(s.x, ref.x)
+
+
 def test_context_holds_the_K_pass_state_afterwards(gpu_lib):
     from paper_1504_06847_amd import Solver
     inst, p, kw = _grad64()

@@ -397,3 +397,20 @@ def test_jvp_gradient_matches_central_differences():
     ])
     np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
     assert loss == pytest.approx(L_at(base.mu_s, base.mu_nu, 1.0), rel=1e-14)
+
+
+def test_dirty_image_tangent_against_central_differences():
+    """The oracle's tangent along a change dY of the dirty images equals
+    central differences of K passes in Y (smooth away from the prox kinks)."""
+    rng = np.random.default_rng(12)
+    L, n = 3, 8
+    psf = _psf(rng, L, n)
+    Y = rng.uniform(-0.2, 1.5, (L, n, n))
+    p = O.Params(1e-3, 0.05, 0.1, 1.0, 1.0, 1.0, 1.0)
+    dY = rng.standard_normal((L, n, n))
+    _, dX = O.jvp_run(O.Problem(psf, Y, p), 6, (0.0, 0.0, 0.0), dY=dY)
+    h = 1e-6
+    xp = O.run(O.Problem(psf, Y + h * dY, p), 6).X
+    xm = O.run(O.Problem(psf, Y - h * dY, p), 6).X
+    fd = (xp - xm) / (2 * h)
+    assert np.abs(fd - dX).max() <= 1e-6 * np.abs(dX).max()
