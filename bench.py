@@ -17,7 +17,8 @@ Each pass is replayed from a HIP graph unless --no-graph is given.  The
 16-cube batch (uneven sizes and band counts) is timed in its per-cube
 sequential, grouped, grouped + graph and autotuned forms, and the paper's
 spatial dictionary (Dirac + Db1..Db8) on the same cube and on the paper's
-256 x 256 x 15 run shape (the `dictionary` object).
+256 x 256 x 15 run shape (the `dictionary` object).  The `grad` object times
+the reverse sweep of 20 unrolled passes at full size against 20 forward passes.
 """
 from __future__ import annotations
 
@@ -142,6 +143,32 @@ def run_gpu(inst, params, dtype, steps, warmup, profile_iters, graph=False):
     return ms, prof, schedule
 
 
+def run_grad(inst, params, K, ckpt_every=5):
+    """The reverse sweep of K unrolled FP32 passes (MSE loss against the sky,
+    gradient in mu_s, mu_nu, rho) at the cube's full size, timed once after
+    an untimed sweep, against K forward passes."""
+    import torch
+    from paper_1504_06847_amd import Solver
+    kw = dict(mu_eps=params.mu_eps, mu_s=params.mu_s, mu_nu=params.mu_nu, rho=params.rho_P)
+    s = Solver(inst.psf, inst.dirty, graph=True, **kw)
+    s.autotune(reps=3)
+    s.grad(K, sky=inst.sky, ckpt_every=ckpt_every)          # scratch allocation, warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, g = s.grad(K, sky=inst.sky, ckpt_every=ckpt_every)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(K)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    s.close()
+    return {"K": K, "ckpt_every": ckpt_every, "ms": round(t_grad * 1e3, 2), "forward_ms": round(t_fwd * 1e3, 2),
+            "ratio_to_forward": round(t_grad / t_fwd, 2), "loss": loss, "grad": [float(v) for v in g]}
+
+
 # algorithmic elements per voxel of one wavelet basis in a pass: X read,
 # the basis's coefficient cube read and written, B_rest read and written
 DICT_ELEMS_PER_BASIS = 5.0
@@ -254,7 +281,9 @@ def main(argv=None):
     ap.add_argument("--config", default="cube1024")
     ap.add_argument("--profile-iters", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=20)
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--grad-K", type=int, default=20,
+                    help="passes unrolled in the timed reverse sweep (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="launch each pass's kernels one by one instead of replaying a HIP graph")
@@ -305,6 +334,10 @@ def main(argv=None):
         ms64, prof64, sched64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5, graph=a.graph)
         fp64 = dict(value=V * a.fp64_steps / (ms64 / 1e3), ms_per_step=round(ms64 / a.fp64_steps, 4),
                     kernels_ms={k: round(v, 5) for k, v in prof64.items()}, schedule=list(sched64))
+    grad = None
+    if a.grad_K > 0:
+        _log(f"bench: reverse sweep of {a.grad_K} passes")
+        grad = run_grad(inst, cfg.params, a.grad_K)
     dictionary = None
     if a.dict_steps > 0:
         _log(f"bench: spatial dictionary, {a.dict_steps} timed passes")
@@ -345,6 +378,7 @@ def main(argv=None):
         "iteration_62B_frac": round(ITER_MIN5_ELEMS * 4 * value / 1e9 / HBM_PEAK_GBPS, 4),
         "kernels": kernels,
         "fp64": fp64,
+        "grad": grad,
         "dictionary": dictionary,
         "batched": batch,
         "cpu_baseline": cpu,
