@@ -14,16 +14,18 @@
 //   a[m] = sum_k h[k] x[(2m + k) mod n],  d[m] = sum_k g[k] x[(2m + k) mod n]
 // along x, then along y, coefficients in Mallat layout (LL top-left, then
 // x-high top-right, y-high bottom-left, both high bottom-right); each level
-// recurses on LL.  One launch per level and direction, all bands at once: a
-// work-group transforms one tile (16 rows x 32 columns of coefficients per
-// sub-band, so each row of a sub-band block is one 128-B line) staged with
-// its periodic halo in LDS.
-//   k_dwt_fwd: one analysis level; the detail coefficients (and at the last
-//     level the LL block) go straight into the z_b update; LL otherwise to a
-//     dense scratch image for the next level.
-//   k_dwt_inv: one synthesis level of u_b = 2 soft(z_b) - z_b (the LL input
-//     from the coarser level's scratch image, or from z_b at the last level);
-//     the finest level adds scale * W_b^T u_b into B_rest.
+// recurses on LL.  A work-group transforms one tile (16 rows x 32 columns of
+// coefficients per sub-band, so each row of a sub-band block is one 128-B
+// line) staged with its periodic halo in LDS.
+//   k_dwt_fwd_all: one analysis level of every basis and band in one launch;
+//     the detail coefficients (and at the last level the LL block) go
+//     straight into the z_b update, LL otherwise to the basis's dense
+//     scratch image for the next level.
+//   k_dwt_inv_all: one synthesis level above the finest of every basis, of
+//     u_b = 2 soft(z_b) - z_b (the LL input from the coarser level's scratch
+//     image, or from z_b at the last level).
+//   k_dwt_inv0: the finest synthesis level of one basis, added into B_rest;
+//     one launch per basis, so the sum over the bases has a fixed order.
 #include "muffin_device.hpp"
 #include "muffin_kernels.hpp"
 
