@@ -48,17 +48,22 @@ __device__ __forceinline__ void store_grad_partials(const double (&vals)[GRAD_NQ
 // pass (aP, aT, aS, aG, overwritten in place by those of the state before
 // it, this part of them) and, with has_ext, an outside cotangent of X in Xb.
 // Out: Xb = the total cotangent of X.
-template <typename T, int LT, bool DENSE>
-__global__ void __launch_bounds__(ADJ_NTH)
-k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int has_ext,
-               double* __restrict__ partials) {
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
-    const unsigned bb = A.band_bytes;
-    const int gs_ = A.gshift;
-    const BandArray<T> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_}, GS{A.GS, bb, gs_},
-        X{A.X, bb, gs_}, aP{A.aP, bb, gs_}, aT{A.aT, bb, gs_}, aS{A.aS, bb, gs_}, aG{A.aG, bb, gs_},
-        Xb{A.Xb, bb, gs_};
+// compiler fence between the stages of the kernel: memory accesses are not
+// moved (nor merged) across it, nor is other code scheduled across it
+__device__ __forceinline__ void stage_fence() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// the value is computed here: without it the compiler sinks the sums of a
+// stage (and so every band's operands, live) to where the sums are stored
+__device__ __forceinline__ void settle(double& x) { asm volatile("" : "+v"(x)); }
+
+template <typename T, int LT, bool DENSE, bool EXT, typename BA>
+__device__ __forceinline__ void adj_spectral_body(const BA& zP, const BA& zT, const BA& zV, const BA& GS,
+                                                  const BA& X, const BA& aP, const BA& aT, const BA& aS,
+                                                  const BA& aG, const BA& Xb, unsigned off, const T* __restrict__ D,
+                                                  int Lrt, const SpecArgs& a, double* __restrict__ partials) {
     const int L = DENSE ? Lrt : LT;
     const T rhoV = T(a.rho_V), rhoS = T(a.rho_S), tauT = T(a.tau_T), tauV = T(a.tau_V);
     const T inv_rhoV = T(1.0 / a.rho_V), inv_VS = T(1.0 / (a.rho_V + a.rho_S));
@@ -73,7 +78,7 @@ k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int ha
 #pragma unroll
     for (int l = 0; l < LT; ++l) v[l] = (l < L) ? zV.load(l, off) : T(0);
     dct_any<T, LT, DENSE, false>(v, D, L);
-    __builtin_amdgcn_sched_barrier(0);
+    stage_fence();
 #pragma unroll
     for (int k = 0; k < LT; ++k) {
         if (fabs(v[k]) > tauV) mc[k >> 5] |= 1u << (k & 31);
@@ -81,7 +86,7 @@ k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int ha
         v[k] = softt(v[k], tauV);
     }
     dct_any<T, LT, DENSE, true>(v, D, L);        // q
-    __builtin_amdgcn_sched_barrier(0);
+    stage_fence();
 
     double g_tT = 0.0, g_tV = 0.0, g_rV = 0.0, g_rS = 0.0;
     // steps VI and V backwards, band by band: v becomes the cotangent of q
@@ -98,25 +103,32 @@ k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int ha
             g_rS += double(sig * (x - s2) * inv_VS);
         }
     }
-    __builtin_amdgcn_sched_barrier(0);
+    settle(g_rV);
+    settle(g_rS);
+    // the cotangents read above are read again after the DCTs: the fences
+    // keep every band's reads beside their use, not live across the DCTs
+    stage_fence();
     // step IV backwards: V-bar = DCT(q-bar), c-bar = V-bar on the support of soft
     dct_any<T, LT, DENSE, false>(v, D, L);
 #pragma unroll
     for (int k = 0; k < LT; ++k) {
+        // selects, not branches: a branch here copies all of v at every k
         const bool m = (mc[k >> 5] >> (k & 31)) & 1u;
         const bool neg = (sc[k >> 5] >> (k & 31)) & 1u;
-        if (m) g_tV += double(neg ? v[k] : -v[k]);
-        else v[k] = T(0);
+        const T vk = m ? v[k] : T(0);
+        g_tV += double(neg ? vk : -vk);
+        v[k] = vk;
     }
+    settle(g_tV);
     dct_any<T, LT, DENSE, true>(v, D, L);         // u-bar = IDCT(c-bar)
-    __builtin_amdgcn_sched_barrier(0);
+    stage_fence();
     // the state cotangents before the pass, X-bar, and steps III, II backwards
 #pragma unroll
     for (int l = 0; l < LT; ++l) {
         if (l < L) {
             const T sb = aS.load(l, off), gb = aG.load(l, off), pb = aP.load(l, off), tb = aT.load(l, off);
             const T zp = zP.load(l, off), zt = zT.load(l, off), gs = GS.load(l, off);
-            const T ext = has_ext ? Xb.load(l, off) : T(0);
+            const T ext = EXT ? Xb.load(l, off) : T(0);
             const T sig = sb - rhoV * gb;
             const T ub = v[l];
             Xb.store(l, off, ext + pb + tb + sig * rhoS * inv_VS);
@@ -126,11 +138,27 @@ k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, int ha
             aP.store(l, off, zp < T(0) ? pb : T(0));
             const bool out = fabs(zt) > tauT;
             aT.store(l, off, out ? T(0) : tb);
-            if (out) g_tT += double(zt > T(0) ? tb : -tb);
+            const T tbo = out ? tb : T(0);
+            g_tT += double(zt > T(0) ? tbo : -tbo);
         }
     }
     const double vals[GRAD_NQ] = {g_tT, g_tV, 0.0, 0.0, g_rV, g_rS, 0.0, 0.0};
     store_grad_partials(vals, partials, blockIdx.x);
+}
+
+// EXT: an external cotangent of X is added (a separate instance, so that no
+// branch splits the band loop)
+template <typename T, int LT, bool DENSE, bool EXT>
+__global__ void __launch_bounds__(ADJ_NTH)
+k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, double* __restrict__ partials) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const unsigned bb = A.band_bytes;
+    const int gs_ = A.gshift;
+    const BandArray<T> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_}, GS{A.GS, bb, gs_},
+        X{A.X, bb, gs_}, aP{A.aP, bb, gs_}, aT{A.aT, bb, gs_}, aS{A.aS, bb, gs_}, aG{A.aG, bb, gs_},
+        Xb{A.Xb, bb, gs_};
+    adj_spectral_body<T, LT, DENSE, EXT>(zP, zT, zV, GS, X, aP, aT, aS, aG, Xb, off, D, Lrt, a, partials);
 }
 
 // Adjoint of the right-hand side of step I (eq. matB): Bb = Q^{-1} X-bar is
@@ -202,8 +230,12 @@ static hipError_t adj_t(const AdjArrays& A, const void* D, int L, long npix, con
     if (npix < 64 || (npix & (npix - 1)) != 0) return hipErrorInvalidValue;
     const unsigned g = (unsigned)(npix / nth);
     *nblocks = (int)g;
-    hipLaunchKernelGGL((k_adj_spectral<T, LT, DENSE>), dim3(g), dim3(nth), 0, s, A, (const T*)D, L, a,
-                       has_ext, partials);
+    if (has_ext)
+        hipLaunchKernelGGL((k_adj_spectral<T, LT, DENSE, true>), dim3(g), dim3(nth), 0, s, A, (const T*)D, L, a,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_adj_spectral<T, LT, DENSE, false>), dim3(g), dim3(nth), 0, s, A, (const T*)D, L, a,
+                           partials);
     return hipGetLastError();
 }
 
