@@ -1,9 +1,11 @@
 // Reverse sweep of K unrolled passes of Algorithm 1 (Section 3) on gfx950:
 // the adjoint of the reduced pass of muffin_spectral.hip, one launch per
-// pass for the band-coupled part (steps II-VI) and one elementwise launch
-// for the right-hand side of step I (eq. matB).  The step I solve itself is
-// symmetric (Q = H^T H + rho I, eq. Qlsimp), so its adjoint reuses the
-// column pass in filter mode.
+// pass for the band-coupled part (steps II-VI) and the adjoint of the
+// right-hand side of step I (eq. matB), either on its own or inside the
+// band-coupled launch of the pass before (in sweep order: the next launch),
+// which saves a read-modify-write of the four state cotangents.  The step I
+// solve itself is symmetric (Q = H^T H + rho I, eq. Qlsimp), so its adjoint
+// reuses the column pass in filter mode.
 //
 // Forward pass k, per pixel, from the state (z_P, z_T, S, Gamma_S):
 //   B   = H^T Y + rho_T (2 soft(z_T, tau_T) - z_T) + rho_P |z_P| + Gamma_S + rho_S S
@@ -32,6 +34,36 @@ template <typename T> __device__ __forceinline__ T sgnt(T z) {
     return z > T(0) ? T(1) : (z < T(0) ? T(-1) : T(0));
 }
 
+// Step-I part of the adjoint at one voxel: b = B-bar there (the cotangent of
+// the right-hand side, eq. matB), (zp, zt, zv, gs, x) the state before the
+// pass and the pass's X.  Adds b's terms to the state cotangents (pb, tb, sb,
+// gb) and to the parameter sums, -<b, X> for rho_Q included.  Products that
+// are added are explicit fma's: every kernel that inlines it rounds alike.
+struct Step1Sums {
+    double tT = 0.0, rP = 0.0, rT = 0.0, rS = 0.0, rQ = 0.0;
+};
+
+template <typename T> __device__ __forceinline__ void step1_sg(T b, T rhoS, T& sb, T& gb) {
+    sb = fma(rhoS, b, sb);
+    gb = gb + b;
+}
+
+template <typename T>
+__device__ __forceinline__ void step1_elem(T b, T zp, T zt, T zv, T gs, T x, const SpecArgs& a, T& pb, T& tb,
+                                           T& sb, T& gb, Step1Sums& h) {
+    const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoS = T(a.rho_S), tauT = T(a.tau_T);
+    const T inv_rhoV = T(1.0 / a.rho_V);
+    const bool out = fabs(zt) > tauT;
+    tb = fma(out ? rhoT : -rhoT, b, tb);
+    pb = fma(rhoP * sgnt(zp), b, pb);
+    step1_sg(b, rhoS, sb, gb);
+    h.tT += double(out ? (T(-2) * rhoT * sgnt(zt)) * b : T(0));
+    h.rT += double(b * fma(T(2), softt(zt, tauT), -zt));
+    h.rP += double(b * fabs(zp));
+    h.rS += double(b * fma(gs, inv_rhoV, zv));
+    h.rQ -= double(b * x);
+}
+
 // writes the GRAD_NQ block sums of vals (thread 0 of each block)
 __device__ __forceinline__ void store_grad_partials(const double (&vals)[GRAD_NQ], double* partials,
                                                     unsigned blk) {
@@ -43,11 +75,6 @@ __device__ __forceinline__ void store_grad_partials(const double (&vals)[GRAD_NQ
     }
 }
 
-// Adjoint of steps II-VI of pass k at one pixel.  In: the state before the
-// pass (zP, zT, zV, GS), the pass's X, the cotangents of the state after the
-// pass (aP, aT, aS, aG, overwritten in place by those of the state before
-// it, this part of them) and, with has_ext, an outside cotangent of X in Xb.
-// Out: Xb = the total cotangent of X.
 // compiler fence between the stages of the kernel: memory accesses are not
 // moved (nor merged) across it, nor is other code scheduled across it
 __device__ __forceinline__ void stage_fence() {
@@ -59,11 +86,28 @@ __device__ __forceinline__ void stage_fence() {
 // stage (and so every band's operands, live) to where the sums are stored
 __device__ __forceinline__ void settle(double& x) { asm volatile("" : "+v"(x)); }
 
-template <typename T, int LT, bool DENSE, bool EXT, typename BA>
+enum AdjMode { ADJ_PLAIN = 0, ADJ_EXT = 1, ADJ_STEP1 = 2 };
+
+// the value as if read from memory: the arithmetic that follows is not
+// combined with the arithmetic that made it, so the fused step-I adjoint
+// rounds as the separate launch does, whose results pass through memory
+template <typename T> __device__ __forceinline__ void opaque(T& x) { asm volatile("" : "+v"(x)); }
+
+// Adjoint of steps II-VI of pass k at one pixel.  In: the state before the
+// pass (zP, zT, zV, GS), the pass's X, the cotangents of the state after the
+// pass (aP, aT, aS, aG, overwritten in place by those of the state before
+// it, this part of them) and, with ADJ_EXT, an outside cotangent of X in Xb.
+// Out: Xb = the total cotangent of X.  With ADJ_STEP1 the step-I part of
+// pass k + 1 comes first (its B-bar bB, its state zP1.., its X1; parameter
+// sums to partials1): the cotangents read are the ones it leaves.
+template <typename T, int LT, bool DENSE, int MODE, typename BA>
 __device__ __forceinline__ void adj_spectral_body(const BA& zP, const BA& zT, const BA& zV, const BA& GS,
                                                   const BA& X, const BA& aP, const BA& aT, const BA& aS,
-                                                  const BA& aG, const BA& Xb, unsigned off, const T* __restrict__ D,
-                                                  int Lrt, const SpecArgs& a, double* __restrict__ partials) {
+                                                  const BA& aG, const BA& Xb, const BA& bB, const BA& zP1,
+                                                  const BA& zT1, const BA& zV1, const BA& GS1, const BA& X1,
+                                                  unsigned off, const T* __restrict__ D, int Lrt, const SpecArgs& a,
+                                                  double* __restrict__ partials, double* __restrict__ partials1) {
+    constexpr bool EXT = MODE == ADJ_EXT, S1 = MODE == ADJ_STEP1;
     const int L = DENSE ? Lrt : LT;
     const T rhoV = T(a.rho_V), rhoS = T(a.rho_S), tauT = T(a.tau_T), tauV = T(a.tau_V);
     const T inv_rhoV = T(1.0 / a.rho_V), inv_VS = T(1.0 / (a.rho_V + a.rho_S));
@@ -89,12 +133,19 @@ __device__ __forceinline__ void adj_spectral_body(const BA& zP, const BA& zT, co
     stage_fence();
 
     double g_tT = 0.0, g_tV = 0.0, g_rV = 0.0, g_rS = 0.0;
+    Step1Sums h1;
     // steps VI and V backwards, band by band: v becomes the cotangent of q
     // (the cotangent of S' in total is sig = aS - rho_V aG)
 #pragma unroll
     for (int l = 0; l < LT; ++l) {
         if (l < L) {
-            const T x = X.load(l, off), sb = aS.load(l, off), gb = aG.load(l, off);
+            const T x = X.load(l, off);
+            T sb = aS.load(l, off), gb = aG.load(l, off);
+            if constexpr (S1) {
+                step1_sg(bB.load(l, off), rhoS, sb, gb);
+                opaque(sb);
+                opaque(gb);
+            }
             const T q = v[l];
             const T s2 = (rhoV * q + rhoS * x) * inv_VS;
             const T sig = sb - rhoV * gb;
@@ -126,7 +177,15 @@ __device__ __forceinline__ void adj_spectral_body(const BA& zP, const BA& zT, co
 #pragma unroll
     for (int l = 0; l < LT; ++l) {
         if (l < L) {
-            const T sb = aS.load(l, off), gb = aG.load(l, off), pb = aP.load(l, off), tb = aT.load(l, off);
+            T sb = aS.load(l, off), gb = aG.load(l, off), pb = aP.load(l, off), tb = aT.load(l, off);
+            if constexpr (S1) {
+                step1_elem(bB.load(l, off), zP1.load(l, off), zT1.load(l, off), zV1.load(l, off), GS1.load(l, off),
+                           X1.load(l, off), a, pb, tb, sb, gb, h1);
+                opaque(pb);
+                opaque(tb);
+                opaque(sb);
+                opaque(gb);
+            }
             const T zp = zP.load(l, off), zt = zT.load(l, off), gs = GS.load(l, off);
             const T ext = EXT ? Xb.load(l, off) : T(0);
             const T sig = sb - rhoV * gb;
@@ -140,53 +199,93 @@ __device__ __forceinline__ void adj_spectral_body(const BA& zP, const BA& zT, co
             aT.store(l, off, out ? T(0) : tb);
             const T tbo = out ? tb : T(0);
             g_tT += double(zt > T(0) ? tbo : -tbo);
+            if constexpr (S1) {
+                // band by band: left to itself the scheduler defers the FP64
+                // sums of this loop to its end, every band's operands live
+                settle(g_tT);
+                settle(g_rV);
+                settle(h1.tT);
+                settle(h1.rP);
+                settle(h1.rT);
+                settle(h1.rS);
+                settle(h1.rQ);
+            }
         }
+    }
+    settle(g_tT);
+    settle(g_rV);
+    if constexpr (S1) {
+        settle(h1.tT);
+        settle(h1.rP);
+        settle(h1.rT);
+        settle(h1.rS);
+        settle(h1.rQ);
     }
     const double vals[GRAD_NQ] = {g_tT, g_tV, 0.0, 0.0, g_rV, g_rS, 0.0, 0.0};
     store_grad_partials(vals, partials, blockIdx.x);
+    if constexpr (S1) {
+        const double v1[GRAD_NQ] = {h1.tT, 0.0, h1.rP, h1.rT, 0.0, h1.rS, h1.rQ, 0.0};
+        store_grad_partials(v1, partials1, blockIdx.x);
+    }
 }
 
-// EXT: an external cotangent of X is added (a separate instance, so that no
-// branch splits the band loop)
-template <typename T, int LT, bool DENSE, bool EXT>
+// MODE (AdjMode) is a template argument, so that no branch splits the band
+// loops.  ONE: every array lies within 2^30 bytes of its base, one buffer
+// descriptor per array (BandArray1); else one per band group (BandArray),
+// whose run-time group shift makes them per array and band (scalar
+// registers, spilled in the fused mode, which is built with ONE only).
+template <typename T, int LT, bool DENSE, int MODE, bool ONE>
 __global__ void __launch_bounds__(ADJ_NTH)
-k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, double* __restrict__ partials) {
+k_adj_spectral(AdjArrays A, const T* __restrict__ D, int Lrt, SpecArgs a, double* __restrict__ partials,
+               double* __restrict__ partials1) {
+    static_assert(ONE || MODE != ADJ_STEP1, "the fused mode takes single-descriptor arrays");
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
-    const int gs_ = A.gshift;
-    const BandArray<T> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_}, GS{A.GS, bb, gs_},
-        X{A.X, bb, gs_}, aP{A.aP, bb, gs_}, aT{A.aT, bb, gs_}, aS{A.aS, bb, gs_}, aG{A.aG, bb, gs_},
-        Xb{A.Xb, bb, gs_};
-    adj_spectral_body<T, LT, DENSE, EXT>(zP, zT, zV, GS, X, aP, aT, aS, aG, Xb, off, D, Lrt, a, partials);
+    if constexpr (ONE) {
+        const BandArray1<T> zP(A.zP, bb), zT(A.zT, bb), zV(A.zV, bb), GS(A.GS, bb), X(A.X, bb), aP(A.aP, bb),
+            aT(A.aT, bb), aS(A.aS, bb), aG(A.aG, bb), Xb(A.Xb, bb);
+        if constexpr (MODE == ADJ_STEP1) {
+            const BandArray1<T> bB(A.Bb, bb), zP1(A.zP1, bb), zT1(A.zT1, bb), zV1(A.zV1, bb), GS1(A.GS1, bb),
+                X1(A.X1, bb);
+            adj_spectral_body<T, LT, DENSE, MODE>(zP, zT, zV, GS, X, aP, aT, aS, aG, Xb, bB, zP1, zT1, zV1, GS1,
+                                                  X1, off, D, Lrt, a, partials, partials1);
+        } else {
+            adj_spectral_body<T, LT, DENSE, MODE>(zP, zT, zV, GS, X, aP, aT, aS, aG, Xb, X, X, X, X, X, X, off, D,
+                                                  Lrt, a, partials, partials1);
+        }
+    } else {
+        const int gs_ = A.gshift;
+        const BandArray<T> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_}, GS{A.GS, bb, gs_},
+            X{A.X, bb, gs_}, aP{A.aP, bb, gs_}, aT{A.aT, bb, gs_}, aS{A.aS, bb, gs_}, aG{A.aG, bb, gs_},
+            Xb{A.Xb, bb, gs_};
+        adj_spectral_body<T, LT, DENSE, MODE>(zP, zT, zV, GS, X, aP, aT, aS, aG, Xb, X, X, X, X, X, X, off, D,
+                                              Lrt, a, partials, partials1);
+    }
 }
 
-// Adjoint of the right-hand side of step I (eq. matB): Bb = Q^{-1} X-bar is
-// the cotangent of B; adds its part to the state cotangents (in place) and
-// accumulates the parameter terms, -<Bb, X> for rho_Q included.
+// Adjoint of the right-hand side of step I (eq. matB) on its own: Bb =
+// Q^{-1} X-bar is the cotangent of B.  One thread per pixel over the bands,
+// as in k_adj_spectral, so that its parameter sums are those of the fused
+// form bit for bit.
 template <typename T>
 __global__ void __launch_bounds__(ADJ_NTH)
 k_adj_step1(const T* __restrict__ Bb, const T* __restrict__ zP, const T* __restrict__ zT,
             const T* __restrict__ zV, const T* __restrict__ GS, const T* __restrict__ X, T* __restrict__ aP,
-            T* __restrict__ aT, T* __restrict__ aS, T* __restrict__ aG, long n, SpecArgs a,
+            T* __restrict__ aT, T* __restrict__ aS, T* __restrict__ aG, long npix, int L, SpecArgs a,
             double* __restrict__ partials) {
-    const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoS = T(a.rho_S), tauT = T(a.tau_T);
-    const T inv_rhoV = T(1.0 / a.rho_V);
-    double g_tT = 0, g_rP = 0, g_rT = 0, g_rS = 0, g_rQ = 0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const T b = Bb[i], zp = zP[i], zt = zT[i];
-        const bool out = fabs(zt) > tauT;
-        aT[i] += b * rhoT * (out ? T(1) : T(-1));
-        aP[i] += b * rhoP * sgnt(zp);
-        aG[i] += b;
-        aS[i] += rhoS * b;
-        if (out) g_tT += double(-T(2) * rhoT * b * sgnt(zt));
-        g_rT += double(b * (T(2) * softt(zt, tauT) - zt));
-        g_rP += double(b * fabs(zp));
-        g_rS += double(b * (zV[i] + GS[i] * inv_rhoV));
-        g_rQ -= double(b * X[i]);
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    Step1Sums h;
+    for (int l = 0; l < L; ++l) {
+        const long i = (long)l * npix + p;
+        T pb = aP[i], tb = aT[i], sb = aS[i], gb = aG[i];
+        step1_elem(Bb[i], zP[i], zT[i], zV[i], GS[i], X[i], a, pb, tb, sb, gb, h);
+        aP[i] = pb;
+        aT[i] = tb;
+        aS[i] = sb;
+        aG[i] = gb;
     }
-    const double vals[GRAD_NQ] = {g_tT, 0.0, g_rP, g_rT, 0.0, g_rS, g_rQ, 0.0};
+    const double vals[GRAD_NQ] = {h.tT, 0.0, h.rP, h.rT, 0.0, h.rS, h.rQ, 0.0};
     store_grad_partials(vals, partials, blockIdx.x);
 }
 
@@ -223,62 +322,82 @@ static unsigned adj_grid(long n) {
     return (unsigned)b;
 }
 
+bool adj_single_descriptor(int L, unsigned band_bytes) {
+    return (unsigned long long)L * band_bytes <= (1ull << 30);
+}
+
+// one thread per pixel: npix a power of two, at least 64
+static bool pixel_grid(long npix, int* nth, unsigned* g) {
+    if (npix < 64 || (npix & (npix - 1)) != 0) return false;
+    *nth = npix < ADJ_NTH ? (int)npix : ADJ_NTH;
+    *g = (unsigned)(npix / *nth);
+    return true;
+}
+
 template <typename T, int LT, bool DENSE>
 static hipError_t adj_t(const AdjArrays& A, const void* D, int L, long npix, const SpecArgs& a,
-                        int has_ext, double* partials, int* nblocks, hipStream_t s) {
-    const int nth = npix < ADJ_NTH ? (int)npix : ADJ_NTH;
-    if (npix < 64 || (npix & (npix - 1)) != 0) return hipErrorInvalidValue;
-    const unsigned g = (unsigned)(npix / nth);
+                        int mode, double* partials, double* partials1, int* nblocks, hipStream_t s) {
+    int nth;
+    unsigned g;
+    if (!pixel_grid(npix, &nth, &g)) return hipErrorInvalidValue;
     *nblocks = (int)g;
-    if (has_ext)
-        hipLaunchKernelGGL((k_adj_spectral<T, LT, DENSE, true>), dim3(g), dim3(nth), 0, s, A, (const T*)D, L, a,
-                           partials);
-    else
-        hipLaunchKernelGGL((k_adj_spectral<T, LT, DENSE, false>), dim3(g), dim3(nth), 0, s, A, (const T*)D, L, a,
-                           partials);
+    const bool one = adj_single_descriptor(L, A.band_bytes);
+    if (mode == ADJ_STEP1 && !one) return hipErrorInvalidValue;
+#define MUFFIN_ADJ_LAUNCH(M, O)                                                                                 \
+    hipLaunchKernelGGL((k_adj_spectral<T, LT, DENSE, M, O>), dim3(g), dim3(nth), 0, s, A, (const T*)D, L, a,     \
+                       partials, partials1)
+    if (mode == ADJ_STEP1) MUFFIN_ADJ_LAUNCH(ADJ_STEP1, true);
+    else if (mode == ADJ_EXT && one) MUFFIN_ADJ_LAUNCH(ADJ_EXT, true);
+    else if (mode == ADJ_EXT) MUFFIN_ADJ_LAUNCH(ADJ_EXT, false);
+    else if (one) MUFFIN_ADJ_LAUNCH(ADJ_PLAIN, true);
+    else MUFFIN_ADJ_LAUNCH(ADJ_PLAIN, false);
+#undef MUFFIN_ADJ_LAUNCH
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t adj_dispatch(const AdjArrays& A, const void* D, int L, long npix, const SpecArgs& a,
-                               int has_ext, double* partials, int* nb, hipStream_t s) {
+                               int mode, double* partials, double* partials1, int* nb, hipStream_t s) {
     switch (L) {
-        case 1: return adj_t<T, 1, false>(A, D, L, npix, a, has_ext, partials, nb, s);
-        case 2: return adj_t<T, 2, false>(A, D, L, npix, a, has_ext, partials, nb, s);
-        case 4: return adj_t<T, 4, false>(A, D, L, npix, a, has_ext, partials, nb, s);
-        case 8: return adj_t<T, 8, false>(A, D, L, npix, a, has_ext, partials, nb, s);
-        case 16: return adj_t<T, 16, false>(A, D, L, npix, a, has_ext, partials, nb, s);
-        case 32: return adj_t<T, 32, false>(A, D, L, npix, a, has_ext, partials, nb, s);
-        case 64: return adj_t<T, 64, false>(A, D, L, npix, a, has_ext, partials, nb, s);
-        case 128: return adj_t<T, 128, false>(A, D, L, npix, a, has_ext, partials, nb, s);
+        case 1: return adj_t<T, 1, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+        case 2: return adj_t<T, 2, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+        case 4: return adj_t<T, 4, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+        case 8: return adj_t<T, 8, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+        case 16: return adj_t<T, 16, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+        case 32: return adj_t<T, 32, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+        case 64: return adj_t<T, 64, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+        case 128: return adj_t<T, 128, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
         default: break;
     }
     if (L < 1 || L > 32) return hipErrorInvalidValue;
-    if (L <= 8) return adj_t<T, 8, true>(A, D, L, npix, a, has_ext, partials, nb, s);
-    if (L <= 16) return adj_t<T, 16, true>(A, D, L, npix, a, has_ext, partials, nb, s);
-    return adj_t<T, 32, true>(A, D, L, npix, a, has_ext, partials, nb, s);
+    if (L <= 8) return adj_t<T, 8, true>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+    if (L <= 16) return adj_t<T, 16, true>(A, D, L, npix, a, mode, partials, partials1, nb, s);
+    return adj_t<T, 32, true>(A, D, L, npix, a, mode, partials, partials1, nb, s);
 }
 
 hipError_t launch_adj_spectral(int dtype, const AdjArrays& A, const void* D, int L, long npix,
-                               const SpecArgs& a, int has_ext, double* partials, int* nblocks,
+                               const SpecArgs& a, int mode, double* partials, double* partials1, int* nblocks,
                                hipStream_t s) {
-    return dtype == 0 ? adj_dispatch<float>(A, D, L, npix, a, has_ext, partials, nblocks, s)
-                      : adj_dispatch<double>(A, D, L, npix, a, has_ext, partials, nblocks, s);
+    if (mode < ADJ_PLAIN || mode > ADJ_STEP1 || (mode == ADJ_STEP1 && !partials1)) return hipErrorInvalidValue;
+    return dtype == 0 ? adj_dispatch<float>(A, D, L, npix, a, mode, partials, partials1, nblocks, s)
+                      : adj_dispatch<double>(A, D, L, npix, a, mode, partials, partials1, nblocks, s);
 }
 
 hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* zV,
-                            const void* GS, const void* X, void* aP, void* aT, void* aS, void* aG, size_t n,
+                            const void* GS, const void* X, void* aP, void* aT, void* aS, void* aG, long npix, int L,
                             const SpecArgs& a, double* partials, int* nblocks, hipStream_t s) {
-    const unsigned g = adj_grid((long)n);
+    int nth;
+    unsigned g;
+    if (!pixel_grid(npix, &nth, &g) || L < 1) return hipErrorInvalidValue;
     *nblocks = (int)g;
     if (dtype == 0)
-        hipLaunchKernelGGL((k_adj_step1<float>), dim3(g), dim3(ADJ_NTH), 0, s, (const float*)Bb,
-                           (const float*)zP, (const float*)zT, (const float*)zV, (const float*)GS,
-                           (const float*)X, (float*)aP, (float*)aT, (float*)aS, (float*)aG, (long)n, a, partials);
+        hipLaunchKernelGGL((k_adj_step1<float>), dim3(g), dim3(nth), 0, s, (const float*)Bb, (const float*)zP,
+                           (const float*)zT, (const float*)zV, (const float*)GS, (const float*)X, (float*)aP,
+                           (float*)aT, (float*)aS, (float*)aG, npix, L, a, partials);
     else
-        hipLaunchKernelGGL((k_adj_step1<double>), dim3(g), dim3(ADJ_NTH), 0, s, (const double*)Bb,
+        hipLaunchKernelGGL((k_adj_step1<double>), dim3(g), dim3(nth), 0, s, (const double*)Bb,
                            (const double*)zP, (const double*)zT, (const double*)zV, (const double*)GS,
-                           (const double*)X, (double*)aP, (double*)aT, (double*)aS, (double*)aG, (long)n, a,
+                           (const double*)X, (double*)aP, (double*)aT, (double*)aS, (double*)aG, npix, L, a,
                            partials);
     return hipGetLastError();
 }

@@ -295,11 +295,12 @@ size_t state_array_bytes(const muffin_ctx* c) {
 // from its checkpoint, storing the state before every pass and its X, and
 // its passes are reversed.  Scratch (device, owned by the context):
 //   ckpt : ceil(K / C) x 4 state arrays
-//   seg  : C x 5 arrays (state before the pass, X of the pass)
+//   seg  : 2 x C x 5 arrays (state before the pass, X of the pass), two
+//          stores used in turn by consecutive segments
 //   fin  : 5 arrays (the state after K passes, restored at the end)
 //   adj  : 4 state cotangents, X-bar, B-bar
 //   gyac : (with gy_out) the sum over the passes of B-bar
-//   partials, acc (FP64)
+//   partials, partials1 (FP64 block sums), acc
 // With gy_out, the cotangent of the dirty images goes there too: Y enters
 // every pass through H^T Y in step I's right-hand side (eq. matB), so
 // dL/dY = H sum_k B-bar_k.
@@ -311,9 +312,10 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     const size_t ab = state_array_bytes(c), nb = voxels(s) * elem_size(s);
     const long npix = long(s.ny) * s.nx;
     const size_t nparts = size_t(npix / 64 > 8192 ? npix / 64 : 8192);
-    const size_t n_arrays = size_t(nseg) * kNumState + size_t(C) * (kNumState + 1) + (kNumState + 1) +
+    const int nbuf = nseg > 1 ? 2 : 1;
+    const size_t n_arrays = size_t(nseg) * kNumState + size_t(nbuf) * C * (kNumState + 1) + (kNumState + 1) +
                             (kNumState + 2) + (gy_out ? 1 : 0);
-    const size_t need = n_arrays * ab + nparts * GRAD_NQ * 8 + kAlign;
+    const size_t need = n_arrays * ab + 2 * nparts * GRAD_NQ * 8 + kAlign;
     if (c->grad_bytes < need) {
         if (c->grad_buf) HIP_TRY(hipFree(c->grad_buf));
         c->grad_buf = nullptr;
@@ -324,12 +326,14 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     char* g = (char*)c->grad_buf;
     auto ckpt = [&](int seg, int i) { return g + (size_t(seg) * kNumState + i) * ab; };
     char* seg0 = g + size_t(nseg) * kNumState * ab;
-    auto segs = [&](int j, int i) { return seg0 + (size_t(j) * (kNumState + 1) + i) * ab; };   // i = 4: X
-    char* fin = seg0 + size_t(C) * (kNumState + 1) * ab;
+    // store b, pass j of the segment, array i (i = 4: X)
+    auto segs = [&](int b, int j, int i) { return seg0 + ((size_t(b) * C + j) * (kNumState + 1) + i) * ab; };
+    char* fin = seg0 + size_t(nbuf) * C * (kNumState + 1) * ab;
     char* adj = fin + (kNumState + 1) * ab;                  // aP, aT, aS, aG, Xb, Bb
     char* gyac = adj + (kNumState + 2) * ab;
     double* partials = (double*)(gyac + (gy_out ? ab : 0));
-    double* acc = partials + nparts * GRAD_NQ;
+    double* partials1 = partials + nparts * GRAD_NQ;      // step-I sums of a fused launch
+    double* acc = partials1 + nparts * GRAD_NQ;
     const int dt = s.dtype, nrows = s.L * s.ny;
     const SpecArgs a = spec_args(c->params);
     hipStream_t st_ = c->stream;
@@ -363,24 +367,33 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
 
     const unsigned bb = unsigned(npix * long(elem_size(s)));
     const int gsh = spectral_gshift(bb);
+    const bool fuse_ok = adj_single_descriptor(s.L, bb);
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * C, k1 = (k0 + C < K) ? k0 + C : K;
+        const int b = seg & (nbuf - 1);
         for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), ckpt(seg, i)));
         if ((rc = recompute_brest(c)) != MUFFIN_OK) return rc;
         for (int k = k0 + 1; k <= k1; ++k) {
             const int j = k - k0 - 1;
-            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(j, i), st(c, i)));
+            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(b, j, i), st(c, i)));
             if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
-            HIP_TRY(copy(segs(j, kNumState), P(c, c->lay.x)));
+            HIP_TRY(copy(segs(b, j, kNumState), P(c, c->lay.x)));
         }
+        // pass k's step-I adjoint runs inside the band-coupled launch of pass
+        // k - 1 (its operands stay in the segment store: the first pass of a
+        // segment is in the other store while the segment before it is
+        // processed); pass 1's runs on its own.  The same launches for any
+        // checkpoint spacing, and the parameter sums added in one order:
+        // steps II-VI of k, step I of k, steps II-VI of k - 1, ...
         for (int k = k1; k > k0; --k) {
             const int j = k - k0 - 1;
+            const bool fused = k < K && fuse_ok;       // step I of pass k + 1 is pending
             AdjArrays A;
-            A.zP = segs(j, ST_ZP);
-            A.zT = segs(j, ST_ZT);
-            A.zV = segs(j, ST_ZV);
-            A.GS = segs(j, ST_GS);
-            A.X = segs(j, kNumState);
+            A.zP = segs(b, j, ST_ZP);
+            A.zT = segs(b, j, ST_ZT);
+            A.zV = segs(b, j, ST_ZV);
+            A.GS = segs(b, j, ST_GS);
+            A.X = segs(b, j, kNumState);
             A.aP = adj;
             A.aT = adj + ab;
             A.aS = adj + 2 * ab;
@@ -388,9 +401,21 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             A.Xb = Xb;
             A.band_bytes = bb;
             A.gshift = gsh;
+            if (fused) {
+                // pass k + 1: the next slot of this store, or the first of the other
+                const int b1 = k < k1 ? b : b ^ 1, j1 = k < k1 ? j + 1 : 0;
+                A.Bb = Bb;
+                A.zP1 = segs(b1, j1, ST_ZP);
+                A.zT1 = segs(b1, j1, ST_ZT);
+                A.zV1 = segs(b1, j1, ST_ZV);
+                A.GS1 = segs(b1, j1, ST_GS);
+                A.X1 = segs(b1, j1, kNumState);
+            }
             int nbk = 0;
-            HIP_TRY(launch_adj_spectral(dt, A, P(c, c->lay.dctm), s.L, npix, a, k == K ? 1 : 0, partials,
-                                        &nbk, st_));
+            const int mode = fused ? 2 : (k == K ? 1 : 0);
+            HIP_TRY(launch_adj_spectral(dt, A, P(c, c->lay.dctm), s.L, npix, a, mode, partials, partials1, &nbk,
+                                        st_));
+            if (fused) HIP_TRY(launch_grad_accum(partials1, nbk, acc, st_));
             HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
             // B-bar = Q^{-1} X-bar (Q is symmetric)
             HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, Xb, P(c, c->lay.z), nrows, s.nx, s.ny, false, false,
@@ -401,9 +426,11 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), Bb, nrows, s.nx, P(c, c->lay.tw), c->twlog, st_,
                                    c->row_v));
             if (gy_out) HIP_TRY(launch_add(dt, gyac, Bb, voxels(s), st_));
-            HIP_TRY(launch_adj_step1(dt, Bb, A.zP, A.zT, A.zV, A.GS, A.X, A.aP, A.aT, A.aS, A.aG, voxels(s), a,
-                                     partials, &nbk, st_));
-            HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
+            if (k == 1 || !fuse_ok) {
+                HIP_TRY(launch_adj_step1(dt, Bb, A.zP, A.zT, A.zV, A.GS, A.X, A.aP, A.aT, A.aS, A.aG, npix, s.L, a,
+                                         partials, &nbk, st_));
+                HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
+            }
         }
     }
     // leave the context at the state after K passes

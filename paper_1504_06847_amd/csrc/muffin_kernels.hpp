@@ -139,19 +139,26 @@ enum GradSlot {
 
 // [L][npix] arrays of the adjoint of one pass: the state before the pass
 // (z_P, z_T, z_V, Gamma_S), the pass's X, the state cotangents (in place;
-// those of z_P, z_T, S and Gamma_S) and the cotangent of X
+// those of z_P, z_T, S and Gamma_S) and the cotangent of X; for the fused
+// step-I adjoint of the pass after, its B-bar, state and X
 struct AdjArrays {
     char *zP, *zT, *zV, *GS, *X;
     char *aP, *aT, *aS, *aG, *Xb;
+    char *Bb = nullptr, *zP1 = nullptr, *zT1 = nullptr, *zV1 = nullptr, *GS1 = nullptr, *X1 = nullptr;
     unsigned band_bytes;
     int gshift;
 };
 
+// mode: 0 plain, 1 with an outside cotangent of X in Xb, 2 with the step-I
+// adjoint of the pass after first (its parameter sums to partials1; only
+// where adj_single_descriptor holds: every band array within 2^30 bytes).
+// Both kernels run one thread per pixel (npix a power of two, at least 64).
+bool adj_single_descriptor(int L, unsigned band_bytes);
 hipError_t launch_adj_spectral(int dtype, const AdjArrays& A, const void* D, int L, long npix,
-                               const SpecArgs& a, int has_ext, double* partials, int* nblocks,
+                               const SpecArgs& a, int mode, double* partials, double* partials1, int* nblocks,
                                hipStream_t s);
 hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* zV,
-                            const void* GS, const void* X, void* aP, void* aT, void* aS, void* aG, size_t n,
+                            const void* GS, const void* X, void* aP, void* aT, void* aS, void* aG, long npix, int L,
                             const SpecArgs& a, double* partials, int* nblocks, hipStream_t s);
 hipError_t launch_mse_seed(int dtype, const void* X, const void* sky, void* Xb, size_t n,
                            double* partials, int* nblocks, hipStream_t s);
