@@ -84,6 +84,31 @@ def test_vjp_matches_oracle_jvp(gpu_lib):
         assert abs(g[i] - ref) <= 1e-8 * max(abs(ref), np.abs(g).max())
 
 
+@pytest.mark.parametrize("L", [6, 15])
+def test_vjp_at_band_counts_off_the_power_of_two_path(gpu_lib, L):
+    """L = 6 and 15 take the dense band transform; K = 8 with checkpoints
+    every 3 puts the step-I adjoint of a segment's first pass into the next
+    segment's first launch.  <gx, J e_i> as in the test above."""
+    from synth import make_instance
+    from paper_1504_06847_amd import Solver
+    inst = make_instance(32, 32, L, n_points=4, n_gauss=2, n_ant=16, noise_sigma=0.01, seed=40 + L)
+    p = get_config("grad64").params
+    kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho=p.rho_P)
+    gx = np.random.default_rng(11).standard_normal(inst.dirty.shape)
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw)
+    _, g = s.grad(8, gx=gx, ckpt_every=3)
+    _, g1 = s.grad(8, gx=gx, ckpt_every=8)
+    assert np.array_equal(g, g1)
+    prob = O.Problem(inst.psf, inst.dirty, p)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        _, dX = O.jvp_run(prob, 8, e)
+        ref = float(np.sum(gx * dX))
+        _say("vjp L", L, i, g[i], ref)
+        assert abs(g[i] - ref) <= 1e-8 * max(abs(ref), np.abs(g).max())
+
+
 def test_per_parameter_gradient_matches_oracle_jvp(gpu_lib):
     """muffin_grad_params: (J^T gx) along each of mu_eps, mu_s, mu_nu and the
     four rho's equals <gx, J e_i> from the oracle's tangents; the four rho
