@@ -294,7 +294,8 @@ size_t state_array_bytes(const muffin_ctx* c) {
 // sweep stores the checkpoints, then each segment (last first) is run again
 // from its checkpoint, storing the state before every pass and its X, and
 // its passes are reversed.  Scratch (device, owned by the context):
-//   ckpt : ceil(K / C) x 4 state arrays
+//   ckpt : ceil(K / C) x 4 state arrays (the last one unused: that segment
+//          is stored on the way forward)
 //   seg  : 2 x C x 5 arrays (state before the pass, X of the pass), two
 //          stores used in turn by consecutive segments
 //   fin  : 5 arrays (the state after K passes, restored at the end)
@@ -341,13 +342,20 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     auto copy = [&](void* dst, const void* src) {
         return hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToDevice, st_);
     };
-    // forward sweep with checkpoints
+    // forward sweep with checkpoints; the last segment goes straight into its
+    // segment store (the reverse sweep starts there, no recompute)
+    const int blast = (nseg - 1) & (nbuf - 1);
     int rc = zero_state(c);
     if (rc) return rc;
     for (int k = 1; k <= K; ++k) {
-        if ((k - 1) % C == 0)
-            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(ckpt((k - 1) / C, i), st(c, i)));
+        const int seg = (k - 1) / C, j = (k - 1) % C;
+        const bool last = seg == nseg - 1;
+        if (j == 0 && !last)
+            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(ckpt(seg, i), st(c, i)));
+        if (last)
+            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(blast, j, i), st(c, i)));
         if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
+        if (last) HIP_TRY(copy(segs(blast, j, kNumState), P(c, c->lay.x)));
     }
     for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(fin + i * ab, st(c, i)));
     HIP_TRY(copy(fin + kNumState * ab, P(c, c->lay.x)));
@@ -371,13 +379,15 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * C, k1 = (k0 + C < K) ? k0 + C : K;
         const int b = seg & (nbuf - 1);
-        for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), ckpt(seg, i)));
-        if ((rc = recompute_brest(c)) != MUFFIN_OK) return rc;
-        for (int k = k0 + 1; k <= k1; ++k) {
-            const int j = k - k0 - 1;
-            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(b, j, i), st(c, i)));
-            if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
-            HIP_TRY(copy(segs(b, j, kNumState), P(c, c->lay.x)));
+        if (seg < nseg - 1) {
+            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), ckpt(seg, i)));
+            if ((rc = recompute_brest(c)) != MUFFIN_OK) return rc;
+            for (int k = k0 + 1; k <= k1; ++k) {
+                const int j = k - k0 - 1;
+                for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(b, j, i), st(c, i)));
+                if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
+                HIP_TRY(copy(segs(b, j, kNumState), P(c, c->lay.x)));
+            }
         }
         // pass k's step-I adjoint runs inside the band-coupled launch of pass
         // k - 1 (its operands stay in the segment store: the first pass of a
