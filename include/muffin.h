@@ -190,7 +190,7 @@ int muffin_get_p(muffin_ctx* ctx, void* p_out);
    context's state afterwards equals the state after K passes from zero.
    Allocates its own device scratch, kept for the next call and freed by
    muffin_destroy: 4 ceil(K / C) + 10 C + 11 cubes for C = ckpt_every < K
-   (4 + 5 C + 11 for C >= K), one more with muffin_grad_dirty.
+   (4 + 5 K + 11 for C >= K), one more with muffin_grad_dirty.
    Errors: EINVAL, EDEVICE. */
 int muffin_grad(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
                 double* loss, double grad[3]);
