@@ -294,10 +294,11 @@ size_t state_array_bytes(const muffin_ctx* c) {
 // sweep stores the checkpoints, then each segment (last first) is run again
 // from its checkpoint, storing the state before every pass and its X, and
 // its passes are reversed.  Scratch (device, owned by the context):
-//   ckpt : ceil(K / C) x 4 state arrays (the last one unused: that segment
-//          is stored on the way forward)
-//   seg  : 2 x C x 5 arrays (state before the pass, X of the pass), two
-//          stores used in turn by consecutive segments
+//   ckpt : ceil(K / C) x 4 state arrays (the state before each segment's
+//          first pass, for the recompute and for that pass's adjoint)
+//   seg  : 2 x C x 5 arrays (state before the pass, X of the pass; the
+//          state slots of pass 0 unused), two stores used in turn by
+//          consecutive segments
 //   fin  : 5 arrays (the state after K passes, restored at the end)
 //   adj  : 4 state cotangents, X-bar, B-bar
 //   gyac : (with gy_out) the sum over the passes of B-bar
@@ -329,6 +330,9 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     char* seg0 = g + size_t(nseg) * kNumState * ab;
     // store b, pass j of the segment, array i (i = 4: X)
     auto segs = [&](int b, int j, int i) { return seg0 + ((size_t(b) * C + j) * (kNumState + 1) + i) * ab; };
+    // the state before pass j of segment sg in store b: its checkpoint for
+    // j = 0 (never overwritten, so not copied into the store)
+    auto stv = [&](int b, int sg, int j, int i) { return j == 0 ? ckpt(sg, i) : segs(b, j, i); };
     char* fin = seg0 + size_t(nbuf) * C * (kNumState + 1) * ab;
     char* adj = fin + (kNumState + 1) * ab;                  // aP, aT, aS, aG, Xb, Bb
     char* gyac = adj + (kNumState + 2) * ab;
@@ -350,9 +354,9 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     for (int k = 1; k <= K; ++k) {
         const int seg = (k - 1) / C, j = (k - 1) % C;
         const bool last = seg == nseg - 1;
-        if (j == 0 && !last)
+        if (j == 0)
             for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(ckpt(seg, i), st(c, i)));
-        if (last)
+        else if (last)
             for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(blast, j, i), st(c, i)));
         if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
         if (last) HIP_TRY(copy(segs(blast, j, kNumState), P(c, c->lay.x)));
@@ -384,7 +388,8 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             if ((rc = recompute_brest(c)) != MUFFIN_OK) return rc;
             for (int k = k0 + 1; k <= k1; ++k) {
                 const int j = k - k0 - 1;
-                for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(b, j, i), st(c, i)));
+                if (j > 0)
+                    for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(b, j, i), st(c, i)));
                 if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
                 HIP_TRY(copy(segs(b, j, kNumState), P(c, c->lay.x)));
             }
@@ -399,10 +404,10 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             const int j = k - k0 - 1;
             const bool fused = k < K && fuse_ok;       // step I of pass k + 1 is pending
             AdjArrays A;
-            A.zP = segs(b, j, ST_ZP);
-            A.zT = segs(b, j, ST_ZT);
-            A.zV = segs(b, j, ST_ZV);
-            A.GS = segs(b, j, ST_GS);
+            A.zP = stv(b, seg, j, ST_ZP);
+            A.zT = stv(b, seg, j, ST_ZT);
+            A.zV = stv(b, seg, j, ST_ZV);
+            A.GS = stv(b, seg, j, ST_GS);
             A.X = segs(b, j, kNumState);
             A.aP = adj;
             A.aT = adj + ab;
@@ -413,12 +418,12 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             A.gshift = gsh;
             if (fused) {
                 // pass k + 1: the next slot of this store, or the first of the other
-                const int b1 = k < k1 ? b : b ^ 1, j1 = k < k1 ? j + 1 : 0;
+                const int b1 = k < k1 ? b : b ^ 1, s1 = k < k1 ? seg : seg + 1, j1 = k < k1 ? j + 1 : 0;
                 A.Bb = Bb;
-                A.zP1 = segs(b1, j1, ST_ZP);
-                A.zT1 = segs(b1, j1, ST_ZT);
-                A.zV1 = segs(b1, j1, ST_ZV);
-                A.GS1 = segs(b1, j1, ST_GS);
+                A.zP1 = stv(b1, s1, j1, ST_ZP);
+                A.zT1 = stv(b1, s1, j1, ST_ZT);
+                A.zV1 = stv(b1, s1, j1, ST_ZV);
+                A.GS1 = stv(b1, s1, j1, ST_GS);
                 A.X1 = segs(b1, j1, kNumState);
             }
             int nbk = 0;
