@@ -158,6 +158,14 @@ def run_grad(inst, params, K, ckpt_every=5):
     loss, g = s.grad(K, sky=inst.sky, ckpt_every=ckpt_every)
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0
+    # every pass stored on the way forward (checkpoint spacing K): no
+    # recompute, K x 5 cubes of segment store (HBM holds them at this size)
+    s.grad(K, sky=inst.sky, ckpt_every=K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.grad(K, sky=inst.sky, ckpt_every=K)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
     s.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -165,8 +173,12 @@ def run_grad(inst, params, K, ckpt_every=5):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     s.close()
+    cube_gib = inst.dirty.size * 4 / 2**30
     return {"K": K, "ckpt_every": ckpt_every, "ms": round(t_grad * 1e3, 2), "forward_ms": round(t_fwd * 1e3, 2),
-            "ratio_to_forward": round(t_grad / t_fwd, 2), "loss": loss, "grad": [float(v) for v in g]}
+            "ratio_to_forward": round(t_grad / t_fwd, 2), "loss": loss, "grad": [float(v) for v in g],
+            "all_stored": {"ckpt_every": K, "ms": round(t_all * 1e3, 2),
+                           "ratio_to_forward": round(t_all / t_fwd, 2),
+                           "scratch_GiB": round((4 + 5 * K + 11) * cube_gib, 2)}}
 
 
 # algorithmic elements per voxel of one wavelet basis in a pass: X read,
