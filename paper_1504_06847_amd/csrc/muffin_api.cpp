@@ -361,8 +361,12 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
         if (last) HIP_TRY(copy(segs(blast, j, kNumState), P(c, c->lay.x)));
     }
-    for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(fin + i * ab, st(c, i)));
-    HIP_TRY(copy(fin + kNumState * ab, P(c, c->lay.x)));
+    // the state after K passes, kept aside while segments are recomputed
+    // (with one segment nothing is recomputed and the context keeps it)
+    if (nseg > 1) {
+        for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(fin + i * ab, st(c, i)));
+        HIP_TRY(copy(fin + kNumState * ab, P(c, c->lay.x)));
+    }
     // seed: the cotangent of X^K
     char* Xb = adj + kNumState * ab;
     char* Bb = adj + (kNumState + 1) * ab;
@@ -449,8 +453,10 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         }
     }
     // leave the context at the state after K passes
-    for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), fin + i * ab));
-    HIP_TRY(copy(P(c, c->lay.x), fin + kNumState * ab));
+    if (nseg > 1) {
+        for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), fin + i * ab));
+        HIP_TRY(copy(P(c, c->lay.x), fin + kNumState * ab));
+    }
     if (gy_out) {
         // dL/dY = H (sum of B-bar): the transfer function applied in the
         // Fourier domain (Z is scratch here; B_rest is rebuilt below)

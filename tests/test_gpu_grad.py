@@ -159,13 +159,16 @@ def test_dirty_image_gradient_matches_oracle_jvp(gpu_lib, dtype, bar):
     assert torch.equal(s.x, ref.x)
 
 
-def test_context_holds_the_K_pass_state_afterwards(gpu_lib):
+@pytest.mark.parametrize("ckpt_every", [4, 9, 20])
+def test_context_holds_the_K_pass_state_afterwards(gpu_lib, ckpt_every):
+    """Checkpoints every 4: the state after K passes is set aside and put
+    back; every 9 or 20 (one segment): the context keeps it throughout."""
     from paper_1504_06847_amd import Solver
     inst, p, kw = _grad64()
     a = Solver(inst.psf, inst.dirty, **kw)
     b = Solver(inst.psf, inst.dirty, **kw)
     a.iterate(3)
-    a.grad(9, sky=inst.sky, ckpt_every=4)
+    a.grad(9, sky=inst.sky, ckpt_every=ckpt_every)
     b.iterate(9)
     torch.cuda.synchronize()
     assert a.iterations == 9
