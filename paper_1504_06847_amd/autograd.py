@@ -13,17 +13,19 @@ class MuffinUnroll(torch.autograd.Function):
 
     mu_s, mu_nu, rho: 0-d tensors (or floats); rho is the common value of
     rho_P = rho_T = rho_V = rho_S.  x_K has the dtype of psf (float32 or
-    float64) and lives on its device.  Gradients flow to mu_s, mu_nu and
+    float64) and lives on its device.  ckpt_every: the reverse sweep's
+    checkpoint spacing (default: Solver.sweep_ckpt_every).  Gradients flow to mu_s, mu_nu and
     rho; psf and dirty get none."""
 
     @staticmethod
-    def forward(ctx, psf, dirty, mu_s, mu_nu, rho, K, ckpt_every=5, mu_eps=1e-3):
+    def forward(ctx, psf, dirty, mu_s, mu_nu, rho, K, ckpt_every=None, mu_eps=1e-3):
         dtype = psf.dtype if psf.dtype in (torch.float32, torch.float64) else torch.float32
         dev = psf.device if psf.device.type == "cuda" else torch.device("cuda")
         s = Solver(psf.detach(), dirty.detach(), dtype=dtype, device=dev, mu_eps=float(mu_eps),
                    mu_s=float(mu_s), mu_nu=float(mu_nu), rho=float(rho))
         s.iterate(int(K))
-        ctx.solver, ctx.K, ctx.ckpt = s, int(K), int(ckpt_every)
+        ctx.solver, ctx.K = s, int(K)
+        ctx.ckpt = None if ckpt_every is None else int(ckpt_every)
         ctx.kinds = tuple(torch.is_tensor(v) for v in (mu_s, mu_nu, rho))
         return s.x
 

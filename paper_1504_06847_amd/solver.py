@@ -249,14 +249,37 @@ class Solver:
         L.check(self._lib.muffin_reset(self._ctx), "muffin_reset", self._lib)
 
     # -------------------------------------------------------------- gradients
-    def grad(self, K: int, *, sky=None, gx=None, ckpt_every: int = 5):
+    def sweep_ckpt_every(self, K: int, extra_cubes: int = 0, fraction: float = 0.5) -> int:
+        """Checkpoint spacing for a reverse sweep of K passes: the largest
+        whose scratch (4 ceil(K/C) + 10 C + 11 cubes, 4 + 5 K + 11 for C >= K,
+        plus ``extra_cubes``) fits in ``fraction`` of the device's free
+        memory.  The larger the spacing the fewer passes are recomputed;
+        C = K recomputes none."""
+        K = max(1, int(K))
+        free, _ = torch.cuda.mem_get_info(self.device)
+        cube = 1
+        for n in self.shape:
+            cube *= int(n)
+        cube *= torch.empty((), dtype=self.dtype).element_size()
+        budget = fraction * free
+        for C in range(K, 0, -1):
+            nseg = -(-K // C)
+            cubes = 4 * nseg + (2 if nseg > 1 else 1) * C * 5 + 11 + extra_cubes
+            if cubes * cube <= budget:
+                return C
+        return 1
+
+    def grad(self, K: int, *, sky=None, gx=None, ckpt_every: int | None = None):
         """Gradient with respect to (mu_s, mu_nu, rho) of a loss of X^K, the X
         iterate after K passes from the zero state (rho: the common value of
         the four rho's, derivative along (1, 1, 1, 1)).  Give ``sky`` for
         loss = ||X^K - sky||^2, or ``gx`` = dloss/dX^K.  Returns (loss, grad)
         with grad a length-3 numpy array (loss is 0.0 with gx).  Afterwards
-        the solver holds the state after K passes."""
+        the solver holds the state after K passes.  ckpt_every: the
+        checkpoint spacing, by default ``sweep_ckpt_every(K)``."""
         import numpy as np
+        if ckpt_every is None:
+            ckpt_every = self.sweep_ckpt_every(K)
         if (sky is None) == (gx is None):
             raise ValueError("give exactly one of sky and gx")
         ref = _as_cube(sky if sky is not None else gx, self.dtype, self.device)
@@ -273,9 +296,11 @@ class Solver:
 
     GRAD_PARAMS = ("mu_eps", "mu_s", "mu_nu", "rho_P", "rho_T", "rho_V", "rho_S")
 
-    def grad_params(self, K: int, *, sky=None, gx=None, ckpt_every: int = 5):
+    def grad_params(self, K: int, *, sky=None, gx=None, ckpt_every: int | None = None):
         """As ``grad``, with the derivative along each parameter on its own:
         returns (loss, {name: d loss / d name}) for GRAD_PARAMS."""
+        if ckpt_every is None:
+            ckpt_every = self.sweep_ckpt_every(K)
         if (sky is None) == (gx is None):
             raise ValueError("give exactly one of sky and gx")
         ref = _as_cube(sky if sky is not None else gx, self.dtype, self.device)
@@ -290,9 +315,11 @@ class Solver:
         L.check(rc, "muffin_grad_params", self._lib)
         return loss.value, {n: g[i] for i, n in enumerate(self.GRAD_PARAMS)}
 
-    def grad_dirty(self, K: int, *, sky=None, gx=None, ckpt_every: int = 5):
+    def grad_dirty(self, K: int, *, sky=None, gx=None, ckpt_every: int | None = None):
         """Cotangent of the dirty images: returns (loss, dL/dY) with dL/dY a
         cube on the device (muffin_grad_dirty)."""
+        if ckpt_every is None:
+            ckpt_every = self.sweep_ckpt_every(K, extra_cubes=2)
         if (sky is None) == (gx is None):
             raise ValueError("give exactly one of sky and gx")
         ref = _as_cube(sky if sky is not None else gx, self.dtype, self.device)

@@ -65,6 +65,25 @@ def test_checkpoint_spacing_does_not_change_the_gradient(gpu_lib):
         assert r[0] == ref[0] and np.array_equal(r[1], ref[1]), C
 
 
+def test_default_checkpoint_spacing_from_free_memory(gpu_lib):
+    """The default spacing is the largest whose scratch fits the given share
+    of free device memory: K for a small cube, smaller for a tiny share, and
+    the gradient at the default equals the one at that spacing."""
+    from paper_1504_06847_amd import Solver
+    inst, p, kw = _grad64()
+    s = Solver(inst.psf, inst.dirty, **kw)
+    assert s.sweep_ckpt_every(20) == 20
+    free, _ = torch.cuda.mem_get_info()
+    cube = 64 * 64 * 8 * 4
+    # room for 80 cubes: spacing 5 needs 4 x 4 + 10 x 5 + 11 = 77, every
+    # larger one more (6: 87, ..., 20: 4 + 100 + 11)
+    assert s.sweep_ckpt_every(20, fraction=80 * cube / free) == 5
+    assert s.sweep_ckpt_every(20, fraction=10 * cube / free) == 1      # nothing fits
+    r0 = s.grad(20, sky=inst.sky)
+    r1 = s.grad(20, sky=inst.sky, ckpt_every=20)
+    assert r0[0] == r1[0] and np.array_equal(r0[1], r1[1])
+
+
 def test_vjp_matches_oracle_jvp(gpu_lib):
     """<gx, J e_i> from the oracle's tangents equals the GPU's (J^T gx)_i."""
     from paper_1504_06847_amd import Solver
