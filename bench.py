@@ -220,22 +220,6 @@ def run_dictionary(inst, params, steps, warmup, profile_iters, graph=True):
     return out
 
 
-def batch_instances():
-    """The uneven batch: 16 cubes, N^2 in {128^2, 256^2, 512^2} x L in {16, 32,
-    64, 128} (shapes drawn with seed 3), each drawn with the 256^2 x 32
-    generator settings (40 points, 10 Gaussians, 40 antennas, sigma 0.005),
-    seed 300 + i."""
-    from synth import get_config, make_instance
-    from synth.configs import batched_shapes
-    c = get_config("fp32_256")
-    out = []
-    for i, (ny, nx, L) in enumerate(batched_shapes()):
-        inst = make_instance(ny, nx, L, n_points=c.n_points, n_gauss=c.n_gauss, n_ant=c.n_ant,
-                             noise_sigma=c.noise_sigma, seed=300 + i)
-        out.append((inst.psf, inst.dirty))
-    return out, c.params
-
-
 def run_batch(steps, warmup):
     """voxel-iterations/s of the batch: each cube iterated on its own (one
     cube after another, the plain per-cube launches), then grouped launches,
@@ -243,6 +227,7 @@ def run_batch(steps, warmup):
     schedule autotuner."""
     import torch
     from paper_1504_06847_amd import Batch, Solver
+    from synth.configs import batch_instances
     cubes, p = batch_instances()
     kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho_P=p.rho_P, rho_T=p.rho_T,
               rho_V=p.rho_V, rho_S=p.rho_S)

@@ -35,6 +35,14 @@ What it computes, and where the paper defines it
 
 Layout: every cube is a float64 array [L][ny][nx]; the paper's matrix X
 (pixels x bands) is its transpose-reshape, so "X W_nu" is a DCT along axis 0.
+
+Precision: float64 by default.  ``Problem(..., dtype=np.longdouble)`` runs
+the same steps in the host's extended precision (64-bit significand,
+eps = 1.1e-19; scipy.fft transforms long doubles natively).  Step I divides
+by |h_hat|^2 + rho, so rounding in the right-hand side reaches X amplified
+by up to max |h_hat|^2 / rho (about 1e6 on the 1024^2 workloads): there the
+float64 oracle's own error is of the order of a float64 GPU pass's, and the
+extended-precision run is the reference that the FP64 GPU path is held to.
 """
 from __future__ import annotations
 
@@ -111,13 +119,14 @@ class Params:
 
 
 class Problem:
-    """One cube: PSFs, dirty images and parameters, all in float64.
-    ``bases``: the spatial dictionary W_s (codes of ``oracle/wavelets.py``;
-    the Dirac basis alone by default)."""
+    """One cube: PSFs, dirty images and parameters, in float64 (or in the
+    floating type ``dtype``: np.longdouble for the extended-precision
+    reference).  ``bases``: the spatial dictionary W_s (codes of
+    ``oracle/wavelets.py``; the Dirac basis alone by default)."""
 
-    def __init__(self, psf, dirty, params, bases=(DIRAC,)):
-        self.psf = np.asarray(psf, dtype=np.float64)
-        self.Y = np.asarray(dirty, dtype=np.float64)
+    def __init__(self, psf, dirty, params, bases=(DIRAC,), dtype=np.float64):
+        self.psf = np.asarray(psf, dtype=dtype)
+        self.Y = np.asarray(dirty, dtype=dtype)
         assert self.psf.shape == self.Y.shape and self.psf.ndim == 3
         self.p = Params.from_any(params)
         self.W = Dictionary(bases)

@@ -64,10 +64,17 @@ def wavelet_filter(h: np.ndarray) -> np.ndarray:
     return np.array([(-1) ** k * h[K - 1 - k] for k in range(K)])
 
 
+def _real(x):
+    """x as an array of its floating type (float64, or the extended type of an
+    extended-precision run)."""
+    x = np.asarray(x)
+    return x.astype(np.result_type(x.dtype, np.float64), copy=False)
+
+
 def analysis_1d(x: np.ndarray, h: np.ndarray, axis: int):
     """Periodised one-level analysis along ``axis``: (a, d), each half length."""
     g = wavelet_filter(h)
-    x = np.moveaxis(np.asarray(x, np.float64), axis, -1)
+    x = np.moveaxis(_real(x), axis, -1)
     n = x.shape[-1]
     idx = (2 * np.arange(n // 2)[:, None] + np.arange(len(h))[None, :]) % n   # [m, k]
     a = np.einsum("...mk,k->...m", x[..., idx], h)
@@ -78,11 +85,11 @@ def analysis_1d(x: np.ndarray, h: np.ndarray, axis: int):
 def synthesis_1d(a: np.ndarray, d: np.ndarray, h: np.ndarray, axis: int):
     """Transpose of ``analysis_1d``: x[(2m + k) mod n] += h[k] a[m] + g[k] d[m]."""
     g = wavelet_filter(h)
-    a = np.moveaxis(np.asarray(a, np.float64), axis, -1)
-    d = np.moveaxis(np.asarray(d, np.float64), axis, -1)
+    a = np.moveaxis(_real(a), axis, -1)
+    d = np.moveaxis(_real(d), axis, -1)
     half = a.shape[-1]
     n = 2 * half
-    x = np.zeros(a.shape[:-1] + (n,))
+    x = np.zeros(a.shape[:-1] + (n,), dtype=np.result_type(a.dtype, d.dtype))
     for m in range(half):
         for k in range(len(h)):
             x[..., (2 * m + k) % n] += h[k] * a[..., m] + g[k] * d[..., m]
@@ -91,7 +98,7 @@ def synthesis_1d(a: np.ndarray, d: np.ndarray, h: np.ndarray, axis: int):
 
 def dwt2(img: np.ndarray, h: np.ndarray, levels: int) -> np.ndarray:
     """Multi-level periodised 2-D DWT of [..., ny, nx] arrays, Mallat layout."""
-    out = np.array(img, dtype=np.float64, copy=True)
+    out = np.array(_real(img), copy=True)
     ny, nx = out.shape[-2:]
     for j in range(levels):
         sy, sx = ny >> j, nx >> j
@@ -108,7 +115,7 @@ def dwt2(img: np.ndarray, h: np.ndarray, levels: int) -> np.ndarray:
 
 def idwt2(coef: np.ndarray, h: np.ndarray, levels: int) -> np.ndarray:
     """Inverse (= transpose) of ``dwt2``."""
-    out = np.array(coef, dtype=np.float64, copy=True)
+    out = np.array(_real(coef), copy=True)
     ny, nx = out.shape[-2:]
     for j in reversed(range(levels)):
         sy, sx = ny >> j, nx >> j
@@ -148,7 +155,7 @@ class Dictionary:
     def adjoint(self, C: np.ndarray) -> np.ndarray:
         """W_s^T C for stacked coefficient cubes C [n_s][L][ny][nx]."""
         J = self._levels(C[0])
-        out = np.zeros(C.shape[1:])
+        out = np.zeros(C.shape[1:], dtype=_real(C).dtype)
         for i, b in enumerate(self.bases):
             out += C[i] if b == DIRAC else idwt2(C[i], self.filters[b], J)
         return out

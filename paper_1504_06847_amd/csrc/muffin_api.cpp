@@ -35,7 +35,7 @@ int row_forward(muffin_ctx* c) {
 
 int col_solve(muffin_ctx* c) {
     const muffin_shape& s = c->shape;
-    HIP_TRY(launch_col(s.dtype, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
+    HIP_TRY(launch_col(s.dtype, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.yfnyq), P(c, c->lay.h2),
                        P(c, c->lay.h2nyq), rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx,
                        P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream, c->col_v));
     c->zvalid = 0;
@@ -253,7 +253,7 @@ int pass_with_report(muffin_ctx* c, muffin_report* rep) {
     HIP_TRY(launch_row_fwd(s.dtype, s.dtype == MUFFIN_F64, st(c, ST_ZP), P(c, c->lay.z), nrows,
                            s.nx, s.ny, false, true, P(c, c->lay.tw), c->twlog, c->stream));
     int nbc = 0;
-    HIP_TRY(launch_col(s.dtype, COL_OBJ, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
+    HIP_TRY(launch_col(s.dtype, COL_OBJ, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.yfnyq), P(c, c->lay.h2),
                        P(c, c->lay.h2nyq), 0.0, 1.0, s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog,
                        partials, &nbc, c->stream));
     HIP_TRY(launch_reduce_final(partials, nbc, 1, sums + RED_NQ, c->stream));
@@ -439,7 +439,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             // B-bar = Q^{-1} X-bar (Q is symmetric)
             HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, Xb, P(c, c->lay.z), nrows, s.nx, s.ny, false, false,
                                    P(c, c->lay.tw), c->twlog, st_, c->row_v));
-            HIP_TRY(launch_col(dt, COL_FILTER, P(c, c->lay.z), nullptr, P(c, c->lay.h2), P(c, c->lay.h2nyq),
+            HIP_TRY(launch_col(dt, COL_FILTER, P(c, c->lay.z), nullptr, nullptr, P(c, c->lay.h2), P(c, c->lay.h2nyq),
                                rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog,
                                nullptr, nullptr, st_));
             HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), Bb, nrows, s.nx, P(c, c->lay.tw), c->twlog, st_,
@@ -462,7 +462,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         // Fourier domain (Z is scratch here; B_rest is rebuilt below)
         HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, gyac, P(c, c->lay.z), nrows, s.nx, s.ny, false, false,
                                P(c, c->lay.tw), c->twlog, st_, c->row_v));
-        HIP_TRY(launch_col(dt, COL_CONV, P(c, c->lay.z), P(c, c->lay.hh), nullptr, P(c, c->lay.hhnyq), 0.0,
+        HIP_TRY(launch_col(dt, COL_CONV, P(c, c->lay.z), P(c, c->lay.hh), nullptr, nullptr, P(c, c->lay.hhnyq), 0.0,
                            fft_scale(s), s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog, nullptr, nullptr, st_));
         HIP_TRY(launch_row_inv(dt, P(c, c->lay.z), gy_out, nrows, s.nx, P(c, c->lay.tw), c->twlog, st_,
                                c->row_v));
@@ -587,16 +587,16 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     e = launch_row_fwd(MUFFIN_F64, in64, psf, Ch, nrows, shape->nx, shape->ny, true, false,
                        P(c, lay.tw64), c->twlog, c->stream);
     if (e == hipSuccess)
-        e = launch_col(MUFFIN_F64, COL_FWD, Ch, nullptr, nullptr, nullptr, 0.0, 1.0, shape->L, shape->ny,
+        e = launch_col(MUFFIN_F64, COL_FWD, Ch, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0, shape->L, shape->ny,
                        shape->nx, P(c, lay.tw64), c->twlog, nullptr, nullptr, c->stream);
     if (e == hipSuccess)
         e = launch_row_fwd(MUFFIN_F64, in64, dirty, Cy, nrows, shape->nx, shape->ny, false, false,
                            P(c, lay.tw64), c->twlog, c->stream);
     if (e == hipSuccess)
-        e = launch_col(MUFFIN_F64, COL_FWD, Cy, nullptr, nullptr, nullptr, 0.0, 1.0, shape->L, shape->ny,
+        e = launch_col(MUFFIN_F64, COL_FWD, Cy, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0, shape->L, shape->ny,
                        shape->nx, P(c, lay.tw64), c->twlog, nullptr, nullptr, c->stream);
     if (e == hipSuccess)
-        e = launch_setup_combine(shape->dtype, Ch, Cy, P(c, lay.yf), P(c, lay.h2), P(c, lay.h2nyq), P(c, lay.hh),
+        e = launch_setup_combine(shape->dtype, Ch, Cy, P(c, lay.yf), P(c, lay.yfnyq), P(c, lay.h2), P(c, lay.h2nyq), P(c, lay.hh),
                                  P(c, lay.hhnyq),
                                  shape->L, shape->ny, shape->nx, c->stream);
     if (e != hipSuccess) { set_error("setup transform launch failed: %s", hipGetErrorString(e)); return fail(MUFFIN_EDEVICE); }
@@ -935,7 +935,7 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
                                   false, false, P(c, c->lay.tw), c->twlog, c->stream, v);
         });
         t[1][v] = timeit([&] {
-            return launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.h2),
+            return launch_col(dt, COL_SOLVE, P(c, c->lay.z), P(c, c->lay.yf), P(c, c->lay.yfnyq), P(c, c->lay.h2),
                               P(c, c->lay.h2nyq), rho_Q(c->params), fft_scale(s), s.L, s.ny, s.nx,
                               P(c, c->lay.tw), c->twlog, nullptr, nullptr, c->stream, v);
         });

@@ -117,6 +117,7 @@ void fill_desc(const muffin_batch* b, const Class& k, muffin_ctx* c, int first, 
         ColDesc d{};
         d.data = P(c, c->lay.z);
         d.Yf = P(c, c->lay.yf);
+        d.Yfn = P(c, c->lay.yfnyq);
         d.H2 = P(c, c->lay.h2);
         d.H2nyq = P(c, c->lay.h2nyq);
         d.tw = P(c, c->lay.tw);

@@ -320,11 +320,12 @@ __device__ __forceinline__ void fft_stage_range(cx<T>* buf, const cx<T>* __restr
 }
 
 // The first stage (no twiddles) with its input read from global memory:
-// element e of transform tr at src[e * ld + tr], zero for tr >= ntr.  Its
-// output goes to the LDS tile; ends with a barrier.
+// element e of transform tr at src[e * ld + tr], zero for tr >= ntr; with
+// re0, transform 0 reads only the real parts (its imaginary parts as zero).
+// Its output goes to the LDS tile; ends with a barrier.
 template <typename T, int LEN, int NTRANS, int NTH, int TS, int ES, bool TFAST, bool PAD, bool INV>
 __device__ __forceinline__ void fft_first_stage_global(cx<T>* buf, const cx<T>* __restrict__ src, long ld,
-                                                       int ntr, int t) {
+                                                       int ntr, int t, bool re0 = false) {
     constexpr int R = plan_radix(LEN, 0);
     constexpr int NB = LEN / R;
     constexpr int ITEMS = NB * NTRANS;
@@ -337,8 +338,10 @@ __device__ __forceinline__ void fft_first_stage_global(cx<T>* buf, const cx<T>* 
             const int tr = TFAST ? item % NTRANS : item / NB;
             const int j = TFAST ? item / NTRANS : item % NB;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
+            for (int r = 0; r < R; ++r) {
                 v[i][r] = tr < ntr ? src[(long)(j + r * NB) * ld + tr] : cx<T>{T(0), T(0)};
+                if (re0 && tr == 0) v[i][r].y = T(0);
+            }
             dftR<T, R, INV>(v[i]);
         }
     }

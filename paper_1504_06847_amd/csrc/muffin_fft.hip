@@ -209,6 +209,7 @@ k_row_inv_group(const RowDesc* __restrict__ d, int n) {
 // tiles per band.
 template <typename T, int NY, int MODE, int TC>
 __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ Yf,
+                                         const cx<T>* __restrict__ Yfn,
                                          const T* __restrict__ H2, const T* __restrict__ H2nyq,
                                          T rhoQ, T scale, int M, const cx<T>* __restrict__ tw,
                                          int twlog, double* __restrict__ partials, double inv_n,
@@ -239,10 +240,19 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
     if constexpr (TWL) {
         for (int i = t; i < NY; i += NTH) twl[tw_at<COL_TWP>(i)] = tw[i << (twlog - ilog2c(NY))];
     }
+    // Slot 0 of a spectrum row packs the kx = 0 and kx = nx/2 values of the
+    // row transform (both real).  Transformed along y as one complex column,
+    // the two would share its rounding: the error of the large kx = 0 column
+    // (the image mean and its slow variations) would land on the kx = nx/2
+    // column, whose filter gain 1 / (|h_hat|^2 + rho) is the largest of the
+    // band.  In the solving modes the tile holding slot 0 therefore
+    // transforms the real parts (kx = 0) with its other columns and the
+    // imaginary parts (kx = nx/2) as a column of their own.
+    constexpr bool FILT = MODE == COL_SOLVE || MODE == COL_FILTER;
+    const bool dc = FILT && c0 == 0;
     // the data term and the filter of this thread's elements, loaded before
     // the forward transform so that their latency hides behind it (up to 8
     // elements per thread: more would cost the occupancy of wide tiles)
-    constexpr bool FILT = MODE == COL_SOLVE || MODE == COL_FILTER;
     constexpr int IPT = NIT;
     constexpr bool PRE = FILT && IPT <= 8;
     cx<T> yfp[MODE == COL_SOLVE && PRE ? IPT : 1];
@@ -254,7 +264,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
             const int y = i / TC, c = i % TC, kx = c0 + c;
             gp[j] = T(0);
             if constexpr (MODE == COL_SOLVE) yfp[j] = {T(0), T(0)};
-            if (i < NY * TC && kx != 0 && kx < M) {
+            if (i < NY * TC && kx < M) {
                 const long g = base + filt_pos(NY, fsh, y, kx);
                 if constexpr (MODE == COL_SOLVE) yfp[j] = stream_load(Yf + g);
                 gp[j] = scale / (stream_load(H2 + g) + rhoQ);
@@ -263,7 +273,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
     }
     // forward FFT along y; its first stage reads the tile straight from Z
     // (the barrier that ends it also publishes the twiddle table)
-    fft_first_stage_global<T, NY, TC, NTH, 1, 0, true, false, false>(lds, data + base + c0, M, ntr, t);
+    fft_first_stage_global<T, NY, TC, NTH, 1, 0, true, false, false>(lds, data + base + c0, M, ntr, t, dc);
     if constexpr (TWL) fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, false, 1, NST, COL_TWP>(lds, twl, ilog2c(NY), t);
     else fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, false, 1, NST>(lds, tw, twlog, t);
 
@@ -273,7 +283,7 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         for (int j = 0; j < IPT; ++j) {
             const int i = t + j * NTH;
             const int y = i / TC, c = i % TC, kx = c0 + c;
-            if (i >= NY * TC || kx == 0 || kx >= M) continue;
+            if (i >= NY * TC || kx >= M) continue;
             cx<T> v = lds[swz_pos<NY, TC>(y, c)];
             if constexpr (PRE) {
                 if constexpr (MODE == COL_SOLVE) v = v + yfp[j];
@@ -284,36 +294,55 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
                 lds[swz_pos<NY, TC>(y, c)] = v * (scale / (stream_load(H2 + g) + rhoQ));
             }
         }
-        if (c0 == 0) {
-            // slot 0 packs the real columns kx = 0 (A) and kx = nx/2 (B): C = A + i B
-            for (int ky = t; ky <= NY / 2; ky += NTH) {
-                const int kn = (NY - ky) & (NY - 1);
-                const long g1 = base + filt_pos(NY, fsh, ky, 0), g2 = base + filt_pos(NY, fsh, kn, 0);
-                cx<T> c1 = lds[swz_pos<NY, TC>(ky, 0)], c2 = lds[swz_pos<NY, TC>(kn, 0)];
-                if constexpr (MODE == COL_SOLVE) {
-                    c1 = c1 + Yf[g1];
-                    c2 = c2 + Yf[g2];
-                }
-                const T g0 = scale / (H2[g1] + rhoQ);
-                const T gm = scale / (H2nyq[(long)band * NY + ky] + rhoQ);
-                cx<T> A = {T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)};
-                cx<T> B = {T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x)};
-                A = A * g0;
-                B = B * gm;
-                lds[swz_pos<NY, TC>(ky, 0)] = A + mul_i(B);
-                if (kn != ky) lds[swz_pos<NY, TC>(kn, 0)] = conj(A) + mul_i(conj(B));
-            }
-        }
         __syncthreads();
-        // inverse FFT along y; its last stage writes the tile straight to Z
-        if constexpr (TWL) {
-            fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1, COL_TWP>(lds, twl, ilog2c(NY), t);
-            fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true, COL_TWP>(lds, twl, ilog2c(NY),
-                                                                                   data + base + c0, M, ntr, t);
+        if (!dc) {
+            // inverse FFT along y; its last stage writes the tile straight to Z
+            if constexpr (TWL) {
+                fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1, COL_TWP>(lds, twl, ilog2c(NY), t);
+                fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true, COL_TWP>(lds, twl, ilog2c(NY),
+                                                                                       data + base + c0, M, ntr, t);
+            } else {
+                fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1>(lds, tw, twlog, t);
+                fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true>(lds, tw, twlog, data + base + c0, M,
+                                                                              ntr, t);
+            }
         } else {
-            fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST - 1>(lds, tw, twlog, t);
-            fft_last_stage_global<T, NY, TC, NTH, 1, 0, true, false, true>(lds, tw, twlog, data + base + c0, M,
-                                                                          ntr, t);
+            // the tile of slot 0: the whole inverse in LDS, the other columns
+            // written out, the kx = 0 results kept in registers (element y of
+            // the column by thread y mod NTH)
+            if constexpr (TWL) fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST, COL_TWP>(lds, twl, ilog2c(NY), t);
+            else fft_stage_range<T, NY, TC, NTH, 1, 0, true, false, true, 0, NST>(lds, tw, twlog, t);
+            for (int i = t; i < NY * TC; i += NTH) {
+                const int y = i / TC, c = i % TC;
+                if (c > 0 && c < ntr) data[base + (long)y * M + c] = lds[swz_pos<NY, TC>(y, c)];
+            }
+            constexpr int NA = (NY + NTH - 1) / NTH;
+            T a0[NA];
+#pragma unroll
+            for (int j = 0; j < NA; ++j) {
+                const int y = t + j * NTH;
+                a0[j] = y < NY ? lds[swz_pos<NY, TC>(y, 0)].x : T(0);
+            }
+            __syncthreads();
+            // the kx = nx/2 column (imaginary parts of slot 0, still in Z):
+            // forward FFT, data term and filter, inverse FFT, contiguous in LDS
+            for (int y = t; y < NY; y += NTH) lds[y] = {data[base + (long)y * M].y, T(0)};
+            __syncthreads();
+            if constexpr (TWL) fft_stages<T, NY, 1, NTH, 0, 1, false, false, false, 0, COL_TWP>(lds, twl, ilog2c(NY), t);
+            else fft_stages<T, NY, 1, NTH, 0, 1, false, false, false, 0>(lds, tw, twlog, t);
+            for (int y = t; y < NY; y += NTH) {
+                cx<T> v = lds[y];
+                if constexpr (MODE == COL_SOLVE) v = v + Yfn[(long)band * NY + y];
+                lds[y] = v * (scale / (H2nyq[(long)band * NY + y] + rhoQ));
+            }
+            __syncthreads();
+            if constexpr (TWL) fft_stages<T, NY, 1, NTH, 0, 1, false, false, true, 0, COL_TWP>(lds, twl, ilog2c(NY), t);
+            else fft_stages<T, NY, 1, NTH, 0, 1, false, false, true, 0>(lds, tw, twlog, t);
+#pragma unroll
+            for (int j = 0; j < NA; ++j) {
+                const int y = t + j * NTH;
+                if (y < NY) data[base + (long)y * M] = {a0[j], lds[y].x};
+            }
         }
     }
 
@@ -378,13 +407,12 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
         if (c0 == 0) {
             for (int ky = t; ky <= NY / 2; ky += NTH) {
                 const int kn = (NY - ky) & (NY - 1);
-                const long g1 = base + filt_pos(NY, fsh, ky, 0), g2 = base + filt_pos(NY, fsh, kn, 0);
+                const long g1 = base + filt_pos(NY, fsh, ky, 0);
                 const cx<T> c1 = lds[swz_pos<NY, TC>(ky, 0)], c2 = lds[swz_pos<NY, TC>(kn, 0)];
-                const cx<T> f1 = Yf[g1], f2 = Yf[g2];
                 const cx<T> A = {T(0.5) * (c1.x + c2.x), T(0.5) * (c1.y - c2.y)};
                 const cx<T> B = {T(0.5) * (c1.y + c2.y), T(-0.5) * (c1.x - c2.x)};
-                const cx<T> FA = {T(0.5) * (f1.x + f2.x), T(0.5) * (f1.y - f2.y)};
-                const cx<T> FB = {T(0.5) * (f1.y + f2.y), T(-0.5) * (f1.x - f2.x)};
+                // the data terms of the kx = 0 and kx = nx/2 columns, stored apart
+                const cx<T> FA = Yf[g1], FB = Yfn[(long)band * NY + ky];
                 const double wgt = (kn == ky) ? 1.0 : 2.0;
                 const double a2 = double(A.x) * A.x + double(A.y) * A.y;
                 const double b2 = double(B.x) * B.x + double(B.y) * B.y;
@@ -401,14 +429,14 @@ __device__ __forceinline__ void col_body(cx<T>* data, const cx<T>* __restrict__ 
 
 template <typename T, int NY, int MODE, int V>
 __global__ void __launch_bounds__((col_nth<T, NY, col_tc<T, NY, V>()>()))
-k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const T* __restrict__ H2,
+k_col(cx<T>* data, const cx<T>* __restrict__ Yf, const cx<T>* __restrict__ Yfn, const T* __restrict__ H2,
       const T* __restrict__ H2nyq, T rhoQ, T scale, int M, const cx<T>* __restrict__ tw,
       int twlog, double* __restrict__ partials, double inv_n) {
     constexpr int TC = col_tc<T, NY, V>();
     __shared__ cx<T> lds[NY * TC];
     __shared__ cx<T> twl[col_twl<T, NY>() ? col_twl_len<NY>() : 1];
     __shared__ double red[col_nth<T, NY, TC>() / 64];
-    col_body<T, NY, MODE, TC>(data, Yf, H2, H2nyq, rhoQ, scale, M, tw, twlog, partials, inv_n,
+    col_body<T, NY, MODE, TC>(data, Yf, Yfn, H2, H2nyq, rhoQ, scale, M, tw, twlog, partials, inv_n,
                               blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y, gridDim.x,
                               lds, twl, red);
 }
@@ -426,7 +454,8 @@ k_col_group(const ColDesc* __restrict__ d, int n) {
     if (j < 0) return;
     const int M = d[j].M;
     const unsigned ntiles = (unsigned)((M + TC - 1) / TC);
-    col_body<T, NY, COL_SOLVE, TC>((cx<T>*)d[j].data, (const cx<T>*)d[j].Yf, (const T*)d[j].H2,
+    col_body<T, NY, COL_SOLVE, TC>((cx<T>*)d[j].data, (const cx<T>*)d[j].Yf, (const cx<T>*)d[j].Yfn,
+                                   (const T*)d[j].H2,
                                    (const T*)d[j].H2nyq, T(d[j].rhoQ), T(d[j].scale), M,
                                    (const cx<T>*)d[j].tw, d[j].twlog, nullptr, 0.0,
                                    blockIdx.x - (unsigned)d[j].first, (unsigned)d[j].nblk, ntiles,
@@ -437,8 +466,8 @@ k_col_group(const ColDesc* __restrict__ d, int n) {
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_setup_combine(const cx<double>* __restrict__ Ch, const cx<double>* __restrict__ Cy,
-                cx<T>* __restrict__ Yf, T* __restrict__ H2, T* __restrict__ H2nyq, cx<T>* __restrict__ Hh,
-                cx<T>* __restrict__ Hhnyq, int L, int ny, int M) {
+                cx<T>* __restrict__ Yf, cx<T>* __restrict__ Yfnyq, T* __restrict__ H2, T* __restrict__ H2nyq,
+                cx<T>* __restrict__ Hh, cx<T>* __restrict__ Hhnyq, int L, int ny, int M) {
     // Ch, Cy in spectrum order [L][ny][M]; Yf, H2 written in column-block order
     const long n = (long)L * ny * M;
     const int fsh = filt_shift<T>(ny, M);
@@ -464,9 +493,14 @@ k_setup_combine(const cx<double>* __restrict__ Ch, const cx<double>* __restrict_
             const cx<double> By = {0.5 * (y1.y + y2.y), -0.5 * (y1.x - y2.x)};
             const cx<double> FA = {Ah.x * Ay.x + Ah.y * Ay.y, Ah.x * Ay.y - Ah.y * Ay.x};
             const cx<double> FB = {Bh.x * By.x + Bh.y * By.y, Bh.x * By.y - Bh.y * By.x};
-            // packed: FA + i FB at ky, conj(FA) + i conj(FB) at -ky
-            Yf[o] = {T(FA.x - FB.y), T(FA.y + FB.x)};
-            Yf[o2] = {T(FA.x + FB.y), T(FB.x - FA.y)};
+            // the data terms of the two columns stored apart (each Hermitian
+            // in ky): kx = 0 in slot 0, kx = nx/2 in its own column.  Packed
+            // into one complex value, the rounding of the large kx = 0 term
+            // would fall on the small kx = nx/2 one.
+            Yf[o] = {T(FA.x), T(FA.y)};
+            Yf[o2] = {T(FA.x), T(-FA.y)};
+            Yfnyq[band * ny + ky] = {T(FB.x), T(FB.y)};
+            Yfnyq[band * ny + kn] = {T(FB.x), T(-FB.y)};
             const T a2 = T(Ah.x * Ah.x + Ah.y * Ah.y), b2 = T(Bh.x * Bh.x + Bh.y * Bh.y);
             H2[o] = a2;
             H2[o2] = a2;
@@ -593,8 +627,8 @@ int col_blocks(int dtype, int L, int ny, int nx, int variant) {
 }
 
 template <typename T, int MODE, int V>
-static hipError_t col_t(void* data, const void* Yf, const void* H2, const void* H2nyq, double rhoQ,
-                        double scale, int L, int ny, int nx, const void* tw, int twlog,
+static hipError_t col_t(void* data, const void* Yf, const void* Yfn, const void* H2, const void* H2nyq,
+                        double rhoQ, double scale, int L, int ny, int nx, const void* tw, int twlog,
                         double* partials, int* nblocks_out, hipStream_t s) {
     const int M = nx / 2;
     switch (ny) {
@@ -604,7 +638,8 @@ static hipError_t col_t(void* data, const void* Yf, const void* H2, const void* 
         dim3 grid((M + TC - 1) / TC, L);                                                      \
         if (nblocks_out) *nblocks_out = int(grid.x * grid.y);                                 \
         hipLaunchKernelGGL((k_col<T, N, MODE, V>), grid, dim3(col_nth<T, N, TC>()), 0, s,     \
-                           (cx<T>*)data, (const cx<T>*)Yf, (const T*)H2, (const T*)H2nyq,     \
+                           (cx<T>*)data, (const cx<T>*)Yf, (const cx<T>*)Yfn, (const T*)H2,   \
+                           (const T*)H2nyq,                                                   \
                            T(rhoQ), T(scale), M, (const cx<T>*)tw, twlog, partials,           \
                            1.0 / (double(nx) * double(ny)));                                  \
         return hipGetLastError();                                                             \
@@ -615,33 +650,33 @@ static hipError_t col_t(void* data, const void* Yf, const void* H2, const void* 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const void* H2,
+hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const void* Yfnyq, const void* H2,
                       const void* H2nyq, double rhoQ, double scale, int L, int ny, int nx,
                       const void* tw, int twlog, double* partials, int* nblocks_out,
                       hipStream_t s, int variant) {
     constexpr int D = kDefaultColVariant;
     if (dtype == 0) {
         if (mode == COL_SOLVE) {
-            MUFFIN_VARIANT(variant, return (col_t<float, COL_SOLVE, V>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s)))
+            MUFFIN_VARIANT(variant, return (col_t<float, COL_SOLVE, V>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s)))
         }
         if (mode == COL_OBJ)
-            return col_t<float, COL_OBJ, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+            return col_t<float, COL_OBJ, D>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
         if (mode == COL_FILTER)
-            return col_t<float, COL_FILTER, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+            return col_t<float, COL_FILTER, D>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
         if (mode == COL_CONV)
-            return col_t<float, COL_CONV, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+            return col_t<float, COL_CONV, D>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
         return hipErrorInvalidValue;
     }
     if (mode == COL_FILTER)
-        return col_t<double, COL_FILTER, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+        return col_t<double, COL_FILTER, D>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
     if (mode == COL_CONV)
-        return col_t<double, COL_CONV, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+        return col_t<double, COL_CONV, D>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
     if (mode == COL_SOLVE) {
-        MUFFIN_VARIANT(variant, return (col_t<double, COL_SOLVE, V>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s)))
+        MUFFIN_VARIANT(variant, return (col_t<double, COL_SOLVE, V>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s)))
     }
     if (mode == COL_FWD)
-        return col_t<double, COL_FWD, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
-    return col_t<double, COL_OBJ, D>(data, Yf, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+        return col_t<double, COL_FWD, D>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
+    return col_t<double, COL_OBJ, D>(data, Yf, Yfnyq, H2, H2nyq, rhoQ, scale, L, ny, nx, tw, twlog, partials, nblocks_out, s);
 }
 
 // ------------------------------------------------------------------ grouped launchers
@@ -694,18 +729,18 @@ hipError_t launch_col_group(int dtype, int ny, int variant, const ColDesc* d, in
     MUFFIN_VARIANT(variant, return (col_group_t<double, V>(ny, d, n, nblocks, s)))
 }
 
-hipError_t launch_setup_combine(int dtype, const void* Ch, const void* Cy, void* Yf, void* H2,
+hipError_t launch_setup_combine(int dtype, const void* Ch, const void* Cy, void* Yf, void* Yfnyq, void* H2,
                                 void* H2nyq, void* Hh, void* Hhnyq, int L, int ny, int nx, hipStream_t s) {
     const int M = nx / 2;
     const long n = (long)L * ny * M;
     const int blocks = int((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
     if (dtype == 0)
         hipLaunchKernelGGL((k_setup_combine<float>), dim3(blocks), dim3(256), 0, s,
-                           (const cx<double>*)Ch, (const cx<double>*)Cy, (cx<float>*)Yf,
+                           (const cx<double>*)Ch, (const cx<double>*)Cy, (cx<float>*)Yf, (cx<float>*)Yfnyq,
                            (float*)H2, (float*)H2nyq, (cx<float>*)Hh, (cx<float>*)Hhnyq, L, ny, M);
     else
         hipLaunchKernelGGL((k_setup_combine<double>), dim3(blocks), dim3(256), 0, s,
-                           (const cx<double>*)Ch, (const cx<double>*)Cy, (cx<double>*)Yf,
+                           (const cx<double>*)Ch, (const cx<double>*)Cy, (cx<double>*)Yf, (cx<double>*)Yfnyq,
                            (double*)H2, (double*)H2nyq, (cx<double>*)Hh, (cx<double>*)Hhnyq, L, ny, M);
     return hipGetLastError();
 }

@@ -59,8 +59,11 @@ hipError_t launch_row_inv(int dtype, const void* in, void* out, int nrows, int n
 // FFT along y, multiplication by h_hat * scale (the convolution H; Yf points
 // at the packed h_hat, H2nyq at its kx = nx/2 column, complex), inverse FFT.
 // Yf, H2 and h_hat are in the column-block order launch_setup_combine
-// writes (H2nyq: [L][ny]; the h_hat column: [L][ny] complex).
-hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const void* H2,
+// writes; Yf's slot 0 holds the kx = 0 column alone and Yfnyq ([L][ny]
+// complex) the kx = nx/2 column (H2nyq: [L][ny]; the h_hat column: [L][ny]
+// complex).  In COL_SOLVE and COL_FILTER the two real columns packed in
+// slot 0 are transformed apart (one rounding each).
+hipError_t launch_col(int dtype, int mode, void* data, const void* Yf, const void* Yfnyq, const void* H2,
                       const void* H2nyq, double rhoQ, double scale, int L, int ny, int nx,
                       const void* tw, int twlog, double* partials, int* nblocks_out,
                       hipStream_t s, int variant = kDefaultColVariant);
@@ -79,6 +82,7 @@ struct RowDesc {             // a row pass (forward: in = B_rest, out = Z; inver
 struct ColDesc {             // the solving column pass of one cube
     void* data;
     const void* Yf;
+    const void* Yfn;
     const void* H2;
     const void* H2nyq;
     const void* tw;
@@ -104,7 +108,7 @@ struct SpecDesc {
 };
 
 // the host (g++) and device (hipcc) compilers must agree on these layouts
-static_assert(sizeof(SpecArgs) == 48 && sizeof(RowDesc) == 40 && sizeof(ColDesc) == 80 &&
+static_assert(sizeof(SpecArgs) == 48 && sizeof(RowDesc) == 40 && sizeof(ColDesc) == 88 &&
                   sizeof(SpecArrays) == 88 && sizeof(SpecDesc) == 168,
               "descriptor layout");
 
@@ -211,12 +215,13 @@ hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, in
                            hipStream_t s);
 
 // Setup: combine the FP64 packed column spectra of the shifted PSF (Ch) and of
-// the dirty image (Cy) into conj(h_hat) y_hat (Yf), |h_hat|^2 (H2, and H2nyq
-// for the kx = nx/2 column), stored in the iteration's precision.  Yf and H2
+// the dirty image (Cy) into conj(h_hat) y_hat (Yf, and Yfnyq for the kx = nx/2
+// column), |h_hat|^2 (H2, and H2nyq for the kx = nx/2 column), stored in the
+// iteration's precision.  Yf and H2
 // go in column-block order: per band, blocks of W adjacent kx columns (W =
 // min(16, 64 KiB / (ny complex values), nx/2), the default column tile),
 // each block's ny rows contiguous.
-hipError_t launch_setup_combine(int dtype, const void* Ch, const void* Cy, void* Yf, void* H2,
+hipError_t launch_setup_combine(int dtype, const void* Ch, const void* Cy, void* Yf, void* Yfnyq, void* H2,
                                 void* H2nyq, void* Hh, void* Hhnyq, int L, int ny, int nx, hipStream_t s);
 
 // dst[i] += src[i], i < n

@@ -18,7 +18,7 @@ constexpr int kMaxDwtLevels = 4;
 struct Layout {
     size_t state[2][kNumState];   // current and alternate state sets (a reporting
                                   // pass writes the alternate set, then they swap)
-    size_t brest, x, z, yf, h2, h2nyq, tw, tw64, dctm, partials, vpart, sums;
+    size_t brest, x, z, yf, yfnyq, h2, h2nyq, tw, tw64, dctm, partials, vpart, sums;
     size_t hh, hhnyq;             // h_hat packed like Yf, and its kx = nx/2 column (complex)
     // wavelet bases of the spatial dictionary: one coefficient cube z_b per
     // basis, per basis the scratch image of each DWT level j >= 1 (its LL

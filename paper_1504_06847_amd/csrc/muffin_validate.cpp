@@ -122,6 +122,7 @@ Layout make_layout(const muffin_shape* s, int n_s) {
             lay.wtmp[b][j] = take(size_t(s->L) * size_t(s->ny >> j) * size_t(s->nx >> j) * sz);
     lay.z = take(HS * 2 * sz);
     lay.yf = take(HS * 2 * sz);
+    lay.yfnyq = take(size_t(s->L) * s->ny * 2 * sz);
     lay.h2 = take(HS * sz);
     lay.h2nyq = take(size_t(s->L) * s->ny * sz);
     lay.hh = take(HS * 2 * sz);

@@ -108,3 +108,18 @@ def batched_shapes(seed: int = 3, n_cubes: int = 16):
 
 def get_config(name: str) -> Config:
     return CONFIGS[name]
+
+
+def batch_instances(seed: int = 3, n_cubes: int = 16):
+    """The uneven batch: ``n_cubes`` cubes with the shapes of
+    ``batched_shapes`` (N^2 in {128^2, 256^2, 512^2} x L in {16, 32, 64,
+    128}), cube i drawn with the 256^2 x 32 generator settings (40 points,
+    10 Gaussians, 40 antennas, sigma 0.005) and seed 300 + i.  Returns
+    ([(psf, dirty), ...], parameters)."""
+    c = get_config("fp32_256")
+    out = []
+    for i, (ny, nx, L) in enumerate(batched_shapes(seed, n_cubes)):
+        inst = make_instance(ny, nx, L, n_points=c.n_points, n_gauss=c.n_gauss, n_ant=c.n_ant,
+                             noise_sigma=c.noise_sigma, seed=300 + i)
+        out.append((inst.psf, inst.dirty))
+    return out, c.params

@@ -9,13 +9,13 @@ import math
 import numpy as np
 
 
-def dense_conv_matrix(psf_band):
+def dense_conv_matrix(psf_band, dtype=np.float64):
     """Dense H_l for one band: 2-D circular convolution with a PSF whose peak
     sits at 0-based pixel (ny/2, nx/2).  (H x)[p] = sum_q psf[p - q + c] x[q]."""
     ny, nx = psf_band.shape
     cy, cx = ny // 2, nx // 2
     n = ny * nx
-    H = np.zeros((n, n))
+    H = np.zeros((n, n), dtype=dtype)
     for py in range(ny):
         for px in range(nx):
             for qy in range(ny):

@@ -37,14 +37,16 @@ def test_adaptive_solve_matches_oracle(gpu_lib, dtype, rho, bar):
               eps_abs=1e-6, eps_rel=1e-5)
     s = Solver(inst.psf, inst.dirty, dtype=torch.float64 if dtype == "f64" else torch.float32, **kw)
     rep = s.solve(120, adaptive=(10.0, 2.0))
-    st, pr, hist = O.solve_adaptive(O.Problem(inst.psf, inst.dirty, p), 120, 10, 10.0, 2.0,
-                                    eps_abs=1e-6, eps_rel=1e-5)
+    # FP64 against the oracle in extended precision, FP32 against float64
+    prob = O.Problem(inst.psf, inst.dirty, p, dtype=np.longdouble if dtype == "f64" else np.float64)
+    st, pr, hist = O.solve_adaptive(prob, 120, 10, 10.0, 2.0, eps_abs=1e-6, eps_rel=1e-5)
     _say(dtype, rho, "gpu rho", s.params["rho_P"], "iters", rep["iters"], "oracle rho", pr.p.rho_P,
          "iters", hist[-1][0], "history", [(k, r) for k, r, _, _ in hist])
     assert s.params["rho_P"] == pr.p.rho_P and s.params["rho_S"] == pr.p.rho_S
     assert pr.p.rho_P != rho                       # the rule fired
     assert rep["iters"] == hist[-1][0]
     x = s.x.cpu().double().numpy()
-    err = float(np.linalg.norm(x - st.X) / np.linalg.norm(st.X))
+    xr = st.X.astype(np.float64)
+    err = float(np.linalg.norm(x - xr) / np.linalg.norm(xr))
     _say("  X rel err", err)
     assert err <= bar

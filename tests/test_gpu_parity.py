@@ -1,9 +1,12 @@
-"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+"""Parity of the HIP path (through the C ABI) with the oracle.
 
 Error metric: relative L2 over the whole cube, ||X_gpu^k - X_or^k|| / ||X_or^k||,
-for every iterate k.  Bars: FP64 instantiation 1e-12 (a few hundred passes of
-double rounding, each well under 1e-14); FP32 1e-5 per iterate and 1e-4 on
-the final cube (the stated FP32-vs-FP64 tolerance).
+for every iterate k.  Bars: FP32 1e-5 per iterate and 1e-4 on the final cube
+against the float64 oracle (the stated FP32-vs-FP64 tolerance); the FP64
+instantiation 1e-12 against the oracle run in extended precision (step I
+amplifies the rounding of either float64 evaluation by up to
+max |h_hat|^2 / rho, so float64 against float64 would measure the
+oracle's error as much as the kernel's).
 """
 import os
 import sys
@@ -36,14 +39,15 @@ def _params(p):
 def _per_iterate(inst, params, K, dtype, every=1):
     from paper_1504_06847_amd import Solver
     s = Solver(inst.psf, inst.dirty, dtype=dtype, **_params(params))
-    prob = O.Problem(inst.psf, inst.dirty, params)
+    prob = O.Problem(inst.psf, inst.dirty, params,
+                     dtype=np.longdouble if dtype == torch.float64 else np.float64)
     st = O.State.zeros(prob.shape)
     errs = []
     for k in range(1, K + 1):
         s.iterate(1)
         st = O.admm_iteration(prob, st)
         if k % every == 0 or k == K:
-            errs.append(rel(s.x.cpu().double().numpy(), st.X))
+            errs.append(rel(s.x.cpu().double().numpy(), st.X.astype(np.float64)))
     return errs, s, prob, st
 
 
@@ -59,31 +63,17 @@ SHAPES = [
 ]
 
 
-def _fp64_floor(inst, p):
-    """Relative spread of X^1 between two FP64 evaluations (scipy.fft in the
-    oracle, numpy.fft here): the FP64 noise floor of this instance.  Step I
-    divides by |h_hat|^2 + rho, so cancellation in H^T Y sets the floor."""
-    prob = O.Problem(inst.psf, inst.dirty, p)
-    x1 = O.admm_iteration(prob, O.State.zeros(prob.shape)).X
-    h = np.fft.fft2(np.fft.ifftshift(inst.psf.astype(np.float64), axes=(-2, -1)))
-    y = np.fft.fft2(inst.dirty.astype(np.float64))
-    x1b = np.fft.ifft2(np.conj(h) * y / (np.abs(h) ** 2 + p.rho_Q)).real
-    return rel(x1b, x1)
-
-
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_step_I_fp64_matches_oracle(gpu_lib, shape):
-    """First passes from the zero state (X^1 = Q^{-1} H^T Y), FP64 instantiation.
-    Bar: 1e-12, or 10x the instance's FP64 noise floor when that is larger."""
+    """First passes from the zero state (X^1 = Q^{-1} H^T Y), FP64 instantiation."""
     L, ny, nx = shape
     _say("step I fp64", shape)
     inst = make_instance(ny, nx, L, n_points=4, n_gauss=2, n_ant=12, noise_sigma=0.01,
                          seed=100 + L + ny + nx, sigma_range=(1.0, 3.0))
     p = O.Params(1e-3, 0.5, 1.0, 1.0, 5.0, 2.0, 1.0)
     errs, s, prob, st = _per_iterate(inst, p, 3, torch.float64)
-    bar = max(1e-12, 10.0 * _fp64_floor(inst, p))
-    _say("errs", errs, "bar", bar)
-    assert max(errs) < bar, errs
+    _say("errs", errs)
+    assert max(errs) < 1e-12, errs
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))

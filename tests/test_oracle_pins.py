@@ -120,6 +120,52 @@ def test_fourier_solve_nonsymmetric_psf():
         np.testing.assert_allclose(prob.solve_Q(b)[l], ref, atol=1e-12)
 
 
+def _ill_conditioned(dtype):
+    """An 8 x 8 problem whose filter gain spans about 1e5 (a PSF with a large
+    DC response, a small rho)."""
+    rng = np.random.default_rng(21)
+    psf = rng.uniform(0.5, 1.0, size=(2, 8, 8))
+    psf[:, 4, 4] = 1.0
+    Y = rng.standard_normal((2, 8, 8))
+    prob = O.Problem(psf, Y, O.Params(1e-3, 0.1, 0.1, 0.01, 0.01, 0.01, 0.01), dtype=dtype)
+    return prob, psf, rng
+
+
+@pytest.mark.parametrize("dtype,bar", [(np.float64, 1e-15), (np.longdouble, 1e-18)],
+                         ids=["float64", "extended"])
+def test_fourier_solve_residual_at_working_precision(dtype, bar):
+    """Step I in float64 and in extended precision: the residual of
+    (H^T H + rho I) x = b against the dense matrices (built from the PSF and
+    multiplied in extended precision) is at the working precision's rounding
+    level, relative to ||Q|| ||x||, on a system with condition number ~1e5."""
+    prob, psf, rng = _ill_conditioned(dtype)
+    ld = np.longdouble
+    b = rng.standard_normal(prob.shape)
+    x = prob.solve_Q(b.astype(dtype))
+    assert x.dtype == dtype
+    gain = float((np.abs(prob.hhat) ** 2).max() / prob.rho_Q)
+    assert gain > 1e4
+    for l in range(2):
+        H = dense_conv_matrix(psf[l], dtype=ld)
+        Q = H.T @ H + ld(prob.rho_Q) * np.eye(64, dtype=ld)
+        xv = x[l].ravel().astype(ld)
+        r = Q @ xv - b[l].ravel().astype(ld)
+        qn = float(np.abs(Q).sum(axis=1).max())            # ||Q||_inf
+        res = float(np.abs(r).max()) / (qn * float(np.abs(xv).max()))
+        assert res < bar, (l, res)
+
+
+def test_extended_precision_oracle_agrees_with_float64(tiny):
+    """The same iteration in the two precisions: 20 passes on a well
+    conditioned cube agree to float64 rounding."""
+    prob, Hd, rng = tiny
+    a = O.run(prob, 20)
+    b = O.run(O.Problem(prob.psf, prob.Y, prob.p, dtype=np.longdouble), 20)
+    assert b.X.dtype == np.longdouble and b.GV.dtype == np.longdouble
+    d = float(np.linalg.norm((a.X - b.X).astype(np.float64)) / np.linalg.norm(b.X.astype(np.float64)))
+    assert d < 1e-13, d
+
+
 # ------------------------------------------------ Steps II-IV: proximity operators
 def test_steps_II_III_IV_are_block_minimisers(tiny):
     """Comparison-based minimisation resolves an argmin to about sqrt(eps) of
