@@ -136,8 +136,11 @@ int muffin_wavelet_filter(int p, double* h);
    (stored in the shape's precision) into `workspace`, scans psf/dirty for
    non-finite values, zeroes the ADMM state (Algorithm 1 initialisation) and
    writes the new context to *ctx.  psf, dirty: device [L][ny][nx] arrays.
-   Asynchronous on `stream` except for one 8-byte read-back of the scan
-   result.  Errors: EINVAL, EUNSUPPORTED, EWORKSPACE, EDEVICE, ENONFINITE. */
+   Synchronous: it reads the scan result back, uploads the twiddle and DCT
+   tables with blocking copies and synchronises `stream` before returning,
+   so psf and dirty may be freed or overwritten as soon as it returns.  It
+   creates one private stream per context (graph capture).
+   Errors: EINVAL, EUNSUPPORTED, EWORKSPACE, EDEVICE, ENONFINITE. */
 int muffin_setup(muffin_ctx** ctx, const muffin_shape* shape, const muffin_params* params,
                  const void* psf, const void* dirty, void* workspace, size_t ws_bytes,
                  void* stream);
@@ -186,14 +189,30 @@ int muffin_get_p(muffin_ctx* ctx, void* p_out);
    along (1, 1, 1, 1)).  mode = MUFFIN_MODE_MSE: sky_or_gx is a device cube
    (the reference sky), loss = ||x_K - sky||^2.  mode = MUFFIN_MODE_VJP:
    sky_or_gx is dL/dx_K and *loss is left as 0.  Uses a reverse sweep with
-   state checkpoints every ckpt_every passes.  grad: host double[3].  The
-   context's state afterwards equals the state after K passes from zero.
-   Allocates its own device scratch, kept for the next call and freed by
-   muffin_destroy: 4 ceil(K / C) + 10 C + 11 cubes for C = ckpt_every < K
-   (4 + 5 K + 11 for C >= K), one more with muffin_grad_dirty.
-   Errors: EINVAL, EDEVICE. */
+   state checkpoints every ckpt_every passes, in the device scratch attached
+   with muffin_set_grad_workspace (muffin_grad_workspace_bytes(ctx, K,
+   ckpt_every, 0) bytes; the library allocates nothing).  grad: host
+   double[3].  The context's state afterwards equals the state after K
+   passes from zero.  Synchronises the stream.
+   Errors: EINVAL, EUNSUPPORTED (wavelet dictionary), EWORKSPACE (no or a too
+   small workspace attached), EDEVICE, ENONFINITE. */
 int muffin_grad(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
                 double* loss, double grad[3]);
+
+/* Bytes of device scratch the reverse sweep of K passes with checkpoints
+   every ckpt_every needs (dirty = 1: for muffin_grad_dirty, one cube more):
+   4 ceil(K / C) + 10 C + 11 cubes for C = ckpt_every < K (4 + 5 K + 11 for
+   C >= K), a cube being L ny nx values of the context's dtype rounded up to
+   256 B, plus FP64 block sums.  0 for a NULL or batch context, K < 1 or
+   ckpt_every < 1.  Host-only. */
+size_t muffin_grad_workspace_bytes(const muffin_ctx* ctx, int K, int ckpt_every, int dirty);
+
+/* Attach the caller's device scratch for the gradient calls (ws 256-byte
+   aligned, `bytes` long; NULL detaches).  The context keeps the pointer
+   until it is replaced or the context destroyed; the caller keeps it
+   allocated meanwhile.  Its contents between calls are not used.
+   Errors: EINVAL, EWORKSPACE (misaligned). */
+int muffin_set_grad_workspace(muffin_ctx* ctx, void* ws, size_t bytes);
 
 /* The same reverse sweep, with the derivative along each parameter on its
    own: grad = d/d(mu_eps, mu_s, mu_nu, rho_P, rho_T, rho_V, rho_S) (host
@@ -207,7 +226,9 @@ int muffin_grad_params(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_o
    gy_out (device [L][ny][nx], the iteration's dtype, caller-owned) receives
    dL/dY.  Y enters every pass through H^T Y in the right-hand side of step
    I (eq. matB), so dL/dY = H sum_k Q^{-1} X-bar_k, with X-bar_k the
-   cotangent of pass k's X.  loss as muffin_grad.  Errors as muffin_grad. */
+   cotangent of pass k's X.  loss as muffin_grad.  The attached workspace
+   must hold muffin_grad_workspace_bytes(ctx, K, ckpt_every, 1) bytes.
+   Errors as muffin_grad. */
 int muffin_grad_dirty(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
                       double* loss, void* gy_out);
 
@@ -283,8 +304,13 @@ int muffin_fused_available(const muffin_ctx* ctx);
    passes per nx, the column pass per ny, the spectral pass per band count)
    that covers the tiles of every cube in the class, so that small cubes
    share the GPU instead of running one after another.  Results are bitwise
-   identical to iterating each cube on its own with the same schedule. */
-typedef struct muffin_batch muffin_batch;
+   identical to iterating each cube on its own with the same schedule.
+
+   A batch is held by a batch context.  On it, muffin_iterate runs n passes
+   of every cube, muffin_set_graph replays each batch pass from one HIP
+   graph, muffin_iterations counts the batch passes and muffin_destroy
+   releases the batch and its cubes; every other single-cube call returns
+   MUFFIN_EINVAL on it and works on the cube contexts of muffin_batch_cube. */
 
 /* Device workspace bytes for n cubes: the per-cube workspaces
    (muffin_workspace_bytes, 256-B aligned) plus the launch descriptors.
@@ -293,36 +319,32 @@ typedef struct muffin_batch muffin_batch;
 #define MUFFIN_MAX_BATCH 256
 size_t muffin_batch_workspace_bytes(int n, const muffin_shape* shapes, const muffin_params* params);
 
-/* Set up n cubes: shapes[i], params[i], psf[i], dirty[i] as for
-   muffin_setup (every cube in one dtype), one 256-B aligned workspace of at
-   least muffin_batch_workspace_bytes bytes, one stream for all cubes.
-   Errors: as muffin_setup, plus EINVAL for n out of range or mixed dtypes. */
-int muffin_batch_setup(muffin_batch** batch, int n, const muffin_shape* shapes,
+/* Set up n cubes and write the batch context to *ctx: shapes[i],
+   params[i], psf[i], dirty[i] as for muffin_setup (every cube in one dtype,
+   the Dirac spatial basis), one 256-B aligned workspace of at least
+   muffin_batch_workspace_bytes bytes, one stream for all cubes.
+   Synchronous, as muffin_setup.
+   Errors: as muffin_setup, plus EINVAL for n out of range or mixed dtypes,
+   EUNSUPPORTED for a wavelet dictionary. */
+int muffin_setup_batch(muffin_ctx** ctx, int n, const muffin_shape* shapes,
                        const muffin_params* params, const void* const* psf,
                        const void* const* dirty, void* workspace, size_t ws_bytes, void* stream);
 
-/* n_iter passes of every cube (asynchronous on the batch stream). */
-int muffin_batch_iterate(muffin_batch* batch, int n_iter);
-
-/* The context of cube i (owned by the batch; do not destroy it).  Every
-   single-cube call works on it (muffin_get_x, muffin_step_report,
-   muffin_solve, muffin_set_params, state calls ...); the batch notices the
-   changes before its next pass.  NULL if i is out of range. */
-muffin_ctx* muffin_batch_cube(muffin_batch* batch, int i);
+/* The context of cube i of a batch context (owned by the batch; do not
+   destroy it).  Every single-cube call works on it (muffin_get_x,
+   muffin_step_report, muffin_solve, muffin_set_params, state calls ...); the
+   batch notices the changes before its next pass.  NULL if `batch` is not a
+   batch context or i is out of range (muffin_last_error says which). */
+muffin_ctx* muffin_batch_cube(muffin_ctx* batch, int i);
 
 /* Autotune every cube's own schedule (muffin_autotune: which pass form the
    cube joins), then time the variants of each grouped transform launch per
    shape class and keep the fastest.  Synchronises the stream. */
-int muffin_batch_autotune(muffin_batch* batch, int reps);
+int muffin_batch_autotune(muffin_ctx* batch, int reps);
 
-/* Replay each batch pass from one HIP graph (as muffin_set_graph). */
-int muffin_batch_set_graph(muffin_batch* batch, int enable);
-
-/* Number of grouped launches per pass (shape classes of the four passes). */
-int muffin_batch_launches(const muffin_batch* batch);
-
-/* Release the batch and its cube contexts.  NULL is a no-op. */
-int muffin_batch_destroy(muffin_batch* batch);
+/* Number of grouped launches per pass (shape classes of the four passes);
+   -1 if `batch` is not a batch context. */
+int muffin_batch_launches(const muffin_ctx* batch);
 
 /* Time n_iter passes with HIP events around every kernel launch on the
    context's stream; writes the mean duration in ms of each kernel of one
@@ -330,7 +352,8 @@ int muffin_batch_destroy(muffin_batch* batch);
    kernels; returns the number of kernels per pass (negative on error). */
 int muffin_profile(muffin_ctx* ctx, int n_iter, double* ms, const char** names, int cap);
 
-/* Release the context (not the caller's workspace).  NULL is a no-op. */
+/* Release the context (not the caller's workspaces); a batch context
+   releases its cubes too.  NULL is a no-op. */
 int muffin_destroy(muffin_ctx* ctx);
 
 /* Message for the last error on the calling thread ("" if none). */

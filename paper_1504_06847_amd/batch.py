@@ -1,6 +1,7 @@
 """Python front end of the batched form: many independent cubes of uneven
-size and band count iterating together through grouped launches (the C ABI's
-muffin_batch_* calls).  Each cube is also reachable as a ``Solver`` view."""
+size and band count iterating together through grouped launches (a batch
+context of the C ABI, muffin_setup_batch).  Each cube is also reachable as a
+``Solver`` view."""
 from __future__ import annotations
 
 import ctypes
@@ -58,10 +59,10 @@ class Batch:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         psfs = (c_void_p * n)(*[self._inputs[2 * i].data_ptr() for i in range(n)])
         dirts = (c_void_p * n)(*[self._inputs[2 * i + 1].data_ptr() for i in range(n)])
-        rc = self._lib.muffin_batch_setup(byref(self._b), n, shapes, prm, psfs, dirts,
+        rc = self._lib.muffin_setup_batch(byref(self._b), n, shapes, prm, psfs, dirts,
                                           c_void_p(self._ws.data_ptr() + off), ws,
                                           c_void_p(self.stream.cuda_stream))
-        L.check(rc, "muffin_batch_setup", self._lib)
+        L.check(rc, "muffin_setup_batch", self._lib)
         self._inputs = None          # setup keeps no pointer to them
         self.n = n
         if graph:
@@ -75,28 +76,34 @@ class Batch:
         if not 0 <= i < self.n:
             raise IndexError(i)
         ctx = self._lib.muffin_batch_cube(self._b, int(i))
+        if not ctx:
+            raise L.MuffinError(L.MUFFIN_EINVAL, "muffin_batch_cube", L.last_error(self._lib))
         return Solver._view(self._lib, ctx, self.shapes[i], self.dtype, self.device, self.stream,
                             self._prm[i])
 
     def iterate(self, n: int = 1):
-        L.check(self._lib.muffin_batch_iterate(self._b, int(n)), "muffin_batch_iterate", self._lib)
+        L.check(self._lib.muffin_iterate(self._b, int(n)), "muffin_iterate", self._lib)
         return self
 
     def set_graph(self, enable: bool = True):
-        L.check(self._lib.muffin_batch_set_graph(self._b, 1 if enable else 0), "muffin_batch_set_graph",
-                self._lib)
+        L.check(self._lib.muffin_set_graph(self._b, 1 if enable else 0), "muffin_set_graph", self._lib)
 
     @property
     def launches(self) -> int:
         """Grouped launches per pass."""
         return self._lib.muffin_batch_launches(self._b)
 
+    @property
+    def iterations(self) -> int:
+        """Batch passes run since setup."""
+        return self._lib.muffin_iterations(self._b)
+
     def autotune(self, reps: int = 10):
         L.check(self._lib.muffin_batch_autotune(self._b, int(reps)), "muffin_batch_autotune", self._lib)
 
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:
-            self._lib.muffin_batch_destroy(self._b)
+            self._lib.muffin_destroy(self._b)
             self._b = c_void_p()
 
     def __del__(self):

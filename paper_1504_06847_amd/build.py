@@ -45,7 +45,19 @@ def _run(cmd, verbose):
     return r
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """An object older than its source or than any header it may include."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    deps += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every translation unit (with ``incremental``, only those whose
+    object is older than the source or a header) and link libmuffin.so."""
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     gxx = shutil.which("g++") or "g++"
     os.makedirs(BUILD, exist_ok=True)
@@ -54,13 +66,17 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     objs = []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        cmds.append([hipcc, *HIP_FLAGS, *incs, "-c", os.path.join(CSRC, src), "-o", obj])
+        path = os.path.join(CSRC, src)
+        if not incremental or _stale(obj, path):
+            cmds.append([hipcc, *HIP_FLAGS, *incs, "-c", path, "-o", obj])
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        cmds.append([gxx, *HOST_FLAGS, *incs, "-c", os.path.join(CSRC, src), "-o", obj])
+        path = os.path.join(CSRC, src)
+        if not incremental or _stale(obj, path):
+            cmds.append([gxx, *HOST_FLAGS, *incs, "-c", path, "-o", obj])
         objs.append(obj)
-    jobs = jobs or min(len(cmds), os.cpu_count() or 4)
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 4))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for r in ex.map(lambda c: _run(c, verbose), cmds):
             if r.stderr and verbose:
@@ -76,8 +92,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only units older than their source or a header")
     a = ap.parse_args(argv)
-    print(build(a.jobs, a.verbose))
+    print(build(a.jobs, a.verbose, a.incremental))
 
 
 if __name__ == "__main__":

@@ -306,26 +306,43 @@ size_t state_array_bytes(const muffin_ctx* c) {
 // With gy_out, the cotangent of the dirty images goes there too: Y enters
 // every pass through H^T Y in step I's right-hand side (eq. matB), so
 // dL/dY = H sum_k B-bar_k.
+// FP64 block sums of one adjoint launch
+size_t grad_nparts(const muffin_ctx* c) {
+    const long npix = long(c->shape.ny) * c->shape.nx;
+    return size_t(npix / 64 > 8192 ? npix / 64 : 8192);
+}
+
+}  // namespace
+
+namespace muffin {
+
+size_t grad_scratch_bytes(const muffin_ctx* c, int K, int C, bool dirty) {
+    if (C > K) C = K;
+    const int nseg = (K + C - 1) / C;
+    const int nbuf = nseg > 1 ? 2 : 1;
+    const size_t n_arrays = size_t(nseg) * kNumState + size_t(nbuf) * C * (kNumState + 1) + (kNumState + 1) +
+                            (kNumState + 2) + (dirty ? 1 : 0);
+    return n_arrays * state_array_bytes(c) + 2 * grad_nparts(c) * GRAD_NQ * 8 + GRAD_NQ * 8;
+}
+
+// The reverse sweep in the device scratch g (at least grad_scratch_bytes,
+// 256-B aligned; every part of it that is read is written first).
 int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, double* loss,
-               double grad[7], void* gy_out = nullptr) {
+               double grad[7], void* gy_out, char* g, size_t g_bytes) {
     const muffin_shape& s = c->shape;
+    const size_t need = grad_scratch_bytes(c, K, C, gy_out != nullptr);
+    if (!g || g_bytes < need) {
+        set_error("the reverse sweep of %d passes with checkpoints every %d needs %zu bytes of scratch "
+                  "(muffin_grad_workspace_bytes), %zu given (muffin_set_grad_workspace)",
+                  K, C, need, g ? g_bytes : size_t(0));
+        return MUFFIN_EWORKSPACE;
+    }
     if (C > K) C = K;
     const int nseg = (K + C - 1) / C;
     const size_t ab = state_array_bytes(c), nb = voxels(s) * elem_size(s);
     const long npix = long(s.ny) * s.nx;
-    const size_t nparts = size_t(npix / 64 > 8192 ? npix / 64 : 8192);
+    const size_t nparts = grad_nparts(c);
     const int nbuf = nseg > 1 ? 2 : 1;
-    const size_t n_arrays = size_t(nseg) * kNumState + size_t(nbuf) * C * (kNumState + 1) + (kNumState + 1) +
-                            (kNumState + 2) + (gy_out ? 1 : 0);
-    const size_t need = n_arrays * ab + 2 * nparts * GRAD_NQ * 8 + kAlign;
-    if (c->grad_bytes < need) {
-        if (c->grad_buf) HIP_TRY(hipFree(c->grad_buf));
-        c->grad_buf = nullptr;
-        c->grad_bytes = 0;
-        HIP_TRY(hipMalloc(&c->grad_buf, need));
-        c->grad_bytes = need;
-    }
-    char* g = (char*)c->grad_buf;
     auto ckpt = [&](int seg, int i) { return g + (size_t(seg) * kNumState + i) * ab; };
     char* seg0 = g + size_t(nseg) * kNumState * ab;
     // store b, pass j of the segment, array i (i = 4: X)
@@ -496,7 +513,26 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     return MUFFIN_OK;
 }
 
-}  // namespace
+// the checks shared by the gradient entry points
+int grad_args(const muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, const void* out,
+              const char* what) {
+    if (int rc = check_ctx(c)) return rc;
+    if (c->lay.n_w) {
+        set_error("%s: not built for a spatial dictionary with wavelet bases (n_s = %d)", what, c->params.n_s);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    if (K < 1 || ckpt_every < 1) {
+        set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
+        return MUFFIN_EINVAL;
+    }
+    if (!sky_or_gx || !out || (mode != MUFFIN_MODE_MSE && mode != MUFFIN_MODE_VJP)) {
+        set_error("%s: sky_or_gx and the output must be non-NULL, mode MSE or VJP", what);
+        return MUFFIN_EINVAL;
+    }
+    return MUFFIN_OK;
+}
+
+}  // namespace muffin
 
 namespace muffin {
 int refresh_brest(muffin_ctx* c) { return recompute_brest(c); }
@@ -542,6 +578,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     c->fused = lay.n_w ? 0 : kDefaultFused;    // the fused kernel serves the Dirac basis alone
     c->zvalid = 0;
     c->version = 0;
+    c->batch = nullptr;
     c->grad_buf = nullptr;
     c->grad_bytes = 0;
     c->use_graph = 0;
@@ -608,6 +645,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
 }
 
 int muffin_iterate(muffin_ctx* c, int n_iter) {
+    if (c && c->batch) return batch_iterate(c->batch, n_iter);
     if (int rc = check_ctx(c)) return rc;
     if (n_iter < 0) { set_error("n_iter = %d < 0", n_iter); return MUFFIN_EINVAL; }
     for (int i = 0; i < n_iter; ++i) {
@@ -794,7 +832,10 @@ int muffin_reset(muffin_ctx* c) {
     return zero_state(c);
 }
 
-int muffin_iterations(const muffin_ctx* c) { return c ? c->iters : -1; }
+int muffin_iterations(const muffin_ctx* c) {
+    if (!c) return -1;
+    return c->batch ? batch_iterations(c->batch) : c->iters;
+}
 
 int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, int cap) {
     if (int rc = check_ctx(c)) return rc;
@@ -856,18 +897,10 @@ int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, in
 
 int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode,
                 double* loss, double grad[3]) {
-    if (int rc = check_ctx(c)) return rc;
-    if (int rc = no_wavelets(c, "muffin_grad")) return rc;
-    if (K < 1 || ckpt_every < 1) {
-        set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
-        return MUFFIN_EINVAL;
-    }
-    if (!sky_or_gx || !grad || (mode != MUFFIN_MODE_MSE && mode != MUFFIN_MODE_VJP)) {
-        set_error("muffin_grad: sky_or_gx and grad must be non-NULL, mode MSE or VJP");
-        return MUFFIN_EINVAL;
-    }
+    if (int rc = grad_args(c, K, ckpt_every, sky_or_gx, mode, grad, "muffin_grad")) return rc;
     double full[7];
-    const int rc = grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, full);
+    const int rc = grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, full, nullptr, (char*)c->grad_buf,
+                              c->grad_bytes);
     if (rc) return rc;
     grad[0] = full[1];
     grad[1] = full[2];
@@ -877,33 +910,31 @@ int muffin_grad(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int
 
 int muffin_grad_dirty(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, double* loss,
                       void* gy_out) {
-    if (int rc = check_ctx(c)) return rc;
-    if (int rc = no_wavelets(c, "muffin_grad_dirty")) return rc;
-    if (K < 1 || ckpt_every < 1) {
-        set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
-        return MUFFIN_EINVAL;
-    }
-    if (!sky_or_gx || !gy_out || (mode != MUFFIN_MODE_MSE && mode != MUFFIN_MODE_VJP)) {
-        set_error("muffin_grad_dirty: sky_or_gx and gy_out must be non-NULL, mode MSE or VJP");
-        return MUFFIN_EINVAL;
-    }
+    if (int rc = grad_args(c, K, ckpt_every, sky_or_gx, mode, gy_out, "muffin_grad_dirty")) return rc;
     double full[7];
-    return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, full, gy_out);
+    return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, full, gy_out, (char*)c->grad_buf, c->grad_bytes);
 }
 
 int muffin_grad_params(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, double* loss,
                        double grad[7]) {
+    if (int rc = grad_args(c, K, ckpt_every, sky_or_gx, mode, grad, "muffin_grad_params")) return rc;
+    return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, grad, nullptr, (char*)c->grad_buf, c->grad_bytes);
+}
+
+size_t muffin_grad_workspace_bytes(const muffin_ctx* c, int K, int ckpt_every, int dirty) {
+    if (check_ctx(c) != MUFFIN_OK || K < 1 || ckpt_every < 1) return 0;
+    return grad_scratch_bytes(c, K, ckpt_every, dirty != 0);
+}
+
+int muffin_set_grad_workspace(muffin_ctx* c, void* ws, size_t bytes) {
     if (int rc = check_ctx(c)) return rc;
-    if (int rc = no_wavelets(c, "muffin_grad_params")) return rc;
-    if (K < 1 || ckpt_every < 1) {
-        set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
-        return MUFFIN_EINVAL;
+    if (ws && (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) {
+        set_error("the gradient workspace must be %zu-byte aligned", kAlign);
+        return MUFFIN_EWORKSPACE;
     }
-    if (!sky_or_gx || !grad || (mode != MUFFIN_MODE_MSE && mode != MUFFIN_MODE_VJP)) {
-        set_error("muffin_grad_params: sky_or_gx and grad must be non-NULL, mode MSE or VJP");
-        return MUFFIN_EINVAL;
-    }
-    return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, grad);
+    c->grad_buf = ws;
+    c->grad_bytes = ws ? bytes : 0;
+    return MUFFIN_OK;
 }
 
 int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
@@ -1024,6 +1055,7 @@ int muffin_fused_available(const muffin_ctx* c) {
 }
 
 int muffin_set_graph(muffin_ctx* c, int enable) {
+    if (c && c->batch) return batch_set_graph(c->batch, enable);
     if (int rc = check_ctx(c)) return rc;
     c->use_graph = enable ? 1 : 0;
     return MUFFIN_OK;
@@ -1031,9 +1063,9 @@ int muffin_set_graph(muffin_ctx* c, int enable) {
 
 int muffin_destroy(muffin_ctx* c) {
     if (!c) return MUFFIN_OK;
+    if (c->batch) return batch_destroy(c);
     drop_graphs(c);
     if (c->cap) hipStreamDestroy(c->cap);
-    if (c->grad_buf) hipFree(c->grad_buf);
     delete c;
     return MUFFIN_OK;
 }

@@ -57,6 +57,7 @@ struct muffin_batch {
     int use_graph;
     hipStream_t cap;
     hipGraphExec_t gexec;
+    int passes;                            // batch passes run since setup
 };
 
 namespace {
@@ -276,9 +277,13 @@ int capture(muffin_batch* b) {
     return MUFFIN_OK;
 }
 
-int check_batch(const muffin_batch* b) {
-    if (!b) { set_error("batch is NULL"); return MUFFIN_EINVAL; }
-    return MUFFIN_OK;
+// the batch of a batch context (NULL, with the error set, for anything else)
+muffin_batch* batch_of(const muffin_ctx* c) {
+    if (!c || !c->batch) {
+        set_error("not a batch context (muffin_setup_batch)");
+        return nullptr;
+    }
+    return c->batch;
 }
 
 int check_shapes(int n, const muffin_shape* shapes, const muffin_params* params) {
@@ -341,7 +346,7 @@ int choose_pass_form(muffin_batch* b, int reps) {
     double t[2] = {0.0, 0.0};
     for (int form = 0; form < 2 && rc == MUFFIN_OK; ++form) {
         if ((rc = set_form(form == 1)) != MUFFIN_OK || (rc = restore()) != MUFFIN_OK) break;
-        if ((rc = muffin_batch_iterate(b, 1)) != MUFFIN_OK) break;       // warm-up pass
+        if ((rc = batch_iterate(b, 1)) != MUFFIN_OK) break;       // warm-up pass
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
             set_error("batch autotune: event creation failed");
@@ -349,7 +354,7 @@ int choose_pass_form(muffin_batch* b, int reps) {
             break;
         }
         hipError_t e = hipEventRecord(e0, b->stream);
-        if (e == hipSuccess && (rc = muffin_batch_iterate(b, reps)) != MUFFIN_OK) e = hipSuccess;
+        if (e == hipSuccess && (rc = batch_iterate(b, reps)) != MUFFIN_OK) e = hipSuccess;
         if (rc == MUFFIN_OK && e == hipSuccess) e = hipEventRecord(e1, b->stream);
         if (rc == MUFFIN_OK && e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -374,70 +379,9 @@ int choose_pass_form(muffin_batch* b, int reps) {
 
 }  // namespace
 
-extern "C" {
+namespace muffin {
 
-size_t muffin_batch_workspace_bytes(int n, const muffin_shape* shapes, const muffin_params* params) {
-    if (check_shapes(n, shapes, params) != MUFFIN_OK) return 0;
-    size_t total = 0;
-    for (int i = 0; i < n; ++i) total += align_up(muffin_workspace_bytes(&shapes[i], &params[i]));
-    return total + desc_region_bytes(n);
-}
-
-int muffin_batch_setup(muffin_batch** out, int n, const muffin_shape* shapes, const muffin_params* params,
-                       const void* const* psf, const void* const* dirty, void* workspace, size_t ws_bytes,
-                       void* stream) {
-    if (!out) { set_error("batch output pointer is NULL"); return MUFFIN_EINVAL; }
-    *out = nullptr;
-    if (int rc = check_shapes(n, shapes, params)) return rc;
-    if (!psf || !dirty || !workspace) {
-        set_error("psf, dirty and workspace must be non-NULL");
-        return MUFFIN_EINVAL;
-    }
-    const size_t need = muffin_batch_workspace_bytes(n, shapes, params);
-    if (ws_bytes < need) {
-        set_error("batch workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, need);
-        return MUFFIN_EWORKSPACE;
-    }
-    if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0) {
-        set_error("workspace must be %zu-byte aligned", kAlign);
-        return MUFFIN_EWORKSPACE;
-    }
-    muffin_batch* b = new (std::nothrow) muffin_batch();
-    if (!b) { set_error("out of host memory"); return MUFFIN_EDEVICE; }
-    b->n = n;
-    b->dtype = shapes[0].dtype;
-    b->stream = (hipStream_t)stream;
-    b->ws = (char*)workspace;
-    b->ws_bytes = ws_bytes;
-    b->built = false;
-    b->use_graph = 0;
-    b->cap = nullptr;
-    b->gexec = nullptr;
-    size_t off = 0;
-    for (int i = 0; i < n; ++i) {
-        const size_t wi = muffin_workspace_bytes(&shapes[i], &params[i]);
-        muffin_ctx* c = nullptr;
-        const int rc = muffin_setup(&c, &shapes[i], &params[i], psf[i], dirty[i], b->ws + off, wi, stream);
-        if (rc != MUFFIN_OK) {
-            muffin_batch_destroy(b);
-            return rc;
-        }
-        b->cubes.push_back(c);
-        off += align_up(wi);
-    }
-    b->desc = b->ws + off;
-    b->host_desc.assign(desc_region_bytes(n), 0);
-    b->seen.assign(n, 0);
-    if (int rc = rebuild(b)) {
-        muffin_batch_destroy(b);
-        return rc;
-    }
-    *out = b;
-    return MUFFIN_OK;
-}
-
-int muffin_batch_iterate(muffin_batch* b, int n_iter) {
-    if (int rc = check_batch(b)) return rc;
+int batch_iterate(muffin_batch* b, int n_iter) {
     if (n_iter < 0) { set_error("n_iter = %d < 0", n_iter); return MUFFIN_EINVAL; }
     if (n_iter == 0) return MUFFIN_OK;
     // a fused cube's pass starts from Z (the row spectra of B_rest), the
@@ -463,17 +407,116 @@ int muffin_batch_iterate(muffin_batch* b, int n_iter) {
             c->iters++;
             c->zvalid = fused_pass(c) ? 1 : 0;
         }
+        b->passes++;
     }
     return MUFFIN_OK;
 }
 
-muffin_ctx* muffin_batch_cube(muffin_batch* b, int i) {
-    if (!b || i < 0 || i >= b->n) return nullptr;
+int batch_set_graph(muffin_batch* b, int enable) {
+    b->use_graph = enable ? 1 : 0;
+    return MUFFIN_OK;
+}
+
+int batch_iterations(const muffin_batch* b) { return b->passes; }
+
+int batch_destroy(muffin_ctx* c) {
+    muffin_batch* b = c->batch;
+    if (b) {
+        drop_graph(b);
+        if (b->cap) hipStreamDestroy(b->cap);
+        for (muffin_ctx* q : b->cubes) muffin_destroy(q);
+        delete b;
+    }
+    delete c;
+    return MUFFIN_OK;
+}
+
+}  // namespace muffin
+
+extern "C" {
+
+size_t muffin_batch_workspace_bytes(int n, const muffin_shape* shapes, const muffin_params* params) {
+    if (check_shapes(n, shapes, params) != MUFFIN_OK) return 0;
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) total += align_up(muffin_workspace_bytes(&shapes[i], &params[i]));
+    return total + desc_region_bytes(n);
+}
+
+int muffin_setup_batch(muffin_ctx** out, int n, const muffin_shape* shapes, const muffin_params* params,
+                       const void* const* psf, const void* const* dirty, void* workspace, size_t ws_bytes,
+                       void* stream) {
+    if (!out) { set_error("ctx output pointer is NULL"); return MUFFIN_EINVAL; }
+    *out = nullptr;
+    if (int rc = check_shapes(n, shapes, params)) return rc;
+    if (!psf || !dirty || !workspace) {
+        set_error("psf, dirty and workspace must be non-NULL");
+        return MUFFIN_EINVAL;
+    }
+    const size_t need = muffin_batch_workspace_bytes(n, shapes, params);
+    if (ws_bytes < need) {
+        set_error("batch workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, need);
+        return MUFFIN_EWORKSPACE;
+    }
+    if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0) {
+        set_error("workspace must be %zu-byte aligned", kAlign);
+        return MUFFIN_EWORKSPACE;
+    }
+    muffin_ctx* w = new (std::nothrow) muffin_ctx();
+    muffin_batch* b = w ? new (std::nothrow) muffin_batch() : nullptr;
+    if (!b) {
+        delete w;
+        set_error("out of host memory");
+        return MUFFIN_EDEVICE;
+    }
+    w->batch = b;
+    w->shape = shapes[0];
+    w->stream = (hipStream_t)stream;
+    b->n = n;
+    b->dtype = shapes[0].dtype;
+    b->stream = (hipStream_t)stream;
+    b->ws = (char*)workspace;
+    b->ws_bytes = ws_bytes;
+    b->built = false;
+    b->use_graph = 0;
+    b->cap = nullptr;
+    b->gexec = nullptr;
+    b->passes = 0;
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t wi = muffin_workspace_bytes(&shapes[i], &params[i]);
+        muffin_ctx* c = nullptr;
+        const int rc = muffin_setup(&c, &shapes[i], &params[i], psf[i], dirty[i], b->ws + off, wi, stream);
+        if (rc != MUFFIN_OK) {
+            batch_destroy(w);
+            return rc;
+        }
+        b->cubes.push_back(c);
+        off += align_up(wi);
+    }
+    b->desc = b->ws + off;
+    b->host_desc.assign(desc_region_bytes(n), 0);
+    b->seen.assign(n, 0);
+    if (int rc = rebuild(b)) {
+        batch_destroy(w);
+        return rc;
+    }
+    *out = w;
+    return MUFFIN_OK;
+}
+
+muffin_ctx* muffin_batch_cube(muffin_ctx* c, int i) {
+    muffin_batch* b = batch_of(c);
+    if (!b) return nullptr;
+    if (i < 0 || i >= b->n) {
+        set_error("cube %d outside the batch of %d", i, b->n);
+        return nullptr;
+    }
     return b->cubes[i];
 }
 
-int muffin_batch_autotune(muffin_batch* b, int reps) {
-    if (int rc = check_batch(b)) return rc;
+int muffin_batch_autotune(muffin_ctx* ctx, int reps) {
+    muffin_batch* b = batch_of(ctx);
+    if (!b) return MUFFIN_EINVAL;
     if (reps < 1) { set_error("reps = %d < 1", reps); return MUFFIN_EINVAL; }
     // each cube's own schedule first (which pass form it joins), then the
     // tile schedule of every grouped transform launch
@@ -526,21 +569,9 @@ int muffin_batch_autotune(muffin_batch* b, int reps) {
     return choose_pass_form(b, reps);
 }
 
-int muffin_batch_set_graph(muffin_batch* b, int enable) {
-    if (int rc = check_batch(b)) return rc;
-    b->use_graph = enable ? 1 : 0;
-    return MUFFIN_OK;
-}
-
-int muffin_batch_launches(const muffin_batch* b) { return b ? int(b->classes.size()) : -1; }
-
-int muffin_batch_destroy(muffin_batch* b) {
-    if (!b) return MUFFIN_OK;
-    drop_graph(b);
-    if (b->cap) hipStreamDestroy(b->cap);
-    for (muffin_ctx* c : b->cubes) muffin_destroy(c);
-    delete b;
-    return MUFFIN_OK;
+int muffin_batch_launches(const muffin_ctx* c) {
+    const muffin_batch* b = batch_of(c);
+    return b ? int(b->classes.size()) : -1;
 }
 
 }  // extern "C"

@@ -7,7 +7,12 @@
 #include "muffin_kernels.hpp"
 #include "muffin_layout.hpp"
 
+struct muffin_batch;
+
 struct muffin_ctx {
+    // a batch context (muffin_setup_batch) holds its cubes here and none of
+    // the per-cube fields below; a cube context has batch == nullptr
+    muffin_batch* batch;
     muffin_shape shape;
     muffin_params params;
     hipStream_t stream;
@@ -27,7 +32,7 @@ struct muffin_ctx {
     // bumped whenever the arrays, parameters or schedules of the next pass
     // change (a batch rebuilds its launch descriptors then)
     unsigned version;
-    // scratch owned by the library (reverse sweep of muffin_grad)
+    // the caller's workspace of the reverse sweep (muffin_set_grad_workspace)
     void* grad_buf;
     size_t grad_bytes;
     // graph replay of one pass: captured on a private stream, one executable
@@ -94,9 +99,33 @@ int dict_pass(muffin_ctx* c);
 int dict_brest(muffin_ctx* c);
 int dict_reencode(muffin_ctx* c, double ratio, double tau);
 
+// a cube context (not NULL, not a batch context)
 inline int check_ctx(const muffin_ctx* c) {
     if (!c) { set_error("context is NULL"); return MUFFIN_EINVAL; }
+    if (c->batch) {
+        set_error("a batch context: this call works on one cube (muffin_batch_cube)");
+        return MUFFIN_EINVAL;
+    }
     return MUFFIN_OK;
 }
+
+// the reverse sweep of the gradient entry points (muffin_api.cpp): bytes of
+// its device scratch for K passes with checkpoints every C (one more cube
+// for the cotangent of the dirty images), and the sweep itself with its
+// scratch at g (g_bytes of it; MUFFIN_EWORKSPACE when short); grad receives
+// the derivatives along (mu_eps, mu_s, mu_nu, rho_P, rho_T, rho_V, rho_S)
+size_t grad_scratch_bytes(const muffin_ctx* c, int K, int C, bool dirty);
+int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, double* loss, double grad[7],
+               void* gy_out, char* g, size_t g_bytes);
+// argument checks of the gradient entry points (`out`: their output pointer)
+int grad_args(const muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, const void* out,
+              const char* what);
+
+// the batch calls behind muffin_iterate, muffin_set_graph, muffin_iterations
+// and muffin_destroy on a batch context (muffin_batch.cpp)
+int batch_iterate(muffin_batch* b, int n_iter);
+int batch_set_graph(muffin_batch* b, int enable);
+int batch_iterations(const muffin_batch* b);
+int batch_destroy(muffin_ctx* c);
 
 }  // namespace muffin

@@ -78,6 +78,8 @@ SIGNATURES = [
     ("muffin_grad_params", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double),
                                    POINTER(c_double)]),
     ("muffin_grad_dirty", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double), c_void_p]),
+    ("muffin_grad_workspace_bytes", c_size_t, [c_void_p, c_int, c_int, c_int]),
+    ("muffin_set_grad_workspace", c_int, [c_void_p, c_void_p, c_size_t]),
     ("muffin_state_bytes", c_size_t, [c_void_p]),
     ("muffin_get_state", c_int, [c_void_p, c_void_p]),
     ("muffin_set_state", c_int, [c_void_p, c_void_p]),
@@ -90,14 +92,11 @@ SIGNATURES = [
     ("muffin_get_schedule", c_int, [c_void_p, POINTER(c_int)]),
     ("muffin_fused_available", c_int, [c_void_p]),
     ("muffin_batch_workspace_bytes", c_size_t, [c_int, POINTER(MuffinShape), POINTER(MuffinParams)]),
-    ("muffin_batch_setup", c_int, [POINTER(c_void_p), c_int, POINTER(MuffinShape), POINTER(MuffinParams),
+    ("muffin_setup_batch", c_int, [POINTER(c_void_p), c_int, POINTER(MuffinShape), POINTER(MuffinParams),
                                    POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_size_t, c_void_p]),
-    ("muffin_batch_iterate", c_int, [c_void_p, c_int]),
     ("muffin_batch_cube", c_void_p, [c_void_p, c_int]),
     ("muffin_batch_autotune", c_int, [c_void_p, c_int]),
-    ("muffin_batch_set_graph", c_int, [c_void_p, c_int]),
     ("muffin_batch_launches", c_int, [c_void_p]),
-    ("muffin_batch_destroy", c_int, [c_void_p]),
     ("muffin_profile", c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_char_p), c_int]),
     ("muffin_destroy", c_int, [c_void_p]),
     ("muffin_last_error", c_char_p, []),

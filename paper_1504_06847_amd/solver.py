@@ -37,6 +37,24 @@ def _store_cache(path, table):
     os.replace(tmp, path)
 
 
+def best_ckpt_every(K: int, budget: float, nbytes) -> int:
+    """Checkpoint spacing C of a reverse sweep of K passes: among the C in
+    1..K whose scratch nbytes(C) fits in ``budget``, the one that recomputes
+    the fewest passes ((ceil(K / C) - 1) C: every segment but the last runs
+    twice; C = K recomputes none), the smaller scratch on a tie; 1 when
+    none fits."""
+    K = max(1, int(K))
+    best = None
+    for C in range(1, K + 1):
+        need = nbytes(C)
+        if need > budget:
+            continue
+        key = ((-(-K // C)) - 1) * C, need
+        if best is None or key < best[0]:
+            best = (key, C)
+    return 1 if best is None else best[1]
+
+
 def _as_cube(a, dtype, device):
     t = a if isinstance(a, torch.Tensor) else torch.as_tensor(a)
     t = t.to(device=device, dtype=dtype).contiguous()
@@ -249,25 +267,39 @@ class Solver:
         L.check(self._lib.muffin_reset(self._ctx), "muffin_reset", self._lib)
 
     # -------------------------------------------------------------- gradients
-    def sweep_ckpt_every(self, K: int, extra_cubes: int = 0, fraction: float = 0.5) -> int:
-        """Checkpoint spacing for a reverse sweep of K passes: the largest
-        whose scratch (4 ceil(K/C) + 10 C + 11 cubes, 4 + 5 K + 11 for C >= K,
-        plus ``extra_cubes``) fits in ``fraction`` of the device's free
-        memory.  The larger the spacing the fewer passes are recomputed;
-        C = K recomputes none."""
-        K = max(1, int(K))
-        free, _ = torch.cuda.mem_get_info(self.device)
-        cube = 1
-        for n in self.shape:
-            cube *= int(n)
-        cube *= torch.empty((), dtype=self.dtype).element_size()
-        budget = fraction * free
-        for C in range(K, 0, -1):
-            nseg = -(-K // C)
-            cubes = 4 * nseg + (2 if nseg > 1 else 1) * C * 5 + 11 + extra_cubes
-            if cubes * cube <= budget:
-                return C
-        return 1
+    def grad_workspace_bytes(self, K: int, ckpt_every: int, dirty: bool = False) -> int:
+        """Device bytes of the reverse sweep's scratch (muffin_grad_workspace_bytes)."""
+        return int(self._lib.muffin_grad_workspace_bytes(self._ctx, int(K), int(ckpt_every), 1 if dirty else 0))
+
+    def sweep_ckpt_every(self, K: int, dirty: bool = False, fraction: float = 0.5,
+                         budget: int | None = None) -> int:
+        """Checkpoint spacing for a reverse sweep of K passes
+        (``best_ckpt_every``) within ``budget`` bytes, by default ``fraction``
+        of the device memory available: free, plus what torch's allocator
+        holds unused (the sweep's workspace comes from it)."""
+        if budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            cached = torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+            budget = fraction * (free + max(0, cached))
+        return best_ckpt_every(K, budget, lambda C: self.grad_workspace_bytes(K, C, dirty))
+
+    def _sweep(self, name, K, ckpt_every, dirty, call):
+        """Run one reverse sweep in a workspace allocated for it (released
+        to torch's allocator afterwards)."""
+        nbytes = self.grad_workspace_bytes(K, ckpt_every, dirty)
+        if nbytes == 0:
+            raise L.MuffinError(L.MUFFIN_EINVAL, "muffin_grad_workspace_bytes", L.last_error(self._lib))
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+        L.check(self._lib.muffin_set_grad_workspace(self._ctx, c_void_p(ptr), nbytes),
+                "muffin_set_grad_workspace", self._lib)
+        try:
+            with torch.cuda.stream(self.stream):
+                rc = call()
+            L.check(rc, name, self._lib)
+        finally:
+            self._lib.muffin_set_grad_workspace(self._ctx, None, 0)
+            del ws
 
     def grad(self, K: int, *, sky=None, gx=None, ckpt_every: int | None = None):
         """Gradient with respect to (mu_s, mu_nu, rho) of a loss of X^K, the X
@@ -288,10 +320,9 @@ class Solver:
         mode = L.MUFFIN_MODE_MSE if sky is not None else L.MUFFIN_MODE_VJP
         loss = c_double()
         g = (c_double * 3)()
-        with torch.cuda.stream(self.stream):
-            rc = self._lib.muffin_grad(self._ctx, int(K), int(ckpt_every), c_void_p(ref.data_ptr()), mode,
-                                       byref(loss), g)
-        L.check(rc, "muffin_grad", self._lib)
+        self._sweep("muffin_grad", K, ckpt_every, False,
+                    lambda: self._lib.muffin_grad(self._ctx, int(K), int(ckpt_every), c_void_p(ref.data_ptr()),
+                                                  mode, byref(loss), g))
         return loss.value, np.array([g[0], g[1], g[2]])
 
     GRAD_PARAMS = ("mu_eps", "mu_s", "mu_nu", "rho_P", "rho_T", "rho_V", "rho_S")
@@ -309,17 +340,16 @@ class Solver:
         mode = L.MUFFIN_MODE_MSE if sky is not None else L.MUFFIN_MODE_VJP
         loss = c_double()
         g = (c_double * 7)()
-        with torch.cuda.stream(self.stream):
-            rc = self._lib.muffin_grad_params(self._ctx, int(K), int(ckpt_every), c_void_p(ref.data_ptr()), mode,
-                                              byref(loss), g)
-        L.check(rc, "muffin_grad_params", self._lib)
+        self._sweep("muffin_grad_params", K, ckpt_every, False,
+                    lambda: self._lib.muffin_grad_params(self._ctx, int(K), int(ckpt_every),
+                                                         c_void_p(ref.data_ptr()), mode, byref(loss), g))
         return loss.value, {n: g[i] for i, n in enumerate(self.GRAD_PARAMS)}
 
     def grad_dirty(self, K: int, *, sky=None, gx=None, ckpt_every: int | None = None):
         """Cotangent of the dirty images: returns (loss, dL/dY) with dL/dY a
         cube on the device (muffin_grad_dirty)."""
         if ckpt_every is None:
-            ckpt_every = self.sweep_ckpt_every(K, extra_cubes=2)
+            ckpt_every = self.sweep_ckpt_every(K, dirty=True)
         if (sky is None) == (gx is None):
             raise ValueError("give exactly one of sky and gx")
         ref = _as_cube(sky if sky is not None else gx, self.dtype, self.device)
@@ -328,10 +358,10 @@ class Solver:
         mode = L.MUFFIN_MODE_MSE if sky is not None else L.MUFFIN_MODE_VJP
         loss = c_double()
         gy = self._empty_cube()
-        with torch.cuda.stream(self.stream):
-            rc = self._lib.muffin_grad_dirty(self._ctx, int(K), int(ckpt_every), c_void_p(ref.data_ptr()), mode,
-                                             byref(loss), c_void_p(gy.data_ptr()))
-        L.check(rc, "muffin_grad_dirty", self._lib)
+        self._sweep("muffin_grad_dirty", K, ckpt_every, True,
+                    lambda: self._lib.muffin_grad_dirty(self._ctx, int(K), int(ckpt_every),
+                                                        c_void_p(ref.data_ptr()), mode, byref(loss),
+                                                        c_void_p(gy.data_ptr())))
         return loss.value, gy
 
     # -------------------------------------------------------------- timing

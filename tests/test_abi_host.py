@@ -164,17 +164,31 @@ def test_batch_validation_without_device(lib):
     assert lib.muffin_batch_workspace_bytes(2, bad, prm) == 0
     b = ctypes.c_void_p()
     dummy = (ctypes.c_void_p * n)(0x1000, 0x1000, 0x1000)
-    assert lib.muffin_batch_setup(ctypes.byref(b), 0, shapes, prm, dummy, dummy,
+    assert lib.muffin_setup_batch(ctypes.byref(b), 0, shapes, prm, dummy, dummy,
                                   ctypes.c_void_p(0x1000), 1 << 40, None) == -1
-    assert lib.muffin_batch_setup(ctypes.byref(b), n, shapes, prm, dummy, dummy,
+    assert lib.muffin_setup_batch(ctypes.byref(b), n, shapes, prm, dummy, dummy,
                                   ctypes.c_void_p(0x1000), 16, None) == -3
-    assert lib.muffin_batch_setup(ctypes.byref(b), n, shapes, prm, None, dummy,
+    assert lib.muffin_setup_batch(ctypes.byref(b), n, shapes, prm, None, dummy,
+                                  ctypes.c_void_p(0x1000), 1 << 40, None) == -1
+    assert lib.muffin_setup_batch(None, n, shapes, prm, dummy, dummy,
                                   ctypes.c_void_p(0x1000), 1 << 40, None) == -1
     assert b.value is None
-    assert lib.muffin_batch_iterate(None, 1) == -1
+    assert lib.muffin_iterate(None, 1) == -1
     assert lib.muffin_batch_cube(None, 0) is None
+    assert "batch context" in L.last_error(lib)
+    assert lib.muffin_batch_autotune(None, 1) == -1
     assert lib.muffin_batch_launches(None) == -1
-    assert lib.muffin_batch_destroy(None) == 0
+    assert lib.muffin_destroy(None) == 0
+
+
+def test_gradient_workspace_calls_without_device(lib):
+    """The reverse sweep's scratch size and the workspace calls on a NULL
+    context (no device needed)."""
+    assert lib.muffin_grad_workspace_bytes(None, 20, 5, 0) == 0
+    assert lib.muffin_set_grad_workspace(None, None, 0) == -1
+    g = (ctypes.c_double * 3)()
+    loss = ctypes.c_double()
+    assert lib.muffin_grad(None, 20, 5, ctypes.c_void_p(0x1000), 0, ctypes.byref(loss), g) == -1
 
 
 def test_schedule_calls_reject_bad_arguments(lib):
@@ -221,3 +235,23 @@ def test_workspace_grows_by_one_cube_per_wavelet_basis(lib):
     extra = 8 * (V + V // 4 + V // 16 + V // 64)
     assert extra <= nine - one <= extra + 40 * 256
 
+
+
+def test_checkpoint_spacing_minimises_recomputed_passes():
+    """Solver's spacing rule on the scratch sizes the header documents
+    (4 ceil(K/C) + 10 C + 11 cubes, 4 + 5 K + 11 at C = K): the spacing with
+    the fewest recomputed passes among those that fit, not the largest."""
+    from paper_1504_06847_amd.solver import best_ckpt_every
+
+    def cubes(K, C):
+        n = -(-K // C)
+        return 4 + 5 * K + 11 if n == 1 else 4 * n + 10 * C + 11
+
+    # K = 20, room for 105 cubes: C = 8 (103 cubes) recomputes 16 passes,
+    # C = 7 (93 cubes) 14
+    assert best_ckpt_every(20, 105, lambda C: cubes(20, C)) == 7
+    # K = 120, room for 600 cubes: C = 54 would recompute 108, C = 40 only 80
+    assert best_ckpt_every(120, 600, lambda C: cubes(120, C)) == 40
+    # everything fits: no recompute
+    assert best_ckpt_every(20, 1e9, lambda C: cubes(20, C)) == 20
+    assert best_ckpt_every(20, 10, lambda C: cubes(20, C)) == 1

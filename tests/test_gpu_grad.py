@@ -66,19 +66,20 @@ def test_checkpoint_spacing_does_not_change_the_gradient(gpu_lib):
 
 
 def test_default_checkpoint_spacing_from_free_memory(gpu_lib):
-    """The default spacing is the largest whose scratch fits the given share
-    of free device memory: K for a small cube, smaller for a tiny share, and
-    the gradient at the default equals the one at that spacing."""
+    """The default spacing recomputes the fewest passes within the memory
+    budget: K for a small cube, smaller for a small budget, and the gradient
+    at the default equals the one at that spacing."""
     from paper_1504_06847_amd import Solver
     inst, p, kw = _grad64()
     s = Solver(inst.psf, inst.dirty, **kw)
     assert s.sweep_ckpt_every(20) == 20
-    free, _ = torch.cuda.mem_get_info()
-    cube = 64 * 64 * 8 * 4
-    # room for 80 cubes: spacing 5 needs 4 x 4 + 10 x 5 + 11 = 77, every
-    # larger one more (6: 87, ..., 20: 4 + 100 + 11)
-    assert s.sweep_ckpt_every(20, fraction=80 * cube / free) == 5
-    assert s.sweep_ckpt_every(20, fraction=10 * cube / free) == 1      # nothing fits
+    # the workspace of spacing 5 (4 x 4 + 10 x 5 + 11 cubes): every spacing
+    # that recomputes fewer passes (7, 10, 20) needs more
+    b5 = s.grad_workspace_bytes(20, 5)
+    assert s.grad_workspace_bytes(20, 20) == s.grad_workspace_bytes(20, 50) > b5
+    assert s.sweep_ckpt_every(20, budget=b5) == 5
+    smallest = min(s.grad_workspace_bytes(20, C) for C in range(1, 21))
+    assert s.sweep_ckpt_every(20, budget=smallest - 1) == 1      # nothing fits
     r0 = s.grad(20, sky=inst.sky)
     r1 = s.grad(20, sky=inst.sky, ckpt_every=20)
     assert r0[0] == r1[0] and np.array_equal(r0[1], r1[1])
