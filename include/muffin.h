@@ -214,6 +214,22 @@ size_t muffin_grad_workspace_bytes(const muffin_ctx* ctx, int K, int ckpt_every,
    Errors: EINVAL, EWORKSPACE (misaligned). */
 int muffin_set_grad_workspace(muffin_ctx* ctx, void* ws, size_t bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc):
+   muffin_grad with the reverse sweep's scratch in a static device array of
+   MUFFIN_NOALLOC_SCRATCH_MIB MiB, which the library holds on every GPU it
+   runs on until the process ends.  No workspace is needed and nothing is
+   allocated.  The sweep must fit: muffin_grad_workspace_bytes(ctx, K,
+   ckpt_every, 0) <= MUFFIN_NOALLOC_SCRATCH_MIB MiB, else MUFFIN_EWORKSPACE.
+   Every call on a GPU uses that GPU's one array, which keeps the last call's
+   contents (each call writes what it reads): calls that overlap on one GPU
+   (several streams or host threads) race, and the caller must serialise
+   them.  The passes are launched one by one (no graph is recorded).  The
+   results equal muffin_grad's bit for bit.  Errors as muffin_grad. */
+#define MUFFIN_NOALLOC_SCRATCH_MIB 64
+int muffin_grad_noalloc(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
+                        double* loss, double grad[3]);
+
 /* The same reverse sweep, with the derivative along each parameter on its
    own: grad = d/d(mu_eps, mu_s, mu_nu, rho_P, rho_T, rho_V, rho_S) (host
    double[7]).  mu_eps enters through rho of eq. Qlsimp only; the tied-rho

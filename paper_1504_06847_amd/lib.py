@@ -29,6 +29,7 @@ MUFFIN_MODE_MSE = 0
 MUFFIN_MODE_VJP = 1
 MUFFIN_MAX_BANDS = 128
 MUFFIN_MAX_BATCH = 256
+MUFFIN_NOALLOC_SCRATCH_MIB = 64
 
 ERROR_NAMES = {
     MUFFIN_EINVAL: "MUFFIN_EINVAL", MUFFIN_EUNSUPPORTED: "MUFFIN_EUNSUPPORTED",
@@ -80,6 +81,8 @@ SIGNATURES = [
     ("muffin_grad_dirty", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double), c_void_p]),
     ("muffin_grad_workspace_bytes", c_size_t, [c_void_p, c_int, c_int, c_int]),
     ("muffin_set_grad_workspace", c_int, [c_void_p, c_void_p, c_size_t]),
+    ("muffin_grad_noalloc", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double),
+                                    POINTER(c_double)]),
     ("muffin_state_bytes", c_size_t, [c_void_p]),
     ("muffin_get_state", c_int, [c_void_p, c_void_p]),
     ("muffin_set_state", c_int, [c_void_p, c_void_p]),
