@@ -103,10 +103,9 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(inst, params, iters: int):
+def cpu_baseline(inst, params, iters: int, workers: int):
     """Time the FP64 oracle (as it stands) on `iters` passes of the same cube."""
     import oracle as O
-    workers = min(16, os.cpu_count() or 1)
     O.set_workers(workers)
     prob = O.Problem(inst.psf, inst.dirty, params)
     st = O.State.zeros(prob.shape)
@@ -117,7 +116,7 @@ def cpu_baseline(inst, params, iters: int):
     dt = time.perf_counter() - t0
     L, ny, nx = prob.shape
     return dict(value=L * ny * nx * iters / dt, unit="voxel-iterations/s", cores=workers,
-                kind="oracle",
+                kind="oracle", cpu=cpu_model(),
                 sample=f"{iters} FP64 passes of the full {nx}x{ny}x{L} cube after one untimed "
                        f"pass; scipy.fft with {workers} threads, {dt:.1f} s")
 
@@ -220,6 +219,91 @@ def run_dictionary(inst, params, steps, warmup, profile_iters, graph=True):
     return out
 
 
+def run_large(steps, warmup, profile_iters, graph=True):
+    """The large workload: 2048 x 2048 x 256 bands FP32 (curved spectra, 200
+    antennas, 500 points + 100 Gaussians), its own 200 passes timed after a
+    warm-up, each kernel of a pass timed with events, the spectral pass (the
+    largest) against the HBM peak."""
+    import torch
+    from paper_1504_06847_amd import Solver
+    from synth import get_config
+    cfg = get_config("large2048")
+    t0 = time.perf_counter()
+    inst = cfg.make()
+    t_gen = time.perf_counter() - t0
+    p = cfg.params
+    t0 = time.perf_counter()
+    s = Solver(inst.psf, inst.dirty, graph=graph, mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho=p.rho_P)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    del inst
+    schedule = s.autotune(reps=2)
+    s.iterate(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    s.iterate(steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = s.profile(profile_iters) if profile_iters > 0 else {}
+    rep = s.step_report()
+    ws_gib = s._ws_bytes / 2**30
+    s.close()
+    V = cfg.voxels
+    kernels = {}
+    for name, kms in prof.items():
+        nbytes = KERNEL_ELEMS.get(name, 0.0) * 4 * V
+        kernels[name] = dict(ms=round(kms, 4), alg_bytes=int(nbytes), GBps=round(nbytes / (kms * 1e-3) / 1e9, 1))
+    dom = max(prof, key=prof.get) if prof else None
+    value = V * steps / (ms / 1e3)
+    return {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} pixels x {cfg.L} bands, FP32, {cfg.n_ant} antennas, "
+                        f"{cfg.n_points} points + {cfg.n_gauss} Gaussians with curved spectra",
+            "value": value, "unit": "voxel-iterations/s", "steps": steps, "ms_per_step": round(ms / steps, 4),
+            "schedule": list(schedule), "kernels": kernels,
+            "roofline": None if dom is None else dict(
+                bound="hbm", kernel=dom, achieved=kernels[dom]["GBps"], peak=HBM_PEAK_GBPS, unit="GB/s",
+                frac=round(kernels[dom]["GBps"] / HBM_PEAK_GBPS, 4)),
+            "iteration_62B_frac": round(ITER_MIN5_ELEMS * 4 * value / 1e9 / HBM_PEAK_GBPS, 4),
+            "workspace_GiB": round(ws_gib, 2), "generate_s": round(t_gen, 1), "setup_s": round(t_setup, 2),
+            "report_after": {k: rep[k] for k in ("iters", "r_pri", "r_dual", "E", "objective")}}
+
+
+def cpu_context(workers_all):
+    """The oracle's full runs of the small workloads (64 x 64 x 8, 100
+    passes; the paper's 256 x 256 x 15 shape, 350 passes; 256 x 256 x 32,
+    300 passes), on every host core, and the first with one thread too."""
+    import oracle as O
+    from synth import get_config
+    out = {}
+    for name, workers in (("plain64", 1), ("plain64", workers_all), ("paper256", workers_all),
+                          ("fp32_256", workers_all)):
+        c = get_config(name)
+        inst = c.make()
+        O.set_workers(workers)
+        prob = O.Problem(inst.psf, inst.dirty, c.params)
+        t0 = time.perf_counter()
+        O.run(prob, c.iters)
+        dt = time.perf_counter() - t0
+        out[f"{name}_w{workers}"] = {"passes": c.iters, "shape": [c.L, c.ny, c.nx], "workers": workers,
+                                     "seconds": round(dt, 2), "value": c.voxels * c.iters / dt,
+                                     "unit": "voxel-iterations/s"}
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def run_batch(steps, warmup):
     """voxel-iterations/s of the batch: each cube iterated on its own (one
     cube after another, the plain per-cube launches), then grouped launches,
@@ -288,6 +372,10 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--dict-steps", type=int, default=10,
                     help="timed passes with the paper's spatial dictionary (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=200,
+                    help="timed passes of the 2048 x 2048 x 256 workload (0: skip)")
+    ap.add_argument("--no-cpu-context", action="store_true",
+                    help="skip the oracle's full runs of the small workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration)")
     a = ap.parse_args(argv)
@@ -346,10 +434,19 @@ def main(argv=None):
     if not a.no_batch:
         _log(f"bench: 16-cube batch, {a.batch_steps} passes per form")
         batch = run_batch(a.batch_steps, 3)
+    large = None
+    if a.large_steps > 0:
+        _log(f"bench: 2048 x 2048 x 256, {a.large_steps} timed passes")
+        large = run_large(a.large_steps, 3, 5, graph=a.graph)
     cpu = None
+    workers_all = os.cpu_count() or 1
     if not a.no_cpu_baseline:
         _log(f"bench: CPU oracle, {a.cpu_iters} passes")
-        cpu = cpu_baseline(inst, cfg.params, a.cpu_iters)
+        cpu = cpu_baseline(inst, cfg.params, a.cpu_iters, workers_all)
+        cpu["one_thread"] = cpu_baseline(inst, cfg.params, 1, 1)
+        if not a.no_cpu_context:
+            _log("bench: CPU oracle, full runs of the small workloads")
+            cpu["full_runs"] = cpu_context(workers_all)
     out = {
         "metric": METRIC,
         "value": value,
@@ -378,6 +475,7 @@ def main(argv=None):
         "grad": grad,
         "dictionary": dictionary,
         "batched": batch,
+        "large": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

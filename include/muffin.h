@@ -76,8 +76,12 @@ extern "C" {
 #define MUFFIN_MODE_MSE 0          /* muffin_grad: loss = ||x_K - sky||^2, sky given */
 #define MUFFIN_MODE_VJP 1          /* muffin_grad: cotangent dL/dx_K given */
 
-#define MUFFIN_MAX_BANDS 128       /* largest L of the register-resident spectral pass;
-                                      above 32 bands L must be a power of two */
+#define MUFFIN_MAX_BANDS 256       /* largest L: up to 128 bands a pixel's band vector
+                                      and its DCT stay in one thread's registers, at 256
+                                      they are split over two waves (the DCT-II of length
+                                      256 as a butterfly, a DCT-II and a DCT-IV of length
+                                      128); above 32 bands L must be a power of two.
+                                      Batches and the gradient take L <= 128. */
 
 /* ---- plain-data structs -------------------------------------------------- */
 typedef struct muffin_ctx muffin_ctx;        /* opaque, owned by the library */

@@ -521,6 +521,10 @@ int grad_args(const muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx,
         set_error("%s: not built for a spatial dictionary with wavelet bases (n_s = %d)", what, c->params.n_s);
         return MUFFIN_EUNSUPPORTED;
     }
+    if (c->shape.L > 128) {
+        set_error("%s: the reverse sweep is built for band counts up to 128 (L = %d)", what, c->shape.L);
+        return MUFFIN_EUNSUPPORTED;
+    }
     if (K < 1 || ckpt_every < 1) {
         set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
         return MUFFIN_EINVAL;

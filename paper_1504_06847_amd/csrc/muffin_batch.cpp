@@ -298,6 +298,10 @@ int check_shapes(int n, const muffin_shape* shapes, const muffin_params* params)
             set_error("cube %d: batches run the Dirac spatial basis only (n_s = %d)", i, params[i].n_s);
             return MUFFIN_EUNSUPPORTED;
         }
+        if (shapes[i].L > 128) {
+            set_error("cube %d: batches take band counts up to 128 (L = %d)", i, shapes[i].L);
+            return MUFFIN_EUNSUPPORTED;
+        }
         if (shapes[i].dtype != shapes[0].dtype) {
             set_error("cube %d has dtype %d, cube 0 has %d: a batch has one dtype", i, shapes[i].dtype,
                       shapes[0].dtype);

@@ -647,6 +647,47 @@ template <typename T, int L> __host__ __device__ __forceinline__ void dct3_ortho
     }
 }
 
+// Orthonormal DCT-IV of N (a power of two) values in registers, its own
+// inverse: y_k = sqrt(2/N) sum_n w_n cos(pi (2n + 1)(2k + 1) / (4N)).
+// With M = N/2: z_m = (w_{2m} + i w_{N-1-2m}) exp(-i pi (4m + 1) / (4N)),
+// Z the M-point DFT of z, u_k = Z_k exp(-i pi k / N); then
+// y_{2k} = sqrt(2/N) Re u_k and y_{N-1-2k} = -sqrt(2/N) Im u_k.
+template <typename T, int N, int K>
+__host__ __device__ __forceinline__ void dct4_pre(const T (&a)[N], T (&re)[N / 2], T (&im)[N / 2]) {
+    if constexpr (K < N / 2) {
+        constexpr double c = cospi_ratio(4 * K + 1, 4 * N), s = sinpi_ratio(4 * K + 1, 4 * N);
+        const T x = a[2 * K], y = a[N - 1 - 2 * K];
+        re[K] = x * T(c) + y * T(s);
+        im[K] = y * T(c) - x * T(s);
+        dct4_pre<T, N, K + 1>(a, re, im);
+    }
+}
+
+template <typename T, int N, int K>
+__host__ __device__ __forceinline__ void dct4_post(T (&a)[N], const T (&re)[N / 2], const T (&im)[N / 2]) {
+    if constexpr (K < N / 2) {
+        constexpr double c = cospi_ratio(K, N), s = sinpi_ratio(K, N);
+        constexpr double sc = sqrt_c(2.0 / double(N));
+        const T ur = re[K] * T(c) + im[K] * T(s);
+        const T ui = im[K] * T(c) - re[K] * T(s);
+        a[2 * K] = ur * T(sc);
+        a[N - 1 - 2 * K] = -(ui * T(sc));
+        dct4_post<T, N, K + 1>(a, re, im);
+    }
+}
+
+template <typename T, int N> __host__ __device__ __forceinline__ void dct4_ortho(T (&a)[N]) {
+    if constexpr (N == 1) {
+        return;
+    } else {
+        constexpr int M = N / 2;
+        T re[M], im[M];
+        dct4_pre<T, N, 0>(a, re, im);
+        reg_fft<T, M, false>(re, im);
+        dct4_post<T, N, 0>(a, re, im);
+    }
+}
+
 // ---------------------------------------------------------------- band-axis helpers
 // deterministic block sum (valid in thread 0): wavefront tree, then the
 // per-wave sums in wave order; blockDim.x is a multiple of 64, at most NTH

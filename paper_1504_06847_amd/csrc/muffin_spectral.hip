@@ -129,6 +129,203 @@ k_spectral_group(const SpecDesc* __restrict__ d, int n) {
     spectral_body<T, LT, DENSE, false>(d[j].A, (const T*)d[j].D, d[j].Lrt, d[j].a, nullptr, b);
 }
 
+// ---------------------------------------------------------------- 256 bands
+// A pixel's 256 band values do not fit one thread's registers beside the
+// transform.  The orthonormal DCT-II of length 2N (N = 128) splits into a
+// butterfly of the two halves, u_n = (x_n + x_{2N-1-n}) / sqrt 2 and
+// w_n = (x_n - x_{2N-1-n}) / sqrt 2, followed by c_{2k} = DCT-II_N(u)_k and
+// c_{2k+1} = DCT-IV_N(w)_k; the inverse takes the same steps backwards
+// (DCT-III_N of the even and DCT-IV_N of the odd coefficients, then the
+// butterfly).  A work-group of two waves serves 64 pixels: wave 0 holds
+// bands 0..127 of its pixels and then the even coefficients, wave 1 bands
+// 128..255 and the odd ones, so each wave runs one transform and every band
+// access is uniform over the wave.  The butterflies exchange the halves
+// through LDS, 64 registers per round.  Steps IV and V touch the
+// coefficients one by one, so which wave holds which does not matter.
+constexpr int SPLIT_N = 128;       // bands per wave
+constexpr int SPLIT_NTH = 128;     // two waves, 64 pixels
+
+// round q of an exchange moves registers [0, 32) and [96, 128) (q = 0), then
+// [32, 96) (q = 1), so that register r and register 127 - r travel together;
+// slot i of a round holds register round_reg(q, i), register r sits in slot
+// slot_of(r)
+__host__ __device__ constexpr int round_reg(int q, int i) { return q == 0 ? (i < 32 ? i : 64 + i) : 32 + i; }
+__host__ __device__ constexpr int slot_of(int r) { return r < 32 ? r : (r < 96 ? r - 32 : r - 64); }
+
+// the forward butterfly: wave 0 (h = 0) ends with u_n in register n, wave 1
+// with w_j in register j (its register r held band 128 + r = x_{255 - (127 - r)})
+template <typename T>
+__device__ __forceinline__ void split_fwd(T (&v)[SPLIT_N], int h, T (*xch)[SPLIT_NTH]) {
+    const T rs = T(0.70710678118654752440084436210484903928);
+    const int t = threadIdx.x, o = t ^ 64;      // the partner: same lane of the other wave
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int i = 0; i < 64; ++i) xch[i][t] = v[round_reg(q, i)];
+        __syncthreads();
+        if (h == 0) {
+#pragma unroll
+            for (int i = 0; i < 64; ++i) {
+                const int n = round_reg(q, i);
+                v[n] = (v[n] + xch[slot_of(127 - n)][o]) * rs;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const int j = q == 0 ? i : 32 + i;
+                const T a = v[j], b = v[127 - j];
+                v[j] = (xch[slot_of(j)][o] - b) * rs;
+                v[127 - j] = (xch[slot_of(127 - j)][o] - a) * rs;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// the inverse butterfly: from u_n (wave 0) and w_n (wave 1) in register n
+// back to bands 0..127 (wave 0) and 128..255 (wave 1)
+template <typename T>
+__device__ __forceinline__ void split_inv(T (&v)[SPLIT_N], int h, T (*xch)[SPLIT_NTH]) {
+    const T rs = T(0.70710678118654752440084436210484903928);
+    const int t = threadIdx.x, o = t ^ 64;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int i = 0; i < 64; ++i) xch[i][t] = v[round_reg(q, i)];
+        __syncthreads();
+        if (h == 0) {
+#pragma unroll
+            for (int i = 0; i < 64; ++i) {
+                const int n = round_reg(q, i);
+                v[n] = (v[n] + xch[slot_of(n)][o]) * rs;                 // x_n = (u_n + w_n) / sqrt 2
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const int j = q == 0 ? i : 32 + i;
+                const T a = v[j], b = v[127 - j];
+                v[127 - j] = (xch[slot_of(j)][o] - a) * rs;              // x_{255-j} = (u_j - w_j) / sqrt 2
+                v[j] = (xch[slot_of(127 - j)][o] - b) * rs;              // x_{128+j}
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The pass runs in two launches, each with the occupancy it can have: the
+// transforms (q = IDCT(soft(DCT(z_V))), 128 registers of band values per
+// thread) write q into the B_rest array, then an element-wise launch forms
+// steps II, III, V, VI and B_rest from it at full occupancy.  That is 8 B
+// per voxel more than one launch (q out and back in); measured at
+// 2048 x 2048 x 256 FP32 the two launches take 11.9 ms, one launch with
+// both halves (344 registers, one wave per SIMD) 16.7 ms.
+template <typename T, bool REDUCE>
+__global__ void __launch_bounds__(SPLIT_NTH)
+k_spectral_split_q(SpecArrays A, SpecArgs a, double* __restrict__ partials) {
+    __shared__ T xch[64][SPLIT_NTH];
+    const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long p = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const unsigned bb = A.band_bytes;
+    const int gs_ = A.gshift;
+    const BandArray<T, kStreamCpol> zV{A.zV, bb, gs_};
+    const BandArray<T> Q{A.Brest, bb, gs_};
+    const int l0 = h * SPLIT_N;
+    const T tauV = T(a.tau_V);
+    double v2 = 0.0;
+    T v[SPLIT_N];
+#pragma unroll
+    for (int l = 0; l < SPLIT_N; ++l) v[l] = zV.load(l0 + l, off);
+    split_fwd<T>(v, h, xch);
+    if (h == 0) dct2_ortho<T, SPLIT_N>(v);
+    else dct4_ortho<T, SPLIT_N>(v);
+#pragma unroll
+    for (int k = 0; k < SPLIT_N; ++k) {
+        const T V = softt(v[k], tauV);
+        v[k] = V;
+        if constexpr (REDUCE) v2 += double(V) * V;
+    }
+    if (h == 0) dct3_ortho<T, SPLIT_N>(v);
+    else dct4_ortho<T, SPLIT_N>(v);
+    split_inv<T>(v, h, xch);
+#pragma unroll
+    for (int i = 0; i < SPLIT_N; ++i) Q.store(l0 + i, off, v[i]);
+    if constexpr (REDUCE) {
+        __shared__ double sh[SPLIT_NTH / 64];
+        const double sv = block_sum_s<SPLIT_NTH>(v2, sh);
+        if (threadIdx.x == 0) partials[blockIdx.x] = sv;
+    }
+}
+
+// steps II, III, V, VI element by element from q (in B_rest), 4 voxels per
+// thread: the arrays are [L][npix] with npix a multiple of 64, so the L npix
+// voxels split into whole 16-B (FP32) or 32-B (FP64) groups
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_spectral_elem(SpecArrays A, SpecArgs a, long n4) {
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    const T4* X = (const T4*)A.X;
+    const T4 *zP = (const T4*)A.zP, *zT = (const T4*)A.zT, *GS = (const T4*)A.GS;
+    T4 *zPo = (T4*)A.zPo, *zTo = (T4*)A.zTo, *zVo = (T4*)A.zVo, *GSo = (T4*)A.GSo;
+    T4* B = (T4*)A.Brest;
+    const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
+    const T tauT = T(a.tau_T);
+    const T inv_rhoV = T(1.0 / a.rho_V), inv_VS = T(1.0 / (a.rho_V + a.rho_S));
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long)gridDim.x * blockDim.x) {
+        const T4 x4 = X[i], q4 = B[i];
+        const T4 gs4 = __builtin_nontemporal_load(GS + i), zp4 = __builtin_nontemporal_load(zP + i),
+                 zt4 = __builtin_nontemporal_load(zT + i);
+        T4 zv_o, gs_o, zp_o, zt_o, b_o;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const T x = x4[c], q = q4[c], gs = gs4[c], zp = zp4[c], zt = zt4[c];
+            const T s = (rhoV * q + rhoS * x) * inv_VS;
+            const T gs2 = gs + rhoV * (q - s);
+            const T zp2 = x - (zp < T(0) ? -zp : T(0));
+            const T zt2 = x + clipt(zt, tauT);
+            const T tt = softt(zt2, tauT);
+            const T zv2 = s - gs2 * inv_rhoV;
+            const T sv = zv2 + gs2 * inv_rhoV;
+            zv_o[c] = zv2;
+            gs_o[c] = gs2;
+            zp_o[c] = zp2;
+            zt_o[c] = zt2;
+            b_o[c] = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * sv;
+        }
+        __builtin_nontemporal_store(zv_o, zVo + i);
+        __builtin_nontemporal_store(gs_o, GSo + i);
+        __builtin_nontemporal_store(zp_o, zPo + i);
+        __builtin_nontemporal_store(zt_o, zTo + i);
+        B[i] = b_o;
+    }
+}
+
+// sum over pixels of |P W_nu|_1 for 256 bands (blocks of 64 pixels)
+template <typename T>
+__global__ void __launch_bounds__(SPLIT_NTH)
+k_dct_l1_split(SpecArrays A, double* __restrict__ partials) {
+    __shared__ T xch[64][SPLIT_NTH];
+    const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long p = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const BandArray<T> zP{A.zP, A.band_bytes, A.gshift};
+    T v[SPLIT_N];
+#pragma unroll
+    for (int l = 0; l < SPLIT_N; ++l) {
+        const T z = zP.load(h * SPLIT_N + l, off);
+        v[l] = z > T(0) ? z : T(0);
+    }
+    split_fwd<T>(v, h, xch);
+    if (h == 0) dct2_ortho<T, SPLIT_N>(v);
+    else dct4_ortho<T, SPLIT_N>(v);
+    double pd = 0.0;
+#pragma unroll
+    for (int k = 0; k < SPLIT_N; ++k) pd += fabs(double(v[k]));
+    __shared__ double sh[SPLIT_NTH / 64];
+    const double sq = block_sum_s<SPLIT_NTH>(pd, sh);
+    if (threadIdx.x == 0) partials[(long)blockIdx.x * RED_NQ + RED_DCTP1] = sq;
+}
+
 // FP64 sums of a reporting pass from the old state (z_P, z_T, z_V, Gamma_S),
 // the new state (primed) and X, per block into partials[block * RED_NQ + q]
 // (RED_V2 copied from vpart[block], written by the spectral pass; RED_DCTP1
@@ -251,6 +448,39 @@ static hipError_t spectral_t(const SpecLaunch& g, const SpecArgs& a, hipStream_t
     return hipGetLastError();
 }
 
+// 256 bands: blocks of 64 pixels (two waves); a reporting pass runs k_report
+// with 64-thread blocks, so that its blocks are the spectral pass's
+template <typename T>
+static hipError_t spectral_split_t(const SpecLaunch& g, const SpecArgs& a, hipStream_t s) {
+    const long npix = g.npix;
+    if (npix < 64 || (npix & (npix - 1)) != 0) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(npix / 64));
+    const unsigned bb = (unsigned)(npix * (long)sizeof(T));
+    SpecArrays A{(char*)g.X, (char*)g.st[0], (char*)g.st[1], (char*)g.st[2], (char*)g.st[3],
+                 (char*)g.out[0], (char*)g.out[1], (char*)g.out[2], (char*)g.out[3], (char*)g.brest,
+                 bb, band_group_shift(bb)};
+    const long n4 = (long)g.L * npix / 4;
+    long eb = (n4 + 255) / 256;
+    if (eb > 65536) eb = 65536;
+    if (g.report) {
+        hipLaunchKernelGGL((k_spectral_split_q<T, true>), grid, dim3(SPLIT_NTH), 0, s, A, a, g.vpart);
+        hipLaunchKernelGGL((k_spectral_elem<T>), dim3((unsigned)eb), dim3(256), 0, s, A, a, n4);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_report<T>), grid, dim3(64), 0, s, A, g.L, npix, a, (const double*)g.vpart,
+                           g.partials);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        SpecArrays B = A;
+        B.zP = A.zPo;
+        hipLaunchKernelGGL((k_dct_l1_split<T>), grid, dim3(SPLIT_NTH), 0, s, B, g.partials);
+    } else {
+        hipLaunchKernelGGL((k_spectral_split_q<T, false>), grid, dim3(SPLIT_NTH), 0, s, A, a, g.vpart);
+        hipLaunchKernelGGL((k_spectral_elem<T>), dim3((unsigned)eb), dim3(256), 0, s, A, a, n4);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t spectral_dispatch(const SpecLaunch& g, const SpecArgs& a, hipStream_t s) {
     switch (g.L) {
@@ -262,6 +492,7 @@ static hipError_t spectral_dispatch(const SpecLaunch& g, const SpecArgs& a, hipS
         case 32: return spectral_t<T, 32, false>(g, a, s);
         case 64: return spectral_t<T, 64, false>(g, a, s);
         case 128: return spectral_t<T, 128, false>(g, a, s);
+        case 256: return spectral_split_t<T>(g, a, s);
         default: break;
     }
     // band counts that are not powers of two: dense DCT, up to 32 bands
@@ -305,7 +536,8 @@ hipError_t launch_spectral_group(int dtype, int L, int nth, const SpecDesc* d, i
 
 hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, int* nblocks_out,
                            hipStream_t s) {
-    if (nblocks_out) *nblocks_out = (int)(g.npix / (g.npix < SPEC_NTH ? g.npix : SPEC_NTH));
+    if (nblocks_out)
+        *nblocks_out = (int)(g.L == 2 * SPLIT_N ? g.npix / 64 : g.npix / (g.npix < SPEC_NTH ? g.npix : SPEC_NTH));
     return dtype == 0 ? spectral_dispatch<float>(g, a, s) : spectral_dispatch<double>(g, a, s);
 }
 

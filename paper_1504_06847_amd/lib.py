@@ -27,7 +27,7 @@ MUFFIN_DIRAC = 0
 MUFFIN_DCT2_ORTHO = 0
 MUFFIN_MODE_MSE = 0
 MUFFIN_MODE_VJP = 1
-MUFFIN_MAX_BANDS = 128
+MUFFIN_MAX_BANDS = 256
 MUFFIN_MAX_BATCH = 256
 MUFFIN_NOALLOC_SCRATCH_MIB = 64
 

@@ -26,6 +26,7 @@ those float32 values.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -155,7 +156,8 @@ def make_instance(ny: int, nx: int, L: int, *, n_points: int, n_gauss: int,
     psf = np.empty((L, ny, nx), dtype=np.float32)
     sky = np.empty((L, ny, nx), dtype=np.float32)
     dirty = np.empty((L, ny, nx), dtype=np.float32)
-    for l in range(L):
+
+    def band(l, noise):
         beam = _psf_band(u, v, base * freqs[l] / nu0, ny, nx)
         s = np.zeros((ny, nx), dtype=np.float64)
         np.add.at(s, (pts_y, pts_x), pts_spec[:, l])
@@ -164,11 +166,29 @@ def make_instance(ny: int, nx: int, L: int, *, n_points: int, n_gauss: int,
         # circular convolution with the band's PSF (peak moved to lag 0)
         conv = np.fft.irfft2(np.fft.rfft2(np.fft.ifftshift(beam)) * np.fft.rfft2(s),
                              s=(ny, nx))
-        # 3. noise: drawn band by band, after every source draw
-        conv += rng.normal(0.0, noise_sigma, size=(ny, nx))
+        conv += noise
         psf[l] = beam
         sky[l] = s
         dirty[l] = conv
+
+    # 3. noise: drawn band by band, after every source draw, in this thread;
+    # the bands themselves are independent and large ones run in a thread
+    # pool (the FFTs release the GIL), with the same results
+    workers = min(16, os.cpu_count() or 1) if ny * nx >= 1 << 18 and L > 1 else 1
+    if workers == 1:
+        for l in range(L):
+            band(l, rng.normal(0.0, noise_sigma, size=(ny, nx)))
+    else:
+        from collections import deque
+        from concurrent.futures import ThreadPoolExecutor
+        pending = deque()
+        with ThreadPoolExecutor(workers) as ex:
+            for l in range(L):
+                pending.append(ex.submit(band, l, rng.normal(0.0, noise_sigma, size=(ny, nx))))
+                if len(pending) > 2 * workers:
+                    pending.popleft().result()
+            while pending:
+                pending.popleft().result()
     meta = dict(seed=seed, n_points=n_points, n_gauss=n_gauss, n_ant=n_ant,
                 noise_sigma=noise_sigma, curvature_sigma=curvature_sigma)
     return Instance(psf=psf, dirty=dirty, sky=sky, freqs_ghz=freqs, meta=meta)

@@ -1,38 +1,99 @@
-// Checks the register-resident DCT-II / DCT-III of the spectral kernel, the
-// same source compiled for the host, against the O(L^2) definition in long
-// double: c_k = a_k sum_l x_l cos(pi (2l + 1) k / (2L)).
+// Checks the register-resident transforms of the spectral kernels, the same
+// source compiled for the host, against their O(L^2) definitions in long
+// double:
+//   DCT-II  c_k = a_k sum_l x_l cos(pi (2l + 1) k / (2L)), a_0 = sqrt(1/L), a_k = sqrt(2/L)
+//   DCT-III its transpose (the inverse)
+//   DCT-IV  y_k = sqrt(2/L) sum_l x_l cos(pi (2l + 1)(2k + 1) / (4L))
+// and the 256-band form of the DCT-II: a butterfly of the two halves
+// (u_n = (x_n + x_{255-n}) / sqrt 2, w_n = (x_n - x_{255-n}) / sqrt 2) then
+// DCT-II(u) for the even and DCT-IV(w) for the odd coefficients, and back,
+// in the kernel's order of operations.
 #include <cmath>
 #include <cstdio>
 #include <random>
 
 #include "muffin_device.hpp"
 
+enum Kind { DCT2 = 0, DCT3 = 1, DCT4 = 2 };
+
+static long double basis(int kind, int L, int k, int l) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    if (kind == DCT2) return (k == 0 ? sqrtl(1.0L / L) : sqrtl(2.0L / L)) * cosl(pi * (2 * l + 1) * k / (2.0L * L));
+    if (kind == DCT3) return (l == 0 ? sqrtl(1.0L / L) : sqrtl(2.0L / L)) * cosl(pi * (2 * k + 1) * l / (2.0L * L));
+    return sqrtl(2.0L / L) * cosl(pi * (2 * l + 1) * (2 * k + 1) / (4.0L * L));
+}
+
 template <typename T, int L>
-static double check(std::mt19937_64& rng, bool inverse) {
+static double check(std::mt19937_64& rng, int kind) {
     std::normal_distribution<double> nd;
     double worst = 0.0;
     for (int trial = 0; trial < 20; ++trial) {
         T v[L];
         long double x[L];
         for (int l = 0; l < L; ++l) { x[l] = (long double)(T)nd(rng); v[l] = (T)x[l]; }
-        if (inverse) muffin::dct3_ortho<T, L>(v); else muffin::dct2_ortho<T, L>(v);
-        const long double pi = 3.141592653589793238462643383279502884L;
+        if (kind == DCT2) muffin::dct2_ortho<T, L>(v);
+        else if (kind == DCT3) muffin::dct3_ortho<T, L>(v);
+        else muffin::dct4_ortho<T, L>(v);
         long double nrm = 0, err = 0;
         for (int k = 0; k < L; ++k) {
             long double ref = 0;
-            for (int l = 0; l < L; ++l) {
-                if (!inverse) {
-                    long double a = k == 0 ? sqrtl(1.0L / L) : sqrtl(2.0L / L);
-                    ref += a * cosl(pi * (2 * l + 1) * k / (2.0L * L)) * x[l];
-                } else {
-                    long double a = l == 0 ? sqrtl(1.0L / L) : sqrtl(2.0L / L);
-                    ref += a * cosl(pi * (2 * k + 1) * l / (2.0L * L)) * x[l];
-                }
-            }
+            for (int l = 0; l < L; ++l) ref += basis(kind, L, k, l) * x[l];
             nrm += ref * ref;
             err += (ref - v[k]) * (ref - v[k]);
         }
-        double r = (double)sqrtl(err / nrm);
+        const double r = (double)sqrtl(err / nrm);
+        if (r > worst) worst = r;
+    }
+    return worst;
+}
+
+// The 256-band DCT-II and its inverse through the two halves, as the kernel
+// does it (the exchange between its two waves is a plain copy here).
+template <typename T>
+static void split256(T (&lo)[128], T (&hi)[128], bool inverse) {
+    constexpr int N = 128;
+    const T rs = T(0.70710678118654752440084436210484903928);
+    T a[N], b[N];
+    for (int i = 0; i < N; ++i) { a[i] = lo[i]; b[i] = hi[i]; }
+    if (!inverse) {
+        // lo: bands 0..127, hi: bands 128..255
+        for (int n = 0; n < N; ++n) lo[n] = (a[n] + b[N - 1 - n]) * rs;      // u
+        for (int j = 0; j < N; ++j) hi[j] = (a[j] - b[N - 1 - j]) * rs;      // w
+        muffin::dct2_ortho<T, N>(lo);                                       // c_{2k}
+        muffin::dct4_ortho<T, N>(hi);                                       // c_{2k+1}
+    } else {
+        muffin::dct3_ortho<T, N>(a);                                        // u
+        muffin::dct4_ortho<T, N>(b);                                        // w
+        for (int n = 0; n < N; ++n) lo[n] = (a[n] + b[n]) * rs;            // x_n
+        for (int n = 0; n < N; ++n) hi[N - 1 - n] = (a[n] - b[n]) * rs;    // x_{255-n}
+    }
+}
+
+template <typename T>
+static double check_split(std::mt19937_64& rng, bool inverse) {
+    constexpr int L = 256, N = 128;
+    std::normal_distribution<double> nd;
+    double worst = 0.0;
+    for (int trial = 0; trial < 10; ++trial) {
+        T lo[N], hi[N];
+        long double x[L];
+        for (int l = 0; l < L; ++l) x[l] = (long double)(T)nd(rng);
+        if (!inverse) {
+            for (int i = 0; i < N; ++i) { lo[i] = (T)x[i]; hi[i] = (T)x[N + i]; }
+        } else {
+            // coefficient c_{2k} in lo[k], c_{2k+1} in hi[k]
+            for (int k = 0; k < N; ++k) { lo[k] = (T)x[2 * k]; hi[k] = (T)x[2 * k + 1]; }
+        }
+        split256<T>(lo, hi, inverse);
+        long double nrm = 0, err = 0;
+        for (int k = 0; k < L; ++k) {
+            long double ref = 0;
+            for (int l = 0; l < L; ++l) ref += basis(inverse ? DCT3 : DCT2, L, k, l) * x[l];
+            const long double got = inverse ? (k < N ? lo[k] : hi[k - N]) : (k % 2 == 0 ? lo[k / 2] : hi[k / 2]);
+            nrm += ref * ref;
+            err += (ref - got) * (ref - got);
+        }
+        const double r = (double)sqrtl(err / nrm);
         if (r > worst) worst = r;
     }
     return worst;
@@ -41,17 +102,29 @@ static double check(std::mt19937_64& rng, bool inverse) {
 template <int L>
 static int run(std::mt19937_64& rng) {
     int bad = 0;
-    const double e64f = check<double, L>(rng, false), e64i = check<double, L>(rng, true);
-    const double e32f = check<float, L>(rng, false), e32i = check<float, L>(rng, true);
-    std::printf("L=%3d  f64 dct2 %.2e dct3 %.2e   f32 dct2 %.2e dct3 %.2e\n", L, e64f, e64i, e32f, e32i);
-    if (e64f > 1e-14 || e64i > 1e-14) ++bad;
-    if (e32f > 2e-6 || e32i > 2e-6) ++bad;
+    double e[2][3];
+    for (int kind = 0; kind < 3; ++kind) {
+        e[0][kind] = check<double, L>(rng, kind);
+        e[1][kind] = check<float, L>(rng, kind);
+    }
+    std::printf("L=%3d  f64 dct2 %.2e dct3 %.2e dct4 %.2e   f32 dct2 %.2e dct3 %.2e dct4 %.2e\n", L, e[0][0],
+                e[0][1], e[0][2], e[1][0], e[1][1], e[1][2]);
+    for (int kind = 0; kind < 3; ++kind) {
+        if (e[0][kind] > 1e-14) ++bad;
+        if (e[1][kind] > 2e-6) ++bad;
+    }
     return bad;
 }
 
 int main() {
     std::mt19937_64 rng(1234);
-    int bad = run<1>(rng) + run<2>(rng) + run<4>(rng) + run<8>(rng) + run<16>(rng) + run<32>(rng) + run<64>(rng);
+    int bad = run<1>(rng) + run<2>(rng) + run<4>(rng) + run<8>(rng) + run<16>(rng) + run<32>(rng) + run<64>(rng) +
+              run<128>(rng);
+    const double s64f = check_split<double>(rng, false), s64i = check_split<double>(rng, true);
+    const double s32f = check_split<float>(rng, false), s32i = check_split<float>(rng, true);
+    std::printf("L=256 (two halves)  f64 dct2 %.2e dct3 %.2e   f32 dct2 %.2e dct3 %.2e\n", s64f, s64i, s32f, s32i);
+    if (s64f > 1e-14 || s64i > 1e-14) ++bad;
+    if (s32f > 2e-6 || s32i > 2e-6) ++bad;
     if (!bad) std::printf("ALL OK\n");
     return bad ? 1 : 0;
 }

@@ -81,7 +81,7 @@ def test_parameter_validation(lib, field, value, code):
     (64, 64, 8, 0, 0), (8, 8, 1, 1, 0), (4096, 8, 64, 0, 0), (64, 64, 15, 0, 0),
     (64, 64, 0, 0, -1), (0, 64, 8, 0, -1), (60, 64, 8, 0, -2), (64, 8192, 8, 0, -2),
     (4, 64, 8, 0, -2), (64, 64, 129, 0, -2), (64, 64, 48, 0, -2), (64, 64, 96, 0, -2),
-    (64, 64, 128, 0, 0), (64, 64, 8, 7, -2),
+    (64, 64, 128, 0, 0), (64, 64, 256, 0, 0), (64, 64, 257, 0, -2), (64, 64, 512, 0, -2), (64, 64, 8, 7, -2),
 ])
 def test_shape_validation(lib, nx, ny, Lb, dtype, code):
     from paper_1504_06847_amd import lib as L
@@ -162,6 +162,9 @@ def test_batch_validation_without_device(lib):
     assert "dtype" in L.last_error(lib)
     bad = (L.MuffinShape * 2)(L.MuffinShape(64, 64, 8, 0), L.MuffinShape(60, 64, 8, 0))
     assert lib.muffin_batch_workspace_bytes(2, bad, prm) == 0
+    wide = (L.MuffinShape * 2)(L.MuffinShape(64, 64, 8, 0), L.MuffinShape(64, 64, 256, 0))
+    assert lib.muffin_batch_workspace_bytes(2, wide, prm) == 0      # batches take L <= 128
+    assert "128" in L.last_error(lib)
     b = ctypes.c_void_p()
     dummy = (ctypes.c_void_p * n)(0x1000, 0x1000, 0x1000)
     assert lib.muffin_setup_batch(ctypes.byref(b), 0, shapes, prm, dummy, dummy,
