@@ -11,8 +11,11 @@ from .muffin_oracle import (Params, Problem, State, soft, dct_nu, idct_nu,
                             set_workers, solve_adaptive)
 from .wavelets import (DIRAC, PAPER_DICTIONARY, Dictionary, daubechies_filter,
                        dwt2, idwt2, dwt_levels)
+from .spectral import (DCT, CHEBYSHEV, SPECTRAL_DIRAC, SpectralDictionary, chebyshev_basis,
+                       basis_matrix)
 
 __all__ = ["Params", "Problem", "State", "soft", "dct_nu", "idct_nu", "run",
            "admm_iteration", "objective", "residuals", "energy", "jvp_run",
            "mse_loss", "mse_grad", "set_workers", "solve_adaptive", "DIRAC", "PAPER_DICTIONARY",
-           "Dictionary", "daubechies_filter", "dwt2", "idwt2", "dwt_levels"]
+           "Dictionary", "daubechies_filter", "dwt2", "idwt2", "dwt_levels", "DCT", "CHEBYSHEV",
+           "SPECTRAL_DIRAC", "SpectralDictionary", "chebyshev_basis", "basis_matrix"]

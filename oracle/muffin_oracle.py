@@ -52,6 +52,7 @@ from dataclasses import dataclass, fields
 import numpy as np
 import scipy.fft as sfft
 
+from .spectral import DCT, SpectralDictionary
 from .wavelets import DIRAC, Dictionary
 
 _WORKERS = int(os.environ.get("MUFFIN_ORACLE_WORKERS", "1"))
@@ -124,9 +125,10 @@ class Problem:
     reference).  ``bases``: the spatial dictionary W_s (codes of
     ``oracle/wavelets.py``; the Dirac basis alone by default)."""
 
-    def __init__(self, psf, dirty, params, bases=(DIRAC,), dtype=np.float64):
+    def __init__(self, psf, dirty, params, bases=(DIRAC,), dtype=np.float64, spectral=(DCT,)):
         self.psf = np.asarray(psf, dtype=dtype)
         self.Y = np.asarray(dirty, dtype=dtype)
+        self.Wnu = SpectralDictionary(spectral)
         assert self.psf.shape == self.Y.shape and self.psf.ndim == 3
         self.p = Params.from_any(params)
         self.W = Dictionary(bases)
@@ -141,6 +143,7 @@ class Problem:
     def with_params(self, params):
         q = object.__new__(Problem)
         q.psf, q.Y, q.hhat, q.HtY, q.W = self.psf, self.Y, self.hhat, self.HtY, self.W
+        q.Wnu = self.Wnu
         q.p = Params.from_any(params)
         q._set_filter()
         return q
@@ -161,6 +164,10 @@ class Problem:
     def dirac_only(self) -> bool:
         return self.W.bases == (DIRAC,)
 
+    @property
+    def m_nu(self) -> int:
+        return self.Wnu.m
+
     def Ws(self, x):
         """W_s x: x itself for the Dirac basis alone, else the stacked
         coefficient cubes [n_s][L][ny][nx]."""
@@ -171,7 +178,7 @@ class Problem:
         return c if self.dirac_only else self.W.adjoint(c)
 
     def zero_state(self):
-        return State.zeros(self.shape, 1 if self.dirac_only else self.n_s)
+        return State.zeros(self.shape, 1 if self.dirac_only else self.n_s, self.m_nu)
 
     def H(self, x):
         """Band-wise circular convolution with the PSF (eq. nbmodel)."""
@@ -199,11 +206,13 @@ class State:
     GS: np.ndarray
 
     @classmethod
-    def zeros(cls, shape, n_s: int = 1):
-        """All nine arrays zero; with n_s > 1 bases T and Gamma_T hold one
-        coefficient cube per basis ([n_s][L][ny][nx])."""
+    def zeros(cls, shape, n_s: int = 1, m_nu: int = 1):
+        """All nine arrays zero; with n_s > 1 spatial bases T and Gamma_T hold
+        one coefficient cube per basis ([n_s][L][ny][nx]), with m_nu > 1
+        spectral bases V and Gamma_V likewise ([m_nu][L][ny][nx])."""
         tshape = tuple(shape) if n_s == 1 else (n_s,) + tuple(shape)
-        a = [np.zeros(tshape) if f in ("T", "GT") else np.zeros(shape)
+        vshape = tuple(shape) if m_nu == 1 else (m_nu,) + tuple(shape)
+        a = [np.zeros(tshape) if f in ("T", "GT") else (np.zeros(vshape) if f in ("V", "GV") else np.zeros(shape))
              for f in ("X", "P", "T", "V", "S", "GP", "GT", "GV", "GS")]
         return cls(*a)
 
@@ -223,14 +232,15 @@ def admm_iteration(prob: Problem, st: State) -> State:
     # Step III: spatial soft threshold, per coefficient of every basis
     WX = prob.Ws(X)
     T = soft(WX - st.GT / p.rho_T, p.mu_s / p.rho_T)
-    # Step IV: spectral soft threshold, on the S of the previous pass
-    V = soft(dct_nu(st.S) - st.GV / p.rho_V, p.mu_nu / p.rho_V)
-    # Step V: closed form for one orthonormal W_nu (m_nu = 1)
-    S = (idct_nu(st.GV + p.rho_V * V) - st.GS + p.rho_S * X) / (p.rho_V + p.rho_S)
+    # Step IV: spectral soft threshold, on the S of the previous pass, per
+    # coefficient of every spectral basis
+    V = soft(prob.Wnu.forward(st.S) - st.GV / p.rho_V, p.mu_nu / p.rho_V)
+    # Step V: closed form for a union of m_nu orthonormal W_nu
+    S = (prob.Wnu.adjoint(st.GV + p.rho_V * V) - st.GS + p.rho_S * X) / (prob.m_nu * p.rho_V + p.rho_S)
     # Step VI: multipliers, with the new P, T, V, S
     GP = st.GP + p.rho_P * (P - X)
     GT = st.GT + p.rho_T * (T - WX)
-    GV = st.GV + p.rho_V * (V - dct_nu(S))
+    GV = st.GV + p.rho_V * (V - prob.Wnu.forward(S))
     GS = st.GS + p.rho_S * (S - X)
     return State(X, P, T, V, S, GP, GT, GV, GS)
 
@@ -253,29 +263,30 @@ def objective(prob: Problem, P: np.ndarray) -> float:
     p = prob.p
     r = prob.Y - prob.H(P)
     return float(0.5 * np.sum(r * r) + 0.5 * p.mu_eps * np.sum(P * P)
-                 + p.mu_s * np.sum(np.abs(prob.Ws(P))) + p.mu_nu * np.sum(np.abs(dct_nu(P))))
+                 + p.mu_s * np.sum(np.abs(prob.Ws(P))) + p.mu_nu * np.sum(np.abs(prob.Wnu.forward(P))))
 
 
 def residuals(prob: Problem, prev: State, cur: State, eps_abs=1e-5, eps_rel=1e-4):
     """Primal / dual residual norms and tolerances (Boyd et al. 2011, Sec. 3.3).
 
     Constraints P - X, T - W_s X, V - S W_nu, S - X; block 1 = (X, V),
-    block 2 = (P, T, S)."""
+    block 2 = (P, T, S).  The constraint space has (2 + n_s + m_nu) nvox
+    entries, block 1 (1 + m_nu) nvox."""
     p = prob.p
     WX = prob.Ws(cur.X)
+    SW = prob.Wnu.forward(cur.S)
     r2 = (np.sum((cur.P - cur.X) ** 2) + np.sum((cur.T - WX) ** 2)
-          + np.sum((cur.V - dct_nu(cur.S)) ** 2) + np.sum((cur.S - cur.X) ** 2))
+          + np.sum((cur.V - SW) ** 2) + np.sum((cur.S - cur.X) ** 2))
     dP, dT, dS = cur.P - prev.P, cur.T - prev.T, cur.S - prev.S
     sX = p.rho_P * dP + p.rho_T * prob.WsT(dT) + p.rho_S * dS
-    sV = p.rho_V * dct_nu(dS)
+    sV = p.rho_V * prob.Wnu.forward(dS)
     s2 = np.sum(sX ** 2) + np.sum(sV ** 2)
     nvox = cur.X.size
     Ax = np.sqrt(2.0 * np.sum(cur.X ** 2) + np.sum(WX ** 2) + np.sum(cur.V ** 2))
-    Bz = np.sqrt(np.sum(cur.P ** 2) + np.sum(cur.T ** 2) + np.sum(dct_nu(cur.S) ** 2)
-                 + np.sum(cur.S ** 2))
+    Bz = np.sqrt(np.sum(cur.P ** 2) + np.sum(cur.T ** 2) + np.sum(SW ** 2) + np.sum(cur.S ** 2))
     Aty = np.sqrt(np.sum((cur.GP + prob.WsT(cur.GT) + cur.GS) ** 2) + np.sum(cur.GV ** 2))
-    eps_pri = np.sqrt((3.0 + prob.n_s) * nvox) * eps_abs + eps_rel * max(Ax, Bz)
-    eps_dual = np.sqrt(2.0 * nvox) * eps_abs + eps_rel * Aty
+    eps_pri = np.sqrt((2.0 + prob.n_s + prob.m_nu) * nvox) * eps_abs + eps_rel * max(Ax, Bz)
+    eps_dual = np.sqrt((1.0 + prob.m_nu) * nvox) * eps_abs + eps_rel * Aty
     return dict(r=float(np.sqrt(r2)), s=float(np.sqrt(s2)),
                 eps_pri=float(eps_pri), eps_dual=float(eps_dual))
 
@@ -287,7 +298,7 @@ def energy(prob: Problem, prev: State, cur: State) -> float:
     return float(p.rho_P * np.sum((cur.P - prev.P) ** 2)
                  + p.rho_T * np.sum((cur.T - prev.T) ** 2)
                  + p.rho_S * np.sum(dS ** 2)
-                 + p.rho_V * np.sum(dct_nu(dS) ** 2)
+                 + p.rho_V * np.sum(prob.Wnu.forward(dS) ** 2)
                  + np.sum((cur.GP - prev.GP) ** 2) / p.rho_P
                  + np.sum((cur.GT - prev.GT) ** 2) / p.rho_T
                  + np.sum((cur.GV - prev.GV) ** 2) / p.rho_V
@@ -332,9 +343,11 @@ def mse_loss(XK, sky) -> float:
 
 
 def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params, dHtY=None):
-    """Primal pass of Algorithm 1 with its forward-mode tangent (Dirac W_s);
-    dHtY: the tangent of H^T Y (a change of the dirty images), or None."""
+    """Primal pass of Algorithm 1 with its forward-mode tangent (Dirac W_s,
+    DCT W_nu); dHtY: the tangent of H^T Y (a change of the dirty images), or
+    None."""
     assert prob.dirac_only, "the tangent pass is written for W_s = identity"
+    assert prob.Wnu.bases == (DCT,), "the tangent pass is written for W_nu = DCT"
     p = prob.p
     drhoQ = dp.mu_eps + dp.rho_S + dp.rho_P + dp.rho_T
     B = (prob.HtY + st.GT + p.rho_T * st.T + st.GP + p.rho_P * st.P
