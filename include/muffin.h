@@ -71,7 +71,16 @@ extern "C" {
 #define MUFFIN_DB6 6
 #define MUFFIN_DB7 7
 #define MUFFIN_DB8 8
-#define MUFFIN_DCT2_ORTHO 0        /* W_nu = orthonormal DCT-II along the bands */
+/* spectral bases W_nu along the bands (one, or a union of up to
+   MUFFIN_MAX_SPECTRAL distinct ones: Section 3, the closed form of step V for
+   a union of m_nu orthonormal transforms) */
+#define MUFFIN_DCT2_ORTHO 0        /* orthonormal DCT-II along the bands (Section 4) */
+#define MUFFIN_CHEBYSHEV 1         /* Chebyshev polynomials T_0 .. T_{L-1} at the bands
+                                      (equispaced, mapped onto [-1, 1]) orthonormalised in
+                                      order of degree, degree-k coefficient positive
+                                      (Section 4 names the family as an alternative) */
+#define MUFFIN_SPECTRAL_DIRAC 2    /* the identity along the bands */
+#define MUFFIN_MAX_SPECTRAL 4
 
 #define MUFFIN_MODE_MSE 0          /* muffin_grad: loss = ||x_K - sky||^2, sky given */
 #define MUFFIN_MODE_VJP 1          /* muffin_grad: cotangent dL/dx_K given */
@@ -104,7 +113,11 @@ typedef struct {
                          three-launch pass, no convergence reports
                          (muffin_step_report, muffin_solve), no gradient and
                          no batches (MUFFIN_EUNSUPPORTED) */
-    int spectral;     /* MUFFIN_DCT2_ORTHO */
+    int n_nu;         /* number of spectral bases W_nu stacks, 1 <= n_nu <= MUFFIN_MAX_SPECTRAL */
+    int spectral[MUFFIN_MAX_SPECTRAL];  /* spectral[0 .. n_nu-1]: distinct codes above.
+                         Anything but the DCT alone takes a dense L x L transform
+                         per basis, for L <= 32 or L = 64; a union (n_nu > 1) has
+                         no fused pass, batches or gradient (MUFFIN_EUNSUPPORTED) */
     int check_every;  /* muffin_solve: iterations between FP64 residual checks (>= 1) */
     double eps_abs, eps_rel;   /* stopping tolerances of Boyd et al. (2011), Sec. 3.3.1 */
 } muffin_params;
@@ -119,7 +132,8 @@ typedef struct {
 
 /* Fill `p` with the paper's parameter values (Section 4): mu_eps = 1e-3,
    mu_s = 0.5, mu_nu = 1, rho_P = 1, rho_T = 5, rho_V = 2, rho_S = 1,
-   n_s = 1 (Dirac), DCT-II, check_every = 10, eps_abs = 1e-5, eps_rel = 1e-4. */
+   n_s = 1 (Dirac), n_nu = 1 (DCT-II), check_every = 10, eps_abs = 1e-5,
+   eps_rel = 1e-4. */
 void muffin_default_params(muffin_params* p);
 
 /* Bytes of device workspace muffin_setup needs for this shape (0 if the
@@ -129,6 +143,12 @@ size_t muffin_workspace_bytes(const muffin_shape* shape, const muffin_params* pa
 /* Host-only validation of a shape and parameter set: MUFFIN_OK or the code
    muffin_setup would return before touching the device. */
 int muffin_validate(const muffin_shape* shape, const muffin_params* params);
+
+/* Host-only: the orthonormal spectral basis `code` for L bands into W
+   (row-major L x L, FP64): the spectrum of a pixel's band vector x is
+   x W, as the library's spectral passes use it.  Errors: EINVAL (code or L
+   out of range, W NULL). */
+int muffin_spectral_basis(int code, int L, double* W);
 
 /* Host-only: the scaling filter of the wavelet basis Db_p (MUFFIN_DB1 <= p
    <= MUFFIN_DB8; Section 4's dictionary) into h[0 .. 2p-1], FP64, as the

@@ -344,10 +344,11 @@ def mse_loss(XK, sky) -> float:
 
 def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params, dHtY=None):
     """Primal pass of Algorithm 1 with its forward-mode tangent (Dirac W_s,
-    DCT W_nu); dHtY: the tangent of H^T Y (a change of the dirty images), or
-    None."""
+    one orthonormal spectral basis W_nu); dHtY: the tangent of H^T Y (a
+    change of the dirty images), or None."""
     assert prob.dirac_only, "the tangent pass is written for W_s = identity"
-    assert prob.Wnu.bases == (DCT,), "the tangent pass is written for W_nu = DCT"
+    assert prob.m_nu == 1, "the tangent pass is written for one spectral basis"
+    fw, bw = prob.Wnu.forward, prob.Wnu.adjoint
     p = prob.p
     drhoQ = dp.mu_eps + dp.rho_S + dp.rho_P + dp.rho_T
     B = (prob.HtY + st.GT + p.rho_T * st.T + st.GP + p.rho_P * st.P
@@ -368,20 +369,20 @@ def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params, dHtY=None):
     dtT = dp.mu_s / p.rho_T - p.mu_s * dp.rho_T / p.rho_T ** 2
     T = soft(zT, tT)
     dT = np.where(np.abs(zT) > tT, dzT - np.sign(zT) * dtT, 0.0)
-    zV = dct_nu(st.S) - st.GV / p.rho_V
-    dzV = dct_nu(dst.S) - dst.GV / p.rho_V + st.GV * dp.rho_V / p.rho_V ** 2
+    zV = fw(st.S) - st.GV / p.rho_V
+    dzV = fw(dst.S) - dst.GV / p.rho_V + st.GV * dp.rho_V / p.rho_V ** 2
     tV = p.mu_nu / p.rho_V
     dtV = dp.mu_nu / p.rho_V - p.mu_nu * dp.rho_V / p.rho_V ** 2
     V = soft(zV, tV)
     dV = np.where(np.abs(zV) > tV, dzV - np.sign(zV) * dtV, 0.0)
     den = p.rho_V + p.rho_S
     dden = dp.rho_V + dp.rho_S
-    num = idct_nu(st.GV + p.rho_V * V) - st.GS + p.rho_S * X
-    dnum = (idct_nu(dst.GV + dp.rho_V * V + p.rho_V * dV) - dst.GS
+    num = bw(st.GV + p.rho_V * V) - st.GS + p.rho_S * X
+    dnum = (bw(dst.GV + dp.rho_V * V + p.rho_V * dV) - dst.GS
             + dp.rho_S * X + p.rho_S * dX)
     S = num / den
     dS = (dnum - S * dden) / den
-    cS, dcS = dct_nu(S), dct_nu(dS)
+    cS, dcS = fw(S), fw(dS)
     GP = st.GP + p.rho_P * (P - X)
     dGP = dst.GP + dp.rho_P * (P - X) + p.rho_P * (dP - dX)
     GT = st.GT + p.rho_T * (T - X)

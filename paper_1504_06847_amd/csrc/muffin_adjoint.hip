@@ -357,8 +357,9 @@ static hipError_t adj_t(const AdjArrays& A, const void* D, int L, long npix, con
 
 template <typename T>
 static hipError_t adj_dispatch(const AdjArrays& A, const void* D, int L, long npix, const SpecArgs& a,
-                               int mode, double* partials, double* partials1, int* nb, hipStream_t s) {
-    switch (L) {
+                               int mode, double* partials, double* partials1, int* nb, hipStream_t s,
+                               bool dense) {
+    if (!dense) switch (L) {
         case 1: return adj_t<T, 1, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
         case 2: return adj_t<T, 2, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
         case 4: return adj_t<T, 4, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
@@ -369,6 +370,8 @@ static hipError_t adj_dispatch(const AdjArrays& A, const void* D, int L, long np
         case 128: return adj_t<T, 128, false>(A, D, L, npix, a, mode, partials, partials1, nb, s);
         default: break;
     }
+    // the dense product with D: band counts that are not powers of two, and
+    // the spectral bases other than the DCT, up to 32 bands
     if (L < 1 || L > 32) return hipErrorInvalidValue;
     if (L <= 8) return adj_t<T, 8, true>(A, D, L, npix, a, mode, partials, partials1, nb, s);
     if (L <= 16) return adj_t<T, 16, true>(A, D, L, npix, a, mode, partials, partials1, nb, s);
@@ -377,10 +380,10 @@ static hipError_t adj_dispatch(const AdjArrays& A, const void* D, int L, long np
 
 hipError_t launch_adj_spectral(int dtype, const AdjArrays& A, const void* D, int L, long npix,
                                const SpecArgs& a, int mode, double* partials, double* partials1, int* nblocks,
-                               hipStream_t s) {
+                               hipStream_t s, bool dense) {
     if (mode < ADJ_PLAIN || mode > ADJ_STEP1 || (mode == ADJ_STEP1 && !partials1)) return hipErrorInvalidValue;
-    return dtype == 0 ? adj_dispatch<float>(A, D, L, npix, a, mode, partials, partials1, nblocks, s)
-                      : adj_dispatch<double>(A, D, L, npix, a, mode, partials, partials1, nblocks, s);
+    return dtype == 0 ? adj_dispatch<float>(A, D, L, npix, a, mode, partials, partials1, nblocks, s, dense)
+                      : adj_dispatch<double>(A, D, L, npix, a, mode, partials, partials1, nblocks, s, dense);
 }
 
 hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* zV,

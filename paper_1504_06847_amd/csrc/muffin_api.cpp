@@ -18,9 +18,17 @@ using namespace muffin;
 
 namespace {
 
-bool use_fused(const muffin_ctx* c) {
-    return c->fused && c->lay.n_w == 0 && fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L);
+// the fused row/spectral launch exists for the fast DCT and the Dirac spatial basis
+bool fused_possible(const muffin_ctx* c) {
+    return c->lay.n_w == 0 && !spectral_dense(c->shape, c->params) &&
+           fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L);
 }
+
+bool use_fused(const muffin_ctx* c) { return c->fused && fused_possible(c); }
+
+// the coefficient cubes z_V,j of a union of spectral bases (current set, or the other)
+void* uz(muffin_ctx* c, int j) { return c->ws + c->lay.uz[c->cur][j]; }
+void* uz_alt(muffin_ctx* c, int j) { return c->ws + c->lay.uz[1 - c->cur][j]; }
 
 // the row pass of step I: Z = row spectra of B_rest, unless Z holds them
 // already (after a fused pass)
@@ -89,6 +97,13 @@ int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
     g.report = report;
     g.vpart = (double*)P(c, c->lay.vpart);
     g.partials = (double*)P(c, c->lay.partials);
+    g.dense = spectral_dense(s, c->params);
+    g.n_nu = c->params.n_nu;
+    if (g.n_nu > 1)
+        for (int j = 0; j < g.n_nu; ++j) {
+            g.uz[j] = uz(c, j);
+            g.uzo[j] = report ? uz_alt(c, j) : uz(c, j);
+        }
     HIP_TRY(launch_spectral(s.dtype, g, spec_args(c->params), nblocks, c->stream));
     c->zvalid = 0;        // B_rest written; Z holds the previous step I's spectrum
     if (report) {
@@ -164,8 +179,10 @@ int one_pass(muffin_ctx* c) {
 }
 
 int recompute_brest(muffin_ctx* c) {
+    // with a union of spectral bases the third state array is S itself
     HIP_TRY(launch_brest(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), st(c, ST_ZV), st(c, ST_GS),
-                         P(c, c->lay.brest), voxels(c->shape), spec_args(c->params), c->stream));
+                         P(c, c->lay.brest), voxels(c->shape), spec_args(c->params), c->stream,
+                         spectral_union(c->params)));
     c->zvalid = 0;
     return c->lay.n_w ? dict_brest(c) : MUFFIN_OK;
 }
@@ -206,18 +223,20 @@ int upload_tables(muffin_ctx* c) {
         t32[2 * k] = float(cr);
         t32[2 * k + 1] = float(-sr);
     }
-    // dense DCT-II matrix, zero-padded to the spectral kernel's register width
-    const int L = s.L, LT = dense_width(L);
-    std::vector<double> d64(size_t(LT) * LT, 0.0);
-    std::vector<float> d32(size_t(LT) * LT, 0.0f);
-    const long double pi = 3.141592653589793238462643383279502884L;
-    for (int k = 0; k < L; ++k) {
-        const long double a = k == 0 ? sqrtl(1.0L / L) : sqrtl(2.0L / L);
-        for (int l = 0; l < L; ++l) {
-            const long double v = a * cosl(pi * (long double)((2 * l + 1) * k) / (long double)(2 * L));
-            d64[size_t(k) * LT + l] = double(v);
-            d32[size_t(k) * LT + l] = float(v);
-        }
+    // the dense band transform of each spectral basis j, zero-padded to the
+    // kernels' register width: D_j[k * LT + l] = W_j[l][k]
+    const int L = s.L, LT = dense_width(L), m = c->params.n_nu;
+    std::vector<double> d64(size_t(m) * LT * LT, 0.0);
+    std::vector<float> d32(size_t(m) * LT * LT, 0.0f);
+    std::vector<long double> W(size_t(L) * L);
+    for (int j = 0; j < m; ++j) {
+        if (int rc = spectral_basis_ld(c->params.spectral[j], L, W.data())) return rc;
+        for (int k = 0; k < L; ++k)
+            for (int l = 0; l < L; ++l) {
+                const size_t o = size_t(j) * LT * LT + size_t(k) * LT + l;
+                d64[o] = double(W[size_t(l) * L + k]);
+                d32[o] = float(W[size_t(l) * L + k]);
+            }
     }
     HIP_TRY(hipMemcpy(P(c, c->lay.tw64), t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
     if (s.dtype == MUFFIN_F64) {
@@ -274,8 +293,9 @@ int pass_with_report(muffin_ctx* c, muffin_report* rep) {
     rep->iters = c->iters;
     rep->r_pri = std::sqrt(h[RED_R2]);
     rep->r_dual = std::sqrt(h[RED_S2]);
-    rep->eps_pri = std::sqrt(4.0 * nv) * p.eps_abs + p.eps_rel * (Ax > Bz ? Ax : Bz);
-    rep->eps_dual = std::sqrt(2.0 * nv) * p.eps_abs + p.eps_rel * Aty;
+    // constraint space (2 + n_s + m_nu) nv entries, block 1 (1 + m_nu) nv (n_s = 1 here)
+    rep->eps_pri = std::sqrt((3.0 + p.n_nu) * nv) * p.eps_abs + p.eps_rel * (Ax > Bz ? Ax : Bz);
+    rep->eps_dual = std::sqrt((1.0 + p.n_nu) * nv) * p.eps_abs + p.eps_rel * Aty;
     rep->objective = 0.5 * (c->ynorm2 + h[RED_NQ]) + 0.5 * p.mu_eps * h[RED_P2] + p.mu_s * h[RED_P1]
                      + p.mu_nu * h[RED_DCTP1];
     rep->E = h[RED_E];
@@ -450,7 +470,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             int nbk = 0;
             const int mode = fused ? 2 : (k == K ? 1 : 0);
             HIP_TRY(launch_adj_spectral(dt, A, P(c, c->lay.dctm), s.L, npix, a, mode, partials, partials1, &nbk,
-                                        st_));
+                                        st_, spectral_dense(s, c->params)));
             if (fused) HIP_TRY(launch_grad_accum(partials1, nbk, acc, st_));
             HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
             // B-bar = Q^{-1} X-bar (Q is symmetric)
@@ -525,6 +545,14 @@ int grad_args(const muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx,
         set_error("%s: the reverse sweep is built for band counts up to 128 (L = %d)", what, c->shape.L);
         return MUFFIN_EUNSUPPORTED;
     }
+    if (spectral_union(c->params)) {
+        set_error("%s: the reverse sweep is built for one spectral basis (n_nu = %d)", what, c->params.n_nu);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    if (spectral_dense(c->shape, c->params) && c->shape.L > 32) {
+        set_error("%s: the reverse sweep's dense band transform is built for L <= 32 (L = %d)", what, c->shape.L);
+        return MUFFIN_EUNSUPPORTED;
+    }
     if (K < 1 || ckpt_every < 1) {
         set_error("K = %d and ckpt_every = %d must be >= 1", K, ckpt_every);
         return MUFFIN_EINVAL;
@@ -556,7 +584,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
         set_error("psf, dirty and workspace must be non-NULL device pointers");
         return MUFFIN_EINVAL;
     }
-    const Layout lay = make_layout(shape, params->n_s);
+    const Layout lay = make_layout(shape, params->n_s, params->n_nu);
     if (ws_bytes < lay.total) {
         set_error("workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, lay.total);
         return MUFFIN_EWORKSPACE;
@@ -750,13 +778,16 @@ int muffin_get_p(muffin_ctx* c, void* p_out) {
     return MUFFIN_OK;
 }
 
-// state arrays of a snapshot: the four of the reduced state, X, then the
-// coefficient cube z_b of every wavelet basis
-static int snapshot_arrays(const muffin_ctx* c) { return kNumState + 1 + c->lay.n_w; }
+// state arrays of a snapshot: the four of the reduced state, X, the
+// coefficient cube z_b of every wavelet basis, then (a union of spectral
+// bases) the coefficient cube z_V,j of every spectral basis
+static int snapshot_unions(const muffin_ctx* c) { return c->params.n_nu > 1 ? c->params.n_nu : 0; }
+static int snapshot_arrays(const muffin_ctx* c) { return kNumState + 1 + c->lay.n_w + snapshot_unions(c); }
 static char* snapshot_array(muffin_ctx* c, int i) {
     if (i < kNumState) return (char*)st(c, i);
     if (i == kNumState) return P(c, c->lay.x);
-    return P(c, c->lay.wz[i - kNumState - 1]);
+    if (i < kNumState + 1 + c->lay.n_w) return P(c, c->lay.wz[i - kNumState - 1]);
+    return (char*)uz(c, i - kNumState - 1 - c->lay.n_w);
 }
 
 size_t muffin_state_bytes(const muffin_ctx* c) {
@@ -814,15 +845,29 @@ int muffin_set_params(muffin_ctx* c, const muffin_params* params) {
         set_error("the spatial dictionary (n_s, spatial) is fixed at setup");
         return MUFFIN_EINVAL;
     }
+    if (params->n_nu != c->params.n_nu ||
+        std::memcmp(params->spectral, c->params.spectral, sizeof(int) * size_t(params->n_nu)) != 0) {
+        set_error("the spectral dictionary (n_nu, spectral) is fixed at setup");
+        return MUFFIN_EINVAL;
+    }
     const muffin_params old = c->params;
     drop_graphs(c);      // the parameters are kernel arguments of the recorded pass
     if (old.rho_P != params->rho_P || old.rho_T != params->rho_T || old.rho_V != params->rho_V) {
-        // keep P, Gamma_P, S and T, Gamma_T of the stored state under the new rho's
-        HIP_TRY(launch_reencode(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), st(c, ST_ZV), st(c, ST_GS),
-                                voxels(c->shape), old.rho_P / params->rho_P, old.rho_T / params->rho_T,
-                                old.mu_s / old.rho_T,
+        // keep P, Gamma_P, S and T, Gamma_T of the stored state under the new
+        // rho's (a union keeps S itself; its z_V,j re-encode below)
+        const bool un = spectral_union(old);
+        HIP_TRY(launch_reencode(c->shape.dtype, st(c, ST_ZP), st(c, ST_ZT), un ? nullptr : st(c, ST_ZV),
+                                st(c, ST_GS), voxels(c->shape), old.rho_P / params->rho_P,
+                                old.rho_T / params->rho_T, old.mu_s / old.rho_T,
                                 old.rho_V != params->rho_V ? 1.0 / old.rho_V - 1.0 / params->rho_V : 0.0,
                                 c->stream));
+        if (un && old.rho_V != params->rho_V) {
+            void* z[kMaxSpectral];
+            for (int j = 0; j < old.n_nu; ++j) z[j] = uz(c, j);
+            HIP_TRY(launch_union_reencode(c->shape.dtype, st(c, ST_ZV), z, old.n_nu, P(c, c->lay.dctm),
+                                          c->shape.L, long(c->shape.ny) * c->shape.nx, old.rho_V / params->rho_V,
+                                          c->stream));
+        }
         if (old.rho_T != params->rho_T)
             if (int rc2 = dict_reencode(c, old.rho_T / params->rho_T, old.mu_s / old.rho_T)) return rc2;
     }
@@ -986,7 +1031,7 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
     // fused or not: the spectral pass and the fused kernel on a copy of the
     // state in the second set (X of the fused kernel into the B_rest buffer)
     int fu = 0;
-    if (e == hipSuccess && c->lay.n_w == 0 && fused_supported(dt, s.nx, s.ny, s.L)) {
+    if (e == hipSuccess && fused_possible(c)) {
         const size_t nb = voxels(s) * elem_size(s);
         for (int i = 0; i < kNumState && e == hipSuccess; ++i)
             e = hipMemcpyAsync(st_alt(c, i), st(c, i), nb, hipMemcpyDeviceToDevice, c->stream);
@@ -1055,7 +1100,7 @@ int muffin_get_schedule(const muffin_ctx* c, int schedule[3]) {
 }
 
 int muffin_fused_available(const muffin_ctx* c) {
-    return c && c->lay.n_w == 0 && fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L) ? 1 : 0;
+    return c && !c->batch && fused_possible(c) ? 1 : 0;
 }
 
 int muffin_set_graph(muffin_ctx* c, int enable) {

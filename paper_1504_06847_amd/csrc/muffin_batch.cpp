@@ -302,6 +302,10 @@ int check_shapes(int n, const muffin_shape* shapes, const muffin_params* params)
             set_error("cube %d: batches take band counts up to 128 (L = %d)", i, shapes[i].L);
             return MUFFIN_EUNSUPPORTED;
         }
+        if (params[i].n_nu != 1 || params[i].spectral[0] != MUFFIN_DCT2_ORTHO) {
+            set_error("cube %d: batches run the DCT spectral basis alone", i);
+            return MUFFIN_EUNSUPPORTED;
+        }
         if (shapes[i].dtype != shapes[0].dtype) {
             set_error("cube %d has dtype %d, cube 0 has %d: a batch has one dtype", i, shapes[i].dtype,
                       shapes[0].dtype);

@@ -158,9 +158,10 @@ struct AdjArrays {
 // where adj_single_descriptor holds: every band array within 2^30 bytes).
 // Both kernels run one thread per pixel (npix a power of two, at least 64).
 bool adj_single_descriptor(int L, unsigned band_bytes);
+// dense: the band transform is the dense product with D (up to 32 bands)
 hipError_t launch_adj_spectral(int dtype, const AdjArrays& A, const void* D, int L, long npix,
                                const SpecArgs& a, int mode, double* partials, double* partials1, int* nblocks,
-                               hipStream_t s);
+                               hipStream_t s, bool dense = false);
 hipError_t launch_adj_step1(int dtype, const void* Bb, const void* zP, const void* zT, const void* zV,
                             const void* GS, const void* X, void* aP, void* aT, void* aS, void* aG, long npix, int L,
                             const SpecArgs& a, double* partials, int* nblocks, hipStream_t s);
@@ -195,19 +196,24 @@ hipError_t launch_fused_group(int dtype, int nx, int L, const FusedDesc* d, int 
 hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
                         const SpecArgs& a, const void* tw, int twlog, hipStream_t s);
 
-// Arrays of one spectral pass.  st: the state read (z_P, z_T, z_V, Gamma_S);
-// out: where the new state goes (= st except in a reporting pass).
+// Arrays of one spectral pass.  st: the state read (z_P, z_T, z_V, Gamma_S;
+// for a union of spectral bases z_P, z_T, S, Gamma_S); out: where the new
+// state goes (= st except in a reporting pass).
 struct SpecLaunch {
     const void* X;
     void* st[4];
     void* out[4];
     void* brest;
-    const void* dctm;
+    const void* dctm;   // the dense transform(s): per basis D[k * LT + l] = W[l][k], LT = dense_width(L)
     int L;
     long npix;
-    bool report;        // also run k_report: FP64 partials (RED_NQ per block)
+    bool report;        // also run the reporting kernels: FP64 partials (RED_NQ per block)
     double* vpart;      // one double per block: sum of V^2 (reporting pass)
     double* partials;   // RED_NQ doubles per block (reporting pass)
+    bool dense = false; // the band transform is the dense product with dctm (else the fast DCT)
+    int n_nu = 1;       // spectral bases; > 1: a union, with the coefficient cubes below
+    void* uz[4] = {nullptr, nullptr, nullptr, nullptr};    // z_V,j read
+    void* uzo[4] = {nullptr, nullptr, nullptr, nullptr};   // z_V,j written
 };
 
 // Spectral pass (steps II-VI of one iteration) over every pixel.
@@ -272,8 +278,14 @@ hipError_t launch_dwt_inv0(int dtype, int K, const double* h, const void* llin, 
 
 // Elementwise helpers.
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// B_rest from the stored state; s_stored: the third array holds S itself (a
+// union of spectral bases) instead of z_V = S - Gamma_S / rho_V
 hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* zV, const void* GS,
-                        void* Brest, size_t n, const SpecArgs& a, hipStream_t s);
+                        void* Brest, size_t n, const SpecArgs& a, hipStream_t s, bool s_stored = false);
+// A union of spectral bases under a new rho_V (ratio = rho_V / rho_V'):
+// z_V,j <- (S W_j) (1 - ratio) + z_V,j ratio, which keeps S and Gamma_V,j
+hipError_t launch_union_reencode(int dtype, const void* S, void* const* uz, int n_nu, const void* D, int L,
+                                 long npix, double ratio, hipStream_t s);
 hipError_t launch_positive(int dtype, const void* z, void* out, size_t n, hipStream_t s);
 // z_P <- max(0, z_P) - rP max(0, -z_P);  z_T <- soft(z_T, tau) + rT clip(z_T, tau);
 // z_V <- z_V + dV Gamma_S (dV = 1 / rho_V - 1 / rho_V', skipped when 0); a

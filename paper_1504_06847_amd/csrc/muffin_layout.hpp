@@ -14,6 +14,7 @@ enum StateIdx { ST_ZP = 0, ST_ZT = 1, ST_ZV = 2, ST_GS = 3 };
 
 constexpr int kMaxWavelets = 8;  // Db1..Db8 beside the Dirac basis
 constexpr int kMaxDwtLevels = 4;
+constexpr int kMaxSpectral = MUFFIN_MAX_SPECTRAL;
 
 struct Layout {
     size_t state[2][kNumState];   // current and alternate state sets (a reporting
@@ -28,6 +29,11 @@ struct Layout {
     size_t wtmp[kMaxWavelets][kMaxDwtLevels];
     size_t wfilt;
     int n_w, levels;
+    // spectral bases: their number, and with more than one (a union) the
+    // prox input of each basis's soft threshold, z_V,j = S W_j - Gamma_V,j /
+    // rho_V in that basis's coefficients, in both state sets
+    int n_nu;
+    size_t uz[2][kMaxSpectral];
     size_t total;
     size_t setup_scratch_bytes, state_region_bytes;
     int nblk;
@@ -36,13 +42,21 @@ struct Layout {
 void set_error(const char* fmt, ...);
 int validate_shape(const muffin_shape* s);
 int validate_params(const muffin_params* p);
-Layout make_layout(const muffin_shape* s, int n_s = 1);
+Layout make_layout(const muffin_shape* s, int n_s = 1, int n_nu = 1);
+// whether the spectral transform of these parameters is a dense L x L
+// product (any basis but the DCT alone at a power-of-two band count) and
+// whether W_nu is a union of bases
+bool spectral_dense(const muffin_shape& s, const muffin_params& p);
+inline bool spectral_union(const muffin_params& p) { return p.n_nu > 1; }
+// the orthonormal spectral basis `code` for L bands, row-major L x L,
+// spectrum of a pixel = x W (long double; EINVAL for a bad code or L)
+int spectral_basis_ld(int code, int L, long double* W);
 // DWT depth of the wavelet bases: 4 levels, fewer when the smaller image side
 // would leave a coarsest band under 2 x 2
 int dwt_levels(int nx, int ny);
 int max_blocks_host(int L, int ny, int nx);
 
 // register width of the dense DCT used for band counts that are not powers of two
-inline int dense_width(int L) { return L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 32 ? 32 : L)); }
+inline int dense_width(int L) { return L <= 8 ? 8 : (L <= 16 ? 16 : (L <= 32 ? 32 : (L <= 64 ? 64 : L))); }
 
 }  // namespace muffin

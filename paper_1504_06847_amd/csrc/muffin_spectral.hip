@@ -483,23 +483,27 @@ static hipError_t spectral_split_t(const SpecLaunch& g, const SpecArgs& a, hipSt
 
 template <typename T>
 static hipError_t spectral_dispatch(const SpecLaunch& g, const SpecArgs& a, hipStream_t s) {
-    switch (g.L) {
-        case 1: return spectral_t<T, 1, false>(g, a, s);
-        case 2: return spectral_t<T, 2, false>(g, a, s);
-        case 4: return spectral_t<T, 4, false>(g, a, s);
-        case 8: return spectral_t<T, 8, false>(g, a, s);
-        case 16: return spectral_t<T, 16, false>(g, a, s);
-        case 32: return spectral_t<T, 32, false>(g, a, s);
-        case 64: return spectral_t<T, 64, false>(g, a, s);
-        case 128: return spectral_t<T, 128, false>(g, a, s);
-        case 256: return spectral_split_t<T>(g, a, s);
-        default: break;
+    if (!g.dense) {
+        switch (g.L) {
+            case 1: return spectral_t<T, 1, false>(g, a, s);
+            case 2: return spectral_t<T, 2, false>(g, a, s);
+            case 4: return spectral_t<T, 4, false>(g, a, s);
+            case 8: return spectral_t<T, 8, false>(g, a, s);
+            case 16: return spectral_t<T, 16, false>(g, a, s);
+            case 32: return spectral_t<T, 32, false>(g, a, s);
+            case 64: return spectral_t<T, 64, false>(g, a, s);
+            case 128: return spectral_t<T, 128, false>(g, a, s);
+            case 256: return spectral_split_t<T>(g, a, s);
+            default: break;
+        }
     }
-    // band counts that are not powers of two: dense DCT, up to 32 bands
-    if (g.L < 1 || g.L > 32) return hipErrorInvalidValue;
+    // the dense product with dctm: band counts that are not powers of two
+    // (the DCT), and the other spectral bases, up to 32 bands or 64
+    if (g.L < 1 || (g.L > 32 && g.L != 64)) return hipErrorInvalidValue;
     if (g.L <= 8) return spectral_t<T, 8, true>(g, a, s);
     if (g.L <= 16) return spectral_t<T, 16, true>(g, a, s);
-    return spectral_t<T, 32, true>(g, a, s);
+    if (g.L <= 32) return spectral_t<T, 32, true>(g, a, s);
+    return spectral_t<T, 64, true>(g, a, s);
 }
 
 int spectral_block_threads(long npix) { return npix < SPEC_NTH ? (int)npix : SPEC_NTH; }
@@ -534,20 +538,281 @@ hipError_t launch_spectral_group(int dtype, int L, int nth, const SpecDesc* d, i
                       : spectral_group_t<double>(L, d, n, nblocks, nth, s);
 }
 
+// a union of spectral bases (defined with its kernels below)
+template <typename T>
+static hipError_t union_dispatch(const SpecLaunch& g, const SpecArgs& a, hipStream_t s);
+
 hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, int* nblocks_out,
                            hipStream_t s) {
-    if (nblocks_out)
-        *nblocks_out = (int)(g.L == 2 * SPLIT_N ? g.npix / 64 : g.npix / (g.npix < SPEC_NTH ? g.npix : SPEC_NTH));
+    const bool split = g.L == 2 * SPLIT_N && !g.dense && g.n_nu == 1;
+    if (nblocks_out) *nblocks_out = (int)(split ? g.npix / 64 : g.npix / (g.npix < SPEC_NTH ? g.npix : SPEC_NTH));
+    if (g.n_nu > 1) return dtype == 0 ? union_dispatch<float>(g, a, s) : union_dispatch<double>(g, a, s);
     return dtype == 0 ? spectral_dispatch<float>(g, a, s) : spectral_dispatch<double>(g, a, s);
+}
+
+// ------------------------------------------------------------------ a union of spectral bases
+// W_nu = [W_1 .. W_m], m orthonormal bases, each applied as a dense product
+// (D + j LT^2 holds W_j as D_j[k * LT + l] = W_j[l][k]).  With m > 1 the
+// multiplier Gamma_V has m coefficient blocks that Gamma_S = Gamma_V W_nu^T
+// does not determine, so the state is z_P, z_T, S, Gamma_S and, per basis,
+// z_V,j = S W_j - Gamma_V,j / rho_V (the input of step IV's soft threshold,
+// in basis j's coefficients).  Per pixel (Section 3, steps IV-VI):
+//   V_j = soft(z_V,j, mu_nu / rho_V)                           (step IV)
+//   q = sum_j V_j W_j^T,  S' = (rho_V q + rho_S X) / (m rho_V + rho_S)
+//       (step V: sum_j Gamma_V,j W_j^T = Gamma_S + ... cancels exactly;
+//        the oracle's closed form with the m_nu rho_V denominator)
+//   Gamma_S' = Gamma_S + rho_S (S' - X)                         (step VI)
+//   z_V,j' = S' W_j - Gamma_V,j' / rho_V = (2 S' - S) W_j + z_V,j - V_j
+//          = (2 S' - S) W_j + clip(z_V,j, mu_nu / rho_V)
+// and B_rest = rho_T (2 T - z_T) + rho_P |z_P| + Gamma_S' + rho_S S'.
+struct UnionZ {
+    char* in[4];
+    char* out[4];
+};
+
+template <typename T, int LT>
+__device__ __forceinline__ void dense_fwd(T (&c)[LT], const T (&u)[LT], const T* __restrict__ Dj) {
+#pragma unroll
+    for (int k = 0; k < LT; ++k) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < LT; ++l) acc += Dj[k * LT + l] * u[l];
+        c[k] = acc;
+    }
+}
+
+template <typename T, int LT>
+__global__ void __launch_bounds__(SPEC_NTH)
+k_spectral_union(SpecArrays A, UnionZ Z, const T* __restrict__ D, int Lrt, int m, SpecArgs a) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const unsigned bb = A.band_bytes;
+    const int gs_ = A.gshift;
+    const int L = Lrt;
+    const BandArray<T> X{A.X, bb, gs_}, Brest{A.Brest, bb, gs_};
+    const BandArray<T, kStreamCpol> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.zV, bb, gs_}, GS{A.GS, bb, gs_};
+    const BandArray<T, kStreamCpol> zPo{A.zPo, bb, gs_}, zTo{A.zTo, bb, gs_}, So{A.zVo, bb, gs_},
+        GSo{A.GSo, bb, gs_};
+    const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
+    const T tauT = T(a.tau_T), tauV = T(a.tau_V);
+    const T inv_mVS = T(1.0 / (double(m) * a.rho_V + a.rho_S));
+    T q[LT];
+#pragma unroll
+    for (int l = 0; l < LT; ++l) q[l] = T(0);
+    // steps IV and V: q = sum_j soft(z_V,j) W_j^T
+    for (int j = 0; j < m; ++j) {
+        const BandArray<T, kStreamCpol> zv{Z.in[j], bb, gs_};
+        const T* Dj = D + (long)j * LT * LT;
+        T c[LT];
+#pragma unroll
+        for (int k = 0; k < LT; ++k) c[k] = k < L ? softt(zv.load(k, off), tauV) : T(0);
+#pragma unroll
+        for (int k = 0; k < LT; ++k)
+#pragma unroll
+            for (int l = 0; l < LT; ++l) q[l] += Dj[k * LT + l] * c[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // steps II, III, V, VI band by band; q[l] becomes 2 S' - S
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+        if (l < L) {
+            const T x = X.load(l, off), so = S.load(l, off), gs = GS.load(l, off), zp = zP.load(l, off),
+                    zt = zT.load(l, off);
+            const T sn = (rhoV * q[l] + rhoS * x) * inv_mVS;
+            const T gs2 = gs + rhoS * (sn - x);
+            const T zp2 = x - (zp < T(0) ? -zp : T(0));
+            const T zt2 = x + clipt(zt, tauT);
+            const T tt = softt(zt2, tauT);
+            So.store(l, off, sn);
+            GSo.store(l, off, gs2);
+            zPo.store(l, off, zp2);
+            zTo.store(l, off, zt2);
+            Brest.store(l, off, rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * sn);
+            q[l] = T(2) * sn - so;
+        } else {
+            q[l] = T(0);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // z_V,j' = (2 S' - S) W_j + clip(z_V,j)
+    for (int j = 0; j < m; ++j) {
+        const BandArray<T, kStreamCpol> zv{Z.in[j], bb, gs_}, zvo{Z.out[j], bb, gs_};
+        T c[LT];
+        dense_fwd<T, LT>(c, q, D + (long)j * LT * LT);
+#pragma unroll
+        for (int k = 0; k < LT; ++k)
+            if (k < L) zvo.store(k, off, c[k] + clipt(zv.load(k, off), tauV));
+    }
+}
+
+// The FP64 sums of a reporting pass for a union (every RED slot), from the
+// old state (z_P, z_T, S, Gamma_S, z_V,j), the new one (primed) and X:
+//   r^2  = ||P - X||^2 + ||T - X||^2 + ||S' - X||^2 + sum_j ||V_j - S' W_j||^2
+//   s^2  = ||rho_P dP + rho_T dT + rho_S dS||^2 + m rho_V^2 ||dS||^2
+//   E    = rho_P ||dP||^2 + rho_T ||dT||^2 + (rho_S + m rho_V) ||dS||^2
+//          + ||dGamma_P||^2 / rho_P + ||dGamma_T||^2 / rho_T + ||dGamma_S||^2 / rho_S
+//          + rho_V sum_j ||V_j - S' W_j||^2         (dGamma_V,j = rho_V (V_j - S' W_j))
+//   ||X||^2, sum_j ||V_j||^2, ||P||^2 + ||T||^2 + (m + 1) ||S'||^2,
+//   ||Gamma_P + Gamma_T + Gamma_S'||^2 + sum_j ||Gamma_V,j'||^2 with
+//   Gamma_V,j' = rho_V (S' W_j - z_V,j'), ||P||^2, sum P, sum_j |P W_j|_1
+// (V_j = soft(z_V,j) of the old state; W_nu orthonormal per basis).
+template <typename T, int LT>
+__global__ void __launch_bounds__(SPEC_NTH)
+k_report_union(SpecArrays A, UnionZ Z, const T* __restrict__ D, int Lrt, int m, SpecArgs a,
+               double* __restrict__ partials) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const unsigned bb = A.band_bytes;
+    const int gs_ = A.gshift;
+    const int L = Lrt;
+    const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.zV, bb, gs_}, GS{A.GS, bb, gs_},
+        zPo{A.zPo, bb, gs_}, zTo{A.zTo, bb, gs_}, So{A.zVo, bb, gs_}, GSo{A.GSo, bb, gs_};
+    const T rP = T(a.rho_P), rT = T(a.rho_T), rV = T(a.rho_V), rS = T(a.rho_S), tT = T(a.tau_T), tV = T(a.tau_V);
+    const T irP = T(1.0 / a.rho_P), irT = T(1.0 / a.rho_T), irS = T(1.0 / a.rho_S);
+    const T mT = T(m);
+    double r2 = 0, s2 = 0, x2 = 0, v2 = 0, bz2 = 0, aty2 = 0, e = 0, p2 = 0, p1 = 0, pd = 0;
+    T sv[LT], pv[LT];
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+        sv[l] = T(0);
+        pv[l] = T(0);
+        if (l < L) {
+            const T x = X.load(l, off);
+            const T zp = zP.load(l, off), zt = zT.load(l, off), go = GS.load(l, off), so = S.load(l, off);
+            const T zp2 = zPo.load(l, off), zt2 = zTo.load(l, off), gn = GSo.load(l, off), sn = So.load(l, off);
+            const T P = zp2 > T(0) ? zp2 : T(0), Po = zp > T(0) ? zp : T(0);
+            const T Tn = softt(zt2, tT), To = softt(zt, tT);
+            const T gp = rP * (zp2 < T(0) ? -zp2 : T(0)), gpo = rP * (zp < T(0) ? -zp : T(0));
+            const T gt = -rT * clipt(zt2, tT), gto = -rT * clipt(zt, tT);
+            const T dP = P - Po, dT = Tn - To, dS = sn - so, dg = gn - go;
+            const T a1 = P - x, a2 = Tn - x, a3 = sn - x;
+            r2 += double(a1 * a1 + a2 * a2 + a3 * a3);
+            const T sx = rP * dP + rT * dT + rS * dS;
+            s2 += double(sx * sx + mT * rV * rV * dS * dS);
+            x2 += double(x * x);
+            bz2 += double(P * P + Tn * Tn + (mT + T(1)) * sn * sn);
+            const T g = gp + gt + gn;
+            aty2 += double(g * g);
+            const T dgp = gp - gpo, dgt = gt - gto;
+            e += double(rP * dP * dP + rT * dT * dT + (rS + mT * rV) * dS * dS + dgp * dgp * irP +
+                        dgt * dgt * irT + dg * dg * irS);
+            p2 += double(P * P);
+            p1 += double(P);
+            sv[l] = sn;
+            pv[l] = P;
+        }
+    }
+    for (int j = 0; j < m; ++j) {
+        const BandArray<T> zv{Z.in[j], bb, gs_}, zvo{Z.out[j], bb, gs_};
+        const T* Dj = D + (long)j * LT * LT;
+        T c[LT];
+        dense_fwd<T, LT>(c, sv, Dj);
+#pragma unroll
+        for (int k = 0; k < LT; ++k) {
+            if (k < L) {
+                const T V = softt(zv.load(k, off), tV);
+                const T dv = V - c[k];
+                const T gv = rV * (c[k] - zvo.load(k, off));
+                r2 += double(dv * dv);
+                e += double(rV * dv * dv);
+                v2 += double(V * V);
+                aty2 += double(gv * gv);
+            }
+        }
+        dense_fwd<T, LT>(c, pv, Dj);
+#pragma unroll
+        for (int k = 0; k < LT; ++k) pd += fabs(double(c[k]));
+    }
+    __shared__ double sh[SPEC_NTH / 64];
+    const double vals[RED_NQ] = {r2, s2, x2, v2, bz2, aty2, e, p2, p1, pd};
+#pragma unroll
+    for (int q = 0; q < RED_NQ; ++q) {
+        const double sq = block_sum_s<SPEC_NTH>(vals[q], sh);
+        if (threadIdx.x == 0) partials[(long)blockIdx.x * RED_NQ + q] = sq;
+    }
+}
+
+// z_V,j <- (S W_j)(1 - ratio) + z_V,j ratio (new rho_V, ratio = rho_V / rho_V')
+template <typename T, int LT>
+__global__ void __launch_bounds__(SPEC_NTH)
+k_union_reencode(const T* __restrict__ S, UnionZ Z, const T* __restrict__ D, int Lrt, int m, long npix, T ratio) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    T sv[LT];
+#pragma unroll
+    for (int l = 0; l < LT; ++l) sv[l] = l < Lrt ? S[(long)l * npix + p] : T(0);
+    for (int j = 0; j < m; ++j) {
+        T c[LT];
+        dense_fwd<T, LT>(c, sv, D + (long)j * LT * LT);
+        T* z = (T*)Z.in[j];
+#pragma unroll
+        for (int k = 0; k < LT; ++k)
+            if (k < Lrt) z[(long)k * npix + p] = c[k] * (T(1) - ratio) + z[(long)k * npix + p] * ratio;
+    }
+}
+
+template <typename T, int LT>
+static hipError_t union_t(const SpecLaunch& g, const SpecArgs& a, hipStream_t s) {
+    const long npix = g.npix;
+    const int nth = npix < SPEC_NTH ? (int)npix : SPEC_NTH;
+    if (npix < 64 || (npix & (npix - 1)) != 0) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(npix / nth));
+    const unsigned bb = (unsigned)(npix * (long)sizeof(T));
+    SpecArrays A{(char*)g.X, (char*)g.st[0], (char*)g.st[1], (char*)g.st[2], (char*)g.st[3],
+                 (char*)g.out[0], (char*)g.out[1], (char*)g.out[2], (char*)g.out[3], (char*)g.brest,
+                 bb, band_group_shift(bb)};
+    UnionZ Z{};
+    for (int j = 0; j < g.n_nu; ++j) {
+        Z.in[j] = (char*)g.uz[j];
+        Z.out[j] = (char*)g.uzo[j];
+    }
+    hipLaunchKernelGGL((k_spectral_union<T, LT>), grid, dim3(nth), 0, s, A, Z, (const T*)g.dctm, g.L, g.n_nu, a);
+    if (g.report) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // every partial sum of the convergence checks, the spectral terms included
+        hipLaunchKernelGGL((k_report_union<T, LT>), grid, dim3(nth), 0, s, A, Z, (const T*)g.dctm, g.L, g.n_nu, a,
+                           g.partials);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t union_dispatch(const SpecLaunch& g, const SpecArgs& a, hipStream_t s) {
+    if (g.L < 1 || (g.L > 32 && g.L != 64) || g.n_nu < 2 || g.n_nu > 4) return hipErrorInvalidValue;
+    if (g.L <= 8) return union_t<T, 8>(g, a, s);
+    if (g.L <= 16) return union_t<T, 16>(g, a, s);
+    if (g.L <= 32) return union_t<T, 32>(g, a, s);
+    return union_t<T, 64>(g, a, s);
+}
+
+template <typename T>
+static hipError_t union_reencode_t(const void* S, void* const* uz, int n_nu, const void* D, int L, long npix,
+                                   double ratio, hipStream_t s) {
+    UnionZ Z{};
+    for (int j = 0; j < n_nu; ++j) Z.in[j] = (char*)uz[j];
+    const dim3 grid((unsigned)((npix + SPEC_NTH - 1) / SPEC_NTH)), blk(SPEC_NTH);
+    if (L <= 8) hipLaunchKernelGGL((k_union_reencode<T, 8>), grid, blk, 0, s, (const T*)S, Z, (const T*)D, L, n_nu, npix, T(ratio));
+    else if (L <= 16) hipLaunchKernelGGL((k_union_reencode<T, 16>), grid, blk, 0, s, (const T*)S, Z, (const T*)D, L, n_nu, npix, T(ratio));
+    else if (L <= 32) hipLaunchKernelGGL((k_union_reencode<T, 32>), grid, blk, 0, s, (const T*)S, Z, (const T*)D, L, n_nu, npix, T(ratio));
+    else hipLaunchKernelGGL((k_union_reencode<T, 64>), grid, blk, 0, s, (const T*)S, Z, (const T*)D, L, n_nu, npix, T(ratio));
+    return hipGetLastError();
+}
+
+hipError_t launch_union_reencode(int dtype, const void* S, void* const* uz, int n_nu, const void* D, int L,
+                                 long npix, double ratio, hipStream_t s) {
+    if (n_nu < 2 || n_nu > 4 || L < 1 || (L > 32 && L != 64)) return hipErrorInvalidValue;
+    return dtype == 0 ? union_reencode_t<float>(S, uz, n_nu, D, L, npix, ratio, s)
+                      : union_reencode_t<double>(S, uz, n_nu, D, L, npix, ratio, s);
 }
 
 // ------------------------------------------------------------------ element-wise
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_brest(const T* __restrict__ zP, const T* __restrict__ zT, const T* __restrict__ zV,
-        const T* __restrict__ GS, T* __restrict__ Brest, long n, SpecArgs a) {
+        const T* __restrict__ GS, T* __restrict__ Brest, long n, SpecArgs a, bool s_stored) {
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoS = T(a.rho_S), tauT = T(a.tau_T);
-    const T inv_rhoV = T(1.0 / a.rho_V);
+    const T inv_rhoV = s_stored ? T(0) : T(1.0 / a.rho_V);
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const T zt = zT[i], gs = GS[i];
         const T sv = zV[i] + gs * inv_rhoV;
@@ -631,13 +896,15 @@ static unsigned grid_for(long n) {
 }
 
 hipError_t launch_brest(int dtype, const void* zP, const void* zT, const void* zV, const void* GS,
-                        void* Brest, size_t n, const SpecArgs& a, hipStream_t s) {
+                        void* Brest, size_t n, const SpecArgs& a, hipStream_t s, bool s_stored) {
     if (dtype == 0)
         hipLaunchKernelGGL((k_brest<float>), dim3(grid_for(n)), dim3(256), 0, s, (const float*)zP,
-                           (const float*)zT, (const float*)zV, (const float*)GS, (float*)Brest, (long)n, a);
+                           (const float*)zT, (const float*)zV, (const float*)GS, (float*)Brest, (long)n, a,
+                           s_stored);
     else
         hipLaunchKernelGGL((k_brest<double>), dim3(grid_for(n)), dim3(256), 0, s, (const double*)zP,
-                           (const double*)zT, (const double*)zV, (const double*)GS, (double*)Brest, (long)n, a);
+                           (const double*)zT, (const double*)zV, (const double*)GS, (double*)Brest, (long)n, a,
+                           s_stored);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "muffin.h"
 #include "muffin_layout.hpp"
@@ -84,9 +85,70 @@ int validate_params(const muffin_params* p) {
             return MUFFIN_EUNSUPPORTED;
         }
     }
-    if (p->spectral != MUFFIN_DCT2_ORTHO) {
-        set_error("spectral transform %d is not MUFFIN_DCT2_ORTHO", p->spectral);
+    if (p->n_nu < 1 || p->n_nu > kMaxSpectral) {
+        set_error("n_nu = %d spectral bases: 1 to %d are supported", p->n_nu, kMaxSpectral);
         return MUFFIN_EUNSUPPORTED;
+    }
+    for (int j = 0; j < p->n_nu; ++j) {
+        const int b = p->spectral[j];
+        if (b != MUFFIN_DCT2_ORTHO && b != MUFFIN_CHEBYSHEV && b != MUFFIN_SPECTRAL_DIRAC) {
+            set_error("spectral[%d] = %d is not a spectral basis code", j, b);
+            return MUFFIN_EUNSUPPORTED;
+        }
+        for (int i = 0; i < j; ++i) {
+            if (p->spectral[i] == b) {
+                set_error("spectral[%d] = spectral[%d] = %d: the bases of a union are distinct", i, j, b);
+                return MUFFIN_EINVAL;
+            }
+        }
+    }
+    return MUFFIN_OK;
+}
+
+bool spectral_dense(const muffin_shape& s, const muffin_params& p) {
+    const bool pow2 = (s.L & (s.L - 1)) == 0;
+    return !(p.n_nu == 1 && p.spectral[0] == MUFFIN_DCT2_ORTHO && pow2);
+}
+
+int spectral_basis_ld(int code, int L, long double* W) {
+    if (!W || L < 1 || L > 4096) { set_error("spectral basis: bad L = %d or NULL output", L); return MUFFIN_EINVAL; }
+    const long double pi = 3.141592653589793238462643383279502884L;
+    if (code == MUFFIN_DCT2_ORTHO) {
+        for (int l = 0; l < L; ++l)
+            for (int k = 0; k < L; ++k)
+                W[size_t(l) * L + k] = (k == 0 ? sqrtl(1.0L / L) : sqrtl(2.0L / L)) *
+                                       cosl(pi * (long double)((2 * l + 1) * k) / (2.0L * L));
+        return MUFFIN_OK;
+    }
+    if (code == MUFFIN_SPECTRAL_DIRAC) {
+        for (int l = 0; l < L; ++l)
+            for (int k = 0; k < L; ++k) W[size_t(l) * L + k] = l == k ? 1.0L : 0.0L;
+        return MUFFIN_OK;
+    }
+    if (code != MUFFIN_CHEBYSHEV) { set_error("spectral basis code %d unknown", code); return MUFFIN_EINVAL; }
+    // The polynomials of degree < L at the band positions x_l, orthonormal
+    // under the plain sum over the bands: the span of T_0 .. T_k is that of
+    // 1, x, .., x^k, so the orthonormalised Chebyshev columns are the
+    // discrete orthonormal polynomials, built by the Lanczos recurrence on
+    // diag(x): p_0 = 1 / sqrt(L), p_{k+1} = the part of x p_k orthogonal to
+    // p_0 .. p_k (projected out twice), normalised.  The degree-(k+1)
+    // coefficient of x p_k is p_k's, so every column keeps a positive one.
+    std::vector<long double> x(L), q(L);
+    for (int l = 0; l < L; ++l) x[l] = L == 1 ? 0.0L : -1.0L + 2.0L * l / (L - 1);
+    for (int l = 0; l < L; ++l) W[size_t(l) * L] = 1.0L / sqrtl((long double)L);
+    for (int k = 0; k + 1 < L; ++k) {
+        for (int l = 0; l < L; ++l) q[l] = x[l] * W[size_t(l) * L + k];
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int j = 0; j <= k; ++j) {
+                long double c = 0.0L;
+                for (int l = 0; l < L; ++l) c += q[l] * W[size_t(l) * L + j];
+                for (int l = 0; l < L; ++l) q[l] -= c * W[size_t(l) * L + j];
+            }
+        }
+        long double nrm = 0.0L;
+        for (int l = 0; l < L; ++l) nrm += q[l] * q[l];
+        nrm = sqrtl(nrm);
+        for (int l = 0; l < L; ++l) W[size_t(l) * L + k + 1] = q[l] / nrm;
     }
     return MUFFIN_OK;
 }
@@ -101,7 +163,7 @@ int dwt_levels(int nx, int ny) {
     return J < 1 ? 1 : J;
 }
 
-Layout make_layout(const muffin_shape* s, int n_s) {
+Layout make_layout(const muffin_shape* s, int n_s, int n_nu) {
     Layout lay{};
     const size_t sz = s->dtype == MUFFIN_F64 ? 8 : 4;
     const size_t V = size_t(s->L) * s->ny * s->nx;
@@ -114,6 +176,10 @@ Layout make_layout(const muffin_shape* s, int n_s) {
         for (int i = 0; i < kNumState; ++i) lay.state[set][i] = take(V * sz);
     lay.brest = take(V * sz);
     lay.x = take(V * sz);
+    lay.n_nu = n_nu;
+    if (n_nu > 1)
+        for (int set = 0; set < 2; ++set)
+            for (int j = 0; j < n_nu; ++j) lay.uz[set][j] = take(V * sz);
     lay.n_w = n_s > 1 ? n_s - 1 : 0;
     lay.levels = dwt_levels(s->nx, s->ny);
     for (int b = 0; b < lay.n_w; ++b) lay.wz[b] = take(V * sz);
@@ -129,7 +195,7 @@ Layout make_layout(const muffin_shape* s, int n_s) {
     lay.hhnyq = take(size_t(s->L) * s->ny * 2 * sz);
     lay.tw = take(size_t(NT) * 2 * sz);
     lay.tw64 = take(size_t(NT) * 16);
-    lay.dctm = take(size_t(dense_width(s->L)) * dense_width(s->L) * sz);
+    lay.dctm = take(size_t(n_nu) * dense_width(s->L) * dense_width(s->L) * sz);
     lay.nblk = max_blocks_host(s->L, s->ny, s->nx);
     lay.partials = take(size_t(lay.nblk) * kNumRed * 8);
     lay.vpart = take(size_t(lay.nblk) * 8);
@@ -170,7 +236,8 @@ void muffin_default_params(muffin_params* p) {
     p->rho_S = 1.0;
     p->n_s = 1;
     p->spatial[0] = MUFFIN_DIRAC;
-    p->spectral = MUFFIN_DCT2_ORTHO;
+    p->n_nu = 1;
+    p->spectral[0] = MUFFIN_DCT2_ORTHO;
     p->check_every = 10;
     p->eps_abs = 1e-5;
     p->eps_rel = 1e-4;
@@ -179,12 +246,25 @@ void muffin_default_params(muffin_params* p) {
 int muffin_validate(const muffin_shape* shape, const muffin_params* params) {
     int rc = validate_shape(shape);
     if (rc != MUFFIN_OK) return rc;
-    return validate_params(params);
+    if ((rc = validate_params(params)) != MUFFIN_OK) return rc;
+    if (spectral_dense(*shape, *params) && shape->L > 32 && shape->L != 64) {
+        set_error("L = %d: spectral bases other than the DCT alone take L <= 32 or L = 64", shape->L);
+        return MUFFIN_EUNSUPPORTED;
+    }
+    return MUFFIN_OK;
 }
 
 size_t muffin_workspace_bytes(const muffin_shape* shape, const muffin_params* params) {
     if (muffin_validate(shape, params) != MUFFIN_OK) return 0;
-    return make_layout(shape, params->n_s).total;
+    return make_layout(shape, params->n_s, params->n_nu).total;
+}
+
+int muffin_spectral_basis(int code, int L, double* W) {
+    if (!W || L < 1 || L > 4096) { set_error("muffin_spectral_basis: bad L = %d or NULL output", L); return MUFFIN_EINVAL; }
+    std::vector<long double> w(size_t(L) * L);
+    if (int rc = spectral_basis_ld(code, L, w.data())) return rc;
+    for (size_t i = 0; i < w.size(); ++i) W[i] = double(w[i]);
+    return MUFFIN_OK;
 }
 
 const char* muffin_last_error(void) { return g_err; }

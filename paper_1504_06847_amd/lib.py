@@ -25,6 +25,9 @@ MUFFIN_F32 = 0
 MUFFIN_F64 = 1
 MUFFIN_DIRAC = 0
 MUFFIN_DCT2_ORTHO = 0
+MUFFIN_CHEBYSHEV = 1
+MUFFIN_SPECTRAL_DIRAC = 2
+MUFFIN_MAX_SPECTRAL = 4
 MUFFIN_MODE_MSE = 0
 MUFFIN_MODE_VJP = 1
 MUFFIN_MAX_BANDS = 256
@@ -46,8 +49,8 @@ class MuffinParams(Structure):
     _fields_ = [("mu_eps", c_double), ("mu_s", c_double), ("mu_nu", c_double),
                 ("rho_P", c_double), ("rho_T", c_double), ("rho_V", c_double),
                 ("rho_S", c_double), ("n_s", c_int), ("spatial", c_int * 9),
-                ("spectral", c_int), ("check_every", c_int), ("eps_abs", c_double),
-                ("eps_rel", c_double)]
+                ("n_nu", c_int), ("spectral", c_int * 4), ("check_every", c_int),
+                ("eps_abs", c_double), ("eps_rel", c_double)]
 
 
 class MuffinReport(Structure):
@@ -65,6 +68,7 @@ SIGNATURES = [
     ("muffin_workspace_bytes", c_size_t, [POINTER(MuffinShape), POINTER(MuffinParams)]),
     ("muffin_validate", c_int, [POINTER(MuffinShape), POINTER(MuffinParams)]),
     ("muffin_wavelet_filter", c_int, [c_int, POINTER(c_double)]),
+    ("muffin_spectral_basis", c_int, [c_int, c_int, POINTER(c_double)]),
     ("muffin_setup", c_int, [POINTER(c_void_p), POINTER(MuffinShape), POINTER(MuffinParams),
                              c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("muffin_iterate", c_int, [c_void_p, c_int]),
@@ -153,6 +157,11 @@ def make_params(lib=None, **kw) -> MuffinParams:
         if k == "spatial":
             for i, s in enumerate(v):
                 p.spatial[i] = s
+        elif k == "spectral":
+            v = tuple(v) if isinstance(v, (tuple, list)) else (int(v),)
+            p.n_nu = len(v)
+            for i, s in enumerate(v):
+                p.spectral[i] = s
         elif not hasattr(p, k):
             raise TypeError(f"unknown parameter {k}")
         else:

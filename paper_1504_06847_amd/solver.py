@@ -13,7 +13,7 @@ import torch
 from . import lib as L
 
 PARAM_NAMES = ("mu_eps", "mu_s", "mu_nu", "rho_P", "rho_T", "rho_V", "rho_S",
-               "check_every", "eps_abs", "eps_rel", "spatial")
+               "check_every", "eps_abs", "eps_rel", "spatial", "spectral")
 
 # Section 4's spatial dictionary: the Dirac basis and Db1..Db8
 PAPER_DICTIONARY = (0, 1, 2, 3, 4, 5, 6, 7, 8)
@@ -71,8 +71,11 @@ class Solver:
     (defaults: the paper's Section 4 values), ``rho`` to set the four rho's
     at once, check_every, eps_abs, eps_rel, ``spatial`` (the spatial
     dictionary: 0 for the Dirac basis first, then Daubechies orders 1..8;
-    ``PAPER_DICTIONARY`` is Section 4's; default the Dirac basis alone), and
-    ``dtype`` (torch.float32 or torch.float64) for the iteration's precision.
+    ``PAPER_DICTIONARY`` is Section 4's; default the Dirac basis alone),
+    ``spectral`` (the spectral bases W_nu along the bands: a code or a tuple of
+    distinct codes, 0 the DCT-II, 1 the orthonormalised Chebyshev
+    polynomials, 2 the identity; default the DCT alone), and ``dtype``
+    (torch.float32 or torch.float64) for the iteration's precision.
     """
 
     def __init__(self, psf, dirty, *, dtype=torch.float32, device="cuda", stream=None, graph=False,
@@ -175,12 +178,16 @@ class Solver:
         if "spatial" in kw:
             kw["spatial"] = tuple(int(b) for b in kw["spatial"])
             kw["n_s"] = len(kw["spatial"])
+        if "spectral" in kw:
+            sp = kw["spectral"]
+            kw["spectral"] = tuple(int(b) for b in sp) if isinstance(sp, (tuple, list)) else (int(sp),)
         return L.make_params(self._lib, **kw)
 
     @property
     def params(self):
-        d = {k: getattr(self._params, k) for k in PARAM_NAMES if k != "spatial"}
+        d = {k: getattr(self._params, k) for k in PARAM_NAMES if k not in ("spatial", "spectral")}
         d["spatial"] = tuple(self._params.spatial[i] for i in range(self._params.n_s))
+        d["spectral"] = tuple(self._params.spectral[i] for i in range(self._params.n_nu))
         return d
 
     def set_params(self, **params):

@@ -45,8 +45,8 @@ def test_binding_covers_the_header():
 
 def test_struct_layouts_match_header():
     from paper_1504_06847_amd import lib as L
-    # muffin_params: 7 doubles, n_s, spatial[9], spectral, check_every, 2 doubles
-    assert ctypes.sizeof(L.MuffinParams) == 7 * 8 + 4 + 36 + 4 + 4 + 2 * 8
+    # muffin_params: 7 doubles, n_s, spatial[9], n_nu, spectral[4], check_every, 2 doubles
+    assert ctypes.sizeof(L.MuffinParams) == 7 * 8 + 4 + 36 + 4 + 16 + 4 + 2 * 8
     assert ctypes.sizeof(L.MuffinShape) == 16
     assert ctypes.sizeof(L.MuffinReport) == 8 + 6 * 8
 
@@ -66,7 +66,7 @@ def test_default_params_are_the_papers(lib):
 @pytest.mark.parametrize("field,value,code", [
     ("mu_s", -1.0, -1), ("mu_nu", float("nan"), -1), ("mu_eps", float("inf"), -1),
     ("rho_P", 0.0, -1), ("rho_T", -2.0, -1), ("rho_V", float("nan"), -1),
-    ("check_every", 0, -1), ("eps_abs", -1e-3, -1), ("n_s", 10, -2), ("n_s", 0, -2), ("spectral", 3, -2),
+    ("check_every", 0, -1), ("eps_abs", -1e-3, -1), ("n_s", 10, -2), ("n_s", 0, -2), ("n_nu", 0, -2), ("n_nu", 5, -2),
 ])
 def test_parameter_validation(lib, field, value, code):
     from paper_1504_06847_amd import lib as L
@@ -258,3 +258,50 @@ def test_checkpoint_spacing_minimises_recomputed_passes():
     # everything fits: no recompute
     assert best_ckpt_every(20, 1e9, lambda C: cubes(20, C)) == 20
     assert best_ckpt_every(20, 10, lambda C: cubes(20, C)) == 1
+
+
+@pytest.mark.parametrize("spectral,code", [((0,), 0), ((1,), 0), ((2,), 0), ((0, 1), 0), ((0, 1, 2), 0),
+                                           ((3,), -2), ((0, 0), -1), ((1, 2, 1), -1)])
+def test_spectral_dictionary_validation(lib, spectral, code):
+    from paper_1504_06847_amd import lib as L
+    p = L.make_params(lib, spectral=spectral)
+    assert p.n_nu == len(spectral)
+    s = L.MuffinShape(32, 32, 16, 0)
+    assert lib.muffin_validate(ctypes.byref(s), ctypes.byref(p)) == code
+
+
+@pytest.mark.parametrize("Lb,spectral,code", [(64, (1,), 0), (128, (1,), -2), (48, (0,), -2), (24, (0, 2), 0),
+                                              (256, (0,), 0), (256, (0, 1), -2), (128, (0,), 0)])
+def test_spectral_dictionary_band_limits(lib, Lb, spectral, code):
+    """Bases other than the DCT alone take a dense transform: L <= 32 or 64."""
+    from paper_1504_06847_amd import lib as L
+    p = L.make_params(lib, spectral=spectral)
+    s = L.MuffinShape(32, 32, Lb, 0)
+    assert lib.muffin_validate(ctypes.byref(s), ctypes.byref(p)) == code
+
+
+def test_union_workspace_adds_two_cubes_per_basis(lib):
+    """A union of m bases carries one coefficient cube per basis in each of
+    the two state sets."""
+    from paper_1504_06847_amd import lib as L
+    s = L.MuffinShape(32, 32, 16, 0)
+    one = lib.muffin_workspace_bytes(ctypes.byref(s), ctypes.byref(L.make_params(lib, spectral=(1,))))
+    two = lib.muffin_workspace_bytes(ctypes.byref(s), ctypes.byref(L.make_params(lib, spectral=(0, 1))))
+    cube = 32 * 32 * 16 * 4
+    assert two - one >= 4 * cube and two - one < 4 * cube + 16 * 16 * 4 + 16 * 256
+
+
+@pytest.mark.parametrize("L_", [1, 2, 3, 8, 15, 32, 64])
+def test_spectral_bases_match_the_oracle(lib, L_):
+    """The library's bases (the Chebyshev one by a long-double Lanczos
+    recurrence) against the oracle's (exact rational Gram-Schmidt, the DCT by
+    scipy, the identity)."""
+    import oracle as O
+    for code in (0, 1, 2):
+        W = (ctypes.c_double * (L_ * L_))()
+        assert lib.muffin_spectral_basis(code, L_, W) == 0
+        Wl = np.array(W[:]).reshape(L_, L_)
+        np.testing.assert_allclose(Wl, O.basis_matrix(code, L_), atol=2e-15, rtol=0)
+    W = (ctypes.c_double * 4)()
+    assert lib.muffin_spectral_basis(5, 2, W) == -1
+    assert lib.muffin_spectral_basis(1, 0, W) == -1
