@@ -138,7 +138,18 @@ def run_gpu(inst, params, dtype, steps, warmup, profile_iters, graph=False):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     prof = s.profile(profile_iters) if profile_iters > 0 else {}
+    # the fused kernel in both forms (one or two pixels per thread), timed
+    # the same way, whichever the autotuner kept
+    forms = {}
+    if profile_iters > 0 and s.fused_available:
+        for form in (1, 2):
+            s.set_schedule((schedule[0], schedule[1], form))
+            forms[str(form)] = round(s.profile(profile_iters).get("fused", float("nan")), 5)
+        s.set_schedule(schedule)
     s.close()
+    if forms:
+        prof = dict(prof)
+        prof["_fused_forms_ms"] = forms
     return ms, prof, schedule
 
 
@@ -399,6 +410,7 @@ def main(argv=None):
     ms32, prof32, sched32 = run_gpu(inst, cfg.params, torch.float32, a.steps, a.warmup, a.profile_iters,
                                     graph=a.graph)
     value = V * a.steps / (ms32 / 1e3)
+    fused_forms = prof32.pop("_fused_forms_ms", None)
     kernels = {}
     for name, kms in prof32.items():
         nbytes = KERNEL_ELEMS.get(name, 0.0) * 4 * V
@@ -417,6 +429,7 @@ def main(argv=None):
     if a.fp64_steps > 0:
         _log(f"bench: FP64 {a.fp64_steps} timed passes")
         ms64, prof64, sched64 = run_gpu(inst, cfg.params, torch.float64, a.fp64_steps, 2, 5, graph=a.graph)
+        prof64.pop("_fused_forms_ms", None)
         fp64 = dict(value=V * a.fp64_steps / (ms64 / 1e3), ms_per_step=round(ms64 / a.fp64_steps, 4),
                     kernels_ms={k: round(v, 5) for k, v in prof64.items()}, schedule=list(sched64))
     grad = None
@@ -471,6 +484,7 @@ def main(argv=None):
         "iteration_min_bytes_frac": round(ITER_MIN_ELEMS * 4 * value / 1e9 / HBM_PEAK_GBPS, 4),
         "iteration_62B_frac": round(ITER_MIN5_ELEMS * 4 * value / 1e9 / HBM_PEAK_GBPS, 4),
         "kernels": kernels,
+        "fused_forms_ms": fused_forms,
         "fp64": fp64,
         "grad": grad,
         "dictionary": dictionary,

@@ -316,13 +316,16 @@ int muffin_iterations(const muffin_ctx* ctx);
    64 KiB of LDS; twice only where the LDS holds it), schedule[2] = 1 to run
    the inverse row pass, steps II-VI and the forward row pass of the next
    step I as one fused launch where it is built (muffin_fused_available),
-   0 for three launches.  Every schedule evaluates the same formulas in the
-   same order; the compiler may fuse a product and a sum into one FMA in one
-   schedule's code and not in another's, so results agree to rounding (a few
-   ulps), not bit for bit.  Default {1, 1, 1}. */
+   2 for the same launch with two pixels per thread (built for 64 bands on
+   rows of 256 to 1024 pixels and 32 bands on rows of 1024; elsewhere, and
+   in a batch, it runs as 1), 0 for three launches.  Every
+   schedule evaluates the same formulas in the same order; the compiler may
+   fuse a product and a sum into one FMA in one schedule's code and not in
+   another's, so results agree to rounding (a few ulps), not bit for bit.
+   Default {1, 1, 1}. */
 
-/* Time each variant of the transform passes, and the fused launch against
-   the three it replaces, `reps` times on this context's own arrays (the
+/* Time each variant of the transform passes, and the fused launch (both
+   forms where built) against the three it replaces, `reps` times on this context's own arrays (the
    timing writes only internal scratch: X and the state are unchanged), keep
    the fastest and write it to schedule (may be NULL).  Synchronises the
    stream.  Errors: EINVAL (reps < 1), EDEVICE. */

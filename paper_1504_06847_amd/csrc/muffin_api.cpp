@@ -75,7 +75,7 @@ int fused_rows(muffin_ctx* c) {
     A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
     A.gshift = 0;
     HIP_TRY(launch_fused(s.dtype, A, P(c, c->lay.dctm), s.L, s.ny, s.nx, spec_args(c->params),
-                         P(c, c->lay.tw), c->twlog, c->stream));
+                         P(c, c->lay.tw), c->twlog, c->stream, c->fused));
     c->zvalid = 1;
     return MUFFIN_OK;
 }
@@ -1056,10 +1056,15 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
         A.Z = P(c, c->lay.z);
         A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
         A.gshift = 0;
-        const double tfu = timeit([&] {
-            return launch_fused(dt, A, P(c, c->lay.dctm), s.L, s.ny, s.nx, a, P(c, c->lay.tw), c->twlog, c->stream);
-        });
-        fu = (tfu < t[0][rv] + t[2][rv] + tspec) ? 1 : 0;
+        double best = t[0][rv] + t[2][rv] + tspec;
+        const int nfv = fused_two_pixel_variant(s.nx, s.L) ? 2 : 1;
+        for (int fv = 1; fv <= nfv; ++fv) {
+            const double tfu = timeit([&] {
+                return launch_fused(dt, A, P(c, c->lay.dctm), s.L, s.ny, s.nx, a, P(c, c->lay.tw), c->twlog,
+                                    c->stream, fv);
+            });
+            if (tfu < best) { best = tfu; fu = fv; }
+        }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1073,8 +1078,8 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
 int muffin_set_schedule(muffin_ctx* c, const int schedule[3]) {
     if (int rc = check_ctx(c)) return rc;
     if (!schedule || schedule[0] < 0 || schedule[0] >= kNumVariants || schedule[1] < 0 ||
-        schedule[1] >= kNumVariants || schedule[2] < 0 || schedule[2] > 1) {
-        set_error("schedule must hold two variant indices in [0, %d) and a 0/1 fused flag", kNumVariants);
+        schedule[1] >= kNumVariants || schedule[2] < 0 || schedule[2] > 2) {
+        set_error("schedule must hold two variant indices in [0, %d) and a fused form in [0, 2]", kNumVariants);
         return MUFFIN_EINVAL;
     }
     if (c->row_v != schedule[0] || c->col_v != schedule[1] || c->fused != schedule[2]) {

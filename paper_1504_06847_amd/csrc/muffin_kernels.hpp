@@ -193,8 +193,11 @@ static_assert(sizeof(FusedArrays) == 56 && sizeof(FusedDesc) == 144, "descriptor
 bool fused_supported(int dtype, int nx, int ny, int L);
 hipError_t launch_fused_group(int dtype, int nx, int L, const FusedDesc* d, int n, int nblocks,
                               hipStream_t s);
+// variant 1: one pixel per thread; 2: two pixels per thread where
+// fused_two_pixel_variant(nx, L) (otherwise as 1); results agree to rounding
 hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
-                        const SpecArgs& a, const void* tw, int twlog, hipStream_t s);
+                        const SpecArgs& a, const void* tw, int twlog, hipStream_t s, int variant);
+bool fused_two_pixel_variant(int nx, int L);
 
 // Arrays of one spectral pass.  st: the state read (z_P, z_T, z_V, Gamma_S;
 // for a union of spectral bases z_P, z_T, S, Gamma_S); out: where the new

@@ -155,7 +155,7 @@ def test_autotune_keeps_results_and_state(gpu_lib, tmp_path):
     cache = str(tmp_path / "sched.json")
     sch = b.autotune(reps=3, cache=cache)
     _say("autotuned schedule", sch)
-    assert 0 <= sch[0] < 3 and 0 <= sch[1] < 3 and sch[2] in (0, 1) and b.schedule == tuple(sch)
+    assert 0 <= sch[0] < 3 and 0 <= sch[1] < 3 and sch[2] in (0, 1, 2) and b.schedule == tuple(sch)
     torch.cuda.synchronize()
     assert torch.equal(b.x, x0)                     # the timing leaves X and the state alone
     assert torch.equal(b.get_state(), st0)
@@ -165,6 +165,25 @@ def test_autotune_keeps_results_and_state(gpu_lib, tmp_path):
     assert _relmax(b.x, a.x) <= TOL[torch.float32]
     c = Solver(inst.psf, inst.dirty, **PARAMS)
     assert c.autotune(cache=cache) == tuple(sch)    # read back from the cache file
+
+
+def test_batch_runs_fused_form_2_as_form_1(gpu_lib):
+    """A cube set to the two-pixel fused form joins the batch's grouped
+    fused launch, which has one pixel per thread: the batch repeats the
+    single-cube runs of form 1 bit for bit."""
+    from paper_1504_06847_amd import Batch, Solver
+    cubes = _cubes([(64, 16, 256), (64, 8, 512), (8, 32, 32)], seed0=340)
+    b = Batch(cubes, params=PARAMS)
+    singles = [Solver(p, d, **PARAMS) for p, d in cubes]
+    for i in (0, 1):
+        b.cube(i).set_schedule((1, 1, 2))
+    b.iterate(4)
+    for s in singles:
+        s.iterate(4)
+    torch.cuda.synchronize()
+    for i, s in enumerate(singles):
+        assert torch.equal(b.cube(i).x, s.x), f"cube {i}"
+    b.close()
 
 
 def test_batch_autotune_keeps_results(gpu_lib):

@@ -61,6 +61,44 @@ def test_fused_pass_matches_oracle(gpu_lib, shape):
     assert worst < 1e-5 and worst_u < 1e-5
 
 
+@pytest.mark.parametrize("shape", [(64, 8, 1024), (64, 16, 512), (64, 32, 256), (32, 8, 1024), (32, 16, 512), (64, 128, 64)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_two_pixel_form_matches_oracle_and_one_pixel_form(gpu_lib, shape):
+    """Fused form 2 (two pixels per thread, half-size work-groups) against
+    the oracle per iterate, and against form 1 to rounding (the same
+    formulas; the compiler fuses products and sums into FMAs differently in
+    the two kernels, as between tile schedules).  Where the two-pixel kernel
+    is not built (fewer bands, short rows) form 2 runs as form 1, bit for
+    bit.  Graph replay of form 2 repeats its launched passes bit for bit."""
+    from paper_1504_06847_amd import Solver
+    L, ny, nx = shape
+    inst = make_instance(ny, nx, L, n_points=4, n_gauss=2, n_ant=12, noise_sigma=0.01, seed=33)
+    a = Solver(inst.psf, inst.dirty, **PARAMS)
+    b = Solver(inst.psf, inst.dirty, **PARAMS)
+    g = Solver(inst.psf, inst.dirty, graph=True, **PARAMS)
+    b.set_schedule((1, 1, 2))
+    g.set_schedule((1, 1, 2))
+    assert b.schedule == (1, 1, 2)
+    built = (L == 64 and nx >= 256) or (L == 32 and nx == 1024)
+    prob = O.Problem(inst.psf, inst.dirty, O.Params(**PARAMS))
+    st = O.State.zeros(prob.shape)
+    worst = 0.0
+    for k in range(8):
+        a.iterate(1)
+        b.iterate(1)
+        g.iterate(1)
+        st = O.admm_iteration(prob, st)
+        worst = max(worst, rel(b.x.cpu().double().numpy(), st.X))
+        torch.cuda.synchronize()
+        d = float((a.x.double() - b.x.double()).abs().max() / a.x.double().abs().max())
+        assert d <= 1e-6, (k, d)
+        if not built:
+            assert torch.equal(a.x, b.x)
+        assert torch.equal(b.x, g.x)
+    _say("two-pixel form", shape, "worst per-iterate rel err", worst, "vs form 1", d)
+    assert worst < 1e-5
+
+
 def test_fused_and_three_launch_agree_over_a_long_run(gpu_lib):
     from paper_1504_06847_amd import Solver
     cfg = get_config("fp32_256")
@@ -163,11 +201,15 @@ def test_full_size_fused_first_passes(gpu_lib):
     p = cfg.params
     s = Solver(inst.psf, inst.dirty, mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho=p.rho_P)
     assert s.schedule[2] == 1 and s.fused_available
+    t = Solver(inst.psf, inst.dirty, mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho=p.rho_P)
+    t.set_schedule((1, 1, 2))                 # two pixels per thread
     prob = O.Problem(inst.psf, inst.dirty, p)
     st = O.State.zeros(prob.shape)
     for k in range(3):
         s.iterate(1)
+        t.iterate(1)
         st = O.admm_iteration(prob, st)
         e = rel(s.x.cpu().double().numpy(), st.X)
-        _say("full size fused pass", k + 1, e)
-        assert e < 1e-5
+        e2 = rel(t.x.cpu().double().numpy(), st.X)
+        _say("full size fused pass", k + 1, e, "two pixels per thread", e2)
+        assert e < 1e-5 and e2 < 1e-5
