@@ -153,42 +153,47 @@ def run_gpu(inst, params, dtype, steps, warmup, profile_iters, graph=False):
     return ms, prof, schedule
 
 
-def run_grad(inst, params, K, ckpt_every=5):
+def run_grad(inst, params, K, ckpt_small=5):
     """The reverse sweep of K unrolled FP32 passes (MSE loss against the sky,
     gradient in mu_s, mu_nu, rho) at the cube's full size, timed once after
-    an untimed sweep, against K forward passes."""
+    an untimed sweep, against K forward passes: with the library's default
+    checkpoint spacing (the largest whose scratch fits half the free HBM:
+    every pass stored at this size) and with checkpoints every
+    ``ckpt_small`` passes (a memory-bound setting: segments recomputed)."""
     import torch
     from paper_1504_06847_amd import Solver
     kw = dict(mu_eps=params.mu_eps, mu_s=params.mu_s, mu_nu=params.mu_nu, rho=params.rho_P)
     s = Solver(inst.psf, inst.dirty, graph=True, **kw)
     s.autotune(reps=3)
-    s.grad(K, sky=inst.sky, ckpt_every=ckpt_every)          # scratch allocation, warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss, g = s.grad(K, sky=inst.sky, ckpt_every=ckpt_every)
-    torch.cuda.synchronize()
-    t_grad = time.perf_counter() - t0
-    # every pass stored on the way forward (checkpoint spacing K): no
-    # recompute, K x 5 cubes of segment store (HBM holds them at this size)
-    s.grad(K, sky=inst.sky, ckpt_every=K)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.grad(K, sky=inst.sky, ckpt_every=K)
-    torch.cuda.synchronize()
-    t_all = time.perf_counter() - t0
+    C = s.sweep_ckpt_every(K)
+
+    def timed(c):
+        s.grad(K, sky=inst.sky, ckpt_every=c)          # workspace allocation, warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = s.grad(K, sky=inst.sky, ckpt_every=c)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    t_grad, (loss, g) = timed(C)
+    t_small, _ = timed(ckpt_small)
+    s.reset()
+    s.iterate(1)
     s.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.iterate(K)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    scratch = s.grad_workspace_bytes(K, C, False)
+    scratch_small = s.grad_workspace_bytes(K, ckpt_small, False)
     s.close()
-    cube_gib = inst.dirty.size * 4 / 2**30
-    return {"K": K, "ckpt_every": ckpt_every, "ms": round(t_grad * 1e3, 2), "forward_ms": round(t_fwd * 1e3, 2),
-            "ratio_to_forward": round(t_grad / t_fwd, 2), "loss": loss, "grad": [float(v) for v in g],
-            "all_stored": {"ckpt_every": K, "ms": round(t_all * 1e3, 2),
-                           "ratio_to_forward": round(t_all / t_fwd, 2),
-                           "scratch_GiB": round((4 + 5 * K + 11) * cube_gib, 2)}}
+    return {"K": K, "ckpt_every": C, "ms": round(t_grad * 1e3, 2), "forward_ms": round(t_fwd * 1e3, 2),
+            "ratio_to_forward": round(t_grad / t_fwd, 2), "scratch_GiB": round(scratch / 2**30, 2),
+            "loss": loss, "grad": [float(v) for v in g],
+            "recomputed": {"ckpt_every": ckpt_small, "ms": round(t_small * 1e3, 2),
+                           "ratio_to_forward": round(t_small / t_fwd, 2),
+                           "scratch_GiB": round(scratch_small / 2**30, 2)}}
 
 
 # algorithmic elements per voxel of one wavelet basis in a pass: X read,

@@ -63,14 +63,18 @@ int step_one(muffin_ctx* c) {
 // the inverse row pass, steps II-VI and the forward row pass of the next
 // step I in one launch: X and the state as step_one + step_spectral, and Z
 // holds the row spectra of the new B_rest (B_rest itself is not written)
-int fused_rows(muffin_ctx* c) {
+int fused_rows_io(muffin_ctx* c, void* const in[4], void* const out[4], void* xo) {
     const muffin_shape& s = c->shape;
-    FusedArrays A;
-    A.X = P(c, c->lay.x);
-    A.zP = (char*)st(c, ST_ZP);
-    A.zT = (char*)st(c, ST_ZT);
-    A.zV = (char*)st(c, ST_ZV);
-    A.GS = (char*)st(c, ST_GS);
+    FusedArrays A{};
+    A.X = (char*)xo;
+    A.zP = (char*)in[ST_ZP];
+    A.zT = (char*)in[ST_ZT];
+    A.zV = (char*)in[ST_ZV];
+    A.GS = (char*)in[ST_GS];
+    A.zPo = (char*)out[ST_ZP];
+    A.zTo = (char*)out[ST_ZT];
+    A.zVo = (char*)out[ST_ZV];
+    A.GSo = (char*)out[ST_GS];
     A.Z = P(c, c->lay.z);
     A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
     A.gshift = 0;
@@ -80,15 +84,23 @@ int fused_rows(muffin_ctx* c) {
     return MUFFIN_OK;
 }
 
-// steps II-VI; a reporting pass writes the alternate state set and the FP64
-// partials of the convergence quantities, then the sets swap
-int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
+int fused_rows(muffin_ctx* c) {
+    void* cur[4];
+    for (int i = 0; i < kNumState; ++i) cur[i] = st(c, i);
+    return fused_rows_io(c, cur, cur, P(c, c->lay.x));
+}
+
+// steps II-VI from the state `in` and X, the new state to `out` (a
+// reporting pass: the alternate set); a reporting pass also writes the FP64
+// partials of the convergence quantities, and the sets swap
+int step_spectral_io(muffin_ctx* c, bool report, int* nblocks, void* const in[4], void* const out[4],
+                     const void* X) {
     const muffin_shape& s = c->shape;
-    SpecLaunch g;
-    g.X = P(c, c->lay.x);
+    SpecLaunch g{};
+    g.X = X;
     for (int i = 0; i < kNumState; ++i) {
-        g.st[i] = st(c, i);
-        g.out[i] = report ? st_alt(c, i) : st(c, i);
+        g.st[i] = in[i];
+        g.out[i] = out[i];
     }
     g.brest = P(c, c->lay.brest);
     g.dctm = P(c, c->lay.dctm);
@@ -110,6 +122,36 @@ int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
         c->cur = 1 - c->cur;
         c->version++;
     }
+    return MUFFIN_OK;
+}
+
+int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
+    void* in[4];
+    void* out[4];
+    for (int i = 0; i < kNumState; ++i) {
+        in[i] = st(c, i);
+        out[i] = report ? st_alt(c, i) : st(c, i);
+    }
+    return step_spectral_io(c, report, nblocks, in, out, P(c, c->lay.x));
+}
+
+// One pass launched without a graph, its state read from `in` and the new
+// state written to `out` (in place when they are the same arrays), X to xo;
+// B_rest (or Z after a fused pass) is the context's and follows the chain of
+// passes.  The reverse sweep runs its forward passes this way, straight into
+// its checkpoints and segment stores.  One spectral basis, Dirac W_s.
+int pass_io(muffin_ctx* c, void* const in[4], void* const out[4], void* xo) {
+    const muffin_shape& s = c->shape;
+    if (int rc = row_forward(c)) return rc;
+    if (int rc = col_solve(c)) return rc;
+    if (use_fused(c)) {
+        if (int rc = fused_rows_io(c, in, out, xo)) return rc;
+    } else {
+        HIP_TRY(launch_row_inv(s.dtype, P(c, c->lay.z), xo, s.L * s.ny, s.nx, P(c, c->lay.tw), c->twlog,
+                               c->stream, c->row_v));
+        if (int rc = step_spectral_io(c, false, nullptr, in, out, xo)) return rc;
+    }
+    c->iters++;
     return MUFFIN_OK;
 }
 
@@ -311,15 +353,15 @@ size_t state_array_bytes(const muffin_ctx* c) {
 // ---------------------------------------------------------------- reverse sweep
 // Gradient of a loss of X^K (K passes from the zero state) by the adjoint of
 // the reduced pass, with the state checkpointed every C passes: a forward
-// sweep stores the checkpoints, then each segment (last first) is run again
-// from its checkpoint, storing the state before every pass and its X, and
-// its passes are reversed.  Scratch (device, owned by the context):
+// sweep writes the checkpoints (and the whole last segment), then each other
+// segment (last first) is run again from its checkpoint, its passes writing
+// the state before every pass and its X into a segment store, and its passes
+// are reversed.  Scratch (device, owned by the context):
 //   ckpt : ceil(K / C) x 4 state arrays (the state before each segment's
 //          first pass, for the recompute and for that pass's adjoint)
 //   seg  : 2 x C x 5 arrays (state before the pass, X of the pass; the
-//          state slots of pass 0 unused), two stores used in turn by
-//          consecutive segments
-//   fin  : 5 arrays (the state after K passes, restored at the end)
+//          state slots of pass 0 hold no input), two stores used in turn by
+//          consecutive segments (one with a single segment)
 //   adj  : 4 state cotangents, X-bar, B-bar
 //   gyac : (with gy_out) the sum over the passes of B-bar
 //   partials, partials1 (FP64 block sums), acc
@@ -340,8 +382,8 @@ size_t grad_scratch_bytes(const muffin_ctx* c, int K, int C, bool dirty) {
     if (C > K) C = K;
     const int nseg = (K + C - 1) / C;
     const int nbuf = nseg > 1 ? 2 : 1;
-    const size_t n_arrays = size_t(nseg) * kNumState + size_t(nbuf) * C * (kNumState + 1) + (kNumState + 1) +
-                            (kNumState + 2) + (dirty ? 1 : 0);
+    const size_t n_arrays = size_t(nseg) * kNumState + size_t(nbuf) * C * (kNumState + 1) + (kNumState + 2) +
+                            (dirty ? 1 : 0);
     return n_arrays * state_array_bytes(c) + 2 * grad_nparts(c) * GRAD_NQ * 8 + GRAD_NQ * 8;
 }
 
@@ -370,8 +412,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     // the state before pass j of segment sg in store b: its checkpoint for
     // j = 0 (never overwritten, so not copied into the store)
     auto stv = [&](int b, int sg, int j, int i) { return j == 0 ? ckpt(sg, i) : segs(b, j, i); };
-    char* fin = seg0 + size_t(nbuf) * C * (kNumState + 1) * ab;
-    char* adj = fin + (kNumState + 1) * ab;                  // aP, aT, aS, aG, Xb, Bb
+    char* adj = seg0 + size_t(nbuf) * C * (kNumState + 1) * ab;   // aP, aT, aS, aG, Xb, Bb
     char* gyac = adj + (kNumState + 2) * ab;
     double* partials = (double*)(gyac + (gy_out ? ab : 0));
     double* partials1 = partials + nparts * GRAD_NQ;      // step-I sums of a fused launch
@@ -383,27 +424,43 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     auto copy = [&](void* dst, const void* src) {
         return hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToDevice, st_);
     };
-    // forward sweep with checkpoints; the last segment goes straight into its
-    // segment store (the reverse sweep starts there, no recompute)
+    // Where the forward passes keep their state and X.  Pass k (segment seg,
+    // j = (k - 1) mod C) reads the state before it from checkpoint seg (j = 0),
+    // from slot j of a segment store (the last segment, and every segment
+    // when it is recomputed) or from the context's own arrays (the other
+    // segments on the way forward, in place), and writes the state after it
+    // where pass k + 1 reads it: the context's arrays after pass K.  X of a
+    // stored pass goes to its slot, X^K to the context.  No state is copied.
+    // The state arrays of slot 0 of a store are never read (slot 0's state is
+    // the checkpoint): a recomputed segment's last pass writes its (already
+    // checkpointed) output there.
+    void* ctx_st[4];
+    for (int i = 0; i < kNumState; ++i) ctx_st[i] = st(c, i);
+    auto set_ptrs = [&](void* dst[4], auto&& loc) {
+        for (int i = 0; i < kNumState; ++i) dst[i] = loc(i);
+    };
     const int blast = (nseg - 1) & (nbuf - 1);
     int rc = zero_state(c);
     if (rc) return rc;
+    for (int i = 0; i < kNumState; ++i) HIP_TRY(launch_fill_zero(ckpt(0, i), nb, st_));
     for (int k = 1; k <= K; ++k) {
         const int seg = (k - 1) / C, j = (k - 1) % C;
         const bool last = seg == nseg - 1;
-        if (j == 0)
-            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(ckpt(seg, i), st(c, i)));
-        else if (last)
-            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(blast, j, i), st(c, i)));
-        if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
-        if (last) HIP_TRY(copy(segs(blast, j, kNumState), P(c, c->lay.x)));
+        void *in[4], *out[4];
+        if (j == 0) set_ptrs(in, [&](int i) -> void* { return ckpt(seg, i); });
+        else if (last) set_ptrs(in, [&](int i) -> void* { return segs(blast, j, i); });
+        else set_ptrs(in, [&](int i) -> void* { return ctx_st[i]; });
+        if (k == K) set_ptrs(out, [&](int i) -> void* { return ctx_st[i]; });
+        else if (j == C - 1) set_ptrs(out, [&](int i) -> void* { return ckpt(seg + 1, i); });
+        else if (last) set_ptrs(out, [&](int i) -> void* { return segs(blast, j + 1, i); });
+        else set_ptrs(out, [&](int i) -> void* { return ctx_st[i]; });
+        void* xo = (last && k < K) ? (void*)segs(blast, j, kNumState) : (void*)P(c, c->lay.x);
+        if ((rc = pass_io(c, in, out, xo)) != MUFFIN_OK) return rc;
     }
-    // the state after K passes, kept aside while segments are recomputed
-    // (with one segment nothing is recomputed and the context keeps it)
-    if (nseg > 1) {
-        for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(fin + i * ab, st(c, i)));
-        HIP_TRY(copy(fin + kNumState * ab, P(c, c->lay.x)));
-    }
+    // X of pass k: its slot, X^K in the context
+    auto xloc = [&](int b_, int j_, int k_) -> char* {
+        return k_ == K ? (char*)P(c, c->lay.x) : segs(b_, j_, kNumState);
+    };
     // seed: the cotangent of X^K
     char* Xb = adj + kNumState * ab;
     char* Bb = adj + (kNumState + 1) * ab;
@@ -425,14 +482,18 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         const int k0 = seg * C, k1 = (k0 + C < K) ? k0 + C : K;
         const int b = seg & (nbuf - 1);
         if (seg < nseg - 1) {
-            for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), ckpt(seg, i)));
-            if ((rc = recompute_brest(c)) != MUFFIN_OK) return rc;
+            // recompute the segment from its checkpoint into store b (B_rest
+            // from the checkpoint's state)
+            HIP_TRY(launch_brest(dt, ckpt(seg, ST_ZP), ckpt(seg, ST_ZT), ckpt(seg, ST_ZV), ckpt(seg, ST_GS),
+                                 P(c, c->lay.brest), voxels(s), a, st_, false));
+            c->zvalid = 0;
             for (int k = k0 + 1; k <= k1; ++k) {
                 const int j = k - k0 - 1;
-                if (j > 0)
-                    for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(segs(b, j, i), st(c, i)));
-                if ((rc = one_pass(c)) != MUFFIN_OK) return rc;
-                HIP_TRY(copy(segs(b, j, kNumState), P(c, c->lay.x)));
+                void *in[4], *out[4];
+                set_ptrs(in, [&](int i) -> void* { return stv(b, seg, j, i); });
+                const int jo = j + 1 < C ? j + 1 : 0;
+                set_ptrs(out, [&](int i) -> void* { return segs(b, jo, i); });
+                if ((rc = pass_io(c, in, out, segs(b, j, kNumState))) != MUFFIN_OK) return rc;
             }
         }
         // pass k's step-I adjoint runs inside the band-coupled launch of pass
@@ -449,7 +510,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             A.zT = stv(b, seg, j, ST_ZT);
             A.zV = stv(b, seg, j, ST_ZV);
             A.GS = stv(b, seg, j, ST_GS);
-            A.X = segs(b, j, kNumState);
+            A.X = xloc(b, j, k);
             A.aP = adj;
             A.aT = adj + ab;
             A.aS = adj + 2 * ab;
@@ -465,7 +526,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
                 A.zT1 = stv(b1, s1, j1, ST_ZT);
                 A.zV1 = stv(b1, s1, j1, ST_ZV);
                 A.GS1 = stv(b1, s1, j1, ST_GS);
-                A.X1 = segs(b1, j1, kNumState);
+                A.X1 = xloc(b1, j1, k + 1);
             }
             int nbk = 0;
             const int mode = fused ? 2 : (k == K ? 1 : 0);
@@ -489,11 +550,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             }
         }
     }
-    // leave the context at the state after K passes
-    if (nseg > 1) {
-        for (int i = 0; i < kNumState; ++i) HIP_TRY(copy(st(c, i), fin + i * ab));
-        HIP_TRY(copy(P(c, c->lay.x), fin + kNumState * ab));
-    }
+    // the context holds the state after K passes (pass K wrote it there)
     if (gy_out) {
         // dL/dY = H (sum of B-bar): the transfer function applied in the
         // Fourier domain (Z is scratch here; B_rest is rebuilt below)
@@ -1035,7 +1092,7 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
         const size_t nb = voxels(s) * elem_size(s);
         for (int i = 0; i < kNumState && e == hipSuccess; ++i)
             e = hipMemcpyAsync(st_alt(c, i), st(c, i), nb, hipMemcpyDeviceToDevice, c->stream);
-        SpecLaunch g;
+        SpecLaunch g{};
         g.X = P(c, c->lay.x);
         for (int i = 0; i < kNumState; ++i) g.st[i] = g.out[i] = st_alt(c, i);
         g.brest = P(c, c->lay.brest);
@@ -1047,12 +1104,12 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
         g.partials = (double*)P(c, c->lay.partials);
         const SpecArgs a = spec_args(c->params);
         const double tspec = timeit([&] { return launch_spectral(dt, g, a, nullptr, c->stream); });
-        FusedArrays A;
+        FusedArrays A{};
         A.X = P(c, c->lay.brest);
-        A.zP = (char*)st_alt(c, ST_ZP);
-        A.zT = (char*)st_alt(c, ST_ZT);
-        A.zV = (char*)st_alt(c, ST_ZV);
-        A.GS = (char*)st_alt(c, ST_GS);
+        A.zP = A.zPo = (char*)st_alt(c, ST_ZP);
+        A.zT = A.zTo = (char*)st_alt(c, ST_ZT);
+        A.zV = A.zVo = (char*)st_alt(c, ST_ZV);
+        A.GS = A.GSo = (char*)st_alt(c, ST_GS);
         A.Z = P(c, c->lay.z);
         A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
         A.gshift = 0;

@@ -133,10 +133,10 @@ void fill_desc(const muffin_batch* b, const Class& k, muffin_ctx* c, int first, 
     } else if (k.kind == K_FUSED) {
         FusedDesc d{};
         d.A.X = P(c, c->lay.x);
-        d.A.zP = (char*)st(c, ST_ZP);
-        d.A.zT = (char*)st(c, ST_ZT);
-        d.A.zV = (char*)st(c, ST_ZV);
-        d.A.GS = (char*)st(c, ST_GS);
+        d.A.zP = d.A.zPo = (char*)st(c, ST_ZP);
+        d.A.zT = d.A.zTo = (char*)st(c, ST_ZT);
+        d.A.zV = d.A.zVo = (char*)st(c, ST_ZV);
+        d.A.GS = d.A.GSo = (char*)st(c, ST_GS);
         d.A.Z = P(c, c->lay.z);
         d.A.band_bytes = unsigned(long(s.ny) * s.nx * long(elem_size(s)));
         d.A.gshift = 0;

@@ -14,7 +14,8 @@
 //        forward real FFT of B_rest -> the spectrum rows of the next column
 //          pass (written over the rows read)
 // X and B_rest never make an HBM round trip between kernels: 44 B/voxel in
-// FP32 (Z, z_P, z_T, z_V, Gamma_S in; Z, X, z_P, z_T, z_V, Gamma_S out)
+// FP32 (Z, z_P, z_T, z_V, Gamma_S in; Z, X, z_P, z_T, z_V, Gamma_S out; the
+// new state in place or into other arrays)
 // against 56 B for the inverse row pass, spectral pass and forward row pass
 // launched one after another.  The state is that of muffin_spectral.hip
 // (z_V = S - Gamma_S / rho_V in place of S).
@@ -72,6 +73,7 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
     // every band of an array within 2^30 bytes of its base (checked on the host)
     // the state and X stream through once per pass: non-temporal
     const BandArray1<T, kStreamCpol> X(A.X, bb), zP(A.zP, bb), zT(A.zT, bb), zV(A.zV, bb), GS(A.GS, bb);
+    const BandArray1<T, kStreamCpol> zPo(A.zPo, bb), zTo(A.zTo, bb), zVo(A.zVo, bb), GSo(A.GSo, bb);
     cx<T>* Z = (cx<T>*)A.Z;
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
@@ -147,10 +149,10 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
                     const T sv = zv2 + gs2 * inv_rhoV;       // S as stored (see k_spectral)
                     lrow[e] = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * sv;
                     X.store(l, offp, xv);
-                    zV.store(l, offp, zv2);
-                    GS.store(l, offp, gs2);
-                    zP.store(l, offp, zp2);
-                    zT.store(l, offp, zt2);
+                    zVo.store(l, offp, zv2);
+                    GSo.store(l, offp, gs2);
+                    zPo.store(l, offp, zp2);
+                    zTo.store(l, offp, zt2);
                 }
             }
             if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -236,6 +238,8 @@ bool fused_two_pixel_variant(int nx, int L) { return fused_two_pixels_at(nx, L);
 hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
                         const SpecArgs& a, const void* tw, int twlog, hipStream_t s, int variant) {
     if (!fused_supported(dtype, nx, ny, L) || variant < 1 || variant > 2) return hipErrorInvalidValue;
+    if (!A.X || !A.zP || !A.zT || !A.zV || !A.GS || !A.zPo || !A.zTo || !A.zVo || !A.GSo || !A.Z)
+        return hipErrorInvalidValue;
     switch (nx) {
         case 64: return fused_l<float, 64>(A, D, L, ny, a, tw, twlog, s, variant);
         case 128: return fused_l<float, 128>(A, D, L, ny, a, tw, twlog, s, variant);

@@ -176,8 +176,11 @@ hipError_t launch_grad_accum(const double* partials, int nblocks, double* acc, h
 // reads the column pass's
 // spectrum Z and the state, writes X, the new state and the spectrum of
 // B_rest over Z.
+// the state is read from zP .. GS and written to zPo .. GSo (the same
+// arrays for a pass in place)
 struct FusedArrays {
     char *X, *zP, *zT, *zV, *GS;
+    char *zPo, *zTo, *zVo, *GSo;
     char* Z;
     unsigned band_bytes;
     int gshift;
@@ -189,12 +192,14 @@ struct FusedDesc {                   // one cube of a grouped fused launch
     const void* tw;
     int twlog, L, ny, first, nblk, pad;
 };
-static_assert(sizeof(FusedArrays) == 56 && sizeof(FusedDesc) == 144, "descriptor layout");
+static_assert(sizeof(FusedArrays) == 88 && sizeof(FusedDesc) == 176, "descriptor layout");
 bool fused_supported(int dtype, int nx, int ny, int L);
 hipError_t launch_fused_group(int dtype, int nx, int L, const FusedDesc* d, int n, int nblocks,
                               hipStream_t s);
 // variant 1: one pixel per thread; 2: two pixels per thread where
-// fused_two_pixel_variant(nx, L) (otherwise as 1); results agree to rounding
+// fused_two_pixel_variant(nx, L) (otherwise as 1); results agree to rounding.
+// Every array of A must be set (for a pass in place zPo = zP, ...): a null
+// one is rejected (hipErrorInvalidValue).
 hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
                         const SpecArgs& a, const void* tw, int twlog, hipStream_t s, int variant);
 bool fused_two_pixel_variant(int nx, int L);
@@ -203,10 +208,10 @@ bool fused_two_pixel_variant(int nx, int L);
 // for a union of spectral bases z_P, z_T, S, Gamma_S); out: where the new
 // state goes (= st except in a reporting pass).
 struct SpecLaunch {
-    const void* X;
-    void* st[4];
-    void* out[4];
-    void* brest;
+    const void* X = nullptr;
+    void* st[4] = {nullptr, nullptr, nullptr, nullptr};
+    void* out[4] = {nullptr, nullptr, nullptr, nullptr};   // = st for a pass in place
+    void* brest = nullptr;
     const void* dctm;   // the dense transform(s): per basis D[k * LT + l] = W[l][k], LT = dense_width(L)
     int L;
     long npix;

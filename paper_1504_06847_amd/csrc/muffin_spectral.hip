@@ -36,8 +36,9 @@ namespace muffin {
 
 constexpr int SPEC_NTH = 256;
 
-// One ADMM pass after step I.  REDUCE (a reporting pass): the new state goes
-// to the second array set, so k_report can compare old and new, and the
+// One ADMM pass after step I, the state read from zP .. GS and the new one
+// written to zPo .. GSo.  REDUCE (a reporting pass): the new state goes to
+// the second array set, so k_report can compare old and new, and the
 // block sums of ||V||^2 (the only DCT-domain quantity of the convergence
 // checks) are written to partials[block].
 template <typename T, int LT, bool DENSE, bool REDUCE>
@@ -55,8 +56,10 @@ __device__ __forceinline__ void spectral_body(const SpecArrays& A, const T* __re
     const BandArray<T> X{A.X, bb, gs_}, Brest{A.Brest, bb, gs_};
     const BandArray<T, kStreamCpol> zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_},
         GS{A.GS, bb, gs_};
-    const BandArray<T, kStreamCpol> zPo{REDUCE ? A.zPo : A.zP, bb, gs_}, zTo{REDUCE ? A.zTo : A.zT, bb, gs_},
-        zVo{REDUCE ? A.zVo : A.zV, bb, gs_}, GSo{REDUCE ? A.GSo : A.GS, bb, gs_};
+    // the new state: the other set in a reporting pass, the same arrays for
+    // a pass in place, or wherever the caller directs it
+    const BandArray<T, kStreamCpol> zPo{A.zPo, bb, gs_}, zTo{A.zTo, bb, gs_}, zVo{A.zVo, bb, gs_},
+        GSo{A.GSo, bb, gs_};
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
     const T tauT = T(a.tau_T), tauV = T(a.tau_V);
@@ -544,6 +547,12 @@ static hipError_t union_dispatch(const SpecLaunch& g, const SpecArgs& a, hipStre
 
 hipError_t launch_spectral(int dtype, const SpecLaunch& g, const SpecArgs& a, int* nblocks_out,
                            hipStream_t s) {
+    // every array the kernels read or write must be set (out = st in place)
+    if (!g.X || !g.brest || g.n_nu < 1 || g.n_nu > 4) return hipErrorInvalidValue;
+    for (int i = 0; i < 4; ++i)
+        if (!g.st[i] || !g.out[i]) return hipErrorInvalidValue;
+    for (int j = 0; g.n_nu > 1 && j < g.n_nu; ++j)
+        if (!g.uz[j] || !g.uzo[j]) return hipErrorInvalidValue;
     const bool split = g.L == 2 * SPLIT_N && !g.dense && g.n_nu == 1;
     if (nblocks_out) *nblocks_out = (int)(split ? g.npix / 64 : g.npix / (g.npix < SPEC_NTH ? g.npix : SPEC_NTH));
     if (g.n_nu > 1) return dtype == 0 ? union_dispatch<float>(g, a, s) : union_dispatch<double>(g, a, s);
