@@ -434,14 +434,21 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     // The state arrays of slot 0 of a store are never read (slot 0's state is
     // the checkpoint): a recomputed segment's last pass writes its (already
     // checkpointed) output there.
+    // The sweep starts from the zero state: checkpoint 0 and B_rest are
+    // cleared (pass 1 reads nothing else), the context's state set 0 will
+    // hold the state after K passes.
+    c->cur = 0;
+    c->iters = 0;
+    c->zvalid = 0;
+    c->version++;
     void* ctx_st[4];
     for (int i = 0; i < kNumState; ++i) ctx_st[i] = st(c, i);
     auto set_ptrs = [&](void* dst[4], auto&& loc) {
         for (int i = 0; i < kNumState; ++i) dst[i] = loc(i);
     };
     const int blast = (nseg - 1) & (nbuf - 1);
-    int rc = zero_state(c);
-    if (rc) return rc;
+    int rc = MUFFIN_OK;
+    HIP_TRY(launch_fill_zero(P(c, c->lay.brest), nb, st_));
     for (int i = 0; i < kNumState; ++i) HIP_TRY(launch_fill_zero(ckpt(0, i), nb, st_));
     for (int k = 1; k <= K; ++k) {
         const int seg = (k - 1) / C, j = (k - 1) % C;

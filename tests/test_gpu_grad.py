@@ -73,7 +73,7 @@ def test_default_checkpoint_spacing_from_free_memory(gpu_lib):
     inst, p, kw = _grad64()
     s = Solver(inst.psf, inst.dirty, **kw)
     assert s.sweep_ckpt_every(20) == 20
-    # the workspace of spacing 5 (4 x 4 + 10 x 5 + 11 cubes): every spacing
+    # the workspace of spacing 5 (4 x 4 + 10 x 5 + 6 cubes): every spacing
     # that recomputes fewer passes (7, 10, 20) needs more
     b5 = s.grad_workspace_bytes(20, 5)
     assert s.grad_workspace_bytes(20, 20) == s.grad_workspace_bytes(20, 50) > b5
@@ -124,6 +124,33 @@ def test_vjp_at_band_counts_off_the_power_of_two_path(gpu_lib, L):
         e = np.zeros(3)
         e[i] = 1.0
         _, dX = O.jvp_run(prob, 8, e)
+        ref = float(np.sum(gx * dX))
+        _say("vjp L", L, i, g[i], ref)
+        assert abs(g[i] - ref) <= 1e-8 * max(abs(ref), np.abs(g).max())
+
+
+@pytest.mark.parametrize("L,ny,nx", [(32, 16, 8), (64, 8, 16), (128, 8, 8)], ids=["L32", "L64", "L128"])
+def test_vjp_at_the_register_band_widths(gpu_lib, L, ny, nx):
+    """The register-resident adjoint at 32, 64 and 128 bands (FP64) on small
+    images: <gx, J e_i> from the oracle's tangents, with checkpoints every
+    4 of 6 passes (two segments, the second short: the step-I adjoint of
+    pass 5 runs inside pass 4's launch, across the segment boundary) and
+    bitwise the same with every pass stored."""
+    from synth import make_instance
+    from paper_1504_06847_amd import Solver
+    inst = make_instance(ny, nx, L, n_points=3, n_gauss=1, n_ant=12, noise_sigma=0.01, seed=50 + L)
+    p = get_config("grad64").params
+    kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho=p.rho_P)
+    gx = np.random.default_rng(12).standard_normal(inst.dirty.shape)
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw)
+    _, g = s.grad(6, gx=gx, ckpt_every=4)
+    _, g1 = s.grad(6, gx=gx, ckpt_every=6)
+    assert np.array_equal(g, g1)
+    prob = O.Problem(inst.psf, inst.dirty, p)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        _, dX = O.jvp_run(prob, 6, e)
         ref = float(np.sum(gx * dX))
         _say("vjp L", L, i, g[i], ref)
         assert abs(g[i] - ref) <= 1e-8 * max(abs(ref), np.abs(g).max())
@@ -180,14 +207,20 @@ def test_dirty_image_gradient_matches_oracle_jvp(gpu_lib, dtype, bar):
 
 
 @pytest.mark.parametrize("ckpt_every", [4, 9, 20])
-def test_context_holds_the_K_pass_state_afterwards(gpu_lib, ckpt_every):
-    """Checkpoints every 4: the state after K passes is set aside and put
-    back; every 9 or 20 (one segment): the context keeps it throughout."""
+@pytest.mark.parametrize("report_first", [False, True], ids=["iterate", "report"])
+def test_context_holds_the_K_pass_state_afterwards(gpu_lib, ckpt_every, report_first):
+    """The last forward pass of the sweep writes the context's own state
+    arrays, and recomputed segments (checkpoints every 4) never touch them;
+    with one segment (every 9 or 20) nothing is recomputed.  A reporting
+    pass before the sweep (which switches the context's state set) changes
+    nothing."""
     from paper_1504_06847_amd import Solver
     inst, p, kw = _grad64()
     a = Solver(inst.psf, inst.dirty, **kw)
     b = Solver(inst.psf, inst.dirty, **kw)
     a.iterate(3)
+    if report_first:
+        a.step_report()
     a.grad(9, sky=inst.sky, ckpt_every=ckpt_every)
     b.iterate(9)
     torch.cuda.synchronize()
