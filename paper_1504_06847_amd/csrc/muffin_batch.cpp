@@ -33,7 +33,7 @@ size_t desc_region_bytes(int n) { return align_up(size_t(K_NUM) * n * kDescSlot)
 struct Class {
     int kind;
     int key;                 // nx (row and fused passes), ny (column pass), L (spectral pass)
-    int nth;                 // spectral block size; L of a fused class
+    int nth;                 // pixels per block of a spectral class; L of a fused class
     int variant;             // tile schedule (transform passes)
     std::vector<int> cubes;
     int nblocks;             // grid of the grouped launch
@@ -207,7 +207,7 @@ void build_classes(muffin_batch* b) {
             b->classes[class_of(b, K_ROWF, s.nx, 0)].cubes.push_back(i);
             b->classes[class_of(b, K_COL, s.ny, 0)].cubes.push_back(i);
             b->classes[class_of(b, K_ROWI, s.nx, 0)].cubes.push_back(i);
-            b->classes[class_of(b, K_SPEC, s.L, spectral_block_threads(long(s.ny) * s.nx))].cubes.push_back(i);
+            b->classes[class_of(b, K_SPEC, s.L, spectral_block_pixels(s.L, long(s.ny) * s.nx, int(elem_size(s))))].cubes.push_back(i);
         }
     }
     size_t slot = 0;

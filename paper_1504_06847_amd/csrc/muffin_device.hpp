@@ -647,6 +647,18 @@ template <typename T, int L> __host__ __device__ __forceinline__ void dct3_ortho
     }
 }
 
+// The two-wave split of a 2N-band vector (the spectral passes at 128 and
+// 256 bands) exchanges its N registers through LDS in two rounds: round q
+// moves registers [0, N/4) and [3N/4, N) (q = 0), then [N/4, 3N/4) (q = 1),
+// so that register r and register N - 1 - r travel together; slot i of a
+// round holds register round_reg(q, i), register r sits in slot slot_of(r).
+template <int N> __host__ __device__ constexpr int round_reg(int q, int i) {
+    return q == 0 ? (i < N / 4 ? i : N / 2 + i) : N / 4 + i;
+}
+template <int N> __host__ __device__ constexpr int slot_of(int r) {
+    return r < N / 4 ? r : (r < 3 * N / 4 ? r - N / 4 : r - N / 2);
+}
+
 // Orthonormal DCT-IV of N (a power of two) values in registers, its own
 // inverse: y_k = sqrt(2/N) sum_n w_n cos(pi (2n + 1)(2k + 1) / (4N)).
 // With M = N/2: z_m = (w_{2m} + i w_{N-1-2m}) exp(-i pi (4m + 1) / (4N)),

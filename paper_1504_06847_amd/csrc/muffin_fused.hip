@@ -178,8 +178,11 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
     }
 }
 
+// one pixel per thread: at most 128 registers (4 waves per SIMD), so that a
+// CU holds 16 waves at every row length (two 512-thread work-groups, four
+// of 256, ...) as at 1024; two pixels per thread: 256 (2 waves per SIMD)
 template <typename T, int NX, int LT, bool DENSE, int PPT>
-__global__ void __launch_bounds__(NX / PPT)
+__global__ void __launch_bounds__(NX / PPT, PPT == 1 ? 4 : 2)
 k_fused(FusedArrays A, const T* __restrict__ D, int Lrt, int ny, SpecArgs a,
         const cx<T>* __restrict__ tw, int twlog) {
     __shared__ FusedLds<T, NX, LT> sh;
@@ -189,7 +192,7 @@ k_fused(FusedArrays A, const T* __restrict__ D, int Lrt, int ny, SpecArgs a,
 // the fused pass over the rows of several cubes of one row length and band
 // count (one block per image row of each cube)
 template <typename T, int NX, int LT, bool DENSE>
-__global__ void __launch_bounds__(NX)
+__global__ void __launch_bounds__(NX, 4)
 k_fused_group(const FusedDesc* __restrict__ d, int n) {
     __shared__ FusedLds<T, NX, LT> sh;
     int j = 0;

@@ -117,13 +117,20 @@ int spectral_gshift(unsigned band_bytes);     // SpecArrays::gshift for this ban
 int row_blocks(int nrows, int nx, int variant);
 int col_blocks(int dtype, int L, int ny, int nx, int variant);
 int spectral_block_threads(long npix);
+// pixels per block of the (grouped) spectral pass of L bands over npix
+// pixels of elem bytes: the `nth` of launch_spectral_group (128 bands: 64
+// pixels on two waves where spectral_pair_fits, i.e. 64 bands of an array
+// span at most 2^31 bytes; otherwise one pixel per thread)
+bool spectral_pair_fits(long npix, int elem);
+int spectral_block_pixels(int L, long npix, int elem);
 hipError_t launch_row_fwd_group(int dtype, int nx, int variant, const RowDesc* d, int n, int nblocks,
                                 hipStream_t s);
 hipError_t launch_row_inv_group(int dtype, int nx, int variant, const RowDesc* d, int n, int nblocks,
                                 hipStream_t s);
 hipError_t launch_col_group(int dtype, int ny, int variant, const ColDesc* d, int n, int nblocks,
                             hipStream_t s);
-// cubes of one band count L and one block size (npix >= 256 or all equal npix)
+// cubes of one band count L and one block size; nth = spectral_block_pixels
+// (npix >= 256 or all equal npix)
 hipError_t launch_spectral_group(int dtype, int L, int nth, const SpecDesc* d, int n, int nblocks,
                                  hipStream_t s);
 

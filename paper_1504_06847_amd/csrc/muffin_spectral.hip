@@ -148,37 +148,32 @@ k_spectral_group(const SpecDesc* __restrict__ d, int n) {
 constexpr int SPLIT_N = 128;       // bands per wave
 constexpr int SPLIT_NTH = 128;     // two waves, 64 pixels
 
-// round q of an exchange moves registers [0, 32) and [96, 128) (q = 0), then
-// [32, 96) (q = 1), so that register r and register 127 - r travel together;
-// slot i of a round holds register round_reg(q, i), register r sits in slot
-// slot_of(r)
-__host__ __device__ constexpr int round_reg(int q, int i) { return q == 0 ? (i < 32 ? i : 64 + i) : 32 + i; }
-__host__ __device__ constexpr int slot_of(int r) { return r < 32 ? r : (r < 96 ? r - 32 : r - 64); }
-
-// the forward butterfly: wave 0 (h = 0) ends with u_n in register n, wave 1
-// with w_j in register j (its register r held band 128 + r = x_{255 - (127 - r)})
-template <typename T>
-__device__ __forceinline__ void split_fwd(T (&v)[SPLIT_N], int h, T (*xch)[SPLIT_NTH]) {
+// (the exchange rounds: round_reg, slot_of in muffin_device.hpp)
+// the forward butterfly of a 2N-band vector held as two halves of N:
+// wave 0 (h = 0) ends with u_n in register n, wave 1 with w_j in register j
+// (its register r held band N + r = x_{2N-1 - (N-1 - r)})
+template <typename T, int N>
+__device__ __forceinline__ void split_fwd(T (&v)[N], int h, T (*xch)[SPLIT_NTH]) {
     const T rs = T(0.70710678118654752440084436210484903928);
     const int t = threadIdx.x, o = t ^ 64;      // the partner: same lane of the other wave
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
 #pragma unroll
-        for (int i = 0; i < 64; ++i) xch[i][t] = v[round_reg(q, i)];
+        for (int i = 0; i < N / 2; ++i) xch[i][t] = v[round_reg<N>(q, i)];
         __syncthreads();
         if (h == 0) {
 #pragma unroll
-            for (int i = 0; i < 64; ++i) {
-                const int n = round_reg(q, i);
-                v[n] = (v[n] + xch[slot_of(127 - n)][o]) * rs;
+            for (int i = 0; i < N / 2; ++i) {
+                const int n = round_reg<N>(q, i);
+                v[n] = (v[n] + xch[slot_of<N>(N - 1 - n)][o]) * rs;
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                const int j = q == 0 ? i : 32 + i;
-                const T a = v[j], b = v[127 - j];
-                v[j] = (xch[slot_of(j)][o] - b) * rs;
-                v[127 - j] = (xch[slot_of(127 - j)][o] - a) * rs;
+            for (int i = 0; i < N / 4; ++i) {
+                const int j = q == 0 ? i : N / 4 + i;
+                const T a = v[j], b = v[N - 1 - j];
+                v[j] = (xch[slot_of<N>(j)][o] - b) * rs;
+                v[N - 1 - j] = (xch[slot_of<N>(N - 1 - j)][o] - a) * rs;
             }
         }
         __syncthreads();
@@ -186,33 +181,114 @@ __device__ __forceinline__ void split_fwd(T (&v)[SPLIT_N], int h, T (*xch)[SPLIT
 }
 
 // the inverse butterfly: from u_n (wave 0) and w_n (wave 1) in register n
-// back to bands 0..127 (wave 0) and 128..255 (wave 1)
-template <typename T>
-__device__ __forceinline__ void split_inv(T (&v)[SPLIT_N], int h, T (*xch)[SPLIT_NTH]) {
+// back to bands 0..N-1 (wave 0) and N..2N-1 (wave 1)
+template <typename T, int N>
+__device__ __forceinline__ void split_inv(T (&v)[N], int h, T (*xch)[SPLIT_NTH]) {
     const T rs = T(0.70710678118654752440084436210484903928);
     const int t = threadIdx.x, o = t ^ 64;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
 #pragma unroll
-        for (int i = 0; i < 64; ++i) xch[i][t] = v[round_reg(q, i)];
+        for (int i = 0; i < N / 2; ++i) xch[i][t] = v[round_reg<N>(q, i)];
         __syncthreads();
         if (h == 0) {
 #pragma unroll
-            for (int i = 0; i < 64; ++i) {
-                const int n = round_reg(q, i);
-                v[n] = (v[n] + xch[slot_of(n)][o]) * rs;                 // x_n = (u_n + w_n) / sqrt 2
+            for (int i = 0; i < N / 2; ++i) {
+                const int n = round_reg<N>(q, i);
+                v[n] = (v[n] + xch[slot_of<N>(n)][o]) * rs;               // x_n = (u_n + w_n) / sqrt 2
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                const int j = q == 0 ? i : 32 + i;
-                const T a = v[j], b = v[127 - j];
-                v[127 - j] = (xch[slot_of(j)][o] - a) * rs;              // x_{255-j} = (u_j - w_j) / sqrt 2
-                v[j] = (xch[slot_of(127 - j)][o] - b) * rs;              // x_{128+j}
+            for (int i = 0; i < N / 4; ++i) {
+                const int j = q == 0 ? i : N / 4 + i;
+                const T a = v[j], b = v[N - 1 - j];
+                v[N - 1 - j] = (xch[slot_of<N>(j)][o] - a) * rs;         // x_{2N-1-j} = (u_j - w_j) / sqrt 2
+                v[j] = (xch[slot_of<N>(N - 1 - j)][o] - b) * rs;         // x_{N+j}
             }
         }
         __syncthreads();
     }
+}
+
+// 128 bands: the same split at N = 64 in one launch.  With 64 band values
+// per thread the transforms fit beside the element-wise steps (as the
+// one-thread pass at 64 bands), so q stays in registers: wave h forms
+// steps II, III, V, VI for bands 64 h .. 64 h + 63 of its 64 pixels.  The
+// one-thread pass at 128 bands holds 128 values (192 registers, 2 waves per
+// SIMD); the reporting pass still uses it.
+constexpr int PAIR_N = 64;
+
+template <typename T>
+__device__ __forceinline__ void spectral_pair_body(const SpecArrays& A, const SpecArgs& a, unsigned blk) {
+    constexpr int N = PAIR_N;
+    __shared__ T xch[N / 2][SPLIT_NTH];
+    const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long p = (long)blk * 64 + (threadIdx.x & 63);
+    const unsigned off = (unsigned)p * (unsigned)sizeof(T);
+    const unsigned bb = A.band_bytes;
+    // one buffer descriptor per array for the wave's 64 bands (64 band_bytes
+    // within 2^31 bytes: checked on the host, spectral_pair_fits)
+    const size_t h0 = (size_t)h * N * bb;
+    const BandArray1<T> X(A.X + h0, bb), Brest(A.Brest + h0, bb);
+    const BandArray1<T, kStreamCpol> zP(A.zP + h0, bb), zT(A.zT + h0, bb), zV(A.zV + h0, bb), GS(A.GS + h0, bb);
+    const BandArray1<T, kStreamCpol> zPo(A.zPo + h0, bb), zTo(A.zTo + h0, bb), zVo(A.zVo + h0, bb),
+        GSo(A.GSo + h0, bb);
+    const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
+    const T tauT = T(a.tau_T), tauV = T(a.tau_V);
+    const T inv_rhoV = T(1.0 / a.rho_V), inv_VS = T(1.0 / (a.rho_V + a.rho_S));
+    T v[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) v[l] = zV.load(l, off);
+    // step IV: DCT-II of 128 = butterfly, DCT-II of 64 (even coefficients,
+    // wave 0) and DCT-IV of 64 (odd, wave 1); soft threshold; back
+    split_fwd<T, N>(v, h, xch);
+    if (h == 0) dct2_ortho<T, N>(v);
+    else dct4_ortho<T, N>(v);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = softt(v[k], tauV);
+    if (h == 0) dct3_ortho<T, N>(v);
+    else dct4_ortho<T, N>(v);
+    split_inv<T, N>(v, h, xch);
+    __builtin_amdgcn_sched_barrier(0);
+    // steps II, III, V, VI for this wave's bands (the formulas of spectral_body)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int l = i;              // band 64 h + i
+        const T x = X.load(l, off), gs = GS.load(l, off), zp = zP.load(l, off), zt = zT.load(l, off);
+        const T q = v[i];
+        const T s = (rhoV * q + rhoS * x) * inv_VS;
+        const T gs2 = gs + rhoV * (q - s);
+        const T zp2 = x - (zp < T(0) ? -zp : T(0));
+        const T zt2 = x + clipt(zt, tauT);
+        const T tt = softt(zt2, tauT);
+        const T zv2 = s - gs2 * inv_rhoV;
+        const T sv = zv2 + gs2 * inv_rhoV;
+        const T b = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * sv;
+        zVo.store(l, off, zv2);
+        GSo.store(l, off, gs2);
+        zPo.store(l, off, zp2);
+        zTo.store(l, off, zt2);
+        Brest.store(l, off, b);
+        if ((i & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SPLIT_NTH)
+k_spectral_pair(SpecArrays A, SpecArgs a) {
+    spectral_pair_body<T>(A, a, blockIdx.x);
+}
+
+// the 128-band pass over the pixels of several cubes (64 pixels per block)
+template <typename T>
+__global__ void __launch_bounds__(SPLIT_NTH)
+k_spectral_pair_group(const SpecDesc* __restrict__ d, int n) {
+    int j = 0;
+    while (j + 1 < n && blockIdx.x >= (unsigned)d[j + 1].first) ++j;
+    const unsigned b = blockIdx.x - (unsigned)d[j].first;
+    if (blockIdx.x < (unsigned)d[j].first || b >= (unsigned)d[j].nblk) return;
+    spectral_pair_body<T>(d[j].A, d[j].a, b);
 }
 
 // The pass runs in two launches, each with the occupancy it can have: the
@@ -239,7 +315,7 @@ k_spectral_split_q(SpecArrays A, SpecArgs a, double* __restrict__ partials) {
     T v[SPLIT_N];
 #pragma unroll
     for (int l = 0; l < SPLIT_N; ++l) v[l] = zV.load(l0 + l, off);
-    split_fwd<T>(v, h, xch);
+    split_fwd<T, SPLIT_N>(v, h, xch);
     if (h == 0) dct2_ortho<T, SPLIT_N>(v);
     else dct4_ortho<T, SPLIT_N>(v);
 #pragma unroll
@@ -250,7 +326,7 @@ k_spectral_split_q(SpecArrays A, SpecArgs a, double* __restrict__ partials) {
     }
     if (h == 0) dct3_ortho<T, SPLIT_N>(v);
     else dct4_ortho<T, SPLIT_N>(v);
-    split_inv<T>(v, h, xch);
+    split_inv<T, SPLIT_N>(v, h, xch);
 #pragma unroll
     for (int i = 0; i < SPLIT_N; ++i) Q.store(l0 + i, off, v[i]);
     if constexpr (REDUCE) {
@@ -318,7 +394,7 @@ k_dct_l1_split(SpecArrays A, double* __restrict__ partials) {
         const T z = zP.load(h * SPLIT_N + l, off);
         v[l] = z > T(0) ? z : T(0);
     }
-    split_fwd<T>(v, h, xch);
+    split_fwd<T, SPLIT_N>(v, h, xch);
     if (h == 0) dct2_ortho<T, SPLIT_N>(v);
     else dct4_ortho<T, SPLIT_N>(v);
     double pd = 0.0;
@@ -444,6 +520,8 @@ static hipError_t spectral_t(const SpecLaunch& g, const SpecArgs& a, hipStream_t
         B.zP = A.zPo;
         hipLaunchKernelGGL((k_dct_l1<T, LT, DENSE>), grid, dim3(nth), 0, s, B, (const T*)g.dctm, g.L,
                            npix, g.partials);
+    } else if (LT == 2 * PAIR_N && !DENSE && spectral_pair_fits(npix, (int)sizeof(T))) {
+        hipLaunchKernelGGL((k_spectral_pair<T>), dim3((unsigned)(npix / 64)), dim3(SPLIT_NTH), 0, s, A, a);
     } else {
         hipLaunchKernelGGL((k_spectral<T, LT, DENSE, false>), grid, dim3(nth), 0, s, A,
                            (const T*)g.dctm, g.L, npix, a, g.vpart);
@@ -510,6 +588,10 @@ static hipError_t spectral_dispatch(const SpecLaunch& g, const SpecArgs& a, hipS
 }
 
 int spectral_block_threads(long npix) { return npix < SPEC_NTH ? (int)npix : SPEC_NTH; }
+bool spectral_pair_fits(long npix, int elem) { return (long long)PAIR_N * npix * elem <= (1ll << 31); }
+int spectral_block_pixels(int L, long npix, int elem) {
+    return L == 2 * PAIR_N && spectral_pair_fits(npix, elem) ? 64 : spectral_block_threads(npix);
+}
 int spectral_gshift(unsigned band_bytes) { return band_group_shift(band_bytes); }
 
 template <typename T>
@@ -523,7 +605,12 @@ static hipError_t spectral_group_t(int L, const SpecDesc* d, int n, int nblocks,
         case 16: hipLaunchKernelGGL((k_spectral_group<T, 16, false>), g, b, 0, s, d, n); return hipGetLastError();
         case 32: hipLaunchKernelGGL((k_spectral_group<T, 32, false>), g, b, 0, s, d, n); return hipGetLastError();
         case 64: hipLaunchKernelGGL((k_spectral_group<T, 64, false>), g, b, 0, s, d, n); return hipGetLastError();
-        case 128: hipLaunchKernelGGL((k_spectral_group<T, 128, false>), g, b, 0, s, d, n); return hipGetLastError();
+        case 128:
+            // 64 pixels per block: the two-wave pass (every cube within
+            // spectral_pair_fits), else one pixel per thread
+            if (nth == 64) hipLaunchKernelGGL((k_spectral_pair_group<T>), g, dim3(SPLIT_NTH), 0, s, d, n);
+            else hipLaunchKernelGGL((k_spectral_group<T, 128, false>), g, b, 0, s, d, n);
+            return hipGetLastError();
         default: break;
     }
     if (L < 1 || L > 32) return hipErrorInvalidValue;

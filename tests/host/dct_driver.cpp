@@ -4,10 +4,10 @@
 //   DCT-II  c_k = a_k sum_l x_l cos(pi (2l + 1) k / (2L)), a_0 = sqrt(1/L), a_k = sqrt(2/L)
 //   DCT-III its transpose (the inverse)
 //   DCT-IV  y_k = sqrt(2/L) sum_l x_l cos(pi (2l + 1)(2k + 1) / (4L))
-// and the 256-band form of the DCT-II: a butterfly of the two halves
-// (u_n = (x_n + x_{255-n}) / sqrt 2, w_n = (x_n - x_{255-n}) / sqrt 2) then
-// DCT-II(u) for the even and DCT-IV(w) for the odd coefficients, and back,
-// in the kernel's order of operations.
+// and the 2N-band form of the DCT-II (256 and 128 bands): a butterfly of the
+// two halves (u_n = (x_n + x_{2N-1-n}) / sqrt 2, w_n = (x_n - x_{2N-1-n}) /
+// sqrt 2) then DCT-II(u) for the even and DCT-IV(w) for the odd
+// coefficients, and back, in the kernels' order of operations.
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -47,16 +47,16 @@ static double check(std::mt19937_64& rng, int kind) {
     return worst;
 }
 
-// The 256-band DCT-II and its inverse through the two halves, as the kernel
-// does it (the exchange between its two waves is a plain copy here).
-template <typename T>
-static void split256(T (&lo)[128], T (&hi)[128], bool inverse) {
-    constexpr int N = 128;
+// The 2N-band DCT-II and its inverse through the two halves, as the kernels
+// do it at 256 bands (N = 128) and 128 bands (N = 64); the exchange between
+// their two waves is a plain copy here.
+template <typename T, int N>
+static void split2n(T (&lo)[N], T (&hi)[N], bool inverse) {
     const T rs = T(0.70710678118654752440084436210484903928);
     T a[N], b[N];
     for (int i = 0; i < N; ++i) { a[i] = lo[i]; b[i] = hi[i]; }
     if (!inverse) {
-        // lo: bands 0..127, hi: bands 128..255
+        // lo: bands 0..N-1, hi: bands N..2N-1
         for (int n = 0; n < N; ++n) lo[n] = (a[n] + b[N - 1 - n]) * rs;      // u
         for (int j = 0; j < N; ++j) hi[j] = (a[j] - b[N - 1 - j]) * rs;      // w
         muffin::dct2_ortho<T, N>(lo);                                       // c_{2k}
@@ -65,13 +65,13 @@ static void split256(T (&lo)[128], T (&hi)[128], bool inverse) {
         muffin::dct3_ortho<T, N>(a);                                        // u
         muffin::dct4_ortho<T, N>(b);                                        // w
         for (int n = 0; n < N; ++n) lo[n] = (a[n] + b[n]) * rs;            // x_n
-        for (int n = 0; n < N; ++n) hi[N - 1 - n] = (a[n] - b[n]) * rs;    // x_{255-n}
+        for (int n = 0; n < N; ++n) hi[N - 1 - n] = (a[n] - b[n]) * rs;    // x_{2N-1-n}
     }
 }
 
-template <typename T>
+template <typename T, int N>
 static double check_split(std::mt19937_64& rng, bool inverse) {
-    constexpr int L = 256, N = 128;
+    constexpr int L = 2 * N;
     std::normal_distribution<double> nd;
     double worst = 0.0;
     for (int trial = 0; trial < 10; ++trial) {
@@ -84,7 +84,7 @@ static double check_split(std::mt19937_64& rng, bool inverse) {
             // coefficient c_{2k} in lo[k], c_{2k+1} in hi[k]
             for (int k = 0; k < N; ++k) { lo[k] = (T)x[2 * k]; hi[k] = (T)x[2 * k + 1]; }
         }
-        split256<T>(lo, hi, inverse);
+        split2n<T, N>(lo, hi, inverse);
         long double nrm = 0, err = 0;
         for (int k = 0; k < L; ++k) {
             long double ref = 0;
@@ -97,6 +97,51 @@ static double check_split(std::mt19937_64& rng, bool inverse) {
         if (r > worst) worst = r;
     }
     return worst;
+}
+
+// The kernels' exchange of the forward and inverse butterflies (two rounds
+// of N/2 registers through LDS, slots by round_reg / slot_of) with the two
+// waves' LDS rows as host arrays: it must give the plain butterflies of
+// split2n bit for bit.
+template <typename T, int N>
+static bool exchange_matches(std::mt19937_64& rng) {
+    using muffin::round_reg;
+    using muffin::slot_of;
+    const T rs = T(0.70710678118654752440084436210484903928);
+    std::normal_distribution<double> nd;
+    for (int inverse = 0; inverse < 2; ++inverse) {
+        T v0[N], v1[N], lo[N], hi[N];
+        for (int i = 0; i < N; ++i) { v0[i] = lo[i] = (T)nd(rng); v1[i] = hi[i] = (T)nd(rng); }
+        for (int q = 0; q < 2; ++q) {
+            T x0[N / 2], x1[N / 2];
+            for (int i = 0; i < N / 2; ++i) { x0[i] = v0[round_reg<N>(q, i)]; x1[i] = v1[round_reg<N>(q, i)]; }
+            for (int i = 0; i < N / 2; ++i) {
+                const int n = round_reg<N>(q, i);
+                v0[n] = (v0[n] + x1[inverse ? slot_of<N>(n) : slot_of<N>(N - 1 - n)]) * rs;
+            }
+            for (int i = 0; i < N / 4; ++i) {
+                const int j = q == 0 ? i : N / 4 + i;
+                const T a = v1[j], b = v1[N - 1 - j];
+                if (!inverse) {
+                    v1[j] = (x0[slot_of<N>(j)] - b) * rs;
+                    v1[N - 1 - j] = (x0[slot_of<N>(N - 1 - j)] - a) * rs;
+                } else {
+                    v1[N - 1 - j] = (x0[slot_of<N>(j)] - a) * rs;
+                    v1[j] = (x0[slot_of<N>(N - 1 - j)] - b) * rs;
+                }
+            }
+        }
+        // the plain butterflies on the same values
+        T a[N], b[N];
+        for (int i = 0; i < N; ++i) { a[i] = lo[i]; b[i] = hi[i]; }
+        for (int n = 0; n < N; ++n) {
+            if (!inverse) { lo[n] = (a[n] + b[N - 1 - n]) * rs; hi[n] = (a[n] - b[N - 1 - n]) * rs; }
+            else { lo[n] = (a[n] + b[n]) * rs; hi[N - 1 - n] = (a[n] - b[n]) * rs; }
+        }
+        for (int i = 0; i < N; ++i)
+            if (v0[i] != lo[i] || v1[i] != hi[i]) return false;
+    }
+    return true;
 }
 
 template <int L>
@@ -120,11 +165,20 @@ int main() {
     std::mt19937_64 rng(1234);
     int bad = run<1>(rng) + run<2>(rng) + run<4>(rng) + run<8>(rng) + run<16>(rng) + run<32>(rng) + run<64>(rng) +
               run<128>(rng);
-    const double s64f = check_split<double>(rng, false), s64i = check_split<double>(rng, true);
-    const double s32f = check_split<float>(rng, false), s32i = check_split<float>(rng, true);
+    const double s64f = check_split<double, 128>(rng, false), s64i = check_split<double, 128>(rng, true);
+    const double s32f = check_split<float, 128>(rng, false), s32i = check_split<float, 128>(rng, true);
     std::printf("L=256 (two halves)  f64 dct2 %.2e dct3 %.2e   f32 dct2 %.2e dct3 %.2e\n", s64f, s64i, s32f, s32i);
     if (s64f > 1e-14 || s64i > 1e-14) ++bad;
     if (s32f > 2e-6 || s32i > 2e-6) ++bad;
+    const double h64f = check_split<double, 64>(rng, false), h64i = check_split<double, 64>(rng, true);
+    const double h32f = check_split<float, 64>(rng, false), h32i = check_split<float, 64>(rng, true);
+    std::printf("L=128 (two halves)  f64 dct2 %.2e dct3 %.2e   f32 dct2 %.2e dct3 %.2e\n", h64f, h64i, h32f, h32i);
+    if (h64f > 1e-14 || h64i > 1e-14) ++bad;
+    if (h32f > 2e-6 || h32i > 2e-6) ++bad;
+    const bool ex = exchange_matches<float, 128>(rng) && exchange_matches<double, 128>(rng) &&
+                    exchange_matches<float, 64>(rng) && exchange_matches<double, 64>(rng);
+    std::printf("two-wave exchange (N = 128, 64): %s\n", ex ? "bitwise the plain butterflies" : "MISMATCH");
+    if (!ex) ++bad;
     if (!bad) std::printf("ALL OK\n");
     return bad ? 1 : 0;
 }

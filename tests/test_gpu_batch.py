@@ -167,6 +167,25 @@ def test_autotune_keeps_results_and_state(gpu_lib, tmp_path):
     assert c.autotune(cache=cache) == tuple(sch)    # read back from the cache file
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_128_band_cubes_batch_bitwise(gpu_lib, dtype):
+    """128-band cubes take the two-wave spectral pass (64 pixels per block)
+    in grouped launches as on their own: the batch repeats the single-cube
+    runs bit for bit, next to a cube of another band count."""
+    from paper_1504_06847_amd import Batch, Solver
+    cubes = _cubes([(128, 16, 16), (128, 8, 32), (64, 8, 8)], seed0=360)
+    b = Batch(cubes, dtype=dtype, params=PARAMS)
+    singles = [Solver(p, d, dtype=dtype, **PARAMS) for p, d in cubes]
+    b.iterate(5)
+    for s in singles:
+        s.iterate(5)
+    torch.cuda.synchronize()
+    for i, s in enumerate(singles):
+        assert torch.equal(b.cube(i).x, s.x), f"cube {i}"
+        assert torch.equal(b.cube(i).get_state(), s.get_state()), f"cube {i}"
+    b.close()
+
+
 def test_batch_runs_fused_form_2_as_form_1(gpu_lib):
     """A cube set to the two-pixel fused form joins the batch's grouped
     fused launch, which has one pixel per thread: the batch repeats the
