@@ -13,9 +13,11 @@ from .wavelets import (DIRAC, PAPER_DICTIONARY, Dictionary, daubechies_filter,
                        dwt2, idwt2, dwt_levels)
 from .spectral import (DCT, CHEBYSHEV, SPECTRAL_DIRAC, SpectralDictionary, chebyshev_basis,
                        basis_matrix)
+from .visibility import (VisProblem, vis_forward, vis_adjoint, toeplitz_kernel, toeplitz_apply, cg)
 
 __all__ = ["Params", "Problem", "State", "soft", "dct_nu", "idct_nu", "run",
            "admm_iteration", "objective", "residuals", "energy", "jvp_run",
            "mse_loss", "mse_grad", "set_workers", "solve_adaptive", "DIRAC", "PAPER_DICTIONARY",
            "Dictionary", "daubechies_filter", "dwt2", "idwt2", "dwt_levels", "DCT", "CHEBYSHEV",
-           "SPECTRAL_DIRAC", "SpectralDictionary", "chebyshev_basis", "basis_matrix"]
+           "SPECTRAL_DIRAC", "SpectralDictionary", "chebyshev_basis", "basis_matrix", "VisProblem",
+           "vis_forward", "vis_adjoint", "toeplitz_kernel", "toeplitz_apply", "cg"]

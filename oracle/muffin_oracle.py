@@ -22,7 +22,8 @@ What it computes, and where the paper defines it
   Gamma_P, Gamma_T, Gamma_V, Gamma_S are stored explicitly and start at zero.
   Step I solves Q_l x_l = b_l with Q_l = H_l^T H_l + rho I,
   rho = mu_eps + rho_S + rho_P + n_s rho_T (eq. Qlsimp), exactly, through the
-  Fourier-domain filter 1 / (|h_hat|^2 + rho) (end of Section 3).  Step V uses
+  Fourier-domain filter 1 / (|h_hat|^2 + rho) (end of Section 3); with the
+  visibility-domain model (``oracle/visibility.py``) by conjugate gradients.  Step V uses
   the closed form for one orthonormal W_nu (m_nu = 1).
 * Stopping quantities: primal / dual residuals of the two-block splitting
   (block 1 = {X, V}, block 2 = {P, T, S}) in the standard form of Boyd et al.
@@ -192,6 +193,15 @@ class Problem:
         """Q_l^{-1} b_l for every band: filter with (|h_hat|^2 + rho)^{-1}."""
         return _ifft2(self.filt * _fft2(b)).real
 
+    def step_one(self, b, x0):
+        """Step I: the exact solve (x0, the previous X, is not needed)."""
+        return self.solve_Q(b)
+
+    def misfit(self, x):
+        """1/2 ||Y - H x||^2."""
+        r = self.Y - self.H(x)
+        return 0.5 * np.sum(r * r)
+
 
 @dataclass
 class State:
@@ -226,7 +236,7 @@ def admm_iteration(prob: Problem, st: State) -> State:
     # Step I: b_l from eq. matB, then Q_l x_l = b_l
     B = (prob.HtY + prob.WsT(st.GT + p.rho_T * st.T) + st.GP + p.rho_P * st.P
          + st.GS + p.rho_S * st.S)
-    X = prob.solve_Q(B)
+    X = prob.step_one(B, st.X)
     # Step II: positivity
     P = np.maximum(0.0, X - st.GP / p.rho_P)
     # Step III: spatial soft threshold, per coefficient of every basis
@@ -261,8 +271,7 @@ def run(prob: Problem, K: int, state: State | None = None, callback=None) -> Sta
 def objective(prob: Problem, P: np.ndarray) -> float:
     """Criterion (costreg) + (RegAll) at P; finite because P >= 0."""
     p = prob.p
-    r = prob.Y - prob.H(P)
-    return float(0.5 * np.sum(r * r) + 0.5 * p.mu_eps * np.sum(P * P)
+    return float(prob.misfit(P) + 0.5 * p.mu_eps * np.sum(P * P)
                  + p.mu_s * np.sum(np.abs(prob.Ws(P))) + p.mu_nu * np.sum(np.abs(prob.Wnu.forward(P))))
 
 
