@@ -389,6 +389,49 @@ int muffin_batch_autotune(muffin_ctx* batch, int reps);
    -1 if `batch` is not a batch context. */
 int muffin_batch_launches(const muffin_ctx* batch);
 
+/* ---- the visibility-domain model -------------------------------------------
+   Section 2: the same algorithm with y_l the sampled visibilities of band l
+   and H_l the operator from the sky to them, (H_l x)_j = sum_{m,n} x[m][n]
+   exp(-2 pi i (u_j (n - nx/2) / nx + v_j (m - ny/2) / ny)), (u_j, v_j) in
+   cells of the nx x ny Fourier grid at that band's frequency (any real
+   values; the phase centre is pixel (ny/2, nx/2) as the PSF peak of
+   muffin_setup).  The sky is real: H_l^T = Re(H_l^H .) and Q_l = Re(H_l^H
+   H_l) + rho I (eq. Qlsimp), no longer diagonal in the Fourier domain, so
+   step I of Algorithm 1 runs n_cg conjugate-gradient iterations per band
+   (Hestenes-Stiefel), started from the previous pass's X (zero at the
+   first).  Each applies Re(H^H H) as a circular convolution on the
+   2ny x 2nx grid with the Toeplitz kernel c(d) = sum_j cos(2 pi (u_j d_x /
+   nx + v_j d_y / ny)), formed at setup (FP64) with the data term
+   Re(H^H y).  Built for the Dirac spatial basis (n_s = 1) and nx, ny <=
+   2048; any spectral dictionary.  On such a context muffin_iterate,
+   muffin_set_graph, muffin_get_x, muffin_get_p, the state calls,
+   muffin_set_params, muffin_reset, muffin_iterations and muffin_destroy work
+   as for muffin_setup's contexts; reports, muffin_solve*, the gradients,
+   muffin_autotune, muffin_set_schedule and muffin_profile return
+   MUFFIN_EUNSUPPORTED. */
+
+/* Bytes of device workspace muffin_setup_vis needs (0 if the shape or the
+   parameters are invalid for this model).  Host-only. */
+size_t muffin_vis_workspace_bytes(const muffin_shape* shape, const muffin_params* params);
+
+/* Set up one cube in the visibility domain.  n_vis: host [L], visibilities
+   per band (>= 0); uv: host, sum(n_vis) pairs (u, v) of doubles, band after
+   band; vis: host, sum(n_vis) pairs (re, im) of doubles in the same order
+   (both read during the call only); n_cg in [1, 100000].  workspace: device,
+   256-byte aligned, at least muffin_vis_workspace_bytes, owned by the
+   caller and held for the context's life.  Synchronous; allocates setup
+   temporaries (the visibilities, the kernel) and frees them before
+   returning.  Errors: EINVAL (NULL pointers, n_vis < 0, n_cg out of range),
+   EUNSUPPORTED (n_s > 1, nx or ny > 2048), EWORKSPACE, ENONFINITE (a
+   non-finite uv or vis), EDEVICE. */
+int muffin_setup_vis(muffin_ctx** ctx, const muffin_shape* shape, const muffin_params* params, const int* n_vis,
+                     const double* uv, const double* vis, int n_cg, void* workspace, size_t ws_bytes,
+                     void* stream);
+
+/* CG iterations per band and pass of a visibility-domain context (negative
+   if ctx is not one). */
+int muffin_vis_cg_iters(const muffin_ctx* ctx);
+
 /* Time n_iter passes with HIP events around every kernel launch on the
    context's stream; writes the mean duration in ms of each kernel of one
    pass to ms[i] and its name to names[i] (static strings), for up to `cap`

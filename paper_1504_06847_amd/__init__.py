@@ -9,5 +9,6 @@ from . import lib
 from .autograd import MuffinUnroll
 from .batch import Batch
 from .solver import PAPER_DICTIONARY, Solver
+from .vis import VisSolver
 
-__all__ = ["lib", "Batch", "MuffinUnroll", "PAPER_DICTIONARY", "Solver"]
+__all__ = ["lib", "Batch", "MuffinUnroll", "PAPER_DICTIONARY", "Solver", "VisSolver"]

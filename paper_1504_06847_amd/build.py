@@ -25,8 +25,8 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["muffin_fft.hip", "muffin_spectral.hip", "muffin_adjoint.hip", "muffin_fused.hip",
-               "muffin_wavelet.hip", "muffin_noalloc.hip"]
-HOST_SOURCES = ["muffin_validate.cpp", "muffin_api.cpp", "muffin_batch.cpp", "muffin_dict.cpp"]
+               "muffin_wavelet.hip", "muffin_noalloc.hip", "muffin_vis.hip"]
+HOST_SOURCES = ["muffin_validate.cpp", "muffin_api.cpp", "muffin_batch.cpp", "muffin_dict.cpp", "muffin_vis.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              # packed FP32 instructions stay disabled on this target

@@ -20,7 +20,7 @@ namespace {
 
 // the fused row/spectral launch exists for the fast DCT and the Dirac spatial basis
 bool fused_possible(const muffin_ctx* c) {
-    return c->lay.n_w == 0 && !spectral_dense(c->shape, c->params) &&
+    return !c->vis && c->lay.n_w == 0 && !spectral_dense(c->shape, c->params) &&
            fused_supported(c->shape.dtype, c->shape.nx, c->shape.ny, c->shape.L);
 }
 
@@ -156,6 +156,11 @@ int pass_io(muffin_ctx* c, void* const in[4], void* const out[4], void* xo) {
 }
 
 int pass_kernels(muffin_ctx* c) {
+    if (c->vis) {
+        // the visibility-domain model: step I by CG, then steps II-VI
+        if (int rc = vis_step_one(c)) return rc;
+        return step_spectral(c, false, nullptr);
+    }
     if (use_fused(c)) {
         if (int rc = row_forward(c)) return rc;
         if (int rc = col_solve(c)) return rc;
@@ -601,6 +606,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
 int grad_args(const muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, const void* out,
               const char* what) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = vis_unsupported(c, what)) return rc;
     if (c->lay.n_w) {
         set_error("%s: not built for a spatial dictionary with wavelet bases (n_s = %d)", what, c->params.n_s);
         return MUFFIN_EUNSUPPORTED;
@@ -759,6 +765,7 @@ static int no_wavelets(const muffin_ctx* c, const char* what) {
 
 int muffin_step_report(muffin_ctx* c, muffin_report* rep) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = vis_unsupported(c, "muffin_step_report")) return rc;
     if (int rc = no_wavelets(c, "convergence reports")) return rc;
     if (!rep) { set_error("report is NULL"); return MUFFIN_EINVAL; }
     return pass_with_report(c, rep);
@@ -766,6 +773,7 @@ int muffin_step_report(muffin_ctx* c, muffin_report* rep) {
 
 int muffin_solve(muffin_ctx* c, int max_iter, muffin_report* report) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = vis_unsupported(c, "muffin_solve")) return rc;
     if (int rc = no_wavelets(c, "muffin_solve (convergence reports)")) return rc;
     if (max_iter < 1) { set_error("max_iter = %d < 1", max_iter); return MUFFIN_EINVAL; }
     muffin_report rep{};
@@ -786,6 +794,7 @@ int muffin_solve(muffin_ctx* c, int max_iter, muffin_report* report) {
 
 int muffin_solve_adaptive(muffin_ctx* c, int max_iter, double mu, double tau, muffin_report* report) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = vis_unsupported(c, "muffin_solve_adaptive")) return rc;
     if (int rc = no_wavelets(c, "muffin_solve_adaptive (convergence reports)")) return rc;
     if (max_iter < 1) { set_error("max_iter = %d < 1", max_iter); return MUFFIN_EINVAL; }
     if (!std::isfinite(mu) || !std::isfinite(tau) || mu <= 1.0 || tau <= 1.0) {
@@ -952,6 +961,7 @@ int muffin_iterations(const muffin_ctx* c) {
 
 int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, int cap) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = vis_unsupported(c, "muffin_profile")) return rc;
     if (n_iter < 1 || !ms || cap < 1) { set_error("muffin_profile: bad arguments"); return MUFFIN_EINVAL; }
     // the kernels of one pass of the context's schedule, timed with events
     // between the launches (each pass runs: the state advances)
@@ -1052,6 +1062,7 @@ int muffin_set_grad_workspace(muffin_ctx* c, void* ws, size_t bytes) {
 
 int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = vis_unsupported(c, "muffin_autotune")) return rc;
     if (reps < 1) { set_error("reps = %d < 1", reps); return MUFFIN_EINVAL; }
     const muffin_shape& s = c->shape;
     const int dt = s.dtype, nrows = s.L * s.ny;
@@ -1141,6 +1152,7 @@ int muffin_autotune(muffin_ctx* c, int reps, int schedule[3]) {
 
 int muffin_set_schedule(muffin_ctx* c, const int schedule[3]) {
     if (int rc = check_ctx(c)) return rc;
+    if (int rc = vis_unsupported(c, "muffin_set_schedule")) return rc;
     if (!schedule || schedule[0] < 0 || schedule[0] >= kNumVariants || schedule[1] < 0 ||
         schedule[1] >= kNumVariants || schedule[2] < 0 || schedule[2] > 2) {
         set_error("schedule must hold two variant indices in [0, %d) and a fused form in [0, 2]", kNumVariants);
@@ -1183,6 +1195,7 @@ int muffin_destroy(muffin_ctx* c) {
     if (!c) return MUFFIN_OK;
     if (c->batch) return batch_destroy(c);
     drop_graphs(c);
+    if (c->vis) vis_destroy(c);
     if (c->cap) hipStreamDestroy(c->cap);
     delete c;
     return MUFFIN_OK;

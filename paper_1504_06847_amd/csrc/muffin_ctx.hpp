@@ -8,6 +8,7 @@
 #include "muffin_layout.hpp"
 
 struct muffin_batch;
+struct muffin_vis;
 
 struct muffin_ctx {
     // a batch context (muffin_setup_batch) holds its cubes here and none of
@@ -44,6 +45,9 @@ struct muffin_ctx {
     // scaling filter of each (lay.n_w of them)
     int wK[muffin::kMaxWavelets];
     double wh[muffin::kMaxWavelets][16];
+    // the visibility-domain model (muffin_setup_vis): step I by conjugate
+    // gradients; nullptr for the dirty-image model
+    muffin_vis* vis;
 };
 
 namespace muffin {
@@ -120,6 +124,13 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
 // argument checks of the gradient entry points (`out`: their output pointer)
 int grad_args(const muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, const void* out,
               const char* what);
+
+// the visibility-domain model (muffin_vis.cpp): step I of one pass by CG
+// (launches only, capturable); freeing its parts; EUNSUPPORTED for a call
+// the model does not have
+int vis_step_one(muffin_ctx* c);
+void vis_destroy(muffin_ctx* c);
+int vis_unsupported(const muffin_ctx* c, const char* what);
 
 // the batch calls behind muffin_iterate, muffin_set_graph, muffin_iterations
 // and muffin_destroy on a batch context (muffin_batch.cpp)

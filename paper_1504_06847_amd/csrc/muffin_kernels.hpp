@@ -134,6 +134,32 @@ hipError_t launch_col_group(int dtype, int ny, int variant, const ColDesc* d, in
 hipError_t launch_spectral_group(int dtype, int L, int nth, const SpecDesc* d, int n, int nblocks,
                                  hipStream_t s);
 
+// ---------------------------------------------------------------- visibility model
+// (muffin_vis.hip) Setup sums over the visibilities of each band (uv, vis:
+// device, 2 doubles per visibility, band l from off[l] to off[l + 1]):
+// mode 0 the Toeplitz kernel c on the 2ny x 2nx grid of lags, lag (0, 0) at
+// (ny, nx); mode 1 the data term Re(H^H y) on the ny x nx image.
+hipError_t launch_vis_sum(int dtype, int mode, const double* uv, const double* vis, const long* off, int L,
+                          int ny, int nx, void* out, hipStream_t s);
+// a cube of L unit impulses at pixel (ny/2, nx/2)
+hipError_t launch_vis_delta(int dtype, void* out, int L, int ny, int nx, hipStream_t s);
+// CG on Q_l x = b_l for every band: x, r, Ap, hty, brest plain cubes; P2 the
+// zero-padded 2ny x 2nx cube holding p; A2 = Re(H^H H) p on the padded grid
+// (the convolution's output); partials per (band, block); rr, alpha, beta
+// per band (FP64, device).  CG_PAD: x into P2.  CG_INIT: r = hty + brest -
+// (A2 + rho x), p = r, rr = r.r.  CG_AP: Ap = A2 + rho p, alpha = rr / p.Ap.
+// CG_XR: x += alpha p, r -= alpha Ap, beta = r.r / rr, rr = r.r.  CG_P:
+// p = r + beta p.
+enum CgOp { CG_PAD = 0, CG_INIT = 1, CG_AP = 2, CG_XR = 3, CG_P = 4 };
+struct CgVectors {
+    int L, ny, nx;
+    void *x, *r, *Ap, *P2;
+    const void *A2, *hty, *brest;
+    double *partials, *rr, *alpha, *beta;
+};
+int cg_blocks(long npix);       // blocks per band of the CG kernels (partials per band)
+hipError_t launch_cg(int dtype, int op, const CgVectors& v, double rho, hipStream_t s);
+
 // ---------------------------------------------------------------- reverse sweep
 // FP64 cotangent slots accumulated per block by the adjoint kernels
 enum GradSlot {

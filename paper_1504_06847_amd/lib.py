@@ -104,6 +104,10 @@ SIGNATURES = [
     ("muffin_batch_cube", c_void_p, [c_void_p, c_int]),
     ("muffin_batch_autotune", c_int, [c_void_p, c_int]),
     ("muffin_batch_launches", c_int, [c_void_p]),
+    ("muffin_vis_workspace_bytes", c_size_t, [POINTER(MuffinShape), POINTER(MuffinParams)]),
+    ("muffin_setup_vis", c_int, [POINTER(c_void_p), POINTER(MuffinShape), POINTER(MuffinParams), POINTER(c_int),
+                                 POINTER(c_double), POINTER(c_double), c_int, c_void_p, c_size_t, c_void_p]),
+    ("muffin_vis_cg_iters", c_int, [c_void_p]),
     ("muffin_profile", c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_char_p), c_int]),
     ("muffin_destroy", c_int, [c_void_p]),
     ("muffin_last_error", c_char_p, []),

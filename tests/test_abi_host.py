@@ -305,3 +305,49 @@ def test_spectral_bases_match_the_oracle(lib, L_):
     W = (ctypes.c_double * 4)()
     assert lib.muffin_spectral_basis(5, 2, W) == -1
     assert lib.muffin_spectral_basis(1, 0, W) == -1
+
+
+def test_visibility_workspace_and_validation(lib):
+    """muffin_vis_workspace_bytes: the image context, the 2ny x 2nx
+    convolution context and three cubes of CG vectors; 0 (with a reason) for
+    the wavelet dictionary and for images over 2048 on a side."""
+    from paper_1504_06847_amd import lib as L
+    s = L.MuffinShape(32, 16, 4, 0)
+    p = L.make_params(lib)
+    vb = lib.muffin_vis_workspace_bytes(ctypes.byref(s), ctypes.byref(p))
+    one = lib.muffin_workspace_bytes(ctypes.byref(s), ctypes.byref(p))
+    big = lib.muffin_workspace_bytes(ctypes.byref(L.MuffinShape(64, 32, 4, 0)), ctypes.byref(p))
+    assert vb >= one + big + 3 * 32 * 16 * 4 * 4
+    p9 = L.make_params(lib, spatial=(0, 1, 2), n_s=3)
+    assert lib.muffin_vis_workspace_bytes(ctypes.byref(s), ctypes.byref(p9)) == 0
+    assert "Dirac" in L.last_error(lib)
+    assert lib.muffin_vis_workspace_bytes(ctypes.byref(L.MuffinShape(4096, 16, 4, 0)), ctypes.byref(p)) == 0
+    assert "2048" in L.last_error(lib)
+
+
+def test_setup_vis_rejects_bad_arguments_before_touching_the_gpu(lib):
+    from ctypes import POINTER, byref, c_double, c_int, c_void_p
+    from paper_1504_06847_amd import lib as L
+    s = L.MuffinShape(16, 16, 2, 0)
+    p = L.make_params(lib)
+    ctx = c_void_p()
+    n_vis = (c_int * 2)(3, 2)
+    uv = (c_double * 10)(*([0.5] * 10))
+    vis = (c_double * 10)(*([1.0] * 10))
+    ws_ok = lib.muffin_vis_workspace_bytes(byref(s), byref(p))
+    fake = c_void_p(1 << 20)                # never dereferenced on these paths
+
+    def setup(nv=n_vis, u=uv, v=vis, n_cg=4, ws=fake, nb=ws_ok, out=True):
+        return lib.muffin_setup_vis(byref(ctx) if out else None, byref(s), byref(p), nv, u, v, n_cg, ws, nb, None)
+
+    assert setup(out=False) == L.MUFFIN_EINVAL
+    assert setup(nv=None) == L.MUFFIN_EINVAL
+    assert setup(n_cg=0) == L.MUFFIN_EINVAL and "n_cg" in L.last_error(lib)
+    assert setup(n_cg=100001) == L.MUFFIN_EINVAL
+    assert setup(nv=(c_int * 2)(3, -1)) == L.MUFFIN_EINVAL
+    assert setup(u=None) == L.MUFFIN_EINVAL
+    bad = (c_double * 10)(*([0.5] * 9 + [float("nan")]))
+    assert setup(u=bad) == L.MUFFIN_ENONFINITE
+    assert setup(nb=ws_ok - 1) == L.MUFFIN_EWORKSPACE
+    assert setup(ws=c_void_p((1 << 20) + 8)) == L.MUFFIN_EWORKSPACE and "aligned" in L.last_error(lib)
+    assert not ctx.value
