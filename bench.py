@@ -321,6 +321,39 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def run_vis(steps, warmup, n_cg=10):
+    """The visibility-domain model (step I by n_cg CG iterations per band) at
+    the paper's run shape, 256 x 256 x 15, FP32, graph replay: the 20-antenna
+    track's 190 baselines x 60 samples = 11,400 visibilities per band."""
+    import torch
+    from paper_1504_06847_amd import VisSolver
+    from synth import get_config
+    from synth.visibilities import make_vis_instance
+    p = get_config("paper256").params
+    inst = make_vis_instance(256, 256, 15, n_points=20, n_gauss=5, n_ant=20, noise_sigma=0.01, seed=6, n_time=60)
+    kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho_P=p.rho_P, rho_T=p.rho_T, rho_V=p.rho_V,
+              rho_S=p.rho_S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = VisSolver(inst.uv, inst.vis, inst.shape, n_cg=n_cg, graph=True, **kw)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    s.iterate(warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    s.iterate(steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    s.close()
+    V = 15 * 256 * 256
+    return {"shape": [15, 256, 256], "n_vis_per_band": int(inst.vis[0].size), "n_cg": n_cg, "steps": steps,
+            "value": V * steps / (ms / 1e3), "unit": "voxel-iterations/s", "ms_per_step": round(ms / steps, 4),
+            "setup_s": round(t_setup, 3),
+            "paper_350_iterations_s": round(350 * ms / steps / 1e3, 3)}
+
+
 def run_batch(steps, warmup):
     """voxel-iterations/s of the batch: each cube iterated on its own (one
     cube after another, the plain per-cube launches), then grouped launches,
@@ -387,6 +420,8 @@ def main(argv=None):
                     help="launch each pass's kernels one by one instead of replaying a HIP graph")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-cube batch measurement")
     ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--vis-steps", type=int, default=20,
+                    help="timed passes of the visibility-domain model at 256x256x15 (0: skip)")
     ap.add_argument("--dict-steps", type=int, default=10,
                     help="timed passes with the paper's spatial dictionary (0: skip)")
     ap.add_argument("--large-steps", type=int, default=200,
@@ -449,6 +484,10 @@ def main(argv=None):
         pcfg = get_config("paper256")
         dictionary["paper_shape"] = run_dictionary(pcfg.make(), pcfg.params, 5 * a.dict_steps, 3, 3,
                                                    graph=a.graph)
+    vis = None
+    if a.vis_steps > 0:
+        _log(f"bench: visibility-domain model, {a.vis_steps} timed passes")
+        vis = run_vis(a.vis_steps, 3)
     batch = None
     if not a.no_batch:
         _log(f"bench: 16-cube batch, {a.batch_steps} passes per form")
@@ -494,6 +533,7 @@ def main(argv=None):
         "fp64": fp64,
         "grad": grad,
         "dictionary": dictionary,
+        "visibility": vis,
         "batched": batch,
         "large": large,
         "cpu_baseline": cpu,
