@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "muffin.h"
@@ -38,7 +39,16 @@ struct Class {
     std::vector<int> cubes;
     int nblocks;             // grid of the grouped launch
     size_t slot0;            // first descriptor slot of the class
+    int lane;                // stream lane of the class (see assign_lanes)
 };
+
+// The cubes of a batch are independent: they are spread over up to
+// kMaxLanes streams (lanes), balanced by voxels, and a grouped launch only
+// groups cubes of one lane, so that the launches of different lanes overlap
+// (the small, latency-bound launches of small cubes with the large ones).  A
+// pass forks from the caller's stream to the lanes and joins back (events),
+// which graph capture records as parallel branches.
+constexpr int kMaxLanes = 4;
 
 }  // namespace
 
@@ -58,6 +68,10 @@ struct muffin_batch {
     hipStream_t cap;
     hipGraphExec_t gexec;
     int passes;                            // batch passes run since setup
+    int n_lanes;                           // stream lanes of the current classes
+    hipStream_t lane_s[kMaxLanes];
+    hipEvent_t lane_e[kMaxLanes];
+    hipEvent_t fork_e;
 };
 
 namespace {
@@ -67,15 +81,16 @@ void drop_graph(muffin_batch* b) {
     b->gexec = nullptr;
 }
 
-int class_of(muffin_batch* b, int kind, int key, int nth) {
+int class_of(muffin_batch* b, int kind, int key, int nth, int lane) {
     for (size_t i = 0; i < b->classes.size(); ++i) {
         const Class& c = b->classes[i];
-        if (c.kind == kind && c.key == key && c.nth == nth) return int(i);
+        if (c.kind == kind && c.key == key && c.nth == nth && c.lane == lane) return int(i);
     }
     Class c{};
     c.kind = kind;
     c.key = key;
     c.nth = nth;
+    c.lane = lane;
     c.variant = kind == K_COL ? kDefaultColVariant : kDefaultRowVariant;
     b->classes.push_back(c);
     return int(b->classes.size() - 1);
@@ -192,22 +207,62 @@ int upload(muffin_batch* b) {
     return MUFFIN_OK;
 }
 
+// lanes: cubes of one shape and pass form stay together (they share every
+// grouped launch); these groups, largest first, go to the least loaded lane
+void assign_lanes(muffin_batch* b, std::vector<int>& lane_of) {
+    std::vector<int> group(size_t(b->n), -1);
+    std::vector<double> load;
+    for (int i = 0; i < b->n; ++i) {
+        if (group[size_t(i)] >= 0) continue;
+        const muffin_shape& s = b->cubes[size_t(i)]->shape;
+        const bool f = fused_pass(b->cubes[size_t(i)]);
+        const int g = int(load.size());
+        load.push_back(0.0);
+        for (int j = i; j < b->n; ++j) {
+            const muffin_shape& t = b->cubes[size_t(j)]->shape;
+            if (group[size_t(j)] < 0 && t.nx == s.nx && t.ny == s.ny && t.L == s.L && fused_pass(b->cubes[size_t(j)]) == f) {
+                group[size_t(j)] = g;
+                load[size_t(g)] += double(voxels(t));
+            }
+        }
+    }
+    std::vector<int> order(load.size());
+    for (size_t g = 0; g < order.size(); ++g) order[g] = int(g);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return load[size_t(x)] > load[size_t(y)]; });
+    b->n_lanes = int(order.size()) < kMaxLanes ? int(order.size()) : kMaxLanes;
+    std::vector<double> lane_load(size_t(b->n_lanes), 0.0);
+    std::vector<int> lane_of_group(load.size(), 0);
+    for (int g : order) {
+        int best = 0;
+        for (int l = 1; l < b->n_lanes; ++l)
+            if (lane_load[size_t(l)] < lane_load[size_t(best)]) best = l;
+        lane_of_group[size_t(g)] = best;
+        lane_load[size_t(best)] += load[size_t(g)];
+    }
+    lane_of.assign(size_t(b->n), 0);
+    for (int i = 0; i < b->n; ++i) lane_of[size_t(i)] = lane_of_group[size_t(group[size_t(i)])];
+}
+
 // class membership: a cube whose schedule runs the fused pass (where built)
 // joins a column class and a fused class, the others the four classes of
 // the three-launch pass; tile schedules chosen earlier are kept
 void build_classes(muffin_batch* b) {
     std::vector<Class> old;
     old.swap(b->classes);
+    std::vector<int> lane;
+    assign_lanes(b, lane);
     for (int i = 0; i < b->n; ++i) {
         const muffin_shape& s = b->cubes[i]->shape;
+        const int l = lane[size_t(i)];
         if (fused_pass(b->cubes[i])) {
-            b->classes[class_of(b, K_COL, s.ny, 0)].cubes.push_back(i);
-            b->classes[class_of(b, K_FUSED, s.nx, s.L)].cubes.push_back(i);
+            b->classes[class_of(b, K_COL, s.ny, 0, l)].cubes.push_back(i);
+            b->classes[class_of(b, K_FUSED, s.nx, s.L, l)].cubes.push_back(i);
         } else {
-            b->classes[class_of(b, K_ROWF, s.nx, 0)].cubes.push_back(i);
-            b->classes[class_of(b, K_COL, s.ny, 0)].cubes.push_back(i);
-            b->classes[class_of(b, K_ROWI, s.nx, 0)].cubes.push_back(i);
-            b->classes[class_of(b, K_SPEC, s.L, spectral_block_pixels(s.L, long(s.ny) * s.nx, int(elem_size(s))))].cubes.push_back(i);
+            b->classes[class_of(b, K_ROWF, s.nx, 0, l)].cubes.push_back(i);
+            b->classes[class_of(b, K_COL, s.ny, 0, l)].cubes.push_back(i);
+            b->classes[class_of(b, K_ROWI, s.nx, 0, l)].cubes.push_back(i);
+            b->classes[class_of(b, K_SPEC, s.L, spectral_block_pixels(s.L, long(s.ny) * s.nx, int(elem_size(s))), l)]
+                .cubes.push_back(i);
         }
     }
     size_t slot = 0;
@@ -249,9 +304,26 @@ hipError_t launch_class(const muffin_batch* b, const Class& k, int variant, hipS
 }
 
 int pass_kernels(muffin_batch* b, hipStream_t s) {
+    if (b->n_lanes <= 1) {
+        for (int kind = 0; kind < K_NUM; ++kind)
+            for (const Class& k : b->classes)
+                if (k.kind == kind) HIP_TRY(launch_class(b, k, k.variant, s));
+        return MUFFIN_OK;
+    }
+    for (int l = 0; l < b->n_lanes; ++l) {
+        if (!b->lane_s[l]) HIP_TRY(hipStreamCreateWithFlags(&b->lane_s[l], hipStreamNonBlocking));
+        if (!b->lane_e[l]) HIP_TRY(hipEventCreateWithFlags(&b->lane_e[l], hipEventDisableTiming));
+    }
+    if (!b->fork_e) HIP_TRY(hipEventCreateWithFlags(&b->fork_e, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(b->fork_e, s));
+    for (int l = 0; l < b->n_lanes; ++l) HIP_TRY(hipStreamWaitEvent(b->lane_s[l], b->fork_e, 0));
     for (int kind = 0; kind < K_NUM; ++kind)
         for (const Class& k : b->classes)
-            if (k.kind == kind) HIP_TRY(launch_class(b, k, k.variant, s));
+            if (k.kind == kind) HIP_TRY(launch_class(b, k, k.variant, b->lane_s[k.lane]));
+    for (int l = 0; l < b->n_lanes; ++l) {
+        HIP_TRY(hipEventRecord(b->lane_e[l], b->lane_s[l]));
+        HIP_TRY(hipStreamWaitEvent(s, b->lane_e[l], 0));
+    }
     return MUFFIN_OK;
 }
 
@@ -432,6 +504,11 @@ int batch_destroy(muffin_ctx* c) {
     if (b) {
         drop_graph(b);
         if (b->cap) hipStreamDestroy(b->cap);
+        for (int l = 0; l < kMaxLanes; ++l) {
+            if (b->lane_s[l]) hipStreamDestroy(b->lane_s[l]);
+            if (b->lane_e[l]) hipEventDestroy(b->lane_e[l]);
+        }
+        if (b->fork_e) hipEventDestroy(b->fork_e);
         for (muffin_ctx* q : b->cubes) muffin_destroy(q);
         delete b;
     }
@@ -489,6 +566,12 @@ int muffin_setup_batch(muffin_ctx** out, int n, const muffin_shape* shapes, cons
     b->cap = nullptr;
     b->gexec = nullptr;
     b->passes = 0;
+    b->n_lanes = 0;
+    for (int l = 0; l < kMaxLanes; ++l) {
+        b->lane_s[l] = nullptr;
+        b->lane_e[l] = nullptr;
+    }
+    b->fork_e = nullptr;
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
         const size_t wi = muffin_workspace_bytes(&shapes[i], &params[i]);
