@@ -110,9 +110,11 @@ typedef struct {
     int n_s;          /* number of spatial bases W_s stacks, 1 <= n_s <= 9 */
     int spatial[9];   /* spatial[0] = MUFFIN_DIRAC; spatial[1 .. n_s-1] in
                          MUFFIN_DB1 .. MUFFIN_DB8.  With n_s > 1: the
-                         three-launch pass, no convergence reports
-                         (muffin_step_report, muffin_solve), no gradient and
-                         no batches (MUFFIN_EUNSUPPORTED) */
+                         three-launch pass, no gradient and no batches
+                         (MUFFIN_EUNSUPPORTED); a reporting pass runs each
+                         basis's analysis once more in report form and three
+                         syntheses for W_s^T dT and W_s^T Gamma_T (three more
+                         cubes of workspace) */
     int n_nu;         /* number of spectral bases W_nu stacks, 1 <= n_nu <= MUFFIN_MAX_SPECTRAL */
     int spectral[MUFFIN_MAX_SPECTRAL];  /* spectral[0 .. n_nu-1]: distinct codes above.
                          Anything but the DCT alone takes a dense L x L transform
@@ -188,8 +190,8 @@ int muffin_solve(muffin_ctx* ctx, int max_iter, muffin_report* report);
    multipliers held as in muffin_set_params (the filter of eq. Qlsimp follows
    the new rho).  mu > 1, tau > 1 (Boyd et al. use 10 and 2).  The rho's in
    force at the end are read back with muffin_get_params.
-   Returns as muffin_solve.  Errors: EINVAL, EUNSUPPORTED (wavelet
-   dictionary), EDEVICE, ENONFINITE. */
+   Returns as muffin_solve.  Errors: EINVAL, EUNSUPPORTED (visibility-domain
+   context), EDEVICE, ENONFINITE. */
 int muffin_solve_adaptive(muffin_ctx* ctx, int max_iter, double mu, double tau, muffin_report* report);
 
 /* The context's parameters (host copy).  Errors: EINVAL. */

@@ -111,6 +111,10 @@ int step_spectral_io(muffin_ctx* c, bool report, int* nblocks, void* const in[4]
     g.partials = (double*)P(c, c->lay.partials);
     g.dense = spectral_dense(s, c->params);
     g.n_nu = c->params.n_nu;
+    if (report && c->lay.n_w) {
+        g.wdt = P(c, c->lay.wrep[1]);
+        g.wg = P(c, c->lay.wrep[2]);
+    }
     if (g.n_nu > 1)
         for (int j = 0; j < g.n_nu; ++j) {
             g.uz[j] = uz(c, j);
@@ -303,17 +307,23 @@ int read_sums(muffin_ctx* c, int n, double* out) {
 }
 
 // one pass with the FP64 reductions of the spectral step, then the data term
-// of the objective at P = max(0, z_P) through a forward FFT pass
+// of the objective at P = max(0, z_P) through a forward FFT pass.  With
+// wavelet bases in W_s their steps III and VI run before steps II-VI (they
+// read X and z_b only) with their report terms, their B_rest terms after.
 int pass_with_report(muffin_ctx* c, muffin_report* rep) {
     const muffin_shape& s = c->shape;
+    const bool wav = c->lay.n_w > 0;
+    double* partials = (double*)P(c, c->lay.partials);
+    double* sums = (double*)P(c, c->lay.sums);
+    constexpr int WREP = 16;            // the wavelet sums: r^2, E, ||T||^2 parts, l1 of W_b P
     int rc = step_one(c);
     if (rc) return rc;
+    if (wav && (rc = dict_report_pre(c, sums + WREP))) return rc;
     int nb = 0;
     rc = step_spectral(c, true, &nb);
     if (rc) return rc;
+    if (wav && (rc = dict_brest(c))) return rc;
     c->iters++;
-    double* partials = (double*)P(c, c->lay.partials);
-    double* sums = (double*)P(c, c->lay.sums);
     HIP_TRY(launch_reduce_final(partials, nb, RED_NQ, sums, c->stream));
     const int nrows = s.L * s.ny;
     HIP_TRY(launch_row_fwd(s.dtype, s.dtype == MUFFIN_F64, st(c, ST_ZP), P(c, c->lay.z), nrows,
@@ -323,10 +333,11 @@ int pass_with_report(muffin_ctx* c, muffin_report* rep) {
                        P(c, c->lay.h2nyq), 0.0, 1.0, s.L, s.ny, s.nx, P(c, c->lay.tw), c->twlog,
                        partials, &nbc, c->stream));
     HIP_TRY(launch_reduce_final(partials, nbc, 1, sums + RED_NQ, c->stream));
-    double h[RED_NQ + 1];
-    rc = read_sums(c, RED_NQ + 1, h);
+    if (wav && (rc = dict_report_l1(c, st(c, ST_ZP), sums + WREP + 3))) return rc;
+    double h[WREP + 4] = {};
+    rc = read_sums(c, wav ? WREP + 4 : RED_NQ + 1, h);
     if (rc) return rc;
-    for (int i = 0; i <= RED_NQ; ++i) {
+    for (int i = 0; i < WREP + 4; ++i) {
         if (!std::isfinite(h[i])) {
             set_error("non-finite FP64 reduction (slot %d) at iteration %d", i, c->iters);
             return MUFFIN_ENONFINITE;
@@ -334,18 +345,20 @@ int pass_with_report(muffin_ctx* c, muffin_report* rep) {
     }
     const muffin_params& p = c->params;
     const double nv = double(voxels(s));
-    const double Ax = std::sqrt(3.0 * h[RED_X2] + h[RED_V2]);
-    const double Bz = std::sqrt(h[RED_BZ2]);
+    const double n_s = double(p.n_s);
+    // ||W_s X||^2 = n_s ||X||^2 (orthonormal bases)
+    const double Ax = std::sqrt((2.0 + n_s) * h[RED_X2] + h[RED_V2]);
+    const double Bz = std::sqrt(h[RED_BZ2] + h[WREP + 2]);
     const double Aty = std::sqrt(h[RED_ATY2]);
     rep->iters = c->iters;
-    rep->r_pri = std::sqrt(h[RED_R2]);
+    rep->r_pri = std::sqrt(h[RED_R2] + h[WREP]);
     rep->r_dual = std::sqrt(h[RED_S2]);
-    // constraint space (2 + n_s + m_nu) nv entries, block 1 (1 + m_nu) nv (n_s = 1 here)
-    rep->eps_pri = std::sqrt((3.0 + p.n_nu) * nv) * p.eps_abs + p.eps_rel * (Ax > Bz ? Ax : Bz);
+    // constraint space (2 + n_s + m_nu) nv entries, block 1 (1 + m_nu) nv
+    rep->eps_pri = std::sqrt((2.0 + n_s + p.n_nu) * nv) * p.eps_abs + p.eps_rel * (Ax > Bz ? Ax : Bz);
     rep->eps_dual = std::sqrt((1.0 + p.n_nu) * nv) * p.eps_abs + p.eps_rel * Aty;
-    rep->objective = 0.5 * (c->ynorm2 + h[RED_NQ]) + 0.5 * p.mu_eps * h[RED_P2] + p.mu_s * h[RED_P1]
-                     + p.mu_nu * h[RED_DCTP1];
-    rep->E = h[RED_E];
+    rep->objective = 0.5 * (c->ynorm2 + h[RED_NQ]) + 0.5 * p.mu_eps * h[RED_P2] +
+                     p.mu_s * (h[RED_P1] + h[WREP + 3]) + p.mu_nu * h[RED_DCTP1];
+    rep->E = h[RED_E] + h[WREP + 1];
     rep->converged = (rep->r_pri <= rep->eps_pri && rep->r_dual <= rep->eps_dual) ? 1 : 0;
     return MUFFIN_OK;
 }
@@ -757,16 +770,9 @@ int muffin_iterate(muffin_ctx* c, int n_iter) {
     return MUFFIN_OK;
 }
 
-static int no_wavelets(const muffin_ctx* c, const char* what) {
-    if (c->lay.n_w == 0) return MUFFIN_OK;
-    set_error("%s: not built for a spatial dictionary with wavelet bases (n_s = %d)", what, c->params.n_s);
-    return MUFFIN_EUNSUPPORTED;
-}
-
 int muffin_step_report(muffin_ctx* c, muffin_report* rep) {
     if (int rc = check_ctx(c)) return rc;
     if (int rc = vis_unsupported(c, "muffin_step_report")) return rc;
-    if (int rc = no_wavelets(c, "convergence reports")) return rc;
     if (!rep) { set_error("report is NULL"); return MUFFIN_EINVAL; }
     return pass_with_report(c, rep);
 }
@@ -774,7 +780,6 @@ int muffin_step_report(muffin_ctx* c, muffin_report* rep) {
 int muffin_solve(muffin_ctx* c, int max_iter, muffin_report* report) {
     if (int rc = check_ctx(c)) return rc;
     if (int rc = vis_unsupported(c, "muffin_solve")) return rc;
-    if (int rc = no_wavelets(c, "muffin_solve (convergence reports)")) return rc;
     if (max_iter < 1) { set_error("max_iter = %d < 1", max_iter); return MUFFIN_EINVAL; }
     muffin_report rep{};
     int done = 0;
@@ -795,7 +800,6 @@ int muffin_solve(muffin_ctx* c, int max_iter, muffin_report* report) {
 int muffin_solve_adaptive(muffin_ctx* c, int max_iter, double mu, double tau, muffin_report* report) {
     if (int rc = check_ctx(c)) return rc;
     if (int rc = vis_unsupported(c, "muffin_solve_adaptive")) return rc;
-    if (int rc = no_wavelets(c, "muffin_solve_adaptive (convergence reports)")) return rc;
     if (max_iter < 1) { set_error("max_iter = %d < 1", max_iter); return MUFFIN_EINVAL; }
     if (!std::isfinite(mu) || !std::isfinite(tau) || mu <= 1.0 || tau <= 1.0) {
         set_error("residual balancing needs finite mu > 1 and tau > 1 (mu = %g, tau = %g)", mu, tau);

@@ -102,6 +102,10 @@ int dict_setup(muffin_ctx* c);
 int dict_pass(muffin_ctx* c);
 int dict_brest(muffin_ctx* c);
 int dict_reencode(muffin_ctx* c, double ratio, double tau);
+// reporting pass with wavelet bases: sums[0..2] (r^2, E, ||T||^2 parts) and
+// the report kernel's cubes; after it, sum_b ||W_b max(0, z_P)||_1 into *sum1
+int dict_report_pre(muffin_ctx* c, double* sums);
+int dict_report_l1(muffin_ctx* c, const void* zP, double* sum1);
 
 // a cube context (not NULL, not a batch context)
 inline int check_ctx(const muffin_ctx* c) {

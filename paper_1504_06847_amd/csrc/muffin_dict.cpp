@@ -99,71 +99,174 @@ int dict_setup(muffin_ctx* c) {
     return MUFFIN_OK;
 }
 
-// steps III and VI of every wavelet basis from X (z_b updated) and their
-// terms of B_rest (added to it); with update = false only the B_rest terms
-// of the stored z_b.  Analysis: one launch per level for every basis;
-// synthesis: one launch per coarser level for every basis, then the finest
-// level basis by basis into B_rest (a fixed summation order).
-static int dict_run(muffin_ctx* c, bool update) {
-    const muffin_shape& s = c->shape;
-    const int J = c->lay.levels, nw = c->lay.n_w;
-    if (nw == 0) return MUFFIN_OK;
-    const size_t es = elem_size(s);
-    const long vb = long(s.ny) * s.nx;
-    // consecutive bases' cubes and scratch images lie at fixed strides
-    auto stride = [&](const size_t* off0, const size_t* off1) { return nw > 1 ? long((*off1 - *off0) / es) : 0L; };
-    const long zstride = stride(&c->lay.wz[0], &c->lay.wz[nw > 1 ? 1 : 0]);
+namespace {
+
+// consecutive bases' cubes and scratch images lie at fixed strides (elements)
+struct DictGeom {
+    long zstride = 0;
     long tstride[kMaxDwtLevels] = {};
-    for (int j = 1; j < J; ++j) tstride[j] = stride(&c->lay.wtmp[0][j], &c->lay.wtmp[nw > 1 ? 1 : 0][j]);
+};
+
+int dict_geom(muffin_ctx* c, DictGeom& G) {
+    const int J = c->lay.levels, nw = c->lay.n_w;
+    const size_t es = elem_size(c->shape);
+    auto stride = [&](size_t off0, size_t off1) { return nw > 1 ? long((off1 - off0) / es) : 0L; };
+    G.zstride = stride(c->lay.wz[0], c->lay.wz[nw > 1 ? 1 : 0]);
+    for (int j = 1; j < J; ++j) G.tstride[j] = stride(c->lay.wtmp[0][j], c->lay.wtmp[nw > 1 ? 1 : 0][j]);
     for (int b = 1; b < nw; ++b) {
-        bool ok = c->lay.wz[b] - c->lay.wz[0] == size_t(b) * size_t(zstride) * es;
-        for (int j = 1; j < J; ++j) ok = ok && c->lay.wtmp[b][j] - c->lay.wtmp[0][j] == size_t(b) * size_t(tstride[j]) * es;
+        bool ok = c->lay.wz[b] - c->lay.wz[0] == size_t(b) * size_t(G.zstride) * es;
+        for (int j = 1; j < J; ++j)
+            ok = ok && c->lay.wtmp[b][j] - c->lay.wtmp[0][j] == size_t(b) * size_t(G.tstride[j]) * es;
         if (!ok) {
             set_error("wavelet workspace regions are not evenly spaced");
             return MUFFIN_EDEVICE;
         }
     }
-    DwtLevel A{};
-    A.ftab = P(c, c->lay.wfilt);
-    for (int b = 0; b < nw; ++b) A.kpack |= unsigned(c->wK[b] / 2) << (4 * b);
-    A.n = nw;
-    A.L = s.L;
-    A.ld = s.nx;
-    A.z0 = P(c, c->lay.wz[0]);
-    A.zstride = zstride;
-    A.z_bs = vb;
-    A.tau = c->params.mu_s / c->params.rho_T;
-    if (update) {
-        for (int j = 0; j < J; ++j) {
-            A.sy = s.ny >> j;
-            A.sx = s.nx >> j;
-            A.in0 = j == 0 ? (const void*)P(c, c->lay.x) : (const void*)P(c, c->lay.wtmp[0][j]);
-            A.in_bstride = j == 0 ? 0 : tstride[j];
-            A.in_ld = j == 0 ? s.nx : A.sx;
-            A.in_bs = j == 0 ? vb : long(A.sy) * A.sx;
-            A.ll0 = j + 1 < J ? (void*)P(c, c->lay.wtmp[0][j + 1]) : nullptr;
-            A.llstride = j + 1 < J ? tstride[j + 1] : 0;
-            HIP_TRY(launch_dwt_fwd_all(s.dtype, A, c->stream));
-        }
-    }
-    for (int j = J - 1; j >= 1; --j) {
-        A.sy = s.ny >> j;
-        A.sx = s.nx >> j;
-        A.ll0 = j + 1 < J ? (void*)P(c, c->lay.wtmp[0][j + 1]) : nullptr;
-        A.llstride = j + 1 < J ? tstride[j + 1] : 0;
-        A.out0 = P(c, c->lay.wtmp[0][j]);
-        A.outstride = tstride[j];
-        HIP_TRY(launch_dwt_inv_all(s.dtype, A, c->stream));
-    }
-    for (int b = 0; b < nw; ++b)
-        HIP_TRY(launch_dwt_inv0(s.dtype, c->wK[b], c->wh[b], J > 1 ? (const void*)P(c, c->lay.wtmp[b][1]) : nullptr,
-                                P(c, c->lay.wz[b]), P(c, c->lay.brest), s.ny, s.nx, s.L, A.tau, c->params.rho_T,
-                                c->stream));
     return MUFFIN_OK;
 }
 
+// the launch descriptor of bases b0 .. b0 + n - 1 (coefficients in z_b)
+DwtLevel dict_level(muffin_ctx* c, const DictGeom& G, int b0, int n) {
+    const muffin_shape& s = c->shape;
+    DwtLevel A{};
+    A.ftab = P(c, c->lay.wfilt) + size_t(b0) * 32 * elem_size(s);
+    for (int b = 0; b < n; ++b) A.kpack |= unsigned(c->wK[b0 + b] / 2) << (4 * b);
+    A.n = n;
+    A.L = s.L;
+    A.ld = s.nx;
+    A.z0 = P(c, c->lay.wz[b0]);
+    A.zstride = G.zstride;
+    A.z_bs = long(s.ny) * s.nx;
+    A.tau = c->params.mu_s / c->params.rho_T;
+    A.rho_T = c->params.rho_T;
+    return A;
+}
+
+// Analysis of the image cube `in` ([L][ny][nx]) by bases b0 .. b0 + A.n - 1,
+// level by level (LL through the scratch images); in modes 1 and 2 the
+// work-group sums go to wpart from block *pos on (advanced).
+int dict_analysis(muffin_ctx* c, const DictGeom& G, DwtLevel A, int b0, const void* in, long* pos) {
+    const muffin_shape& s = c->shape;
+    const int J = c->lay.levels;
+    const int nq = A.mode == 1 ? 3 : 1;
+    for (int j = 0; j < J; ++j) {
+        A.sy = s.ny >> j;
+        A.sx = s.nx >> j;
+        A.in0 = j == 0 ? in : (const void*)P(c, c->lay.wtmp[b0][j]);
+        A.in_bstride = j == 0 ? 0 : G.tstride[j];
+        A.in_ld = j == 0 ? s.nx : A.sx;
+        A.in_bs = j == 0 ? long(s.ny) * s.nx : long(A.sy) * A.sx;
+        A.ll0 = j + 1 < J ? (void*)P(c, c->lay.wtmp[b0][j + 1]) : nullptr;
+        A.llstride = j + 1 < J ? G.tstride[j + 1] : 0;
+        if (A.mode != 0) {
+            const long nb = dwt_tiles(A.sy, A.sx) * s.L * A.n;
+            if (*pos + nb > c->lay.wblocks) {
+                set_error("wavelet report sums: %ld work-groups beyond %ld", *pos + nb, c->lay.wblocks);
+                return MUFFIN_EDEVICE;
+            }
+            A.partials = (double*)P(c, c->lay.wpart) + *pos * nq;
+            *pos += nb;
+        }
+        HIP_TRY(launch_dwt_fwd_all(s.dtype, A, c->stream));
+    }
+    return MUFFIN_OK;
+}
+
+// Synthesis by bases b0 .. b0 + A.n - 1 of their coefficient cubes (A.z0,
+// stride A.zstride, coefficient function A.mode), the finest level of each
+// basis added into out: out += scale * sum_b W_b^T f(z_b), bases in order.
+int dict_synthesis(muffin_ctx* c, const DictGeom& G, DwtLevel A, int b0, void* out, double scale) {
+    const muffin_shape& s = c->shape;
+    const int J = c->lay.levels;
+    const size_t es = elem_size(s);
+    for (int j = J - 1; j >= 1; --j) {
+        A.sy = s.ny >> j;
+        A.sx = s.nx >> j;
+        A.ll0 = j + 1 < J ? (void*)P(c, c->lay.wtmp[b0][j + 1]) : nullptr;
+        A.llstride = j + 1 < J ? G.tstride[j + 1] : 0;
+        A.out0 = P(c, c->lay.wtmp[b0][j]);
+        A.outstride = G.tstride[j];
+        HIP_TRY(launch_dwt_inv_all(s.dtype, A, c->stream));
+    }
+    for (int b = 0; b < A.n; ++b)
+        HIP_TRY(launch_dwt_inv0(s.dtype, c->wK[b0 + b], c->wh[b0 + b],
+                                J > 1 ? (const void*)P(c, c->lay.wtmp[b0 + b][1]) : nullptr,
+                                (const char*)A.z0 + size_t(b) * size_t(A.zstride) * es, out, s.ny, s.nx, s.L, A.tau,
+                                scale, c->stream, A.mode));
+    return MUFFIN_OK;
+}
+
+// steps III and VI of every wavelet basis from X (z_b updated) and their
+// terms of B_rest (added to it); with update = false only the B_rest terms
+// of the stored z_b.  Analysis: one launch per level for every basis;
+// synthesis: one launch per coarser level for every basis, then the finest
+// level basis by basis into B_rest (a fixed summation order).
+int dict_run(muffin_ctx* c, bool update) {
+    if (c->lay.n_w == 0) return MUFFIN_OK;
+    DictGeom G;
+    if (int rc = dict_geom(c, G)) return rc;
+    const DwtLevel A = dict_level(c, G, 0, c->lay.n_w);
+    if (update)
+        if (int rc = dict_analysis(c, G, A, 0, P(c, c->lay.x), nullptr)) return rc;
+    return dict_synthesis(c, G, A, 0, P(c, c->lay.brest), c->params.rho_T);
+}
+
+}  // namespace
+
 int dict_pass(muffin_ctx* c) { return dict_run(c, true); }
 int dict_brest(muffin_ctx* c) { return dict_run(c, false); }
+
+// A reporting pass, before steps II-VI: steps III and VI of every wavelet
+// basis (z_b updated exactly as dict_pass does) with the elementwise report
+// terms summed (FP64) into sums[WREP_SLOT ..] = r^2, E and ||T||^2 parts,
+// and the two cubes the report kernel needs:
+//   wrep[1] = rho_T sum_b W_b^T (T_b' - T_b),  wrep[2] = sum_b W_b^T Gamma_T,b'.
+// Basis by basis (the difference cube wrep[0] holds one basis at a time).
+int dict_report_pre(muffin_ctx* c, double* sums) {
+    const muffin_shape& s = c->shape;
+    DictGeom G;
+    if (int rc = dict_geom(c, G)) return rc;
+    const size_t cube = voxels(s) * elem_size(s);
+    void* D = P(c, c->lay.wrep[0]);
+    void* Wd = P(c, c->lay.wrep[1]);
+    void* Wg = P(c, c->lay.wrep[2]);
+    HIP_TRY(launch_fill_zero(Wd, cube, c->stream));
+    HIP_TRY(launch_fill_zero(Wg, cube, c->stream));
+    long pos = 0;
+    for (int b = 0; b < c->lay.n_w; ++b) {
+        DwtLevel A = dict_level(c, G, b, 1);
+        A.mode = 1;
+        A.d0 = D;
+        if (int rc = dict_analysis(c, G, A, b, P(c, c->lay.x), &pos)) return rc;
+        // rho_T W_b^T dT_b: the differences as they are (coefficient function 1)
+        DwtLevel B = dict_level(c, G, b, 1);
+        B.z0 = D;
+        B.zstride = 0;
+        B.mode = 1;
+        if (int rc = dict_synthesis(c, G, B, b, Wd, c->params.rho_T)) return rc;
+    }
+    HIP_TRY(launch_reduce_final((const double*)P(c, c->lay.wpart), int(pos), 3, sums, c->stream));
+    // W^T Gamma_T,b' = rho_T W_b^T (-clip(z_b')), every basis at once
+    DwtLevel A = dict_level(c, G, 0, c->lay.n_w);
+    A.mode = 2;
+    return dict_synthesis(c, G, A, 0, Wg, c->params.rho_T);
+}
+
+// sum_b ||W_b P||_1 for P = max(0, z_P) (the objective's wavelet terms):
+// P into the scratch cube wrep[1], its analysis by every basis, into *sum1.
+int dict_report_l1(muffin_ctx* c, const void* zP, double* sum1) {
+    const muffin_shape& s = c->shape;
+    DictGeom G;
+    if (int rc = dict_geom(c, G)) return rc;
+    void* Pc = P(c, c->lay.wrep[1]);
+    HIP_TRY(launch_positive(s.dtype, zP, Pc, voxels(s), c->stream));
+    DwtLevel A = dict_level(c, G, 0, c->lay.n_w);
+    A.mode = 2;
+    long pos = 0;
+    if (int rc = dict_analysis(c, G, A, 0, Pc, &pos)) return rc;
+    HIP_TRY(launch_reduce_final((const double*)P(c, c->lay.wpart), int(pos), 1, sum1, c->stream));
+    return MUFFIN_OK;
+}
 
 // keep T_b, Gamma_T,b of every wavelet basis under new parameters (as the
 // re-encoding of z_T): z_b <- soft(z_b, tau) + ratio clip(z_b, tau)

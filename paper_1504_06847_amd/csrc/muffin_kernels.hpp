@@ -255,6 +255,10 @@ struct SpecLaunch {
     int n_nu = 1;       // spectral bases; > 1: a union, with the coefficient cubes below
     void* uz[4] = {nullptr, nullptr, nullptr, nullptr};    // z_V,j read
     void* uzo[4] = {nullptr, nullptr, nullptr, nullptr};   // z_V,j written
+    // reporting pass with wavelet bases in W_s: rho_T W^T dT and W^T Gamma_T
+    // summed over them (cubes like X), else null
+    const void* wdt = nullptr;
+    const void* wg = nullptr;
 };
 
 // Spectral pass (steps II-VI of one iteration) over every pixel.
@@ -308,6 +312,17 @@ struct DwtLevel {
     void* out0;
     long outstride;
     double tau;
+    // analysis: 0 z_b <- c + clip(z_b, tau); 1 the same, with d_b = soft(z_b')
+    // - soft(z_b) written to d0 (z_b's layout, basis stride dstride) and per
+    // work-group the FP64 sums of (clip(z_b) - clip(z_b'))^2, rho_T ((clip(z_b)
+    // - clip(z_b'))^2 + d_b^2) and soft(z_b')^2 to partials; 2 z_b untouched,
+    // the sum of |c| per work-group to partials.  Synthesis: the coefficient
+    // function, 0 u = 2 soft(z, tau) - z, 1 z itself, 2 -clip(z, tau)
+    int mode = 0;
+    void* d0 = nullptr;
+    long dstride = 0;
+    double* partials = nullptr;
+    double rho_T = 0.0;
 };
 hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s);
 hipError_t launch_dwt_inv_all(int dtype, const DwtLevel& A, hipStream_t s);
@@ -315,7 +330,7 @@ hipError_t launch_dwt_inv_all(int dtype, const DwtLevel& A, hipStream_t s);
 // array): Brest += scale * the ny x nx images of u (LL from llin, dense
 // [L][ny/2][nx/2], or from z when null; z row stride nx).
 hipError_t launch_dwt_inv0(int dtype, int K, const double* h, const void* llin, const void* z, void* Brest, int ny,
-                           int nx, int L, double tau, double scale, hipStream_t s);
+                           int nx, int L, double tau, double scale, hipStream_t s, int cmode = 0);
 
 // Elementwise helpers.
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

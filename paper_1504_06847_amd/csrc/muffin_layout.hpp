@@ -14,6 +14,8 @@ enum StateIdx { ST_ZP = 0, ST_ZT = 1, ST_ZV = 2, ST_GS = 3 };
 
 constexpr int kMaxWavelets = 8;  // Db1..Db8 beside the Dirac basis
 constexpr int kMaxDwtLevels = 4;
+// coefficients per sub-band of one DWT work-group tile (rows, columns)
+constexpr int kDwtTileY = 16, kDwtTileX = 32;
 constexpr int kMaxSpectral = MUFFIN_MAX_SPECTRAL;
 
 struct Layout {
@@ -28,6 +30,11 @@ struct Layout {
     size_t wz[kMaxWavelets];
     size_t wtmp[kMaxWavelets][kMaxDwtLevels];
     size_t wfilt;
+    // a reporting pass with wavelet bases: three cubes (soft(z_b') -
+    // soft(z_b) of the basis in hand, rho_T W^T dT and W^T Gamma_T summed
+    // over the bases) and FP64 block sums of every analysis launch
+    size_t wrep[3], wpart;
+    long wblocks;
     int n_w, levels;
     // spectral bases: their number, and with more than one (a union) the
     // prox input of each basis's soft threshold, z_V,j = S W_j - Gamma_V,j /
@@ -54,6 +61,8 @@ int spectral_basis_ld(int code, int L, long double* W);
 // DWT depth of the wavelet bases: 4 levels, fewer when the smaller image side
 // would leave a coarsest band under 2 x 2
 int dwt_levels(int nx, int ny);
+// work-groups of one DWT level over an sy x sx image, per band and basis
+long dwt_tiles(int sy, int sx);
 int max_blocks_host(int L, int ny, int nx);
 
 // register width of the dense DCT used for band counts that are not powers of two

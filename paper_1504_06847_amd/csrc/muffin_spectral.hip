@@ -419,10 +419,14 @@ k_dct_l1_split(SpecArrays A, double* __restrict__ partials) {
 //   + ||Gamma_S||^2, ||P||^2, sum P
 // using Gamma_V = Gamma_S W_nu and the orthonormality of W_nu.  Each band's
 // terms are formed in the iteration's precision T and accumulated in FP64.
+// With wavelet bases in W_s (Wd, Wg not null), rho_T W_b^T dT_b and
+// W_b^T Gamma_T,b summed over them (Wd, Wg) join the Dirac basis's dT and
+// Gamma_T in s^2 and in the dual tolerance's norm; their elementwise terms
+// are summed by the analysis itself.
 template <typename T>
 __global__ void __launch_bounds__(SPEC_NTH)
 k_report(SpecArrays A, int L, long npix, SpecArgs a, const double* __restrict__ vpart,
-         double* __restrict__ partials) {
+         double* __restrict__ partials, char* Wd, char* Wg) {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
@@ -430,6 +434,8 @@ k_report(SpecArrays A, int L, long npix, SpecArgs a, const double* __restrict__ 
     const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, zV{A.zV, bb, gs_},
         GS{A.GS, bb, gs_}, zPo{A.zPo, bb, gs_}, zTo{A.zTo, bb, gs_}, zVo{A.zVo, bb, gs_},
         GSo{A.GSo, bb, gs_};
+    const BandArray<T> Wdt{Wd, bb, gs_}, Wgt{Wg, bb, gs_};
+    const bool wav = Wd != nullptr;
     const T rP = T(a.rho_P), rT = T(a.rho_T), rV = T(a.rho_V), rS = T(a.rho_S), tT = T(a.tau_T);
     const T irP = T(1.0 / a.rho_P), irT = T(1.0 / a.rho_T), irV2 = T(1.0 / (a.rho_V * a.rho_V));
     const T irV = T(1.0 / a.rho_V);
@@ -448,11 +454,13 @@ k_report(SpecArrays A, int L, long npix, SpecArgs a, const double* __restrict__ 
         const T dP = P - Po, dT = Tn - To, dS = sn - so, dg = gn - go;
         const T a1 = P - x, a2 = Tn - x, a3 = sn - x;
         r2 += double(a1 * a1 + a2 * a2 + a3 * a3 + dg * dg * irV2);
-        const T sx = rP * dP + rT * dT + rS * dS;
+        T sx = rP * dP + rT * dT + rS * dS;
+        if (wav) sx += Wdt.load(l, off);
         s2 += double(sx * sx + rV * rV * dS * dS);
         x2 += double(x * x);
         bz2 += double(P * P + Tn * Tn + T(2) * sn * sn);
-        const T g = gp + gt + gn;
+        T g = gp + gt + gn;
+        if (wav) g += Wgt.load(l, off);
         aty2 += double(g * g + gn * gn);
         const T dgp = gp - gpo, dgt = gt - gto;
         e += double(rP * dP * dP + rT * dT * dT + rSV * dS * dS + dgp * dgp * irP + dgt * dgt * irT
@@ -512,7 +520,8 @@ static hipError_t spectral_t(const SpecLaunch& g, const SpecArgs& a, hipStream_t
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_report<T>), grid, dim3(nth), 0, s, A, g.L, npix, a,
-                           (const double*)g.vpart, g.partials);
+                           (const double*)g.vpart, g.partials,
+                           (char*)g.wdt, (char*)g.wg);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         // the spectral l1 term reads the new z_P
@@ -549,7 +558,7 @@ static hipError_t spectral_split_t(const SpecLaunch& g, const SpecArgs& a, hipSt
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_report<T>), grid, dim3(64), 0, s, A, g.L, npix, a, (const double*)g.vpart,
-                           g.partials);
+                           g.partials, (char*)g.wdt, (char*)g.wg);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         SpecArrays B = A;
@@ -752,10 +761,11 @@ k_spectral_union(SpecArrays A, UnionZ Z, const T* __restrict__ D, int Lrt, int m
 //   ||Gamma_P + Gamma_T + Gamma_S'||^2 + sum_j ||Gamma_V,j'||^2 with
 //   Gamma_V,j' = rho_V (S' W_j - z_V,j'), ||P||^2, sum P, sum_j |P W_j|_1
 // (V_j = soft(z_V,j) of the old state; W_nu orthonormal per basis).
+// With wavelet bases in W_s, Wd and Wg as in k_report.
 template <typename T, int LT>
 __global__ void __launch_bounds__(SPEC_NTH)
 k_report_union(SpecArrays A, UnionZ Z, const T* __restrict__ D, int Lrt, int m, SpecArgs a,
-               double* __restrict__ partials) {
+               double* __restrict__ partials, char* Wd, char* Wg) {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned off = (unsigned)p * (unsigned)sizeof(T);
     const unsigned bb = A.band_bytes;
@@ -763,6 +773,8 @@ k_report_union(SpecArrays A, UnionZ Z, const T* __restrict__ D, int Lrt, int m, 
     const int L = Lrt;
     const BandArray<T> X{A.X, bb, gs_}, zP{A.zP, bb, gs_}, zT{A.zT, bb, gs_}, S{A.zV, bb, gs_}, GS{A.GS, bb, gs_},
         zPo{A.zPo, bb, gs_}, zTo{A.zTo, bb, gs_}, So{A.zVo, bb, gs_}, GSo{A.GSo, bb, gs_};
+    const BandArray<T> Wdt{Wd, bb, gs_}, Wgt{Wg, bb, gs_};
+    const bool wav = Wd != nullptr;
     const T rP = T(a.rho_P), rT = T(a.rho_T), rV = T(a.rho_V), rS = T(a.rho_S), tT = T(a.tau_T), tV = T(a.tau_V);
     const T irP = T(1.0 / a.rho_P), irT = T(1.0 / a.rho_T), irS = T(1.0 / a.rho_S);
     const T mT = T(m);
@@ -783,11 +795,13 @@ k_report_union(SpecArrays A, UnionZ Z, const T* __restrict__ D, int Lrt, int m, 
             const T dP = P - Po, dT = Tn - To, dS = sn - so, dg = gn - go;
             const T a1 = P - x, a2 = Tn - x, a3 = sn - x;
             r2 += double(a1 * a1 + a2 * a2 + a3 * a3);
-            const T sx = rP * dP + rT * dT + rS * dS;
+            T sx = rP * dP + rT * dT + rS * dS;
+            if (wav) sx += Wdt.load(l, off);
             s2 += double(sx * sx + mT * rV * rV * dS * dS);
             x2 += double(x * x);
             bz2 += double(P * P + Tn * Tn + (mT + T(1)) * sn * sn);
-            const T g = gp + gt + gn;
+            T g = gp + gt + gn;
+            if (wav) g += Wgt.load(l, off);
             aty2 += double(g * g);
             const T dgp = gp - gpo, dgt = gt - gto;
             e += double(rP * dP * dP + rT * dT * dT + (rS + mT * rV) * dS * dS + dgp * dgp * irP +
@@ -868,7 +882,7 @@ static hipError_t union_t(const SpecLaunch& g, const SpecArgs& a, hipStream_t s)
         if (e != hipSuccess) return e;
         // every partial sum of the convergence checks, the spectral terms included
         hipLaunchKernelGGL((k_report_union<T, LT>), grid, dim3(nth), 0, s, A, Z, (const T*)g.dctm, g.L, g.n_nu, a,
-                           g.partials);
+                           g.partials, (char*)g.wdt, (char*)g.wg);
     }
     return hipGetLastError();
 }

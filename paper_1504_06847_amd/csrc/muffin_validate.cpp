@@ -163,6 +163,12 @@ int dwt_levels(int nx, int ny) {
     return J < 1 ? 1 : J;
 }
 
+long dwt_tiles(int sy, int sx) {
+    const int hy = sy / 2, hx = sx / 2;
+    const int oty = hy < kDwtTileY ? hy : kDwtTileY, otx = hx < kDwtTileX ? hx : kDwtTileX;
+    return long(hy / oty) * (hx / otx);
+}
+
 Layout make_layout(const muffin_shape* s, int n_s, int n_nu) {
     Layout lay{};
     const size_t sz = s->dtype == MUFFIN_F64 ? 8 : 4;
@@ -186,6 +192,12 @@ Layout make_layout(const muffin_shape* s, int n_s, int n_nu) {
     for (int b = 0; b < lay.n_w; ++b)
         for (int j = 1; j < lay.levels; ++j)
             lay.wtmp[b][j] = take(size_t(s->L) * size_t(s->ny >> j) * size_t(s->nx >> j) * sz);
+    if (lay.n_w) {
+        for (int i = 0; i < 3; ++i) lay.wrep[i] = take(V * sz);
+        // the analysis launches of every basis and level, three sums per block
+        for (int j = 0; j < lay.levels; ++j) lay.wblocks += dwt_tiles(s->ny >> j, s->nx >> j) * s->L * lay.n_w;
+        lay.wpart = take(size_t(lay.wblocks) * 3 * 8);
+    }
     lay.z = take(HS * 2 * sz);
     lay.yf = take(HS * 2 * sz);
     lay.yfnyq = take(size_t(s->L) * s->ny * 2 * sz);

@@ -28,11 +28,12 @@
 //     one launch per basis, so the sum over the bases has a fixed order.
 #include "muffin_device.hpp"
 #include "muffin_kernels.hpp"
+#include "muffin_layout.hpp"
 
 namespace muffin {
 
-constexpr int DWT_OTY = 16;     // coefficient rows per sub-band per tile
-constexpr int DWT_OTX = 32;     // coefficient columns per sub-band per tile
+constexpr int DWT_OTY = kDwtTileY;     // coefficient rows per sub-band per tile
+constexpr int DWT_OTX = kDwtTileX;     // coefficient columns per sub-band per tile
 constexpr int DWT_NTH = 256;
 
 template <typename T> struct WFilt {
@@ -52,14 +53,42 @@ template <typename T> __device__ __forceinline__ T wsoft(T z, T t) {
 template <typename T> __device__ __forceinline__ void zupdate(T* p, T c, T tau) { *p = c + wclip(*p, tau); }
 // u = 2 soft(z, tau) - z
 template <typename T> __device__ __forceinline__ T ucoef(T z, T tau) { return T(2) * wsoft(z, tau) - z; }
+// the synthesis input of coefficient z: u (CF 0), z (CF 1), -clip(z) (CF 2)
+template <typename T, int CF> __device__ __forceinline__ T scoef(T z, T tau) {
+    if constexpr (CF == 0) return ucoef(z, tau);
+    else if constexpr (CF == 1) return z;
+    else return -wclip(z, tau);
+}
+
+// The report terms of one updated coefficient (old z, new zn): with
+// T_b = soft(z_b), Gamma_T,b = -rho_T clip(z_b) and W_b X = zn - clip(z),
+//   T_b' - W_b X = clip(z) - clip(zn),  dGamma_T,b = rho_T (clip(z) - clip(zn)),
+// so r^2 gains dc^2, E gains rho_T dT^2 + rho_T dc^2, ||T||^2 gains soft(zn)^2.
+struct WStats {
+    double r2 = 0.0, e = 0.0, bz = 0.0;
+};
+template <typename T>
+__device__ __forceinline__ T wstat(T z, T zn, T tau, T rT, WStats& st) {
+    const T dc = wclip(z, tau) - wclip(zn, tau);
+    const T tn = wsoft(zn, tau);
+    const T dt = tn - wsoft(z, tau);
+    st.r2 += double(dc * dc);
+    st.e += double(rT * (dt * dt + dc * dc));
+    st.bz += double(tn * tn);
+    return dt;
+}
 
 // One analysis tile of an sy x sx image (one band): src with row stride
 // in_ld; zb the band's coefficient block (row stride ld); llb the band's
 // dense LL image ([sy/2][sx/2]) or null (last level: LL into zb).
-template <typename T, int K>
+// MODE 0: update z_b; 1: update, soft(z_b') - soft(z_b) to db and the
+// report terms into st; 2: no z_b access, sum |c| (LL at the last level
+// included) into st.r2.
+template <typename T, int K, int MODE>
 __device__ __forceinline__ void dwt_fwd_tile(const T* __restrict__ src, int in_ld, T* __restrict__ zb, int ld,
                                              T* __restrict__ llb, int sy, int sx, const T (&h)[K],
-                                             const T (&g)[K], T tau, T* smem) {
+                                             const T (&g)[K], T tau, T* smem, T* __restrict__ db, T rT,
+                                             WStats& st) {
     constexpr int HMX = 2 * DWT_OTX + K - 2;
     constexpr int HMY = 2 * DWT_OTY + K - 2;
     T* tin = smem;
@@ -76,7 +105,7 @@ __device__ __forceinline__ void dwt_fwd_tile(const T* __restrict__ src, int in_l
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int e = threadIdx.x + j * DWT_NTH;
-        if (e < oty * otx) {
+        if (MODE != 2 && e < oty * otx) {
             const int i = e / otx, m = e - i * otx;
             const long gi = i0 + i, gm = m0 + m;
             zq[j][0] = zb[gi * ld + hx + gm];
@@ -120,11 +149,36 @@ __device__ __forceinline__ void dwt_fwd_tile(const T* __restrict__ src, int in_l
                 d += g[k] * vh;
             }
             const long gi = i0 + i, gm = m0 + m;
-            zb[gi * ld + hx + gm] = bx + wclip(zq[j][0], tau);               // x high, y low
-            zb[(hy + gi) * ld + gm] = by + wclip(zq[j][1], tau);             // x low, y high
-            zb[(hy + gi) * ld + hx + gm] = d + wclip(zq[j][2], tau);
+            if constexpr (MODE == 0) {
+                zb[gi * ld + hx + gm] = bx + wclip(zq[j][0], tau);               // x high, y low
+                zb[(hy + gi) * ld + gm] = by + wclip(zq[j][1], tau);             // x low, y high
+                zb[(hy + gi) * ld + hx + gm] = d + wclip(zq[j][2], tau);
+                if (llb) llb[gi * hx + gm] = a;
+                else zb[gi * ld + gm] = a + wclip(zq[j][3], tau);
+                continue;
+            }
             if (llb) llb[gi * hx + gm] = a;
-            else zb[gi * ld + gm] = a + wclip(zq[j][3], tau);
+            if constexpr (MODE == 2) {
+                st.r2 += double(fabs(bx)) + double(fabs(by)) + double(fabs(d));
+                if (!llb) st.r2 += double(fabs(a));
+                continue;
+            }
+            const long o0 = gi * ld + hx + gm, o1 = (hy + gi) * ld + gm, o2 = (hy + gi) * ld + hx + gm,
+                       o3 = gi * ld + gm;
+            const T n0 = bx + wclip(zq[j][0], tau);               // x high, y low
+            const T n1 = by + wclip(zq[j][1], tau);               // x low, y high
+            const T n2 = d + wclip(zq[j][2], tau);
+            const T n3 = a + wclip(zq[j][3], tau);
+            zb[o0] = n0;
+            zb[o1] = n1;
+            zb[o2] = n2;
+            if (!llb) zb[o3] = n3;
+            if constexpr (MODE == 1) {
+                db[o0] = wstat(zq[j][0], n0, tau, rT, st);
+                db[o1] = wstat(zq[j][1], n1, tau, rT, st);
+                db[o2] = wstat(zq[j][2], n2, tau, rT, st);
+                if (!llb) db[o3] = wstat(zq[j][3], n3, tau, rT, st);
+            }
         }
     }
 }
@@ -133,7 +187,7 @@ __device__ __forceinline__ void dwt_fwd_tile(const T* __restrict__ src, int in_l
 // band) from the four sub-bands of u = 2 soft(z, tau) - z (LL from llb, the
 // band's dense [sy/2][sx/2] image, or from zb when null); ob with row stride
 // out_ld: ob = x, or ob += scale x.
-template <typename T, int K>
+template <typename T, int K, int CF>
 __device__ __forceinline__ void dwt_inv_tile(const T* __restrict__ llb, const T* __restrict__ zb, int ld,
                                              T* __restrict__ ob, int out_ld, int sy, int sx, const T (&h)[K],
                                              const T (&g)[K], T tau, T scale, bool accumulate, T* smem) {
@@ -168,10 +222,10 @@ __device__ __forceinline__ void dwt_inv_tile(const T* __restrict__ llb, const T*
         const int n = e / CX, q = e - n * CX;
         // periodic coefficient indices i0 - H2 + n, m0 - H2 + q (hy, hx powers of two)
         const long gi = (i0 - H2 + n + 8 * hy) & (hy - 1), gm = (m0 - H2 + q + 8 * hx) & (hx - 1);
-        ca[n * CM + q] = llb ? llb[gi * hx + gm] : ucoef(zb[gi * ld + gm], tau);
-        cbx[n * CM + q] = ucoef(zb[gi * ld + hx + gm], tau);
-        cby[n * CM + q] = ucoef(zb[(hy + gi) * ld + gm], tau);
-        cd[n * CM + q] = ucoef(zb[(hy + gi) * ld + hx + gm], tau);
+        ca[n * CM + q] = llb ? llb[gi * hx + gm] : scoef<T, CF>(zb[gi * ld + gm], tau);
+        cbx[n * CM + q] = scoef<T, CF>(zb[gi * ld + hx + gm], tau);
+        cby[n * CM + q] = scoef<T, CF>(zb[(hy + gi) * ld + gm], tau);
+        cd[n * CM + q] = scoef<T, CF>(zb[(hy + gi) * ld + hx + gm], tau);
     }
     __syncthreads();
     // along y: output rows rr = 2 r2 + p of the tile (the parity p picks the
@@ -225,32 +279,48 @@ __device__ __forceinline__ void load_taps(const T* __restrict__ fb, T (&h)[K], T
 }
 
 // One analysis level of every basis and band: blockIdx.z = basis * L + band.
-template <typename T>
+// MODE 1 and 2 end with the work-group's FP64 sums in
+// A.partials[work-group * nq + q], nq = 3 (MODE 1) or 1 (MODE 2).
+template <typename T, int MODE>
 __global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd_all(DwtLevel A) {
     __shared__ T smem[DWT_FWD_LDS];
     const int b = blockIdx.z / A.L;
     const long band = blockIdx.z - b * A.L;
     const T* src = (const T*)A.in0 + b * A.in_bstride + band * A.in_bs;
-    T* zb = (T*)A.z0 + b * A.zstride + band * A.z_bs;
+    T* zb = MODE == 2 ? nullptr : (T*)A.z0 + b * A.zstride + band * A.z_bs;
+    T* db = MODE == 1 ? (T*)A.d0 + b * A.dstride + band * A.z_bs : nullptr;
     T* llb = A.ll0 ? (T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
     const T* fb = (const T*)A.ftab + 32 * b;
+    WStats st;
     switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
-#define F(KK)                                                                                  \
-    case KK: {                                                                                 \
-        T h[KK], g[KK];                                                                        \
-        load_taps<T, KK>(fb, h, g);                                                            \
-        dwt_fwd_tile<T, KK>(src, A.in_ld, zb, A.ld, llb, A.sy, A.sx, h, g, T(A.tau), smem);    \
-        break;                                                                                 \
+#define F(KK)                                                                                           \
+    case KK: {                                                                                          \
+        T h[KK], g[KK];                                                                                 \
+        load_taps<T, KK>(fb, h, g);                                                                     \
+        dwt_fwd_tile<T, KK, MODE>(src, A.in_ld, zb, A.ld, llb, A.sy, A.sx, h, g, T(A.tau), smem, db,    \
+                                  T(A.rho_T), st);                                                      \
+        break;                                                                                          \
     }
         MUFFIN_DWT_K_CASES(F)
 #undef F
         default: break;
     }
+    if constexpr (MODE != 0) {
+        __shared__ double sh[DWT_NTH / 64];
+        const long wg = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        constexpr int nq = MODE == 1 ? 3 : 1;
+        const double v[3] = {st.r2, st.e, st.bz};
+#pragma unroll
+        for (int q = 0; q < nq; ++q) {
+            const double sq = block_sum_s<DWT_NTH>(v[q], sh);
+            if (threadIdx.x == 0) A.partials[wg * nq + q] = sq;
+        }
+    }
 }
 
 // One synthesis level (not the finest) of every basis and band into the
 // bases' dense scratch images: blockIdx.z = basis * L + band.
-template <typename T>
+template <typename T, int CF>
 __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     __shared__ T smem[DWT_INV_LDS];
     const int b = blockIdx.z / A.L;
@@ -264,7 +334,7 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     case KK: {                                                                                         \
         T h[KK], g[KK];                                                                                \
         load_taps<T, KK>(fb, h, g);                                                                    \
-        dwt_inv_tile<T, KK>(llb, zb, A.ld, ob, A.sx, A.sy, A.sx, h, g, T(A.tau), T(1), false, smem);   \
+        dwt_inv_tile<T, KK, CF>(llb, zb, A.ld, ob, A.sx, A.sy, A.sx, h, g, T(A.tau), T(1), false, smem); \
         break;                                                                                         \
     }
         MUFFIN_DWT_K_CASES(F)
@@ -275,7 +345,7 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
 
 // The finest synthesis level of one basis, added into B_rest (row stride nx,
 // band stride ny nx): Brest += scale * x.
-template <typename T, int K>
+template <typename T, int K, int CF>
 __global__ void __launch_bounds__(DWT_NTH)
 k_dwt_inv0(const T* __restrict__ llin, const T* __restrict__ z, T* __restrict__ Brest, int ny, int nx,
            WFilt<T> f, T tau, T scale) {
@@ -289,8 +359,8 @@ k_dwt_inv0(const T* __restrict__ llin, const T* __restrict__ z, T* __restrict__ 
         g[k] = f.g[k];
     }
     const long vb = long(ny) * nx;
-    dwt_inv_tile<T, K>(llin ? llin + band * (vb / 4) : nullptr, z + band * vb, nx, Brest + band * vb, nx, ny, nx,
-                       h, g, tau, scale, true, smem);
+    dwt_inv_tile<T, K, CF>(llin ? llin + band * (vb / 4) : nullptr, z + band * vb, nx, Brest + band * vb, nx, ny,
+                           nx, h, g, tau, scale, true, smem);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -319,39 +389,65 @@ static bool level_ok(const DwtLevel& A) {
     return true;
 }
 
+template <typename T>
+static void fwd_all_t(const DwtLevel& A, dim3 grid, hipStream_t s) {
+    if (A.mode == 1) hipLaunchKernelGGL((k_dwt_fwd_all<T, 1>), grid, dim3(DWT_NTH), 0, s, A);
+    else if (A.mode == 2) hipLaunchKernelGGL((k_dwt_fwd_all<T, 2>), grid, dim3(DWT_NTH), 0, s, A);
+    else hipLaunchKernelGGL((k_dwt_fwd_all<T, 0>), grid, dim3(DWT_NTH), 0, s, A);
+}
+
 hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s) {
-    if (!level_ok(A)) return hipErrorInvalidValue;
+    if (!level_ok(A) || A.mode < 0 || A.mode > 2 || !A.in0) return hipErrorInvalidValue;
+    if ((A.mode != 2 && !A.z0) || (A.mode == 1 && !A.d0) || (A.mode != 0 && !A.partials))
+        return hipErrorInvalidValue;
     const dim3 grid = dwt_grid(A.sy, A.sx, A.n * A.L);
-    if (dtype == 0) hipLaunchKernelGGL(k_dwt_fwd_all<float>, grid, dim3(DWT_NTH), 0, s, A);
-    else hipLaunchKernelGGL(k_dwt_fwd_all<double>, grid, dim3(DWT_NTH), 0, s, A);
+    if (dtype == 0) fwd_all_t<float>(A, grid, s);
+    else fwd_all_t<double>(A, grid, s);
     return hipGetLastError();
 }
 
+template <typename T>
+static void inv_all_t(const DwtLevel& A, dim3 grid, hipStream_t s) {
+    if (A.mode == 1) hipLaunchKernelGGL((k_dwt_inv_all<T, 1>), grid, dim3(DWT_NTH), 0, s, A);
+    else if (A.mode == 2) hipLaunchKernelGGL((k_dwt_inv_all<T, 2>), grid, dim3(DWT_NTH), 0, s, A);
+    else hipLaunchKernelGGL((k_dwt_inv_all<T, 0>), grid, dim3(DWT_NTH), 0, s, A);
+}
+
 hipError_t launch_dwt_inv_all(int dtype, const DwtLevel& A, hipStream_t s) {
-    if (!level_ok(A) || !A.out0) return hipErrorInvalidValue;
+    if (!level_ok(A) || !A.out0 || !A.z0 || A.mode < 0 || A.mode > 2) return hipErrorInvalidValue;
     const dim3 grid = dwt_grid(A.sy, A.sx, A.n * A.L);
-    if (dtype == 0) hipLaunchKernelGGL(k_dwt_inv_all<float>, grid, dim3(DWT_NTH), 0, s, A);
-    else hipLaunchKernelGGL(k_dwt_inv_all<double>, grid, dim3(DWT_NTH), 0, s, A);
+    if (dtype == 0) inv_all_t<float>(A, grid, s);
+    else inv_all_t<double>(A, grid, s);
     return hipGetLastError();
 }
 
 template <typename T, int K>
 static hipError_t inv0_t(const double* h, const void* llin, const void* z, void* Brest, int ny, int nx, int L,
-                         double tau, double scale, hipStream_t s) {
-    hipLaunchKernelGGL((k_dwt_inv0<T, K>), dwt_grid(ny, nx, L), dim3(DWT_NTH), 0, s, (const T*)llin, (const T*)z,
-                       (T*)Brest, ny, nx, make_filt<T>(h, K), T(tau), T(scale));
+                         double tau, double scale, hipStream_t s, int cmode) {
+    const dim3 grid = dwt_grid(ny, nx, L);
+    const WFilt<T> f = make_filt<T>(h, K);
+    if (cmode == 1)
+        hipLaunchKernelGGL((k_dwt_inv0<T, K, 1>), grid, dim3(DWT_NTH), 0, s, (const T*)llin, (const T*)z, (T*)Brest,
+                           ny, nx, f, T(tau), T(scale));
+    else if (cmode == 2)
+        hipLaunchKernelGGL((k_dwt_inv0<T, K, 2>), grid, dim3(DWT_NTH), 0, s, (const T*)llin, (const T*)z, (T*)Brest,
+                           ny, nx, f, T(tau), T(scale));
+    else
+        hipLaunchKernelGGL((k_dwt_inv0<T, K, 0>), grid, dim3(DWT_NTH), 0, s, (const T*)llin, (const T*)z, (T*)Brest,
+                           ny, nx, f, T(tau), T(scale));
     return hipGetLastError();
 }
 
 hipError_t launch_dwt_inv0(int dtype, int K, const double* h, const void* llin, const void* z, void* Brest, int ny,
-                           int nx, int L, double tau, double scale, hipStream_t s) {
-    if (K < 2 || K > 16 || (K & 1) || ny < 4 || nx < 4 || L < 1 || (ny & (ny - 1)) || (nx & (nx - 1)))
+                           int nx, int L, double tau, double scale, hipStream_t s, int cmode) {
+    if (K < 2 || K > 16 || (K & 1) || ny < 4 || nx < 4 || L < 1 || (ny & (ny - 1)) || (nx & (nx - 1)) || !z ||
+        !Brest || cmode < 0 || cmode > 2)
         return hipErrorInvalidValue;
     switch (K) {
 #define F(KK)                                                                                          \
     case KK:                                                                                           \
-        return dtype == 0 ? inv0_t<float, KK>(h, llin, z, Brest, ny, nx, L, tau, scale, s)             \
-                          : inv0_t<double, KK>(h, llin, z, Brest, ny, nx, L, tau, scale, s);
+        return dtype == 0 ? inv0_t<float, KK>(h, llin, z, Brest, ny, nx, L, tau, scale, s, cmode)      \
+                          : inv0_t<double, KK>(h, llin, z, Brest, ny, nx, L, tau, scale, s, cmode);
         MUFFIN_DWT_K_CASES(F)
 #undef F
     }

@@ -128,16 +128,103 @@ def test_dictionary_graph_state_and_params(gpu_lib):
     assert err <= 1e-10
 
 
-def test_dictionary_rejects_reports_gradient_and_new_bases(gpu_lib):
+def test_dictionary_rejects_gradient_and_new_bases(gpu_lib):
     from paper_1504_06847_amd import Solver
     from paper_1504_06847_amd.lib import MuffinError
     inst = make_instance(16, 16, 2, n_points=3, n_gauss=1, n_ant=10, noise_sigma=0.01, seed=2)
     s = Solver(inst.psf, inst.dirty, spatial=PAPER)
     s.iterate(2)
-    for call in (lambda: s.step_report(), lambda: s.solve(5), lambda: s.grad(2, sky=inst.dirty)):
-        with pytest.raises(MuffinError) as ei:
-            call()
-        assert ei.value.code == -2
+    with pytest.raises(MuffinError) as ei:
+        s.grad(2, sky=inst.dirty)
+    assert ei.value.code == -2
     with pytest.raises(MuffinError):
         s.set_params(spatial=(0, 1))
     s.iterate(1)           # the context still works
+
+
+REPORT_CASES = [
+    # (L, ny, nx, bases, dtype): the paper's dictionary; a subset on a
+    # non-square image; images smaller than the longest filter
+    (8, 64, 64, PAPER, "f64"),
+    (4, 32, 64, (0, 1, 2, 8), "f64"),
+    (2, 8, 8, PAPER, "f64"),
+    (8, 64, 64, PAPER, "f32"),
+]
+
+
+@pytest.mark.parametrize("L,ny,nx,bases,dtype", REPORT_CASES)
+def test_dictionary_report_matches_oracle(gpu_lib, L, ny, nx, bases, dtype):
+    """The residuals (with ||T - W_s X||, W_s^T dT and W_s^T Gamma_T over
+    every basis), E^k and the objective (mu_s sum_b ||W_b P||_1) of one
+    reporting pass against the oracle; then the run goes on from the state
+    the reporting pass left as the oracle's does.  Bars: FP64 1e-9 (the
+    Dirac report's), FP32 against the float64 oracle 1e-3 on the residuals
+    and E (differences of nearby iterates), 1e-5 on the tolerances and the
+    objective."""
+    from paper_1504_06847_amd import Solver
+    cfg = get_config("plain64")
+    inst = make_instance(ny, nx, L, n_points=5, n_gauss=2, n_ant=20, noise_sigma=0.01, seed=31 + L)
+    p = cfg.params
+    f64 = dtype == "f64"
+    _say("dictionary report", L, ny, nx, bases, dtype)
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float64 if f64 else torch.float32, spatial=bases, **_kw(p))
+    prob = O.Problem(inst.psf, inst.dirty, p, bases=bases, dtype=np.longdouble if f64 else np.float64)
+    s.iterate(5)
+    prev = O.run(prob, 5)
+    rep = s.step_report()
+    cur = O.admm_iteration(prob, prev)
+    res = O.residuals(prob, prev, cur, eps_abs=1e-5, eps_rel=1e-4)
+    E = O.energy(prob, prev, cur)
+    F = O.objective(prob, cur.P)
+    _say("  gpu", {k: rep[k] for k in ("r_pri", "r_dual", "eps_pri", "eps_dual", "E", "objective")})
+    _say("  oracle", res, "E", E, "F", F)
+    b1, b2 = (1e-9, 1e-9) if f64 else (1e-3, 1e-5)
+    assert rep["iters"] == 6
+    assert rep["r_pri"] == pytest.approx(res["r"], rel=b1)
+    assert rep["r_dual"] == pytest.approx(res["s"], rel=b1)
+    assert rep["E"] == pytest.approx(E, rel=b1)
+    assert rep["eps_pri"] == pytest.approx(res["eps_pri"], rel=b2)
+    assert rep["eps_dual"] == pytest.approx(res["eps_dual"], rel=b2)
+    assert rep["objective"] == pytest.approx(F, rel=b2)
+    s.iterate(3)
+    st = O.run(prob, 3, state=cur)
+    err = rel(s.x.cpu().double().numpy(), st.X.astype(np.float64))
+    _say("  X after 3 more", err)
+    assert err <= (1e-12 if f64 else 1e-4)
+
+
+def test_dictionary_adaptive_solve_matches_oracle(gpu_lib):
+    """muffin_solve_adaptive with wavelet bases: the same rho decisions at
+    the same checks, the same stopping iteration and the same X as the
+    oracle's solve_adaptive (FP64, 1e-12)."""
+    from paper_1504_06847_amd import Solver
+    inst = make_instance(32, 32, 4, n_points=4, n_gauss=1, n_ant=14, noise_sigma=0.01, seed=13)
+    bases = (0, 1, 4)
+    p = O.Params(1e-3, 0.02, 0.02, 0.05, 0.05, 0.05, 0.05)
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float64, spatial=bases, mu_eps=p.mu_eps, mu_s=p.mu_s,
+               mu_nu=p.mu_nu, rho=0.05, check_every=10, eps_abs=1e-6, eps_rel=1e-5)
+    rep = s.solve(150, adaptive=(10.0, 2.0))
+    prob = O.Problem(inst.psf, inst.dirty, p, bases=bases, dtype=np.longdouble)
+    st, pr, hist = O.solve_adaptive(prob, 150, 10, 10.0, 2.0, eps_abs=1e-6, eps_rel=1e-5)
+    _say("gpu rho", s.params["rho_P"], "iters", rep["iters"], "oracle rho", pr.p.rho_P, "iters", hist[-1][0],
+         "history", [(k, r) for k, r, _, _ in hist])
+    assert s.params["rho_P"] == pr.p.rho_P
+    assert pr.p.rho_P != 0.05                       # the rule fired
+    assert rep["iters"] == hist[-1][0]
+    err = rel(s.x.cpu().numpy(), st.X.astype(np.float64))
+    _say("  X rel err", err)
+    assert err <= 1e-12
+
+
+def test_dictionary_solve_stops_on_residuals(gpu_lib):
+    """muffin_solve with the paper's dictionary stops at a check whose
+    residuals are under their tolerances."""
+    from paper_1504_06847_amd import Solver
+    inst = make_instance(16, 16, 4, n_points=3, n_gauss=1, n_ant=12, noise_sigma=0.01, seed=9)
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float64, spatial=PAPER, rho=1.0, mu_s=0.05, mu_nu=0.05,
+               check_every=5, eps_abs=1e-6, eps_rel=1e-5)
+    rep = s.solve(5000)
+    _say("dictionary solve", rep)
+    assert rep["status"] == 0 and rep["converged"] == 1
+    assert rep["r_pri"] <= rep["eps_pri"] and rep["r_dual"] <= rep["eps_dual"]
+    assert rep["iters"] % 5 == 0
