@@ -159,7 +159,8 @@ int dict_analysis(muffin_ctx* c, const DictGeom& G, DwtLevel A, int b0, const vo
         A.ll0 = j + 1 < J ? (void*)P(c, c->lay.wtmp[b0][j + 1]) : nullptr;
         A.llstride = j + 1 < J ? G.tstride[j + 1] : 0;
         if (A.mode != 0) {
-            const long nb = dwt_tiles(A.sy, A.sx) * s.L * A.n;
+            // the finest level runs every basis in one work-group per tile and band
+            const long nb = dwt_tiles(A.sy, A.sx) * s.L * (j == 0 ? 1 : A.n);
             if (*pos + nb > c->lay.wblocks) {
                 set_error("wavelet report sums: %ld work-groups beyond %ld", *pos + nb, c->lay.wblocks);
                 return MUFFIN_EDEVICE;
@@ -167,18 +168,17 @@ int dict_analysis(muffin_ctx* c, const DictGeom& G, DwtLevel A, int b0, const vo
             A.partials = (double*)P(c, c->lay.wpart) + *pos * nq;
             *pos += nb;
         }
-        HIP_TRY(launch_dwt_fwd_all(s.dtype, A, c->stream));
+        HIP_TRY(launch_dwt_fwd_all(s.dtype, A, c->stream, j == 0));
     }
     return MUFFIN_OK;
 }
 
 // Synthesis by bases b0 .. b0 + A.n - 1 of their coefficient cubes (A.z0,
-// stride A.zstride, coefficient function A.mode), the finest level of each
-// basis added into out: out += scale * sum_b W_b^T f(z_b), bases in order.
+// stride A.zstride, coefficient function A.mode): out += scale * sum_b
+// W_b^T f(z_b), the finest level of every basis summed in one launch.
 int dict_synthesis(muffin_ctx* c, const DictGeom& G, DwtLevel A, int b0, void* out, double scale) {
     const muffin_shape& s = c->shape;
     const int J = c->lay.levels;
-    const size_t es = elem_size(s);
     for (int j = J - 1; j >= 1; --j) {
         A.sy = s.ny >> j;
         A.sx = s.nx >> j;
@@ -188,11 +188,13 @@ int dict_synthesis(muffin_ctx* c, const DictGeom& G, DwtLevel A, int b0, void* o
         A.outstride = G.tstride[j];
         HIP_TRY(launch_dwt_inv_all(s.dtype, A, c->stream));
     }
-    for (int b = 0; b < A.n; ++b)
-        HIP_TRY(launch_dwt_inv0(s.dtype, c->wK[b0 + b], c->wh[b0 + b],
-                                J > 1 ? (const void*)P(c, c->lay.wtmp[b0 + b][1]) : nullptr,
-                                (const char*)A.z0 + size_t(b) * size_t(A.zstride) * es, out, s.ny, s.nx, s.L, A.tau,
-                                scale, c->stream, A.mode));
+    A.sy = s.ny;
+    A.sx = s.nx;
+    A.ll0 = J > 1 ? (void*)P(c, c->lay.wtmp[b0][1]) : nullptr;
+    A.llstride = J > 1 ? G.tstride[1] : 0;
+    A.out0 = out;
+    A.scale = scale;
+    HIP_TRY(launch_dwt_inv0_all(s.dtype, A, c->stream));
     return MUFFIN_OK;
 }
 
@@ -200,7 +202,7 @@ int dict_synthesis(muffin_ctx* c, const DictGeom& G, DwtLevel A, int b0, void* o
 // terms of B_rest (added to it); with update = false only the B_rest terms
 // of the stored z_b.  Analysis: one launch per level for every basis;
 // synthesis: one launch per coarser level for every basis, then the finest
-// level basis by basis into B_rest (a fixed summation order).
+// level of every basis summed into B_rest (a fixed summation order).
 int dict_run(muffin_ctx* c, bool update) {
     if (c->lay.n_w == 0) return MUFFIN_OK;
     DictGeom G;

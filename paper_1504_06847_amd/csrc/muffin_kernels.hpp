@@ -323,14 +323,16 @@ struct DwtLevel {
     long dstride = 0;
     double* partials = nullptr;
     double rho_T = 0.0;
+    double scale = 1.0;      // the finest synthesis: out0 += scale * (sum over the bases)
 };
-hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s);
+// finest: one work-group per tile and band runs every basis over one staged
+// image tile (grid z = L, one input image per band); else grid z = n L
+hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s, bool finest = false);
 hipError_t launch_dwt_inv_all(int dtype, const DwtLevel& A, hipStream_t s);
-// The finest synthesis level of one basis (filter h, length K, FP64 host
-// array): Brest += scale * the ny x nx images of u (LL from llin, dense
-// [L][ny/2][nx/2], or from z when null; z row stride nx).
-hipError_t launch_dwt_inv0(int dtype, int K, const double* h, const void* llin, const void* z, void* Brest, int ny,
-                           int nx, int L, double tau, double scale, hipStream_t s, int cmode = 0);
+// The finest synthesis level (sy x sx = ny x nx) of every basis, summed:
+// out0 += scale * sum_b W_b^T f(z_b) at that level (LL from ll0, dense
+// [L][ny/2][nx/2] per basis, or from z_b when null).
+hipError_t launch_dwt_inv0_all(int dtype, const DwtLevel& A, hipStream_t s);
 
 // Elementwise helpers.
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

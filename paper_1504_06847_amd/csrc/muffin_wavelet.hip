@@ -24,8 +24,9 @@
 //   k_dwt_inv_all: one synthesis level above the finest of every basis, of
 //     u_b = 2 soft(z_b) - z_b (the LL input from the coarser level's scratch
 //     image, or from z_b at the last level).
-//   k_dwt_inv0: the finest synthesis level of one basis, added into B_rest;
-//     one launch per basis, so the sum over the bases has a fixed order.
+//   k_dwt_inv0_all: the finest synthesis level of every basis, the bases
+//     in order inside each work-group and their sum added into B_rest, so
+//     B_rest is read and written once and the sum has a fixed order.
 #include "muffin_device.hpp"
 #include "muffin_kernels.hpp"
 #include "muffin_layout.hpp"
@@ -36,9 +37,6 @@ constexpr int DWT_OTY = kDwtTileY;     // coefficient rows per sub-band per tile
 constexpr int DWT_OTX = kDwtTileX;     // coefficient columns per sub-band per tile
 constexpr int DWT_NTH = 256;
 
-template <typename T> struct WFilt {
-    T h[16], g[16];
-};
 #define MUFFIN_DWT_K_CASES(F) F(2) F(4) F(6) F(8) F(10) F(12) F(14) F(16)
 
 // LDS of one tile, in elements, for the longest filter (K = 16)
@@ -81,118 +79,197 @@ __device__ __forceinline__ T wstat(T z, T zn, T tau, T rT, WStats& st) {
 // One analysis tile of an sy x sx image (one band): src with row stride
 // in_ld; zb the band's coefficient block (row stride ld); llb the band's
 // dense LL image ([sy/2][sx/2]) or null (last level: LL into zb).
+// One analysis tile: oty x otx coefficients of each sub-band of an sy x sx
+// image (one band) from the image rows and columns it needs (periodic
+// halo of K - 2), staged in LDS.  Register blocking: a thread of the row
+// pass forms DWT_MB adjacent outputs of one row from 2 DWT_MB + K - 2 LDS
+// values, a thread of the column pass DWT_IB adjacent coefficient rows of
+// one column (all four sub-bands) from 2 DWT_IB + K - 2 values of each row
+// image, so each staged value is read a few times instead of K.  Each
+// output's taps are summed in k order.
 // MODE 0: update z_b; 1: update, soft(z_b') - soft(z_b) to db and the
 // report terms into st; 2: no z_b access, sum |c| (LL at the last level
 // included) into st.r2.
-template <typename T, int K, int MODE>
-__device__ __forceinline__ void dwt_fwd_tile(const T* __restrict__ src, int in_ld, T* __restrict__ zb, int ld,
-                                             T* __restrict__ llb, int sy, int sx, const T (&h)[K],
-                                             const T (&g)[K], T tau, T* smem, T* __restrict__ db, T rT,
-                                             WStats& st) {
-    constexpr int HMX = 2 * DWT_OTX + K - 2;
-    constexpr int HMY = 2 * DWT_OTY + K - 2;
-    T* tin = smem;
-    T* rl = smem + HMY * HMX;
-    T* rh = rl + HMY * DWT_OTX;
+constexpr int DWT_MB = 4;
+constexpr int DWT_IB = 2;
+// LDS of an analysis tile: the staged image (row stride for the longest
+// filter, whatever the basis), then the row pass's low and high halves
+constexpr int DWT_HMX = 2 * DWT_OTX + 14, DWT_HMY = 2 * DWT_OTY + 14;
+
+// this thread's column-pass item: coefficient rows ci .. ci + DWT_IB - 1 of
+// column cm (oty >= 2, so (oty / DWT_IB) otx <= 256 items)
+struct FwdItem {
+    bool on;
+    int ci, cm;
+};
+__device__ __forceinline__ FwdItem fwd_item(int oty, int otx) {
+    return {(int)threadIdx.x < (oty / DWT_IB) * otx, (int)(threadIdx.x / otx) * DWT_IB, (int)(threadIdx.x % otx)};
+}
+
+// The coefficients the item updates (zq[r][sub-band]; the LL one only at
+// the last level), loaded ahead of the tile so that their latency overlaps it.
+template <typename T, int MODE>
+__device__ __forceinline__ void fwd_load_z(const T* __restrict__ zb, int ld, bool last, int sy, int sx,
+                                           const FwdItem& it, T (&zq)[DWT_IB][4]) {
+    if (MODE == 2 || !it.on) return;
+    const int hy = sy >> 1, hx = sx >> 1;
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
+    const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
+#pragma unroll
+    for (int r = 0; r < DWT_IB; ++r) {
+        const long gi = i0 + it.ci + r, gm = m0 + it.cm;
+        zq[r][0] = zb[gi * ld + hx + gm];
+        zq[r][1] = zb[(hy + gi) * ld + gm];
+        zq[r][2] = zb[(hy + gi) * ld + hx + gm];
+        zq[r][3] = last ? zb[gi * ld + gm] : T(0);
+    }
+}
+
+// Stage the image rows and columns an analysis tile with filters of up to
+// K taps needs (periodic halo of K - 2 below and right) into tin.
+template <typename T>
+__device__ __forceinline__ void fwd_stage(const T* __restrict__ src, int in_ld, int sy, int sx, int K, T* tin) {
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
     const int HY = 2 * oty + K - 2, HX = 2 * otx + K - 2;
-    // the coefficients this thread updates, loaded first so that their
-    // latency overlaps the tile load and the row pass
-    constexpr int IPT = (DWT_OTY * DWT_OTX + DWT_NTH - 1) / DWT_NTH;
-    T zq[IPT][4];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const int e = threadIdx.x + j * DWT_NTH;
-        if (MODE != 2 && e < oty * otx) {
-            const int i = e / otx, m = e - i * otx;
-            const long gi = i0 + i, gm = m0 + m;
-            zq[j][0] = zb[gi * ld + hx + gm];
-            zq[j][1] = zb[(hy + gi) * ld + gm];
-            zq[j][2] = zb[(hy + gi) * ld + hx + gm];
-            zq[j][3] = llb ? T(0) : zb[gi * ld + gm];
-        }
-    }
     for (int e = threadIdx.x; e < HY * HX; e += DWT_NTH) {
         const int r = e / HX, c = e - r * HX;
-        tin[r * HMX + c] = src[(long)((2 * i0 + r) & (sy - 1)) * in_ld + ((2 * m0 + c) & (sx - 1))];
+        tin[r * DWT_HMX + c] = src[(long)((2 * i0 + r) & (sy - 1)) * in_ld + ((2 * m0 + c) & (sx - 1))];
     }
-    __syncthreads();
-    // along x
-    for (int e = threadIdx.x; e < HY * otx; e += DWT_NTH) {
-        const int r = e / otx, m = e - r * otx;
-        T lo = T(0), hi = T(0);
+}
+
+// One analysis tile of one basis (filter length K) from the staged image:
+// oty x otx coefficients of each sub-band of an sy x sx image.  Register
+// blocking: a thread of the row pass forms DWT_MB adjacent outputs of one
+// row from 2 DWT_MB + K - 2 LDS values, a thread of the column pass DWT_IB
+// adjacent coefficient rows of one column (all four sub-bands) from
+// 2 DWT_IB + K - 2 values of each row image, so each staged value is read a
+// few times instead of K.  Each output's taps are summed in k order.
+// MODE 0: update z_b; 1: update, soft(z_b') - soft(z_b) to db and the
+// report terms into st; 2: no z_b access, sum |c| (LL at the last level
+// included) into st.r2.  Starts and ends between barriers: the caller
+// synchronises after the staging and before the next tile's row pass.
+template <typename T, int K, int MODE>
+__device__ __forceinline__ void dwt_fwd_tile(T* __restrict__ zb, int ld, T* __restrict__ llb, int sy, int sx,
+                                             const T (&h)[K], const T (&g)[K], T tau, T* smem,
+                                             T* __restrict__ db, T rT, WStats& st, const FwdItem& it,
+                                             const T (&zq)[DWT_IB][4]) {
+    constexpr int NV = 2 * DWT_MB + K - 2, NR = 2 * DWT_IB + K - 2;
+    const T* tin = smem;
+    T* rl = smem + DWT_HMY * DWT_HMX;
+    T* rh = rl + DWT_HMY * DWT_OTX;
+    const int hy = sy >> 1, hx = sx >> 1;
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
+    const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
+    const int HY = 2 * oty + K - 2;
+    // along x: row r, outputs mb .. mb + DWT_MB - 1 (a tile narrower than
+    // DWT_MB reads past its columns inside the LDS array and keeps only its own)
+    const int nmb = otx >= DWT_MB ? otx / DWT_MB : 1;
+    for (int e = threadIdx.x; e < HY * nmb; e += DWT_NTH) {
+        const int r = e / nmb, mb = (e - r * nmb) * DWT_MB;
+        const T* row = tin + r * DWT_HMX + 2 * mb;
+        T v[NV];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const T v = tin[r * HMX + 2 * m + k];
-            lo += h[k] * v;
-            hi += g[k] * v;
-        }
-        rl[r * DWT_OTX + m] = lo;
-        rh[r * DWT_OTX + m] = hi;
-    }
-    __syncthreads();
-    // along y: the four sub-bands; z <- c + clip(z, tau)
+        for (int t = 0; t < NV; ++t) v[t] = row[t];
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const int e = threadIdx.x + j * DWT_NTH;
-        if (e < oty * otx) {
-            const int i = e / otx, m = e - i * otx;
-            T a = T(0), by = T(0), bx = T(0), d = T(0);
+        for (int o = 0; o < DWT_MB; ++o) {
+            T lo = T(0), hi = T(0);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const T vl = rl[(2 * i + k) * DWT_OTX + m], vh = rh[(2 * i + k) * DWT_OTX + m];
-                a += h[k] * vl;
-                by += g[k] * vl;
-                bx += h[k] * vh;
-                d += g[k] * vh;
+                lo += h[k] * v[2 * o + k];
+                hi += g[k] * v[2 * o + k];
             }
-            const long gi = i0 + i, gm = m0 + m;
-            if constexpr (MODE == 0) {
-                zb[gi * ld + hx + gm] = bx + wclip(zq[j][0], tau);               // x high, y low
-                zb[(hy + gi) * ld + gm] = by + wclip(zq[j][1], tau);             // x low, y high
-                zb[(hy + gi) * ld + hx + gm] = d + wclip(zq[j][2], tau);
-                if (llb) llb[gi * hx + gm] = a;
-                else zb[gi * ld + gm] = a + wclip(zq[j][3], tau);
-                continue;
+            if (mb + o < otx) {
+                rl[r * DWT_OTX + mb + o] = lo;
+                rh[r * DWT_OTX + mb + o] = hi;
             }
+        }
+    }
+    __syncthreads();
+    if (!it.on) return;
+    // along y: the four sub-bands of rows ci + r; z <- c + clip(z, tau)
+    const int ci = it.ci, cm = it.cm;
+    T vl[NR], vh[NR];
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+        vl[t] = rl[(2 * ci + t) * DWT_OTX + cm];
+        vh[t] = rh[(2 * ci + t) * DWT_OTX + cm];
+    }
+#pragma unroll
+    for (int r = 0; r < DWT_IB; ++r) {
+        T a = T(0), by = T(0), bx = T(0), d = T(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            a += h[k] * vl[2 * r + k];
+            by += g[k] * vl[2 * r + k];
+            bx += h[k] * vh[2 * r + k];
+            d += g[k] * vh[2 * r + k];
+        }
+        const long gi = i0 + ci + r, gm = m0 + cm;
+        if constexpr (MODE == 0) {
+            zb[gi * ld + hx + gm] = bx + wclip(zq[r][0], tau);               // x high, y low
+            zb[(hy + gi) * ld + gm] = by + wclip(zq[r][1], tau);             // x low, y high
+            zb[(hy + gi) * ld + hx + gm] = d + wclip(zq[r][2], tau);
             if (llb) llb[gi * hx + gm] = a;
-            if constexpr (MODE == 2) {
-                st.r2 += double(fabs(bx)) + double(fabs(by)) + double(fabs(d));
-                if (!llb) st.r2 += double(fabs(a));
-                continue;
-            }
-            const long o0 = gi * ld + hx + gm, o1 = (hy + gi) * ld + gm, o2 = (hy + gi) * ld + hx + gm,
-                       o3 = gi * ld + gm;
-            const T n0 = bx + wclip(zq[j][0], tau);               // x high, y low
-            const T n1 = by + wclip(zq[j][1], tau);               // x low, y high
-            const T n2 = d + wclip(zq[j][2], tau);
-            const T n3 = a + wclip(zq[j][3], tau);
-            zb[o0] = n0;
-            zb[o1] = n1;
-            zb[o2] = n2;
-            if (!llb) zb[o3] = n3;
-            if constexpr (MODE == 1) {
-                db[o0] = wstat(zq[j][0], n0, tau, rT, st);
-                db[o1] = wstat(zq[j][1], n1, tau, rT, st);
-                db[o2] = wstat(zq[j][2], n2, tau, rT, st);
-                if (!llb) db[o3] = wstat(zq[j][3], n3, tau, rT, st);
-            }
+            else zb[gi * ld + gm] = a + wclip(zq[r][3], tau);
+            continue;
+        }
+        if (llb) llb[gi * hx + gm] = a;
+        if constexpr (MODE == 2) {
+            st.r2 += double(fabs(bx)) + double(fabs(by)) + double(fabs(d));
+            if (!llb) st.r2 += double(fabs(a));
+            continue;
+        }
+        const long o0 = gi * ld + hx + gm, o1 = (hy + gi) * ld + gm, o2 = (hy + gi) * ld + hx + gm,
+                   o3 = gi * ld + gm;
+        const T n0 = bx + wclip(zq[r][0], tau);               // x high, y low
+        const T n1 = by + wclip(zq[r][1], tau);               // x low, y high
+        const T n2 = d + wclip(zq[r][2], tau);
+        const T n3 = a + wclip(zq[r][3], tau);
+        zb[o0] = n0;
+        zb[o1] = n1;
+        zb[o2] = n2;
+        if (!llb) zb[o3] = n3;
+        if constexpr (MODE == 1) {
+            db[o0] = wstat(zq[r][0], n0, tau, rT, st);
+            db[o1] = wstat(zq[r][1], n1, tau, rT, st);
+            db[o2] = wstat(zq[r][2], n2, tau, rT, st);
+            if (!llb) db[o3] = wstat(zq[r][3], n3, tau, rT, st);
         }
     }
 }
 
+// Synthesis output ownership: thread t forms 8 adjacent pixels of one row
+// of the 2 oty x 2 otx tile (row rr, columns c0 .. c0 + 7); n of them lie
+// in the tile (4 when the tile is 4 pixels wide).  False for threads
+// without pixels.
+constexpr int DWT_C2 = 4;    // coefficient columns per thread in the column synthesis (8 pixels)
+__device__ __forceinline__ bool inv_out(int oty, int otx, int& rr, int& c0, int& n) {
+    const int nc = otx >= DWT_C2 ? otx / DWT_C2 : 1;
+    const int t = threadIdx.x;
+    rr = t / nc;
+    c0 = (t - rr * nc) * 2 * DWT_C2;
+    n = otx >= DWT_C2 ? 2 * DWT_C2 : 2 * otx;
+    return t < 2 * oty * nc;
+}
+
 // One synthesis tile producing 2 oty x 2 otx pixels of an sy x sx image (one
-// band) from the four sub-bands of u = 2 soft(z, tau) - z (LL from llb, the
-// band's dense [sy/2][sx/2] image, or from zb when null); ob with row stride
-// out_ld: ob = x, or ob += scale x.
+// band) from the four sub-bands of f(z) (scoef; LL from llb, the band's
+// dense [sy/2][sx/2] image, or from zb when null), added to the thread's 8
+// pixels acc (inv_out).  Register blocking: a thread of the row synthesis
+// forms both output parities of 2 coefficient rows of one column from
+// K / 2 + 1 rows of each sub-band; a thread of the column synthesis forms 8
+// adjacent pixels from K / 2 + 3 values of each half.  Each output's taps
+// are summed in tap order.  Ends with a barrier, so the next tile may reuse
+// the LDS at once.
 template <typename T, int K, int CF>
-__device__ __forceinline__ void dwt_inv_tile(const T* __restrict__ llb, const T* __restrict__ zb, int ld,
-                                             T* __restrict__ ob, int out_ld, int sy, int sx, const T (&h)[K],
-                                             const T (&g)[K], T tau, T scale, bool accumulate, T* smem) {
+__device__ __forceinline__ void dwt_inv_tile(const T* __restrict__ llb, const T* __restrict__ zb, int ld, int sy,
+                                             int sx, const T (&h)[K], const T (&g)[K], T tau, T* smem,
+                                             T (&acc)[2 * DWT_C2]) {
     constexpr int H2 = K / 2 - 1;                 // coefficient halo below the tile
     constexpr int CMY = DWT_OTY + H2, CM = DWT_OTX + H2;
+    constexpr int NY = K / 2 + 1, NX = K / 2 + DWT_C2 - 1;
     T* ca = smem;
     T* cbx = ca + CMY * CM;
     T* cby = cbx + CMY * CM;
@@ -203,21 +280,6 @@ __device__ __forceinline__ void dwt_inv_tile(const T* __restrict__ llb, const T*
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
     const int CY = oty + H2, CX = otx + H2;
-    // the outputs this thread adds to, loaded first (accumulating form)
-    constexpr int OPT = (2 * DWT_OTY * DWT_OTX + DWT_NTH - 1) / DWT_NTH;
-    T oq[2][OPT];
-    if (accumulate) {
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int j = 0; j < OPT; ++j) {
-                const int e = threadIdx.x + j * DWT_NTH;
-                if (e < 2 * oty * otx) {
-                    const int rr = e / otx, c2 = e - rr * otx;
-                    oq[p][j] = ob[long(2 * i0 + rr) * out_ld + 2 * m0 + 2 * c2 + p];
-                }
-            }
-    }
     for (int e = threadIdx.x; e < CY * CX; e += DWT_NTH) {
         const int n = e / CX, q = e - n * CX;
         // periodic coefficient indices i0 - H2 + n, m0 - H2 + q (hy, hx powers of two)
@@ -228,45 +290,61 @@ __device__ __forceinline__ void dwt_inv_tile(const T* __restrict__ llb, const T*
         cd[n * CM + q] = scoef<T, CF>(zb[(hy + gi) * ld + hx + gm], tau);
     }
     __syncthreads();
-    // along y: output rows rr = 2 r2 + p of the tile (the parity p picks the
-    // filter taps, so it is the outer, unrolled loop), coefficient columns q
+    // along y: coefficient rows r2 = rb + r (r < 2) of column q, output rows
+    // 2 r2 + p; row r2 takes coefficient rows r2 + H2 - kk, kk < K / 2
+    for (int e = threadIdx.x; e < (oty / 2) * CX; e += DWT_NTH) {
+        const int rb = (e / CX) * 2, q = e - (e / CX) * CX;
+        T va[NY], vby[NY], vbx[NY], vd[NY];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        for (int e = threadIdx.x; e < oty * CX; e += DWT_NTH) {
-            const int r2 = e / CX, q = e - r2 * CX;
-            const int base = r2 + H2;
-            T lo = T(0), hi = T(0);
-#pragma unroll
-            for (int kk = 0; kk < K / 2; ++kk) {
-                const int n = base - kk;
-                lo += h[2 * kk + p] * ca[n * CM + q] + g[2 * kk + p] * cby[n * CM + q];
-                hi += h[2 * kk + p] * cbx[n * CM + q] + g[2 * kk + p] * cd[n * CM + q];
-            }
-            xl[(2 * r2 + p) * CM + q] = lo;
-            xh[(2 * r2 + p) * CM + q] = hi;
+        for (int t = 0; t < NY; ++t) {
+            va[t] = ca[(rb + t) * CM + q];
+            vby[t] = cby[(rb + t) * CM + q];
+            vbx[t] = cbx[(rb + t) * CM + q];
+            vd[t] = cd[(rb + t) * CM + q];
         }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                T lo = T(0), hi = T(0);
+#pragma unroll
+                for (int kk = 0; kk < K / 2; ++kk) {
+                    const int t = r + H2 - kk;
+                    lo += h[2 * kk + p] * va[t] + g[2 * kk + p] * vby[t];
+                    hi += h[2 * kk + p] * vbx[t] + g[2 * kk + p] * vd[t];
+                }
+                xl[(2 * (rb + r) + p) * CM + q] = lo;
+                xh[(2 * (rb + r) + p) * CM + q] = hi;
+            }
     }
     __syncthreads();
-    // along x: output columns cc = 2 c2 + p
+    // along x: row rr, coefficient columns c2 = cb + c (c < DWT_C2), output
+    // columns 2 c2 + p; column c2 takes c2 + H2 - kk, kk < K / 2 (a tile
+    // narrower than DWT_C2 reads past its columns inside the LDS array and
+    // keeps only its own pixels)
+    int rr, c0, n;
+    if (inv_out(oty, otx, rr, c0, n)) {
+        const int cb = c0 / 2;
+        T ul[NX], uh[NX];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+        for (int t = 0; t < NX; ++t) {
+            ul[t] = xl[rr * CM + cb + t];
+            uh[t] = xh[rr * CM + cb + t];
+        }
 #pragma unroll
-        for (int j = 0; j < OPT; ++j) {
-            const int e = threadIdx.x + j * DWT_NTH;
-            if (e < 2 * oty * otx) {
-                const int rr = e / otx, c2 = e - rr * otx;
-                const int base = c2 + H2;
+        for (int c = 0; c < DWT_C2; ++c)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
                 T v = T(0);
 #pragma unroll
                 for (int kk = 0; kk < K / 2; ++kk) {
-                    const int q = base - kk;
-                    v += h[2 * kk + p] * xl[rr * CM + q] + g[2 * kk + p] * xh[rr * CM + q];
+                    const int t = c + H2 - kk;
+                    v += h[2 * kk + p] * ul[t] + g[2 * kk + p] * uh[t];
                 }
-                T* o = ob + long(2 * i0 + rr) * out_ld + 2 * m0 + 2 * c2 + p;
-                *o = accumulate ? oq[p][j] + scale * v : v;
+                acc[2 * c + p] += v;
             }
-        }
     }
+    __syncthreads();
 }
 
 template <typename T, int K>
@@ -278,33 +356,10 @@ __device__ __forceinline__ void load_taps(const T* __restrict__ fb, T (&h)[K], T
     }
 }
 
-// One analysis level of every basis and band: blockIdx.z = basis * L + band.
-// MODE 1 and 2 end with the work-group's FP64 sums in
-// A.partials[work-group * nq + q], nq = 3 (MODE 1) or 1 (MODE 2).
-template <typename T, int MODE>
-__global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd_all(DwtLevel A) {
-    __shared__ T smem[DWT_FWD_LDS];
-    const int b = blockIdx.z / A.L;
-    const long band = blockIdx.z - b * A.L;
-    const T* src = (const T*)A.in0 + b * A.in_bstride + band * A.in_bs;
-    T* zb = MODE == 2 ? nullptr : (T*)A.z0 + b * A.zstride + band * A.z_bs;
-    T* db = MODE == 1 ? (T*)A.d0 + b * A.dstride + band * A.z_bs : nullptr;
-    T* llb = A.ll0 ? (T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
-    const T* fb = (const T*)A.ftab + 32 * b;
-    WStats st;
-    switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
-#define F(KK)                                                                                           \
-    case KK: {                                                                                          \
-        T h[KK], g[KK];                                                                                 \
-        load_taps<T, KK>(fb, h, g);                                                                     \
-        dwt_fwd_tile<T, KK, MODE>(src, A.in_ld, zb, A.ld, llb, A.sy, A.sx, h, g, T(A.tau), smem, db,    \
-                                  T(A.rho_T), st);                                                      \
-        break;                                                                                          \
-    }
-        MUFFIN_DWT_K_CASES(F)
-#undef F
-        default: break;
-    }
+// The work-group's FP64 report sums (MODE 1: 3, MODE 2: 1) into
+// partials[work-group * nq + q].
+template <int MODE>
+__device__ __forceinline__ void fwd_sums(const WStats& st, double* partials) {
     if constexpr (MODE != 0) {
         __shared__ double sh[DWT_NTH / 64];
         const long wg = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -313,10 +368,87 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd_all(DwtLevel A) {
 #pragma unroll
         for (int q = 0; q < nq; ++q) {
             const double sq = block_sum_s<DWT_NTH>(v[q], sh);
-            if (threadIdx.x == 0) A.partials[wg * nq + q] = sq;
+            if (threadIdx.x == 0) partials[wg * nq + q] = sq;
         }
     }
 }
+
+#define MUFFIN_DWT_FWD_CASE(KK)                                                                  \
+    case KK: {                                                                                   \
+        T h[KK], g[KK];                                                                          \
+        load_taps<T, KK>(fb, h, g);                                                              \
+        dwt_fwd_tile<T, KK, MODE>(zb, A.ld, llb, A.sy, A.sx, h, g, T(A.tau), smem, db,           \
+                                  T(A.rho_T), st, it, zq);                                       \
+        break;                                                                                   \
+    }
+
+// One analysis level of every basis and band (a level above the finest).
+// MODE 1 and 2 end with the work-group's FP64 sums (fwd_sums).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd_all(DwtLevel A) {
+    __shared__ T smem[DWT_FWD_LDS];
+    // blockIdx.z = band * n + basis: the bases of one band run side by side,
+    // so the re-reads of its image hit the caches
+    const long band = blockIdx.z / A.n;
+    const int b = blockIdx.z - int(band) * A.n;
+    const T* src = (const T*)A.in0 + b * A.in_bstride + band * A.in_bs;
+    T* zb = MODE == 2 ? nullptr : (T*)A.z0 + b * A.zstride + band * A.z_bs;
+    T* db = MODE == 1 ? (T*)A.d0 + b * A.dstride + band * A.z_bs : nullptr;
+    T* llb = A.ll0 ? (T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
+    const T* fb = (const T*)A.ftab + 32 * b;
+    const int K = 2 * int((A.kpack >> (4 * b)) & 15u);
+    const int hy = A.sy >> 1, hx = A.sx >> 1;
+    const FwdItem it = fwd_item(hy < DWT_OTY ? hy : DWT_OTY, hx < DWT_OTX ? hx : DWT_OTX);
+    T zq[DWT_IB][4];
+    fwd_load_z<T, MODE>(zb, A.ld, llb == nullptr, A.sy, A.sx, it, zq);
+    fwd_stage<T>(src, A.in_ld, A.sy, A.sx, K, smem);
+    __syncthreads();
+    WStats st;
+    switch (K) {
+        MUFFIN_DWT_K_CASES(MUFFIN_DWT_FWD_CASE)
+        default: break;
+    }
+    fwd_sums<MODE>(st, A.partials);
+}
+
+// The finest analysis level of every basis: one work-group per tile and
+// band stages the image tile once (with the longest filter's halo) and
+// runs the bases over it in order.  MODE 1 and 2 end with the work-group's
+// FP64 sums (fwd_sums).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd0_all(DwtLevel A) {
+    __shared__ T smem[DWT_FWD_LDS];
+    const long band = blockIdx.z;
+    const T* src = (const T*)A.in0 + band * A.in_bs;
+    const int hy = A.sy >> 1, hx = A.sx >> 1;
+    const FwdItem it = fwd_item(hy < DWT_OTY ? hy : DWT_OTY, hx < DWT_OTX ? hx : DWT_OTX);
+    int kmax = 2;
+    for (int b = 0; b < A.n; ++b) {
+        const int K = 2 * int((A.kpack >> (4 * b)) & 15u);
+        kmax = K > kmax ? K : kmax;
+    }
+    T zq[DWT_IB][4];
+    fwd_load_z<T, MODE>(MODE == 2 ? nullptr : (const T*)A.z0 + band * A.z_bs, A.ld, A.ll0 == nullptr, A.sy,
+                        A.sx, it, zq);
+    fwd_stage<T>(src, A.in_ld, A.sy, A.sx, kmax, smem);
+    __syncthreads();
+    WStats st;
+    for (int b = 0; b < A.n; ++b) {
+        T* zb = MODE == 2 ? nullptr : (T*)A.z0 + b * A.zstride + band * A.z_bs;
+        T* db = MODE == 1 ? (T*)A.d0 + b * A.dstride + band * A.z_bs : nullptr;
+        T* llb = A.ll0 ? (T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
+        const T* fb = (const T*)A.ftab + 32 * b;
+        if (b > 0) fwd_load_z<T, MODE>(zb, A.ld, llb == nullptr, A.sy, A.sx, it, zq);
+        switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
+            MUFFIN_DWT_K_CASES(MUFFIN_DWT_FWD_CASE)
+            default: break;
+        }
+        // the next basis's row pass overwrites the row images
+        __syncthreads();
+    }
+    fwd_sums<MODE>(st, A.partials);
+}
+#undef MUFFIN_DWT_FWD_CASE
 
 // One synthesis level (not the finest) of every basis and band into the
 // bases' dense scratch images: blockIdx.z = basis * L + band.
@@ -329,49 +461,79 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     const T* llb = A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
     T* ob = (T*)A.out0 + b * A.outstride + band * long(A.sy) * A.sx;
     const T* fb = (const T*)A.ftab + 32 * b;
+    T acc[2 * DWT_C2] = {};
     switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
-#define F(KK)                                                                                          \
-    case KK: {                                                                                         \
-        T h[KK], g[KK];                                                                                \
-        load_taps<T, KK>(fb, h, g);                                                                    \
-        dwt_inv_tile<T, KK, CF>(llb, zb, A.ld, ob, A.sx, A.sy, A.sx, h, g, T(A.tau), T(1), false, smem); \
-        break;                                                                                         \
+#define F(KK)                                                                              \
+    case KK: {                                                                             \
+        T h[KK], g[KK];                                                                    \
+        load_taps<T, KK>(fb, h, g);                                                        \
+        dwt_inv_tile<T, KK, CF>(llb, zb, A.ld, A.sy, A.sx, h, g, T(A.tau), smem, acc);     \
+        break;                                                                             \
     }
         MUFFIN_DWT_K_CASES(F)
 #undef F
         default: break;
     }
+    const int hy = A.sy >> 1, hx = A.sx >> 1;
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
+    int rr, c0, n;
+    if (inv_out(oty, otx, rr, c0, n)) {
+        T* o = ob + long(2 * blockIdx.y * oty + rr) * A.sx + 2 * blockIdx.x * otx + c0;
+#pragma unroll
+        for (int c = 0; c < 2 * DWT_C2; ++c)
+            if (c < n) o[c] = acc[c];
+    }
 }
 
-// The finest synthesis level of one basis, added into B_rest (row stride nx,
-// band stride ny nx): Brest += scale * x.
-template <typename T, int K, int CF>
-__global__ void __launch_bounds__(DWT_NTH)
-k_dwt_inv0(const T* __restrict__ llin, const T* __restrict__ z, T* __restrict__ Brest, int ny, int nx,
-           WFilt<T> f, T tau, T scale) {
-    constexpr int CMY = DWT_OTY + K / 2 - 1, CM = DWT_OTX + K / 2 - 1;
-    __shared__ T smem[4 * CMY * CM + 2 * (2 * DWT_OTY) * CM];
+// The finest synthesis level of every basis, summed and added into out
+// ([L][sy][sx], row stride sx): out += scale * sum_b x_b, the bases in
+// order inside the work-group, so out is read and written once and the sum
+// has a fixed order.  blockIdx.z = band.
+template <typename T, int CF>
+__global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 4 : 3) k_dwt_inv0_all(DwtLevel A) {
+    __shared__ T smem[DWT_INV_LDS];
     const long band = blockIdx.z;
-    T h[K], g[K];
+    const long vb = long(A.sy) * A.sx;
+    const int hy = A.sy >> 1, hx = A.sx >> 1;
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
+    const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
+    T* ob = (T*)A.out0 + band * vb;
+    // the outputs, loaded first so that their latency overlaps the tiles
+    int rr, c0, n;
+    const bool own = inv_out(oty, otx, rr, c0, n);
+    T* o = ob + long(2 * i0 + rr) * A.sx + 2 * m0 + c0;
+    T oq[2 * DWT_C2], acc[2 * DWT_C2] = {};
+    if (own) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        h[k] = f.h[k];
-        g[k] = f.g[k];
+        for (int c = 0; c < 2 * DWT_C2; ++c)
+            if (c < n) oq[c] = o[c];
     }
-    const long vb = long(ny) * nx;
-    dwt_inv_tile<T, K, CF>(llin ? llin + band * (vb / 4) : nullptr, z + band * vb, nx, Brest + band * vb, nx, ny,
-                           nx, h, g, tau, scale, true, smem);
+    for (int b = 0; b < A.n; ++b) {
+        const T* zb = (const T*)A.z0 + b * A.zstride + band * A.z_bs;
+        const T* llb = A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * (vb / 4) : nullptr;
+        const T* fb = (const T*)A.ftab + 32 * b;
+        switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
+#define F(KK)                                                                              \
+    case KK: {                                                                             \
+        T h[KK], g[KK];                                                                    \
+        load_taps<T, KK>(fb, h, g);                                                        \
+        dwt_inv_tile<T, KK, CF>(llb, zb, A.ld, A.sy, A.sx, h, g, T(A.tau), smem, acc);     \
+        break;                                                                             \
+    }
+            MUFFIN_DWT_K_CASES(F)
+#undef F
+            default: break;
+        }
+    }
+    const T scale = T(A.scale);
+    if (own) {
+#pragma unroll
+        for (int c = 0; c < 2 * DWT_C2; ++c)
+            if (c < n) o[c] = oq[c] + scale * acc[c];
+    }
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename T> static WFilt<T> make_filt(const double* h, int K) {
-    WFilt<T> f{};
-    for (int k = 0; k < K; ++k) {
-        f.h[k] = T(h[k]);
-        f.g[k] = T((k & 1) ? -h[K - 1 - k] : h[K - 1 - k]);
-    }
-    return f;
-}
 
 static dim3 dwt_grid(int sy, int sx, int nz) {
     const int hy = sy / 2, hx = sx / 2;
@@ -389,20 +551,33 @@ static bool level_ok(const DwtLevel& A) {
     return true;
 }
 
-template <typename T>
+template <typename T, bool FINEST>
 static void fwd_all_t(const DwtLevel& A, dim3 grid, hipStream_t s) {
-    if (A.mode == 1) hipLaunchKernelGGL((k_dwt_fwd_all<T, 1>), grid, dim3(DWT_NTH), 0, s, A);
-    else if (A.mode == 2) hipLaunchKernelGGL((k_dwt_fwd_all<T, 2>), grid, dim3(DWT_NTH), 0, s, A);
-    else hipLaunchKernelGGL((k_dwt_fwd_all<T, 0>), grid, dim3(DWT_NTH), 0, s, A);
+    if (FINEST) {
+        if (A.mode == 1) hipLaunchKernelGGL((k_dwt_fwd0_all<T, 1>), grid, dim3(DWT_NTH), 0, s, A);
+        else if (A.mode == 2) hipLaunchKernelGGL((k_dwt_fwd0_all<T, 2>), grid, dim3(DWT_NTH), 0, s, A);
+        else hipLaunchKernelGGL((k_dwt_fwd0_all<T, 0>), grid, dim3(DWT_NTH), 0, s, A);
+    } else {
+        if (A.mode == 1) hipLaunchKernelGGL((k_dwt_fwd_all<T, 1>), grid, dim3(DWT_NTH), 0, s, A);
+        else if (A.mode == 2) hipLaunchKernelGGL((k_dwt_fwd_all<T, 2>), grid, dim3(DWT_NTH), 0, s, A);
+        else hipLaunchKernelGGL((k_dwt_fwd_all<T, 0>), grid, dim3(DWT_NTH), 0, s, A);
+    }
 }
 
-hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s) {
+hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s, bool finest) {
     if (!level_ok(A) || A.mode < 0 || A.mode > 2 || !A.in0) return hipErrorInvalidValue;
     if ((A.mode != 2 && !A.z0) || (A.mode == 1 && !A.d0) || (A.mode != 0 && !A.partials))
         return hipErrorInvalidValue;
-    const dim3 grid = dwt_grid(A.sy, A.sx, A.n * A.L);
-    if (dtype == 0) fwd_all_t<float>(A, grid, s);
-    else fwd_all_t<double>(A, grid, s);
+    // the finest form reads one image per band (no per-basis input stride)
+    if (finest && A.in_bstride != 0) return hipErrorInvalidValue;
+    const dim3 grid = dwt_grid(A.sy, A.sx, finest ? A.L : A.n * A.L);
+    if (finest) {
+        if (dtype == 0) fwd_all_t<float, true>(A, grid, s);
+        else fwd_all_t<double, true>(A, grid, s);
+    } else {
+        if (dtype == 0) fwd_all_t<float, false>(A, grid, s);
+        else fwd_all_t<double, false>(A, grid, s);
+    }
     return hipGetLastError();
 }
 
@@ -421,37 +596,19 @@ hipError_t launch_dwt_inv_all(int dtype, const DwtLevel& A, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int K>
-static hipError_t inv0_t(const double* h, const void* llin, const void* z, void* Brest, int ny, int nx, int L,
-                         double tau, double scale, hipStream_t s, int cmode) {
-    const dim3 grid = dwt_grid(ny, nx, L);
-    const WFilt<T> f = make_filt<T>(h, K);
-    if (cmode == 1)
-        hipLaunchKernelGGL((k_dwt_inv0<T, K, 1>), grid, dim3(DWT_NTH), 0, s, (const T*)llin, (const T*)z, (T*)Brest,
-                           ny, nx, f, T(tau), T(scale));
-    else if (cmode == 2)
-        hipLaunchKernelGGL((k_dwt_inv0<T, K, 2>), grid, dim3(DWT_NTH), 0, s, (const T*)llin, (const T*)z, (T*)Brest,
-                           ny, nx, f, T(tau), T(scale));
-    else
-        hipLaunchKernelGGL((k_dwt_inv0<T, K, 0>), grid, dim3(DWT_NTH), 0, s, (const T*)llin, (const T*)z, (T*)Brest,
-                           ny, nx, f, T(tau), T(scale));
-    return hipGetLastError();
+template <typename T>
+static void inv0_all_t(const DwtLevel& A, dim3 grid, hipStream_t s) {
+    if (A.mode == 1) hipLaunchKernelGGL((k_dwt_inv0_all<T, 1>), grid, dim3(DWT_NTH), 0, s, A);
+    else if (A.mode == 2) hipLaunchKernelGGL((k_dwt_inv0_all<T, 2>), grid, dim3(DWT_NTH), 0, s, A);
+    else hipLaunchKernelGGL((k_dwt_inv0_all<T, 0>), grid, dim3(DWT_NTH), 0, s, A);
 }
 
-hipError_t launch_dwt_inv0(int dtype, int K, const double* h, const void* llin, const void* z, void* Brest, int ny,
-                           int nx, int L, double tau, double scale, hipStream_t s, int cmode) {
-    if (K < 2 || K > 16 || (K & 1) || ny < 4 || nx < 4 || L < 1 || (ny & (ny - 1)) || (nx & (nx - 1)) || !z ||
-        !Brest || cmode < 0 || cmode > 2)
-        return hipErrorInvalidValue;
-    switch (K) {
-#define F(KK)                                                                                          \
-    case KK:                                                                                           \
-        return dtype == 0 ? inv0_t<float, KK>(h, llin, z, Brest, ny, nx, L, tau, scale, s, cmode)      \
-                          : inv0_t<double, KK>(h, llin, z, Brest, ny, nx, L, tau, scale, s, cmode);
-        MUFFIN_DWT_K_CASES(F)
-#undef F
-    }
-    return hipErrorInvalidValue;
+hipError_t launch_dwt_inv0_all(int dtype, const DwtLevel& A, hipStream_t s) {
+    if (!level_ok(A) || !A.out0 || !A.z0 || A.mode < 0 || A.mode > 2) return hipErrorInvalidValue;
+    const dim3 grid = dwt_grid(A.sy, A.sx, A.L);
+    if (dtype == 0) inv0_all_t<float>(A, grid, s);
+    else inv0_all_t<double>(A, grid, s);
+    return hipGetLastError();
 }
 
 }  // namespace muffin
