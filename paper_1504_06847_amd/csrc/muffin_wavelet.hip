@@ -254,42 +254,84 @@ __device__ __forceinline__ bool inv_out(int oty, int otx, int& rr, int& c0, int&
     return t < 2 * oty * nc;
 }
 
-// One synthesis tile producing 2 oty x 2 otx pixels of an sy x sx image (one
-// band) from the four sub-bands of f(z) (scoef; LL from llb, the band's
-// dense [sy/2][sx/2] image, or from zb when null), added to the thread's 8
-// pixels acc (inv_out).  Register blocking: a thread of the row synthesis
-// forms both output parities of 2 coefficient rows of one column from
-// K / 2 + 1 rows of each sub-band; a thread of the column synthesis forms 8
-// adjacent pixels from K / 2 + 3 values of each half.  Each output's taps
-// are summed in tap order.  Ends with a barrier, so the next tile may reuse
-// the LDS at once.
-template <typename T, int K, int CF>
-__device__ __forceinline__ void dwt_inv_tile(const T* __restrict__ llb, const T* __restrict__ zb, int ld, int sy,
-                                             int sx, const T (&h)[K], const T (&g)[K], T tau, T* smem,
-                                             T (&acc)[2 * DWT_C2]) {
-    constexpr int H2 = K / 2 - 1;                 // coefficient halo below the tile
-    constexpr int CMY = DWT_OTY + H2, CM = DWT_OTX + H2;
-    constexpr int NY = K / 2 + 1, NX = K / 2 + DWT_C2 - 1;
-    T* ca = smem;
-    T* cbx = ca + CMY * CM;
-    T* cby = cbx + CMY * CM;
-    T* cd = cby + CMY * CM;
-    T* xl = cd + CMY * CM;
-    T* xh = xl + 2 * DWT_OTY * CM;
+// The coefficients of one synthesis tile (filter length 2 H2 + 2): the
+// (oty + H2) x (otx + H2) block of each sub-band below and right of the
+// tile's own, periodic, as read from memory (LL from llb, the band's dense
+// [sy/2][sx/2] image, when not null, else from zb).  Fetched into registers
+// ahead of their use, then committed to LDS.
+constexpr int DWT_PF = ((DWT_OTY + 7) * (DWT_OTX + 7) + DWT_NTH - 1) / DWT_NTH;
+template <typename T>
+__device__ __forceinline__ void inv_fetch(const T* __restrict__ llb, const T* __restrict__ zb, int ld, int sy,
+                                          int sx, int H2, T (&pf)[DWT_PF][4]) {
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
     const int CY = oty + H2, CX = otx + H2;
-    for (int e = threadIdx.x; e < CY * CX; e += DWT_NTH) {
-        const int n = e / CX, q = e - n * CX;
-        // periodic coefficient indices i0 - H2 + n, m0 - H2 + q (hy, hx powers of two)
-        const long gi = (i0 - H2 + n + 8 * hy) & (hy - 1), gm = (m0 - H2 + q + 8 * hx) & (hx - 1);
-        ca[n * CM + q] = llb ? llb[gi * hx + gm] : scoef<T, CF>(zb[gi * ld + gm], tau);
-        cbx[n * CM + q] = scoef<T, CF>(zb[gi * ld + hx + gm], tau);
-        cby[n * CM + q] = scoef<T, CF>(zb[(hy + gi) * ld + gm], tau);
-        cd[n * CM + q] = scoef<T, CF>(zb[(hy + gi) * ld + hx + gm], tau);
+#pragma unroll
+    for (int j = 0; j < DWT_PF; ++j) {
+        const int e = threadIdx.x + j * DWT_NTH;
+        if (e < CY * CX) {
+            const int n = e / CX, q = e - n * CX;
+            // periodic coefficient indices i0 - H2 + n, m0 - H2 + q (hy, hx powers of two)
+            const long gi = (i0 - H2 + n + 8 * hy) & (hy - 1), gm = (m0 - H2 + q + 8 * hx) & (hx - 1);
+            pf[j][0] = llb ? llb[gi * hx + gm] : zb[gi * ld + gm];
+            pf[j][1] = zb[gi * ld + hx + gm];
+            pf[j][2] = zb[(hy + gi) * ld + gm];
+            pf[j][3] = zb[(hy + gi) * ld + hx + gm];
+        }
     }
-    __syncthreads();
+}
+
+// The fetched coefficients into LDS as f(z) (scoef; the LL block as it is
+// when it came from a coarser level's image), laid out for filter length
+// 2 H2 + 2.  The caller synchronises before the tile reads them.
+template <typename T, int CF>
+__device__ __forceinline__ void inv_commit(const T (&pf)[DWT_PF][4], bool ll_image, int sy, int sx, int H2, T tau,
+                                           T* smem) {
+    const int hy = sy >> 1, hx = sx >> 1;
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
+    const int CY = oty + H2, CX = otx + H2;
+    const int CM = DWT_OTX + H2, CMY = DWT_OTY + H2;
+    T* ca = smem;
+    T* cbx = ca + CMY * CM;
+    T* cby = cbx + CMY * CM;
+    T* cd = cby + CMY * CM;
+#pragma unroll
+    for (int j = 0; j < DWT_PF; ++j) {
+        const int e = threadIdx.x + j * DWT_NTH;
+        if (e < CY * CX) {
+            const int n = e / CX, q = e - n * CX;
+            ca[n * CM + q] = ll_image ? pf[j][0] : scoef<T, CF>(pf[j][0], tau);
+            cbx[n * CM + q] = scoef<T, CF>(pf[j][1], tau);
+            cby[n * CM + q] = scoef<T, CF>(pf[j][2], tau);
+            cd[n * CM + q] = scoef<T, CF>(pf[j][3], tau);
+        }
+    }
+}
+
+// One synthesis tile producing 2 oty x 2 otx pixels of an sy x sx image (one
+// band) from the four sub-bands committed to LDS (inv_commit; the caller
+// synchronises after committing), added to the thread's 8 pixels acc
+// (inv_out).  Register blocking: a thread of the row synthesis forms both
+// output parities of 2 coefficient rows of one column from K / 2 + 1 rows of
+// each sub-band; a thread of the column synthesis forms 8 adjacent pixels
+// from K / 2 + 3 values of each half.  Each output's taps are summed in tap
+// order.  Ends with a barrier, so the next tile may reuse the LDS at once.
+template <typename T, int K>
+__device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], const T (&g)[K], T* smem,
+                                             T (&acc)[2 * DWT_C2]) {
+    constexpr int H2 = K / 2 - 1;                 // coefficient halo below the tile
+    constexpr int CMY = DWT_OTY + H2, CM = DWT_OTX + H2;
+    constexpr int NY = K / 2 + 1, NX = K / 2 + DWT_C2 - 1;
+    const T* ca = smem;
+    const T* cbx = ca + CMY * CM;
+    const T* cby = cbx + CMY * CM;
+    const T* cd = cby + CMY * CM;
+    T* xl = smem + 4 * CMY * CM;
+    T* xh = xl + 2 * DWT_OTY * CM;
+    const int hy = sy >> 1, hx = sx >> 1;
+    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
+    const int CX = otx + H2;
     // along y: coefficient rows r2 = rb + r (r < 2) of column q, output rows
     // 2 r2 + p; row r2 takes coefficient rows r2 + H2 - kk, kk < K / 2
     for (int e = threadIdx.x; e < (oty / 2) * CX; e += DWT_NTH) {
@@ -462,12 +504,19 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     T* ob = (T*)A.out0 + b * A.outstride + band * long(A.sy) * A.sx;
     const T* fb = (const T*)A.ftab + 32 * b;
     T acc[2 * DWT_C2] = {};
-    switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
+    const int K = 2 * int((A.kpack >> (4 * b)) & 15u);
+    {
+        T pf[DWT_PF][4];
+        inv_fetch<T>(llb, zb, A.ld, A.sy, A.sx, K / 2 - 1, pf);
+        inv_commit<T, CF>(pf, llb != nullptr, A.sy, A.sx, K / 2 - 1, T(A.tau), smem);
+    }
+    __syncthreads();
+    switch (K) {
 #define F(KK)                                                                              \
     case KK: {                                                                             \
         T h[KK], g[KK];                                                                    \
         load_taps<T, KK>(fb, h, g);                                                        \
-        dwt_inv_tile<T, KK, CF>(llb, zb, A.ld, A.sy, A.sx, h, g, T(A.tau), smem, acc);     \
+        dwt_inv_tile<T, KK>(A.sy, A.sx, h, g, smem, acc);                                  \
         break;                                                                             \
     }
         MUFFIN_DWT_K_CASES(F)
@@ -508,16 +557,24 @@ __global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 4 : 3) k_dwt_inv0_al
         for (int c = 0; c < 2 * DWT_C2; ++c)
             if (c < n) oq[c] = o[c];
     }
+    // the coefficients of basis b + 1 are fetched while basis b is synthesised
+    auto zb_of = [&](int b) { return (const T*)A.z0 + b * A.zstride + band * A.z_bs; };
+    auto llb_of = [&](int b) { return A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * (vb / 4) : nullptr; };
+    auto k_of = [&](int b) { return 2 * int((A.kpack >> (4 * b)) & 15u); };
+    T pf[DWT_PF][4];
+    inv_fetch<T>(llb_of(0), zb_of(0), A.ld, A.sy, A.sx, k_of(0) / 2 - 1, pf);
     for (int b = 0; b < A.n; ++b) {
-        const T* zb = (const T*)A.z0 + b * A.zstride + band * A.z_bs;
-        const T* llb = A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * (vb / 4) : nullptr;
+        const int K = k_of(b);
+        inv_commit<T, CF>(pf, A.ll0 != nullptr, A.sy, A.sx, K / 2 - 1, T(A.tau), smem);
+        __syncthreads();
+        if (b + 1 < A.n) inv_fetch<T>(llb_of(b + 1), zb_of(b + 1), A.ld, A.sy, A.sx, k_of(b + 1) / 2 - 1, pf);
         const T* fb = (const T*)A.ftab + 32 * b;
-        switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
+        switch (K) {
 #define F(KK)                                                                              \
     case KK: {                                                                             \
         T h[KK], g[KK];                                                                    \
         load_taps<T, KK>(fb, h, g);                                                        \
-        dwt_inv_tile<T, KK, CF>(llb, zb, A.ld, A.sy, A.sx, h, g, T(A.tau), smem, acc);     \
+        dwt_inv_tile<T, KK>(A.sy, A.sx, h, g, smem, acc);                                  \
         break;                                                                             \
     }
             MUFFIN_DWT_K_CASES(F)
