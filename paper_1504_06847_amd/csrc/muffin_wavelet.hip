@@ -427,7 +427,7 @@ __device__ __forceinline__ void fwd_sums(const WStats& st, double* partials) {
 // One analysis level of every basis and band (a level above the finest).
 // MODE 1 and 2 end with the work-group's FP64 sums (fwd_sums).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd_all(DwtLevel A) {
+__global__ void __launch_bounds__(DWT_NTH, (sizeof(T) == 4 && MODE == 0) ? 6 : 1) k_dwt_fwd_all(DwtLevel A) {
     __shared__ T smem[DWT_FWD_LDS];
     // blockIdx.z = band * n + basis: the bases of one band run side by side,
     // so the re-reads of its image hit the caches
