@@ -110,7 +110,8 @@ typedef struct {
     int n_s;          /* number of spatial bases W_s stacks, 1 <= n_s <= 9 */
     int spatial[9];   /* spatial[0] = MUFFIN_DIRAC; spatial[1 .. n_s-1] in
                          MUFFIN_DB1 .. MUFFIN_DB8.  With n_s > 1: the
-                         three-launch pass, no gradient and no batches
+                         three-launch pass (in a batch, the cube's wavelet
+                         launches follow its grouped ones) and no gradient
                          (MUFFIN_EUNSUPPORTED); a reporting pass runs each
                          basis's analysis once more in report form and three
                          syntheses for W_s^T dT and W_s^T Gamma_T (three more

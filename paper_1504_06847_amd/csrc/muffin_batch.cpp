@@ -72,6 +72,7 @@ struct muffin_batch {
     hipStream_t lane_s[kMaxLanes];
     hipEvent_t lane_e[kMaxLanes];
     hipEvent_t fork_e;
+    std::vector<int> cube_lane;            // lane of each cube's classes
 };
 
 namespace {
@@ -251,6 +252,7 @@ void build_classes(muffin_batch* b) {
     old.swap(b->classes);
     std::vector<int> lane;
     assign_lanes(b, lane);
+    b->cube_lane = lane;
     for (int i = 0; i < b->n; ++i) {
         const muffin_shape& s = b->cubes[i]->shape;
         const int l = lane[size_t(i)];
@@ -303,12 +305,28 @@ hipError_t launch_class(const muffin_batch* b, const Class& k, int variant, hipS
     }
 }
 
+// the wavelet part of the pass of every cube whose W_s has wavelet bases
+// (steps III and VI per basis, its terms added to B_rest), each on the
+// stream of its cube's classes, after them
+int dict_passes(muffin_batch* b, hipStream_t s, bool lanes) {
+    for (int i = 0; i < b->n; ++i) {
+        muffin_ctx* c = b->cubes[size_t(i)];
+        if (c->lay.n_w == 0) continue;
+        const hipStream_t keep = c->stream;
+        c->stream = lanes ? b->lane_s[b->cube_lane[size_t(i)]] : s;
+        const int rc = dict_pass(c);
+        c->stream = keep;
+        if (rc) return rc;
+    }
+    return MUFFIN_OK;
+}
+
 int pass_kernels(muffin_batch* b, hipStream_t s) {
     if (b->n_lanes <= 1) {
         for (int kind = 0; kind < K_NUM; ++kind)
             for (const Class& k : b->classes)
                 if (k.kind == kind) HIP_TRY(launch_class(b, k, k.variant, s));
-        return MUFFIN_OK;
+        return dict_passes(b, s, false);
     }
     for (int l = 0; l < b->n_lanes; ++l) {
         if (!b->lane_s[l]) HIP_TRY(hipStreamCreateWithFlags(&b->lane_s[l], hipStreamNonBlocking));
@@ -320,6 +338,7 @@ int pass_kernels(muffin_batch* b, hipStream_t s) {
     for (int kind = 0; kind < K_NUM; ++kind)
         for (const Class& k : b->classes)
             if (k.kind == kind) HIP_TRY(launch_class(b, k, k.variant, b->lane_s[k.lane]));
+    if (int rc = dict_passes(b, s, true)) return rc;
     for (int l = 0; l < b->n_lanes; ++l) {
         HIP_TRY(hipEventRecord(b->lane_e[l], b->lane_s[l]));
         HIP_TRY(hipStreamWaitEvent(s, b->lane_e[l], 0));
@@ -366,10 +385,6 @@ int check_shapes(int n, const muffin_shape* shapes, const muffin_params* params)
     if (!shapes || !params) { set_error("shapes and params must be non-NULL"); return MUFFIN_EINVAL; }
     for (int i = 0; i < n; ++i) {
         if (int rc = muffin_validate(&shapes[i], &params[i])) return rc;
-        if (params[i].n_s != 1) {
-            set_error("cube %d: batches run the Dirac spatial basis only (n_s = %d)", i, params[i].n_s);
-            return MUFFIN_EUNSUPPORTED;
-        }
         if (shapes[i].L > 128) {
             set_error("cube %d: batches take band counts up to 128 (L = %d)", i, shapes[i].L);
             return MUFFIN_EUNSUPPORTED;

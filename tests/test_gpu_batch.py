@@ -220,3 +220,33 @@ def test_batch_autotune_keeps_results(gpu_lib):
         d = _relmax(b.cube(i).x, a.cube(i).x)
         _say("batch autotune: cube", i, "max rel diff", d)
         assert d <= TOL[torch.float32]
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["launch", "graph"])
+def test_batch_with_wavelet_dictionaries_bitwise(gpu_lib, graph):
+    """Cubes with wavelet bases in W_s (the paper's dictionary, a subset, the
+    Dirac basis alone) batched with others: each cube's wavelet launches
+    follow its grouped ones on its lane, so every cube repeats its single
+    run bit for bit."""
+    from paper_1504_06847_amd import Batch, Solver
+    shapes = [(8, 32, 32), (8, 64, 64), (4, 32, 64), (8, 32, 32), (16, 16, 16)]
+    bases = [(0, 1, 2, 3, 4, 5, 6, 7, 8), (0,), (0, 2, 5), (0, 8), (0, 1, 2, 3, 4, 5, 6, 7, 8)]
+    cubes = _cubes(shapes, seed0=400)
+    prm = [dict(PARAMS, spatial=sp) for sp in bases]
+    _say("wavelet batch", "graph" if graph else "launch")
+    b = Batch(cubes, dtype=torch.float32, graph=graph, params=prm)
+    singles = [Solver(p, d, dtype=torch.float32, spatial=sp, **PARAMS) for (p, d), sp in zip(cubes, bases)]
+    for k in range(5):
+        b.iterate(1)
+        for s in singles:
+            s.iterate(1)
+        torch.cuda.synchronize()
+        for i, s in enumerate(singles):
+            assert torch.equal(b.cube(i).x, s.x), f"pass {k + 1}, cube {i} {shapes[i]} {bases[i]}"
+    b.iterate(6)
+    for s in singles:
+        s.iterate(6)
+    torch.cuda.synchronize()
+    for i, s in enumerate(singles):
+        assert torch.equal(b.cube(i).get_state(), s.get_state()), f"cube {i}"
+    b.close()
