@@ -111,8 +111,7 @@ typedef struct {
     int spatial[9];   /* spatial[0] = MUFFIN_DIRAC; spatial[1 .. n_s-1] in
                          MUFFIN_DB1 .. MUFFIN_DB8.  With n_s > 1: the
                          three-launch pass (in a batch, the cube's wavelet
-                         launches follow its grouped ones) and no gradient
-                         (MUFFIN_EUNSUPPORTED); a reporting pass runs each
+                         launches follow its grouped ones); a reporting pass runs each
                          basis's analysis once more in report form and three
                          syntheses for W_s^T dT and W_s^T Gamma_T (three more
                          cubes of workspace) */
@@ -221,16 +220,21 @@ int muffin_get_p(muffin_ctx* ctx, void* p_out);
    ckpt_every, 0) bytes; the library allocates nothing).  grad: host
    double[3].  The context's state afterwards equals the state after K
    passes from zero.  Synchronises the stream.
-   Errors: EINVAL, EUNSUPPORTED (wavelet dictionary), EWORKSPACE (no or a too
-   small workspace attached), EDEVICE, ENONFINITE. */
+   With wavelet bases in W_s their coefficient cubes z_b are stored with the
+   state and the sweep runs the adjoint of their updates and of their B_rest
+   terms (the step-I adjoint of each pass then runs on its own launch).
+   Errors: EINVAL, EUNSUPPORTED (visibility-domain context, a union of
+   spectral bases, L > 128), EWORKSPACE (no or a too small workspace
+   attached), EDEVICE, ENONFINITE. */
 int muffin_grad(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
                 double* loss, double grad[3]);
 
 /* Bytes of device scratch the reverse sweep of K passes with checkpoints
    every ckpt_every needs (dirty = 1: for muffin_grad_dirty, one cube more):
-   4 ceil(K / C) + 10 C + 11 cubes for C = ckpt_every < K (4 + 5 K + 11 for
-   C >= K), a cube being L ny nx values of the context's dtype rounded up to
-   256 B, plus FP64 block sums.  0 for a NULL or batch context, K < 1 or
+   with m = 4 + n_w state cubes per stored state (n_w = n_s - 1 wavelet
+   bases), m ceil(K / C) + 2 (m + 1) C + 6 + n_w cubes for C = ckpt_every < K
+   (m + (m + 1) K + 6 + n_w for C >= K), a cube being L ny nx values of the
+   context's dtype rounded up to 256 B, plus FP64 block sums.  0 for a NULL or batch context, K < 1 or
    ckpt_every < 1.  Host-only. */
 size_t muffin_grad_workspace_bytes(const muffin_ctx* ctx, int K, int ckpt_every, int dirty);
 

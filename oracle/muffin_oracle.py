@@ -352,17 +352,19 @@ def mse_loss(XK, sky) -> float:
 
 
 def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params, dHtY=None):
-    """Primal pass of Algorithm 1 with its forward-mode tangent (Dirac W_s,
-    one orthonormal spectral basis W_nu); dHtY: the tangent of H^T Y (a
-    change of the dirty images), or None."""
-    assert prob.dirac_only, "the tangent pass is written for W_s = identity"
+    """Primal pass of Algorithm 1 with its forward-mode tangent (W_s the
+    Dirac basis or a union of orthonormal bases, one orthonormal spectral
+    basis W_nu); dHtY: the tangent of H^T Y (a change of the dirty images),
+    or None.  W_s is linear, so it carries tangents as it carries values."""
     assert prob.m_nu == 1, "the tangent pass is written for one spectral basis"
     fw, bw = prob.Wnu.forward, prob.Wnu.adjoint
+    Ws, WsT = prob.Ws, prob.WsT
     p = prob.p
-    drhoQ = dp.mu_eps + dp.rho_S + dp.rho_P + dp.rho_T
-    B = (prob.HtY + st.GT + p.rho_T * st.T + st.GP + p.rho_P * st.P
+    # rho of eq. Qlsimp: mu_eps + rho_S + rho_P + n_s rho_T
+    drhoQ = dp.mu_eps + dp.rho_S + dp.rho_P + prob.n_s * dp.rho_T
+    B = (prob.HtY + WsT(st.GT + p.rho_T * st.T) + st.GP + p.rho_P * st.P
          + st.GS + p.rho_S * st.S)
-    dB = (dst.GT + dp.rho_T * st.T + p.rho_T * dst.T + dst.GP + dp.rho_P * st.P
+    dB = (WsT(dst.GT + dp.rho_T * st.T + p.rho_T * dst.T) + dst.GP + dp.rho_P * st.P
           + p.rho_P * dst.P + dst.GS + dp.rho_S * st.S + p.rho_S * dst.S)
     if dHtY is not None:
         dB = dB + dHtY
@@ -372,8 +374,9 @@ def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params, dHtY=None):
     dzP = dX - dst.GP / p.rho_P + st.GP * dp.rho_P / p.rho_P ** 2
     P = np.maximum(0.0, zP)
     dP = np.where(zP > 0.0, dzP, 0.0)
-    zT = X - st.GT / p.rho_T
-    dzT = dX - dst.GT / p.rho_T + st.GT * dp.rho_T / p.rho_T ** 2
+    WX, dWX = Ws(X), Ws(dX)
+    zT = WX - st.GT / p.rho_T
+    dzT = dWX - dst.GT / p.rho_T + st.GT * dp.rho_T / p.rho_T ** 2
     tT = p.mu_s / p.rho_T
     dtT = dp.mu_s / p.rho_T - p.mu_s * dp.rho_T / p.rho_T ** 2
     T = soft(zT, tT)
@@ -394,8 +397,8 @@ def _jvp_iteration(prob: Problem, st: State, dst: State, dp: Params, dHtY=None):
     cS, dcS = fw(S), fw(dS)
     GP = st.GP + p.rho_P * (P - X)
     dGP = dst.GP + dp.rho_P * (P - X) + p.rho_P * (dP - dX)
-    GT = st.GT + p.rho_T * (T - X)
-    dGT = dst.GT + dp.rho_T * (T - X) + p.rho_T * (dT - dX)
+    GT = st.GT + p.rho_T * (T - WX)
+    dGT = dst.GT + dp.rho_T * (T - WX) + p.rho_T * (dT - dWX)
     GV = st.GV + p.rho_V * (V - cS)
     dGV = dst.GV + dp.rho_V * (V - cS) + p.rho_V * (dV - dcS)
     GS = st.GS + p.rho_S * (S - X)
@@ -415,8 +418,8 @@ def jvp_run(prob: Problem, K: int, direction, dY=None):
     else:
         a, b, c = (float(v) for v in direction)
         dp = Params(0.0, a, b, c, c, c, c)
-    st = State.zeros(prob.shape)
-    dst = State.zeros(prob.shape)
+    st = prob.zero_state()
+    dst = prob.zero_state()
     dHtY = None if dY is None else prob.HT(np.asarray(dY, np.float64))
     for _ in range(K):
         st, dst = _jvp_iteration(prob, st, dst, dp, dHtY)

@@ -143,8 +143,9 @@ int step_spectral(muffin_ctx* c, bool report, int* nblocks) {
 // state written to `out` (in place when they are the same arrays), X to xo;
 // B_rest (or Z after a fused pass) is the context's and follows the chain of
 // passes.  The reverse sweep runs its forward passes this way, straight into
-// its checkpoints and segment stores.  One spectral basis, Dirac W_s.
-int pass_io(muffin_ctx* c, void* const in[4], void* const out[4], void* xo) {
+// its checkpoints and segment stores.  One spectral basis; in and out hold
+// the four state arrays, then with wavelet bases in W_s their z_b.
+int pass_io(muffin_ctx* c, void* const* in, void* const* out, void* xo) {
     const muffin_shape& s = c->shape;
     if (int rc = row_forward(c)) return rc;
     if (int rc = col_solve(c)) return rc;
@@ -154,6 +155,8 @@ int pass_io(muffin_ctx* c, void* const in[4], void* const out[4], void* xo) {
         HIP_TRY(launch_row_inv(s.dtype, P(c, c->lay.z), xo, s.L * s.ny, s.nx, P(c, c->lay.tw), c->twlog,
                                c->stream, c->row_v));
         if (int rc = step_spectral_io(c, false, nullptr, in, out, xo)) return rc;
+        if (c->lay.n_w)
+            if (int rc = dict_pass_io(c, xo, in + kNumState, out + kNumState)) return rc;
     }
     c->iters++;
     return MUFFIN_OK;
@@ -400,7 +403,8 @@ size_t grad_scratch_bytes(const muffin_ctx* c, int K, int C, bool dirty) {
     if (C > K) C = K;
     const int nseg = (K + C - 1) / C;
     const int nbuf = nseg > 1 ? 2 : 1;
-    const size_t n_arrays = size_t(nseg) * kNumState + size_t(nbuf) * C * (kNumState + 1) + (kNumState + 2) +
+    const int nw = c->lay.n_w, ns = kNumState + nw;     // state arrays per slot
+    const size_t n_arrays = size_t(nseg) * ns + size_t(nbuf) * C * (ns + 1) + (kNumState + 2 + nw) +
                             (dirty ? 1 : 0);
     return n_arrays * state_array_bytes(c) + 2 * grad_nparts(c) * GRAD_NQ * 8 + GRAD_NQ * 8;
 }
@@ -423,15 +427,18 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     const long npix = long(s.ny) * s.nx;
     const size_t nparts = grad_nparts(c);
     const int nbuf = nseg > 1 ? 2 : 1;
-    auto ckpt = [&](int seg, int i) { return g + (size_t(seg) * kNumState + i) * ab; };
-    char* seg0 = g + size_t(nseg) * kNumState * ab;
-    // store b, pass j of the segment, array i (i = 4: X)
-    auto segs = [&](int b, int j, int i) { return seg0 + ((size_t(b) * C + j) * (kNumState + 1) + i) * ab; };
+    // a stored state: the four state arrays, then the z_b of the wavelet bases
+    const int nw = c->lay.n_w, ns = kNumState + nw;
+    auto ckpt = [&](int seg, int i) { return g + (size_t(seg) * ns + i) * ab; };
+    char* seg0 = g + size_t(nseg) * ns * ab;
+    // store b, pass j of the segment, array i (i = ns: X)
+    auto segs = [&](int b, int j, int i) { return seg0 + ((size_t(b) * C + j) * (ns + 1) + i) * ab; };
     // the state before pass j of segment sg in store b: its checkpoint for
     // j = 0 (never overwritten, so not copied into the store)
     auto stv = [&](int b, int sg, int j, int i) { return j == 0 ? ckpt(sg, i) : segs(b, j, i); };
-    char* adj = seg0 + size_t(nbuf) * C * (kNumState + 1) * ab;   // aP, aT, aS, aG, Xb, Bb
-    char* gyac = adj + (kNumState + 2) * ab;
+    // aP, aT, aS, aG, Xb, Bb, then the cotangents of the z_b
+    char* adj = seg0 + size_t(nbuf) * C * (ns + 1) * ab;
+    char* gyac = adj + (kNumState + 2 + nw) * ab;
     double* partials = (double*)(gyac + (gy_out ? ab : 0));
     double* partials1 = partials + nparts * GRAD_NQ;      // step-I sums of a fused launch
     double* acc = partials1 + nparts * GRAD_NQ;
@@ -459,19 +466,21 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     c->iters = 0;
     c->zvalid = 0;
     c->version++;
-    void* ctx_st[4];
+    constexpr int kMaxSt = kNumState + kMaxWavelets;
+    void* ctx_st[kMaxSt];
     for (int i = 0; i < kNumState; ++i) ctx_st[i] = st(c, i);
-    auto set_ptrs = [&](void* dst[4], auto&& loc) {
-        for (int i = 0; i < kNumState; ++i) dst[i] = loc(i);
+    for (int w = 0; w < nw; ++w) ctx_st[kNumState + w] = P(c, c->lay.wz[w]);
+    auto set_ptrs = [&](void* dst[kMaxSt], auto&& loc) {
+        for (int i = 0; i < ns; ++i) dst[i] = loc(i);
     };
     const int blast = (nseg - 1) & (nbuf - 1);
     int rc = MUFFIN_OK;
     HIP_TRY(launch_fill_zero(P(c, c->lay.brest), nb, st_));
-    for (int i = 0; i < kNumState; ++i) HIP_TRY(launch_fill_zero(ckpt(0, i), nb, st_));
+    for (int i = 0; i < ns; ++i) HIP_TRY(launch_fill_zero(ckpt(0, i), nb, st_));
     for (int k = 1; k <= K; ++k) {
         const int seg = (k - 1) / C, j = (k - 1) % C;
         const bool last = seg == nseg - 1;
-        void *in[4], *out[4];
+        void *in[kMaxSt], *out[kMaxSt];
         if (j == 0) set_ptrs(in, [&](int i) -> void* { return ckpt(seg, i); });
         else if (last) set_ptrs(in, [&](int i) -> void* { return segs(blast, j, i); });
         else set_ptrs(in, [&](int i) -> void* { return ctx_st[i]; });
@@ -479,13 +488,15 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         else if (j == C - 1) set_ptrs(out, [&](int i) -> void* { return ckpt(seg + 1, i); });
         else if (last) set_ptrs(out, [&](int i) -> void* { return segs(blast, j + 1, i); });
         else set_ptrs(out, [&](int i) -> void* { return ctx_st[i]; });
-        void* xo = (last && k < K) ? (void*)segs(blast, j, kNumState) : (void*)P(c, c->lay.x);
+        void* xo = (last && k < K) ? (void*)segs(blast, j, ns) : (void*)P(c, c->lay.x);
         if ((rc = pass_io(c, in, out, xo)) != MUFFIN_OK) return rc;
     }
     // X of pass k: its slot, X^K in the context
     auto xloc = [&](int b_, int j_, int k_) -> char* {
-        return k_ == K ? (char*)P(c, c->lay.x) : segs(b_, j_, kNumState);
+        return k_ == K ? (char*)P(c, c->lay.x) : segs(b_, j_, ns);
     };
+    void* wbar[kMaxWavelets];
+    for (int w = 0; w < nw; ++w) wbar[w] = adj + (kNumState + 2 + w) * ab;
     // seed: the cotangent of X^K
     char* Xb = adj + kNumState * ab;
     char* Bb = adj + (kNumState + 1) * ab;
@@ -498,11 +509,14 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         HIP_TRY(copy(Xb, sky_or_gx));
     }
     for (int i = 0; i < kNumState; ++i) HIP_TRY(launch_fill_zero(adj + i * ab, nb, st_));
+    for (int w = 0; w < nw; ++w) HIP_TRY(launch_fill_zero(wbar[w], nb, st_));
     if (gy_out) HIP_TRY(launch_fill_zero(gyac, nb, st_));
 
     const unsigned bb = unsigned(npix * long(elem_size(s)));
     const int gsh = spectral_gshift(bb);
-    const bool fuse_ok = adj_single_descriptor(s.L, bb);
+    // with wavelet bases the step-I adjoint of every pass runs on its own,
+    // after the wavelet part of B-bar's pass
+    const bool fuse_ok = adj_single_descriptor(s.L, bb) && nw == 0;
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int k0 = seg * C, k1 = (k0 + C < K) ? k0 + C : K;
         const int b = seg & (nbuf - 1);
@@ -511,14 +525,19 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
             // from the checkpoint's state)
             HIP_TRY(launch_brest(dt, ckpt(seg, ST_ZP), ckpt(seg, ST_ZT), ckpt(seg, ST_ZV), ckpt(seg, ST_GS),
                                  P(c, c->lay.brest), voxels(s), a, st_, false));
+            if (nw) {
+                void* zc[kMaxWavelets];
+                for (int w = 0; w < nw; ++w) zc[w] = ckpt(seg, kNumState + w);
+                if ((rc = dict_brest_from(c, zc)) != MUFFIN_OK) return rc;
+            }
             c->zvalid = 0;
             for (int k = k0 + 1; k <= k1; ++k) {
                 const int j = k - k0 - 1;
-                void *in[4], *out[4];
+                void *in[kMaxSt], *out[kMaxSt];
                 set_ptrs(in, [&](int i) -> void* { return stv(b, seg, j, i); });
                 const int jo = j + 1 < C ? j + 1 : 0;
                 set_ptrs(out, [&](int i) -> void* { return segs(b, jo, i); });
-                if ((rc = pass_io(c, in, out, segs(b, j, kNumState))) != MUFFIN_OK) return rc;
+                if ((rc = pass_io(c, in, out, segs(b, j, ns))) != MUFFIN_OK) return rc;
             }
         }
         // pass k's step-I adjoint runs inside the band-coupled launch of pass
@@ -559,6 +578,8 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
                                         st_, spectral_dense(s, c->params)));
             if (fused) HIP_TRY(launch_grad_accum(partials1, nbk, acc, st_));
             HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
+            // the wavelet updates of pass k: X-bar += sum_b W_b^T zbar_b
+            if (nw && (rc = dict_adj_x(c, wbar, Xb)) != MUFFIN_OK) return rc;
             // B-bar = Q^{-1} X-bar (Q is symmetric)
             HIP_TRY(launch_row_fwd(dt, dt == MUFFIN_F64, Xb, P(c, c->lay.z), nrows, s.nx, s.ny, false, false,
                                    P(c, c->lay.tw), c->twlog, st_, c->row_v));
@@ -572,6 +593,14 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
                 HIP_TRY(launch_adj_step1(dt, Bb, A.zP, A.zT, A.zV, A.GS, A.X, A.aP, A.aT, A.aS, A.aG, npix, s.L, a,
                                          partials, &nbk, st_));
                 HIP_TRY(launch_grad_accum(partials, nbk, acc, st_));
+            }
+            if (nw) {
+                // the cotangents of the z_b before pass k: through their update
+                // (clip) and through step I of pass k (B_rest), at the state
+                // before it
+                void* zs[kMaxWavelets];
+                for (int w = 0; w < nw; ++w) zs[w] = stv(b, seg, j, kNumState + w);
+                if ((rc = dict_adj_b(c, Bb, wbar, zs, acc)) != MUFFIN_OK) return rc;
             }
         }
     }
@@ -598,7 +627,8 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         }
     }
     const muffin_params& p = c->params;
-    const double rT = h[G_RHO_T] - h[G_TAU_T] * p.mu_s / (p.rho_T * p.rho_T) + h[G_RHO_Q];
+    // rho of eq. Qlsimp counts n_s rho_T
+    const double rT = h[G_RHO_T] - h[G_TAU_T] * p.mu_s / (p.rho_T * p.rho_T) + p.n_s * h[G_RHO_Q];
     const double rV = h[G_RHO_V] - h[G_TAU_V] * p.mu_nu / (p.rho_V * p.rho_V);
     const double rP = h[G_RHO_P] + h[G_RHO_Q];
     const double rS = h[G_RHO_S] + h[G_RHO_Q];
@@ -620,10 +650,6 @@ int grad_args(const muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx,
               const char* what) {
     if (int rc = check_ctx(c)) return rc;
     if (int rc = vis_unsupported(c, what)) return rc;
-    if (c->lay.n_w) {
-        set_error("%s: not built for a spatial dictionary with wavelet bases (n_s = %d)", what, c->params.n_s);
-        return MUFFIN_EUNSUPPORTED;
-    }
     if (c->shape.L > 128) {
         set_error("%s: the reverse sweep is built for band counts up to 128 (L = %d)", what, c->shape.L);
         return MUFFIN_EUNSUPPORTED;

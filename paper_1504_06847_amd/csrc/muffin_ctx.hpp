@@ -105,6 +105,17 @@ int dict_reencode(muffin_ctx* c, double ratio, double tau);
 // reporting pass with wavelet bases: sums[0..2] (r^2, E, ||T||^2 parts) and
 // the report kernel's cubes; after it, sum_b ||W_b max(0, z_P)||_1 into *sum1
 int dict_report_pre(muffin_ctx* c, double* sums);
+// steps III and VI of every wavelet basis out of place (X given, z_b read
+// from zin[b], written to zout[b]) and their B_rest terms from zout
+int dict_pass_io(muffin_ctx* c, const void* X, void* const* zin, void* const* zout);
+// the B_rest terms of the wavelet bases from the cubes z[b], added to B_rest
+int dict_brest_from(muffin_ctx* c, void* const* z);
+// reverse sweep: X-bar += sum_b W_b^T zbar_b (zbar_b the cotangent of z_b
+// after a pass)
+int dict_adj_x(muffin_ctx* c, void* const* zbar, void* Xb);
+// reverse sweep, after B-bar of the pass: zbar_b <- the cotangent of z_b
+// before the pass (zs[b] the state's z_b then), tau_T and rho_T sums into acc
+int dict_adj_b(muffin_ctx* c, const void* Bb, void* const* zbar, void* const* zs, double* acc);
 int dict_report_l1(muffin_ctx* c, const void* zP, double* sum1);
 
 // a cube context (not NULL, not a batch context)

@@ -148,7 +148,7 @@ DwtLevel dict_level(muffin_ctx* c, const DictGeom& G, int b0, int n) {
 int dict_analysis(muffin_ctx* c, const DictGeom& G, DwtLevel A, int b0, const void* in, long* pos) {
     const muffin_shape& s = c->shape;
     const int J = c->lay.levels;
-    const int nq = A.mode == 1 ? 3 : 1;
+    const int nq = A.mode == 1 ? 3 : (A.mode == 3 ? GRAD_NQ : 1);
     for (int j = 0; j < J; ++j) {
         A.sy = s.ny >> j;
         A.sx = s.nx >> j;
@@ -213,9 +213,76 @@ int dict_run(muffin_ctx* c, bool update) {
     return dict_synthesis(c, G, A, 0, P(c, c->lay.brest), c->params.rho_T);
 }
 
+// The base and element stride of the n_w cubes at p[0 .. n_w - 1], which
+// the all-bases launches need evenly spaced.
+int spaced(muffin_ctx* c, void* const* p, void** base, long* stride) {
+    const int nw = c->lay.n_w;
+    const long es = long(elem_size(c->shape));
+    *base = p[0];
+    *stride = nw > 1 ? long(((char*)p[1] - (char*)p[0]) / es) : 0L;
+    for (int b = 1; b < nw; ++b)
+        if ((char*)p[b] - (char*)p[0] != b * *stride * es) {
+            set_error("the wavelet coefficient cubes of a sweep slot are not evenly spaced");
+            return MUFFIN_EDEVICE;
+        }
+    return MUFFIN_OK;
+}
+
 }  // namespace
 
+static_assert(GRAD_NQ <= kWPartQ, "wavelet work-group sums");
+
 int dict_pass(muffin_ctx* c) { return dict_run(c, true); }
+
+int dict_pass_io(muffin_ctx* c, const void* X, void* const* zin, void* const* zout) {
+    DictGeom G;
+    if (int rc = dict_geom(c, G)) return rc;
+    DwtLevel A = dict_level(c, G, 0, c->lay.n_w);
+    void *zi, *zo;
+    if (int rc = spaced(c, zin, &zi, &A.zstride)) return rc;
+    if (int rc = spaced(c, zout, &zo, &A.zostride)) return rc;
+    A.z0 = zi;
+    A.zo0 = zo == zi ? nullptr : zo;
+    if (int rc = dict_analysis(c, G, A, 0, X, nullptr)) return rc;
+    return dict_brest_from(c, zout);
+}
+
+int dict_brest_from(muffin_ctx* c, void* const* z) {
+    DictGeom G;
+    if (int rc = dict_geom(c, G)) return rc;
+    DwtLevel A = dict_level(c, G, 0, c->lay.n_w);
+    void* zb;
+    if (int rc = spaced(c, z, &zb, &A.zstride)) return rc;
+    A.z0 = zb;
+    return dict_synthesis(c, G, A, 0, P(c, c->lay.brest), c->params.rho_T);
+}
+
+int dict_adj_x(muffin_ctx* c, void* const* zbar, void* Xb) {
+    DictGeom G;
+    if (int rc = dict_geom(c, G)) return rc;
+    DwtLevel A = dict_level(c, G, 0, c->lay.n_w);
+    void* zb;
+    if (int rc = spaced(c, zbar, &zb, &A.zstride)) return rc;
+    A.z0 = zb;
+    A.mode = 1;              // the cotangents as they are
+    return dict_synthesis(c, G, A, 0, Xb, 1.0);
+}
+
+int dict_adj_b(muffin_ctx* c, const void* Bb, void* const* zbar, void* const* zs, double* acc) {
+    DictGeom G;
+    if (int rc = dict_geom(c, G)) return rc;
+    DwtLevel A = dict_level(c, G, 0, c->lay.n_w);
+    void *zb, *sb;
+    if (int rc = spaced(c, zbar, &zb, &A.zstride)) return rc;
+    if (int rc = spaced(c, zs, &sb, &A.sstride)) return rc;
+    A.z0 = zb;
+    A.s0 = sb;
+    A.mode = 3;
+    long pos = 0;
+    if (int rc = dict_analysis(c, G, A, 0, Bb, &pos)) return rc;
+    HIP_TRY(launch_grad_accum((const double*)P(c, c->lay.wpart), int(pos), acc, c->stream));
+    return MUFFIN_OK;
+}
 int dict_brest(muffin_ctx* c) { return dict_run(c, false); }
 
 // A reporting pass, before steps II-VI: steps III and VI of every wavelet

@@ -318,9 +318,16 @@ struct DwtLevel {
     // - clip(z_b'))^2 + d_b^2) and soft(z_b')^2 to partials; 2 z_b untouched,
     // the sum of |c| per work-group to partials.  Synthesis: the coefficient
     // function, 0 u = 2 soft(z, tau) - z, 1 z itself, 2 -clip(z, tau)
+    // 3 the adjoint of the update: z_b holds its cotangent after the pass,
+    // overwritten with the one before it; the state's z_b before the pass
+    // at s0 (stride sstride); GRAD_NQ sums per work-group (tau_T, rho_T)
     int mode = 0;
     void* d0 = nullptr;
     long dstride = 0;
+    void* zo0 = nullptr;     // mode 0: the updated z_b to here (stride zostride) instead of in place
+    long zostride = 0;
+    const void* s0 = nullptr;
+    long sstride = 0;
     double* partials = nullptr;
     double rho_T = 0.0;
     double scale = 1.0;      // the finest synthesis: out0 += scale * (sum over the bases)

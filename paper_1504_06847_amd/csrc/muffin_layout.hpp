@@ -16,6 +16,9 @@ constexpr int kMaxWavelets = 8;  // Db1..Db8 beside the Dirac basis
 constexpr int kMaxDwtLevels = 4;
 // coefficients per sub-band of one DWT work-group tile (rows, columns)
 constexpr int kDwtTileY = 16, kDwtTileX = 32;
+// FP64 sums per work-group of a wavelet launch, at most (report: 3, the
+// reverse sweep: one per gradient slot)
+constexpr int kWPartQ = 8;
 constexpr int kMaxSpectral = MUFFIN_MAX_SPECTRAL;
 
 struct Layout {
@@ -32,7 +35,8 @@ struct Layout {
     size_t wfilt;
     // a reporting pass with wavelet bases: three cubes (soft(z_b') -
     // soft(z_b) of the basis in hand, rho_T W^T dT and W^T Gamma_T summed
-    // over the bases) and FP64 block sums of every analysis launch
+    // over the bases) and FP64 block sums of every analysis launch (also
+    // the reverse sweep's)
     size_t wrep[3], wpart;
     long wblocks;
     int n_w, levels;

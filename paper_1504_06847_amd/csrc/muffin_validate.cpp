@@ -194,9 +194,9 @@ Layout make_layout(const muffin_shape* s, int n_s, int n_nu) {
             lay.wtmp[b][j] = take(size_t(s->L) * size_t(s->ny >> j) * size_t(s->nx >> j) * sz);
     if (lay.n_w) {
         for (int i = 0; i < 3; ++i) lay.wrep[i] = take(V * sz);
-        // the analysis launches of every basis and level, three sums per block
+        // the analysis launches of every basis and level, up to kWPartQ sums per block
         for (int j = 0; j < lay.levels; ++j) lay.wblocks += dwt_tiles(s->ny >> j, s->nx >> j) * s->L * lay.n_w;
-        lay.wpart = take(size_t(lay.wblocks) * 3 * 8);
+        lay.wpart = take(size_t(lay.wblocks) * kWPartQ * 8);
     }
     lay.z = take(HS * 2 * sz);
     lay.yf = take(HS * 2 * sz);

@@ -107,10 +107,12 @@ __device__ __forceinline__ FwdItem fwd_item(int oty, int otx) {
 }
 
 // The coefficients the item updates (zq[r][sub-band]; the LL one only at
-// the last level), loaded ahead of the tile so that their latency overlaps it.
+// the last level), and with MODE 3 the state's at the same places (sq),
+// loaded ahead of the tile so that their latency overlaps it.
 template <typename T, int MODE>
-__device__ __forceinline__ void fwd_load_z(const T* __restrict__ zb, int ld, bool last, int sy, int sx,
-                                           const FwdItem& it, T (&zq)[DWT_IB][4]) {
+__device__ __forceinline__ void fwd_load_z(const T* __restrict__ zb, const T* __restrict__ zs, int ld, bool last,
+                                           int sy, int sx, const FwdItem& it, T (&zq)[DWT_IB][4],
+                                           T (&sq)[DWT_IB][4]) {
     if (MODE == 2 || !it.on) return;
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
@@ -122,7 +124,28 @@ __device__ __forceinline__ void fwd_load_z(const T* __restrict__ zb, int ld, boo
         zq[r][1] = zb[(hy + gi) * ld + gm];
         zq[r][2] = zb[(hy + gi) * ld + hx + gm];
         zq[r][3] = last ? zb[gi * ld + gm] : T(0);
+        if constexpr (MODE == 3) {
+            sq[r][0] = zs[gi * ld + hx + gm];
+            sq[r][1] = zs[(hy + gi) * ld + gm];
+            sq[r][2] = zs[(hy + gi) * ld + hx + gm];
+            sq[r][3] = last ? zs[gi * ld + gm] : T(0);
+        }
     }
+}
+
+// The adjoint of one coefficient (MODE 3): zb the cotangent of z_b after the
+// pass, s the state's z_b before it, c the coefficient of W_b B-bar.  The
+// pass maps z_b to W_b X + clip(z_b) and its step I reads rho_T W_b^T
+// (2 soft(z_b) - z_b), so the cotangent of z_b before the pass is
+// clip'(s) zb + rho_T (2 soft'(s) - 1) c; tau_T gains
+// sgn(s) 1[|s| > tau] (zb - 2 rho_T c), rho_T gains c (2 soft(s) - s).
+template <typename T>
+__device__ __forceinline__ T wadj(T zb, T s, T c, T tau, T rT, WStats& st) {
+    const bool out = fabs(s) > tau;
+    const T sg = s > T(0) ? T(1) : (s < T(0) ? T(-1) : T(0));
+    st.r2 += double(out ? sg * (zb - T(2) * rT * c) : T(0));
+    st.e += double(c * (T(2) * wsoft(s, tau) - s));
+    return (out ? T(0) : zb) + (out ? rT : -rT) * c;
 }
 
 // Stage the image rows and columns an analysis tile with filters of up to
@@ -146,15 +169,17 @@ __device__ __forceinline__ void fwd_stage(const T* __restrict__ src, int in_ld, 
 // adjacent coefficient rows of one column (all four sub-bands) from
 // 2 DWT_IB + K - 2 values of each row image, so each staged value is read a
 // few times instead of K.  Each output's taps are summed in k order.
-// MODE 0: update z_b; 1: update, soft(z_b') - soft(z_b) to db and the
-// report terms into st; 2: no z_b access, sum |c| (LL at the last level
-// included) into st.r2.  Starts and ends between barriers: the caller
+// MODE 0: z_b <- c + clip(z_b) (written to zo: zb itself, or another cube
+// of the same layout); 1: the same in place, soft(z_b') - soft(z_b) to db
+// and the report terms into st; 2: no z_b access, sum |c| (LL at the last
+// level included) into st.r2; 3: the adjoint (wadj) in place, with the
+// state's z_b in sq.  Starts and ends between barriers: the caller
 // synchronises after the staging and before the next tile's row pass.
 template <typename T, int K, int MODE>
-__device__ __forceinline__ void dwt_fwd_tile(T* __restrict__ zb, int ld, T* __restrict__ llb, int sy, int sx,
-                                             const T (&h)[K], const T (&g)[K], T tau, T* smem,
+__device__ __forceinline__ void dwt_fwd_tile(T* __restrict__ zb, T* __restrict__ zo, int ld, T* __restrict__ llb,
+                                             int sy, int sx, const T (&h)[K], const T (&g)[K], T tau, T* smem,
                                              T* __restrict__ db, T rT, WStats& st, const FwdItem& it,
-                                             const T (&zq)[DWT_IB][4]) {
+                                             const T (&zq)[DWT_IB][4], const T (&sq)[DWT_IB][4]) {
     constexpr int NV = 2 * DWT_MB + K - 2, NR = 2 * DWT_IB + K - 2;
     const T* tin = smem;
     T* rl = smem + DWT_HMY * DWT_HMX;
@@ -208,11 +233,19 @@ __device__ __forceinline__ void dwt_fwd_tile(T* __restrict__ zb, int ld, T* __re
         }
         const long gi = i0 + ci + r, gm = m0 + cm;
         if constexpr (MODE == 0) {
-            zb[gi * ld + hx + gm] = bx + wclip(zq[r][0], tau);               // x high, y low
-            zb[(hy + gi) * ld + gm] = by + wclip(zq[r][1], tau);             // x low, y high
-            zb[(hy + gi) * ld + hx + gm] = d + wclip(zq[r][2], tau);
+            zo[gi * ld + hx + gm] = bx + wclip(zq[r][0], tau);               // x high, y low
+            zo[(hy + gi) * ld + gm] = by + wclip(zq[r][1], tau);             // x low, y high
+            zo[(hy + gi) * ld + hx + gm] = d + wclip(zq[r][2], tau);
             if (llb) llb[gi * hx + gm] = a;
-            else zb[gi * ld + gm] = a + wclip(zq[r][3], tau);
+            else zo[gi * ld + gm] = a + wclip(zq[r][3], tau);
+            continue;
+        }
+        if constexpr (MODE == 3) {
+            zb[gi * ld + hx + gm] = wadj(zq[r][0], sq[r][0], bx, tau, rT, st);
+            zb[(hy + gi) * ld + gm] = wadj(zq[r][1], sq[r][1], by, tau, rT, st);
+            zb[(hy + gi) * ld + hx + gm] = wadj(zq[r][2], sq[r][2], d, tau, rT, st);
+            if (llb) llb[gi * hx + gm] = a;
+            else zb[gi * ld + gm] = wadj(zq[r][3], sq[r][3], a, tau, rT, st);
             continue;
         }
         if (llb) llb[gi * hx + gm] = a;
@@ -400,17 +433,26 @@ __device__ __forceinline__ void load_taps(const T* __restrict__ fb, T (&h)[K], T
 
 // The work-group's FP64 report sums (MODE 1: 3, MODE 2: 1) into
 // partials[work-group * nq + q].
+// (MODE 3: GRAD_NQ per work-group, the tau_T and rho_T slots filled)
 template <int MODE>
 __device__ __forceinline__ void fwd_sums(const WStats& st, double* partials) {
     if constexpr (MODE != 0) {
         __shared__ double sh[DWT_NTH / 64];
         const long wg = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        constexpr int nq = MODE == 1 ? 3 : 1;
+        constexpr int nq = MODE == 1 ? 3 : (MODE == 2 ? 1 : 2);
         const double v[3] = {st.r2, st.e, st.bz};
+        double out[3];
 #pragma unroll
-        for (int q = 0; q < nq; ++q) {
-            const double sq = block_sum_s<DWT_NTH>(v[q], sh);
-            if (threadIdx.x == 0) partials[wg * nq + q] = sq;
+        for (int q = 0; q < nq; ++q) out[q] = block_sum_s<DWT_NTH>(v[q], sh);
+        if (threadIdx.x == 0) {
+            if constexpr (MODE == 3) {
+                for (int q = 0; q < GRAD_NQ; ++q) partials[wg * GRAD_NQ + q] = 0.0;
+                partials[wg * GRAD_NQ + G_TAU_T] = out[0];
+                partials[wg * GRAD_NQ + G_RHO_T] = out[1];
+            } else {
+#pragma unroll
+                for (int q = 0; q < nq; ++q) partials[wg * nq + q] = out[q];
+            }
         }
     }
 }
@@ -419,8 +461,8 @@ __device__ __forceinline__ void fwd_sums(const WStats& st, double* partials) {
     case KK: {                                                                                   \
         T h[KK], g[KK];                                                                          \
         load_taps<T, KK>(fb, h, g);                                                              \
-        dwt_fwd_tile<T, KK, MODE>(zb, A.ld, llb, A.sy, A.sx, h, g, T(A.tau), smem, db,           \
-                                  T(A.rho_T), st, it, zq);                                       \
+        dwt_fwd_tile<T, KK, MODE>(zb, zo, A.ld, llb, A.sy, A.sx, h, g, T(A.tau), smem, db,       \
+                                  T(A.rho_T), st, it, zq, sq);                                   \
         break;                                                                                   \
     }
 
@@ -435,14 +477,16 @@ __global__ void __launch_bounds__(DWT_NTH, (sizeof(T) == 4 && MODE == 0) ? 6 : 1
     const int b = blockIdx.z - int(band) * A.n;
     const T* src = (const T*)A.in0 + b * A.in_bstride + band * A.in_bs;
     T* zb = MODE == 2 ? nullptr : (T*)A.z0 + b * A.zstride + band * A.z_bs;
+    T* zo = A.zo0 ? (T*)A.zo0 + b * A.zostride + band * A.z_bs : zb;
+    const T* zs = MODE == 3 ? (const T*)A.s0 + b * A.sstride + band * A.z_bs : nullptr;
     T* db = MODE == 1 ? (T*)A.d0 + b * A.dstride + band * A.z_bs : nullptr;
     T* llb = A.ll0 ? (T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
     const T* fb = (const T*)A.ftab + 32 * b;
     const int K = 2 * int((A.kpack >> (4 * b)) & 15u);
     const int hy = A.sy >> 1, hx = A.sx >> 1;
     const FwdItem it = fwd_item(hy < DWT_OTY ? hy : DWT_OTY, hx < DWT_OTX ? hx : DWT_OTX);
-    T zq[DWT_IB][4];
-    fwd_load_z<T, MODE>(zb, A.ld, llb == nullptr, A.sy, A.sx, it, zq);
+    T zq[DWT_IB][4], sq[DWT_IB][4];
+    fwd_load_z<T, MODE>(zb, zs, A.ld, llb == nullptr, A.sy, A.sx, it, zq, sq);
     fwd_stage<T>(src, A.in_ld, A.sy, A.sx, K, smem);
     __syncthreads();
     WStats st;
@@ -469,18 +513,21 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd0_all(DwtLevel A) {
         const int K = 2 * int((A.kpack >> (4 * b)) & 15u);
         kmax = K > kmax ? K : kmax;
     }
-    T zq[DWT_IB][4];
-    fwd_load_z<T, MODE>(MODE == 2 ? nullptr : (const T*)A.z0 + band * A.z_bs, A.ld, A.ll0 == nullptr, A.sy,
-                        A.sx, it, zq);
+    T zq[DWT_IB][4], sq[DWT_IB][4];
+    fwd_load_z<T, MODE>(MODE == 2 ? nullptr : (const T*)A.z0 + band * A.z_bs,
+                        MODE == 3 ? (const T*)A.s0 + band * A.z_bs : nullptr, A.ld, A.ll0 == nullptr, A.sy, A.sx,
+                        it, zq, sq);
     fwd_stage<T>(src, A.in_ld, A.sy, A.sx, kmax, smem);
     __syncthreads();
     WStats st;
     for (int b = 0; b < A.n; ++b) {
         T* zb = MODE == 2 ? nullptr : (T*)A.z0 + b * A.zstride + band * A.z_bs;
+        T* zo = A.zo0 ? (T*)A.zo0 + b * A.zostride + band * A.z_bs : zb;
+        const T* zs = MODE == 3 ? (const T*)A.s0 + b * A.sstride + band * A.z_bs : nullptr;
         T* db = MODE == 1 ? (T*)A.d0 + b * A.dstride + band * A.z_bs : nullptr;
         T* llb = A.ll0 ? (T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
         const T* fb = (const T*)A.ftab + 32 * b;
-        if (b > 0) fwd_load_z<T, MODE>(zb, A.ld, llb == nullptr, A.sy, A.sx, it, zq);
+        if (b > 0) fwd_load_z<T, MODE>(zb, zs, A.ld, llb == nullptr, A.sy, A.sx, it, zq, sq);
         switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
             MUFFIN_DWT_K_CASES(MUFFIN_DWT_FWD_CASE)
             default: break;
@@ -613,18 +660,21 @@ static void fwd_all_t(const DwtLevel& A, dim3 grid, hipStream_t s) {
     if (FINEST) {
         if (A.mode == 1) hipLaunchKernelGGL((k_dwt_fwd0_all<T, 1>), grid, dim3(DWT_NTH), 0, s, A);
         else if (A.mode == 2) hipLaunchKernelGGL((k_dwt_fwd0_all<T, 2>), grid, dim3(DWT_NTH), 0, s, A);
+        else if (A.mode == 3) hipLaunchKernelGGL((k_dwt_fwd0_all<T, 3>), grid, dim3(DWT_NTH), 0, s, A);
         else hipLaunchKernelGGL((k_dwt_fwd0_all<T, 0>), grid, dim3(DWT_NTH), 0, s, A);
     } else {
         if (A.mode == 1) hipLaunchKernelGGL((k_dwt_fwd_all<T, 1>), grid, dim3(DWT_NTH), 0, s, A);
         else if (A.mode == 2) hipLaunchKernelGGL((k_dwt_fwd_all<T, 2>), grid, dim3(DWT_NTH), 0, s, A);
+        else if (A.mode == 3) hipLaunchKernelGGL((k_dwt_fwd_all<T, 3>), grid, dim3(DWT_NTH), 0, s, A);
         else hipLaunchKernelGGL((k_dwt_fwd_all<T, 0>), grid, dim3(DWT_NTH), 0, s, A);
     }
 }
 
 hipError_t launch_dwt_fwd_all(int dtype, const DwtLevel& A, hipStream_t s, bool finest) {
-    if (!level_ok(A) || A.mode < 0 || A.mode > 2 || !A.in0) return hipErrorInvalidValue;
-    if ((A.mode != 2 && !A.z0) || (A.mode == 1 && !A.d0) || (A.mode != 0 && !A.partials))
+    if (!level_ok(A) || A.mode < 0 || A.mode > 3 || !A.in0) return hipErrorInvalidValue;
+    if ((A.mode != 2 && !A.z0) || (A.mode == 1 && !A.d0) || (A.mode == 3 && !A.s0) || (A.mode != 0 && !A.partials))
         return hipErrorInvalidValue;
+    if (A.zo0 && A.mode != 0) return hipErrorInvalidValue;
     // the finest form reads one image per band (no per-basis input stride)
     if (finest && A.in_bstride != 0) return hipErrorInvalidValue;
     const dim3 grid = dwt_grid(A.sy, A.sx, finest ? A.L : A.n * A.L);

@@ -129,3 +129,36 @@ def test_kkt_certificate_with_wavelet_dictionary():
     nz = np.abs(st.T) > 1e-6
     np.testing.assert_allclose(st.GT[nz], -p.mu_s * np.sign(st.T[nz]), atol=1e-8)
     assert np.abs(st.GT).max() <= p.mu_s + 1e-9
+
+
+def test_tangent_pass_with_wavelet_bases_against_central_differences():
+    """The oracle's forward-mode tangent with wavelet bases in W_s equals
+    central differences of K passes along every parameter alone (mu_eps and
+    rho_T alone check the n_s rho_T of eq. Qlsimp) and along a change of the
+    dirty images (smooth away from the prox kinks at these steps)."""
+    rng = np.random.default_rng(33)
+    L, n = 3, 16
+    psf = np.zeros((L, n, n))
+    for l in range(L):
+        g = np.exp(-((np.arange(n) - n // 2)[:, None] ** 2 + (np.arange(n) - n // 2)[None, :] ** 2)
+                   / (2.0 * (1.2 + 0.3 * l) ** 2))
+        psf[l] = g / g.sum()
+    Y = rng.uniform(-0.1, 1.0, (L, n, n))
+    base = O.Params(1e-3, 0.03, 0.05, 1.1, 0.9, 1.3, 0.8)
+    bases = (0, 1, 3)
+    prob = O.Problem(psf, Y, base, bases=bases)
+    K, h = 5, 1e-6
+    names = ("mu_eps", "mu_s", "mu_nu", "rho_P", "rho_T", "rho_V", "rho_S")
+    for i, name in enumerate(names):
+        d = [0.0] * 7
+        d[i] = 1.0
+        _, dX = O.jvp_run(prob, K, O.Params(*d))
+        xp = O.run(prob.with_params(base.with_(**{name: getattr(base, name) + h})), K).X
+        xm = O.run(prob.with_params(base.with_(**{name: getattr(base, name) - h})), K).X
+        fd = (xp - xm) / (2 * h)
+        assert np.abs(fd - dX).max() <= 1e-6 * max(np.abs(dX).max(), 1e-3), name
+    dY = rng.standard_normal((L, n, n))
+    _, dX = O.jvp_run(prob, K, (0.0, 0.0, 0.0), dY=dY)
+    xp = O.run(O.Problem(psf, Y + h * dY, base, bases=bases), K).X
+    xm = O.run(O.Problem(psf, Y - h * dY, base, bases=bases), K).X
+    assert np.abs((xp - xm) / (2 * h) - dX).max() <= 1e-6 * np.abs(dX).max()
