@@ -233,6 +233,11 @@ def run_dictionary(inst, params, steps, warmup, profile_iters, graph=True):
         nbytes = DICT_ELEMS_PER_BASIS * n_w * 4 * V
         out["dictionary_alg_bytes"] = int(nbytes)
         out["dictionary_GBps"] = round(nbytes / (prof["dictionary"] * 1e-3) / 1e9, 1)
+        # the least any schedule moves: X read once, each z_b read and
+        # written once, B_rest read and written once
+        min_bytes = (3 + 2 * n_w) * 4 * V
+        out["dictionary_min_bytes"] = int(min_bytes)
+        out["dictionary_min_bytes_frac"] = round(min_bytes / (prof["dictionary"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
     return out
 
 

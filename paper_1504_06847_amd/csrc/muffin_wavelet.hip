@@ -41,7 +41,11 @@ constexpr int DWT_NTH = 256;
 
 // LDS of one tile, in elements, for the longest filter (K = 16)
 constexpr int DWT_FWD_LDS = (2 * DWT_OTY + 14) * (2 * DWT_OTX + 14) + 2 * (2 * DWT_OTY + 14) * DWT_OTX;
-constexpr int DWT_INV_LDS = 4 * (DWT_OTY + 7) * (DWT_OTX + 7) + 2 * (2 * DWT_OTY) * (DWT_OTX + 7);
+// row stride of the row synthesis's output in LDS: at least the tile's
+// coefficient columns and 1 modulo 4, so that the column synthesis's reads
+// (8 lanes per row, 4 columns apart) fall in distinct banks across rows
+constexpr int dwt_xstride(int H2) { return DWT_OTX + H2 + ((1 - (DWT_OTX + H2)) & 3); }
+constexpr int DWT_INV_LDS = 4 * (DWT_OTY + 7) * (DWT_OTX + 7) + 2 * (2 * DWT_OTY) * dwt_xstride(7);
 
 template <typename T> __device__ __forceinline__ T wclip(T z, T t) { return z > t ? t : (z < -t ? -t : z); }
 template <typename T> __device__ __forceinline__ T wsoft(T z, T t) {
@@ -90,6 +94,26 @@ __device__ __forceinline__ T wstat(T z, T zn, T tau, T rT, WStats& st) {
 // MODE 0: update z_b; 1: update, soft(z_b') - soft(z_b) to db and the
 // report terms into st; 2: no z_b access, sum |c| (LL at the last level
 // included) into st.r2.
+// The tile (x, y) and slice z of this work-group.  Work-groups go to the 8
+// XCDs in turn (their linear id modulo 8), each XCD with its own L2; the
+// tiles are renumbered so that each XCD takes one contiguous run of them,
+// and neighbouring tiles, whose reads share the lines of their halos, meet
+// in one L2.
+struct Tile {
+    int x, y, z;
+};
+__device__ __forceinline__ Tile xcd_tile() {
+    const unsigned gx = gridDim.x, gy = gridDim.y, n = gx * gy * gridDim.z;
+    unsigned l = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+    if ((n & 7u) == 0) l = (l & 7u) * (n >> 3) + (l >> 3);
+    Tile t;
+    t.x = int(l % gx);
+    l /= gx;
+    t.y = int(l % gy);
+    t.z = int(l / gy);
+    return t;
+}
+
 constexpr int DWT_MB = 4;
 constexpr int DWT_IB = 2;
 // LDS of an analysis tile: the staged image (row stride for the longest
@@ -111,12 +135,12 @@ __device__ __forceinline__ FwdItem fwd_item(int oty, int otx) {
 // loaded ahead of the tile so that their latency overlaps it.
 template <typename T, int MODE>
 __device__ __forceinline__ void fwd_load_z(const T* __restrict__ zb, const T* __restrict__ zs, int ld, bool last,
-                                           int sy, int sx, const FwdItem& it, T (&zq)[DWT_IB][4],
+                                           int sy, int sx, const Tile& tl, const FwdItem& it, T (&zq)[DWT_IB][4],
                                            T (&sq)[DWT_IB][4]) {
     if (MODE == 2 || !it.on) return;
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
-    const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
+    const int i0 = tl.y * oty, m0 = tl.x * otx;
 #pragma unroll
     for (int r = 0; r < DWT_IB; ++r) {
         const long gi = i0 + it.ci + r, gm = m0 + it.cm;
@@ -151,10 +175,11 @@ __device__ __forceinline__ T wadj(T zb, T s, T c, T tau, T rT, WStats& st) {
 // Stage the image rows and columns an analysis tile with filters of up to
 // K taps needs (periodic halo of K - 2 below and right) into tin.
 template <typename T>
-__device__ __forceinline__ void fwd_stage(const T* __restrict__ src, int in_ld, int sy, int sx, int K, T* tin) {
+__device__ __forceinline__ void fwd_stage(const T* __restrict__ src, int in_ld, int sy, int sx, int K, const Tile& tl,
+                                          T* tin) {
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
-    const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
+    const int i0 = tl.y * oty, m0 = tl.x * otx;
     const int HY = 2 * oty + K - 2, HX = 2 * otx + K - 2;
     for (int e = threadIdx.x; e < HY * HX; e += DWT_NTH) {
         const int r = e / HX, c = e - r * HX;
@@ -178,15 +203,16 @@ __device__ __forceinline__ void fwd_stage(const T* __restrict__ src, int in_ld, 
 template <typename T, int K, int MODE>
 __device__ __forceinline__ void dwt_fwd_tile(T* __restrict__ zb, T* __restrict__ zo, int ld, T* __restrict__ llb,
                                              int sy, int sx, const T (&h)[K], const T (&g)[K], T tau, T* smem,
-                                             T* __restrict__ db, T rT, WStats& st, const FwdItem& it,
-                                             const T (&zq)[DWT_IB][4], const T (&sq)[DWT_IB][4]) {
+                                             T* __restrict__ db, T rT, WStats& st, const Tile& tl,
+                                             const FwdItem& it, const T (&zq)[DWT_IB][4],
+                                             const T (&sq)[DWT_IB][4]) {
     constexpr int NV = 2 * DWT_MB + K - 2, NR = 2 * DWT_IB + K - 2;
     const T* tin = smem;
     T* rl = smem + DWT_HMY * DWT_HMX;
     T* rh = rl + DWT_HMY * DWT_OTX;
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
-    const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
+    const int i0 = tl.y * oty, m0 = tl.x * otx;
     const int HY = 2 * oty + K - 2;
     // along x: row r, outputs mb .. mb + DWT_MB - 1 (a tile narrower than
     // DWT_MB reads past its columns inside the LDS array and keeps only its own)
@@ -295,10 +321,10 @@ __device__ __forceinline__ bool inv_out(int oty, int otx, int& rr, int& c0, int&
 constexpr int DWT_PF = ((DWT_OTY + 7) * (DWT_OTX + 7) + DWT_NTH - 1) / DWT_NTH;
 template <typename T>
 __device__ __forceinline__ void inv_fetch(const T* __restrict__ llb, const T* __restrict__ zb, int ld, int sy,
-                                          int sx, int H2, T (&pf)[DWT_PF][4]) {
+                                          int sx, int H2, const Tile& tl, T (&pf)[DWT_PF][4]) {
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
-    const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
+    const int i0 = tl.y * oty, m0 = tl.x * otx;
     const int CY = oty + H2, CX = otx + H2;
 #pragma unroll
     for (int j = 0; j < DWT_PF; ++j) {
@@ -360,8 +386,9 @@ __device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], co
     const T* cbx = ca + CMY * CM;
     const T* cby = cbx + CMY * CM;
     const T* cd = cby + CMY * CM;
+    constexpr int CMX = dwt_xstride(H2);
     T* xl = smem + 4 * CMY * CM;
-    T* xh = xl + 2 * DWT_OTY * CM;
+    T* xh = xl + 2 * DWT_OTY * CMX;
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int CX = otx + H2;
@@ -388,8 +415,8 @@ __device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], co
                     lo += h[2 * kk + p] * va[t] + g[2 * kk + p] * vby[t];
                     hi += h[2 * kk + p] * vbx[t] + g[2 * kk + p] * vd[t];
                 }
-                xl[(2 * (rb + r) + p) * CM + q] = lo;
-                xh[(2 * (rb + r) + p) * CM + q] = hi;
+                xl[(2 * (rb + r) + p) * CMX + q] = lo;
+                xh[(2 * (rb + r) + p) * CMX + q] = hi;
             }
     }
     __syncthreads();
@@ -403,8 +430,8 @@ __device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], co
         T ul[NX], uh[NX];
 #pragma unroll
         for (int t = 0; t < NX; ++t) {
-            ul[t] = xl[rr * CM + cb + t];
-            uh[t] = xh[rr * CM + cb + t];
+            ul[t] = xl[rr * CMX + cb + t];
+            uh[t] = xh[rr * CMX + cb + t];
         }
 #pragma unroll
         for (int c = 0; c < DWT_C2; ++c)
@@ -462,7 +489,7 @@ __device__ __forceinline__ void fwd_sums(const WStats& st, double* partials) {
         T h[KK], g[KK];                                                                          \
         load_taps<T, KK>(fb, h, g);                                                              \
         dwt_fwd_tile<T, KK, MODE>(zb, zo, A.ld, llb, A.sy, A.sx, h, g, T(A.tau), smem, db,       \
-                                  T(A.rho_T), st, it, zq, sq);                                   \
+                                  T(A.rho_T), st, tl, it, zq, sq);                               \
         break;                                                                                   \
     }
 
@@ -471,10 +498,11 @@ __device__ __forceinline__ void fwd_sums(const WStats& st, double* partials) {
 template <typename T, int MODE>
 __global__ void __launch_bounds__(DWT_NTH, (sizeof(T) == 4 && MODE == 0) ? 6 : 1) k_dwt_fwd_all(DwtLevel A) {
     __shared__ T smem[DWT_FWD_LDS];
-    // blockIdx.z = band * n + basis: the bases of one band run side by side,
-    // so the re-reads of its image hit the caches
-    const long band = blockIdx.z / A.n;
-    const int b = blockIdx.z - int(band) * A.n;
+    // slice z = band * n + basis: the bases of one band run side by side, so
+    // the re-reads of its image hit the caches
+    const Tile tl = xcd_tile();
+    const long band = tl.z / A.n;
+    const int b = tl.z - int(band) * A.n;
     const T* src = (const T*)A.in0 + b * A.in_bstride + band * A.in_bs;
     T* zb = MODE == 2 ? nullptr : (T*)A.z0 + b * A.zstride + band * A.z_bs;
     T* zo = A.zo0 ? (T*)A.zo0 + b * A.zostride + band * A.z_bs : zb;
@@ -486,8 +514,8 @@ __global__ void __launch_bounds__(DWT_NTH, (sizeof(T) == 4 && MODE == 0) ? 6 : 1
     const int hy = A.sy >> 1, hx = A.sx >> 1;
     const FwdItem it = fwd_item(hy < DWT_OTY ? hy : DWT_OTY, hx < DWT_OTX ? hx : DWT_OTX);
     T zq[DWT_IB][4], sq[DWT_IB][4];
-    fwd_load_z<T, MODE>(zb, zs, A.ld, llb == nullptr, A.sy, A.sx, it, zq, sq);
-    fwd_stage<T>(src, A.in_ld, A.sy, A.sx, K, smem);
+    fwd_load_z<T, MODE>(zb, zs, A.ld, llb == nullptr, A.sy, A.sx, tl, it, zq, sq);
+    fwd_stage<T>(src, A.in_ld, A.sy, A.sx, K, tl, smem);
     __syncthreads();
     WStats st;
     switch (K) {
@@ -504,7 +532,8 @@ __global__ void __launch_bounds__(DWT_NTH, (sizeof(T) == 4 && MODE == 0) ? 6 : 1
 template <typename T, int MODE>
 __global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd0_all(DwtLevel A) {
     __shared__ T smem[DWT_FWD_LDS];
-    const long band = blockIdx.z;
+    const Tile tl = xcd_tile();
+    const long band = tl.z;
     const T* src = (const T*)A.in0 + band * A.in_bs;
     const int hy = A.sy >> 1, hx = A.sx >> 1;
     const FwdItem it = fwd_item(hy < DWT_OTY ? hy : DWT_OTY, hx < DWT_OTX ? hx : DWT_OTX);
@@ -516,8 +545,8 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd0_all(DwtLevel A) {
     T zq[DWT_IB][4], sq[DWT_IB][4];
     fwd_load_z<T, MODE>(MODE == 2 ? nullptr : (const T*)A.z0 + band * A.z_bs,
                         MODE == 3 ? (const T*)A.s0 + band * A.z_bs : nullptr, A.ld, A.ll0 == nullptr, A.sy, A.sx,
-                        it, zq, sq);
-    fwd_stage<T>(src, A.in_ld, A.sy, A.sx, kmax, smem);
+                        tl, it, zq, sq);
+    fwd_stage<T>(src, A.in_ld, A.sy, A.sx, kmax, tl, smem);
     __syncthreads();
     WStats st;
     for (int b = 0; b < A.n; ++b) {
@@ -527,7 +556,7 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd0_all(DwtLevel A) {
         T* db = MODE == 1 ? (T*)A.d0 + b * A.dstride + band * A.z_bs : nullptr;
         T* llb = A.ll0 ? (T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
         const T* fb = (const T*)A.ftab + 32 * b;
-        if (b > 0) fwd_load_z<T, MODE>(zb, zs, A.ld, llb == nullptr, A.sy, A.sx, it, zq, sq);
+        if (b > 0) fwd_load_z<T, MODE>(zb, zs, A.ld, llb == nullptr, A.sy, A.sx, tl, it, zq, sq);
         switch (2 * int((A.kpack >> (4 * b)) & 15u)) {
             MUFFIN_DWT_K_CASES(MUFFIN_DWT_FWD_CASE)
             default: break;
@@ -540,12 +569,13 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd0_all(DwtLevel A) {
 #undef MUFFIN_DWT_FWD_CASE
 
 // One synthesis level (not the finest) of every basis and band into the
-// bases' dense scratch images: blockIdx.z = basis * L + band.
+// bases' dense scratch images: slice z = basis * L + band.
 template <typename T, int CF>
 __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     __shared__ T smem[DWT_INV_LDS];
-    const int b = blockIdx.z / A.L;
-    const long band = blockIdx.z - b * A.L;
+    const Tile tl = {int(blockIdx.x), int(blockIdx.y), int(blockIdx.z)};
+    const int b = tl.z / A.L;
+    const long band = tl.z - b * A.L;
     const T* zb = (const T*)A.z0 + b * A.zstride + band * A.z_bs;
     const T* llb = A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * long(A.sy / 2) * (A.sx / 2) : nullptr;
     T* ob = (T*)A.out0 + b * A.outstride + band * long(A.sy) * A.sx;
@@ -554,7 +584,7 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     const int K = 2 * int((A.kpack >> (4 * b)) & 15u);
     {
         T pf[DWT_PF][4];
-        inv_fetch<T>(llb, zb, A.ld, A.sy, A.sx, K / 2 - 1, pf);
+        inv_fetch<T>(llb, zb, A.ld, A.sy, A.sx, K / 2 - 1, tl, pf);
         inv_commit<T, CF>(pf, llb != nullptr, A.sy, A.sx, K / 2 - 1, T(A.tau), smem);
     }
     __syncthreads();
@@ -574,7 +604,7 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     int rr, c0, n;
     if (inv_out(oty, otx, rr, c0, n)) {
-        T* o = ob + long(2 * blockIdx.y * oty + rr) * A.sx + 2 * blockIdx.x * otx + c0;
+        T* o = ob + long(2 * tl.y * oty + rr) * A.sx + 2 * tl.x * otx + c0;
 #pragma unroll
         for (int c = 0; c < 2 * DWT_C2; ++c)
             if (c < n) o[c] = acc[c];
@@ -584,15 +614,16 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
 // The finest synthesis level of every basis, summed and added into out
 // ([L][sy][sx], row stride sx): out += scale * sum_b x_b, the bases in
 // order inside the work-group, so out is read and written once and the sum
-// has a fixed order.  blockIdx.z = band.
+// has a fixed order.  Slice z = band.
 template <typename T, int CF>
 __global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 4 : 3) k_dwt_inv0_all(DwtLevel A) {
     __shared__ T smem[DWT_INV_LDS];
-    const long band = blockIdx.z;
+    const Tile tl = xcd_tile();
+    const long band = tl.z;
     const long vb = long(A.sy) * A.sx;
     const int hy = A.sy >> 1, hx = A.sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
-    const int i0 = blockIdx.y * oty, m0 = blockIdx.x * otx;
+    const int i0 = tl.y * oty, m0 = tl.x * otx;
     T* ob = (T*)A.out0 + band * vb;
     // the outputs, loaded first so that their latency overlaps the tiles
     int rr, c0, n;
@@ -609,12 +640,12 @@ __global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 4 : 3) k_dwt_inv0_al
     auto llb_of = [&](int b) { return A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * (vb / 4) : nullptr; };
     auto k_of = [&](int b) { return 2 * int((A.kpack >> (4 * b)) & 15u); };
     T pf[DWT_PF][4];
-    inv_fetch<T>(llb_of(0), zb_of(0), A.ld, A.sy, A.sx, k_of(0) / 2 - 1, pf);
+    inv_fetch<T>(llb_of(0), zb_of(0), A.ld, A.sy, A.sx, k_of(0) / 2 - 1, tl, pf);
     for (int b = 0; b < A.n; ++b) {
         const int K = k_of(b);
         inv_commit<T, CF>(pf, A.ll0 != nullptr, A.sy, A.sx, K / 2 - 1, T(A.tau), smem);
         __syncthreads();
-        if (b + 1 < A.n) inv_fetch<T>(llb_of(b + 1), zb_of(b + 1), A.ld, A.sy, A.sx, k_of(b + 1) / 2 - 1, pf);
+        if (b + 1 < A.n) inv_fetch<T>(llb_of(b + 1), zb_of(b + 1), A.ld, A.sy, A.sx, k_of(b + 1) / 2 - 1, tl, pf);
         const T* fb = (const T*)A.ftab + 32 * b;
         switch (K) {
 #define F(KK)                                                                              \
