@@ -279,6 +279,24 @@ int muffin_grad_params(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_o
 int muffin_grad_dirty(muffin_ctx* ctx, int K, int ckpt_every, const void* sky_or_gx, int mode,
                       double* loss, void* gy_out);
 
+/* The reverse sweep in two halves, for callers that need x_K before they
+   know its cotangent (an autograd forward, then its backward):
+   muffin_grad_record runs the K forward passes from the all-zero state with
+   checkpoints every ckpt_every into the attached workspace
+   (muffin_grad_workspace_bytes(ctx, K, ckpt_every, dirty) bytes), leaving
+   the context after K passes (x_K readable with muffin_get_x);
+   muffin_grad_replay then runs the reverse half: loss as muffin_grad, grad
+   as muffin_grad_params (host double[7]), and with a record taken with
+   dirty = 1 the cotangent of the dirty images to gy_out as
+   muffin_grad_dirty (NULL otherwise).  Together they compute what one
+   muffin_grad_params / muffin_grad_dirty call computes, running each
+   forward pass once.  A replay consumes the record; any pass, state or
+   parameter change, or another workspace in between, voids it (EINVAL).
+   Errors as muffin_grad. */
+int muffin_grad_record(muffin_ctx* ctx, int K, int ckpt_every, int dirty);
+int muffin_grad_replay(muffin_ctx* ctx, const void* sky_or_gx, int mode, double* loss, double grad[7],
+                       void* gy_out);
+
 /* Bytes of one state snapshot: the iteration's carried arrays (the prox
    inputs z_P and z_T of steps II-III, the spectral prox input
    z_V = S - Gamma_S / rho_V of step IV, and Gamma_S; Gamma_V = Gamma_S W_nu

@@ -412,9 +412,10 @@ size_t grad_scratch_bytes(const muffin_ctx* c, int K, int C, bool dirty) {
 // The reverse sweep in the device scratch g (at least grad_scratch_bytes,
 // 256-B aligned; every part of it that is read is written first).
 int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, double* loss,
-               double grad[7], void* gy_out, char* g, size_t g_bytes) {
+               double grad[7], void* gy_out, char* g, size_t g_bytes, int phase, bool dirty) {
     const muffin_shape& s = c->shape;
-    const size_t need = grad_scratch_bytes(c, K, C, gy_out != nullptr);
+    if (phase != 1) dirty = gy_out != nullptr;
+    const size_t need = grad_scratch_bytes(c, K, C, dirty);
     if (!g || g_bytes < need) {
         set_error("the reverse sweep of %d passes with checkpoints every %d needs %zu bytes of scratch "
                   "(muffin_grad_workspace_bytes), %zu given (muffin_set_grad_workspace)",
@@ -439,7 +440,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     // aP, aT, aS, aG, Xb, Bb, then the cotangents of the z_b
     char* adj = seg0 + size_t(nbuf) * C * (ns + 1) * ab;
     char* gyac = adj + (kNumState + 2 + nw) * ab;
-    double* partials = (double*)(gyac + (gy_out ? ab : 0));
+    double* partials = (double*)(gyac + (dirty ? ab : 0));
     double* partials1 = partials + nparts * GRAD_NQ;      // step-I sums of a fused launch
     double* acc = partials1 + nparts * GRAD_NQ;
     const int dt = s.dtype, nrows = s.L * s.ny;
@@ -462,10 +463,12 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     // The sweep starts from the zero state: checkpoint 0 and B_rest are
     // cleared (pass 1 reads nothing else), the context's state set 0 will
     // hold the state after K passes.
-    c->cur = 0;
-    c->iters = 0;
-    c->zvalid = 0;
-    c->version++;
+    if (phase != 2) {
+        c->cur = 0;
+        c->iters = 0;
+        c->zvalid = 0;
+        c->version++;
+    }
     constexpr int kMaxSt = kNumState + kMaxWavelets;
     void* ctx_st[kMaxSt];
     for (int i = 0; i < kNumState; ++i) ctx_st[i] = st(c, i);
@@ -475,9 +478,10 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
     };
     const int blast = (nseg - 1) & (nbuf - 1);
     int rc = MUFFIN_OK;
-    HIP_TRY(launch_fill_zero(P(c, c->lay.brest), nb, st_));
-    for (int i = 0; i < ns; ++i) HIP_TRY(launch_fill_zero(ckpt(0, i), nb, st_));
-    for (int k = 1; k <= K; ++k) {
+    if (phase != 2) HIP_TRY(launch_fill_zero(P(c, c->lay.brest), nb, st_));
+    if (phase != 2)
+        for (int i = 0; i < ns; ++i) HIP_TRY(launch_fill_zero(ckpt(0, i), nb, st_));
+    for (int k = 1; k <= K && phase != 2; ++k) {
         const int seg = (k - 1) / C, j = (k - 1) % C;
         const bool last = seg == nseg - 1;
         void *in[kMaxSt], *out[kMaxSt];
@@ -491,6 +495,7 @@ int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, dou
         void* xo = (last && k < K) ? (void*)segs(blast, j, ns) : (void*)P(c, c->lay.x);
         if ((rc = pass_io(c, in, out, xo)) != MUFFIN_OK) return rc;
     }
+    if (phase == 1) return MUFFIN_OK;
     // X of pass k: its slot, X^K in the context
     auto xloc = [&](int b_, int j_, int k_) -> char* {
         return k_ == K ? (char*)P(c, c->lay.x) : segs(b_, j_, ns);
@@ -1072,6 +1077,47 @@ int muffin_grad_params(muffin_ctx* c, int K, int ckpt_every, const void* sky_or_
                        double grad[7]) {
     if (int rc = grad_args(c, K, ckpt_every, sky_or_gx, mode, grad, "muffin_grad_params")) return rc;
     return grad_sweep(c, K, ckpt_every, sky_or_gx, mode, loss, grad, nullptr, (char*)c->grad_buf, c->grad_bytes);
+}
+
+int muffin_grad_record(muffin_ctx* c, int K, int ckpt_every, int dirty) {
+    if (int rc = check_ctx(c)) return rc;
+    c->grec.valid = 0;
+    // the argument checks of the sweep, with a stand-in for the cotangent it
+    // will take (given to muffin_grad_replay)
+    if (int rc = grad_args(c, K, ckpt_every, c, MUFFIN_MODE_VJP, c, "muffin_grad_record")) return rc;
+    double unused[7];
+    const int rc = grad_sweep(c, K, ckpt_every, nullptr, MUFFIN_MODE_VJP, nullptr, unused, nullptr,
+                              (char*)c->grad_buf, c->grad_bytes, 1, dirty != 0);
+    if (rc) return rc;
+    c->grec.valid = 1;
+    c->grec.K = K;
+    c->grec.C = ckpt_every;
+    c->grec.dirty = dirty != 0;
+    c->grec.iters = c->iters;
+    c->grec.version = c->version;
+    c->grec.buf = c->grad_buf;
+    c->grec.bytes = c->grad_bytes;
+    return MUFFIN_OK;
+}
+
+int muffin_grad_replay(muffin_ctx* c, const void* sky_or_gx, int mode, double* loss, double grad[7],
+                       void* gy_out) {
+    if (int rc = check_ctx(c)) return rc;
+    const auto& r = c->grec;
+    if (!r.valid || r.iters != c->iters || r.version != c->version || r.buf != c->grad_buf ||
+        r.bytes != c->grad_bytes) {
+        set_error("muffin_grad_replay: no recorded forward sweep, or the context, its parameters or the "
+                  "gradient workspace changed since muffin_grad_record");
+        return MUFFIN_EINVAL;
+    }
+    if (r.dirty != (gy_out != nullptr)) {
+        set_error("muffin_grad_replay: the sweep was recorded %s a dirty-image cotangent",
+                  r.dirty ? "for" : "without");
+        return MUFFIN_EINVAL;
+    }
+    if (int rc = grad_args(c, r.K, r.C, sky_or_gx, mode, grad, "muffin_grad_replay")) return rc;
+    c->grec.valid = 0;
+    return grad_sweep(c, r.K, r.C, sky_or_gx, mode, loss, grad, gy_out, (char*)c->grad_buf, c->grad_bytes, 2);
 }
 
 size_t muffin_grad_workspace_bytes(const muffin_ctx* c, int K, int ckpt_every, int dirty) {

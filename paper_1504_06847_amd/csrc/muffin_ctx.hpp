@@ -36,6 +36,15 @@ struct muffin_ctx {
     // the caller's workspace of the reverse sweep (muffin_set_grad_workspace)
     void* grad_buf;
     size_t grad_bytes;
+    // a recorded forward sweep (muffin_grad_record) awaiting its reverse half:
+    // valid while the context's version, pass count and workspace are the ones
+    // it left
+    struct {
+        int valid, K, C, dirty, iters;
+        unsigned version;
+        void* buf;
+        size_t bytes;
+    } grec;
     // graph replay of one pass: captured on a private stream, one executable
     // graph per state set, replayed on `stream`
     int use_graph;
@@ -134,8 +143,12 @@ inline int check_ctx(const muffin_ctx* c) {
 // scratch at g (g_bytes of it; MUFFIN_EWORKSPACE when short); grad receives
 // the derivatives along (mu_eps, mu_s, mu_nu, rho_P, rho_T, rho_V, rho_S)
 size_t grad_scratch_bytes(const muffin_ctx* c, int K, int C, bool dirty);
+// phase 0: the whole sweep; 1: its forward passes only (scratch laid out
+// for a dirty-image cotangent when `dirty`), leaving the context after K
+// passes; 2: the reverse half of a sweep whose forward passes phase 1 ran
+// in the same scratch, the context untouched since
 int grad_sweep(muffin_ctx* c, int K, int C, const void* sky_or_gx, int mode, double* loss, double grad[7],
-               void* gy_out, char* g, size_t g_bytes);
+               void* gy_out, char* g, size_t g_bytes, int phase = 0, bool dirty = false);
 // argument checks of the gradient entry points (`out`: their output pointer)
 int grad_args(const muffin_ctx* c, int K, int ckpt_every, const void* sky_or_gx, int mode, const void* out,
               const char* what);

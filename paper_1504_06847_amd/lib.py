@@ -83,6 +83,8 @@ SIGNATURES = [
     ("muffin_grad_params", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double),
                                    POINTER(c_double)]),
     ("muffin_grad_dirty", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double), c_void_p]),
+    ("muffin_grad_record", c_int, [c_void_p, c_int, c_int, c_int]),
+    ("muffin_grad_replay", c_int, [c_void_p, c_void_p, c_int, POINTER(c_double), POINTER(c_double), c_void_p]),
     ("muffin_grad_workspace_bytes", c_size_t, [c_void_p, c_int, c_int, c_int]),
     ("muffin_set_grad_workspace", c_int, [c_void_p, c_void_p, c_size_t]),
     ("muffin_grad_noalloc", c_int, [c_void_p, c_int, c_int, c_void_p, c_int, POINTER(c_double),

@@ -371,6 +371,59 @@ class Solver:
                                                         c_void_p(gy.data_ptr())))
         return loss.value, gy
 
+    def grad_record(self, K: int, *, ckpt_every: int | None = None, dirty: bool = False):
+        """The forward half of a reverse sweep (muffin_grad_record): K passes
+        from the zero state, checkpointed into a workspace held until
+        ``grad_replay``; afterwards ``x`` is X^K.  ``dirty``: the replay
+        will also return the cotangent of the dirty images."""
+        if ckpt_every is None:
+            ckpt_every = self.sweep_ckpt_every(K, dirty=dirty)
+        self._drop_record()
+        nbytes = self.grad_workspace_bytes(K, ckpt_every, dirty)
+        if nbytes == 0:
+            raise L.MuffinError(L.MUFFIN_EINVAL, "muffin_grad_workspace_bytes", L.last_error(self._lib))
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+        L.check(self._lib.muffin_set_grad_workspace(self._ctx, c_void_p(ptr), nbytes),
+                "muffin_set_grad_workspace", self._lib)
+        self._rec = (ws, bool(dirty))
+        try:
+            with torch.cuda.stream(self.stream):
+                rc = self._lib.muffin_grad_record(self._ctx, int(K), int(ckpt_every), 1 if dirty else 0)
+            L.check(rc, "muffin_grad_record", self._lib)
+        except Exception:
+            self._drop_record()
+            raise
+
+    def grad_replay(self, *, sky=None, gx=None):
+        """The reverse half of the sweep ``grad_record`` ran: returns (loss,
+        {name: d loss / d name} for GRAD_PARAMS, dL/dY or None)."""
+        rec = getattr(self, "_rec", None)
+        if rec is None:
+            raise L.MuffinError(L.MUFFIN_EINVAL, "muffin_grad_replay", "no recorded forward sweep")
+        if (sky is None) == (gx is None):
+            raise ValueError("give exactly one of sky and gx")
+        ref = _as_cube(sky if sky is not None else gx, self.dtype, self.device)
+        if tuple(ref.shape) != tuple(self.shape):
+            raise ValueError(f"expected a cube of shape {self.shape}, got {tuple(ref.shape)}")
+        mode = L.MUFFIN_MODE_MSE if sky is not None else L.MUFFIN_MODE_VJP
+        loss = c_double()
+        g = (c_double * 7)()
+        gy = self._empty_cube() if rec[1] else None
+        try:
+            with torch.cuda.stream(self.stream):
+                rc = self._lib.muffin_grad_replay(self._ctx, c_void_p(ref.data_ptr()), mode, byref(loss), g,
+                                                  c_void_p(gy.data_ptr()) if gy is not None else None)
+            L.check(rc, "muffin_grad_replay", self._lib)
+        finally:
+            self._drop_record()
+        return loss.value, {n: g[i] for i, n in enumerate(self.GRAD_PARAMS)}, gy
+
+    def _drop_record(self):
+        if getattr(self, "_rec", None) is not None:
+            self._lib.muffin_set_grad_workspace(self._ctx, None, 0)
+            self._rec = None
+
     # -------------------------------------------------------------- timing
     def profile(self, n_iter: int = 10) -> dict:
         cap = 16
@@ -385,6 +438,7 @@ class Solver:
             if getattr(self, "_owner", False):
                 self._lib.muffin_destroy(self._ctx)
             self._ctx = c_void_p()
+        self._rec = None
 
     def __del__(self):
         try:

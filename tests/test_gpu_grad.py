@@ -267,7 +267,9 @@ def test_autograd_function(gpu_lib):
     mu_s = torch.tensor(kw["mu_s"], dtype=torch.float64, requires_grad=True)
     mu_nu = torch.tensor(kw["mu_nu"], dtype=torch.float64, requires_grad=True)
     rho = torch.tensor(kw["rho"], dtype=torch.float64, requires_grad=True)
-    x = MuffinUnroll.apply(psf, dirty, mu_s, mu_nu, rho, 15, 5, kw["mu_eps"])
+    mu_eps = torch.tensor(kw["mu_eps"], dtype=torch.float64, requires_grad=True)
+    dirty.requires_grad_(True)
+    x = MuffinUnroll.apply(psf, dirty, mu_s, mu_nu, rho, 15, 5, mu_eps)
     loss = ((x - sky) ** 2).sum()
     loss.backward()
     s = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw)
@@ -276,6 +278,45 @@ def test_autograd_function(gpu_lib):
     _say("autograd", got, g)
     assert abs(loss.item() - l2) <= 1e-12 * l2
     assert np.abs(got - g).max() <= 1e-10 * np.abs(g).max()
+    # the same sweep as muffin_grad_params / muffin_grad_dirty at this spacing
+    s2 = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw)
+    _, gp = s2.grad_params(15, sky=inst.sky, ckpt_every=5)
+    assert mu_eps.grad.item() == gp["mu_eps"]
+    _, gy = s2.grad_dirty(15, sky=inst.sky, ckpt_every=5)
+    assert torch.equal(dirty.grad, gy)
+
+
+def test_recorded_sweep_matches_one_call(gpu_lib):
+    """muffin_grad_record + muffin_grad_replay: X^K after the record equals
+    K iterated passes, and the replay gives what one muffin_grad_params and
+    one muffin_grad_dirty call give, bit for bit, with each forward pass run
+    once; a replay without a record, or after another pass, is refused."""
+    from paper_1504_06847_amd import Solver
+    from paper_1504_06847_amd.lib import MuffinError
+    from synth import make_instance
+    inst = make_instance(32, 32, 8, n_points=4, n_gauss=2, n_ant=16, noise_sigma=0.01, seed=77)
+    p = get_config("grad64").params
+    kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho=p.rho_P)
+    gx = np.random.default_rng(14).standard_normal(inst.dirty.shape)
+    K, C = 9, 4
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw)
+    s.grad_record(K, ckpt_every=C, dirty=True)
+    ref = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw)
+    ref.iterate(K)
+    assert torch.equal(s.x, ref.x)
+    _, g, gy = s.grad_replay(gx=gx)
+    _, gp = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw).grad_params(K, gx=gx, ckpt_every=C)
+    _, gd = Solver(inst.psf, inst.dirty, dtype=torch.float64, **kw).grad_dirty(K, gx=gx, ckpt_every=C)
+    assert g == gp
+    assert torch.equal(gy, gd)
+    assert torch.equal(s.x, ref.x)
+    with pytest.raises(MuffinError):
+        s.grad_replay(gx=gx)
+    s.grad_record(K, ckpt_every=C)
+    s.iterate(1)
+    with pytest.raises(MuffinError) as ei:
+        s.grad_replay(gx=gx)
+    assert ei.value.code == -1
 
 
 def test_full_size_gradient_fp32(gpu_lib):
