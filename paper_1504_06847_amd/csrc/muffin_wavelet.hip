@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
 // order inside the work-group, so out is read and written once and the sum
 // has a fixed order.  Slice z = band.
 template <typename T, int CF>
-__global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 4 : 3) k_dwt_inv0_all(DwtLevel A) {
+__global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 5 : 3) k_dwt_inv0_all(DwtLevel A) {
     __shared__ T smem[DWT_INV_LDS];
     const Tile tl = xcd_tile();
     const long band = tl.z;
@@ -625,17 +625,12 @@ __global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 4 : 3) k_dwt_inv0_al
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int i0 = tl.y * oty, m0 = tl.x * otx;
     T* ob = (T*)A.out0 + band * vb;
-    // the outputs, loaded first so that their latency overlaps the tiles
     int rr, c0, n;
     const bool own = inv_out(oty, otx, rr, c0, n);
     T* o = ob + long(2 * i0 + rr) * A.sx + 2 * m0 + c0;
     T oq[2 * DWT_C2], acc[2 * DWT_C2] = {};
-    if (own) {
-#pragma unroll
-        for (int c = 0; c < 2 * DWT_C2; ++c)
-            if (c < n) oq[c] = o[c];
-    }
-    // the coefficients of basis b + 1 are fetched while basis b is synthesised
+    // the coefficients of basis b + 1 are fetched while basis b is
+    // synthesised, the outputs while the last basis is
     auto zb_of = [&](int b) { return (const T*)A.z0 + b * A.zstride + band * A.z_bs; };
     auto llb_of = [&](int b) { return A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * (vb / 4) : nullptr; };
     auto k_of = [&](int b) { return 2 * int((A.kpack >> (4 * b)) & 15u); };
@@ -645,7 +640,13 @@ __global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 4 : 3) k_dwt_inv0_al
         const int K = k_of(b);
         inv_commit<T, CF>(pf, A.ll0 != nullptr, A.sy, A.sx, K / 2 - 1, T(A.tau), smem);
         __syncthreads();
-        if (b + 1 < A.n) inv_fetch<T>(llb_of(b + 1), zb_of(b + 1), A.ld, A.sy, A.sx, k_of(b + 1) / 2 - 1, tl, pf);
+        if (b + 1 < A.n) {
+            inv_fetch<T>(llb_of(b + 1), zb_of(b + 1), A.ld, A.sy, A.sx, k_of(b + 1) / 2 - 1, tl, pf);
+        } else if (own) {
+#pragma unroll
+            for (int c = 0; c < 2 * DWT_C2; ++c)
+                if (c < n) oq[c] = o[c];
+        }
         const T* fb = (const T*)A.ftab + 32 * b;
         switch (K) {
 #define F(KK)                                                                              \
