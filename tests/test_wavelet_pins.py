@@ -162,3 +162,62 @@ def test_tangent_pass_with_wavelet_bases_against_central_differences():
     xp = O.run(O.Problem(psf, Y + h * dY, base, bases=bases), K).X
     xm = O.run(O.Problem(psf, Y - h * dY, base, bases=bases), K).X
     assert np.abs((xp - xm) / (2 * h) - dX).max() <= 1e-6 * np.abs(dX).max()
+
+
+def test_residuals_energy_objective_with_wavelet_bases_against_dense_operators():
+    """The Boyd residuals, their tolerances, E^k and F(P) with a union of
+    three spatial bases (Dirac, Db1, Db3), against the stacked constraint
+    matrices written out densely: [P - X; T - W_s X; V - S W; S - X] =
+    A (X, V) + B (P, T, S), W_s the loop-built DWT matrices stacked under the
+    identity (T and Gamma_T hold one cube per basis)."""
+    from tests.independent import dense_conv_matrix
+    rng = np.random.default_rng(17)
+    L, n = 3, 8
+    psf = rng.uniform(0.0, 0.3, size=(L, n, n))
+    psf[:, n // 2, n // 2] = 1.0
+    Y = rng.standard_normal((L, n, n)) + 1.0
+    p = O.Params(mu_eps=1e-3, mu_s=0.3, mu_nu=0.7, rho_P=1.0, rho_T=3.0, rho_V=2.0, rho_S=1.5)
+    bases = (0, 1, 3)
+    prob = O.Problem(psf, Y, p, bases=bases)
+    prev = O.run(prob, 3)
+    cur = O.admm_iteration(prob, prev)
+    N = L * n * n
+    J = O.dwt_levels(n, n)
+    blocks = [np.eye(N)] + [np.kron(np.eye(L), dense_dwt_matrix(O.daubechies_filter(b), n, n, J))
+                            for b in bases[1:]]
+    Ws = np.vstack(blocks)                       # (n_s N) x N
+    ns = len(bases)
+    W = dct_matrix(L)
+    Wbig = np.kron(W.T, np.eye(n * n))
+    I = np.eye(N)
+    Z = np.zeros((N, N))
+    ZT = np.zeros((ns * N, N))
+    A = np.block([[-I, Z], [-Ws, ZT], [Z, I], [-I, Z]])
+    B = np.block([[I, np.zeros((N, ns * N)), Z],
+                  [ZT, np.eye(ns * N), ZT],
+                  [Z, np.zeros((N, ns * N)), -Wbig],
+                  [Z, np.zeros((N, ns * N)), I]])
+    rho = np.concatenate([np.full(N, p.rho_P), np.full(ns * N, p.rho_T), np.full(N, p.rho_V),
+                          np.full(N, p.rho_S)])
+    v = lambda a: np.asarray(a).ravel()
+    x = np.concatenate([v(cur.X), v(cur.V)])
+    z = np.concatenate([v(cur.P), v(cur.T), v(cur.S)])
+    dz = z - np.concatenate([v(prev.P), v(prev.T), v(prev.S)])
+    y = np.concatenate([v(cur.GP), v(cur.GT), v(cur.GV), v(cur.GS)])
+    dy = y - np.concatenate([v(prev.GP), v(prev.GT), v(prev.GV), v(prev.GS)])
+    r = A @ x + B @ z
+    s = A.T @ (rho * (B @ dz))
+    res = O.residuals(prob, prev, cur, eps_abs=1e-5, eps_rel=1e-4)
+    assert res["r"] == pytest.approx(np.linalg.norm(r), rel=1e-12)
+    assert res["s"] == pytest.approx(np.linalg.norm(s), rel=1e-12)
+    eps_pri = np.sqrt(A.shape[0]) * 1e-5 + 1e-4 * max(np.linalg.norm(A @ x), np.linalg.norm(B @ z))
+    eps_dual = np.sqrt(A.shape[1]) * 1e-5 + 1e-4 * np.linalg.norm(A.T @ y)
+    assert res["eps_pri"] == pytest.approx(eps_pri, rel=1e-12)
+    assert res["eps_dual"] == pytest.approx(eps_dual, rel=1e-12)
+    E = np.sum(rho * (B @ dz) ** 2) + np.sum(dy ** 2 / rho)
+    assert O.energy(prob, prev, cur) == pytest.approx(E, rel=1e-12)
+    P = cur.P
+    HP = np.stack([(dense_conv_matrix(psf[l]) @ P[l].ravel()).reshape(n, n) for l in range(L)])
+    F = (0.5 * np.sum((Y - HP) ** 2) + 0.5 * p.mu_eps * np.sum(P ** 2)
+         + p.mu_s * np.sum(np.abs(Ws @ P.ravel())) + p.mu_nu * np.sum(np.abs(Wbig @ P.ravel())))
+    assert O.objective(prob, P) == pytest.approx(F, rel=1e-12)
