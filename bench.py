@@ -79,6 +79,26 @@ def measured_traffic(kernel, workload):
     return e["fetch_kib"] * t["fetch_scale"] * 1024 + e["write_kib"] * t["write_scale"] * 1024
 
 
+def read_probe(mib=1024, reps=20):
+    """A read-only pass of a known size: a sum over a device array (a second
+    calibration of the FETCH counter, from another kernel than the copy)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    for _ in range(3):
+        a.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"read_probe_MiB": mib, "ms": round(ms, 4),
+                      "GBps": round(mib * (1 << 20) / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
 def copy_probe(mib=256, reps=20):
     """Plain device copy of a known size (calibrates the FETCH/WRITE counters)."""
     import torch
@@ -434,7 +454,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu-context", action="store_true",
                     help="skip the oracle's full runs of the small workloads")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only run a 256 MiB device copy (counter calibration)")
+                    help="only run a device copy (counter calibration)")
+    ap.add_argument("--probe-mib", type=int, default=256, help="size of the copy or read probe")
+    ap.add_argument("--read-probe", action="store_true",
+                    help="only run a read-only sum over a device array (counter calibration)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
@@ -446,7 +469,10 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     if a.copy_probe:
-        copy_probe()
+        copy_probe(a.probe_mib)
+        return
+    if a.read_probe:
+        read_probe(a.probe_mib)
         return
     cfg = get_config(a.config)
     _log(f"bench: generating {cfg.name} {cfg.nx}x{cfg.ny}x{cfg.L}")
