@@ -243,6 +243,10 @@ def test_batch_with_wavelet_dictionaries_bitwise(gpu_lib, graph):
         torch.cuda.synchronize()
         for i, s in enumerate(singles):
             assert torch.equal(b.cube(i).x, s.x), f"pass {k + 1}, cube {i} {shapes[i]} {bases[i]}"
+    # a reporting pass on a batched cube with the paper's dictionary (its
+    # wavelet report launches), then more batched passes
+    ra, rb = b.cube(0).step_report(), singles[0].step_report()
+    assert ra == rb
     b.iterate(6)
     for s in singles:
         s.iterate(6)

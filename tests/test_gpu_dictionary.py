@@ -267,6 +267,30 @@ def test_dictionary_report_matches_oracle(gpu_lib, L, ny, nx, bases, dtype):
     assert err <= (1e-12 if f64 else 1e-4)
 
 
+def test_dictionary_report_at_the_paper_shape(gpu_lib):
+    """256 x 256 x 15 (Section 4's run shape) with Dirac + Db1..Db8, FP32: the
+    report of the fourth pass against the float64 oracle's (bars as for the
+    FP32 case above)."""
+    cfg = get_config("paper256")
+    inst = cfg.make()
+    p = cfg.params
+    from paper_1504_06847_amd import Solver
+    s = Solver(inst.psf, inst.dirty, dtype=torch.float32, spatial=PAPER, **_kw(p))
+    prob = O.Problem(inst.psf, inst.dirty, p, bases=PAPER)
+    s.iterate(3)
+    prev = O.run(prob, 3)
+    rep = s.step_report()
+    cur = O.admm_iteration(prob, prev)
+    res = O.residuals(prob, prev, cur, eps_abs=1e-5, eps_rel=1e-4)
+    _say("paper shape report", {k: rep[k] for k in ("r_pri", "r_dual", "E", "objective")}, res)
+    assert rep["r_pri"] == pytest.approx(res["r"], rel=1e-3)
+    assert rep["r_dual"] == pytest.approx(res["s"], rel=1e-3)
+    assert rep["E"] == pytest.approx(O.energy(prob, prev, cur), rel=1e-3)
+    assert rep["eps_pri"] == pytest.approx(res["eps_pri"], rel=1e-5)
+    assert rep["eps_dual"] == pytest.approx(res["eps_dual"], rel=1e-5)
+    assert rep["objective"] == pytest.approx(O.objective(prob, cur.P), rel=1e-5)
+
+
 def test_dictionary_adaptive_solve_matches_oracle(gpu_lib):
     """muffin_solve_adaptive with wavelet bases: the same rho decisions at
     the same checks, the same stopping iteration and the same X as the
