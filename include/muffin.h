@@ -172,7 +172,10 @@ int muffin_setup(muffin_ctx** ctx, const muffin_shape* shape, const muffin_param
                  void* stream);
 
 /* Run n_iter passes of Algorithm 1 (steps I-VI) on the context's stream.
-   No host synchronisation.  n_iter = 0 is a no-op.  Errors: EINVAL, EDEVICE. */
+   No host synchronisation.  n_iter = 0 is a no-op.  Every pass computes X;
+   the fused pass stores it to the context's X array only in the last pass
+   of the call, the earlier ones' X being overwritten unread (muffin_get_x
+   and the state snapshot read the last).  Errors: EINVAL, EDEVICE. */
 int muffin_iterate(muffin_ctx* ctx, int n_iter);
 
 /* Iterate until the primal/dual residuals of the two-block splitting fall
@@ -460,7 +463,9 @@ int muffin_vis_cg_iters(const muffin_ctx* ctx);
 /* Time n_iter passes with HIP events around every kernel launch on the
    context's stream; writes the mean duration in ms of each kernel of one
    pass to ms[i] and its name to names[i] (static strings), for up to `cap`
-   kernels; returns the number of kernels per pass (negative on error). */
+   kernels; returns the number of kernels per pass (negative on error).  As
+   in muffin_iterate a fused pass stores X in the last pass only; with
+   n_iter > 1 the means are over the passes before it. */
 int muffin_profile(muffin_ctx* ctx, int n_iter, double* ms, const char** names, int cap);
 
 /* Release the context (not the caller's workspaces); a batch context

@@ -84,10 +84,12 @@ int fused_rows_io(muffin_ctx* c, void* const in[4], void* const out[4], void* xo
     return MUFFIN_OK;
 }
 
-int fused_rows(muffin_ctx* c) {
+// wx: X goes to the context (the last pass of a run); the passes before it
+// leave X unwritten, as the next pass overwrites it unread
+int fused_rows(muffin_ctx* c, bool wx = true) {
     void* cur[4];
     for (int i = 0; i < kNumState; ++i) cur[i] = st(c, i);
-    return fused_rows_io(c, cur, cur, P(c, c->lay.x));
+    return fused_rows_io(c, cur, cur, wx ? P(c, c->lay.x) : nullptr);
 }
 
 // steps II-VI from the state `in` and X, the new state to `out` (a
@@ -162,7 +164,7 @@ int pass_io(muffin_ctx* c, void* const* in, void* const* out, void* xo) {
     return MUFFIN_OK;
 }
 
-int pass_kernels(muffin_ctx* c) {
+int pass_kernels(muffin_ctx* c, bool wx = true) {
     if (c->vis) {
         // the visibility-domain model: step I by CG, then steps II-VI
         if (int rc = vis_step_one(c)) return rc;
@@ -171,7 +173,7 @@ int pass_kernels(muffin_ctx* c) {
     if (use_fused(c)) {
         if (int rc = row_forward(c)) return rc;
         if (int rc = col_solve(c)) return rc;
-        return fused_rows(c);
+        return fused_rows(c, wx);
     }
     int rc = step_one(c);
     if (rc) return rc;
@@ -180,19 +182,21 @@ int pass_kernels(muffin_ctx* c) {
 }
 
 void drop_graphs(muffin_ctx* c) {
-    for (int i = 0; i < 2; ++i) {
-        if (c->gexec[i]) hipGraphExecDestroy(c->gexec[i]);
-        c->gexec[i] = nullptr;
-    }
+    for (int i = 0; i < 2; ++i)
+        for (int w = 0; w < 2; ++w) {
+            if (c->gexec[i][w]) hipGraphExecDestroy(c->gexec[i][w]);
+            c->gexec[i][w] = nullptr;
+        }
 }
 
-// record the kernels of one pass (state set c->cur) into an executable graph
-int capture_pass(muffin_ctx* c) {
+// record the kernels of one pass (state set c->cur; X written or not) into an
+// executable graph
+int capture_pass(muffin_ctx* c, bool wx) {
     if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     hipStream_t user = c->stream;
     c->stream = c->cap;
     hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
-    int rc = e == hipSuccess ? pass_kernels(c) : MUFFIN_EDEVICE;
+    int rc = e == hipSuccess ? pass_kernels(c, wx) : MUFFIN_EDEVICE;
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap, &g);
     c->stream = user;
@@ -202,30 +206,31 @@ int capture_pass(muffin_ctx* c) {
             set_error("graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
         return rc == MUFFIN_OK ? MUFFIN_EDEVICE : rc;
     }
-    e = hipGraphInstantiate(&c->gexec[c->cur], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c->gexec[c->cur][wx], g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c->gexec[c->cur] = nullptr;
+        c->gexec[c->cur][wx] = nullptr;
         set_error("graph instantiation failed: %s", hipGetErrorString(e));
         return MUFFIN_EDEVICE;
     }
     return MUFFIN_OK;
 }
 
-int one_pass(muffin_ctx* c) {
+// one pass; wx: its X is read afterwards (a fused pass writes X only then)
+int one_pass(muffin_ctx* c, bool wx = true) {
     if (c->use_graph) {
         // a recorded fused pass starts from Z (the graph holds the column
         // and fused launches only)
         if (use_fused(c))
             if (int rc = row_forward(c)) return rc;
-        if (!c->gexec[c->cur]) {
-            int rc = capture_pass(c);
+        if (!c->gexec[c->cur][wx]) {
+            int rc = capture_pass(c, wx);
             if (rc) return rc;
         }
-        HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
+        HIP_TRY(hipGraphLaunch(c->gexec[c->cur][wx], c->stream));
         c->zvalid = use_fused(c) ? 1 : 0;
     } else {
-        int rc = pass_kernels(c);
+        int rc = pass_kernels(c, wx);
         if (rc) return rc;
     }
     c->iters++;
@@ -729,7 +734,7 @@ int muffin_setup(muffin_ctx** out, const muffin_shape* shape, const muffin_param
     c->grad_bytes = 0;
     c->use_graph = 0;
     c->cap = nullptr;
-    c->gexec[0] = c->gexec[1] = nullptr;
+    c->gexec[0][0] = c->gexec[0][1] = c->gexec[1][0] = c->gexec[1][1] = nullptr;
 
     auto fail = [&](int code) {
         if (c->cap) hipStreamDestroy(c->cap);
@@ -794,8 +799,10 @@ int muffin_iterate(muffin_ctx* c, int n_iter) {
     if (c && c->batch) return batch_iterate(c->batch, n_iter);
     if (int rc = check_ctx(c)) return rc;
     if (n_iter < 0) { set_error("n_iter = %d < 0", n_iter); return MUFFIN_EINVAL; }
+    // X of a pass is read only after the last (muffin_get_x, the state
+    // snapshot); every pass computes it
     for (int i = 0; i < n_iter; ++i) {
-        int rc = one_pass(c);
+        int rc = one_pass(c, i + 1 == n_iter);
         if (rc) return rc;
     }
     return MUFFIN_OK;
@@ -1016,7 +1023,7 @@ int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, in
         if (fu) {
             if (e == hipSuccess && (rc = col_solve(c)) != MUFFIN_OK) break;
             if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
-            if (e == hipSuccess && (rc = fused_rows(c)) != MUFFIN_OK) break;
+            if (e == hipSuccess && (rc = fused_rows(c, it + 1 == n_iter)) != MUFFIN_OK) break;
             if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
         } else {
             if (e == hipSuccess && (rc = row_forward(c)) != MUFFIN_OK) break;
@@ -1036,18 +1043,21 @@ int muffin_profile(muffin_ctx* c, int n_iter, double* ms, const char** names, in
         }
         if (e == hipSuccess) e = hipEventSynchronize(ev[K]);
         if (e != hipSuccess) { set_error("profile: %s", hipGetErrorString(e)); rc = MUFFIN_EDEVICE; break; }
-        for (int k = 0; k < K; ++k) {
-            float t = 0.f;
-            hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-            acc[k] += t;
-        }
+        // a fused pass writes X on the last of the passes only (as a run's
+        // passes do); the average is over the others when there are others
+        if (!(fu && n_iter > 1 && it + 1 == n_iter))
+            for (int k = 0; k < K; ++k) {
+                float t = 0.f;
+                hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+                acc[k] += t;
+            }
         c->iters++;
     }
     for (int i = 0; i <= K; ++i) hipEventDestroy(ev[i]);
     if (rc) return rc;
     const int m = cap < K ? cap : K;
     for (int k = 0; k < m; ++k) {
-        ms[k] = acc[k] / n_iter;
+        ms[k] = acc[k] / ((fu && n_iter > 1) ? n_iter - 1 : n_iter);
         if (names) names[k] = knames[k];
     }
     return K;

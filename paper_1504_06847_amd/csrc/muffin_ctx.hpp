@@ -46,10 +46,11 @@ struct muffin_ctx {
         size_t bytes;
     } grec;
     // graph replay of one pass: captured on a private stream, one executable
-    // graph per state set, replayed on `stream`
+    // graph per state set and per form of the pass (X written or not),
+    // replayed on `stream`
     int use_graph;
     hipStream_t cap;
-    hipGraphExec_t gexec[2];
+    hipGraphExec_t gexec[2][2];
     // wavelet bases of the spatial dictionary: filter length and the FP64
     // scaling filter of each (lay.n_w of them)
     int wK[muffin::kMaxWavelets];

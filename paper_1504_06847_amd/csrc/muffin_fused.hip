@@ -74,6 +74,9 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
     // the state and X stream through once per pass: non-temporal
     const BandArray1<T, kStreamCpol> X(A.X, bb), zP(A.zP, bb), zT(A.zT, bb), zV(A.zV, bb), GS(A.GS, bb);
     const BandArray1<T, kStreamCpol> zPo(A.zPo, bb), zTo(A.zTo, bb), zVo(A.zVo, bb), GSo(A.GSo, bb);
+    // X goes out only when the caller reads it (A.X not null): the passes of a
+    // run before its last overwrite it unread
+    const bool wx = A.X != nullptr;
     cx<T>* Z = (cx<T>*)A.Z;
     const int L = DENSE ? Lrt : LT;
     const T rhoP = T(a.rho_P), rhoT = T(a.rho_T), rhoV = T(a.rho_V), rhoS = T(a.rho_S);
@@ -148,7 +151,7 @@ __device__ __forceinline__ void fused_body(const FusedArrays& A, const T* __rest
                     const T zv2 = s - gs2 * inv_rhoV;
                     const T sv = zv2 + gs2 * inv_rhoV;       // S as stored (see k_spectral)
                     lrow[e] = rhoT * (T(2) * tt - zt2) + rhoP * fabs(zp2) + gs2 + rhoS * sv;
-                    X.store(l, offp, xv);
+                    if (wx) X.store(l, offp, xv);
                     zVo.store(l, offp, zv2);
                     GSo.store(l, offp, gs2);
                     zPo.store(l, offp, zp2);
@@ -241,7 +244,7 @@ bool fused_two_pixel_variant(int nx, int L) { return fused_two_pixels_at(nx, L);
 hipError_t launch_fused(int dtype, const FusedArrays& A, const void* D, int L, int ny, int nx,
                         const SpecArgs& a, const void* tw, int twlog, hipStream_t s, int variant) {
     if (!fused_supported(dtype, nx, ny, L) || variant < 1 || variant > 2) return hipErrorInvalidValue;
-    if (!A.X || !A.zP || !A.zT || !A.zV || !A.GS || !A.zPo || !A.zTo || !A.zVo || !A.GSo || !A.Z)
+    if (!A.zP || !A.zT || !A.zV || !A.GS || !A.zPo || !A.zTo || !A.zVo || !A.GSo || !A.Z)
         return hipErrorInvalidValue;
     switch (nx) {
         case 64: return fused_l<float, 64>(A, D, L, ny, a, tw, twlog, s, variant);

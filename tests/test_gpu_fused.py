@@ -169,6 +169,33 @@ def test_driver_calls_between_fused_passes(gpu_lib):
     assert rel(a.x.double().cpu().numpy(), c.x.double().cpu().numpy()) < 1e-6
 
 
+@pytest.mark.parametrize("graph", [False, True], ids=["launch", "graph"])
+def test_a_run_stores_x_on_its_last_pass(gpu_lib, graph):
+    """A fused run of n passes stores X in its last pass only: X, the state
+    snapshot and the passes after it are bit for bit those of n runs of one
+    pass (every pass storing X)."""
+    from paper_1504_06847_amd import Solver
+    cfg = get_config("plain64")
+    inst = cfg.make()
+    p = cfg.params
+    kw = dict(mu_eps=p.mu_eps, mu_s=p.mu_s, mu_nu=p.mu_nu, rho_P=p.rho_P, rho_T=p.rho_T,
+              rho_V=p.rho_V, rho_S=p.rho_S)
+    a = Solver(inst.psf, inst.dirty, graph=graph, **kw)
+    b = Solver(inst.psf, inst.dirty, graph=graph, **kw)
+    assert a.schedule[2] != 0                      # the fused pass
+    a.iterate(7)
+    for _ in range(7):
+        b.iterate(1)
+    torch.cuda.synchronize()
+    assert torch.equal(a.x, b.x)
+    assert torch.equal(a.get_state(), b.get_state())
+    a.iterate(3)
+    b.iterate(2)
+    b.iterate(1)
+    torch.cuda.synchronize()
+    assert torch.equal(a.x, b.x)
+
+
 def test_batch_after_fused_single_cube_passes(gpu_lib):
     """A batched pass after fused single-cube passes on the same cube starts
     from B_rest rebuilt from the state."""
