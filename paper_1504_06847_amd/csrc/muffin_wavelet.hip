@@ -375,7 +375,8 @@ __device__ __forceinline__ void inv_commit(const T (&pf)[DWT_PF][4], bool ll_ima
 // output parities of 2 coefficient rows of one column from K / 2 + 1 rows of
 // each sub-band; a thread of the column synthesis forms 8 adjacent pixels
 // from K / 2 + 3 values of each half.  Each output's taps are summed in tap
-// order.  Ends with a barrier, so the next tile may reuse the LDS at once.
+// order, the low-pass term of a tap before its high-pass term, one fused
+// multiply-add each.  Ends with a barrier, so the next tile may reuse the LDS at once.
 template <typename T, int K>
 __device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], const T (&g)[K], T* smem,
                                              T (&acc)[2 * DWT_C2]) {
@@ -412,8 +413,10 @@ __device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], co
 #pragma unroll
                 for (int kk = 0; kk < K / 2; ++kk) {
                     const int t = r + H2 - kk;
-                    lo += h[2 * kk + p] * va[t] + g[2 * kk + p] * vby[t];
-                    hi += h[2 * kk + p] * vbx[t] + g[2 * kk + p] * vd[t];
+                    lo += h[2 * kk + p] * va[t];
+                    lo += g[2 * kk + p] * vby[t];
+                    hi += h[2 * kk + p] * vbx[t];
+                    hi += g[2 * kk + p] * vd[t];
                 }
                 xl[(2 * (rb + r) + p) * CMX + q] = lo;
                 xh[(2 * (rb + r) + p) * CMX + q] = hi;
@@ -441,7 +444,8 @@ __device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], co
 #pragma unroll
                 for (int kk = 0; kk < K / 2; ++kk) {
                     const int t = c + H2 - kk;
-                    v += h[2 * kk + p] * ul[t] + g[2 * kk + p] * uh[t];
+                    v += h[2 * kk + p] * ul[t];
+                    v += g[2 * kk + p] * uh[t];
                 }
                 acc[2 * c + p] += v;
             }
