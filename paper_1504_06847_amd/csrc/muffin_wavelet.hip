@@ -47,14 +47,17 @@ constexpr int DWT_FWD_LDS = (2 * DWT_OTY + 14) * (2 * DWT_OTX + 14) + 2 * (2 * D
 constexpr int dwt_xstride(int H2) { return DWT_OTX + H2 + ((1 - (DWT_OTX + H2)) & 3); }
 constexpr int DWT_INV_LDS = 4 * (DWT_OTY + 7) * (DWT_OTX + 7) + 2 * (2 * DWT_OTY) * dwt_xstride(7);
 
-template <typename T> __device__ __forceinline__ T wclip(T z, T t) { return z > t ? t : (z < -t ? -t : z); }
-template <typename T> __device__ __forceinline__ T wsoft(T z, T t) {
-    return z > t ? z - t : (z < -t ? z + t : T(0));
+// clip to [-t, t] (t >= 0, finite z: the median of z, -t and t) and soft
+// threshold, soft(z) = z - clip(z) (exactly z - t, z + t or +0)
+template <typename T> __device__ __forceinline__ T wclip(T z, T t) {
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_fmed3f(z, -t, t);
+    else return fmin(fmax(z, -t), t);
 }
+template <typename T> __device__ __forceinline__ T wsoft(T z, T t) { return z - wclip(z, t); }
 // z_b <- c + clip(z_b, tau)
 template <typename T> __device__ __forceinline__ void zupdate(T* p, T c, T tau) { *p = c + wclip(*p, tau); }
-// u = 2 soft(z, tau) - z
-template <typename T> __device__ __forceinline__ T ucoef(T z, T tau) { return T(2) * wsoft(z, tau) - z; }
+// u = 2 soft(z, tau) - z = z - 2 clip(z, tau), one rounding
+template <typename T> __device__ __forceinline__ T ucoef(T z, T tau) { return z - T(2) * wclip(z, tau); }
 // the synthesis input of coefficient z: u (CF 0), z (CF 1), -clip(z) (CF 2)
 template <typename T, int CF> __device__ __forceinline__ T scoef(T z, T tau) {
     if constexpr (CF == 0) return ucoef(z, tau);
@@ -214,11 +217,12 @@ __device__ __forceinline__ void dwt_fwd_tile(T* __restrict__ zb, T* __restrict__
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int i0 = tl.y * oty, m0 = tl.x * otx;
     const int HY = 2 * oty + K - 2;
-    // along x: row r, outputs mb .. mb + DWT_MB - 1 (a tile narrower than
-    // DWT_MB reads past its columns inside the LDS array and keeps only its own)
-    const int nmb = otx >= DWT_MB ? otx / DWT_MB : 1;
-    for (int e = threadIdx.x; e < HY * nmb; e += DWT_NTH) {
-        const int r = e / nmb, mb = (e - r * nmb) * DWT_MB;
+    // along x: row r, outputs mb .. mb + DWT_MB - 1 (DWT_OTX / DWT_MB items
+    // per row whatever the tile's width: a narrower tile reads past its
+    // columns inside the LDS array and keeps only its own outputs)
+    constexpr int NMB = DWT_OTX / DWT_MB;
+    for (int e = threadIdx.x; e < HY * NMB; e += DWT_NTH) {
+        const int r = e / NMB, mb = (e - r * NMB) * DWT_MB;
         const T* row = tin + r * DWT_HMX + 2 * mb;
         T v[NV];
 #pragma unroll
@@ -299,111 +303,130 @@ __device__ __forceinline__ void dwt_fwd_tile(T* __restrict__ zb, T* __restrict__
     }
 }
 
-// Synthesis output ownership: thread t forms 8 adjacent pixels of one row
-// of the 2 oty x 2 otx tile (row rr, columns c0 .. c0 + 7); n of them lie
-// in the tile (4 when the tile is 4 pixels wide).  False for threads
-// without pixels.
+// Synthesis output ownership: thread t forms 8 adjacent pixels (columns
+// c0 .. c0 + 7) of row rr of the 2 DWT_OTY x 2 DWT_OTX pixels a tile
+// computes; n of them lie in the image's 2 oty x 2 otx tile (fewer than 8
+// only when the image is narrower than 4 coefficients).  False for threads
+// whose pixels all lie outside it.
 constexpr int DWT_C2 = 4;    // coefficient columns per thread in the column synthesis (8 pixels)
+constexpr int DWT_XT = DWT_OTX / DWT_C2;    // threads per output row
+static_assert(2 * DWT_OTY * DWT_XT == DWT_NTH, "one thread per 8 output pixels");
 __device__ __forceinline__ bool inv_out(int oty, int otx, int& rr, int& c0, int& n) {
-    const int nc = otx >= DWT_C2 ? otx / DWT_C2 : 1;
     const int t = threadIdx.x;
-    rr = t / nc;
-    c0 = (t - rr * nc) * 2 * DWT_C2;
-    n = otx >= DWT_C2 ? 2 * DWT_C2 : 2 * otx;
-    return t < 2 * oty * nc;
+    rr = t / DWT_XT;
+    c0 = (t % DWT_XT) * 2 * DWT_C2;
+    n = 2 * otx - c0 < 2 * DWT_C2 ? 2 * otx - c0 : 2 * DWT_C2;
+    return rr < 2 * oty && c0 < 2 * otx;
 }
 
-// The coefficients of one synthesis tile (filter length 2 H2 + 2): the
-// (oty + H2) x (otx + H2) block of each sub-band below and right of the
-// tile's own, periodic, as read from memory (LL from llb, the band's dense
-// [sy/2][sx/2] image, when not null, else from zb).  Fetched into registers
-// ahead of their use, then committed to LDS.
-constexpr int DWT_PF = ((DWT_OTY + 7) * (DWT_OTX + 7) + DWT_NTH - 1) / DWT_NTH;
-template <typename T>
-__device__ __forceinline__ void inv_fetch(const T* __restrict__ llb, const T* __restrict__ zb, int ld, int sy,
-                                          int sx, int H2, const Tile& tl, T (&pf)[DWT_PF][4]) {
+// The coefficients of one synthesis tile, whatever its filter: the
+// (DWT_OTY + 7) x (DWT_OTX + 7) block of each sub-band that starts 7 rows
+// and columns before the tile's own (the halo of the longest filter),
+// periodic, fetched into registers ahead of their use and committed to LDS
+// with that row stride, so a block element's LDS index is its fetch index.
+// A filter of length 2 H2 + 2 reads the block from (7 - H2, 7 - H2).  A
+// tile narrower or shorter than DWT_OTY x DWT_OTX (small images) still
+// fills and computes the whole block from the periodic extension and keeps
+// only its own pixels.
+constexpr int DWT_SY = DWT_OTY + 7, DWT_SX = DWT_OTX + 7, DWT_SE = DWT_SY * DWT_SX;
+constexpr int DWT_PF = (DWT_SE + DWT_NTH - 1) / DWT_NTH;
+// Where this thread's block elements lie in a sub-band, the same for every
+// basis of a level: periodic coefficient row gi and column gm, packed as
+// gi << 16 | gm (sub-bands below 65536 x 65536).
+struct InvOffsets {
+    unsigned rc[DWT_PF];
+};
+__device__ __forceinline__ InvOffsets inv_offsets(int sy, int sx, const Tile& tl) {
     const int hy = sy >> 1, hx = sx >> 1;
     const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
     const int i0 = tl.y * oty, m0 = tl.x * otx;
-    const int CY = oty + H2, CX = otx + H2;
+    InvOffsets f;
 #pragma unroll
     for (int j = 0; j < DWT_PF; ++j) {
         const int e = threadIdx.x + j * DWT_NTH;
-        if (e < CY * CX) {
-            const int n = e / CX, q = e - n * CX;
-            // periodic coefficient indices i0 - H2 + n, m0 - H2 + q (hy, hx powers of two)
-            const long gi = (i0 - H2 + n + 8 * hy) & (hy - 1), gm = (m0 - H2 + q + 8 * hx) & (hx - 1);
-            pf[j][0] = llb ? llb[gi * hx + gm] : zb[gi * ld + gm];
-            pf[j][1] = zb[gi * ld + hx + gm];
-            pf[j][2] = zb[(hy + gi) * ld + gm];
-            pf[j][3] = zb[(hy + gi) * ld + hx + gm];
+        const int n = e / DWT_SX, q = e - n * DWT_SX;
+        // periodic coefficient indices i0 - 7 + n, m0 - 7 + q (hy, hx powers of two)
+        const unsigned gi = unsigned(i0 - 7 + n + 8 * hy) & unsigned(hy - 1);
+        const unsigned gm = unsigned(m0 - 7 + q + 8 * hx) & unsigned(hx - 1);
+        f.rc[j] = gi << 16 | gm;
+    }
+    return f;
+}
+// the block into registers: from the band's coefficient block zb (row
+// stride ld; LL from llb, the band's dense [sy/2][sx/2] image, when not null)
+template <typename T>
+__device__ __forceinline__ void inv_fetch(const T* __restrict__ llb, const T* __restrict__ zb, int ld, int sy,
+                                          int sx, const InvOffsets& f, T (&pf)[DWT_PF][4]) {
+    const long hy = sy >> 1, hx = sx >> 1;
+    const T* __restrict__ zx = zb + hx;
+    const T* __restrict__ zy = zb + hy * ld;
+    const T* __restrict__ zd = zy + hx;
+#pragma unroll
+    for (int j = 0; j < DWT_PF; ++j) {
+        if (j + 1 < DWT_PF || int(threadIdx.x) + j * DWT_NTH < DWT_SE) {
+            const unsigned gi = f.rc[j] >> 16, gm = f.rc[j] & 0xffffu;
+            const unsigned zo = gi * unsigned(ld) + gm;
+            pf[j][0] = llb ? llb[gi * unsigned(hx) + gm] : zb[zo];
+            pf[j][1] = zx[zo];
+            pf[j][2] = zy[zo];
+            pf[j][3] = zd[zo];
         }
     }
 }
 
 // The fetched coefficients into LDS as f(z) (scoef; the LL block as it is
-// when it came from a coarser level's image), laid out for filter length
-// 2 H2 + 2.  The caller synchronises before the tile reads them.
+// when it came from a coarser level's image).  The caller synchronises
+// before the tile reads them.
 template <typename T, int CF>
-__device__ __forceinline__ void inv_commit(const T (&pf)[DWT_PF][4], bool ll_image, int sy, int sx, int H2, T tau,
-                                           T* smem) {
-    const int hy = sy >> 1, hx = sx >> 1;
-    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
-    const int CY = oty + H2, CX = otx + H2;
-    const int CM = DWT_OTX + H2, CMY = DWT_OTY + H2;
-    T* ca = smem;
-    T* cbx = ca + CMY * CM;
-    T* cby = cbx + CMY * CM;
-    T* cd = cby + CMY * CM;
+__device__ __forceinline__ void inv_commit(const T (&pf)[DWT_PF][4], bool ll_image, T tau, T* smem) {
 #pragma unroll
     for (int j = 0; j < DWT_PF; ++j) {
         const int e = threadIdx.x + j * DWT_NTH;
-        if (e < CY * CX) {
-            const int n = e / CX, q = e - n * CX;
-            ca[n * CM + q] = ll_image ? pf[j][0] : scoef<T, CF>(pf[j][0], tau);
-            cbx[n * CM + q] = scoef<T, CF>(pf[j][1], tau);
-            cby[n * CM + q] = scoef<T, CF>(pf[j][2], tau);
-            cd[n * CM + q] = scoef<T, CF>(pf[j][3], tau);
+        if (j + 1 < DWT_PF || e < DWT_SE) {
+            smem[e] = ll_image ? pf[j][0] : scoef<T, CF>(pf[j][0], tau);
+            smem[DWT_SE + e] = scoef<T, CF>(pf[j][1], tau);
+            smem[2 * DWT_SE + e] = scoef<T, CF>(pf[j][2], tau);
+            smem[3 * DWT_SE + e] = scoef<T, CF>(pf[j][3], tau);
         }
     }
 }
 
-// One synthesis tile producing 2 oty x 2 otx pixels of an sy x sx image (one
-// band) from the four sub-bands committed to LDS (inv_commit; the caller
+// One synthesis tile producing 2 DWT_OTY x 2 DWT_OTX pixels of one band
+// from the four sub-bands committed to LDS (inv_commit; the caller
 // synchronises after committing), added to the thread's 8 pixels acc
 // (inv_out).  Register blocking: a thread of the row synthesis forms both
 // output parities of 2 coefficient rows of one column from K / 2 + 1 rows of
 // each sub-band; a thread of the column synthesis forms 8 adjacent pixels
 // from K / 2 + 3 values of each half.  Each output's taps are summed in tap
 // order, the low-pass term of a tap before its high-pass term, one fused
-// multiply-add each.  Ends with a barrier, so the next tile may reuse the LDS at once.
+// multiply-add each.  Ends with a barrier, so the next tile may reuse the
+// LDS at once.
 template <typename T, int K>
-__device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], const T (&g)[K], T* smem,
-                                             T (&acc)[2 * DWT_C2]) {
+__device__ __forceinline__ void dwt_inv_tile(const T (&h)[K], const T (&g)[K], T* smem, T (&acc)[2 * DWT_C2]) {
     constexpr int H2 = K / 2 - 1;                 // coefficient halo below the tile
-    constexpr int CMY = DWT_OTY + H2, CM = DWT_OTX + H2;
+    constexpr int OFF = 7 - H2;                   // where this filter's block starts in the fetched one
+    constexpr int CX = DWT_OTX + H2;              // coefficient columns the row synthesis forms
     constexpr int NY = K / 2 + 1, NX = K / 2 + DWT_C2 - 1;
-    const T* ca = smem;
-    const T* cbx = ca + CMY * CM;
-    const T* cby = cbx + CMY * CM;
-    const T* cd = cby + CMY * CM;
+    const T* ca = smem + OFF * DWT_SX + OFF;
+    const T* cbx = ca + DWT_SE;
+    const T* cby = cbx + DWT_SE;
+    const T* cd = cby + DWT_SE;
     constexpr int CMX = dwt_xstride(H2);
-    T* xl = smem + 4 * CMY * CM;
+    T* xl = smem + 4 * DWT_SE;
     T* xh = xl + 2 * DWT_OTY * CMX;
-    const int hy = sy >> 1, hx = sx >> 1;
-    const int oty = hy < DWT_OTY ? hy : DWT_OTY, otx = hx < DWT_OTX ? hx : DWT_OTX;
-    const int CX = otx + H2;
     // along y: coefficient rows r2 = rb + r (r < 2) of column q, output rows
-    // 2 r2 + p; row r2 takes coefficient rows r2 + H2 - kk, kk < K / 2
-    for (int e = threadIdx.x; e < (oty / 2) * CX; e += DWT_NTH) {
+    // 2 r2 + p; row r2 takes coefficient rows r2 + H2 - kk, kk < K / 2 (one
+    // item at a time: two unrolled would double the registers it holds)
+#pragma unroll 1
+    for (int e = threadIdx.x; e < (DWT_OTY / 2) * CX; e += DWT_NTH) {
         const int rb = (e / CX) * 2, q = e - (e / CX) * CX;
         T va[NY], vby[NY], vbx[NY], vd[NY];
 #pragma unroll
         for (int t = 0; t < NY; ++t) {
-            va[t] = ca[(rb + t) * CM + q];
-            vby[t] = cby[(rb + t) * CM + q];
-            vbx[t] = cbx[(rb + t) * CM + q];
-            vd[t] = cd[(rb + t) * CM + q];
+            va[t] = ca[(rb + t) * DWT_SX + q];
+            vby[t] = cby[(rb + t) * DWT_SX + q];
+            vbx[t] = cbx[(rb + t) * DWT_SX + q];
+            vd[t] = cd[(rb + t) * DWT_SX + q];
         }
 #pragma unroll
         for (int r = 0; r < 2; ++r)
@@ -424,12 +447,9 @@ __device__ __forceinline__ void dwt_inv_tile(int sy, int sx, const T (&h)[K], co
     }
     __syncthreads();
     // along x: row rr, coefficient columns c2 = cb + c (c < DWT_C2), output
-    // columns 2 c2 + p; column c2 takes c2 + H2 - kk, kk < K / 2 (a tile
-    // narrower than DWT_C2 reads past its columns inside the LDS array and
-    // keeps only its own pixels)
-    int rr, c0, n;
-    if (inv_out(oty, otx, rr, c0, n)) {
-        const int cb = c0 / 2;
+    // columns 2 c2 + p; column c2 takes c2 + H2 - kk, kk < K / 2
+    {
+        const int rr = threadIdx.x / DWT_XT, cb = (threadIdx.x % DWT_XT) * DWT_C2;
         T ul[NX], uh[NX];
 #pragma unroll
         for (int t = 0; t < NX; ++t) {
@@ -588,8 +608,8 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     const int K = 2 * int((A.kpack >> (4 * b)) & 15u);
     {
         T pf[DWT_PF][4];
-        inv_fetch<T>(llb, zb, A.ld, A.sy, A.sx, K / 2 - 1, tl, pf);
-        inv_commit<T, CF>(pf, llb != nullptr, A.sy, A.sx, K / 2 - 1, T(A.tau), smem);
+        inv_fetch<T>(llb, zb, A.ld, A.sy, A.sx, inv_offsets(A.sy, A.sx, tl), pf);
+        inv_commit<T, CF>(pf, llb != nullptr, T(A.tau), smem);
     }
     __syncthreads();
     switch (K) {
@@ -597,7 +617,7 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     case KK: {                                                                             \
         T h[KK], g[KK];                                                                    \
         load_taps<T, KK>(fb, h, g);                                                        \
-        dwt_inv_tile<T, KK>(A.sy, A.sx, h, g, smem, acc);                                  \
+        dwt_inv_tile<T, KK>(h, g, smem, acc);                                              \
         break;                                                                             \
     }
         MUFFIN_DWT_K_CASES(F)
@@ -620,7 +640,7 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
 // order inside the work-group, so out is read and written once and the sum
 // has a fixed order.  Slice z = band.
 template <typename T, int CF>
-__global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 5 : 3) k_dwt_inv0_all(DwtLevel A) {
+__global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 4 : 3) k_dwt_inv0_all(DwtLevel A) {
     __shared__ T smem[DWT_INV_LDS];
     const Tile tl = xcd_tile();
     const long band = tl.z;
@@ -638,14 +658,15 @@ __global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 5 : 3) k_dwt_inv0_al
     auto zb_of = [&](int b) { return (const T*)A.z0 + b * A.zstride + band * A.z_bs; };
     auto llb_of = [&](int b) { return A.ll0 ? (const T*)A.ll0 + b * A.llstride + band * (vb / 4) : nullptr; };
     auto k_of = [&](int b) { return 2 * int((A.kpack >> (4 * b)) & 15u); };
+    const InvOffsets fo = inv_offsets(A.sy, A.sx, tl);
     T pf[DWT_PF][4];
-    inv_fetch<T>(llb_of(0), zb_of(0), A.ld, A.sy, A.sx, k_of(0) / 2 - 1, tl, pf);
+    inv_fetch<T>(llb_of(0), zb_of(0), A.ld, A.sy, A.sx, fo, pf);
     for (int b = 0; b < A.n; ++b) {
         const int K = k_of(b);
-        inv_commit<T, CF>(pf, A.ll0 != nullptr, A.sy, A.sx, K / 2 - 1, T(A.tau), smem);
+        inv_commit<T, CF>(pf, A.ll0 != nullptr, T(A.tau), smem);
         __syncthreads();
         if (b + 1 < A.n) {
-            inv_fetch<T>(llb_of(b + 1), zb_of(b + 1), A.ld, A.sy, A.sx, k_of(b + 1) / 2 - 1, tl, pf);
+            inv_fetch<T>(llb_of(b + 1), zb_of(b + 1), A.ld, A.sy, A.sx, fo, pf);
         } else if (own) {
 #pragma unroll
             for (int c = 0; c < 2 * DWT_C2; ++c)
@@ -657,7 +678,7 @@ __global__ void __launch_bounds__(DWT_NTH, sizeof(T) == 4 ? 5 : 3) k_dwt_inv0_al
     case KK: {                                                                             \
         T h[KK], g[KK];                                                                    \
         load_taps<T, KK>(fb, h, g);                                                        \
-        dwt_inv_tile<T, KK>(A.sy, A.sx, h, g, smem, acc);                                  \
+        dwt_inv_tile<T, KK>(h, g, smem, acc);                                              \
         break;                                                                             \
     }
             MUFFIN_DWT_K_CASES(F)
@@ -684,6 +705,9 @@ static dim3 dwt_grid(int sy, int sx, int nz) {
 static bool level_ok(const DwtLevel& A) {
     if (A.n < 1 || A.n > 8 || A.L < 1 || A.sy < 4 || A.sx < 4 || (A.sy & (A.sy - 1)) || (A.sx & (A.sx - 1)))
         return false;
+    // the synthesis packs a sub-band row and column in 16 bits each and
+    // addresses a band's coefficient block with 32-bit offsets
+    if (A.sy > 65536 || A.sx > 65536 || long(A.sy) * A.ld >= (1L << 32)) return false;
     for (int b = 0; b < A.n; ++b) {
         const unsigned k2 = (A.kpack >> (4 * b)) & 15u;
         if (k2 < 1 || k2 > 8) return false;
