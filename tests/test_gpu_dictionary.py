@@ -65,6 +65,9 @@ CASES = [
     (2, 64, 16, (0, 3, 5), 10),
     (3, 16, 16, (0, 8), 10),
     (2, 8, 8, PAPER, 10),
+    # short and wide: 8 coefficient rows per sub-band (half a tile's rows)
+    # across two tiles of columns at the finest level
+    (2, 16, 128, (0, 2, 8), 8),
 ]
 
 
