@@ -593,11 +593,13 @@ __global__ void __launch_bounds__(DWT_NTH) k_dwt_fwd0_all(DwtLevel A) {
 #undef MUFFIN_DWT_FWD_CASE
 
 // One synthesis level (not the finest) of every basis and band into the
-// bases' dense scratch images: slice z = basis * L + band.
+// bases' dense scratch images: slice z = basis * L + band, the tiles
+// numbered so that each XCD takes a contiguous run (the halos that
+// neighbouring tiles share meet in one L2).
 template <typename T, int CF>
 __global__ void __launch_bounds__(DWT_NTH) k_dwt_inv_all(DwtLevel A) {
     __shared__ T smem[DWT_INV_LDS];
-    const Tile tl = {int(blockIdx.x), int(blockIdx.y), int(blockIdx.z)};
+    const Tile tl = xcd_tile();
     const int b = tl.z / A.L;
     const long band = tl.z - b * A.L;
     const T* zb = (const T*)A.z0 + b * A.zstride + band * A.z_bs;
