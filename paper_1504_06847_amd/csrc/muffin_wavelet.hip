@@ -420,30 +420,34 @@ __device__ __forceinline__ void dwt_inv_tile(const T (&h)[K], const T (&g)[K], T
 #pragma unroll 1
     for (int e = threadIdx.x; e < (DWT_OTY / 2) * CX; e += DWT_NTH) {
         const int rb = (e / CX) * 2, q = e - (e / CX) * CX;
-        T va[NY], vby[NY], vbx[NY], vd[NY];
+        // the low half (LL, y-high) then the high half (x-high, diagonal):
+        // two sub-bands' rows held at a time
 #pragma unroll
-        for (int t = 0; t < NY; ++t) {
-            va[t] = ca[(rb + t) * DWT_SX + q];
-            vby[t] = cby[(rb + t) * DWT_SX + q];
-            vbx[t] = cbx[(rb + t) * DWT_SX + q];
-            vd[t] = cd[(rb + t) * DWT_SX + q];
-        }
+        for (int half = 0; half < 2; ++half) {
+            const T* c0 = half ? cbx : ca;
+            const T* c1 = half ? cd : cby;
+            T* xo = half ? xh : xl;
+            T v0[NY], v1[NY];
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                T lo = T(0), hi = T(0);
-#pragma unroll
-                for (int kk = 0; kk < K / 2; ++kk) {
-                    const int t = r + H2 - kk;
-                    lo += h[2 * kk + p] * va[t];
-                    lo += g[2 * kk + p] * vby[t];
-                    hi += h[2 * kk + p] * vbx[t];
-                    hi += g[2 * kk + p] * vd[t];
-                }
-                xl[(2 * (rb + r) + p) * CMX + q] = lo;
-                xh[(2 * (rb + r) + p) * CMX + q] = hi;
+            for (int t = 0; t < NY; ++t) {
+                v0[t] = c0[(rb + t) * DWT_SX + q];
+                v1[t] = c1[(rb + t) * DWT_SX + q];
             }
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    T a = T(0);
+#pragma unroll
+                    for (int kk = 0; kk < K / 2; ++kk) {
+                        const int t = r + H2 - kk;
+                        a += h[2 * kk + p] * v0[t];
+                        a += g[2 * kk + p] * v1[t];
+                    }
+                    xo[(2 * (rb + r) + p) * CMX + q] = a;
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
     __syncthreads();
     // along x: row rr, coefficient columns c2 = cb + c (c < DWT_C2), output
