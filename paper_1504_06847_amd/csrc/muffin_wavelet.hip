@@ -396,7 +396,8 @@ __device__ __forceinline__ void inv_commit(const T (&pf)[DWT_PF][4], bool ll_ima
 // synchronises after committing), added to the thread's 8 pixels acc
 // (inv_out).  Register blocking: a thread of the row synthesis forms both
 // output parities of 2 coefficient rows of one column from K / 2 + 1 rows of
-// each sub-band; a thread of the column synthesis forms 8 adjacent pixels
+// each sub-band, one pair of sub-bands at a time (LL with y-high, then x-high
+// with diagonal); a thread of the column synthesis forms 8 adjacent pixels
 // from K / 2 + 3 values of each half.  Each output's taps are summed in tap
 // order, the low-pass term of a tap before its high-pass term, one fused
 // multiply-add each.  Ends with a barrier, so the next tile may reuse the
